@@ -1,0 +1,278 @@
+/*
+ * phfem.h -- C ABI of libphfem.so, the MI355X (gfx950) hot path of the
+ * lowest-order primal hybrid finite element method for 2-D second-order
+ * elliptic problems and their Crank-Nicolson parabolic counterpart with mixed
+ * boundary conditions (Nagula Mallesham, Porwal, Valdman, Acharya,
+ * arXiv:2401.15557).
+ *
+ * General rules
+ *  - Every call returns PHF_OK (0) or a negative PHF_E* code; no exception or
+ *    signal crosses the ABI. After an error, phf_last_error() describes it.
+ *  - Indices are 0-based int32. Element vertices must be counter-clockwise.
+ *    Boundary node pairs may be listed in either orientation.
+ *  - A context owns one HIP stream (the caller's, or the null stream); every
+ *    kernel of every call on objects of that context is launched on it, in
+ *    call order. Calls return without synchronising unless stated.
+ *  - Handles are not thread-safe: one host thread per context at a time.
+ *  - Pointers tagged "device" must be HIP device (or managed) memory on the
+ *    context's device; "host" pointers are ordinary host memory. Output
+ *    buffers are owned by the caller and must stay valid until the stream
+ *    has executed the call. Input arrays are copied; the caller keeps them.
+ *  - Sizes are limited by int32 indexing: nE <= 80,000,000 elements.
+ *
+ * Notation (Sections 2-4 of the paper): nE elements, nC nodes, nrEdges
+ * edges, N = 3 nE primal unknowns (discontinuous P1: DOF 3m+i is the
+ * barycentric coordinate of local vertex i of element m), L = number of
+ * interior + Dirichlet edges (multiplier unknowns, one per edge, in ascending
+ * edge id order). "Local edge i" of an element is the edge opposite its local
+ * vertex i.
+ */
+#ifndef PHFEM_H
+#define PHFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PHF_OK 0
+#define PHF_EINVAL -1    /* null pointer, size, index out of range, bad option */
+#define PHF_EORIENT -2   /* element clockwise, degenerate or zero area        */
+#define PHF_EMESH -3     /* edge in > 2 elements or same direction in both    */
+#define PHF_EBOUNDARY -4 /* boundary edge in no list or in two; listed pair
+                            not a boundary edge of the mesh                    */
+#define PHF_ENOMEM -5    /* device or host allocation failed                   */
+#define PHF_ENOCONV -6   /* Krylov solver hit max_iter before rtol             */
+#define PHF_EHIP -7      /* a HIP runtime call failed                          */
+#define PHF_ESTATE -8    /* call out of order (e.g. solve before assemble)     */
+
+typedef struct phf_ctx phf_ctx;
+typedef struct phf_mesh phf_mesh;
+typedef struct phf_cn phf_cn;
+
+typedef enum { PHF_HOST = 0, PHF_DEVICE = 1 } phf_memspace;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Creates a context on HIP device `device` whose kernels run on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). *out receives the handle. */
+int phf_create(phf_ctx** out, int device, void* hip_stream);
+/* Synchronises the stream and frees the context (not its meshes). */
+int phf_destroy(phf_ctx* ctx);
+/* Redirects later launches to another stream of the same device. */
+int phf_set_stream(phf_ctx* ctx, void* hip_stream);
+/* Blocks until all work issued on the context's stream has finished. */
+int phf_synchronize(phf_ctx* ctx);
+/* Static text of a status code / the last error recorded on ctx. */
+const char* phf_status_str(int code);
+const char* phf_last_error(const phf_ctx* ctx);
+/* Library version as "major.minor.patch". */
+const char* phf_version(void);
+
+/* ---- kernel timing (tracing) -------------------------------------------
+ * With tracing on, every kernel the library launches is bracketed by HIP
+ * events on the context's stream; phf_trace_query() synchronises and returns
+ * the launch count and total milliseconds of the kernels whose name equals
+ * `kernel` (NULL: all kernels). phf_trace_reset() clears the record.
+ * phf_trace_dump() writes "name count total_ms" lines into buf (truncated to
+ * len bytes, NUL-terminated) and returns the number of kernel names. */
+int phf_trace_enable(phf_ctx* ctx, int on);
+int phf_trace_reset(phf_ctx* ctx);
+int phf_trace_query(phf_ctx* ctx, const char* kernel, int64_t* count, double* total_ms);
+int phf_trace_dump(phf_ctx* ctx, char* buf, size_t len);
+
+/* ---- mesh: upload, validation, topology, patterns ----------------------
+ * Section 2.1 (data of Table 1) and Section 2.2 (edge_vec): builds on the
+ * device
+ *  - the edge numbering: edges in ascending (larger node, smaller node)
+ *    order, i.e. the column-major upper-triangle order of nodes2edge;
+ *  - edge2element: T+ = the element of the first occurrence of the edge in
+ *    element order, T- the other one (-1 on the boundary); [k,l] = the edge
+ *    as traversed by T+; led / ledTN = local edge number in T+ / T-;
+ *  - the Dirichlet / Neumann edge ids of the listed pairs (Main.m, Dbed and
+ *    Nbed) and the multiplier row of every non-Neumann edge (Redges);
+ *  - the CSR patterns of K, M (3x3 element blocks), C (L x N) and of the
+ *    saddle matrix [A, -C^T; -C, 0] (Section 3.5).
+ * xy: nC x 2 (x, y) float64; elem: nE x 3; dir: nD x 2; neu: nN x 2, all in
+ * memory space `ms`. Synchronises the stream (sizes are read back).
+ * Errors: PHF_EINVAL (sizes, indices), PHF_EORIENT, PHF_EMESH,
+ * PHF_EBOUNDARY, PHF_ENOMEM, PHF_EHIP. */
+int phf_mesh_create(phf_ctx* ctx, const double* xy, int32_t nC, const int32_t* elem, int32_t nE,
+                    const int32_t* dir, int32_t nD, const int32_t* neu, int32_t nN,
+                    phf_memspace ms, phf_mesh** out);
+int phf_mesh_destroy(phf_mesh* mesh);
+
+typedef struct {
+    int32_t nC, nE, n_edges;   /* nodes, elements, edges (nrEdges)         */
+    int32_t N, L;              /* 3 nE primal unknowns; multiplier rows      */
+    int32_t nD, nN;            /* Dirichlet / Neumann edges                  */
+    int32_t n_interior;        /* interior edges                             */
+    int32_t n_free;            /* non-Dirichlet edges (reduced unknowns)     */
+    int64_t nnz_K;             /* 9 nE: nnz of K, M and D                    */
+    int64_t nnz_C;             /* 4 n_interior + 2 nD                        */
+    int64_t nnz_saddle;        /* 9 nE + 2 nnz_C                             */
+    int64_t nnz_reduced;       /* nnz of the edge-midpoint (reduced) operator */
+    int64_t device_bytes;      /* device memory held by the mesh             */
+} phf_mesh_info;
+
+int phf_mesh_get_info(const phf_mesh* mesh, phf_mesh_info* out);
+
+/* Copies topology tables into caller buffers in memory space `ms` (device
+ * copies are stream-ordered; host copies synchronise). Any pointer may be
+ * NULL to skip it. Sizes: edge_nodes, edge_elems 2 n_edges; elem_edges
+ * 3 nE (entry 3m+i = edge opposite local vertex i); led, ledTN, edge_type
+ * (0 interior, 1 Dirichlet, 2 Neumann), edge_row (-1 for Neumann) n_edges;
+ * dir_edges nD; neu_edges nN (list order). */
+int phf_mesh_topology(const phf_mesh* mesh, int32_t* edge_nodes, int32_t* edge_elems,
+                      int32_t* elem_edges, int8_t* led, int8_t* ledTN, int8_t* edge_type,
+                      int32_t* edge_row, int32_t* dir_edges, int32_t* neu_edges,
+                      phf_memspace ms);
+
+/* Copies CSR patterns (rowptr int32 rows+1, col int32 nnz). K/M/D: N rows,
+ * columns 3m..3m+2 ascending; C: L rows, the two vertex columns of T+ then
+ * those of T-; saddle: N + L rows, columns ascending. NULL skips. */
+int phf_mesh_pattern(const phf_mesh* mesh, int32_t* K_rowptr, int32_t* K_col,
+                     int32_t* C_rowptr, int32_t* C_col, int32_t* S_rowptr, int32_t* S_col,
+                     phf_memspace ms);
+
+/* ---- problem data -------------------------------------------------------
+ * Coefficients of -div(A grad u + u p) + delta u = f (Section 3.1):
+ * A constant 2x2 symmetric positive definite (row-major), scaled per element
+ * by a_T (device array of nE, or NULL for 1); p constant; delta constant.
+ * The convection block follows the listing's convention
+ * D[j][i] = int_T lambda_j (p . grad lambda_i). */
+typedef struct {
+    double A[4];
+    double p[2];
+    double delta;
+    const double* a_T;
+} phf_coeffs;
+
+/* Source f, Neumann flux g and Dirichlet value u_D (Section 3.1).
+ * kind: */
+#define PHF_FN_ZERO 0          /* 0                                           */
+#define PHF_FN_CONST 1         /* c0                                          */
+#define PHF_FN_SIN_COS 2       /* c0 exp(c1 t) sin(pi x) cos(pi y)            */
+#define PHF_FN_SIN_SIN 3       /* c0 exp(c1 t) sin(pi x) sin(pi y)            */
+#define PHF_FN_GRAD_SIN_COS 4  /* c0 exp(c1 t) grad(sin(pi x)cos(pi y)) . nu  */
+#define PHF_FN_GRAD_SIN_SIN 5  /* c0 exp(c1 t) grad(sin(pi x)sin(pi y)) . nu  */
+#define PHF_FN_PAPER_U 6       /* (c0 + c1 t)(x - x^2)(y - y^2)               */
+#define PHF_FN_PAPER_F 7       /* source of the paper's Examples 1 (c0=1,c1=0)
+                                  and 2 (c0=0, c1=1)                          */
+#define PHF_FN_PAPER_FLUX 8    /* (c0 + c1 t)[(1-x-x^2)(y-y^2),
+                                  (x-x^2)(1-y-y^2)] . nu (Examples 1, 2)      */
+#define PHF_FN_EDGE_ARRAY 100  /* edge_values[e] (device, n_edges doubles) is
+                                  the value at the midpoint of edge e (for g:
+                                  the normal flux, outward from T+)            */
+typedef struct {
+    int32_t kind;
+    int32_t pad_;
+    double c[4];
+    const double* edge_values;
+} phf_fn;
+
+/* f is evaluated at the three edge midpoints of each element, g and u_D
+ * at the midpoint of each Neumann / Dirichlet edge (Section 3.4);
+ * nu is the outward unit normal of the edge's element. t is the time. */
+typedef struct {
+    phf_fn f, g, uD;
+    double t;
+} phf_data;
+
+/* ---- numeric assembly ---------------------------------------------------
+ * Definition 3.1 and Sections 3.4-3.5, one pass over elements and one over
+ * multiplier rows in a single launch. Device output buffers (NULL skips):
+ *   K  nnz_K  stiffness a_T |T| (A grad lambda_j) . grad lambda_i, CSR order
+ *              (element m: 9 values row-major at 9m)
+ *   M  nnz_K  unit mass |T|/12 (1 + delta_ij) (without the reaction delta)
+ *   D  nnz_K  convection (only if p != 0 is wanted)
+ *   C  nnz_C  coupling: row of edge e = [|E|/2, |E|/2] on the vertex DOFs of
+ *              T+ followed by [-|E|/2, -|E|/2] on those of T- (interior)
+ *   F  N      b + LN (midpoint-rule source load + Neumann load)
+ *   bD L      -|E| u_D(m_E) on Dirichlet rows, 0 on interior rows
+ *   S  nnz_saddle  values of [K + D + delta M, -C^T; -C, 0]
+ * Stream-ordered, deterministic (no floating-point atomics), no host sync. */
+typedef struct {
+    double* K;
+    double* M;
+    double* D;
+    double* C;
+    double* F;
+    double* bD;
+    double* S;
+} phf_system;
+
+int phf_assemble(phf_mesh* mesh, const phf_coeffs* coeffs, const phf_data* data,
+                 const phf_system* out);
+
+/* y = alpha * A x + beta * y for a CSR matrix (device arrays, int32 rowptr /
+ * col, nrows rows). Used for residuals of the assembled operators. */
+int phf_spmv(phf_ctx* ctx, int32_t nrows, const int32_t* rowptr, const int32_t* col,
+             const double* val, double alpha, const double* x, double beta, double* y);
+
+/* ---- saddle-point solve -------------------------------------------------
+ * Solves M_vec W = F_vec, i.e. (K + D + delta M) U - C^T Lambda = F and
+ * -C U = b_D (Section 3.5), for the system assembled into `sys`
+ * (K, M, C, F, bD required; D if p != 0 -- only p = 0 is supported by the
+ * conjugate-gradient method). The method is the null-space reduction of the
+ * saddle system: the constraint -C U = b_D is parametrised by edge-midpoint
+ * values (the lowest-order primal hybrid space is the Crouzeix-Raviart space,
+ * Section 1), the projected operator is symmetric positive definite and is
+ * solved by Jacobi-preconditioned CG with CSR SpMV kernels, and Lambda is
+ * recovered element by element. U, Lambda: device, N and L doubles; Lambda
+ * may be NULL. Synchronises the stream. Returns PHF_ENOCONV if rtol is not
+ * reached in max_iter iterations (the iterate is still written). */
+#define PHF_SOLVER_NULLSPACE_CG 0
+typedef struct {
+    int32_t method;      /* PHF_SOLVER_*                                   */
+    int32_t max_iter;    /* 0 = 20000                                      */
+    double rtol;         /* relative residual of the reduced system; 0 = 1e-10 */
+    int32_t check_every; /* host convergence test period (iterations); 0 = 8 */
+    int32_t saddle_residual; /* 1: compute the saddle residual into stats   */
+} phf_solver_opts;
+
+typedef struct {
+    int32_t iterations;
+    int32_t converged;
+    double rel_residual;        /* reduced-system ||r|| / ||b||             */
+    double saddle_rel_residual; /* ||F_vec - M_vec W|| / ||F_vec|| (if asked) */
+} phf_solve_stats;
+
+int phf_solve(phf_mesh* mesh, const phf_coeffs* coeffs, const phf_system* sys,
+              const phf_solver_opts* opts, double* U, double* Lambda, phf_solve_stats* stats);
+
+/* ---- Crank-Nicolson (Section 4) -----------------------------------------
+ * M+ W^n = M- W^{n-1} + [k F^{n-1/2}; b_D^{n-1/2}] with
+ * M(+/-) = [(1 +/- k delta/2) M +/- (k/2)(K + D), -/+ (k/2) C^T;
+ *           -/+ (1/2) C, 0], M the unit mass, and F^{n-1/2}, b_D^{n-1/2} the
+ * averages of their evaluations at t_{n-1} and t_n (Section 4.1).
+ * phf_cn_create assembles K, M, C once (coeffs as for phf_assemble, p = 0),
+ * k > 0. set_state copies U (N) and Lambda (L) device arrays and sets t.
+ * phf_cn_run advances nsteps steps with the time-dependent data `data`
+ * (data->t is ignored); use_graph = 1 captures one step in a HIP graph and
+ * replays it (the per-step solve then runs a fixed budget of
+ * `iters_per_step` CG iterations, each skipped on the device once the
+ * residual is below rtol). get_state copies the current state out (device)
+ * and returns t. stats (may be NULL) receives the total CG iterations and
+ * the worst final reduced residual over the steps. */
+typedef struct {
+    double rtol;            /* 0 = 1e-10                                   */
+    int32_t max_iter;       /* per step, eager mode; 0 = 5000             */
+    int32_t iters_per_step; /* graph mode budget; 0 = 64                   */
+} phf_cn_opts;
+
+int phf_cn_create(phf_mesh* mesh, const phf_coeffs* coeffs, double k, const phf_cn_opts* opts,
+                  phf_cn** out);
+int phf_cn_set_state(phf_cn* cn, const double* U, const double* Lambda, double t);
+int phf_cn_run(phf_cn* cn, const phf_data* data, int32_t nsteps, int32_t use_graph,
+               phf_solve_stats* stats);
+int phf_cn_get_state(phf_cn* cn, double* U, double* Lambda, double* t);
+int phf_cn_destroy(phf_cn* cn);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHFEM_H */

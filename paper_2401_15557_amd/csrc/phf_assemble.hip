@@ -1,0 +1,435 @@
+// Numeric assembly (Definition 3.1, Sections 3.4-3.5): one fused launch with
+// element tiles (K, M, optional D, F = b + LN) and multiplier-row tiles (C,
+// b_D). Every output entry has exactly one producer, so there are no atomics
+// and no reductions across threads: the CSR "scatter" of the block-diagonal
+// K, M, D is the identity map (element m owns values 9m..9m+8), and C rows
+// are written in place at their precomputed row pointers.
+//
+// Memory layout: coordinates are double2 (16 B) records, elements int4
+// records (v0, v1, v2, code). An element tile of 256 triangles computes its
+// 9 K values per element into LDS and the whole tile then streams out as one
+// contiguous 18 KB block with 16-byte stores; M is regenerated from the
+// staged areas; F from a staged 3-value record.
+#include "phf_device.h"
+#include "phf_internal.h"
+
+namespace {
+
+constexpr int TILE = 256;
+
+struct AsmArgs {
+    int32_t nE, L, nbE, nbR;
+    const int4* elem4;
+    const double2* xy;
+    const double* aT;
+    const int32_t* elem_edges;
+    const int2* row_nodes;
+    const int32_t* row_edge;
+    const int32_t* C_rowptr;
+    double A00, A01, A10, A11, p0, p1;
+    phf_fn_dev f, g, uD;
+    double t;
+    const int64_t* t_step;
+    double t0, dt;
+    double* K;
+    double* M;
+    double* D;
+    double* C;
+    double* F;
+    double* bD;
+};
+
+// Splits the fused grid between element tiles and row tiles so that each
+// XCD (block b runs on XCD b % 8) receives a contiguous range of element
+// tiles and a contiguous range of row tiles, interleaved in time.
+__device__ inline void fused_tile(int32_t b, int32_t nbE, int32_t nbR, bool* is_elem,
+                                  int32_t* tile)
+{
+    const int32_t T = nbE + nbR, nx = 8;
+    int32_t per = T / nx, rem = T % nx;
+    int32_t x = b % nx, k = b / nx;
+    int32_t own = per + (x < rem ? 1 : 0);
+    int32_t C0 = x * per + (x < rem ? x : rem);
+    int32_t C1 = C0 + own;
+    int32_t E0 = (int32_t)(((int64_t)C0 * nbE) / T);
+    int32_t E1 = (int32_t)(((int64_t)C1 * nbE) / T);
+    int32_t R0 = C0 - E0;
+    int32_t ex = E1 - E0;
+    int32_t ei0 = (int32_t)(((int64_t)k * ex) / own);
+    int32_t ei1 = (int32_t)(((int64_t)(k + 1) * ex) / own);
+    if (ei1 > ei0) {
+        *is_elem = true;
+        *tile = E0 + ei0;
+    } else {
+        *is_elem = false;
+        *tile = R0 + (k - ei0);
+    }
+}
+
+template <bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A>
+__device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK, double* shD,
+                                    double* shA, double* shF)
+{
+    const int tid = threadIdx.x;
+    const int32_t m0 = tile * TILE;
+    const int32_t nt = min(TILE, a.nE - m0);
+    if (tid < nt) {
+        const int32_t m = m0 + tid;
+        const int4 e = a.elem4[m];
+        const double2 P0 = a.xy[e.x], P1 = a.xy[e.y], P2 = a.xy[e.z];
+        // g_i = 2|T| grad lambda_i (the edge opposite vertex i turned by 90 deg)
+        const double g0x = P1.y - P2.y, g0y = P2.x - P1.x;
+        const double g1x = P2.y - P0.y, g1y = P0.x - P2.x;
+        const double g2x = P0.y - P1.y, g2y = P1.x - P0.x;
+        const double det = (P1.x - P0.x) * (P2.y - P0.y) - (P2.x - P0.x) * (P1.y - P0.y);
+        const double area = 0.5 * det;
+        if (MATS) {
+            const double aT = HAS_AT ? a.aT[m] : 1.0;
+            const double s = aT / (2.0 * det);
+            double k00, k01, k02, k11, k12, k22, k10, k20, k21;
+            if (GEN_A) {
+                // K[j][i] = aT |T| (A grad lambda_j) . grad lambda_i
+                double a0x = a.A00 * g0x + a.A01 * g0y, a0y = a.A10 * g0x + a.A11 * g0y;
+                double a1x = a.A00 * g1x + a.A01 * g1y, a1y = a.A10 * g1x + a.A11 * g1y;
+                double a2x = a.A00 * g2x + a.A01 * g2y, a2y = a.A10 * g2x + a.A11 * g2y;
+                k00 = s * (a0x * g0x + a0y * g0y);
+                k01 = s * (a0x * g1x + a0y * g1y);
+                k02 = s * (a0x * g2x + a0y * g2y);
+                k10 = s * (a1x * g0x + a1y * g0y);
+                k11 = s * (a1x * g1x + a1y * g1y);
+                k12 = s * (a1x * g2x + a1y * g2y);
+                k20 = s * (a2x * g0x + a2y * g0y);
+                k21 = s * (a2x * g1x + a2y * g1y);
+                k22 = s * (a2x * g2x + a2y * g2y);
+            } else {
+                k00 = s * (g0x * g0x + g0y * g0y);
+                k11 = s * (g1x * g1x + g1y * g1y);
+                k22 = s * (g2x * g2x + g2y * g2y);
+                k01 = s * (g0x * g1x + g0y * g1y);
+                k02 = s * (g0x * g2x + g0y * g2y);
+                k12 = s * (g1x * g2x + g1y * g2y);
+                k10 = k01;
+                k20 = k02;
+                k21 = k12;
+            }
+            double* kk = shK + tid * 9;
+            kk[0] = k00; kk[1] = k01; kk[2] = k02;
+            kk[3] = k10; kk[4] = k11; kk[5] = k12;
+            kk[6] = k20; kk[7] = k21; kk[8] = k22;
+            shA[tid] = area / 12.0;
+            if (WITH_D) {
+                // D[j][i] = (|T|/3) p . grad lambda_i = p . g_i / 6
+                double h0 = (a.p0 * g0x + a.p1 * g0y) / 6.0;
+                double h1 = (a.p0 * g1x + a.p1 * g1y) / 6.0;
+                double h2 = (a.p0 * g2x + a.p1 * g2y) / 6.0;
+                double* dd = shD + tid * 9;
+                dd[0] = h0; dd[1] = h1; dd[2] = h2;
+                dd[3] = h0; dd[4] = h1; dd[5] = h2;
+                dd[6] = h0; dd[7] = h1; dd[8] = h2;
+            }
+        }
+        // source load: midpoint rule over the three edge midpoints; the
+        // midpoint of edge i (opposite vertex i) has lambda_j = 1/2, j != i
+        int32_t ed0 = -1, ed1 = -1, ed2 = -1;
+        const bool fe = a.f.kind == PHF_FN_EDGE_ARRAY;
+        if (fe) {
+            ed0 = a.elem_edges[3 * (int64_t)m];
+            ed1 = a.elem_edges[3 * (int64_t)m + 1];
+            ed2 = a.elem_edges[3 * (int64_t)m + 2];
+        }
+        double b0 = 0.0, b1 = 0.0, b2 = 0.0;
+        if (a.f.kind != PHF_FN_ZERO) {
+            const double f0 = phf_fn_eval(a.f, 0.5 * (P1.x + P2.x), 0.5 * (P1.y + P2.y), a.t, 0, 0, ed0);
+            const double f1 = phf_fn_eval(a.f, 0.5 * (P2.x + P0.x), 0.5 * (P2.y + P0.y), a.t, 0, 0, ed1);
+            const double f2 = phf_fn_eval(a.f, 0.5 * (P0.x + P1.x), 0.5 * (P0.y + P1.y), a.t, 0, 0, ed2);
+            const double c = area / 6.0;
+            b0 = c * (f1 + f2);
+            b1 = c * (f0 + f2);
+            b2 = c * (f0 + f1);
+        }
+        // Neumann load: |E| g(m_E) / 2 on the two vertices of each Neumann edge
+        const int code = e.w;
+        if (code & 0x2A) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                if (PHF_CODE_TYPE(code, i) != 2) continue;
+                const double2 Pa = i == 0 ? P1 : (i == 1 ? P2 : P0);
+                const double2 Pb = i == 0 ? P2 : (i == 1 ? P0 : P1);
+                const double dx = Pb.x - Pa.x, dy = Pb.y - Pa.y;
+                const double len = sqrt(dx * dx + dy * dy);
+                int32_t eid = a.g.kind == PHF_FN_EDGE_ARRAY ? a.elem_edges[3 * (int64_t)m + i] : -1;
+                const double gv = phf_fn_eval(a.g, 0.5 * (Pa.x + Pb.x), 0.5 * (Pa.y + Pb.y), a.t,
+                                              dy / len, -dx / len, eid);
+                const double w = len * gv * 0.5;
+                if (i == 0) { b1 += w; b2 += w; }
+                if (i == 1) { b2 += w; b0 += w; }
+                if (i == 2) { b0 += w; b1 += w; }
+            }
+        }
+        shF[3 * tid] = b0;
+        shF[3 * tid + 1] = b1;
+        shF[3 * tid + 2] = b2;
+    }
+    __syncthreads();
+    // coalesced tile stores (16-byte chunks; the tile base is 16-byte aligned)
+    if (MATS) {
+        const int32_t cnt = 9 * nt;
+        double2* K2 = reinterpret_cast<double2*>(a.K + 9 * (int64_t)m0);
+        double2* M2 = reinterpret_cast<double2*>(a.M + 9 * (int64_t)m0);
+        const double2* sK2 = reinterpret_cast<const double2*>(shK);
+        for (int32_t q = tid; q < cnt / 2; q += TILE) {
+            K2[q] = sK2[q];
+            const int32_t v0 = 2 * q, v1 = 2 * q + 1;
+            const int32_t el0 = v0 / 9, el1 = v1 / 9;
+            const int32_t r0 = v0 - 9 * el0, r1 = v1 - 9 * el1;
+            M2[q] = make_double2(shA[el0] * ((r0 & 3) == 0 ? 2.0 : 1.0),
+                                 shA[el1] * ((r1 & 3) == 0 ? 2.0 : 1.0));
+        }
+        if ((cnt & 1) && tid == 0) {
+            const int32_t v = cnt - 1, el = v / 9, rr = v - 9 * el;
+            a.K[9 * (int64_t)m0 + v] = shK[v];
+            a.M[9 * (int64_t)m0 + v] = shA[el] * ((rr & 3) == 0 ? 2.0 : 1.0);
+        }
+        if (WITH_D) {
+            double2* D2 = reinterpret_cast<double2*>(a.D + 9 * (int64_t)m0);
+            const double2* sD2 = reinterpret_cast<const double2*>(shD);
+            for (int32_t q = tid; q < cnt / 2; q += TILE) D2[q] = sD2[q];
+            if ((cnt & 1) && tid == 0) a.D[9 * (int64_t)m0 + cnt - 1] = shD[cnt - 1];
+        }
+    }
+    {
+        const int32_t cnt = 3 * nt;
+        double2* F2 = reinterpret_cast<double2*>(a.F + 3 * (int64_t)m0);
+        const double2* sF2 = reinterpret_cast<const double2*>(shF);
+        for (int32_t q = tid; q < cnt / 2; q += TILE) F2[q] = sF2[q];
+        if ((cnt & 1) && tid == 0) a.F[3 * (int64_t)m0 + cnt - 1] = shF[cnt - 1];
+    }
+}
+
+template <bool MATS>
+__device__ inline void row_tile(const AsmArgs& a, int32_t tile)
+{
+    const int32_t r = tile * TILE + threadIdx.x;
+    if (r >= a.L) return;
+    const int2 kl = a.row_nodes[r];
+    const int32_t c0 = a.C_rowptr[r], c1 = a.C_rowptr[r + 1];
+    const double2 Pk = a.xy[kl.x], Pl = a.xy[kl.y];
+    const double dx = Pl.x - Pk.x, dy = Pl.y - Pk.y;
+    const double len = sqrt(dx * dx + dy * dy);
+    const double h = 0.5 * len;
+    const bool interior = (c1 - c0) == 4;
+    if (MATS) {
+        double2* C2 = reinterpret_cast<double2*>(a.C + c0);
+        C2[0] = make_double2(h, h);
+        if (interior) C2[1] = make_double2(-h, -h);
+    }
+    double v = 0.0;
+    if (!interior && a.uD.kind != PHF_FN_ZERO) {
+        int32_t eid = a.uD.kind == PHF_FN_EDGE_ARRAY ? a.row_edge[r] : -1;
+        v = -len * phf_fn_eval(a.uD, 0.5 * (Pk.x + Pl.x), 0.5 * (Pk.y + Pl.y), a.t, 0, 0, eid);
+    }
+    a.bD[r] = v;
+}
+
+template <bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A>
+__global__ __launch_bounds__(TILE) void k_assemble(AsmArgs a)
+{
+    if (a.t_step) a.t = a.t0 + (double)(*a.t_step) * a.dt;
+    __shared__ __align__(16) double shK[MATS ? TILE * 9 : 2];
+    __shared__ __align__(16) double shD[WITH_D ? TILE * 9 : 2];
+    __shared__ double shA[MATS ? TILE : 1];
+    __shared__ __align__(16) double shF[TILE * 3];
+    bool is_elem;
+    int32_t tile;
+    fused_tile(blockIdx.x, a.nbE, a.nbR, &is_elem, &tile);
+    if (is_elem) element_tile<HAS_AT, MATS, WITH_D, GEN_A>(a, tile, shK, shD, shA, shF);
+    else row_tile<MATS>(a, tile);
+}
+
+// ---- saddle-matrix values -------------------------------------------------
+struct SaddleArgs {
+    int32_t nE, L, nbE, nbR;
+    const int4* elem4;
+    const double2* xy;
+    const double* aT;
+    const int32_t* S_rowptr;
+    const int32_t* C_rowptr;
+    const int2* row_nodes;
+    double A00, A01, A10, A11, p0, p1, delta;
+    double* S;
+};
+
+__global__ __launch_bounds__(TILE) void k_saddle_values(SaddleArgs a)
+{
+    bool is_elem;
+    int32_t tile;
+    fused_tile(blockIdx.x, a.nbE, a.nbR, &is_elem, &tile);
+    const int32_t N = 3 * a.nE;
+    if (is_elem) {
+        const int32_t m = tile * TILE + threadIdx.x;
+        if (m >= a.nE) return;
+        const int4 e = a.elem4[m];
+        const double2 P[3] = {a.xy[e.x], a.xy[e.y], a.xy[e.z]};
+        double gx[3], gy[3];
+        for (int i = 0; i < 3; ++i) {
+            const double2 Pa = P[(i + 1) % 3], Pb = P[(i + 2) % 3];
+            gx[i] = Pa.y - Pb.y;
+            gy[i] = Pb.x - Pa.x;
+        }
+        const double det = (P[1].x - P[0].x) * (P[2].y - P[0].y) - (P[2].x - P[0].x) * (P[1].y - P[0].y);
+        const double area = 0.5 * det;
+        const double aT = a.aT ? a.aT[m] : 1.0;
+        const double s = aT / (2.0 * det);
+        double len[3];
+        for (int i = 0; i < 3; ++i) {
+            const double2 Pa = P[(i + 1) % 3], Pb = P[(i + 2) % 3];
+            const double dx = Pb.x - Pa.x, dy = Pb.y - Pa.y;
+            len[i] = sqrt(dx * dx + dy * dy);
+        }
+        const int code = e.w;
+        for (int j = 0; j < 3; ++j) {
+            int32_t q = a.S_rowptr[3 * (int64_t)m + j];
+            const double ajx = a.A00 * gx[j] + a.A01 * gy[j], ajy = a.A10 * gx[j] + a.A11 * gy[j];
+            for (int i = 0; i < 3; ++i) {
+                double v = s * (ajx * gx[i] + ajy * gy[i]);
+                v += (a.p0 * gx[i] + a.p1 * gy[i]) / 6.0;
+                v += a.delta * (area / 12.0) * (i == j ? 2.0 : 1.0);
+                a.S[q + i] = v;
+            }
+            q += 3;
+            int l1 = j == 0 ? 1 : 0, l2 = j == 2 ? 1 : 2;
+            if (PHF_CODE_SWAP(code, j)) {
+                int t = l1;
+                l1 = l2;
+                l2 = t;
+            }
+            if (PHF_CODE_TYPE(code, l1) != 2)
+                a.S[q++] = -(PHF_CODE_TPLUS(code, l1) ? 0.5 : -0.5) * len[l1];
+            if (PHF_CODE_TYPE(code, l2) != 2)
+                a.S[q++] = -(PHF_CODE_TPLUS(code, l2) ? 0.5 : -0.5) * len[l2];
+        }
+    } else {
+        const int32_t r = tile * TILE + threadIdx.x;
+        if (r >= a.L) return;
+        const int2 kl = a.row_nodes[r];
+        const int32_t c0 = a.C_rowptr[r], c1 = a.C_rowptr[r + 1];
+        const double2 Pk = a.xy[kl.x], Pl = a.xy[kl.y];
+        const double dx = Pl.x - Pk.x, dy = Pl.y - Pk.y;
+        const double h = 0.5 * sqrt(dx * dx + dy * dy);
+        const int32_t q = a.S_rowptr[N + r];
+        a.S[q] = -h;
+        a.S[q + 1] = -h;
+        if (c1 - c0 == 4) {
+            a.S[q + 2] = h;
+            a.S[q + 3] = h;
+        }
+    }
+}
+
+template <bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A>
+int launch_assemble(phf_ctx* ctx, const AsmArgs& a)
+{
+    PHF_LAUNCH(ctx, "k_assemble", (k_assemble<HAS_AT, MATS, WITH_D, GEN_A>), a.nbE + a.nbR, TILE,
+               0, a);
+    return PHF_OK;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+}  // namespace
+
+int phf_assemble_impl(phf_mesh* mesh, const phf_coeffs* co, const phf_data* data,
+                      const phf_system* out, const int64_t* t_step, double t0, double dt)
+{
+    phf_ctx* ctx = mesh->ctx;
+    if (!co || !data || !out) return phf_set_error(ctx, PHF_EINVAL, "phf_assemble: null argument");
+    if (!phf_fn_valid(data->f) || !phf_fn_valid(data->g) || !phf_fn_valid(data->uD))
+        return phf_set_error(ctx, PHF_EINVAL, "phf_assemble: unknown function kind or missing edge array");
+    const bool mats = out->K || out->M || out->C;
+    if (mats && !(out->K && out->M && out->C))
+        return phf_set_error(ctx, PHF_EINVAL, "phf_assemble: K, M and C are written together");
+    if (!out->F || !out->bD)
+        return phf_set_error(ctx, PHF_EINVAL, "phf_assemble: F and bD are required");
+    const void* ptrs[] = {out->K, out->M, out->D, out->C, out->F, out->bD};
+    for (const void* p : ptrs)
+        if (p && !aligned16(p))
+            return phf_set_error(ctx, PHF_EINVAL, "phf_assemble: output buffers must be 16-byte aligned");
+    if (out->D && !mats)
+        return phf_set_error(ctx, PHF_EINVAL, "phf_assemble: D needs K, M and C");
+    AsmArgs a;
+    a.nE = mesh->nE;
+    a.L = mesh->L;
+    a.nbE = (mesh->nE + TILE - 1) / TILE;
+    a.nbR = (mesh->L + TILE - 1) / TILE;
+    a.elem4 = mesh->elem4;
+    a.xy = mesh->xy;
+    a.aT = co->a_T;
+    a.elem_edges = mesh->elem_edges;
+    a.row_nodes = mesh->row_nodes;
+    a.row_edge = mesh->row_edge;
+    a.C_rowptr = mesh->C_rowptr;
+    a.A00 = co->A[0];
+    a.A01 = co->A[1];
+    a.A10 = co->A[2];
+    a.A11 = co->A[3];
+    a.p0 = co->p[0];
+    a.p1 = co->p[1];
+    a.f = phf_fn_to_dev(data->f);
+    a.g = phf_fn_to_dev(data->g);
+    a.uD = phf_fn_to_dev(data->uD);
+    a.t = data->t;
+    a.t_step = t_step;
+    a.t0 = t0;
+    a.dt = dt;
+    a.K = out->K;
+    a.M = out->M;
+    a.D = out->D;
+    a.C = out->C;
+    a.F = out->F;
+    a.bD = out->bD;
+    const bool genA = !(co->A[0] == 1.0 && co->A[1] == 0.0 && co->A[2] == 0.0 && co->A[3] == 1.0);
+    const bool hasAT = co->a_T != nullptr;
+    const bool withD = out->D != nullptr;
+    int rc;
+    if (!mats) rc = launch_assemble<false, false, false, false>(ctx, a);
+    else if (withD || genA) {
+        if (hasAT) rc = withD ? launch_assemble<true, true, true, true>(ctx, a)
+                              : launch_assemble<true, true, false, true>(ctx, a);
+        else rc = withD ? launch_assemble<false, true, true, true>(ctx, a)
+                        : launch_assemble<false, true, false, true>(ctx, a);
+    } else {
+        rc = hasAT ? launch_assemble<true, true, false, false>(ctx, a)
+                   : launch_assemble<false, true, false, false>(ctx, a);
+    }
+    if (rc) return rc;
+    if (out->S) {
+        SaddleArgs s;
+        s.nE = mesh->nE;
+        s.L = mesh->L;
+        s.nbE = a.nbE;
+        s.nbR = a.nbR;
+        s.elem4 = mesh->elem4;
+        s.xy = mesh->xy;
+        s.aT = co->a_T;
+        s.S_rowptr = mesh->S_rowptr;
+        s.C_rowptr = mesh->C_rowptr;
+        s.row_nodes = mesh->row_nodes;
+        s.A00 = co->A[0];
+        s.A01 = co->A[1];
+        s.A10 = co->A[2];
+        s.A11 = co->A[3];
+        s.p0 = co->p[0];
+        s.p1 = co->p[1];
+        s.delta = co->delta;
+        s.S = out->S;
+        PHF_LAUNCH(ctx, "k_saddle_values", k_saddle_values, s.nbE + s.nbR, TILE, 0, s);
+    }
+    return PHF_OK;
+}
+
+extern "C" int phf_assemble(phf_mesh* mesh, const phf_coeffs* coeffs, const phf_data* data,
+                            const phf_system* out)
+{
+    if (!mesh) return PHF_EINVAL;
+    return phf_assemble_impl(mesh, coeffs, data, out);
+}

@@ -1,0 +1,378 @@
+// Crank-Nicolson time stepping of the parabolic problem (Section 4.1):
+//   M+ W^n = M- W^{n-1} + [k F^{n-1/2}; b_D^{n-1/2}],
+// solved each step by the null-space CG of phf_solver with the constant
+// operator A+ = (1 + k delta/2) M + (k/2) K. With mu = (k/2) Lambda^n the
+// step is A+ U^n - C^T mu = r1, -C U^n = r2 where
+//   r1 = A- U^{n-1} + (k/2) C^T Lambda^{n-1} + (k/2)(F^{n-1} + F^n),
+//   r2 = C U^{n-1} + b_D^{n-1} + b_D^n,  A- = (1 - k delta/2) M - (k/2) K.
+// One step is a fixed kernel sequence whose only time input is a device step
+// counter, so it can be captured once in a HIP graph and replayed.
+#include <algorithm>
+#include <cmath>
+
+#include "phf_device.h"
+#include "phf_solver.h"
+
+struct phf_cn {
+    phf_mesh* mesh = nullptr;
+    phf_ns* ns = nullptr;
+    double k = 0, delta = 0;
+    phf_coeffs co{};
+    phf_cn_opts opts{};
+    double *K = nullptr, *M = nullptr, *C = nullptr, *Fs = nullptr, *bs = nullptr;
+    double *U = nullptr, *Lam = nullptr;
+    double *F0 = nullptr, *F1 = nullptr, *bD0 = nullptr, *bD1 = nullptr;
+    double *r1 = nullptr, *r2 = nullptr;
+    int64_t* d_step = nullptr;  // index n of the step being computed
+    double* d_stats = nullptr;  // [0] CG iterations, [1] worst relres, [2] unconverged steps
+    double t0 = 0;
+    int64_t n = 0;              // completed steps since set_state
+    bool have_state = false;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    phf_data gdata{};           // data the graph was captured with
+};
+
+namespace {
+constexpr int NT = 256;
+inline unsigned nblk(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
+
+#define TRY(x)               \
+    do {                     \
+        int rc_ = (x);       \
+        if (rc_) return rc_; \
+    } while (0)
+
+__global__ void k_cn_inc(int64_t* step) { *step += 1; }
+
+// r1 per element (see file comment).
+__global__ __launch_bounds__(NT) void k_cn_rhs_elem(
+    int32_t nE, const int4* __restrict__ elem4, const double* __restrict__ K,
+    const double* __restrict__ M, const double* __restrict__ U, const double* __restrict__ Lam,
+    const int32_t* __restrict__ elem_row, const double* __restrict__ row_h,
+    const double* __restrict__ F0, const double* __restrict__ F1, double cM, double cK,
+    double hk, double* __restrict__ r1)
+{
+    int32_t m = blockIdx.x * NT + threadIdx.x;
+    if (m >= nE) return;
+    const int code = elem4[m].w;
+    double u[3], lt[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        u[l] = U[3 * (int64_t)m + l];
+        // sigma_l h_l Lambda_row(l) for non-Neumann local edges
+        double v = 0.0;
+        if (PHF_CODE_TYPE(code, l) != 2) {
+            int32_t r = elem_row[3 * (int64_t)m + l];
+            v = (PHF_CODE_TPLUS(code, l) ? 1.0 : -1.0) * row_h[r] * Lam[r];
+        }
+        lt[l] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double* k = K + 9 * (int64_t)m + 3 * i;
+        const double* mm = M + 9 * (int64_t)m + 3 * i;
+        double au = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) au += (cM * mm[j] - cK * k[j]) * u[j];
+        // (C^T Lambda)_i = sum over the two edges through vertex i
+        double ctl = 0.0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) ctl += (l == i) ? 0.0 : lt[l];
+        r1[3 * (int64_t)m + i] =
+            au + hk * ctl + hk * (F0[3 * (int64_t)m + i] + F1[3 * (int64_t)m + i]);
+    }
+}
+
+// r2 per multiplier row: (C U)_r + b_D^{n-1} + b_D^n.
+__global__ __launch_bounds__(NT) void k_cn_rhs_row(int32_t L, const int32_t* __restrict__ C_rowptr,
+                                                   const int32_t* __restrict__ C_col,
+                                                   const double* __restrict__ C,
+                                                   const double* __restrict__ U,
+                                                   const double* __restrict__ bD0,
+                                                   const double* __restrict__ bD1,
+                                                   double* __restrict__ r2)
+{
+    int32_t r = blockIdx.x * NT + threadIdx.x;
+    if (r >= L) return;
+    double s = 0.0;
+    for (int32_t q = C_rowptr[r]; q < C_rowptr[r + 1]; ++q) s += C[q] * U[C_col[q]];
+    r2[r] = s + bD0[r] + bD1[r];
+}
+
+__global__ __launch_bounds__(NT) void k_cn_shift(int32_t N, int32_t L, double* __restrict__ F0,
+                                                 const double* __restrict__ F1,
+                                                 double* __restrict__ bD0,
+                                                 const double* __restrict__ bD1)
+{
+    int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (g < N) F0[g] = F1[g];
+    else if (g < (int64_t)N + L) bD0[g - N] = bD1[g - N];
+}
+
+__global__ void k_cn_stats(const int* __restrict__ iflags, const double* __restrict__ scal,
+                           double* __restrict__ st)
+{
+    st[0] += iflags[1];
+    double rel = scal[NS_BB] > 0 ? sqrt(scal[NS_RR] / scal[NS_BB]) : 0.0;
+    st[1] = fmax(st[1], rel);
+    st[2] += iflags[0] ? 0.0 : 1.0;
+}
+
+int cn_loads(phf_cn* cn, const phf_data* data, double* F, double* bD, bool from_device)
+{
+    phf_system s{};
+    s.F = F;
+    s.bD = bD;
+    if (from_device) return phf_assemble_impl(cn->mesh, &cn->co, data, &s, cn->d_step, cn->t0, cn->k);
+    phf_data d = *data;
+    d.t = cn->t0 + (double)cn->n * cn->k;
+    return phf_assemble_impl(cn->mesh, &cn->co, &d, &s);
+}
+
+// Everything of one step before the CG iterations.
+int cn_step_head(phf_cn* cn, const phf_data* data)
+{
+    phf_mesh* mesh = cn->mesh;
+    phf_ctx* ctx = mesh->ctx;
+    const int32_t nE = mesh->nE, L = mesh->L;
+    PHF_LAUNCH(ctx, "k_cn_inc", k_cn_inc, 1, 1, 0, cn->d_step);
+    TRY(cn_loads(cn, data, cn->F1, cn->bD1, true));
+    const double cM = 1.0 - 0.5 * cn->k * cn->delta, cK = 0.5 * cn->k, hk = 0.5 * cn->k;
+    PHF_LAUNCH(ctx, "k_cn_rhs_elem", k_cn_rhs_elem, nblk(nE), NT, 0, nE, mesh->elem4, cn->K, cn->M,
+               cn->U, cn->Lam, cn->ns->elem_row, cn->ns->row_h, cn->F0, cn->F1, cM, cK, hk, cn->r1);
+    if (L > 0)
+        PHF_LAUNCH(ctx, "k_cn_rhs_row", k_cn_rhs_row, nblk(L), NT, 0, L, mesh->C_rowptr,
+                   mesh->C_col, cn->C, cn->U, cn->bD0, cn->bD1, cn->r2);
+    TRY(phf_ns_rhs(cn->ns, cn->r1, cn->r2));
+    TRY(phf_ns_cg_start(cn->ns, cn->opts.rtol));
+    return PHF_OK;
+}
+
+int cn_step_tail(phf_cn* cn)
+{
+    phf_mesh* mesh = cn->mesh;
+    phf_ctx* ctx = mesh->ctx;
+    const int32_t N = 3 * mesh->nE, L = mesh->L;
+    TRY(phf_ns_recover(cn->ns, cn->r1, cn->U, cn->Lam, 2.0 / cn->k));
+    PHF_LAUNCH(ctx, "k_cn_shift", k_cn_shift, nblk((int64_t)N + L), NT, 0, N, L, cn->F0, cn->F1,
+               cn->bD0, cn->bD1);
+    PHF_LAUNCH(ctx, "k_cn_stats", k_cn_stats, 1, 1, 0, cn->ns->iflags, cn->ns->scal, cn->d_stats);
+    return PHF_OK;
+}
+
+void cn_drop_graph(phf_cn* cn)
+{
+    if (cn->gexec) (void)hipGraphExecDestroy(cn->gexec);
+    if (cn->graph) (void)hipGraphDestroy(cn->graph);
+    cn->gexec = nullptr;
+    cn->graph = nullptr;
+}
+
+bool same_fn(const phf_fn& a, const phf_fn& b)
+{
+    return a.kind == b.kind && a.c[0] == b.c[0] && a.c[1] == b.c[1] && a.c[2] == b.c[2] &&
+           a.c[3] == b.c[3] && a.edge_values == b.edge_values;
+}
+
+int cn_capture(phf_cn* cn, const phf_data* data)
+{
+    phf_ctx* ctx = cn->mesh->ctx;
+    hipStream_t cap = nullptr;
+    PHF_HIP(ctx, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipStream_t saved = ctx->stream;
+    bool saved_trace = ctx->trace;
+    ctx->stream = cap;
+    ctx->trace = false;
+    int rc = PHF_OK;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = cn_step_head(cn, data);
+        if (!rc) rc = phf_ns_cg_iterate(cn->ns, cn->opts.iters_per_step);
+        if (!rc) rc = cn_step_tail(cn);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cap, &g);
+        if (!rc && e2 != hipSuccess)
+            rc = phf_set_error(ctx, PHF_EHIP, "graph capture failed: %s", hipGetErrorString(e2));
+        if (!rc) {
+            cn->graph = g;
+            e2 = hipGraphInstantiate(&cn->gexec, g, nullptr, nullptr, 0);
+            if (e2 != hipSuccess)
+                rc = phf_set_error(ctx, PHF_EHIP, "graph instantiation failed: %s",
+                                   hipGetErrorString(e2));
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    } else {
+        rc = phf_set_error(ctx, PHF_EHIP, "begin capture failed: %s", hipGetErrorString(e));
+    }
+    ctx->stream = saved;
+    ctx->trace = saved_trace;
+    (void)hipStreamDestroy(cap);
+    if (rc) cn_drop_graph(cn);
+    else cn->gdata = *data;
+    return rc;
+}
+}  // namespace
+
+extern "C" int phf_cn_destroy(phf_cn* cn)
+{
+    if (!cn) return PHF_EINVAL;
+    (void)hipStreamSynchronize(cn->mesh->ctx->stream);
+    cn_drop_graph(cn);
+    if (cn->ns) phf_ns_destroy(cn->ns);
+    double* bufs[] = {cn->K, cn->M, cn->C, cn->Fs, cn->bs, cn->U, cn->Lam, cn->F0,
+                      cn->F1, cn->bD0, cn->bD1, cn->r1, cn->r2, cn->d_stats};
+    for (double* b : bufs) phf_dfree(b);
+    phf_dfree(cn->d_step);
+    delete cn;
+    return PHF_OK;
+}
+
+extern "C" int phf_cn_create(phf_mesh* mesh, const phf_coeffs* co, double k,
+                             const phf_cn_opts* opts, phf_cn** out)
+{
+    if (!mesh || !co || !out) return PHF_EINVAL;
+    phf_ctx* ctx = mesh->ctx;
+    *out = nullptr;
+    if (!(k > 0.0) || co->p[0] != 0.0 || co->p[1] != 0.0)
+        return phf_set_error(ctx, PHF_EINVAL, "phf_cn_create: need k > 0 and p = 0");
+    phf_cn* cn = new (std::nothrow) phf_cn;
+    if (!cn) return phf_set_error(ctx, PHF_ENOMEM, "host allocation failed");
+    cn->mesh = mesh;
+    cn->k = k;
+    cn->delta = co->delta;
+    cn->co = *co;
+    cn->opts.rtol = opts && opts->rtol > 0 ? opts->rtol : 1e-10;
+    cn->opts.max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 5000;
+    cn->opts.iters_per_step = opts && opts->iters_per_step > 0 ? opts->iters_per_step : 64;
+    const size_t N = 3 * (size_t)mesh->nE, L = mesh->L, nnzK = 9 * (size_t)mesh->nE;
+    auto body = [&]() -> int {
+        TRY(phf_dmalloc(ctx, &cn->K, nnzK, "CN K"));
+        TRY(phf_dmalloc(ctx, &cn->M, nnzK, "CN M"));
+        TRY(phf_dmalloc(ctx, &cn->C, mesh->nnz_C, "CN C"));
+        TRY(phf_dmalloc(ctx, &cn->Fs, N, "CN F"));
+        TRY(phf_dmalloc(ctx, &cn->bs, L, "CN bD"));
+        TRY(phf_dmalloc(ctx, &cn->U, N, "CN U"));
+        TRY(phf_dmalloc(ctx, &cn->Lam, L, "CN Lambda"));
+        TRY(phf_dmalloc(ctx, &cn->F0, N, "CN F0"));
+        TRY(phf_dmalloc(ctx, &cn->F1, N, "CN F1"));
+        TRY(phf_dmalloc(ctx, &cn->bD0, L, "CN bD0"));
+        TRY(phf_dmalloc(ctx, &cn->bD1, L, "CN bD1"));
+        TRY(phf_dmalloc(ctx, &cn->r1, N, "CN r1"));
+        TRY(phf_dmalloc(ctx, &cn->r2, L, "CN r2"));
+        TRY(phf_dmalloc(ctx, &cn->d_stats, 4, "CN stats"));
+        TRY(phf_dmalloc(ctx, &cn->d_step, 1, "CN step"));
+        // K, M, C once (the coefficient is time independent)
+        phf_system s{};
+        s.K = cn->K;
+        s.M = cn->M;
+        s.C = cn->C;
+        s.F = cn->Fs;
+        s.bD = cn->bs;
+        phf_data d{};
+        TRY(phf_assemble_impl(mesh, co, &d, &s));
+        TRY(phf_ns_create(mesh, &cn->ns));
+        TRY(phf_ns_operator(cn->ns, cn->K, cn->M, cn->C, 0.5 * k, 1.0 + 0.5 * k * co->delta));
+        PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        return PHF_OK;
+    };
+    int rc = body();
+    if (rc) {
+        phf_cn_destroy(cn);
+        return rc;
+    }
+    // the per-element coefficient is consumed by the assembly above
+    cn->co.a_T = nullptr;
+    *out = cn;
+    return PHF_OK;
+}
+
+extern "C" int phf_cn_set_state(phf_cn* cn, const double* U, const double* Lambda, double t)
+{
+    if (!cn || !U || !Lambda) return PHF_EINVAL;
+    phf_ctx* ctx = cn->mesh->ctx;
+    const size_t N = 3 * (size_t)cn->mesh->nE, L = cn->mesh->L;
+    PHF_HIP(ctx, hipMemcpyAsync(cn->U, U, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    if (L) PHF_HIP(ctx, hipMemcpyAsync(cn->Lam, Lambda, L * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    cn->t0 = t;
+    cn->n = 0;
+    cn->have_state = true;
+    TRY(phf_ns_zero_w(cn->ns));
+    return PHF_OK;
+}
+
+extern "C" int phf_cn_get_state(phf_cn* cn, double* U, double* Lambda, double* t)
+{
+    if (!cn) return PHF_EINVAL;
+    phf_ctx* ctx = cn->mesh->ctx;
+    const size_t N = 3 * (size_t)cn->mesh->nE, L = cn->mesh->L;
+    if (U) PHF_HIP(ctx, hipMemcpyAsync(U, cn->U, N * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    if (Lambda && L)
+        PHF_HIP(ctx, hipMemcpyAsync(Lambda, cn->Lam, L * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    if (t) *t = cn->t0 + (double)cn->n * cn->k;
+    return PHF_OK;
+}
+
+extern "C" int phf_cn_run(phf_cn* cn, const phf_data* data, int32_t nsteps, int32_t use_graph,
+                          phf_solve_stats* stats)
+{
+    if (!cn || !data || nsteps < 0) return PHF_EINVAL;
+    phf_ctx* ctx = cn->mesh->ctx;
+    if (!cn->have_state) return phf_set_error(ctx, PHF_ESTATE, "phf_cn_run: call phf_cn_set_state first");
+    if (!phf_fn_valid(data->f) || !phf_fn_valid(data->g) || !phf_fn_valid(data->uD))
+        return phf_set_error(ctx, PHF_EINVAL, "phf_cn_run: unknown function kind or missing edge array");
+    // loads at the current time and the device step counter
+    TRY(cn_loads(cn, data, cn->F0, cn->bD0, false));
+    int64_t n_host = cn->n;
+    PHF_HIP(ctx, hipMemcpyAsync(cn->d_step, &n_host, sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    PHF_HIP(ctx, hipMemsetAsync(cn->d_stats, 0, 4 * sizeof(double), ctx->stream));
+    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (use_graph) {
+        if (cn->gexec && !(same_fn(cn->gdata.f, data->f) && same_fn(cn->gdata.g, data->g) &&
+                           same_fn(cn->gdata.uD, data->uD)))
+            cn_drop_graph(cn);
+        if (!cn->gexec) TRY(cn_capture(cn, data));
+        for (int32_t s = 0; s < nsteps; ++s) {
+            phf_trace_rec rec;
+            phf_trace_begin(ctx, "cn_graph_step", &rec);
+            PHF_HIP(ctx, hipGraphLaunch(cn->gexec, ctx->stream));
+            phf_trace_end(ctx, &rec);
+        }
+    } else {
+        for (int32_t s = 0; s < nsteps; ++s) {
+            TRY(cn_step_head(cn, data));
+            int32_t it = 0;
+            double rel = 0;
+            int conv = 0;
+            // phf_ns_cg_solve restarts CG; call its loop body through the public pieces
+            int hf[2] = {0, 0};
+            PHF_HIP(ctx, hipMemcpyAsync(hf, cn->ns->iflags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+            PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            while (!hf[0] && it < cn->opts.max_iter) {
+                int32_t nb = std::min<int32_t>(8, cn->opts.max_iter - it);
+                TRY(phf_ns_cg_iterate(cn->ns, nb));
+                it += nb;
+                PHF_HIP(ctx, hipMemcpyAsync(hf, cn->ns->iflags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+                PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            }
+            (void)rel;
+            (void)conv;
+            TRY(cn_step_tail(cn));
+        }
+    }
+    double st[4] = {0, 0, 0, 0};
+    PHF_HIP(ctx, hipMemcpyAsync(st, cn->d_stats, sizeof(st), hipMemcpyDeviceToHost, ctx->stream));
+    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    cn->n += nsteps;
+    if (stats) {
+        stats->iterations = (int32_t)st[0];
+        stats->converged = st[2] == 0.0;
+        stats->rel_residual = st[1];
+        stats->saddle_rel_residual = -1.0;
+    }
+    if (st[2] != 0.0)
+        return phf_set_error(ctx, PHF_ENOCONV, "phf_cn_run: %d of %d steps did not reach rtol (worst %.3e)",
+                             (int)st[2], nsteps, st[1]);
+    return PHF_OK;
+}

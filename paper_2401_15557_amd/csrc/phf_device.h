@@ -1,0 +1,138 @@
+// Device-side helpers of libphfem: wavefront/block reductions and scans
+// (wave64), and the problem-data function catalogue.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "phf_internal.h"
+
+#define PHF_PI 3.14159265358979323846
+
+// Inclusive sum over the 64 lanes of a wavefront (lane order fixed).
+template <typename T>
+__device__ inline T phf_wave_inclusive_scan(T x)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Exclusive block scan of one int32 per thread; *total = block sum.
+// sh needs NT/64 + 1 ints. Contains barriers: call from all threads.
+template <int NT>
+__device__ inline int32_t phf_block_exscan_i32(int32_t v, int32_t* sh, int32_t* total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int32_t x = phf_wave_inclusive_scan(v);
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    int32_t woff = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+        int32_t s = sh[w];
+        woff += (w < wid) ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return woff + x - v;
+}
+
+// Tree sum over a wavefront with a fixed pairing (bitwise reproducible).
+template <typename T>
+__device__ inline T phf_wave_sum(T x)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+template <int NT>
+__device__ inline int32_t phf_block_sum_i32(int32_t v, int32_t* sh)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int32_t x = phf_wave_sum(v);
+    if (lane == 0) sh[wid] = x;
+    __syncthreads();
+    int32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) tot += sh[w];
+    __syncthreads();
+    return tot;
+}
+
+// Block sum of doubles in a fixed order: wave trees, then waves in order.
+template <int NT>
+__device__ inline double phf_block_sum_f64(double v, double* sh)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double x = phf_wave_sum(v);
+    if (lane == 0) sh[wid] = x;
+    __syncthreads();
+    double tot = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) tot += sh[w];
+    __syncthreads();
+    return tot;
+}
+
+// Problem data (phfem.h PHF_FN_*): value at (x, y, t); flux kinds return the
+// flux vector dotted with (nx, ny); PHF_FN_EDGE_ARRAY reads ev[edge].
+__device__ inline double phf_fn_eval(const phf_fn_dev& f, double x, double y, double t, double nx,
+                                     double ny, int32_t edge)
+{
+    switch (f.kind) {
+    case PHF_FN_ZERO: return 0.0;
+    case PHF_FN_CONST: return f.c0;
+    case PHF_FN_SIN_COS:
+        return f.c0 * exp(f.c1 * t) * sin(PHF_PI * x) * cos(PHF_PI * y);
+    case PHF_FN_SIN_SIN:
+        return f.c0 * exp(f.c1 * t) * sin(PHF_PI * x) * sin(PHF_PI * y);
+    case PHF_FN_GRAD_SIN_COS: {
+        double sx = sin(PHF_PI * x), cx = cos(PHF_PI * x);
+        double sy = sin(PHF_PI * y), cy = cos(PHF_PI * y);
+        return f.c0 * exp(f.c1 * t) * (PHF_PI * cx * cy * nx - PHF_PI * sx * sy * ny);
+    }
+    case PHF_FN_GRAD_SIN_SIN: {
+        double sx = sin(PHF_PI * x), cx = cos(PHF_PI * x);
+        double sy = sin(PHF_PI * y), cy = cos(PHF_PI * y);
+        return f.c0 * exp(f.c1 * t) * (PHF_PI * cx * sy * nx + PHF_PI * sx * cy * ny);
+    }
+    case PHF_FN_PAPER_U: return (f.c0 + f.c1 * t) * (x - x * x) * (y - y * y);
+    case PHF_FN_PAPER_F: {
+        double a = x - x * x, b = y - y * y, tau = f.c0 + f.c1 * t;
+        return f.c1 * a * b +
+               tau * (2.0 * b + 2.0 * a + (1.0 - 2.0 * x) * b + a * (1.0 - 2.0 * y) + a * b);
+    }
+    case PHF_FN_PAPER_FLUX: {
+        double tau = f.c0 + f.c1 * t;
+        double qx = (1.0 - x - x * x) * (y - y * y);
+        double qy = (x - x * x) * (1.0 - y - y * y);
+        return tau * (qx * nx + qy * ny);
+    }
+    case PHF_FN_EDGE_ARRAY: return f.ev[edge];
+    default: return 0.0;
+    }
+}
+
+// Maps a linear block index so that consecutive tiles stay on one XCD: the
+// hardware deals workgroups round-robin over the 8 XCDs of an MI355X, so
+// block b runs on XCD b % 8; giving XCD x the contiguous tile range
+// [x * per, (x + 1) * per) keeps neighbouring tiles (which share vertices)
+// in the same L2.
+__device__ inline int32_t phf_xcd_tile(int32_t b, int32_t nblocks)
+{
+    const int32_t nx = 8;
+    int32_t per = nblocks / nx, rem = nblocks % nx;
+    int32_t x = b % nx, k = b / nx;
+    // XCDs x < rem own per + 1 tiles, the others per
+    int32_t start = x * per + (x < rem ? x : rem);
+    int32_t own = per + (x < rem ? 1 : 0);
+    return k < own ? start + k : b;  // (k < own always holds)
+}

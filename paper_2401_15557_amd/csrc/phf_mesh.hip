@@ -1,0 +1,825 @@
+// Mesh upload, validation, edge topology (Section 2.2), boundary
+// classification and CSR patterns (Section 3.5) on the device.
+//
+// Edge numbering: an edge {a, b} has key (max, min); edges are numbered in
+// ascending key order. The build is a counting sort of the 3 nE directed
+// local edges by their larger node (integer atomics count bucket sizes and
+// hand out slots; the order inside a bucket is then fixed by sorting on
+// (smaller node, position 3m+j)), so every output is independent of atomic
+// ordering. T+ of an edge is its first occurrence in element order.
+#include <cstring>
+
+#include "phf_device.h"
+#include "phf_internal.h"
+
+namespace {
+
+enum : int { FLAG_RANGE = 1, FLAG_ORIENT = 2, FLAG_MESH = 4, FLAG_BOUNDARY = 8 };
+
+__device__ inline void raise_flag(int* flags, int bit, int32_t where)
+{
+    atomicOr(&flags[0], bit);
+    atomicMin(&flags[1], where);
+}
+
+// Validates element m, stores its record and counts its directed edges.
+__global__ __launch_bounds__(256) void k_elem_init(const int32_t* __restrict__ raw, int32_t nE,
+                                                   int32_t nC, const double2* __restrict__ xy,
+                                                   int4* __restrict__ elem4,
+                                                   int32_t* __restrict__ bucket_count,
+                                                   int* flags)
+{
+    int32_t m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= nE) return;
+    int32_t v0 = raw[3 * (int64_t)m], v1 = raw[3 * (int64_t)m + 1], v2 = raw[3 * (int64_t)m + 2];
+    if (v0 < 0 || v0 >= nC || v1 < 0 || v1 >= nC || v2 < 0 || v2 >= nC) {
+        raise_flag(flags, FLAG_RANGE, m);
+        return;
+    }
+    if (v0 == v1 || v1 == v2 || v0 == v2) {
+        raise_flag(flags, FLAG_ORIENT, m);
+        return;
+    }
+    double2 p0 = xy[v0], p1 = xy[v1], p2 = xy[v2];
+    double det = (p1.x - p0.x) * (p2.y - p0.y) - (p2.x - p0.x) * (p1.y - p0.y);
+    if (!(det > 0.0)) raise_flag(flags, FLAG_ORIENT, m);
+    elem4[m] = make_int4(v0, v1, v2, 0);
+    atomicAdd(&bucket_count[max(v0, v1)], 1);
+    atomicAdd(&bucket_count[max(v1, v2)], 1);
+    atomicAdd(&bucket_count[max(v2, v0)], 1);
+}
+
+__global__ __launch_bounds__(256) void k_fill(const int4* __restrict__ elem4, int32_t nE,
+                                              const int32_t* __restrict__ bucket_off,
+                                              int32_t* __restrict__ cursor,
+                                              uint64_t* __restrict__ keys)
+{
+    int32_t m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= nE) return;
+    int4 e = elem4[m];
+    int32_t v[3] = {e.x, e.y, e.z};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        int32_t a = v[j], b = v[(j + 1) % 3];
+        int32_t hi = max(a, b), lo = min(a, b);
+        int32_t slot = bucket_off[hi] + atomicAdd(&cursor[hi], 1);
+        keys[slot] = ((uint64_t)(uint32_t)lo << 32) | (uint32_t)(3 * m + j);
+    }
+}
+
+__device__ inline int32_t start_node(const int4* elem4, uint32_t pos)
+{
+    int4 e = elem4[pos / 3];
+    int j = pos % 3;
+    return j == 0 ? e.x : (j == 1 ? e.y : e.z);
+}
+
+// Sorts bucket v by (smaller node, position) and counts its distinct edges.
+__global__ __launch_bounds__(256) void k_bucket_sort(uint64_t* __restrict__ keys,
+                                                     const int32_t* __restrict__ bucket_off,
+                                                     int32_t nC, const int4* __restrict__ elem4,
+                                                     int32_t* __restrict__ ucount, int* flags)
+{
+    int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= nC) return;
+    int32_t b0 = bucket_off[v], b1 = bucket_off[v + 1];
+    // insertion sort in place (buckets hold ~2 x the lower-neighbour count)
+    for (int32_t q = b0 + 1; q < b1; ++q) {
+        uint64_t k = keys[q];
+        int32_t s = q - 1;
+        while (s >= b0 && keys[s] > k) {
+            keys[s + 1] = keys[s];
+            --s;
+        }
+        keys[s + 1] = k;
+    }
+    int32_t n = 0;
+    int32_t q = b0;
+    while (q < b1) {
+        uint32_t lo = (uint32_t)(keys[q] >> 32);
+        int32_t t = q + 1;
+        while (t < b1 && (uint32_t)(keys[t] >> 32) == lo) ++t;
+        if (t - q > 2) {
+            raise_flag(flags, FLAG_MESH, (int32_t)((uint32_t)keys[q] / 3));
+        } else if (t - q == 2) {
+            uint32_t p0 = (uint32_t)keys[q], p1 = (uint32_t)keys[q + 1];
+            if (start_node(elem4, p0) == start_node(elem4, p1))
+                raise_flag(flags, FLAG_MESH, (int32_t)(p1 / 3));
+        }
+        ++n;
+        q = t;
+    }
+    ucount[v] = n;
+}
+
+// Writes the edge tables of bucket v (edges eoff[v] .. eoff[v+1]-1).
+__global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ keys,
+                                              const int32_t* __restrict__ bucket_off,
+                                              const int32_t* __restrict__ eoff, int32_t nC,
+                                              const int4* __restrict__ elem4,
+                                              int2* __restrict__ edge_nodes,
+                                              int2* __restrict__ edge_elems,
+                                              int32_t* __restrict__ elem_edges,
+                                              int8_t* __restrict__ led, int8_t* __restrict__ ledTN)
+{
+    int32_t v = blockIdx.x * 256 + threadIdx.x;
+    if (v >= nC) return;
+    int32_t b0 = bucket_off[v], b1 = bucket_off[v + 1];
+    int32_t e = eoff[v];
+    int32_t q = b0;
+    while (q < b1) {
+        uint32_t lo = (uint32_t)(keys[q] >> 32);
+        int32_t t = q + 1;
+        while (t < b1 && (uint32_t)(keys[t] >> 32) == lo) ++t;
+        uint32_t p = (uint32_t)keys[q];
+        int32_t m = (int32_t)(p / 3), j = (int32_t)(p % 3);
+        int4 el = elem4[m];
+        int32_t vv[3] = {el.x, el.y, el.z};
+        edge_nodes[e] = make_int2(vv[j], vv[(j + 1) % 3]);
+        int8_t lp = (int8_t)((j + 2) % 3);
+        led[e] = lp;
+        elem_edges[3 * (int64_t)m + lp] = e;
+        if (t - q >= 2) {
+            uint32_t p2 = (uint32_t)keys[q + 1];
+            int32_t m2 = (int32_t)(p2 / 3), j2 = (int32_t)(p2 % 3);
+            int8_t ln = (int8_t)((j2 + 2) % 3);
+            edge_elems[e] = make_int2(m, m2);
+            ledTN[e] = ln;
+            elem_edges[3 * (int64_t)m2 + ln] = e;
+        } else {
+            edge_elems[e] = make_int2(m, -1);
+            ledTN[e] = lp;
+        }
+        ++e;
+        q = t;
+    }
+}
+
+__device__ inline int32_t find_edge(int32_t a, int32_t b, const int32_t* eoff,
+                                    const int2* edge_nodes)
+{
+    int32_t hi = max(a, b), lo = min(a, b);
+    int32_t L = eoff[hi], R = eoff[hi + 1] - 1;
+    while (L <= R) {
+        int32_t mid = L + (R - L) / 2;
+        int2 kl = edge_nodes[mid];
+        int32_t l2 = min(kl.x, kl.y);
+        if (l2 == lo) return mid;
+        if (l2 < lo) L = mid + 1;
+        else R = mid - 1;
+    }
+    return -1;
+}
+
+// One thread per listed boundary pair (Dirichlet first, then Neumann).
+__global__ __launch_bounds__(256) void k_boundary_mark(
+    const int32_t* __restrict__ dir, int32_t nD, const int32_t* __restrict__ neu, int32_t nN,
+    int32_t nC, const int32_t* __restrict__ eoff, const int2* __restrict__ edge_nodes,
+    const int2* __restrict__ edge_elems, int32_t* __restrict__ mark, int8_t* __restrict__ etype,
+    int32_t* __restrict__ dir_edges, int32_t* __restrict__ neu_edges, int* flags)
+{
+    int32_t q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= nD + nN) return;
+    bool isD = q < nD;
+    const int32_t* pr = isD ? dir + 2 * (int64_t)q : neu + 2 * (int64_t)(q - nD);
+    int32_t a = pr[0], b = pr[1];
+    if (a < 0 || a >= nC || b < 0 || b >= nC || a == b) {
+        raise_flag(flags, FLAG_BOUNDARY, q);
+        return;
+    }
+    int32_t e = find_edge(a, b, eoff, edge_nodes);
+    if (e < 0 || edge_elems[e].y >= 0) {
+        raise_flag(flags, FLAG_BOUNDARY, q);
+        return;
+    }
+    if (atomicAdd(&mark[e], 1) != 0) {
+        raise_flag(flags, FLAG_BOUNDARY, q);
+        return;
+    }
+    etype[e] = isD ? 1 : 2;
+    if (isD) dir_edges[q] = e;
+    else neu_edges[q - nD] = e;
+}
+
+// Checks that every boundary edge was listed; writes the 0/1 indicator and
+// row-length arrays scanned into row numbers and C row pointers.
+__global__ __launch_bounds__(256) void k_boundary_check(
+    int32_t n_edges, const int2* __restrict__ edge_elems, const int32_t* __restrict__ mark,
+    const int8_t* __restrict__ etype, int32_t* __restrict__ nonN, int32_t* __restrict__ nonD,
+    int32_t* __restrict__ clen, int32_t* __restrict__ interior, int* flags)
+{
+    int32_t e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n_edges) return;
+    bool bnd = edge_elems[e].y < 0;
+    if (bnd && mark[e] == 0) raise_flag(flags, FLAG_BOUNDARY, e);
+    int t = etype[e];
+    nonN[e] = t != 2;
+    nonD[e] = t != 1;
+    clen[e] = t == 0 ? 4 : (t == 1 ? 2 : 0);
+    interior[e] = !bnd;
+}
+
+// Multiplier-row tables and the C pattern (row = edge_row[e]).
+__global__ __launch_bounds__(256) void k_rows(
+    int32_t n_edges, const int8_t* __restrict__ etype, const int32_t* __restrict__ rowscan,
+    const int32_t* __restrict__ redscan, const int32_t* __restrict__ cptr,
+    const int2* __restrict__ edge_nodes, const int2* __restrict__ edge_elems,
+    const int8_t* __restrict__ led, const int8_t* __restrict__ ledTN,
+    int32_t* __restrict__ edge_row, int32_t* __restrict__ red_row,
+    int32_t* __restrict__ red_edge, int32_t* __restrict__ row_edge,
+    int2* __restrict__ row_nodes, int32_t* __restrict__ C_rowptr, int32_t* __restrict__ C_col)
+{
+    int32_t e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n_edges) return;
+    int t = etype[e];
+    if (t == 1) {
+        red_row[e] = -1;
+    } else {
+        red_row[e] = redscan[e];
+        red_edge[redscan[e]] = e;
+    }
+    if (t == 2) {
+        edge_row[e] = -1;
+        return;
+    }
+    int32_t r = rowscan[e];
+    edge_row[e] = r;
+    row_edge[r] = e;
+    row_nodes[r] = edge_nodes[e];
+    int32_t c = cptr[e];
+    C_rowptr[r] = c;
+    int2 tt = edge_elems[e];
+    // vertex DOFs of the edge in T+ (the two local vertices != led), ascending
+    int lp = led[e];
+    int a = lp == 0 ? 1 : 0, b = lp == 2 ? 1 : 2;
+    C_col[c] = 3 * tt.x + a;
+    C_col[c + 1] = 3 * tt.x + b;
+    if (t == 0) {
+        int ln = ledTN[e];
+        int a2 = ln == 0 ? 1 : 0, b2 = ln == 2 ? 1 : 2;
+        C_col[c + 2] = 3 * tt.y + a2;
+        C_col[c + 3] = 3 * tt.y + b2;
+    }
+}
+
+// Element code words and the saddle row lengths of the element's DOF rows.
+__global__ __launch_bounds__(256) void k_elem_codes(int32_t nE, int4* __restrict__ elem4,
+                                                    const int32_t* __restrict__ elem_edges,
+                                                    const int8_t* __restrict__ etype,
+                                                    const int2* __restrict__ edge_elems,
+                                                    int32_t* __restrict__ slen)
+{
+    int32_t m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= nE) return;
+    int32_t ed[3];
+    int tp[3];
+    int code = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        ed[i] = elem_edges[3 * (int64_t)m + i];
+        tp[i] = etype[ed[i]];
+        code |= tp[i] << (2 * i);
+        if (edge_elems[ed[i]].x == m) code |= 1 << (6 + i);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        int l1 = i == 0 ? 1 : 0, l2 = i == 2 ? 1 : 2;
+        if (ed[l1] > ed[l2]) code |= 1 << (9 + i);
+        slen[3 * (int64_t)m + i] = 3 + (tp[l1] != 2) + (tp[l2] != 2);
+    }
+    elem4[m].w = code;
+}
+
+__global__ __launch_bounds__(256) void k_saddle_rowlen(int32_t L, const int32_t* __restrict__ C_rowptr,
+                                                       int32_t nnzC, int32_t* __restrict__ slen)
+{
+    int32_t r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= L) return;
+    int32_t c1 = r + 1 < L ? C_rowptr[r + 1] : nnzC;
+    slen[r] = c1 - C_rowptr[r];
+}
+
+// Saddle pattern columns: DOF rows 3m+i then multiplier rows N + r.
+__global__ __launch_bounds__(256) void k_saddle_cols(
+    int32_t nE, int32_t L, const int4* __restrict__ elem4, const int32_t* __restrict__ elem_edges,
+    const int32_t* __restrict__ edge_row, const int32_t* __restrict__ C_rowptr,
+    const int32_t* __restrict__ C_col, const int32_t* __restrict__ S_rowptr,
+    int32_t* __restrict__ S_col)
+{
+    int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int32_t N = 3 * nE;
+    if (g < N) {
+        int32_t m = (int32_t)(g / 3), i = (int32_t)(g % 3);
+        int code = elem4[m].w;
+        int32_t s = S_rowptr[g];
+        S_col[s] = 3 * m;
+        S_col[s + 1] = 3 * m + 1;
+        S_col[s + 2] = 3 * m + 2;
+        int l1 = i == 0 ? 1 : 0, l2 = i == 2 ? 1 : 2;
+        if (PHF_CODE_SWAP(code, i)) {
+            int t = l1;
+            l1 = l2;
+            l2 = t;
+        }
+        int32_t k = s + 3;
+        if (PHF_CODE_TYPE(code, l1) != 2) S_col[k++] = N + edge_row[elem_edges[3 * (int64_t)m + l1]];
+        if (PHF_CODE_TYPE(code, l2) != 2) S_col[k++] = N + edge_row[elem_edges[3 * (int64_t)m + l2]];
+    } else if (g < (int64_t)N + L) {
+        int32_t r = (int32_t)(g - N);
+        int32_t s = S_rowptr[g];
+        int32_t c0 = C_rowptr[r], c1 = C_rowptr[r + 1];
+        for (int32_t q = c0; q < c1; ++q) S_col[s + (q - c0)] = C_col[q];
+    }
+}
+
+// Reduced (edge-midpoint) operator pattern: row of free edge e couples e with
+// the other free edges of T+ and T-. Pass 0 counts, pass 1 fills.
+__device__ inline int reduced_entries(int32_t e, const int2* edge_elems, const int8_t* led,
+                                      const int8_t* ledTN, const int32_t* elem_edges,
+                                      const int32_t* red_row, int32_t* col, int32_t* s0,
+                                      int32_t* s1)
+{
+    int n = 0;
+    int2 tt = edge_elems[e];
+    int lp = led[e];
+    // diagonal: block (lp, lp) of T+ plus (ln, ln) of T-
+    col[n] = red_row[e];
+    s0[n] = 9 * tt.x + 4 * lp;
+    s1[n] = tt.y >= 0 ? 9 * tt.y + 4 * ledTN[e] : -1;
+    ++n;
+    for (int side = 0; side < 2; ++side) {
+        int32_t T = side == 0 ? tt.x : tt.y;
+        if (T < 0) continue;
+        int le = side == 0 ? lp : ledTN[e];
+        for (int o = 0; o < 3; ++o) {
+            if (o == le) continue;
+            int32_t e2 = elem_edges[3 * (int64_t)T + o];
+            int32_t r2 = red_row[e2];
+            if (r2 < 0) continue;
+            col[n] = r2;
+            s0[n] = 9 * T + 3 * le + o;
+            s1[n] = -1;
+            ++n;
+        }
+    }
+    // sort by column (at most 5 entries)
+    for (int a = 1; a < n; ++a) {
+        int32_t c = col[a], x0 = s0[a], x1 = s1[a];
+        int b = a - 1;
+        while (b >= 0 && col[b] > c) {
+            col[b + 1] = col[b];
+            s0[b + 1] = s0[b];
+            s1[b + 1] = s1[b];
+            --b;
+        }
+        col[b + 1] = c;
+        s0[b + 1] = x0;
+        s1[b + 1] = x1;
+    }
+    return n;
+}
+
+__global__ __launch_bounds__(256) void k_reduced_pattern(
+    int32_t n_free, int pass, const int32_t* __restrict__ red_edge,
+    const int2* __restrict__ edge_elems, const int8_t* __restrict__ led,
+    const int8_t* __restrict__ ledTN, const int32_t* __restrict__ elem_edges,
+    const int32_t* __restrict__ red_row, int32_t* __restrict__ rlen,
+    const int32_t* __restrict__ R_rowptr, int32_t* __restrict__ R_col,
+    int32_t* __restrict__ R_src)
+{
+    int32_t r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= n_free) return;
+    int32_t col[5], s0[5], s1[5];
+    int n = reduced_entries(red_edge[r], edge_elems, led, ledTN, elem_edges, red_row, col, s0, s1);
+    if (pass == 0) {
+        rlen[r] = n;
+        return;
+    }
+    int32_t p = R_rowptr[r];
+    for (int q = 0; q < n; ++q) {
+        R_col[p + q] = col[q];
+        R_src[2 * (int64_t)(p + q)] = s0[q];
+        R_src[2 * (int64_t)(p + q) + 1] = s1[q];
+    }
+}
+
+__global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+static void mesh_free(phf_mesh* m)
+{
+    if (m->ns) phf_ns_destroy(m->ns);
+    m->ns = nullptr;
+    phf_dfree(m->xy);
+    phf_dfree(m->elem4);
+    phf_dfree(m->edge_nodes);
+    phf_dfree(m->edge_elems);
+    phf_dfree(m->elem_edges);
+    phf_dfree(m->led);
+    phf_dfree(m->ledTN);
+    phf_dfree(m->edge_type);
+    phf_dfree(m->edge_row);
+    phf_dfree(m->dir_edges);
+    phf_dfree(m->neu_edges);
+    phf_dfree(m->row_edge);
+    phf_dfree(m->row_nodes);
+    phf_dfree(m->C_rowptr);
+    phf_dfree(m->C_col);
+    phf_dfree(m->S_rowptr);
+    phf_dfree(m->S_col);
+    phf_dfree(m->red_row);
+    phf_dfree(m->red_edge);
+    phf_dfree(m->R_rowptr);
+    phf_dfree(m->R_col);
+    phf_dfree(m->R_src);
+}
+
+namespace {
+// Temporaries of the mesh build, freed on every exit path.
+struct build_tmp {
+    int32_t* raw = nullptr;
+    int32_t* bcount = nullptr;
+    int32_t* boff = nullptr;
+    uint64_t* keys = nullptr;
+    int32_t* ucount = nullptr;
+    int32_t* eoff = nullptr;
+    int32_t* dirp = nullptr;
+    int32_t* neup = nullptr;
+    int32_t* mark = nullptr;
+    int32_t* nonN = nullptr;
+    int32_t* nonD = nullptr;
+    int32_t* clen = nullptr;
+    int32_t* inter = nullptr;
+    int32_t* slen = nullptr;
+    int32_t* totals = nullptr;
+    ~build_tmp()
+    {
+        phf_dfree(raw); phf_dfree(bcount); phf_dfree(boff); phf_dfree(keys);
+        phf_dfree(ucount); phf_dfree(eoff); phf_dfree(dirp); phf_dfree(neup);
+        phf_dfree(mark); phf_dfree(nonN); phf_dfree(nonD); phf_dfree(clen);
+        phf_dfree(inter); phf_dfree(slen); phf_dfree(totals);
+    }
+};
+
+int read_flags(phf_ctx* ctx, int* code, int* where)
+{
+    int h[2];
+    PHF_HIP(ctx, hipMemcpyAsync(h, ctx->d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                                ctx->stream));
+    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    *code = h[0];
+    *where = h[1];
+    return PHF_OK;
+}
+
+int flags_to_status(phf_ctx* ctx, int bits, int where, const char* stage)
+{
+    if (bits & FLAG_RANGE)
+        return phf_set_error(ctx, PHF_EINVAL, "%s: element %d has a node index out of range",
+                             stage, where);
+    if (bits & FLAG_ORIENT)
+        return phf_set_error(ctx, PHF_EORIENT,
+                             "%s: element %d is clockwise, degenerate or has zero area", stage,
+                             where);
+    if (bits & FLAG_MESH)
+        return phf_set_error(ctx, PHF_EMESH,
+                             "%s: an edge of element %d is shared by more than two elements or "
+                             "traversed in the same direction by both neighbours",
+                             stage, where);
+    if (bits & FLAG_BOUNDARY)
+        return phf_set_error(ctx, PHF_EBOUNDARY,
+                             "%s: boundary pair/edge %d is not a boundary edge, is listed twice "
+                             "or a boundary edge is in neither list",
+                             stage, where);
+    return PHF_OK;
+}
+
+int reset_flags(phf_ctx* ctx)
+{
+    int h[2] = {0, 0x7fffffff};
+    PHF_HIP(ctx, hipMemcpyAsync(ctx->d_flags, h, 2 * sizeof(int), hipMemcpyHostToDevice,
+                                ctx->stream));
+    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PHF_OK;
+}
+
+int read_i32(phf_ctx* ctx, const int32_t* d, int32_t* h)
+{
+    PHF_HIP(ctx, hipMemcpyAsync(h, d, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PHF_OK;
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+#define TRY(x)                 \
+    do {                       \
+        int rc_ = (x);         \
+        if (rc_) return rc_;   \
+    } while (0)
+
+int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t* dir,
+               const int32_t* neu, phf_memspace ms)
+{
+    phf_ctx* ctx = M->ctx;
+    build_tmp T;
+    const int32_t nC = M->nC, nE = M->nE, nD = M->nD, nN = M->nN;
+    hipMemcpyKind kind = ms == PHF_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    int bits = 0, where = 0;
+
+    TRY(phf_dmalloc(ctx, &M->xy, nC, "coordinates"));
+    TRY(phf_dmalloc(ctx, &M->elem4, nE, "elements"));
+    TRY(phf_dmalloc(ctx, &T.raw, 3 * (size_t)nE, "element input"));
+    TRY(phf_dmalloc(ctx, &T.bcount, (size_t)nC + 1, "bucket counts"));
+    TRY(phf_dmalloc(ctx, &T.boff, (size_t)nC + 1, "bucket offsets"));
+    TRY(phf_dmalloc(ctx, &T.totals, 8, "totals"));
+    PHF_HIP(ctx, hipMemcpyAsync(M->xy, xy, sizeof(double2) * nC, kind, ctx->stream));
+    PHF_HIP(ctx, hipMemcpyAsync(T.raw, elem, sizeof(int32_t) * 3 * (size_t)nE, kind, ctx->stream));
+    PHF_HIP(ctx, hipMemsetAsync(T.bcount, 0, sizeof(int32_t) * ((size_t)nC + 1), ctx->stream));
+    TRY(reset_flags(ctx));
+
+    // a1: validation + bucket counts by larger node
+    PHF_LAUNCH(ctx, "k_elem_init", k_elem_init, nblk(nE), 256, 0, T.raw, nE, nC, M->xy, M->elem4,
+               T.bcount, ctx->d_flags);
+    TRY(read_flags(ctx, &bits, &where));
+    TRY(flags_to_status(ctx, bits, where, "validation"));
+    phf_dfree(T.raw);
+
+    // a2: counting sort of directed edges, per-bucket sort, unique count
+    TRY(phf_scan_i32(ctx, T.bcount, T.boff, nC + 1, nullptr));
+    TRY(phf_dmalloc(ctx, &T.keys, 3 * (size_t)nE, "edge keys"));
+    PHF_HIP(ctx, hipMemsetAsync(T.bcount, 0, sizeof(int32_t) * ((size_t)nC + 1), ctx->stream));
+    PHF_LAUNCH(ctx, "k_fill", k_fill, nblk(nE), 256, 0, M->elem4, nE, T.boff, T.bcount, T.keys);
+    TRY(phf_dmalloc(ctx, &T.ucount, (size_t)nC + 1, "unique counts"));
+    TRY(phf_dmalloc(ctx, &T.eoff, (size_t)nC + 1, "edge offsets"));
+    PHF_LAUNCH(ctx, "k_bucket_sort", k_bucket_sort, nblk(nC), 256, 0, T.keys, T.boff, nC,
+               M->elem4, T.ucount, ctx->d_flags);
+    TRY(read_flags(ctx, &bits, &where));
+    TRY(flags_to_status(ctx, bits, where, "topology"));
+    PHF_HIP(ctx, hipMemsetAsync(T.ucount + nC, 0, sizeof(int32_t), ctx->stream));
+    TRY(phf_scan_i32(ctx, T.ucount, T.eoff, nC + 1, T.totals));
+    int32_t ne = 0;
+    TRY(read_i32(ctx, T.totals, &ne));
+    M->n_edges = ne;
+    TRY(phf_dmalloc(ctx, &M->edge_nodes, ne, "edge nodes"));
+    TRY(phf_dmalloc(ctx, &M->edge_elems, ne, "edge elements"));
+    TRY(phf_dmalloc(ctx, &M->elem_edges, 3 * (size_t)nE, "element edges"));
+    TRY(phf_dmalloc(ctx, &M->led, ne, "led"));
+    TRY(phf_dmalloc(ctx, &M->ledTN, ne, "ledTN"));
+    PHF_LAUNCH(ctx, "k_emit", k_emit, nblk(nC), 256, 0, T.keys, T.boff, T.eoff, nC, M->elem4,
+               M->edge_nodes, M->edge_elems, M->elem_edges, M->led, M->ledTN);
+    phf_dfree(T.keys);
+    phf_dfree(T.bcount);
+    phf_dfree(T.boff);
+    phf_dfree(T.ucount);
+
+    // a3: boundary classification
+    TRY(phf_dmalloc(ctx, &M->edge_type, ne, "edge types"));
+    TRY(phf_dmalloc(ctx, &M->dir_edges, nD, "Dirichlet edges"));
+    TRY(phf_dmalloc(ctx, &M->neu_edges, nN, "Neumann edges"));
+    TRY(phf_dmalloc(ctx, &T.mark, ne, "edge marks"));
+    TRY(phf_dmalloc(ctx, &T.dirp, 2 * (size_t)nD, "Dirichlet pairs"));
+    TRY(phf_dmalloc(ctx, &T.neup, 2 * (size_t)nN, "Neumann pairs"));
+    if (nD) PHF_HIP(ctx, hipMemcpyAsync(T.dirp, dir, sizeof(int32_t) * 2 * (size_t)nD, kind, ctx->stream));
+    if (nN) PHF_HIP(ctx, hipMemcpyAsync(T.neup, neu, sizeof(int32_t) * 2 * (size_t)nN, kind, ctx->stream));
+    PHF_HIP(ctx, hipMemsetAsync(M->edge_type, 0, ne, ctx->stream));
+    PHF_HIP(ctx, hipMemsetAsync(T.mark, 0, sizeof(int32_t) * ne, ctx->stream));
+    TRY(reset_flags(ctx));
+    if (nD + nN > 0)
+        PHF_LAUNCH(ctx, "k_boundary_mark", k_boundary_mark, nblk(nD + nN), 256, 0, T.dirp, nD,
+                   T.neup, nN, nC, T.eoff, M->edge_nodes, M->edge_elems, T.mark, M->edge_type,
+                   M->dir_edges, M->neu_edges, ctx->d_flags);
+    TRY(phf_dmalloc(ctx, &T.nonN, (size_t)ne + 1, "row indicator"));
+    TRY(phf_dmalloc(ctx, &T.nonD, (size_t)ne + 1, "reduced indicator"));
+    TRY(phf_dmalloc(ctx, &T.clen, (size_t)ne + 1, "C row lengths"));
+    TRY(phf_dmalloc(ctx, &T.inter, (size_t)ne + 1, "interior indicator"));
+    PHF_LAUNCH(ctx, "k_boundary_check", k_boundary_check, nblk(ne), 256, 0, ne, M->edge_elems,
+               T.mark, M->edge_type, T.nonN, T.nonD, T.clen, T.inter, ctx->d_flags);
+    TRY(read_flags(ctx, &bits, &where));
+    TRY(flags_to_status(ctx, bits, where, "boundary"));
+    phf_dfree(T.eoff);
+    phf_dfree(T.mark);
+    TRY(phf_scan_i32(ctx, T.nonN, T.nonN, ne, T.totals));
+    TRY(phf_scan_i32(ctx, T.nonD, T.nonD, ne, T.totals + 1));
+    TRY(phf_scan_i32(ctx, T.clen, T.clen, ne, T.totals + 2));
+    TRY(phf_scan_i32(ctx, T.inter, T.inter, ne, T.totals + 3));
+    int32_t h[4];
+    PHF_HIP(ctx, hipMemcpyAsync(h, T.totals, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    M->L = h[0];
+    M->n_free = h[1];
+    M->nnz_C = h[2];
+    M->n_int = h[3];
+    const int32_t L = M->L, N = 3 * nE;
+    if ((int64_t)9 * nE + 2 * M->nnz_C > 0x7fffffffLL)
+        return phf_set_error(ctx, PHF_EINVAL, "saddle matrix too large for int32 indices");
+    M->nnz_S = (int64_t)9 * nE + 2 * M->nnz_C;
+
+    TRY(phf_dmalloc(ctx, &M->edge_row, ne, "edge rows"));
+    TRY(phf_dmalloc(ctx, &M->red_row, ne, "reduced rows"));
+    TRY(phf_dmalloc(ctx, &M->red_edge, M->n_free, "reduced edges"));
+    TRY(phf_dmalloc(ctx, &M->row_edge, L, "row edges"));
+    TRY(phf_dmalloc(ctx, &M->row_nodes, L, "row nodes"));
+    TRY(phf_dmalloc(ctx, &M->C_rowptr, (size_t)L + 1, "C rowptr"));
+    TRY(phf_dmalloc(ctx, &M->C_col, M->nnz_C, "C columns"));
+    PHF_LAUNCH(ctx, "k_rows", k_rows, nblk(ne), 256, 0, ne, M->edge_type, T.nonN, T.nonD, T.clen,
+               M->edge_nodes, M->edge_elems, M->led, M->ledTN, M->edge_row, M->red_row,
+               M->red_edge, M->row_edge, M->row_nodes, M->C_rowptr, M->C_col);
+    PHF_LAUNCH(ctx, "k_set", k_set_i32, 1, 1, 0, M->C_rowptr + L, (int32_t)M->nnz_C);
+    phf_dfree(T.nonN);
+    phf_dfree(T.nonD);
+    phf_dfree(T.clen);
+    phf_dfree(T.inter);
+
+    // element codes and the saddle pattern
+    TRY(phf_dmalloc(ctx, &T.slen, (size_t)N + L + 1, "saddle row lengths"));
+    PHF_LAUNCH(ctx, "k_elem_codes", k_elem_codes, nblk(nE), 256, 0, nE, M->elem4, M->elem_edges,
+               M->edge_type, M->edge_elems, T.slen);
+    if (L > 0)
+        PHF_LAUNCH(ctx, "k_saddle_rowlen", k_saddle_rowlen, nblk(L), 256, 0, L, M->C_rowptr,
+                   (int32_t)M->nnz_C, T.slen + N);
+    TRY(phf_dmalloc(ctx, &M->S_rowptr, (size_t)N + L + 1, "saddle rowptr"));
+    PHF_HIP(ctx, hipMemsetAsync(T.slen + N + L, 0, sizeof(int32_t), ctx->stream));
+    TRY(phf_scan_i32(ctx, T.slen, M->S_rowptr, N + L + 1, T.totals + 4));
+    TRY(phf_dmalloc(ctx, &M->S_col, M->nnz_S, "saddle columns"));
+    PHF_LAUNCH(ctx, "k_saddle_cols", k_saddle_cols, nblk((int64_t)N + L), 256, 0, nE, L, M->elem4,
+               M->elem_edges, M->edge_row, M->C_rowptr, M->C_col, M->S_rowptr, M->S_col);
+    phf_dfree(T.slen);
+
+    // reduced operator pattern
+    const int32_t nf = M->n_free;
+    TRY(phf_dmalloc(ctx, &M->R_rowptr, (size_t)nf + 1, "reduced rowptr"));
+    if (nf > 0) {
+        PHF_LAUNCH(ctx, "k_reduced_pattern", k_reduced_pattern, nblk(nf), 256, 0, nf, 0,
+                   M->red_edge, M->edge_elems, M->led, M->ledTN, M->elem_edges, M->red_row,
+                   M->R_rowptr, (const int32_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr);
+    }
+    PHF_HIP(ctx, hipMemsetAsync(M->R_rowptr + nf, 0, sizeof(int32_t), ctx->stream));
+    TRY(phf_scan_i32(ctx, M->R_rowptr, M->R_rowptr, nf + 1, T.totals + 5));
+    int32_t nnzR = 0;
+    TRY(read_i32(ctx, T.totals + 5, &nnzR));
+    M->nnz_R = nnzR;
+    TRY(phf_dmalloc(ctx, &M->R_col, nnzR, "reduced columns"));
+    TRY(phf_dmalloc(ctx, &M->R_src, 2 * (size_t)nnzR, "reduced sources"));
+    if (nf > 0) {
+        PHF_LAUNCH(ctx, "k_reduced_pattern", k_reduced_pattern, nblk(nf), 256, 0, nf, 1,
+                   M->red_edge, M->edge_elems, M->led, M->ledTN, M->elem_edges, M->red_row,
+                   (int32_t*)nullptr, M->R_rowptr, M->R_col, M->R_src);
+    }
+    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    M->bytes = (int64_t)nC * 16 + (int64_t)nE * 16 + (int64_t)ne * (8 + 8 + 1 + 1 + 1 + 4 + 4) +
+               (int64_t)nE * 12 + (int64_t)(nD + nN) * 4 + (int64_t)L * (4 + 8 + 4) +
+               M->nnz_C * 4 + ((int64_t)N + L + 1) * 4 + M->nnz_S * 4 + (int64_t)nf * 8 +
+               M->nnz_R * 12;
+    return PHF_OK;
+}
+}  // namespace
+
+extern "C" int phf_mesh_create(phf_ctx* ctx, const double* xy, int32_t nC, const int32_t* elem,
+                               int32_t nE, const int32_t* dir, int32_t nD, const int32_t* neu,
+                               int32_t nN, phf_memspace ms, phf_mesh** out)
+{
+    if (!ctx || !out) return PHF_EINVAL;
+    *out = nullptr;
+    if (nC < 3 || nE < 1 || nE > 80000000 || nD < 0 || nN < 0 || !xy || !elem ||
+        (nD > 0 && !dir) || (nN > 0 && !neu) || (ms != PHF_HOST && ms != PHF_DEVICE))
+        return phf_set_error(ctx, PHF_EINVAL, "phf_mesh_create: invalid sizes or null arrays");
+    PHF_HIP(ctx, hipSetDevice(ctx->device));
+    phf_mesh* M = new (std::nothrow) phf_mesh;
+    if (!M) return phf_set_error(ctx, PHF_ENOMEM, "host allocation failed");
+    M->ctx = ctx;
+    M->nC = nC;
+    M->nE = nE;
+    M->nD = nD;
+    M->nN = nN;
+    int rc = mesh_build(M, xy, elem, dir, neu, ms);
+    if (rc) {
+        (void)hipStreamSynchronize(ctx->stream);
+        mesh_free(M);
+        delete M;
+        return rc;
+    }
+    *out = M;
+    return PHF_OK;
+}
+
+extern "C" int phf_mesh_destroy(phf_mesh* mesh)
+{
+    if (!mesh) return PHF_EINVAL;
+    (void)hipStreamSynchronize(mesh->ctx->stream);
+    mesh_free(mesh);
+    delete mesh;
+    return PHF_OK;
+}
+
+extern "C" int phf_mesh_get_info(const phf_mesh* m, phf_mesh_info* o)
+{
+    if (!m || !o) return PHF_EINVAL;
+    o->nC = m->nC;
+    o->nE = m->nE;
+    o->n_edges = m->n_edges;
+    o->N = 3 * m->nE;
+    o->L = m->L;
+    o->nD = m->nD;
+    o->nN = m->nN;
+    o->n_interior = m->n_int;
+    o->n_free = m->n_free;
+    o->nnz_K = 9 * (int64_t)m->nE;
+    o->nnz_C = m->nnz_C;
+    o->nnz_saddle = m->nnz_S;
+    o->nnz_reduced = m->nnz_R;
+    o->device_bytes = m->bytes;
+    return PHF_OK;
+}
+
+namespace {
+__global__ void k_split_pairs(const int2* __restrict__ in, int32_t n, int32_t* __restrict__ out)
+{
+    int32_t q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    int2 v = in[q];
+    out[2 * (int64_t)q] = v.x;
+    out[2 * (int64_t)q + 1] = v.y;
+}
+
+__global__ void k_k_pattern(int32_t nE, int32_t* __restrict__ rowptr, int32_t* __restrict__ col)
+{
+    int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int64_t N = 3 * (int64_t)nE;
+    if (g > N) return;
+    if (rowptr) rowptr[g] = (int32_t)(3 * g);
+    if (g < N && col) {
+        int32_t m = (int32_t)(g / 3);
+        col[3 * g] = 3 * m;
+        col[3 * g + 1] = 3 * m + 1;
+        col[3 * g + 2] = 3 * m + 2;
+    }
+}
+
+int copy_out(phf_ctx* ctx, void* dst, const void* src, size_t bytes, phf_memspace ms)
+{
+    if (!dst || bytes == 0) return PHF_OK;
+    PHF_HIP(ctx, hipMemcpyAsync(dst, src, bytes,
+                                ms == PHF_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                                ctx->stream));
+    return PHF_OK;
+}
+}  // namespace
+
+extern "C" int phf_mesh_topology(const phf_mesh* m, int32_t* edge_nodes, int32_t* edge_elems,
+                                 int32_t* elem_edges, int8_t* led, int8_t* ledTN,
+                                 int8_t* edge_type, int32_t* edge_row, int32_t* dir_edges,
+                                 int32_t* neu_edges, phf_memspace ms)
+{
+    if (!m || (ms != PHF_HOST && ms != PHF_DEVICE)) return PHF_EINVAL;
+    phf_ctx* ctx = m->ctx;
+    size_t ne = (size_t)m->n_edges;
+    // int2 arrays are laid out as interleaved pairs already
+    TRY(copy_out(ctx, edge_nodes, m->edge_nodes, ne * 8, ms));
+    TRY(copy_out(ctx, edge_elems, m->edge_elems, ne * 8, ms));
+    TRY(copy_out(ctx, elem_edges, m->elem_edges, (size_t)m->nE * 12, ms));
+    TRY(copy_out(ctx, led, m->led, ne, ms));
+    TRY(copy_out(ctx, ledTN, m->ledTN, ne, ms));
+    TRY(copy_out(ctx, edge_type, m->edge_type, ne, ms));
+    TRY(copy_out(ctx, edge_row, m->edge_row, ne * 4, ms));
+    TRY(copy_out(ctx, dir_edges, m->dir_edges, (size_t)m->nD * 4, ms));
+    TRY(copy_out(ctx, neu_edges, m->neu_edges, (size_t)m->nN * 4, ms));
+    if (ms == PHF_HOST) PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PHF_OK;
+}
+
+extern "C" int phf_mesh_pattern(const phf_mesh* m, int32_t* K_rowptr, int32_t* K_col,
+                                int32_t* C_rowptr, int32_t* C_col, int32_t* S_rowptr,
+                                int32_t* S_col, phf_memspace ms)
+{
+    if (!m || (ms != PHF_HOST && ms != PHF_DEVICE)) return PHF_EINVAL;
+    phf_ctx* ctx = m->ctx;
+    if (K_rowptr || K_col) {
+        const int32_t N = 3 * m->nE;
+        int32_t *rp = nullptr, *cl = nullptr;
+        if (ms == PHF_DEVICE) {
+            rp = K_rowptr;
+            cl = K_col;
+        } else {
+            if (K_rowptr) TRY(phf_dmalloc(ctx, &rp, (size_t)N + 1, "K rowptr"));
+            if (K_col) TRY(phf_dmalloc(ctx, &cl, 9 * (size_t)m->nE, "K columns"));
+        }
+        PHF_LAUNCH(ctx, "k_k_pattern", k_k_pattern, nblk((int64_t)N + 1), 256, 0, m->nE, rp, cl);
+        if (ms == PHF_HOST) {
+            if (K_rowptr) TRY(copy_out(ctx, K_rowptr, rp, ((size_t)N + 1) * 4, ms));
+            if (K_col) TRY(copy_out(ctx, K_col, cl, 9 * (size_t)m->nE * 4, ms));
+            PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            phf_dfree(rp);
+            phf_dfree(cl);
+        }
+    }
+    TRY(copy_out(ctx, C_rowptr, m->C_rowptr, ((size_t)m->L + 1) * 4, ms));
+    TRY(copy_out(ctx, C_col, m->C_col, (size_t)m->nnz_C * 4, ms));
+    TRY(copy_out(ctx, S_rowptr, m->S_rowptr, (3 * (size_t)m->nE + m->L + 1) * 4, ms));
+    TRY(copy_out(ctx, S_col, m->S_col, (size_t)m->nnz_S * 4, ms));
+    if (ms == PHF_HOST) PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PHF_OK;
+}

@@ -1,0 +1,73 @@
+// Null-space conjugate-gradient solver of the primal hybrid saddle system
+// (internal to libphfem).
+//
+// System: A U - C^T mu = rhs1, -C U = rhs2, with A block diagonal (element
+// blocks A_T = cK K_T + cM M_T read from assembled K and M arrays) and C the
+// coupling matrix (row of edge e: +h on the vertex DOFs of T+, -h on those of
+// T-, h = |E|/2).
+//
+// Reduction: on each element the P1 function is determined by its values at
+// the three edge midpoints, U_T = P w_T with P[i][l] = -1 if l == i else +1
+// (local edge l opposite vertex l). Taking w_e shared by both neighbours of
+// every edge satisfies the interior constraints; Dirichlet rows fix w_e; a
+// non-zero interior right-hand side is carried as a jump added on the T+
+// side. The free unknowns are the midpoint values of non-Dirichlet edges and
+// the projected operator R = sum_T P^T A_T P is symmetric positive definite
+// when A is (plus at least one Dirichlet edge when A = K). mu follows element
+// by element from the first block row: C_T^T mu_T = A_T U_T - rhs1_T, whose
+// solution on T+ is mu_e = (P^T (A_T U_T - rhs1_T))_e / |E|.
+#pragma once
+
+#include "phf_internal.h"
+
+struct phf_ns {
+    phf_mesh* mesh = nullptr;
+    int32_t nE = 0, nf = 0, L = 0, nbv = 0;
+    // symbolic (per mesh)
+    int32_t* elem_red = nullptr;  // 3 nE: reduced row of local edge l (-1 Dirichlet)
+    int32_t* elem_row = nullptr;  // 3 nE: multiplier row of local edge l (-1 Neumann)
+    int32_t* ell_col = nullptr;   // 5 nf, column-major ELL of R
+    int32_t* ell_src = nullptr;   // 2 x 5 nf block sources
+    double* row_h = nullptr;      // L: |E|/2 of each multiplier row
+    // numeric
+    double* B = nullptr;          // 9 nE: P^T A_T P
+    double* Ablk = nullptr;       // 9 nE: A_T
+    double* ell_val = nullptr;    // 5 nf
+    double* dinv = nullptr;       // nf
+    double* kv = nullptr;         // 3 nE known midpoint values / jumps
+    double* cs = nullptr;         // 3 nE element right-hand side / residual
+    double* b = nullptr;
+    double* w = nullptr;
+    double* r = nullptr;
+    double* z = nullptr;
+    double* p = nullptr;
+    double* q = nullptr;
+    double* part = nullptr;       // 3 x 1024 partial sums
+    double* scal = nullptr;       // device scalars
+    int* iflags = nullptr;        // [0] done, [1] iterations
+    bool have_operator = false;
+};
+
+// Scalar slots in phf_ns::scal.
+enum { NS_RZ = 0, NS_PQ, NS_ALPHA, NS_BETA, NS_RR, NS_BB, NS_TOL2, NS_NSCAL = 8 };
+
+int phf_ns_create(phf_mesh* mesh, phf_ns** out);
+void phf_ns_destroy(phf_ns* ns);
+// Builds A_T, B, the ELL values, the Jacobi diagonal for A = cK K + cM M,
+// and |E|/2 per multiplier row from the assembled C.
+int phf_ns_operator(phf_ns* ns, const double* K, const double* M, const double* C, double cK,
+                    double cM);
+// Right-hand side reduction (rhs2 is the right-hand side of -C U = rhs2).
+int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2);
+// Starts CG from the current w (zero it first for a cold start).
+int phf_ns_cg_start(phf_ns* ns, double rtol);
+// Issues `iters` CG iterations (skipped on the device once converged).
+int phf_ns_cg_iterate(phf_ns* ns, int32_t iters);
+// U = P (w + kv); mu = mu_scale * element-local multiplier recovery.
+int phf_ns_recover(phf_ns* ns, const double* rhs1, double* U, double* mu, double mu_scale);
+int phf_ns_zero_w(phf_ns* ns);
+// Host convergence loop: cg_start + batches of check_every iterations.
+int phf_ns_cg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_every,
+                    int32_t* iters_out, double* relres_out, int* converged);
+// The mesh's cached workspace (created on first use).
+int phf_ns_get(phf_mesh* mesh, phf_ns** out);

@@ -1,0 +1,649 @@
+// Null-space conjugate-gradient solve of the saddle system of Section 3.5
+// (see phf_solver.h for the reduction) and the phf_solve entry point.
+#include "phf_device.h"
+#include "phf_solver.h"
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int MAXB = 1024;  // max blocks of the vector kernels = partial-sum slots
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
+
+// U_i = (w0 + w1 + w2) - 2 w_i ;  (P^T v)_l = (v0 + v1 + v2) - 2 v_l
+__device__ inline void apply_P(const double w[3], double U[3])
+{
+    const double s = w[0] + w[1] + w[2];
+    U[0] = s - 2.0 * w[0];
+    U[1] = s - 2.0 * w[1];
+    U[2] = s - 2.0 * w[2];
+}
+
+__global__ __launch_bounds__(NT) void k_ns_symbolic(int32_t nE, const int32_t* __restrict__ elem_edges,
+                                                    const int32_t* __restrict__ red_row,
+                                                    const int32_t* __restrict__ edge_row,
+                                                    int32_t* __restrict__ elem_red,
+                                                    int32_t* __restrict__ elem_row)
+{
+    int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (g >= 3 * (int64_t)nE) return;
+    int32_t e = elem_edges[g];
+    elem_red[g] = red_row[e];
+    elem_row[g] = edge_row[e];
+}
+
+__global__ __launch_bounds__(NT) void k_ns_ell(int32_t nf, const int32_t* __restrict__ R_rowptr,
+                                               const int32_t* __restrict__ R_col,
+                                               const int32_t* __restrict__ R_src,
+                                               int32_t* __restrict__ ell_col,
+                                               int32_t* __restrict__ ell_src)
+{
+    int32_t r = blockIdx.x * NT + threadIdx.x;
+    if (r >= nf) return;
+    int32_t q0 = R_rowptr[r], n = R_rowptr[r + 1] - q0;
+    for (int k = 0; k < 5; ++k) {
+        int64_t slot = (int64_t)k * nf + r;
+        if (k < n) {
+            ell_col[slot] = R_col[q0 + k];
+            ell_src[2 * slot] = R_src[2 * (int64_t)(q0 + k)];
+            ell_src[2 * slot + 1] = R_src[2 * (int64_t)(q0 + k) + 1];
+        } else {
+            ell_col[slot] = r;
+            ell_src[2 * slot] = -1;
+            ell_src[2 * slot + 1] = -1;
+        }
+    }
+}
+
+// A_T = cK K_T + cM M_T and B_T = P^T A_T P.
+__global__ __launch_bounds__(NT) void k_ns_blocks(int32_t nE, const double* __restrict__ K,
+                                                  const double* __restrict__ M, double cK,
+                                                  double cM, double* __restrict__ Ablk,
+                                                  double* __restrict__ B)
+{
+    int32_t m = blockIdx.x * NT + threadIdx.x;
+    if (m >= nE) return;
+    double A[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        A[q] = cK * K[9 * (int64_t)m + q] + cM * M[9 * (int64_t)m + q];
+        Ablk[9 * (int64_t)m + q] = A[q];
+    }
+    // AP[i][l] = rowsum_i(A) - 2 A[i][l]
+    double AP[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double rs = A[3 * i] + A[3 * i + 1] + A[3 * i + 2];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) AP[3 * i + l] = rs - 2.0 * A[3 * i + l];
+    }
+    // B[l][l'] = colsum_{l'}(AP) - 2 AP[l][l']
+#pragma unroll
+    for (int lp = 0; lp < 3; ++lp) {
+        double cs = AP[lp] + AP[3 + lp] + AP[6 + lp];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) B[9 * (int64_t)m + 3 * l + lp] = cs - 2.0 * AP[3 * l + lp];
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_ns_ellval(int32_t nf, const int32_t* __restrict__ ell_col,
+                                                  const int32_t* __restrict__ ell_src,
+                                                  const double* __restrict__ B,
+                                                  double* __restrict__ ell_val,
+                                                  double* __restrict__ dinv)
+{
+    int32_t r = blockIdx.x * NT + threadIdx.x;
+    if (r >= nf) return;
+    double d = 0.0;
+    for (int k = 0; k < 5; ++k) {
+        int64_t slot = (int64_t)k * nf + r;
+        int32_t s0 = ell_src[2 * slot], s1 = ell_src[2 * slot + 1];
+        double v = (s0 >= 0 ? B[s0] : 0.0) + (s1 >= 0 ? B[s1] : 0.0);
+        ell_val[slot] = v;
+        if (ell_col[slot] == r && s0 >= 0) d = v;
+    }
+    dinv[r] = d > 0.0 ? 1.0 / d : 1.0;
+}
+
+__global__ __launch_bounds__(NT) void k_ns_rowh(int32_t L, const int32_t* __restrict__ C_rowptr,
+                                                const double* __restrict__ C,
+                                                double* __restrict__ row_h)
+{
+    int32_t r = blockIdx.x * NT + threadIdx.x;
+    if (r >= L) return;
+    row_h[r] = C[C_rowptr[r]];
+}
+
+// Known midpoint values (Dirichlet) and T+-side jumps (interior rows with a
+// non-zero right-hand side), and the element part of the reduced rhs,
+// c_T = P^T (rhs1_T - A_T P kv_T).
+__global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int4* __restrict__ elem4,
+                                                 const int32_t* __restrict__ elem_row,
+                                                 const double* __restrict__ row_h,
+                                                 const double* __restrict__ rhs1,
+                                                 const double* __restrict__ rhs2,
+                                                 const double* __restrict__ Ablk,
+                                                 double* __restrict__ kv, double* __restrict__ cs)
+{
+    int32_t m = blockIdx.x * NT + threadIdx.x;
+    if (m >= nE) return;
+    const int code = elem4[m].w;
+    double k3[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const int t = PHF_CODE_TYPE(code, l);
+        double v = 0.0;
+        if (t == 1 || (t == 0 && PHF_CODE_TPLUS(code, l))) {
+            const int32_t r = elem_row[3 * (int64_t)m + l];
+            v = -rhs2[r] / (2.0 * row_h[r]);
+        }
+        k3[l] = v;
+        kv[3 * (int64_t)m + l] = v;
+    }
+    double Ub[3];
+    apply_P(k3, Ub);
+    double res[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double* a = Ablk + 9 * (int64_t)m + 3 * i;
+        res[i] = rhs1[3 * (int64_t)m + i] - (a[0] * Ub[0] + a[1] * Ub[1] + a[2] * Ub[2]);
+    }
+    double c[3];
+    apply_P(res, c);  // P is symmetric, so P^T v = P v
+#pragma unroll
+    for (int l = 0; l < 3; ++l) cs[3 * (int64_t)m + l] = c[l];
+}
+
+__global__ __launch_bounds__(NT) void k_ns_gather(int32_t nf, const int32_t* __restrict__ red_edge,
+                                                  const int2* __restrict__ edge_elems,
+                                                  const int8_t* __restrict__ led,
+                                                  const int8_t* __restrict__ ledTN,
+                                                  const double* __restrict__ cs,
+                                                  double* __restrict__ b)
+{
+    int32_t r = blockIdx.x * NT + threadIdx.x;
+    if (r >= nf) return;
+    int32_t e = red_edge[r];
+    int2 tt = edge_elems[e];
+    double v = cs[3 * (int64_t)tt.x + led[e]];
+    if (tt.y >= 0) v += cs[3 * (int64_t)tt.y + ledTN[e]];
+    b[r] = v;
+}
+
+// ---- conjugate gradients with device-side scalars --------------------------
+
+__device__ inline double ell_row(int32_t r, int32_t nf, const int32_t* __restrict__ col,
+                                 const double* __restrict__ val, const double* __restrict__ x)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        int64_t slot = (int64_t)k * nf + r;
+        s = fma(val[slot], x[col[slot]], s);
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(NT) void k_cg_init(int32_t nf, const int32_t* __restrict__ col,
+                                                const double* __restrict__ val,
+                                                const double* __restrict__ dinv,
+                                                const double* __restrict__ b,
+                                                const double* __restrict__ w,
+                                                double* __restrict__ r, double* __restrict__ z,
+                                                double* __restrict__ p, double* __restrict__ part)
+{
+    __shared__ double sh[NT / 64];
+    double s_rz = 0.0, s_rr = 0.0, s_bb = 0.0;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
+        double ri = b[i] - ell_row(i, nf, col, val, w);
+        double zi = dinv[i] * ri;
+        r[i] = ri;
+        z[i] = zi;
+        p[i] = zi;
+        s_rz = fma(ri, zi, s_rz);
+        s_rr = fma(ri, ri, s_rr);
+        s_bb = fma(b[i], b[i], s_bb);
+    }
+    double t0 = phf_block_sum_f64<NT>(s_rz, sh);
+    double t1 = phf_block_sum_f64<NT>(s_rr, sh);
+    double t2 = phf_block_sum_f64<NT>(s_bb, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = t0;
+        part[MAXB + blockIdx.x] = t1;
+        part[2 * MAXB + blockIdx.x] = t2;
+    }
+}
+
+__device__ inline double sum_partials(const double* part, int32_t nb, double* sh)
+{
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nb; q += NT) s += part[q];
+    return phf_block_sum_f64<NT>(s, sh);
+}
+
+__global__ __launch_bounds__(NT) void k_cg_init_final(const double* __restrict__ part, int32_t nb,
+                                                      double tol2, double* scal, int* iflags)
+{
+    __shared__ double sh[NT / 64];
+    double rz = sum_partials(part, nb, sh);
+    double rr = sum_partials(part + MAXB, nb, sh);
+    double bb = sum_partials(part + 2 * MAXB, nb, sh);
+    if (threadIdx.x == 0) {
+        scal[NS_RZ] = rz;
+        scal[NS_RR] = rr;
+        scal[NS_BB] = bb;
+        scal[NS_TOL2] = tol2;
+        iflags[0] = (rr <= tol2 * bb) ? 1 : 0;
+        iflags[1] = 0;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_cg_spmv(int32_t nf, const int32_t* __restrict__ col,
+                                                const double* __restrict__ val,
+                                                const double* __restrict__ p,
+                                                double* __restrict__ q, double* __restrict__ part,
+                                                const int* __restrict__ iflags)
+{
+    if (iflags[0]) return;
+    __shared__ double sh[NT / 64];
+    double s = 0.0;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
+        double qi = ell_row(i, nf, col, val, p);
+        q[i] = qi;
+        s = fma(p[i], qi, s);
+    }
+    double t = phf_block_sum_f64<NT>(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(NT) void k_cg_alpha(const double* __restrict__ part, int32_t nb,
+                                                 double* scal, const int* __restrict__ iflags)
+{
+    if (iflags[0]) return;
+    __shared__ double sh[NT / 64];
+    double pq = sum_partials(part, nb, sh);
+    if (threadIdx.x == 0) {
+        scal[NS_PQ] = pq;
+        scal[NS_ALPHA] = scal[NS_RZ] / pq;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_cg_update(int32_t nf, double* __restrict__ w,
+                                                  double* __restrict__ r, double* __restrict__ z,
+                                                  const double* __restrict__ p,
+                                                  const double* __restrict__ q,
+                                                  const double* __restrict__ dinv,
+                                                  const double* __restrict__ scal,
+                                                  double* __restrict__ part,
+                                                  const int* __restrict__ iflags)
+{
+    if (iflags[0]) return;
+    __shared__ double sh[NT / 64];
+    const double alpha = scal[NS_ALPHA];
+    double s_rz = 0.0, s_rr = 0.0;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
+        w[i] = fma(alpha, p[i], w[i]);
+        double ri = fma(-alpha, q[i], r[i]);
+        double zi = dinv[i] * ri;
+        r[i] = ri;
+        z[i] = zi;
+        s_rz = fma(ri, zi, s_rz);
+        s_rr = fma(ri, ri, s_rr);
+    }
+    double t0 = phf_block_sum_f64<NT>(s_rz, sh);
+    double t1 = phf_block_sum_f64<NT>(s_rr, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = t0;
+        part[MAXB + blockIdx.x] = t1;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_cg_beta(const double* __restrict__ part, int32_t nb,
+                                                double* scal, int* iflags)
+{
+    if (iflags[0]) return;
+    __shared__ double sh[NT / 64];
+    double rz = sum_partials(part, nb, sh);
+    double rr = sum_partials(part + MAXB, nb, sh);
+    if (threadIdx.x == 0) {
+        scal[NS_BETA] = rz / scal[NS_RZ];
+        scal[NS_RZ] = rz;
+        scal[NS_RR] = rr;
+        iflags[1] += 1;
+        if (rr <= scal[NS_TOL2] * scal[NS_BB]) iflags[0] = 1;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_cg_p(int32_t nf, double* __restrict__ p,
+                                             const double* __restrict__ z,
+                                             const double* __restrict__ scal,
+                                             const int* __restrict__ iflags)
+{
+    if (iflags[0]) return;
+    const double beta = scal[NS_BETA];
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT)
+        p[i] = fma(beta, p[i], z[i]);
+}
+
+// ---- recovery -------------------------------------------------------------
+
+__global__ __launch_bounds__(NT) void k_ns_recover_u(int32_t nE, const int32_t* __restrict__ elem_red,
+                                                     const double* __restrict__ w,
+                                                     const double* __restrict__ kv,
+                                                     const double* __restrict__ Ablk,
+                                                     const double* __restrict__ rhs1,
+                                                     double* __restrict__ U,
+                                                     double* __restrict__ cs)
+{
+    int32_t m = blockIdx.x * NT + threadIdx.x;
+    if (m >= nE) return;
+    double wt[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        int32_t rr = elem_red[3 * (int64_t)m + l];
+        wt[l] = (rr >= 0 ? w[rr] : 0.0) + kv[3 * (int64_t)m + l];
+    }
+    double u[3];
+    apply_P(wt, u);
+    double res[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        U[3 * (int64_t)m + i] = u[i];
+        const double* a = Ablk + 9 * (int64_t)m + 3 * i;
+        res[i] = (a[0] * u[0] + a[1] * u[1] + a[2] * u[2]) - rhs1[3 * (int64_t)m + i];
+    }
+    double s[3];
+    apply_P(res, s);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) cs[3 * (int64_t)m + l] = s[l];
+}
+
+__global__ __launch_bounds__(NT) void k_ns_recover_mu(int32_t L, const int32_t* __restrict__ row_edge,
+                                                      const int2* __restrict__ edge_elems,
+                                                      const int8_t* __restrict__ led,
+                                                      const double* __restrict__ row_h,
+                                                      const double* __restrict__ cs, double scale,
+                                                      double* __restrict__ mu)
+{
+    int32_t r = blockIdx.x * NT + threadIdx.x;
+    if (r >= L) return;
+    int32_t e = row_edge[r];
+    int32_t T = edge_elems[e].x;
+    mu[r] = scale * cs[3 * (int64_t)T + led[e]] / (2.0 * row_h[r]);
+}
+
+#define TRY(x)               \
+    do {                     \
+        int rc_ = (x);       \
+        if (rc_) return rc_; \
+    } while (0)
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+void phf_ns_destroy(phf_ns* ns)
+{
+    if (!ns) return;
+    phf_dfree(ns->elem_red); phf_dfree(ns->elem_row); phf_dfree(ns->ell_col);
+    phf_dfree(ns->ell_src); phf_dfree(ns->row_h); phf_dfree(ns->B); phf_dfree(ns->Ablk);
+    phf_dfree(ns->ell_val); phf_dfree(ns->dinv); phf_dfree(ns->kv); phf_dfree(ns->cs);
+    phf_dfree(ns->b); phf_dfree(ns->w); phf_dfree(ns->r); phf_dfree(ns->z);
+    phf_dfree(ns->p); phf_dfree(ns->q); phf_dfree(ns->part); phf_dfree(ns->scal);
+    phf_dfree(ns->iflags);
+    delete ns;
+}
+
+int phf_ns_create(phf_mesh* mesh, phf_ns** out)
+{
+    phf_ctx* ctx = mesh->ctx;
+    phf_ns* ns = new (std::nothrow) phf_ns;
+    if (!ns) return phf_set_error(ctx, PHF_ENOMEM, "host allocation failed");
+    ns->mesh = mesh;
+    ns->nE = mesh->nE;
+    ns->nf = mesh->n_free;
+    ns->L = mesh->L;
+    ns->nbv = (int32_t)std::min<int64_t>(std::max<int64_t>(nblk(ns->nf), 1), MAXB);
+    const size_t e3 = 3 * (size_t)ns->nE, e9 = 9 * (size_t)ns->nE, nf = ns->nf;
+    int rc = 0;
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->elem_red, e3, "solver element rows");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->elem_row, e3, "solver element rows");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_col, 5 * nf, "solver ELL columns");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_src, 10 * nf, "solver ELL sources");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->row_h, (size_t)ns->L, "solver row h");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->B, e9, "solver blocks");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->Ablk, e9, "solver blocks");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_val, 5 * nf, "solver ELL values");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->dinv, nf, "solver diagonal");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->kv, e3, "solver known values");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->cs, e3, "solver element rhs");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->b, nf, "solver rhs");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->w, nf, "solver x");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->r, nf, "solver r");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->z, nf, "solver z");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->p, nf, "solver p");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->q, nf, "solver q");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->part, 3 * MAXB, "solver partials");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->scal, NS_NSCAL, "solver scalars");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->iflags, 4, "solver flags");
+    if (rc) {
+        phf_ns_destroy(ns);
+        return rc;
+    }
+    auto launch = [&]() -> int {
+        PHF_LAUNCH(ctx, "k_ns_symbolic", k_ns_symbolic, nblk(3 * (int64_t)ns->nE), NT, 0, ns->nE,
+                   mesh->elem_edges, mesh->red_row, mesh->edge_row, ns->elem_red, ns->elem_row);
+        if (ns->nf > 0)
+            PHF_LAUNCH(ctx, "k_ns_ell", k_ns_ell, nblk(ns->nf), NT, 0, ns->nf, mesh->R_rowptr,
+                       mesh->R_col, mesh->R_src, ns->ell_col, ns->ell_src);
+        PHF_HIP(ctx, hipMemsetAsync(ns->w, 0, sizeof(double) * std::max<size_t>(nf, 1), ctx->stream));
+        PHF_HIP(ctx, hipMemsetAsync(ns->iflags, 0, 4 * sizeof(int), ctx->stream));
+        return PHF_OK;
+    };
+    rc = launch();
+    if (rc) {
+        phf_ns_destroy(ns);
+        return rc;
+    }
+    *out = ns;
+    return PHF_OK;
+}
+
+int phf_ns_operator(phf_ns* ns, const double* K, const double* M, const double* C, double cK,
+                    double cM)
+{
+    phf_mesh* mesh = ns->mesh;
+    phf_ctx* ctx = mesh->ctx;
+    PHF_LAUNCH(ctx, "k_ns_blocks", k_ns_blocks, nblk(ns->nE), NT, 0, ns->nE, K, M, cK, cM,
+               ns->Ablk, ns->B);
+    if (ns->nf > 0)
+        PHF_LAUNCH(ctx, "k_ns_ellval", k_ns_ellval, nblk(ns->nf), NT, 0, ns->nf, ns->ell_col,
+                   ns->ell_src, ns->B, ns->ell_val, ns->dinv);
+    if (ns->L > 0)
+        PHF_LAUNCH(ctx, "k_ns_rowh", k_ns_rowh, nblk(ns->L), NT, 0, ns->L, mesh->C_rowptr, C,
+                   ns->row_h);
+    ns->have_operator = true;
+    return PHF_OK;
+}
+
+int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2)
+{
+    phf_mesh* mesh = ns->mesh;
+    phf_ctx* ctx = mesh->ctx;
+    PHF_LAUNCH(ctx, "k_ns_known", k_ns_known, nblk(ns->nE), NT, 0, ns->nE, mesh->elem4,
+               ns->elem_row, ns->row_h, rhs1, rhs2, ns->Ablk, ns->kv, ns->cs);
+    if (ns->nf > 0)
+        PHF_LAUNCH(ctx, "k_ns_gather", k_ns_gather, nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge,
+                   mesh->edge_elems, mesh->led, mesh->ledTN, ns->cs, ns->b);
+    return PHF_OK;
+}
+
+int phf_ns_zero_w(phf_ns* ns)
+{
+    phf_ctx* ctx = ns->mesh->ctx;
+    PHF_HIP(ctx, hipMemsetAsync(ns->w, 0, sizeof(double) * std::max<int32_t>(ns->nf, 1), ctx->stream));
+    return PHF_OK;
+}
+
+int phf_ns_cg_start(phf_ns* ns, double rtol)
+{
+    phf_ctx* ctx = ns->mesh->ctx;
+    if (ns->nf == 0) {
+        PHF_HIP(ctx, hipMemsetAsync(ns->iflags, 0, 4 * sizeof(int), ctx->stream));
+        return PHF_OK;
+    }
+    PHF_LAUNCH(ctx, "k_cg_init", k_cg_init, ns->nbv, NT, 0, ns->nf, ns->ell_col, ns->ell_val,
+               ns->dinv, ns->b, ns->w, ns->r, ns->z, ns->p, ns->part);
+    PHF_LAUNCH(ctx, "k_cg_init_final", k_cg_init_final, 1, NT, 0, ns->part, ns->nbv, rtol * rtol,
+               ns->scal, ns->iflags);
+    return PHF_OK;
+}
+
+int phf_ns_cg_iterate(phf_ns* ns, int32_t iters)
+{
+    phf_ctx* ctx = ns->mesh->ctx;
+    if (ns->nf == 0) return PHF_OK;
+    for (int32_t it = 0; it < iters; ++it) {
+        PHF_LAUNCH(ctx, "k_cg_spmv", k_cg_spmv, ns->nbv, NT, 0, ns->nf, ns->ell_col, ns->ell_val,
+                   ns->p, ns->q, ns->part, ns->iflags);
+        PHF_LAUNCH(ctx, "k_cg_alpha", k_cg_alpha, 1, NT, 0, ns->part, ns->nbv, ns->scal,
+                   ns->iflags);
+        PHF_LAUNCH(ctx, "k_cg_update", k_cg_update, ns->nbv, NT, 0, ns->nf, ns->w, ns->r, ns->z,
+                   ns->p, ns->q, ns->dinv, ns->scal, ns->part, ns->iflags);
+        PHF_LAUNCH(ctx, "k_cg_beta", k_cg_beta, 1, NT, 0, ns->part, ns->nbv, ns->scal,
+                   ns->iflags);
+        PHF_LAUNCH(ctx, "k_cg_p", k_cg_p, ns->nbv, NT, 0, ns->nf, ns->p, ns->z, ns->scal,
+                   ns->iflags);
+    }
+    return PHF_OK;
+}
+
+int phf_ns_recover(phf_ns* ns, const double* rhs1, double* U, double* mu, double mu_scale)
+{
+    phf_mesh* mesh = ns->mesh;
+    phf_ctx* ctx = mesh->ctx;
+    PHF_LAUNCH(ctx, "k_ns_recover_u", k_ns_recover_u, nblk(ns->nE), NT, 0, ns->nE, ns->elem_red,
+               ns->w, ns->kv, ns->Ablk, rhs1, U, ns->cs);
+    if (mu && ns->L > 0)
+        PHF_LAUNCH(ctx, "k_ns_recover_mu", k_ns_recover_mu, nblk(ns->L), NT, 0, ns->L,
+                   mesh->row_edge, mesh->edge_elems, mesh->led, ns->row_h, ns->cs, mu_scale, mu);
+    return PHF_OK;
+}
+
+// Host-side convergence loop shared by phf_solve and Crank-Nicolson.
+int phf_ns_cg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_every,
+                    int32_t* iters_out, double* relres_out, int* converged)
+{
+    phf_ctx* ctx = ns->mesh->ctx;
+    TRY(phf_ns_cg_start(ns, rtol));
+    int32_t done_iters = 0;
+    int hf[2] = {0, 0};
+    PHF_HIP(ctx, hipMemcpyAsync(hf, ns->iflags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    while (!hf[0] && done_iters < max_iter) {
+        int32_t n = std::min(check_every, max_iter - done_iters);
+        TRY(phf_ns_cg_iterate(ns, n));
+        done_iters += n;
+        PHF_HIP(ctx, hipMemcpyAsync(hf, ns->iflags, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    double sc[NS_NSCAL] = {0};
+    if (ns->nf > 0) {
+        PHF_HIP(ctx, hipMemcpyAsync(sc, ns->scal, sizeof(sc), hipMemcpyDeviceToHost, ctx->stream));
+        PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    if (iters_out) *iters_out = hf[1];
+    if (relres_out) *relres_out = sc[NS_BB] > 0 ? std::sqrt(sc[NS_RR] / sc[NS_BB]) : 0.0;
+    if (converged) *converged = ns->nf == 0 ? 1 : hf[0];
+    return PHF_OK;
+}
+
+int phf_ns_get(phf_mesh* mesh, phf_ns** out)
+{
+    if (!mesh->ns) TRY(phf_ns_create(mesh, &mesh->ns));
+    *out = mesh->ns;
+    return PHF_OK;
+}
+
+namespace {
+__global__ __launch_bounds__(NT) void k_concat(const double* __restrict__ a, int32_t na,
+                                               const double* __restrict__ b, int32_t nbn,
+                                               double* __restrict__ out)
+{
+    int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (g < na) out[g] = a[g];
+    else if (g < (int64_t)na + nbn) out[g] = b[g - na];
+}
+}  // namespace
+
+extern "C" int phf_solve(phf_mesh* mesh, const phf_coeffs* co, const phf_system* sys,
+                         const phf_solver_opts* opts, double* U, double* Lambda,
+                         phf_solve_stats* stats)
+{
+    if (!mesh) return PHF_EINVAL;
+    phf_ctx* ctx = mesh->ctx;
+    if (!co || !sys || !U || !sys->K || !sys->M || !sys->C || !sys->F || !sys->bD)
+        return phf_set_error(ctx, PHF_EINVAL, "phf_solve: K, M, C, F, bD and U are required");
+    if (co->p[0] != 0.0 || co->p[1] != 0.0)
+        return phf_set_error(ctx, PHF_EINVAL,
+                             "phf_solve: the conjugate-gradient method needs p = 0 (symmetric system)");
+    phf_solver_opts o = {PHF_SOLVER_NULLSPACE_CG, 20000, 1e-10, 8, 0};
+    if (opts) {
+        o = *opts;
+        if (o.max_iter <= 0) o.max_iter = 20000;
+        if (o.rtol <= 0) o.rtol = 1e-10;
+        if (o.check_every <= 0) o.check_every = 8;
+    }
+    if (o.method != PHF_SOLVER_NULLSPACE_CG)
+        return phf_set_error(ctx, PHF_EINVAL, "phf_solve: unknown method %d", o.method);
+    phf_ns* ns = nullptr;
+    TRY(phf_ns_get(mesh, &ns));
+    TRY(phf_ns_operator(ns, sys->K, sys->M, sys->C, 1.0, co->delta));
+    TRY(phf_ns_rhs(ns, sys->F, sys->bD));
+    TRY(phf_ns_zero_w(ns));
+    int32_t iters = 0;
+    double relres = 0;
+    int conv = 0;
+    TRY(phf_ns_cg_solve(ns, o.rtol, o.max_iter, o.check_every, &iters, &relres, &conv));
+    TRY(phf_ns_recover(ns, sys->F, U, Lambda, 1.0));
+    double srel = -1.0;
+    if (o.saddle_residual && sys->S && Lambda) {
+        const int32_t N = 3 * mesh->nE, L = mesh->L;
+        double *W = nullptr, *Fv = nullptr, *R = nullptr;
+        TRY(phf_dmalloc(ctx, &W, (size_t)N + L, "residual W"));
+        int rc = phf_dmalloc(ctx, &Fv, (size_t)N + L, "residual F");
+        if (!rc) rc = phf_dmalloc(ctx, &R, 2, "residual norms");
+        double* part = ns->part;
+        auto body = [&]() -> int {
+            PHF_LAUNCH(ctx, "k_concat", k_concat, nblk((int64_t)N + L), NT, 0, U, N, Lambda, L, W);
+            PHF_LAUNCH(ctx, "k_concat", k_concat, nblk((int64_t)N + L), NT, 0, sys->F, N, sys->bD, L, Fv);
+            // Fv <- M_vec W - F_vec
+            TRY(phf_spmv(ctx, N + L, mesh->S_rowptr, mesh->S_col, sys->S, 1.0, W, -1.0, Fv));
+            TRY(phf_dot(ctx, Fv, Fv, N + L, part, R));
+            PHF_LAUNCH(ctx, "k_concat", k_concat, nblk((int64_t)N + L), NT, 0, sys->F, N, sys->bD, L, W);
+            TRY(phf_dot(ctx, W, W, N + L, part, R + 1));
+            double h[2];
+            PHF_HIP(ctx, hipMemcpyAsync(h, R, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+            PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            srel = h[1] > 0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+            return PHF_OK;
+        };
+        if (!rc) rc = body();
+        (void)hipStreamSynchronize(ctx->stream);
+        phf_dfree(W);
+        phf_dfree(Fv);
+        phf_dfree(R);
+        if (rc) return rc;
+    }
+    if (stats) {
+        stats->iterations = iters;
+        stats->converged = conv;
+        stats->rel_residual = relres;
+        stats->saddle_rel_residual = srel;
+    }
+    if (!conv)
+        return phf_set_error(ctx, PHF_ENOCONV, "phf_solve: %d iterations, relative residual %.3e",
+                             iters, relres);
+    return PHF_OK;
+}

@@ -1,0 +1,445 @@
+"""Thin ctypes binding of libphfem.so (the C ABI declared in include/phfem.h).
+
+Every ``phf_*`` function here marshals its arguments and calls the C entry
+point of the same name; all computation runs in the HIP library. Device
+buffers are torch tensors on a ROCm device (torch is used for memory and
+streams only). A missing or unloadable library raises ``PhfLibraryError``:
+there is no fallback path.
+
+Small conveniences on top (``Context``, ``Mesh``, ``alloc_system``) only
+allocate tensors and forward to the same calls.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libphfem.so")
+
+PHF_OK, PHF_EINVAL, PHF_EORIENT, PHF_EMESH = 0, -1, -2, -3
+PHF_EBOUNDARY, PHF_ENOMEM, PHF_ENOCONV, PHF_EHIP, PHF_ESTATE = -4, -5, -6, -7, -8
+PHF_HOST, PHF_DEVICE = 0, 1
+
+PHF_FN_ZERO, PHF_FN_CONST, PHF_FN_SIN_COS, PHF_FN_SIN_SIN = 0, 1, 2, 3
+PHF_FN_GRAD_SIN_COS, PHF_FN_GRAD_SIN_SIN = 4, 5
+PHF_FN_PAPER_U, PHF_FN_PAPER_F, PHF_FN_PAPER_FLUX = 6, 7, 8
+PHF_FN_EDGE_ARRAY = 100
+PHF_SOLVER_NULLSPACE_CG = 0
+
+EXPORTED = (
+    "phf_create", "phf_destroy", "phf_set_stream", "phf_synchronize", "phf_status_str",
+    "phf_last_error", "phf_version", "phf_trace_enable", "phf_trace_reset", "phf_trace_query",
+    "phf_trace_dump", "phf_mesh_create", "phf_mesh_destroy", "phf_mesh_get_info",
+    "phf_mesh_topology", "phf_mesh_pattern", "phf_assemble", "phf_spmv", "phf_solve",
+    "phf_cn_create", "phf_cn_set_state", "phf_cn_run", "phf_cn_get_state", "phf_cn_destroy",
+)
+
+
+class PhfLibraryError(ImportError):
+    """libphfem.so is missing or cannot be loaded."""
+
+
+class PhfError(RuntimeError):
+    def __init__(self, code, fn, msg):
+        super().__init__(f"{fn} failed with {code} ({_status(code)}): {msg}")
+        self.code = code
+
+
+# ---- ABI structures (layout mirrors include/phfem.h) -----------------------
+
+class phf_mesh_info(ctypes.Structure):
+    _fields_ = [("nC", ctypes.c_int32), ("nE", ctypes.c_int32), ("n_edges", ctypes.c_int32),
+                ("N", ctypes.c_int32), ("L", ctypes.c_int32), ("nD", ctypes.c_int32),
+                ("nN", ctypes.c_int32), ("n_interior", ctypes.c_int32),
+                ("n_free", ctypes.c_int32), ("nnz_K", ctypes.c_int64),
+                ("nnz_C", ctypes.c_int64), ("nnz_saddle", ctypes.c_int64),
+                ("nnz_reduced", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+
+class phf_coeffs(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_double * 4), ("p", ctypes.c_double * 2),
+                ("delta", ctypes.c_double), ("a_T", ctypes.c_void_p)]
+
+
+class phf_fn(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("c", ctypes.c_double * 4), ("edge_values", ctypes.c_void_p)]
+
+
+class phf_data(ctypes.Structure):
+    _fields_ = [("f", phf_fn), ("g", phf_fn), ("uD", phf_fn), ("t", ctypes.c_double)]
+
+
+class phf_system(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("K", "M", "D", "C", "F", "bD", "S")]
+
+
+class phf_solver_opts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("rtol", ctypes.c_double), ("check_every", ctypes.c_int32),
+                ("saddle_residual", ctypes.c_int32)]
+
+
+class phf_solve_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("saddle_rel_residual", ctypes.c_double)]
+
+
+class phf_cn_opts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("iters_per_step", ctypes.c_int32)]
+
+
+_lib = None
+_VP, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_SIGS = {
+    "phf_create": [ctypes.POINTER(_VP), ctypes.c_int, _VP],
+    "phf_destroy": [_VP],
+    "phf_set_stream": [_VP, _VP],
+    "phf_synchronize": [_VP],
+    "phf_status_str": [ctypes.c_int],
+    "phf_last_error": [_VP],
+    "phf_version": [],
+    "phf_trace_enable": [_VP, ctypes.c_int],
+    "phf_trace_reset": [_VP],
+    "phf_trace_query": [_VP, ctypes.c_char_p, ctypes.POINTER(_I64), ctypes.POINTER(_D)],
+    "phf_trace_dump": [_VP, ctypes.c_char_p, ctypes.c_size_t],
+    "phf_mesh_create": [_VP, _VP, _I32, _VP, _I32, _VP, _I32, _VP, _I32, ctypes.c_int,
+                        ctypes.POINTER(_VP)],
+    "phf_mesh_destroy": [_VP],
+    "phf_mesh_get_info": [_VP, ctypes.POINTER(phf_mesh_info)],
+    "phf_mesh_topology": [_VP] + [_VP] * 9 + [ctypes.c_int],
+    "phf_mesh_pattern": [_VP] + [_VP] * 6 + [ctypes.c_int],
+    "phf_assemble": [_VP, ctypes.POINTER(phf_coeffs), ctypes.POINTER(phf_data),
+                     ctypes.POINTER(phf_system)],
+    "phf_spmv": [_VP, _I32, _VP, _VP, _VP, _D, _VP, _D, _VP],
+    "phf_solve": [_VP, ctypes.POINTER(phf_coeffs), ctypes.POINTER(phf_system),
+                  ctypes.POINTER(phf_solver_opts), _VP, _VP, ctypes.POINTER(phf_solve_stats)],
+    "phf_cn_create": [_VP, ctypes.POINTER(phf_coeffs), _D, ctypes.POINTER(phf_cn_opts),
+                      ctypes.POINTER(_VP)],
+    "phf_cn_set_state": [_VP, _VP, _VP, _D],
+    "phf_cn_run": [_VP, ctypes.POINTER(phf_data), _I32, _I32, ctypes.POINTER(phf_solve_stats)],
+    "phf_cn_get_state": [_VP, _VP, _VP, ctypes.POINTER(_D)],
+    "phf_cn_destroy": [_VP],
+}
+
+
+def load(path=None):
+    """Loads libphfem.so (once). Raises PhfLibraryError if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise PhfLibraryError(f"{p} not found: build it with `python -m paper_2401_15557_amd.build`")
+    try:
+        lib = ctypes.CDLL(p)
+    except OSError as e:
+        raise PhfLibraryError(f"cannot load {p}: {e}") from e
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name in ("phf_status_str", "phf_last_error",
+                                                 "phf_version") else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _status(code):
+    try:
+        return load().phf_status_str(code).decode()
+    except Exception:
+        return str(code)
+
+
+def _ptr(x):
+    """Raw address of a tensor / numpy array / int / None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if hasattr(x, "ctypes"):
+        return x.ctypes.data
+    raise TypeError(type(x))
+
+
+def _call(name, ctx, *args):
+    rc = getattr(load(), name)(*args)
+    if rc < 0:
+        msg = load().phf_last_error(ctx).decode() if ctx else ""
+        raise PhfError(rc, name, msg)
+    return rc
+
+
+# ---- C entry points (same names) -------------------------------------------
+
+def phf_version():
+    return load().phf_version().decode()
+
+
+def phf_status_str(code):
+    return load().phf_status_str(code).decode()
+
+
+def phf_create(device=0, stream=None):
+    h = _VP()
+    _call("phf_create", None, ctypes.byref(h), int(device), _ptr(stream))
+    return h.value
+
+
+def phf_destroy(ctx):
+    _call("phf_destroy", None, ctx)
+
+
+def phf_set_stream(ctx, stream):
+    _call("phf_set_stream", ctx, ctx, _ptr(stream))
+
+
+def phf_synchronize(ctx):
+    _call("phf_synchronize", ctx, ctx)
+
+
+def phf_last_error(ctx):
+    return load().phf_last_error(ctx).decode()
+
+
+def phf_trace_enable(ctx, on=True):
+    _call("phf_trace_enable", ctx, ctx, 1 if on else 0)
+
+
+def phf_trace_reset(ctx):
+    _call("phf_trace_reset", ctx, ctx)
+
+
+def phf_trace_query(ctx, kernel=None):
+    c, ms = _I64(), _D()
+    _call("phf_trace_query", ctx, ctx, kernel.encode() if kernel else None, ctypes.byref(c),
+          ctypes.byref(ms))
+    return c.value, ms.value
+
+
+def phf_trace_dump(ctx):
+    buf = ctypes.create_string_buffer(1 << 16)
+    _call("phf_trace_dump", ctx, ctx, buf, len(buf))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out
+
+
+def phf_mesh_create(ctx, xy, elem, dirichlet, neumann, memspace=PHF_HOST):
+    """xy (nC,2) float64, elem (nE,3) int32, dirichlet/neumann (n,2) int32,
+    numpy arrays (memspace=PHF_HOST) or device tensors (PHF_DEVICE)."""
+    h = _VP()
+    _call("phf_mesh_create", ctx, ctx, _ptr(xy), int(xy.shape[0]), _ptr(elem),
+          int(elem.shape[0]), _ptr(dirichlet) if len(dirichlet) else None, int(len(dirichlet)),
+          _ptr(neumann) if len(neumann) else None, int(len(neumann)), int(memspace),
+          ctypes.byref(h))
+    return h.value
+
+
+def phf_mesh_destroy(mesh):
+    _call("phf_mesh_destroy", None, mesh)
+
+
+def phf_mesh_get_info(mesh):
+    info = phf_mesh_info()
+    _call("phf_mesh_get_info", None, mesh, ctypes.byref(info))
+    return info
+
+
+def phf_mesh_topology(mesh, edge_nodes=None, edge_elems=None, elem_edges=None, led=None,
+                      ledTN=None, edge_type=None, edge_row=None, dir_edges=None, neu_edges=None,
+                      memspace=PHF_DEVICE):
+    _call("phf_mesh_topology", None, mesh, *(_ptr(a) for a in (
+        edge_nodes, edge_elems, elem_edges, led, ledTN, edge_type, edge_row, dir_edges,
+        neu_edges)), int(memspace))
+
+
+def phf_mesh_pattern(mesh, K_rowptr=None, K_col=None, C_rowptr=None, C_col=None, S_rowptr=None,
+                     S_col=None, memspace=PHF_DEVICE):
+    _call("phf_mesh_pattern", None, mesh, *(_ptr(a) for a in (
+        K_rowptr, K_col, C_rowptr, C_col, S_rowptr, S_col)), int(memspace))
+
+
+def make_coeffs(A=(1.0, 0.0, 0.0, 1.0), p=(0.0, 0.0), delta=0.0, a_T=None):
+    c = phf_coeffs()
+    for q in range(4):
+        c.A[q] = float(A[q])
+    c.p[0], c.p[1] = float(p[0]), float(p[1])
+    c.delta = float(delta)
+    c.a_T = _ptr(a_T)
+    c._keep = a_T
+    return c
+
+
+def make_fn(kind=PHF_FN_ZERO, *c, edge_values=None):
+    f = phf_fn()
+    f.kind = int(kind)
+    for q, v in enumerate(c[:4]):
+        f.c[q] = float(v)
+    if edge_values is not None:
+        f.kind = PHF_FN_EDGE_ARRAY
+        f.edge_values = _ptr(edge_values)
+    return f
+
+
+def make_data(f=None, g=None, uD=None, t=0.0):
+    d = phf_data()
+    d.f = f if f is not None else make_fn()
+    d.g = g if g is not None else make_fn()
+    d.uD = uD if uD is not None else make_fn()
+    d.t = float(t)
+    return d
+
+
+def phf_assemble(mesh, coeffs, data, system):
+    _call("phf_assemble", None, mesh, ctypes.byref(coeffs), ctypes.byref(data),
+          ctypes.byref(system))
+
+
+def phf_spmv(ctx, nrows, rowptr, col, val, alpha, x, beta, y):
+    _call("phf_spmv", ctx, ctx, int(nrows), _ptr(rowptr), _ptr(col), _ptr(val), float(alpha),
+          _ptr(x), float(beta), _ptr(y))
+
+
+def phf_solve(mesh, coeffs, system, U, Lam=None, rtol=1e-10, max_iter=20000, check_every=8,
+              saddle_residual=False, raise_on_noconv=True):
+    o = phf_solver_opts(PHF_SOLVER_NULLSPACE_CG, int(max_iter), float(rtol), int(check_every),
+                        1 if saddle_residual else 0)
+    st = phf_solve_stats()
+    rc = load().phf_solve(mesh, ctypes.byref(coeffs), ctypes.byref(system), ctypes.byref(o),
+                          _ptr(U), _ptr(Lam), ctypes.byref(st))
+    if rc < 0 and (rc != PHF_ENOCONV or raise_on_noconv):
+        raise PhfError(rc, "phf_solve", "")
+    return st
+
+
+def phf_cn_create(mesh, coeffs, k, rtol=1e-10, max_iter=5000, iters_per_step=64):
+    h = _VP()
+    o = phf_cn_opts(float(rtol), int(max_iter), int(iters_per_step))
+    _call("phf_cn_create", None, mesh, ctypes.byref(coeffs), float(k), ctypes.byref(o),
+          ctypes.byref(h))
+    return h.value
+
+
+def phf_cn_set_state(cn, U, Lam, t):
+    _call("phf_cn_set_state", None, cn, _ptr(U), _ptr(Lam), float(t))
+
+
+def phf_cn_run(cn, data, nsteps, use_graph=False, raise_on_noconv=True):
+    st = phf_solve_stats()
+    rc = load().phf_cn_run(cn, ctypes.byref(data), int(nsteps), 1 if use_graph else 0,
+                           ctypes.byref(st))
+    if rc < 0 and (rc != PHF_ENOCONV or raise_on_noconv):
+        raise PhfError(rc, "phf_cn_run", "")
+    return st
+
+
+def phf_cn_get_state(cn, U=None, Lam=None):
+    t = _D()
+    _call("phf_cn_get_state", None, cn, _ptr(U), _ptr(Lam), ctypes.byref(t))
+    return t.value
+
+
+def phf_cn_destroy(cn):
+    _call("phf_cn_destroy", None, cn)
+
+
+# ---- conveniences: tensor allocation around the calls above ----------------
+
+class Context:
+    """A phf context on ``device`` bound to torch's current stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self.handle = phf_create(device, stream.cuda_stream)
+
+    def close(self):
+        if self.handle:
+            phf_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    """Device mesh built from a meshgen.Mesh (host arrays)."""
+
+    def __init__(self, ctx: Context, m):
+        self.ctx = ctx
+        self.handle = phf_mesh_create(ctx.handle, m.coords, m.elements, m.dirichlet, m.neumann,
+                                      PHF_HOST)
+        self.info = phf_mesh_get_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            phf_mesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def topology(self):
+        """Topology tables as host numpy arrays."""
+        import numpy as np
+        i = self.info
+        out = dict(edge_nodes=np.empty((i.n_edges, 2), np.int32),
+                   edge_elems=np.empty((i.n_edges, 2), np.int32),
+                   elem_edges=np.empty((i.nE, 3), np.int32), led=np.empty(i.n_edges, np.int8),
+                   ledTN=np.empty(i.n_edges, np.int8), edge_type=np.empty(i.n_edges, np.int8),
+                   edge_row=np.empty(i.n_edges, np.int32), dir_edges=np.empty(i.nD, np.int32),
+                   neu_edges=np.empty(i.nN, np.int32))
+        phf_mesh_topology(self.handle, memspace=PHF_HOST, **out)
+        return out
+
+    def patterns(self):
+        import numpy as np
+        i = self.info
+        out = dict(K_rowptr=np.empty(i.N + 1, np.int32), K_col=np.empty(i.nnz_K, np.int32),
+                   C_rowptr=np.empty(i.L + 1, np.int32), C_col=np.empty(i.nnz_C, np.int32),
+                   S_rowptr=np.empty(i.N + i.L + 1, np.int32),
+                   S_col=np.empty(i.nnz_saddle, np.int32))
+        phf_mesh_pattern(self.handle, memspace=PHF_HOST, **out)
+        return out
+
+
+def alloc_system(mesh: Mesh, with_D=False, with_S=False):
+    """Device output tensors sized from the mesh info, and the phf_system."""
+    import torch
+    i, dev = mesh.info, mesh.ctx.device
+    t = dict(K=torch.empty(i.nnz_K, dtype=torch.float64, device=dev),
+             M=torch.empty(i.nnz_K, dtype=torch.float64, device=dev),
+             C=torch.empty(max(i.nnz_C, 1), dtype=torch.float64, device=dev),
+             F=torch.empty(i.N, dtype=torch.float64, device=dev),
+             bD=torch.empty(max(i.L, 1), dtype=torch.float64, device=dev))
+    if with_D:
+        t["D"] = torch.empty(i.nnz_K, dtype=torch.float64, device=dev)
+    if with_S:
+        t["S"] = torch.empty(i.nnz_saddle, dtype=torch.float64, device=dev)
+    s = phf_system()
+    for k, v in t.items():
+        setattr(s, k, v.data_ptr())
+    s._keep = t
+    return s, t

@@ -1,0 +1,94 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+declared in include/phfem.h, the binding's structures match the header, and
+calls fail cleanly without a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "phfem.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(phf_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2401_15557_amd import phfem
+    return phfem.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_2401_15557_amd import phfem
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(phfem.EXPORTED) == names
+
+
+def test_struct_sizes_match_header():
+    """Compiles a tiny C program against the header and compares sizeof /
+    offsetof with the ctypes mirrors."""
+    import subprocess
+    import tempfile
+    from paper_2401_15557_amd import phfem
+    prog = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "phfem.h"
+int main(void){
+ printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(phf_mesh_info), sizeof(phf_coeffs),
+   sizeof(phf_fn), sizeof(phf_data), sizeof(phf_system), sizeof(phf_solver_opts),
+   sizeof(phf_solve_stats), sizeof(phf_cn_opts));
+ printf("%zu %zu %zu %zu\n", offsetof(phf_data, g), offsetof(phf_data, t),
+   offsetof(phf_solver_opts, rtol), offsetof(phf_mesh_info, nnz_K));
+ return 0;}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "s.c")
+        open(c, "w").write(prog)
+        exe = os.path.join(d, "s")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.check_output([exe]).decode().split("\n")
+    sizes = [int(v) for v in out[0].split()]
+    offs = [int(v) for v in out[1].split()]
+    mirror = [phfem.phf_mesh_info, phfem.phf_coeffs, phfem.phf_fn, phfem.phf_data,
+              phfem.phf_system, phfem.phf_solver_opts, phfem.phf_solve_stats, phfem.phf_cn_opts]
+    assert sizes == [ctypes.sizeof(s) for s in mirror]
+    assert offs == [phfem.phf_data.g.offset, phfem.phf_data.t.offset,
+                    phfem.phf_solver_opts.rtol.offset, phfem.phf_mesh_info.nnz_K.offset]
+
+
+def test_status_strings(lib):
+    from paper_2401_15557_amd import phfem
+    for code in range(0, -9, -1):
+        assert phfem.phf_status_str(code)
+    assert phfem.phf_version().count(".") == 2
+
+
+def test_null_arguments_rejected(lib):
+    # argument checks happen before any device call
+    assert lib.phf_destroy(None) == -1
+    assert lib.phf_mesh_destroy(None) == -1
+    assert lib.phf_mesh_get_info(None, None) == -1
+    assert lib.phf_assemble(None, None, None, None) == -1
+    assert lib.phf_solve(None, None, None, None, None, None, None) == -1
+    assert lib.phf_cn_destroy(None) == -1
+    assert lib.phf_create(None, 0, None) == -1
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_2401_15557_amd import phfem
+    with pytest.raises(phfem.PhfLibraryError):
+        old = phfem._lib
+        try:
+            phfem._lib = None
+            phfem.load(str(tmp_path / "nope.so"))
+        finally:
+            phfem._lib = old

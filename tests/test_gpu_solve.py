@@ -1,0 +1,190 @@
+"""GPU parity of the saddle-point solve and the Crank-Nicolson stepper
+against the oracle (sparse LU of the same systems)."""
+import numpy as np
+import pytest
+
+from paper_2401_15557_amd import meshgen as G
+
+pytestmark = pytest.mark.gpu
+PI = np.pi
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2401_15557_amd import phfem
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = phfem.Context(0)
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+SOLVE_CASES = {
+    "c1_8x8": dict(mesh=lambda: G.unit_square_structured(8), data="sincos"),
+    "c1b": dict(mesh=lambda: G.unit_square_structured(8, ("bottom", "top")), data="sincos"),
+    "lshape3_aT": dict(mesh=lambda: G.lshape(3), data="const", aT=3),
+    "jitter_reaction": dict(mesh=lambda: G.jittered_square(20, np.random.default_rng(4),
+                                                           dirichlet_sides=()),
+                            data="sincos", delta=2.0),
+    "paper_L4_reaction": dict(mesh=lambda: G.paper_square(4), data="sincos", delta=1.0),
+}
+
+
+def _both(oracle, phfem, kind):
+    if kind == "sincos":
+        return (dict(f=oracle.fn(oracle.FN_SIN_COS, 2 * PI * PI, 0),
+                     g=oracle.fn(oracle.FN_GRAD_SIN_COS, 1, 0),
+                     uD=oracle.fn(oracle.FN_SIN_COS, 1, 0)),
+                phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * PI * PI, 0),
+                                phfem.make_fn(phfem.PHF_FN_GRAD_SIN_COS, 1, 0),
+                                phfem.make_fn(phfem.PHF_FN_SIN_COS, 1, 0)))
+    return (dict(f=oracle.fn(oracle.FN_SIN_COS, 2 * PI * PI, 0), g=oracle.fn(oracle.FN_CONST, 1),
+                 uD=oracle.fn(oracle.FN_CONST, 1)),
+            phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * PI * PI, 0),
+                            phfem.make_fn(phfem.PHF_FN_CONST, 1), phfem.make_fn(phfem.PHF_FN_CONST, 1)))
+
+
+@pytest.mark.parametrize("name", list(SOLVE_CASES))
+def test_solve_parity(ctx, oracle, name):
+    import torch
+    from paper_2401_15557_amd import phfem
+    case = SOLVE_CASES[name]
+    m = case["mesh"]()
+    print(f"case {name}: nE={m.nE}", flush=True)
+    delta = case.get("delta", 0.0)
+    aT = G.per_triangle_coefficient(m.nE, case["aT"]) if "aT" in case else None
+    od, gd = _both(oracle, phfem, case["data"])
+    dm = phfem.Mesh(ctx, m)
+    aT_d = torch.tensor(aT, device=ctx.device) if aT is not None else None
+    co = phfem.make_coeffs(delta=delta, a_T=aT_d)
+    s, t = phfem.alloc_system(dm, with_S=True)
+    phfem.phf_assemble(dm.handle, co, gd, s)
+    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    Lam = torch.empty(max(dm.info.L, 1), dtype=torch.float64, device=ctx.device)
+    st = phfem.phf_solve(dm.handle, co, s, U, Lam, rtol=1e-13, saddle_residual=True)
+    assert st.converged
+    Ug, Lg = U.cpu().numpy(), Lam.cpu().numpy()[:dm.info.L]
+    tables = oracle.mesh_tables(m)
+    asm = oracle.assemble(m, tables, aT=aT, **od)
+    Uo, Lo = oracle.solve_saddle(asm, delta)
+    assert _rel(Ug, Uo) < 1e-9, _rel(Ug, Uo)
+    assert _rel(Lg, Lo) < 1e-8, _rel(Lg, Lo)
+    # residual of the GPU solution in the oracle's own matrix
+    rp, col, val = oracle.saddle(asm, delta)
+    Fv = np.concatenate([asm["F"], asm["bD"]])
+    r = oracle.csr_matvec(rp, col, val, np.concatenate([Ug, Lg])) - Fv
+    assert np.linalg.norm(r) / np.linalg.norm(Fv) < 1e-11
+    assert 0 <= st.saddle_rel_residual < 1e-11
+
+
+def test_solve_deterministic_and_noconv(ctx):
+    import torch
+    from paper_2401_15557_amd import phfem
+    m = G.lshape(4)
+    dm = phfem.Mesh(ctx, m)
+    co = phfem.make_coeffs()
+    d = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * PI * PI, 0),
+                        phfem.make_fn(phfem.PHF_FN_CONST, 1), phfem.make_fn(phfem.PHF_FN_CONST, 1))
+    s, t = phfem.alloc_system(dm)
+    phfem.phf_assemble(dm.handle, co, d, s)
+    res = []
+    for _ in range(2):
+        U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+        L = torch.empty(dm.info.L, dtype=torch.float64, device=ctx.device)
+        phfem.phf_solve(dm.handle, co, s, U, L, rtol=1e-12)
+        res.append((U.cpu().numpy().tobytes(), L.cpu().numpy().tobytes()))
+    assert res[0] == res[1]
+    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    with pytest.raises(phfem.PhfError) as ei:
+        phfem.phf_solve(dm.handle, co, s, U, None, rtol=1e-12, max_iter=2, check_every=1)
+    assert ei.value.code == phfem.PHF_ENOCONV
+    st = phfem.phf_solve(dm.handle, co, s, U, None, rtol=1e-12, max_iter=2, check_every=1,
+                         raise_on_noconv=False)
+    assert st.iterations == 2 and not st.converged
+
+
+def _cn_setup(ctx, oracle, phfem, m, k):
+    import torch
+    tables = oracle.mesh_tables(m)
+    U0 = oracle.cr_interpolant(m, lambda x, y, t: np.sin(PI * x) * np.sin(PI * y))
+    L0 = np.random.default_rng(2).normal(size=tables["L"]) * 0.1
+    od = dict(f=oracle.fn(oracle.FN_SIN_SIN, 2 * PI * PI - 1, -1),
+              g=oracle.fn(oracle.FN_GRAD_SIN_SIN, 1, -1), uD=oracle.fn(oracle.FN_SIN_SIN, 1, -1))
+    gd = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_SIN, 2 * PI * PI - 1, -1),
+                         phfem.make_fn(phfem.PHF_FN_GRAD_SIN_SIN, 1, -1),
+                         phfem.make_fn(phfem.PHF_FN_SIN_SIN, 1, -1))
+    dm = phfem.Mesh(ctx, m)
+    cn = phfem.phf_cn_create(dm.handle, phfem.make_coeffs(), k, rtol=1e-13, iters_per_step=200)
+    Ud = torch.tensor(U0, device=ctx.device)
+    Ld = torch.tensor(L0, device=ctx.device)
+    phfem.phf_cn_set_state(cn, Ud, Ld, 0.0)
+    return tables, U0, L0, od, gd, dm, cn
+
+
+def _get(ctx, cn, dm):
+    import torch
+    from paper_2401_15557_amd import phfem
+    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    L = torch.empty(dm.info.L, dtype=torch.float64, device=ctx.device)
+    t = phfem.phf_cn_get_state(cn, U, L)
+    torch.cuda.synchronize()
+    return U.cpu().numpy(), L.cpu().numpy(), t
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_cn_parity(ctx, oracle, use_graph):
+    from paper_2401_15557_amd import phfem
+    m = G.paper_square(3, bc="x_sides")
+    k, nst = 0.01, 6
+    tables, U0, L0, od, gd, dm, cn = _cn_setup(ctx, oracle, phfem, m, k)
+    st = phfem.phf_cn_run(cn, gd, 3, use_graph=use_graph)
+    st2 = phfem.phf_cn_run(cn, gd, nst - 3, use_graph=use_graph)
+    assert st.converged and st2.converged
+    Ug, Lg, t = _get(ctx, cn, dm)
+    assert t == pytest.approx(nst * k)
+    Uo, Lo, to = oracle.cn_run(m, tables, k, nst, U0, L0, **od)
+    assert _rel(Ug, Uo) < 1e-9, _rel(Ug, Uo)
+    assert _rel(Lg, Lo) < 1e-8, _rel(Lg, Lo)
+    phfem.phf_cn_destroy(cn)
+
+
+def test_cn_graph_equals_eager(ctx, oracle):
+    from paper_2401_15557_amd import phfem
+    m = G.lshape(3)
+    out = []
+    for g in (False, True):
+        tables, U0, L0, od, gd, dm, cn = _cn_setup(ctx, oracle, phfem, m, 0.02)
+        phfem.phf_cn_run(cn, gd, 4, use_graph=g)
+        out.append(_get(ctx, cn, dm))
+        phfem.phf_cn_destroy(cn)
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
+def test_cn_steady_state(ctx, oracle):
+    """Elliptic solution as W^0 with time-independent data stays fixed."""
+    import torch
+    from paper_2401_15557_amd import phfem
+    m = G.lshape(3)
+    dm = phfem.Mesh(ctx, m)
+    co = phfem.make_coeffs(delta=0.5)
+    gd = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 3.0, 0),
+                         phfem.make_fn(phfem.PHF_FN_CONST, 0.5), phfem.make_fn(phfem.PHF_FN_CONST, 1))
+    s, t = phfem.alloc_system(dm)
+    phfem.phf_assemble(dm.handle, co, gd, s)
+    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    L = torch.empty(dm.info.L, dtype=torch.float64, device=ctx.device)
+    phfem.phf_solve(dm.handle, co, s, U, L, rtol=1e-14, max_iter=50000)
+    cn = phfem.phf_cn_create(dm.handle, co, 0.05, rtol=1e-14)
+    phfem.phf_cn_set_state(cn, U, L, 0.0)
+    phfem.phf_cn_run(cn, gd, 5)
+    Ug, Lg, _ = _get(ctx, cn, dm)
+    U0 = U.cpu().numpy()
+    L0 = L.cpu().numpy()
+    assert _rel(Ug, U0) < 1e-10
+    assert _rel(Lg, L0) < 1e-8
+    phfem.phf_cn_destroy(cn)
