@@ -1,0 +1,341 @@
+"""Benchmark of the primal hybrid FEM hot path on one MI355X.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (the elliptic benchmark configuration): L-shaped domain
+[-1,1]^2 minus [0,1]x[-1,0], 12 triangles red-refined 9 times =
+3,145,728 triangles, fp64, per-triangle coefficient a_T ~ U[0.5, 2]
+(seed 0), Dirichlet u_D = 1 on the two re-entrant edges, Neumann g = 1 on
+the rest, f = 2 pi^2 sin(pi x) cos(pi y). Inputs are synthetic and resident
+in device memory before timing starts.
+
+One step = one pass of the elliptic hot path on that mesh: upload of the
+device-resident mesh arrays + validation, edge topology, boundary
+classification and CSR patterns (phf_mesh_create), numeric assembly of K, M,
+C, F, b_D (phf_assemble), and the saddle-point solve to a relative residual
+of 1e-10 (phf_solve), then the mesh is released. `value` is elements per
+second through that step (Melem/s).
+
+The JSON line also carries, measured in the same process:
+  rows      per-stage milliseconds of the step and solver iterations;
+  assembly  the numeric assembly alone (the paper's timed computation):
+            Melem/s, algorithmic GB/s and fraction of the HBM peak;
+  cn        Crank-Nicolson steps/s on the parabolic configuration (unit
+            square, 1,048,576 triangles, k = 1e-3, 200 steps), replaying one
+            captured HIP graph per step, and eagerly;
+  roofline  the dominant kernel of the step, from HIP events on the
+            library's stream over the timed region;
+  cpu_baseline  the CPU oracle on a bounded sample, one core.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "assembled Melem/s + HBM GB/s (4M tris); CN steps/s; served p50/p99 latency"
+
+
+def algorithmic_bytes(info, has_aT=True):
+    """Bytes a kernel must move at least, per launch, by kernel name.
+
+    k_assemble: read coordinates once (16 B/node), element vertices
+    (12 B/elem), a_T (8 B/elem), the two end nodes of each multiplier row
+    (8 B/row); write K and M (72 B/elem each), F (24 B/elem), C (8 B/nnz)
+    and b_D (8 B/row).
+    """
+    nE, nC, L = info.nE, info.nC, info.L
+    nf, nnzR = info.n_free, info.nnz_reduced
+    asm = (16 * nC + 12 * nE + (8 * nE if has_aT else 0) + 8 * L +
+           8 * (9 * nE) * 2 + 8 * 3 * nE + 8 * info.nnz_C + 8 * L)
+    return {
+        "k_assemble": asm,
+        # reduced operator values + columns (12 B/nnz), z in; p, q in and out
+        "k_cg_dir": 12 * nnzR + 40 * nf,
+        # read p, q, w, r, dinv; write w, r, z
+        "k_cg_upd": 64 * nf,
+    }
+
+
+def csrc_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2401_15557_amd", "csrc")
+    for n in sorted(os.listdir(d)):
+        if n.endswith((".hip", ".h")):
+            h.update(open(os.path.join(d, n), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel):
+    """HBM traffic per launch from the committed counter summary, if it was
+    taken on the current kernel sources; otherwise None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or k.get("csrc_hash") != csrc_hash():
+        return None
+    return k.get("bytes_per_launch")
+
+
+def cpu_baseline(level=7, repeat=2):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-m", "oracle.baseline", "--level", str(level),
+                        "--repeat", str(repeat), "--solve"], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    o = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": o["nE"] / o["total_s"] / 1e6, "unit": "Melem/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"L-shape level {level} ({o['nE']} triangles), same data; topology + "
+                       f"assembly + saddle CSR + sparse LU solve, best of {repeat}; "
+                       f"stage s: topo {o['topology_s']:.3f} asm {o['assembly_s']:.3f} "
+                       f"saddle {o['saddle_s']:.3f} solve {o['solve_s']:.3f}")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--level", type=int, default=9, help="L-shape refinement level")
+    ap.add_argument("--asm-reps", type=int, default=30)
+    ap.add_argument("--cn-level", type=int, default=9)
+    ap.add_argument("--cn-steps", type=int, default=200)
+    ap.add_argument("--cn-chunk", type=int, default=32,
+                    help="CG iterations per captured graph chunk")
+    ap.add_argument("--no-cn", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rtol", type=float, default=1e-10)
+    a = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(how the path would shard is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2401_15557_amd import meshgen as G
+    from paper_2401_15557_amd import phfem
+
+    dev = torch.device("cuda", 0)
+    pi = np.pi
+    print(f"[bench] building inputs (L-shape level {a.level})", file=sys.stderr, flush=True)
+    m = G.lshape(a.level)
+    aT = G.per_triangle_coefficient(m.nE, 0)
+    xy_d = torch.tensor(m.coords, device=dev)
+    el_d = torch.tensor(m.elements, device=dev)
+    D_d = torch.tensor(m.dirichlet, device=dev)
+    N_d = torch.tensor(m.neumann, device=dev)
+    aT_d = torch.tensor(aT, device=dev)
+    ctx = phfem.Context(0)
+    co = phfem.make_coeffs(a_T=aT_d)
+    data = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * pi * pi, 0),
+                           phfem.make_fn(phfem.PHF_FN_CONST, 1.0),
+                           phfem.make_fn(phfem.PHF_FN_CONST, 1.0))
+    h = ctx.handle
+    out = {}
+
+    def one_step(rows):
+        t0 = time.perf_counter()
+        mh = phfem.phf_mesh_create(h, xy_d, el_d, D_d, N_d, phfem.PHF_DEVICE)
+        t1 = time.perf_counter()
+        info = phfem.phf_mesh_get_info(mh)
+        if "sys" not in out:
+            sysd = phfem.phf_system()
+            t = dict(K=torch.empty(info.nnz_K, dtype=torch.float64, device=dev),
+                     M=torch.empty(info.nnz_K, dtype=torch.float64, device=dev),
+                     C=torch.empty(info.nnz_C, dtype=torch.float64, device=dev),
+                     F=torch.empty(info.N, dtype=torch.float64, device=dev),
+                     bD=torch.empty(info.L, dtype=torch.float64, device=dev),
+                     U=torch.empty(info.N, dtype=torch.float64, device=dev),
+                     Lam=torch.empty(info.L, dtype=torch.float64, device=dev))
+            for k in ("K", "M", "C", "F", "bD"):
+                setattr(sysd, k, t[k].data_ptr())
+            out["sys"], out["t"], out["info"] = sysd, t, info
+        sysd, t = out["sys"], out["t"]
+        phfem.phf_assemble(mh, co, data, sysd)
+        phfem.phf_synchronize(h)
+        t2 = time.perf_counter()
+        st = phfem.phf_solve(mh, co, sysd, t["U"], t["Lam"], rtol=a.rtol, max_iter=200000,
+                             check_every=32)
+        t3 = time.perf_counter()
+        phfem.phf_mesh_destroy(mh)
+        t4 = time.perf_counter()
+        rows.append(dict(mesh_ms=1e3 * (t1 - t0), assemble_ms=1e3 * (t2 - t1),
+                         solve_ms=1e3 * (t3 - t2), release_ms=1e3 * (t4 - t3),
+                         iterations=st.iterations, rel_residual=st.rel_residual))
+
+    print(f"[bench] warmup {a.warmup} step(s), nE={m.nE}", file=sys.stderr, flush=True)
+    warm = []
+    for _ in range(a.warmup):
+        one_step(warm)
+        print(f"[bench] warmup step {warm[-1]}", file=sys.stderr, flush=True)
+    rows = []
+    phfem.phf_trace_enable(h, True)
+    phfem.phf_trace_reset(h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        one_step(rows)
+        print(f"[bench] step {s}: {rows[-1]}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = phfem.phf_trace_dump(h)
+    phfem.phf_trace_enable(h, False)
+    ms_step = 1e3 * (t1 - t0) / a.steps
+    info = out["info"]
+    nE = info.nE
+
+    # dominant kernel of the timed steps
+    dom = max(kern.items(), key=lambda kv: kv[1][1])
+    dname, (dcount, dms) = dom
+    ab = algorithmic_bytes(info)
+    roof = None
+    if dname in ab:
+        avg_s = dms / dcount / 1e3
+        ach = ab[dname] / avg_s / 1e9
+        tr = traffic_for(dname)
+        roof = {"bound": "hbm", "kernel": dname, "achieved": round(ach, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": tr, "avg_launch_us": round(avg_s * 1e6, 3), "launches": dcount,
+                "algorithmic_bytes_per_launch": ab[dname]}
+
+    # numeric assembly alone (the computation the paper times)
+    print("[bench] assembly-only timing", file=sys.stderr, flush=True)
+    mh = phfem.phf_mesh_create(h, xy_d, el_d, D_d, N_d, phfem.PHF_DEVICE)
+    sysd = out["sys"]
+    for _ in range(3):
+        phfem.phf_assemble(mh, co, data, sysd)
+    phfem.phf_synchronize(h)
+    phfem.phf_trace_enable(h, True)
+    phfem.phf_trace_reset(h)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(a.asm_reps):
+        phfem.phf_assemble(mh, co, data, sysd)
+    ev1.record()
+    torch.cuda.synchronize()
+    cnt, tot = phfem.phf_trace_query(h, "k_assemble")
+    phfem.phf_trace_enable(h, False)
+    asm_us = tot / cnt * 1e3
+    wall_us = ev0.elapsed_time(ev1) / a.asm_reps * 1e3
+    asm_gbs = ab["k_assemble"] / (asm_us * 1e-6) / 1e9
+    out_asm = {"Melem_per_s": round(nE / asm_us, 1), "kernel_us": round(asm_us, 2),
+               "stream_us_per_call": round(wall_us, 2),
+               "algorithmic_bytes": ab["k_assemble"],
+               "bytes_per_elem": round(ab["k_assemble"] / nE, 1),
+               "GB_per_s": round(asm_gbs, 1), "frac_of_hbm_peak": round(asm_gbs / HBM_PEAK_GBS, 4),
+               "traffic": traffic_for("k_assemble"), "launches": cnt}
+    phfem.phf_mesh_destroy(mh)
+
+    # Crank-Nicolson on the parabolic configuration
+    out_cn = None
+    if not a.no_cn:
+        print(f"[bench] Crank-Nicolson (paper mesh level {a.cn_level})", file=sys.stderr,
+              flush=True)
+        mc = G.paper_square(a.cn_level, bc="x_sides")
+        dmc = phfem.phf_mesh_create(h, mc.coords, mc.elements, mc.dirichlet, mc.neumann)
+        ic = phfem.phf_mesh_get_info(dmc)
+        k = 1e-3
+        cn = phfem.phf_cn_create(dmc, phfem.make_coeffs(), k, rtol=1e-10,
+                                 iters_per_step=a.cn_chunk)
+        # initial state: P1 values through u0 at the edge midpoints (exact
+        # for the discrete constraint), Lambda = 0
+        P = mc.coords[mc.elements]
+        mids = np.stack([(P[:, 1] + P[:, 2]) / 2, (P[:, 2] + P[:, 0]) / 2,
+                         (P[:, 0] + P[:, 1]) / 2], axis=1)
+        um = np.sin(pi * mids[..., 0]) * np.sin(pi * mids[..., 1])
+        U0 = np.stack([um[:, 1] + um[:, 2] - um[:, 0], um[:, 2] + um[:, 0] - um[:, 1],
+                       um[:, 0] + um[:, 1] - um[:, 2]], axis=1).reshape(-1)
+        U0d = torch.tensor(U0, device=dev)
+        L0d = torch.zeros(ic.L, dtype=torch.float64, device=dev)
+        cdata = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_SIN, 2 * pi * pi - 1, -1),
+                                phfem.make_fn(phfem.PHF_FN_GRAD_SIN_SIN, 1, -1),
+                                phfem.make_fn(phfem.PHF_FN_SIN_SIN, 1, -1))
+        res = {}
+        for mode, nst in (("eager", max(a.cn_steps // 10, 5)), ("graph", a.cn_steps)):
+            phfem.phf_cn_set_state(cn, U0d, L0d, 0.0)
+            st0 = phfem.phf_cn_run(cn, cdata, 2, use_graph=(mode == "graph"),
+                                   raise_on_noconv=False)  # warm-up / capture
+            print(f"[bench] cn {mode} warm-up: iters={st0.iterations} conv={st0.converged} "
+                  f"rel={st0.rel_residual:.2e}", file=sys.stderr, flush=True)
+            phfem.phf_cn_set_state(cn, U0d, L0d, 0.0)
+            torch.cuda.synchronize()
+            c0 = time.perf_counter()
+            st = phfem.phf_cn_run(cn, cdata, nst, use_graph=(mode == "graph"),
+                                  raise_on_noconv=False)
+            torch.cuda.synchronize()
+            c1 = time.perf_counter()
+            res[mode] = dict(steps=nst, steps_per_s=round(nst / (c1 - c0), 1),
+                             cg_iters_per_step=round(st.iterations / nst, 2),
+                             all_converged=bool(st.converged),
+                             worst_rel_residual=st.rel_residual)
+            print(f"[bench] cn {mode}: {res[mode]}", file=sys.stderr, flush=True)
+        # accuracy at t = 0.2 after the graph run: max nodal error
+        Ud = torch.empty(ic.N, dtype=torch.float64, device=dev)
+        phfem.phf_cn_set_state(cn, U0d, L0d, 0.0)
+        phfem.phf_cn_run(cn, cdata, a.cn_steps, use_graph=True, raise_on_noconv=False)
+        tf = phfem.phf_cn_get_state(cn, Ud, None)
+        torch.cuda.synchronize()
+        ue = np.exp(-tf) * np.sin(pi * P[..., 0]) * np.sin(pi * P[..., 1])
+        err = float(np.abs(Ud.cpu().numpy().reshape(-1, 3) - ue).max())
+        phfem.phf_cn_destroy(cn)
+        phfem.phf_mesh_destroy(dmc)
+        out_cn = dict(workload=f"unit square, paper mesh level {a.cn_level} ({ic.nE} triangles), "
+                               f"u = exp(-t) sin(pi x) sin(pi y), k = {k}",
+                      t_final=tf, max_nodal_error=err, **res)
+
+    cpu = None
+    if not a.no_cpu:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+
+    mean = {k: float(np.mean([r[k] for r in rows])) for k in rows[0]}
+    line = {
+        "metric": METRIC,
+        "value": round(nE / (ms_step * 1e-3) / 1e6, 3),
+        "unit": "Melem/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"elliptic L-shape, {nE} triangles (12 x 4^{a.level}), fp64, "
+                                f"a_T~U[0.5,2] seed 0, mixed BCs; step = mesh upload+topology+"
+                                f"patterns + assembly + saddle solve (rtol {a.rtol})"),
+                   "nE": nE, "n_edges": info.n_edges, "L": info.L, "N": info.N},
+        "rows": {"mesh_topology_patterns_ms": round(mean["mesh_ms"], 3),
+                 "assembly_ms": round(mean["assemble_ms"], 3),
+                 "solve_ms": round(mean["solve_ms"], 3),
+                 "release_ms": round(mean["release_ms"], 3),
+                 "solve_iterations": int(mean["iterations"]),
+                 "solve_rel_residual": mean["rel_residual"]},
+        "assembly": out_asm,
+        "cn": out_cn,
+        "roofline": roof,
+        "kernels_ms": {k: round(v[1], 3) for k, v in sorted(kern.items(), key=lambda kv: -kv[1][1])[:8]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -252,16 +252,18 @@ int phf_solve(phf_mesh* mesh, const phf_coeffs* coeffs, const phf_system* sys,
  * phf_cn_create assembles K, M, C once (coeffs as for phf_assemble, p = 0),
  * k > 0. set_state copies U (N) and Lambda (L) device arrays and sets t.
  * phf_cn_run advances nsteps steps with the time-dependent data `data`
- * (data->t is ignored); use_graph = 1 captures one step in a HIP graph and
- * replays it (the per-step solve then runs a fixed budget of
- * `iters_per_step` CG iterations, each skipped on the device once the
- * residual is below rtol). get_state copies the current state out (device)
- * and returns t. stats (may be NULL) receives the total CG iterations and
- * the worst final reduced residual over the steps. */
+ * (data->t is ignored); use_graph = 1 captures a step as three HIP graphs
+ * (loads, right-hand side and the first `iters_per_step` CG iterations; a
+ * chunk of `iters_per_step` iterations; recovery and state update) and
+ * replays them, the chunk until the device-side convergence flag is set
+ * (iterations after convergence are skipped on the device). get_state
+ * copies the current state out (device) and returns t. stats (may be NULL)
+ * receives the total CG iterations and the worst final reduced residual over
+ * the steps. */
 typedef struct {
     double rtol;            /* 0 = 1e-10                                   */
     int32_t max_iter;       /* per step, eager mode; 0 = 5000             */
-    int32_t iters_per_step; /* graph mode budget; 0 = 64                   */
+    int32_t iters_per_step; /* CG iterations per captured chunk (even); 0 = 32 */
 } phf_cn_opts;
 
 int phf_cn_create(phf_mesh* mesh, const phf_coeffs* coeffs, double k, const phf_cn_opts* opts,

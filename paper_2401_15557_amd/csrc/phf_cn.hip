@@ -24,12 +24,15 @@ struct phf_cn {
     double *F0 = nullptr, *F1 = nullptr, *bD0 = nullptr, *bD1 = nullptr;
     double *r1 = nullptr, *r2 = nullptr;
     int64_t* d_step = nullptr;  // index n of the step being computed
+    double *w1 = nullptr, *w2 = nullptr;  // reduced solutions of the last two steps
+    int32_t* d_nsol = nullptr;            // solves since set_state (0, 1, 2+)
     double* d_stats = nullptr;  // [0] CG iterations, [1] worst relres, [2] unconverged steps
     double t0 = 0;
     int64_t n = 0;              // completed steps since set_state
     bool have_state = false;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
+    // graph mode: head (+ first chunk of CG iterations), chunk, tail
+    hipGraphExec_t gx[3] = {nullptr, nullptr, nullptr};
+    hipGraph_t g[3] = {nullptr, nullptr, nullptr};
     phf_data gdata{};           // data the graph was captured with
 };
 
@@ -44,6 +47,29 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
     } while (0)
 
 __global__ void k_cn_inc(int64_t* step) { *step += 1; }
+
+// Initial CG guess from the last two reduced solutions: 0, w1, or the linear
+// extrapolation 2 w1 - w2 (second order in k for a smooth trajectory).
+__global__ __launch_bounds__(NT) void k_cn_guess(int32_t nf, const int32_t* __restrict__ nsol,
+                                                 const double* __restrict__ w1,
+                                                 const double* __restrict__ w2,
+                                                 double* __restrict__ w)
+{
+    const int32_t c = *nsol;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT)
+        w[i] = c == 0 ? 0.0 : (c == 1 ? w1[i] : 2.0 * w1[i] - w2[i]);
+}
+
+__global__ __launch_bounds__(NT) void k_cn_keep(int32_t nf, int32_t* __restrict__ nsol,
+                                                const double* __restrict__ w,
+                                                double* __restrict__ w1, double* __restrict__ w2)
+{
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
+        w2[i] = w1[i];
+        w1[i] = w[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nsol = min(*nsol + 1, 2);
+}
 
 // r1 per element (see file comment).
 __global__ __launch_bounds__(NT) void k_cn_rhs_elem(
@@ -145,6 +171,9 @@ int cn_step_head(phf_cn* cn, const phf_data* data)
         PHF_LAUNCH(ctx, "k_cn_rhs_row", k_cn_rhs_row, nblk(L), NT, 0, L, mesh->C_rowptr,
                    mesh->C_col, cn->C, cn->U, cn->bD0, cn->bD1, cn->r2);
     TRY(phf_ns_rhs(cn->ns, cn->r1, cn->r2));
+    if (cn->ns->nf > 0)
+        PHF_LAUNCH(ctx, "k_cn_guess", k_cn_guess, cn->ns->nbv, NT, 0, cn->ns->nf, cn->d_nsol,
+                   cn->w1, cn->w2, cn->ns->w);
     TRY(phf_ns_cg_start(cn->ns, cn->opts.rtol));
     return PHF_OK;
 }
@@ -155,6 +184,9 @@ int cn_step_tail(phf_cn* cn)
     phf_ctx* ctx = mesh->ctx;
     const int32_t N = 3 * mesh->nE, L = mesh->L;
     TRY(phf_ns_recover(cn->ns, cn->r1, cn->U, cn->Lam, 2.0 / cn->k));
+    if (cn->ns->nf > 0)
+        PHF_LAUNCH(ctx, "k_cn_keep", k_cn_keep, cn->ns->nbv, NT, 0, cn->ns->nf, cn->d_nsol,
+                   cn->ns->w, cn->w1, cn->w2);
     PHF_LAUNCH(ctx, "k_cn_shift", k_cn_shift, nblk((int64_t)N + L), NT, 0, N, L, cn->F0, cn->F1,
                cn->bD0, cn->bD1);
     PHF_LAUNCH(ctx, "k_cn_stats", k_cn_stats, 1, 1, 0, cn->ns->iflags, cn->ns->scal, cn->d_stats);
@@ -163,16 +195,50 @@ int cn_step_tail(phf_cn* cn)
 
 void cn_drop_graph(phf_cn* cn)
 {
-    if (cn->gexec) (void)hipGraphExecDestroy(cn->gexec);
-    if (cn->graph) (void)hipGraphDestroy(cn->graph);
-    cn->gexec = nullptr;
-    cn->graph = nullptr;
+    for (int q = 0; q < 3; ++q) {
+        if (cn->gx[q]) (void)hipGraphExecDestroy(cn->gx[q]);
+        if (cn->g[q]) (void)hipGraphDestroy(cn->g[q]);
+        cn->gx[q] = nullptr;
+        cn->g[q] = nullptr;
+    }
 }
 
 bool same_fn(const phf_fn& a, const phf_fn& b)
 {
     return a.kind == b.kind && a.c[0] == b.c[0] && a.c[1] == b.c[1] && a.c[2] == b.c[2] &&
            a.c[3] == b.c[3] && a.edge_values == b.edge_values;
+}
+
+// Captures part q of a step (0: head + first chunk, 1: chunk, 2: tail).
+int cn_capture_part(phf_cn* cn, const phf_data* data, int q, hipStream_t cap)
+{
+    phf_ctx* ctx = cn->mesh->ctx;
+    int rc = PHF_OK;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return phf_set_error(ctx, PHF_EHIP, "begin capture failed: %s", hipGetErrorString(e));
+    if (q == 0) {
+        rc = cn_step_head(cn, data);
+        if (!rc) rc = phf_ns_cg_iterate(cn->ns, cn->opts.iters_per_step);
+    } else if (q == 1) {
+        rc = phf_ns_cg_iterate(cn->ns, cn->opts.iters_per_step);
+    } else {
+        rc = cn_step_tail(cn);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cap, &g);
+    if (!rc && e2 != hipSuccess)
+        rc = phf_set_error(ctx, PHF_EHIP, "graph capture failed: %s", hipGetErrorString(e2));
+    if (!rc) {
+        cn->g[q] = g;
+        e2 = hipGraphInstantiate(&cn->gx[q], g, nullptr, nullptr, 0);
+        if (e2 != hipSuccess)
+            rc = phf_set_error(ctx, PHF_EHIP, "graph instantiation failed: %s",
+                               hipGetErrorString(e2));
+    } else if (g) {
+        (void)hipGraphDestroy(g);
+    }
+    return rc;
 }
 
 int cn_capture(phf_cn* cn, const phf_data* data)
@@ -185,27 +251,7 @@ int cn_capture(phf_cn* cn, const phf_data* data)
     ctx->stream = cap;
     ctx->trace = false;
     int rc = PHF_OK;
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        rc = cn_step_head(cn, data);
-        if (!rc) rc = phf_ns_cg_iterate(cn->ns, cn->opts.iters_per_step);
-        if (!rc) rc = cn_step_tail(cn);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(cap, &g);
-        if (!rc && e2 != hipSuccess)
-            rc = phf_set_error(ctx, PHF_EHIP, "graph capture failed: %s", hipGetErrorString(e2));
-        if (!rc) {
-            cn->graph = g;
-            e2 = hipGraphInstantiate(&cn->gexec, g, nullptr, nullptr, 0);
-            if (e2 != hipSuccess)
-                rc = phf_set_error(ctx, PHF_EHIP, "graph instantiation failed: %s",
-                                   hipGetErrorString(e2));
-        } else if (g) {
-            (void)hipGraphDestroy(g);
-        }
-    } else {
-        rc = phf_set_error(ctx, PHF_EHIP, "begin capture failed: %s", hipGetErrorString(e));
-    }
+    for (int q = 0; q < 3 && !rc; ++q) rc = cn_capture_part(cn, data, q, cap);
     ctx->stream = saved;
     ctx->trace = saved_trace;
     (void)hipStreamDestroy(cap);
@@ -225,6 +271,9 @@ extern "C" int phf_cn_destroy(phf_cn* cn)
                       cn->F1, cn->bD0, cn->bD1, cn->r1, cn->r2, cn->d_stats};
     for (double* b : bufs) phf_dfree(b);
     phf_dfree(cn->d_step);
+    phf_dfree(cn->w1);
+    phf_dfree(cn->w2);
+    phf_dfree(cn->d_nsol);
     delete cn;
     return PHF_OK;
 }
@@ -245,7 +294,8 @@ extern "C" int phf_cn_create(phf_mesh* mesh, const phf_coeffs* co, double k,
     cn->co = *co;
     cn->opts.rtol = opts && opts->rtol > 0 ? opts->rtol : 1e-10;
     cn->opts.max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 5000;
-    cn->opts.iters_per_step = opts && opts->iters_per_step > 0 ? opts->iters_per_step : 64;
+    cn->opts.iters_per_step = opts && opts->iters_per_step > 0 ? opts->iters_per_step : 32;
+    cn->opts.iters_per_step += cn->opts.iters_per_step & 1;  // chunks keep the CG parity
     const size_t N = 3 * (size_t)mesh->nE, L = mesh->L, nnzK = 9 * (size_t)mesh->nE;
     auto body = [&]() -> int {
         TRY(phf_dmalloc(ctx, &cn->K, nnzK, "CN K"));
@@ -263,6 +313,9 @@ extern "C" int phf_cn_create(phf_mesh* mesh, const phf_coeffs* co, double k,
         TRY(phf_dmalloc(ctx, &cn->r2, L, "CN r2"));
         TRY(phf_dmalloc(ctx, &cn->d_stats, 4, "CN stats"));
         TRY(phf_dmalloc(ctx, &cn->d_step, 1, "CN step"));
+        TRY(phf_dmalloc(ctx, &cn->w1, std::max<int32_t>(mesh->n_free, 1), "CN w1"));
+        TRY(phf_dmalloc(ctx, &cn->w2, std::max<int32_t>(mesh->n_free, 1), "CN w2"));
+        TRY(phf_dmalloc(ctx, &cn->d_nsol, 1, "CN solves"));
         // K, M, C once (the coefficient is time independent)
         phf_system s{};
         s.K = cn->K;
@@ -299,6 +352,7 @@ extern "C" int phf_cn_set_state(phf_cn* cn, const double* U, const double* Lambd
     cn->n = 0;
     cn->have_state = true;
     TRY(phf_ns_zero_w(cn->ns));
+    PHF_HIP(ctx, hipMemsetAsync(cn->d_nsol, 0, sizeof(int32_t), ctx->stream));
     return PHF_OK;
 }
 
@@ -329,23 +383,31 @@ extern "C" int phf_cn_run(phf_cn* cn, const phf_data* data, int32_t nsteps, int3
     PHF_HIP(ctx, hipMemsetAsync(cn->d_stats, 0, 4 * sizeof(double), ctx->stream));
     PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (use_graph) {
-        if (cn->gexec && !(same_fn(cn->gdata.f, data->f) && same_fn(cn->gdata.g, data->g) &&
+        if (cn->gx[0] && !(same_fn(cn->gdata.f, data->f) && same_fn(cn->gdata.g, data->g) &&
                            same_fn(cn->gdata.uD, data->uD)))
             cn_drop_graph(cn);
-        if (!cn->gexec) TRY(cn_capture(cn, data));
+        if (!cn->gx[0]) TRY(cn_capture(cn, data));
         for (int32_t s = 0; s < nsteps; ++s) {
             phf_trace_rec rec;
             phf_trace_begin(ctx, "cn_graph_step", &rec);
-            PHF_HIP(ctx, hipGraphLaunch(cn->gexec, ctx->stream));
+            PHF_HIP(ctx, hipGraphLaunch(cn->gx[0], ctx->stream));
+            int32_t it = cn->opts.iters_per_step;
+            int hf[2] = {0, 0};
+            for (;;) {
+                PHF_HIP(ctx, hipMemcpyAsync(hf, cn->ns->iflags, 2 * sizeof(int),
+                                            hipMemcpyDeviceToHost, ctx->stream));
+                PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+                if (hf[0] || it >= cn->opts.max_iter) break;
+                PHF_HIP(ctx, hipGraphLaunch(cn->gx[1], ctx->stream));
+                it += cn->opts.iters_per_step;
+            }
+            PHF_HIP(ctx, hipGraphLaunch(cn->gx[2], ctx->stream));
             phf_trace_end(ctx, &rec);
         }
     } else {
         for (int32_t s = 0; s < nsteps; ++s) {
             TRY(cn_step_head(cn, data));
             int32_t it = 0;
-            double rel = 0;
-            int conv = 0;
-            // phf_ns_cg_solve restarts CG; call its loop body through the public pieces
             int hf[2] = {0, 0};
             PHF_HIP(ctx, hipMemcpyAsync(hf, cn->ns->iflags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
             PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -356,8 +418,6 @@ extern "C" int phf_cn_run(phf_cn* cn, const phf_data* data, int32_t nsteps, int3
                 PHF_HIP(ctx, hipMemcpyAsync(hf, cn->ns->iflags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
                 PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
             }
-            (void)rel;
-            (void)conv;
             TRY(cn_step_tail(cn));
         }
     }

@@ -136,11 +136,15 @@ void phf_trace_begin(phf_ctx* ctx, const char* name, phf_trace_rec* rec)
     if (rec->start) (void)hipEventRecord(rec->start, ctx->stream);
 }
 
+static int trace_collect(phf_ctx* ctx);
+
 void phf_trace_end(phf_ctx* ctx, phf_trace_rec* rec)
 {
     if (!ctx->trace || !rec->start || !rec->stop) return;
     (void)hipEventRecord(rec->stop, ctx->stream);
     ctx->pending.push_back(*rec);
+    // bound the number of events in flight; reading them waits for the stream
+    if (ctx->pending.size() >= 16384) (void)trace_collect(ctx);
 }
 
 static int trace_collect(phf_ctx* ctx)
@@ -171,6 +175,15 @@ extern "C" int phf_trace_enable(phf_ctx* ctx, int on)
 {
     if (!ctx) return PHF_EINVAL;
     ctx->trace = on != 0;
+    // create the events up front so that tracing adds no creation cost later
+    while (ctx->trace && ctx->event_pool.size() + 2 * ctx->pending.size() < 2 * 16384 + 64) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            break;
+        }
+        ctx->event_pool.push_back(e);
+    }
     return PHF_OK;
 }
 

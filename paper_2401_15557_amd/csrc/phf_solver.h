@@ -42,14 +42,15 @@ struct phf_ns {
     double* z = nullptr;
     double* p = nullptr;
     double* q = nullptr;
-    double* part = nullptr;       // 3 x 1024 partial sums
+    double* part = nullptr;       // 5 x 1024 partial sums
     double* scal = nullptr;       // device scalars
     int* iflags = nullptr;        // [0] done, [1] iterations
     bool have_operator = false;
+    int32_t next_it = 0;          // index of the next CG iteration issued
 };
 
 // Scalar slots in phf_ns::scal.
-enum { NS_RZ = 0, NS_PQ, NS_ALPHA, NS_BETA, NS_RR, NS_BB, NS_TOL2, NS_NSCAL = 8 };
+enum { NS_RR = 0, NS_BB, NS_TOL2, NS_NSCAL = 8 };
 
 int phf_ns_create(phf_mesh* mesh, phf_ns** out);
 void phf_ns_destroy(phf_ns* ns);

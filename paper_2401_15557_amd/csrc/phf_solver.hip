@@ -171,6 +171,20 @@ __global__ __launch_bounds__(NT) void k_ns_gather(int32_t nf, const int32_t* __r
 }
 
 // ---- conjugate gradients with device-side scalars --------------------------
+//
+// Two kernels per iteration i (i = 0, 1, ...):
+//   dir(i):    beta = rz_i / rz_{i-1} (0 for i = 0); p = z + beta p;
+//              q = A z + beta q  (= A p by linearity); partial sums of p.q.
+//              For i > 0 it first tests the residual of iteration i: if
+//              ||r||^2 <= tol^2 ||b||^2 every block exits and block 0 raises
+//              the done flag.
+//   upd(i):    alpha = rz_i / p.q; w += alpha p; r -= alpha q; z = D^-1 r;
+//              partial sums of r.z (into the slot of parity i+1) and r.r.
+// Every block reduces the partial-sum arrays itself in the same fixed order,
+// so all blocks see bitwise identical scalars and no kernel writes a value
+// that another block of the same launch reads. The iteration index arrives as
+// a kernel argument, so an unrolled chain can be captured in a graph; once
+// done is set, the remaining kernels of the chain return immediately.
 
 __device__ inline double ell_row(int32_t r, int32_t nf, const int32_t* __restrict__ col,
                                  const double* __restrict__ val, const double* __restrict__ x)
@@ -184,13 +198,26 @@ __device__ inline double ell_row(int32_t r, int32_t nf, const int32_t* __restric
     return s;
 }
 
+// Partial-sum layout in phf_ns::part (MAXB slots each).
+enum { P_RZ0 = 0, P_RZ1 = 1, P_PQ = 2, P_RR = 3, P_BB = 4, P_NARR = 5 };
+
+// Sum of nb partials in a fixed order, broadcast to the whole block.
+__device__ inline double block_reduce_partials(const double* __restrict__ part, int32_t nb,
+                                               double* sh)
+{
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nb; q += NT) s += part[q];
+    return phf_block_sum_f64<NT>(s, sh);
+}
+
 __global__ __launch_bounds__(NT) void k_cg_init(int32_t nf, const int32_t* __restrict__ col,
                                                 const double* __restrict__ val,
                                                 const double* __restrict__ dinv,
                                                 const double* __restrict__ b,
                                                 const double* __restrict__ w,
                                                 double* __restrict__ r, double* __restrict__ z,
-                                                double* __restrict__ p, double* __restrict__ part)
+                                                double* __restrict__ p, double* __restrict__ q,
+                                                double* __restrict__ part)
 {
     __shared__ double sh[NT / 64];
     double s_rz = 0.0, s_rr = 0.0, s_bb = 0.0;
@@ -199,7 +226,8 @@ __global__ __launch_bounds__(NT) void k_cg_init(int32_t nf, const int32_t* __res
         double zi = dinv[i] * ri;
         r[i] = ri;
         z[i] = zi;
-        p[i] = zi;
+        p[i] = 0.0;
+        q[i] = 0.0;
         s_rz = fma(ri, zi, s_rz);
         s_rr = fma(ri, ri, s_rr);
         s_bb = fma(b[i], b[i], s_bb);
@@ -208,28 +236,19 @@ __global__ __launch_bounds__(NT) void k_cg_init(int32_t nf, const int32_t* __res
     double t1 = phf_block_sum_f64<NT>(s_rr, sh);
     double t2 = phf_block_sum_f64<NT>(s_bb, sh);
     if (threadIdx.x == 0) {
-        part[blockIdx.x] = t0;
-        part[MAXB + blockIdx.x] = t1;
-        part[2 * MAXB + blockIdx.x] = t2;
+        part[P_RZ0 * MAXB + blockIdx.x] = t0;
+        part[P_RR * MAXB + blockIdx.x] = t1;
+        part[P_BB * MAXB + blockIdx.x] = t2;
     }
-}
-
-__device__ inline double sum_partials(const double* part, int32_t nb, double* sh)
-{
-    double s = 0.0;
-    for (int q = threadIdx.x; q < nb; q += NT) s += part[q];
-    return phf_block_sum_f64<NT>(s, sh);
 }
 
 __global__ __launch_bounds__(NT) void k_cg_init_final(const double* __restrict__ part, int32_t nb,
                                                       double tol2, double* scal, int* iflags)
 {
     __shared__ double sh[NT / 64];
-    double rz = sum_partials(part, nb, sh);
-    double rr = sum_partials(part + MAXB, nb, sh);
-    double bb = sum_partials(part + 2 * MAXB, nb, sh);
+    double rr = block_reduce_partials(part + P_RR * MAXB, nb, sh);
+    double bb = block_reduce_partials(part + P_BB * MAXB, nb, sh);
     if (threadIdx.x == 0) {
-        scal[NS_RZ] = rz;
         scal[NS_RR] = rr;
         scal[NS_BB] = bb;
         scal[NS_TOL2] = tol2;
@@ -238,91 +257,87 @@ __global__ __launch_bounds__(NT) void k_cg_init_final(const double* __restrict__
     }
 }
 
-__global__ __launch_bounds__(NT) void k_cg_spmv(int32_t nf, const int32_t* __restrict__ col,
-                                                const double* __restrict__ val,
-                                                const double* __restrict__ p,
-                                                double* __restrict__ q, double* __restrict__ part,
-                                                const int* __restrict__ iflags)
+__global__ __launch_bounds__(NT) void k_cg_dir(int32_t nf, int32_t it, int32_t nb,
+                                               const int32_t* __restrict__ col,
+                                               const double* __restrict__ val,
+                                               const double* __restrict__ z,
+                                               double* __restrict__ p, double* __restrict__ q,
+                                               double* __restrict__ part, double* scal,
+                                               int* iflags)
 {
     if (iflags[0]) return;
     __shared__ double sh[NT / 64];
+    double beta = 0.0;
+    if (it > 0) {
+        const double rr = block_reduce_partials(part + P_RR * MAXB, nb, sh);
+        const double bb = scal[NS_BB], tol2 = scal[NS_TOL2];
+        if (rr <= tol2 * bb) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                iflags[0] = 1;
+                scal[NS_RR] = rr;
+            }
+            return;
+        }
+        const double rz_new = block_reduce_partials(part + ((it & 1) ? P_RZ1 : P_RZ0) * MAXB, nb, sh);
+        const double rz_old = block_reduce_partials(part + ((it & 1) ? P_RZ0 : P_RZ1) * MAXB, nb, sh);
+        beta = rz_new / rz_old;
+        if (blockIdx.x == 0 && threadIdx.x == 0) scal[NS_RR] = rr;
+    }
     double s = 0.0;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
-        double qi = ell_row(i, nf, col, val, p);
+        const double pi = fma(beta, p[i], z[i]);
+        const double qi = fma(beta, q[i], ell_row(i, nf, col, val, z));
+        p[i] = pi;
         q[i] = qi;
-        s = fma(p[i], qi, s);
+        s = fma(pi, qi, s);
     }
-    double t = phf_block_sum_f64<NT>(s, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
+    const double t = phf_block_sum_f64<NT>(s, sh);
+    if (threadIdx.x == 0) part[P_PQ * MAXB + blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(NT) void k_cg_alpha(const double* __restrict__ part, int32_t nb,
-                                                 double* scal, const int* __restrict__ iflags)
+__global__ __launch_bounds__(NT) void k_cg_upd(int32_t nf, int32_t it, int32_t nb,
+                                               double* __restrict__ w, double* __restrict__ r,
+                                               double* __restrict__ z,
+                                               const double* __restrict__ p,
+                                               const double* __restrict__ q,
+                                               const double* __restrict__ dinv,
+                                               double* __restrict__ part, int* iflags)
 {
     if (iflags[0]) return;
     __shared__ double sh[NT / 64];
-    double pq = sum_partials(part, nb, sh);
-    if (threadIdx.x == 0) {
-        scal[NS_PQ] = pq;
-        scal[NS_ALPHA] = scal[NS_RZ] / pq;
-    }
-}
-
-__global__ __launch_bounds__(NT) void k_cg_update(int32_t nf, double* __restrict__ w,
-                                                  double* __restrict__ r, double* __restrict__ z,
-                                                  const double* __restrict__ p,
-                                                  const double* __restrict__ q,
-                                                  const double* __restrict__ dinv,
-                                                  const double* __restrict__ scal,
-                                                  double* __restrict__ part,
-                                                  const int* __restrict__ iflags)
-{
-    if (iflags[0]) return;
-    __shared__ double sh[NT / 64];
-    const double alpha = scal[NS_ALPHA];
+    const double rz = block_reduce_partials(part + ((it & 1) ? P_RZ1 : P_RZ0) * MAXB, nb, sh);
+    const double pq = block_reduce_partials(part + P_PQ * MAXB, nb, sh);
+    const double alpha = rz / pq;
     double s_rz = 0.0, s_rr = 0.0;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
         w[i] = fma(alpha, p[i], w[i]);
-        double ri = fma(-alpha, q[i], r[i]);
-        double zi = dinv[i] * ri;
+        const double ri = fma(-alpha, q[i], r[i]);
+        const double zi = dinv[i] * ri;
         r[i] = ri;
         z[i] = zi;
         s_rz = fma(ri, zi, s_rz);
         s_rr = fma(ri, ri, s_rr);
     }
-    double t0 = phf_block_sum_f64<NT>(s_rz, sh);
-    double t1 = phf_block_sum_f64<NT>(s_rr, sh);
+    const double t0 = phf_block_sum_f64<NT>(s_rz, sh);
+    const double t1 = phf_block_sum_f64<NT>(s_rr, sh);
     if (threadIdx.x == 0) {
-        part[blockIdx.x] = t0;
-        part[MAXB + blockIdx.x] = t1;
+        part[((it & 1) ? P_RZ0 : P_RZ1) * MAXB + blockIdx.x] = t0;
+        part[P_RR * MAXB + blockIdx.x] = t1;
+        if (blockIdx.x == 0) iflags[1] += 1;
     }
 }
 
-__global__ __launch_bounds__(NT) void k_cg_beta(const double* __restrict__ part, int32_t nb,
-                                                double* scal, int* iflags)
+// Convergence test after the last iteration of a chain.
+__global__ __launch_bounds__(NT) void k_cg_check(int32_t nb, const double* __restrict__ part,
+                                                 double* scal, int* iflags)
 {
     if (iflags[0]) return;
     __shared__ double sh[NT / 64];
-    double rz = sum_partials(part, nb, sh);
-    double rr = sum_partials(part + MAXB, nb, sh);
+    const double rr = block_reduce_partials(part + P_RR * MAXB, nb, sh);
     if (threadIdx.x == 0) {
-        scal[NS_BETA] = rz / scal[NS_RZ];
-        scal[NS_RZ] = rz;
         scal[NS_RR] = rr;
-        iflags[1] += 1;
         if (rr <= scal[NS_TOL2] * scal[NS_BB]) iflags[0] = 1;
     }
-}
-
-__global__ __launch_bounds__(NT) void k_cg_p(int32_t nf, double* __restrict__ p,
-                                             const double* __restrict__ z,
-                                             const double* __restrict__ scal,
-                                             const int* __restrict__ iflags)
-{
-    if (iflags[0]) return;
-    const double beta = scal[NS_BETA];
-    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT)
-        p[i] = fma(beta, p[i], z[i]);
 }
 
 // ---- recovery -------------------------------------------------------------
@@ -423,7 +438,7 @@ int phf_ns_create(phf_mesh* mesh, phf_ns** out)
     rc = rc ? rc : phf_dmalloc(ctx, &ns->z, nf, "solver z");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->p, nf, "solver p");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->q, nf, "solver q");
-    rc = rc ? rc : phf_dmalloc(ctx, &ns->part, 3 * MAXB, "solver partials");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->part, P_NARR * MAXB, "solver partials");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->scal, NS_NSCAL, "solver scalars");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->iflags, 4, "solver flags");
     if (rc) {
@@ -488,12 +503,13 @@ int phf_ns_zero_w(phf_ns* ns)
 int phf_ns_cg_start(phf_ns* ns, double rtol)
 {
     phf_ctx* ctx = ns->mesh->ctx;
+    ns->next_it = 0;
     if (ns->nf == 0) {
         PHF_HIP(ctx, hipMemsetAsync(ns->iflags, 0, 4 * sizeof(int), ctx->stream));
         return PHF_OK;
     }
     PHF_LAUNCH(ctx, "k_cg_init", k_cg_init, ns->nbv, NT, 0, ns->nf, ns->ell_col, ns->ell_val,
-               ns->dinv, ns->b, ns->w, ns->r, ns->z, ns->p, ns->part);
+               ns->dinv, ns->b, ns->w, ns->r, ns->z, ns->p, ns->q, ns->part);
     PHF_LAUNCH(ctx, "k_cg_init_final", k_cg_init_final, 1, NT, 0, ns->part, ns->nbv, rtol * rtol,
                ns->scal, ns->iflags);
     return PHF_OK;
@@ -503,18 +519,16 @@ int phf_ns_cg_iterate(phf_ns* ns, int32_t iters)
 {
     phf_ctx* ctx = ns->mesh->ctx;
     if (ns->nf == 0) return PHF_OK;
-    for (int32_t it = 0; it < iters; ++it) {
-        PHF_LAUNCH(ctx, "k_cg_spmv", k_cg_spmv, ns->nbv, NT, 0, ns->nf, ns->ell_col, ns->ell_val,
-                   ns->p, ns->q, ns->part, ns->iflags);
-        PHF_LAUNCH(ctx, "k_cg_alpha", k_cg_alpha, 1, NT, 0, ns->part, ns->nbv, ns->scal,
-                   ns->iflags);
-        PHF_LAUNCH(ctx, "k_cg_update", k_cg_update, ns->nbv, NT, 0, ns->nf, ns->w, ns->r, ns->z,
-                   ns->p, ns->q, ns->dinv, ns->scal, ns->part, ns->iflags);
-        PHF_LAUNCH(ctx, "k_cg_beta", k_cg_beta, 1, NT, 0, ns->part, ns->nbv, ns->scal,
-                   ns->iflags);
-        PHF_LAUNCH(ctx, "k_cg_p", k_cg_p, ns->nbv, NT, 0, ns->nf, ns->p, ns->z, ns->scal,
-                   ns->iflags);
+    for (int32_t k = 0; k < iters; ++k) {
+        // only the parity and "first or not" of the index matter to the kernels
+        const int32_t it = ns->next_it;
+        ns->next_it = it + 1 >= 2 ? 2 + ((it + 1) & 1) : it + 1;
+        PHF_LAUNCH(ctx, "k_cg_dir", k_cg_dir, ns->nbv, NT, 0, ns->nf, it, ns->nbv, ns->ell_col,
+                   ns->ell_val, ns->z, ns->p, ns->q, ns->part, ns->scal, ns->iflags);
+        PHF_LAUNCH(ctx, "k_cg_upd", k_cg_upd, ns->nbv, NT, 0, ns->nf, it, ns->nbv, ns->w, ns->r,
+                   ns->z, ns->p, ns->q, ns->dinv, ns->part, ns->iflags);
     }
+    PHF_LAUNCH(ctx, "k_cg_check", k_cg_check, 1, NT, 0, ns->nbv, ns->part, ns->scal, ns->iflags);
     return PHF_OK;
 }
 
