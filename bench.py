@@ -66,25 +66,29 @@ def algorithmic_bytes(info, has_aT=True):
     }
 
 
-def csrc_hash():
+def sources_hash(files):
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2401_15557_amd", "csrc")
-    for n in sorted(os.listdir(d)):
-        if n.endswith((".hip", ".h")):
-            h.update(open(os.path.join(d, n), "rb").read())
+    for n in files:
+        h.update(open(os.path.join(d, n), "rb").read())
     return h.hexdigest()[:16]
 
 
 def traffic_for(kernel):
     """HBM traffic per launch from the committed counter summary, if it was
-    taken on the current kernel sources; otherwise None."""
+    taken on the current sources of that kernel; otherwise None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(p))
     except (OSError, ValueError):
         return None
     k = rec.get("kernels", {}).get(kernel)
-    if not k or k.get("csrc_hash") != csrc_hash():
+    if not k:
+        return None
+    try:
+        if k.get("hash") != sources_hash(k.get("sources", [])):
+            return None
+    except OSError:
         return None
     return k.get("bytes_per_launch")
 
@@ -119,6 +123,10 @@ def main():
     ap.add_argument("--no-cn", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--mode", choices=("full", "assembly"), default="full",
+                    help="assembly: only the numeric assembly on the benchmark mesh plus one "
+                         "plain device copy of --copy-mib MiB (for hardware-counter runs)")
+    ap.add_argument("--copy-mib", type=int, default=512)
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -148,6 +156,23 @@ def main():
                            phfem.make_fn(phfem.PHF_FN_CONST, 1.0))
     h = ctx.handle
     out = {}
+
+    if a.mode == "assembly":
+        mh = phfem.phf_mesh_create(h, xy_d, el_d, D_d, N_d, phfem.PHF_DEVICE)
+        info = phfem.phf_mesh_get_info(mh)
+        sysd, t = phfem.alloc_system_for(info, dev)
+        for _ in range(a.asm_reps):
+            phfem.phf_assemble(mh, co, data, sysd)
+        src = torch.ones(a.copy_mib << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        phfem.phf_mesh_destroy(mh)
+        ab = algorithmic_bytes(info)
+        print(json.dumps({"mode": "assembly", "nE": info.nE, "launches": a.asm_reps,
+                          "algorithmic_bytes_per_launch": ab["k_assemble"],
+                          "copy_bytes_each_way": src.numel() * 8}))
+        return
 
     def one_step(rows):
         t0 = time.perf_counter()

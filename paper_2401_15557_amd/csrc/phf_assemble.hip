@@ -5,11 +5,16 @@
 // K, M, D is the identity map (element m owns values 9m..9m+8), and C rows
 // are written in place at their precomputed row pointers.
 //
-// Memory layout: coordinates are double2 (16 B) records, elements int4
-// records (v0, v1, v2, code). An element tile of 256 triangles computes its
-// 9 K values per element into LDS and the whole tile then streams out as one
-// contiguous 18 KB block with 16-byte stores; M is regenerated from the
-// staged areas; F from a staged 3-value record.
+// Memory layout: element tiles read the element-major coordinate copy built
+// with the mesh (three double2 per triangle, streamed) and the element code
+// words, not the node array through vertex ids: with the paper's
+// red-refinement numbering consecutive triangles are far apart, and three
+// scattered 16-byte gathers per triangle cost more than streaming 48 bytes.
+// An element tile of 256 triangles computes its 9 K values per element into
+// LDS and the whole tile then streams out as one contiguous 18 KB block with
+// 16-byte stores; M is regenerated from the staged areas; F from a staged
+// 3-value record. Multiplier rows gather their two end nodes (rows are in
+// edge-id order, so the larger end node is monotone).
 #include "phf_device.h"
 #include "phf_internal.h"
 
@@ -19,13 +24,15 @@ constexpr int TILE = 256;
 
 struct AsmArgs {
     int32_t nE, L, nbE, nbR;
-    const int4* elem4;
+    const double2* exy;
+    const int32_t* ecode;
     const double2* xy;
     const double* aT;
     const int32_t* elem_edges;
     const int2* row_nodes;
     const int32_t* row_edge;
-    const int32_t* C_rowptr;
+    const int32_t* C_tile;
+    const uint64_t* neu_mask;
     double A00, A01, A10, A11, p0, p1;
     phf_fn_dev f, g, uD;
     double t;
@@ -39,30 +46,22 @@ struct AsmArgs {
     double* bD;
 };
 
-// Splits the fused grid between element tiles and row tiles so that each
-// XCD (block b runs on XCD b % 8) receives a contiguous range of element
-// tiles and a contiguous range of row tiles, interleaved in time.
+// Splits the fused grid between element tiles and row tiles in proportion,
+// so that both kinds run side by side over the whole launch: block b is an
+// element tile iff floor((b+1) nbE / T) > floor(b nbE / T), T = nbE + nbR.
+// (Dealing contiguous ranges to each XCD measured slower.)
 __device__ inline void fused_tile(int32_t b, int32_t nbE, int32_t nbR, bool* is_elem,
                                   int32_t* tile)
 {
-    const int32_t T = nbE + nbR, nx = 8;
-    int32_t per = T / nx, rem = T % nx;
-    int32_t x = b % nx, k = b / nx;
-    int32_t own = per + (x < rem ? 1 : 0);
-    int32_t C0 = x * per + (x < rem ? x : rem);
-    int32_t C1 = C0 + own;
-    int32_t E0 = (int32_t)(((int64_t)C0 * nbE) / T);
-    int32_t E1 = (int32_t)(((int64_t)C1 * nbE) / T);
-    int32_t R0 = C0 - E0;
-    int32_t ex = E1 - E0;
-    int32_t ei0 = (int32_t)(((int64_t)k * ex) / own);
-    int32_t ei1 = (int32_t)(((int64_t)(k + 1) * ex) / own);
-    if (ei1 > ei0) {
+    const int32_t T = nbE + nbR;
+    const int32_t e0 = (int32_t)(((int64_t)b * nbE) / T);
+    const int32_t e1 = (int32_t)(((int64_t)(b + 1) * nbE) / T);
+    if (e1 > e0) {
         *is_elem = true;
-        *tile = E0 + ei0;
+        *tile = e0;
     } else {
         *is_elem = false;
-        *tile = R0 + (k - ei0);
+        *tile = b - e0;
     }
 }
 
@@ -75,8 +74,8 @@ __device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK,
     const int32_t nt = min(TILE, a.nE - m0);
     if (tid < nt) {
         const int32_t m = m0 + tid;
-        const int4 e = a.elem4[m];
-        const double2 P0 = a.xy[e.x], P1 = a.xy[e.y], P2 = a.xy[e.z];
+        const double2 P0 = a.exy[3 * (int64_t)m], P1 = a.exy[3 * (int64_t)m + 1];
+        const double2 P2 = a.exy[3 * (int64_t)m + 2];
         // g_i = 2|T| grad lambda_i (the edge opposite vertex i turned by 90 deg)
         const double g0x = P1.y - P2.y, g0y = P2.x - P1.x;
         const double g1x = P2.y - P0.y, g1y = P0.x - P2.x;
@@ -147,9 +146,10 @@ __device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK,
             b1 = c * (f0 + f2);
             b2 = c * (f0 + f1);
         }
-        // Neumann load: |E| g(m_E) / 2 on the two vertices of each Neumann edge
-        const int code = e.w;
-        if (code & 0x2A) {
+        // Neumann load: |E| g(m_E) / 2 on the two vertices of each Neumann
+        // edge, for the (boundary) elements flagged in the mask
+        if ((a.neu_mask[m >> 6] >> (m & 63)) & 1) {
+            const int code = a.ecode[m];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 if (PHF_CODE_TYPE(code, i) != 2) continue;
@@ -157,7 +157,9 @@ __device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK,
                 const double2 Pb = i == 0 ? P2 : (i == 1 ? P0 : P1);
                 const double dx = Pb.x - Pa.x, dy = Pb.y - Pa.y;
                 const double len = sqrt(dx * dx + dy * dy);
-                int32_t eid = a.g.kind == PHF_FN_EDGE_ARRAY ? a.elem_edges[3 * (int64_t)m + i] : -1;
+                const int32_t eid =
+                    a.g.kind == PHF_FN_EDGE_ARRAY ? a.elem_edges[3 * (int64_t)m + i] : -1;
+                // outward normal of the counter-clockwise edge Pa -> Pb
                 const double gv = phf_fn_eval(a.g, 0.5 * (Pa.x + Pb.x), 0.5 * (Pa.y + Pb.y), a.t,
                                               dy / len, -dx / len, eid);
                 const double w = len * gv * 0.5;
@@ -206,27 +208,38 @@ __device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK,
     }
 }
 
+// A row tile: 256 consecutive multiplier rows. Their C values are one
+// contiguous run starting at the tile's base pointer; each row's offset in it
+// is an exclusive scan of the row lengths (4 interior, 2 Dirichlet), the
+// Dirichlet rows being flagged by a negative first end node.
 template <bool MATS>
-__device__ inline void row_tile(const AsmArgs& a, int32_t tile)
+__device__ inline void row_tile(const AsmArgs& a, int32_t tile, int32_t* shs)
 {
     const int32_t r = tile * TILE + threadIdx.x;
+    int2 kl = make_int2(0, 0);
+    int32_t len = 0;
+    if (r < a.L) {
+        kl = a.row_nodes[r];
+        len = kl.x < 0 ? 2 : 4;
+    }
+    int32_t tot;
+    const int32_t off = phf_block_exscan_i32<TILE>(len, shs, &tot);
     if (r >= a.L) return;
-    const int2 kl = a.row_nodes[r];
-    const int32_t c0 = a.C_rowptr[r], c1 = a.C_rowptr[r + 1];
-    const double2 Pk = a.xy[kl.x], Pl = a.xy[kl.y];
+    const bool dirichlet = kl.x < 0;
+    const int32_t c0 = a.C_tile[tile] + off;
+    const double2 Pk = a.xy[dirichlet ? ~kl.x : kl.x], Pl = a.xy[kl.y];
     const double dx = Pl.x - Pk.x, dy = Pl.y - Pk.y;
-    const double len = sqrt(dx * dx + dy * dy);
-    const double h = 0.5 * len;
-    const bool interior = (c1 - c0) == 4;
+    const double len_e = sqrt(dx * dx + dy * dy);
+    const double h = 0.5 * len_e;
     if (MATS) {
         double2* C2 = reinterpret_cast<double2*>(a.C + c0);
         C2[0] = make_double2(h, h);
-        if (interior) C2[1] = make_double2(-h, -h);
+        if (!dirichlet) C2[1] = make_double2(-h, -h);
     }
     double v = 0.0;
-    if (!interior && a.uD.kind != PHF_FN_ZERO) {
+    if (dirichlet && a.uD.kind != PHF_FN_ZERO) {
         int32_t eid = a.uD.kind == PHF_FN_EDGE_ARRAY ? a.row_edge[r] : -1;
-        v = -len * phf_fn_eval(a.uD, 0.5 * (Pk.x + Pl.x), 0.5 * (Pk.y + Pl.y), a.t, 0, 0, eid);
+        v = -len_e * phf_fn_eval(a.uD, 0.5 * (Pk.x + Pl.x), 0.5 * (Pk.y + Pl.y), a.t, 0, 0, eid);
     }
     a.bD[r] = v;
 }
@@ -239,17 +252,19 @@ __global__ __launch_bounds__(TILE) void k_assemble(AsmArgs a)
     __shared__ __align__(16) double shD[WITH_D ? TILE * 9 : 2];
     __shared__ double shA[MATS ? TILE : 1];
     __shared__ __align__(16) double shF[TILE * 3];
+    __shared__ int32_t shs[TILE / 64 + 1];
     bool is_elem;
     int32_t tile;
     fused_tile(blockIdx.x, a.nbE, a.nbR, &is_elem, &tile);
     if (is_elem) element_tile<HAS_AT, MATS, WITH_D, GEN_A>(a, tile, shK, shD, shA, shF);
-    else row_tile<MATS>(a, tile);
+    else row_tile<MATS>(a, tile, shs);
 }
 
 // ---- saddle-matrix values -------------------------------------------------
 struct SaddleArgs {
     int32_t nE, L, nbE, nbR;
-    const int4* elem4;
+    const double2* exy;
+    const int32_t* ecode;
     const double2* xy;
     const double* aT;
     const int32_t* S_rowptr;
@@ -268,8 +283,8 @@ __global__ __launch_bounds__(TILE) void k_saddle_values(SaddleArgs a)
     if (is_elem) {
         const int32_t m = tile * TILE + threadIdx.x;
         if (m >= a.nE) return;
-        const int4 e = a.elem4[m];
-        const double2 P[3] = {a.xy[e.x], a.xy[e.y], a.xy[e.z]};
+        const double2 P[3] = {a.exy[3 * (int64_t)m], a.exy[3 * (int64_t)m + 1],
+                              a.exy[3 * (int64_t)m + 2]};
         double gx[3], gy[3];
         for (int i = 0; i < 3; ++i) {
             const double2 Pa = P[(i + 1) % 3], Pb = P[(i + 2) % 3];
@@ -286,7 +301,7 @@ __global__ __launch_bounds__(TILE) void k_saddle_values(SaddleArgs a)
             const double dx = Pb.x - Pa.x, dy = Pb.y - Pa.y;
             len[i] = sqrt(dx * dx + dy * dy);
         }
-        const int code = e.w;
+        const int code = a.ecode[m];
         for (int j = 0; j < 3; ++j) {
             int32_t q = a.S_rowptr[3 * (int64_t)m + j];
             const double ajx = a.A00 * gx[j] + a.A01 * gy[j], ajy = a.A10 * gx[j] + a.A11 * gy[j];
@@ -313,7 +328,7 @@ __global__ __launch_bounds__(TILE) void k_saddle_values(SaddleArgs a)
         if (r >= a.L) return;
         const int2 kl = a.row_nodes[r];
         const int32_t c0 = a.C_rowptr[r], c1 = a.C_rowptr[r + 1];
-        const double2 Pk = a.xy[kl.x], Pl = a.xy[kl.y];
+        const double2 Pk = a.xy[kl.x < 0 ? ~kl.x : kl.x], Pl = a.xy[kl.y];
         const double dx = Pl.x - Pk.x, dy = Pl.y - Pk.y;
         const double h = 0.5 * sqrt(dx * dx + dy * dy);
         const int32_t q = a.S_rowptr[N + r];
@@ -361,13 +376,15 @@ int phf_assemble_impl(phf_mesh* mesh, const phf_coeffs* co, const phf_data* data
     a.L = mesh->L;
     a.nbE = (mesh->nE + TILE - 1) / TILE;
     a.nbR = (mesh->L + TILE - 1) / TILE;
-    a.elem4 = mesh->elem4;
+    a.exy = mesh->exy;
+    a.ecode = mesh->ecode;
     a.xy = mesh->xy;
     a.aT = co->a_T;
     a.elem_edges = mesh->elem_edges;
     a.row_nodes = mesh->row_nodes;
     a.row_edge = mesh->row_edge;
-    a.C_rowptr = mesh->C_rowptr;
+    a.C_tile = mesh->C_tile;
+    a.neu_mask = mesh->neu_mask;
     a.A00 = co->A[0];
     a.A01 = co->A[1];
     a.A10 = co->A[2];
@@ -408,7 +425,8 @@ int phf_assemble_impl(phf_mesh* mesh, const phf_coeffs* co, const phf_data* data
         s.L = mesh->L;
         s.nbE = a.nbE;
         s.nbR = a.nbR;
-        s.elem4 = mesh->elem4;
+        s.exy = mesh->exy;
+        s.ecode = mesh->ecode;
         s.xy = mesh->xy;
         s.aT = co->a_T;
         s.S_rowptr = mesh->S_rowptr;

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(NT) void k_cn_keep(int32_t nf, int32_t* __restrict_
 
 // r1 per element (see file comment).
 __global__ __launch_bounds__(NT) void k_cn_rhs_elem(
-    int32_t nE, const int4* __restrict__ elem4, const double* __restrict__ K,
+    int32_t nE, const int32_t* __restrict__ ecode, const double* __restrict__ K,
     const double* __restrict__ M, const double* __restrict__ U, const double* __restrict__ Lam,
     const int32_t* __restrict__ elem_row, const double* __restrict__ row_h,
     const double* __restrict__ F0, const double* __restrict__ F1, double cM, double cK,
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(NT) void k_cn_rhs_elem(
 {
     int32_t m = blockIdx.x * NT + threadIdx.x;
     if (m >= nE) return;
-    const int code = elem4[m].w;
+    const int code = ecode[m];
     double u[3], lt[3];
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
@@ -165,7 +165,7 @@ int cn_step_head(phf_cn* cn, const phf_data* data)
     PHF_LAUNCH(ctx, "k_cn_inc", k_cn_inc, 1, 1, 0, cn->d_step);
     TRY(cn_loads(cn, data, cn->F1, cn->bD1, true));
     const double cM = 1.0 - 0.5 * cn->k * cn->delta, cK = 0.5 * cn->k, hk = 0.5 * cn->k;
-    PHF_LAUNCH(ctx, "k_cn_rhs_elem", k_cn_rhs_elem, nblk(nE), NT, 0, nE, mesh->elem4, cn->K, cn->M,
+    PHF_LAUNCH(ctx, "k_cn_rhs_elem", k_cn_rhs_elem, nblk(nE), NT, 0, nE, mesh->ecode, cn->K, cn->M,
                cn->U, cn->Lam, cn->ns->elem_row, cn->ns->row_h, cn->F0, cn->F1, cM, cK, hk, cn->r1);
     if (L > 0)
         PHF_LAUNCH(ctx, "k_cn_rhs_row", k_cn_rhs_row, nblk(L), NT, 0, L, mesh->C_rowptr,

@@ -120,19 +120,3 @@ __device__ inline double phf_fn_eval(const phf_fn_dev& f, double x, double y, do
     default: return 0.0;
     }
 }
-
-// Maps a linear block index so that consecutive tiles stay on one XCD: the
-// hardware deals workgroups round-robin over the 8 XCDs of an MI355X, so
-// block b runs on XCD b % 8; giving XCD x the contiguous tile range
-// [x * per, (x + 1) * per) keeps neighbouring tiles (which share vertices)
-// in the same L2.
-__device__ inline int32_t phf_xcd_tile(int32_t b, int32_t nblocks)
-{
-    const int32_t nx = 8;
-    int32_t per = nblocks / nx, rem = nblocks % nx;
-    int32_t x = b % nx, k = b / nx;
-    // XCDs x < rem own per + 1 tiles, the others per
-    int32_t start = x * per + (x < rem ? x : rem);
-    int32_t own = per + (x < rem ? 1 : 0);
-    return k < own ? start + k : b;  // (k < own always holds)
-}

@@ -106,6 +106,8 @@ struct phf_mesh {
     // geometry and elements
     double2* xy = nullptr;         // nC
     int4* elem4 = nullptr;         // nE: v0, v1, v2, code
+    double2* exy = nullptr;        // 3 nE: vertex coordinates of each element, element-major
+    int32_t* ecode = nullptr;      // nE: the code word alone
     // edge tables
     int2* edge_nodes = nullptr;    // n_edges: (k, l) as traversed by T+
     int2* edge_elems = nullptr;    // n_edges: (T+, T-)
@@ -118,7 +120,11 @@ struct phf_mesh {
     int32_t* neu_edges = nullptr;  // nN
     // multiplier rows
     int32_t* row_edge = nullptr;   // L
-    int2* row_nodes = nullptr;     // L: (k, l) of the row's edge
+    int2* row_nodes = nullptr;     // L: (k, l) of the row's edge; k stored as ~k
+                                   // (negative) on Dirichlet rows
+    int32_t* C_tile = nullptr;     // L/256 + 1: C row pointer of every 256th row
+    uint64_t* neu_mask = nullptr;  // nE/64: bit m%64 of word m/64 set iff element m
+                                   // has a Neumann edge
     int32_t* C_rowptr = nullptr;   // L + 1
     int32_t* C_col = nullptr;      // nnz_C
     int32_t* S_rowptr = nullptr;   // N + L + 1

@@ -245,7 +245,8 @@ __global__ __launch_bounds__(256) void k_rows(
     int32_t r = rowscan[e];
     edge_row[e] = r;
     row_edge[r] = e;
-    row_nodes[r] = edge_nodes[e];
+    const int2 kl = edge_nodes[e];
+    row_nodes[r] = make_int2(t == 1 ? ~kl.x : kl.x, kl.y);
     int32_t c = cptr[e];
     C_rowptr[r] = c;
     int2 tt = edge_elems[e];
@@ -262,11 +263,15 @@ __global__ __launch_bounds__(256) void k_rows(
     }
 }
 
-// Element code words and the saddle row lengths of the element's DOF rows.
+// Element code words, the element-major coordinate copy and the saddle row
+// lengths of the element's DOF rows.
 __global__ __launch_bounds__(256) void k_elem_codes(int32_t nE, int4* __restrict__ elem4,
                                                     const int32_t* __restrict__ elem_edges,
                                                     const int8_t* __restrict__ etype,
                                                     const int2* __restrict__ edge_elems,
+                                                    const double2* __restrict__ xy,
+                                                    double2* __restrict__ exy,
+                                                    int32_t* __restrict__ ecode,
                                                     int32_t* __restrict__ slen)
 {
     int32_t m = blockIdx.x * 256 + threadIdx.x;
@@ -287,7 +292,13 @@ __global__ __launch_bounds__(256) void k_elem_codes(int32_t nE, int4* __restrict
         if (ed[l1] > ed[l2]) code |= 1 << (9 + i);
         slen[3 * (int64_t)m + i] = 3 + (tp[l1] != 2) + (tp[l2] != 2);
     }
-    elem4[m].w = code;
+    int4 e = elem4[m];
+    e.w = code;
+    elem4[m] = e;
+    ecode[m] = code;
+    exy[3 * (int64_t)m] = xy[e.x];
+    exy[3 * (int64_t)m + 1] = xy[e.y];
+    exy[3 * (int64_t)m + 2] = xy[e.z];
 }
 
 __global__ __launch_bounds__(256) void k_saddle_rowlen(int32_t L, const int32_t* __restrict__ C_rowptr,
@@ -405,6 +416,26 @@ __global__ __launch_bounds__(256) void k_reduced_pattern(
 
 __global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
 
+__global__ __launch_bounds__(256) void k_c_tiles(int32_t L, const int32_t* __restrict__ C_rowptr,
+                                                 int32_t* __restrict__ C_tile)
+{
+    int32_t t = blockIdx.x * 256 + threadIdx.x;
+    int32_t nt = (L + 255) / 256;
+    if (t > nt) return;
+    C_tile[t] = C_rowptr[min(256 * t, L)];
+}
+
+// One bit per element: does it own a Neumann edge? Each wavefront packs the
+// bits of 64 consecutive elements with a ballot.
+__global__ __launch_bounds__(256) void k_neu_mask(int32_t nE, const int32_t* __restrict__ ecode,
+                                                  uint64_t* __restrict__ mask)
+{
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool f = m < nE && (ecode[m] & 0x2A) != 0;
+    const uint64_t b = __ballot(f);
+    if ((threadIdx.x & 63) == 0 && m < nE) mask[m >> 6] = b;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -415,6 +446,8 @@ static void mesh_free(phf_mesh* m)
     m->ns = nullptr;
     phf_dfree(m->xy);
     phf_dfree(m->elem4);
+    phf_dfree(m->exy);
+    phf_dfree(m->ecode);
     phf_dfree(m->edge_nodes);
     phf_dfree(m->edge_elems);
     phf_dfree(m->elem_edges);
@@ -426,6 +459,8 @@ static void mesh_free(phf_mesh* m)
     phf_dfree(m->neu_edges);
     phf_dfree(m->row_edge);
     phf_dfree(m->row_nodes);
+    phf_dfree(m->C_tile);
+    phf_dfree(m->neu_mask);
     phf_dfree(m->C_rowptr);
     phf_dfree(m->C_col);
     phf_dfree(m->S_rowptr);
@@ -636,8 +671,10 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
 
     // element codes and the saddle pattern
     TRY(phf_dmalloc(ctx, &T.slen, (size_t)N + L + 1, "saddle row lengths"));
+    TRY(phf_dmalloc(ctx, &M->exy, 3 * (size_t)nE, "element coordinates"));
+    TRY(phf_dmalloc(ctx, &M->ecode, nE, "element codes"));
     PHF_LAUNCH(ctx, "k_elem_codes", k_elem_codes, nblk(nE), 256, 0, nE, M->elem4, M->elem_edges,
-               M->edge_type, M->edge_elems, T.slen);
+               M->edge_type, M->edge_elems, M->xy, M->exy, M->ecode, T.slen);
     if (L > 0)
         PHF_LAUNCH(ctx, "k_saddle_rowlen", k_saddle_rowlen, nblk(L), 256, 0, L, M->C_rowptr,
                    (int32_t)M->nnz_C, T.slen + N);
@@ -648,6 +685,13 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     PHF_LAUNCH(ctx, "k_saddle_cols", k_saddle_cols, nblk((int64_t)N + L), 256, 0, nE, L, M->elem4,
                M->elem_edges, M->edge_row, M->C_rowptr, M->C_col, M->S_rowptr, M->S_col);
     phf_dfree(T.slen);
+
+    // tile bases of the C row pointers and the Neumann element mask
+    TRY(phf_dmalloc(ctx, &M->C_tile, (size_t)(L + 255) / 256 + 1, "C tile bases"));
+    PHF_LAUNCH(ctx, "k_c_tiles", k_c_tiles, nblk((L + 255) / 256 + 1), 256, 0, L, M->C_rowptr,
+               M->C_tile);
+    TRY(phf_dmalloc(ctx, &M->neu_mask, ((size_t)nE + 63) / 64, "Neumann element mask"));
+    PHF_LAUNCH(ctx, "k_neu_mask", k_neu_mask, nblk(nE), 256, 0, nE, M->ecode, M->neu_mask);
 
     // reduced operator pattern
     const int32_t nf = M->n_free;
@@ -670,7 +714,7 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
                    (int32_t*)nullptr, M->R_rowptr, M->R_col, M->R_src);
     }
     PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    M->bytes = (int64_t)nC * 16 + (int64_t)nE * 16 + (int64_t)ne * (8 + 8 + 1 + 1 + 1 + 4 + 4) +
+    M->bytes = (int64_t)nC * 16 + (int64_t)nE * (16 + 48 + 4) + (int64_t)ne * (8 + 8 + 1 + 1 + 1 + 4 + 4) +
                (int64_t)nE * 12 + (int64_t)(nD + nN) * 4 + (int64_t)L * (4 + 8 + 4) +
                M->nnz_C * 4 + ((int64_t)N + L + 1) * 4 + M->nnz_S * 4 + (int64_t)nf * 8 +
                M->nnz_R * 12;

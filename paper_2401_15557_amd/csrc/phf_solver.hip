@@ -117,7 +117,7 @@ __global__ __launch_bounds__(NT) void k_ns_rowh(int32_t L, const int32_t* __rest
 // Known midpoint values (Dirichlet) and T+-side jumps (interior rows with a
 // non-zero right-hand side), and the element part of the reduced rhs,
 // c_T = P^T (rhs1_T - A_T P kv_T).
-__global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int4* __restrict__ elem4,
+__global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int32_t* __restrict__ ecode,
                                                  const int32_t* __restrict__ elem_row,
                                                  const double* __restrict__ row_h,
                                                  const double* __restrict__ rhs1,
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int4* __restr
 {
     int32_t m = blockIdx.x * NT + threadIdx.x;
     if (m >= nE) return;
-    const int code = elem4[m].w;
+    const int code = ecode[m];
     double k3[3];
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
@@ -485,7 +485,7 @@ int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2)
 {
     phf_mesh* mesh = ns->mesh;
     phf_ctx* ctx = mesh->ctx;
-    PHF_LAUNCH(ctx, "k_ns_known", k_ns_known, nblk(ns->nE), NT, 0, ns->nE, mesh->elem4,
+    PHF_LAUNCH(ctx, "k_ns_known", k_ns_known, nblk(ns->nE), NT, 0, ns->nE, mesh->ecode,
                ns->elem_row, ns->row_h, rhs1, rhs2, ns->Ablk, ns->kv, ns->cs);
     if (ns->nf > 0)
         PHF_LAUNCH(ctx, "k_ns_gather", k_ns_gather, nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge,

@@ -427,8 +427,12 @@ class Mesh:
 
 def alloc_system(mesh: Mesh, with_D=False, with_S=False):
     """Device output tensors sized from the mesh info, and the phf_system."""
+    return alloc_system_for(mesh.info, mesh.ctx.device, with_D, with_S)
+
+
+def alloc_system_for(i, dev, with_D=False, with_S=False):
+    """As alloc_system, from a phf_mesh_info and a torch device."""
     import torch
-    i, dev = mesh.info, mesh.ctx.device
     t = dict(K=torch.empty(i.nnz_K, dtype=torch.float64, device=dev),
              M=torch.empty(i.nnz_K, dtype=torch.float64, device=dev),
              C=torch.empty(max(i.nnz_C, 1), dtype=torch.float64, device=dev),
