@@ -9,12 +9,16 @@ Workload (the elliptic benchmark configuration): L-shaped domain
 the rest, f = 2 pi^2 sin(pi x) cos(pi y). Inputs are synthetic and resident
 in device memory before timing starts.
 
-One step = one pass of the elliptic hot path on that mesh: upload of the
-device-resident mesh arrays + validation, edge topology, boundary
-classification and CSR patterns (phf_mesh_create), numeric assembly of K, M,
-C, F, b_D (phf_assemble), and the saddle-point solve to a relative residual
-of 1e-10 (phf_solve), then the mesh is released. `value` is elements per
-second through that step (Melem/s).
+One step = one pass of the elliptic hot path: the 12-triangle L-shape
+(device-resident) is validated and given its edge tables (phf_mesh_create),
+red-refined 9 times on the device, each level getting its edge tables,
+boundary classification and CSR patterns (phf_mesh_refine); the numeric
+assembly of K, M, C, F, b_D runs on the finest mesh (phf_assemble), and the
+saddle-point system is solved to a relative residual of 1e-10 by
+conjugate gradients preconditioned with a V-cycle over the refinement levels
+(phf_solve); then the meshes are released. `value` is finest-mesh elements
+per second through that step (Melem/s). `--precond jacobi` solves with the
+Jacobi preconditioner instead.
 
 The JSON line also carries, measured in the same process:
   rows      per-stage milliseconds of the step and solver iterations;
@@ -45,19 +49,39 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "assembled Melem/s + HBM GB/s (4M tris); CN steps/s; served p50/p99 latency"
 
 
-def algorithmic_bytes(info, has_aT=True):
+def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None):
     """Bytes a kernel must move at least, per launch, by kernel name.
 
     k_assemble: read coordinates once (16 B/node), element vertices
     (12 B/elem), a_T (8 B/elem), the two end nodes of each multiplier row
     (8 B/row); write K and M (72 B/elem each), F (24 B/elem), C (8 B/nnz)
     and b_D (8 B/row).
+    V-cycle kernels on level l with n unknowns (level_nf[l]), operator rows of
+    five (column, value) slots = 60 B/row: smoothing sweep 60 + 8 (dinv) + 8
+    (b) + 8 (x) + 8 (y) = 92 B/row, first sweep from zero 24 B/row, residual
+    84 B/row, prolongation 60 (P) + 16 (x in/out) B/fine row + 8 B/coarse row,
+    finish (z = x, r.z) 24 B/row; restriction from level l: per coarse
+    triangle 36 B of fine row ids, 4 B code word, 24 B of sums written, plus
+    the fine residual once (8 B/fine row), then 32 B per coarse row to sum
+    the two sides.
     """
     nE, nC, L = info.nE, info.nC, info.L
     nf, nnzR = info.n_free, info.nnz_reduced
     asm = (16 * nC + 12 * nE + (8 * nE if has_aT else 0) + 8 * L +
            8 * (9 * nE) * 2 + 8 * 3 * nE + 8 * info.nnz_C + 8 * L)
+    mg = {}
+    for l, n in enumerate(level_nf or []):
+        mg[f"k_mg_smooth.L{l}"] = 92 * n
+        mg[f"k_mg_smooth0.L{l}"] = 24 * n
+        mg[f"k_mg_resid.L{l}"] = 84 * n
+        if l > 0:
+            mg[f"k_mg_prolong.L{l}"] = 76 * n + 8 * level_nf[l - 1]
+            if level_nE:
+                mg[f"k_mg_restrict.L{l}"] = 64 * level_nE[l - 1] + 8 * n
+            mg[f"k_mg_collect.L{l}"] = 32 * level_nf[l - 1]
+        mg[f"k_mg_finish.L{l}"] = 24 * n
     return {
+        **mg,
         "k_assemble": asm,
         # reduced operator values + columns (12 B/nnz), z in; p, q in and out
         "k_cg_dir": 12 * nnzR + 40 * nf,
@@ -118,7 +142,7 @@ def main():
     ap.add_argument("--asm-reps", type=int, default=30)
     ap.add_argument("--cn-level", type=int, default=9)
     ap.add_argument("--cn-steps", type=int, default=200)
-    ap.add_argument("--cn-chunk", type=int, default=32,
+    ap.add_argument("--cn-chunk", type=int, default=8,
                     help="CG iterations per captured graph chunk")
     ap.add_argument("--no-cn", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -127,6 +151,7 @@ def main():
                     help="assembly: only the numeric assembly on the benchmark mesh plus one "
                          "plain device copy of --copy-mib MiB (for hardware-counter runs)")
     ap.add_argument("--copy-mib", type=int, default=512)
+    ap.add_argument("--precond", choices=("multigrid", "jacobi"), default="multigrid")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -143,12 +168,18 @@ def main():
     pi = np.pi
     print(f"[bench] building inputs (L-shape level {a.level})", file=sys.stderr, flush=True)
     m = G.lshape(a.level)
+    base = G.lshape(0)
     aT = G.per_triangle_coefficient(m.nE, 0)
     xy_d = torch.tensor(m.coords, device=dev)
     el_d = torch.tensor(m.elements, device=dev)
     D_d = torch.tensor(m.dirichlet, device=dev)
     N_d = torch.tensor(m.neumann, device=dev)
+    bxy_d = torch.tensor(base.coords, device=dev)
+    bel_d = torch.tensor(base.elements, device=dev)
+    bD_d = torch.tensor(base.dirichlet, device=dev)
+    bN_d = torch.tensor(base.neumann, device=dev)
     aT_d = torch.tensor(aT, device=dev)
+    pc = phfem.PHF_PRECOND_MULTIGRID if a.precond == "multigrid" else phfem.PHF_PRECOND_JACOBI
     ctx = phfem.Context(0)
     co = phfem.make_coeffs(a_T=aT_d)
     data = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * pi * pi, 0),
@@ -176,7 +207,10 @@ def main():
 
     def one_step(rows):
         t0 = time.perf_counter()
-        mh = phfem.phf_mesh_create(h, xy_d, el_d, D_d, N_d, phfem.PHF_DEVICE)
+        chain = [phfem.phf_mesh_create(h, bxy_d, bel_d, bD_d, bN_d, phfem.PHF_DEVICE)]
+        for _ in range(a.level):
+            chain.append(phfem.phf_mesh_refine(chain[-1]))
+        mh = chain[-1]
         t1 = time.perf_counter()
         info = phfem.phf_mesh_get_info(mh)
         if "sys" not in out:
@@ -191,14 +225,18 @@ def main():
             for k in ("K", "M", "C", "F", "bD"):
                 setattr(sysd, k, t[k].data_ptr())
             out["sys"], out["t"], out["info"] = sysd, t, info
+            out["level_nf"] = [phfem.phf_mesh_get_info(c).n_free for c in chain]
+            out["level_nE"] = [phfem.phf_mesh_get_info(c).nE for c in chain]
         sysd, t = out["sys"], out["t"]
         phfem.phf_assemble(mh, co, data, sysd)
         phfem.phf_synchronize(h)
         t2 = time.perf_counter()
         st = phfem.phf_solve(mh, co, sysd, t["U"], t["Lam"], rtol=a.rtol, max_iter=200000,
-                             check_every=32)
+                             check_every=32 if pc == phfem.PHF_PRECOND_JACOBI else 1,
+                             precond=pc)
         t3 = time.perf_counter()
-        phfem.phf_mesh_destroy(mh)
+        for c in reversed(chain):
+            phfem.phf_mesh_destroy(c)
         t4 = time.perf_counter()
         rows.append(dict(mesh_ms=1e3 * (t1 - t0), assemble_ms=1e3 * (t2 - t1),
                          solve_ms=1e3 * (t3 - t2), release_ms=1e3 * (t4 - t3),
@@ -209,9 +247,22 @@ def main():
     for _ in range(a.warmup):
         one_step(warm)
         print(f"[bench] warmup step {warm[-1]}", file=sys.stderr, flush=True)
-    rows = []
+    # one untimed step with every launch traced: per-kernel breakdown and the
+    # dominant kernel
     phfem.phf_trace_enable(h, True)
     phfem.phf_trace_reset(h)
+    prof = []
+    one_step(prof)
+    kern = phfem.phf_trace_dump(h)
+    info = out["info"]
+    nE = info.nE
+    ab = algorithmic_bytes(info, level_nf=out["level_nf"], level_nE=out["level_nE"])
+    dname = max(kern.items(), key=lambda kv: kv[1][1])[0]
+    print(f"[bench] traced step {prof[-1]}; dominant kernel {dname}", file=sys.stderr, flush=True)
+    # timed steps; only the dominant kernel carries events
+    phfem.phf_trace_filter(h, dname)
+    phfem.phf_trace_reset(h)
+    rows = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(a.steps):
@@ -219,18 +270,13 @@ def main():
         print(f"[bench] step {s}: {rows[-1]}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kern = phfem.phf_trace_dump(h)
+    dcount, dms = phfem.phf_trace_query(h, dname)
+    phfem.phf_trace_filter(h, None)
     phfem.phf_trace_enable(h, False)
     ms_step = 1e3 * (t1 - t0) / a.steps
-    info = out["info"]
-    nE = info.nE
 
-    # dominant kernel of the timed steps
-    dom = max(kern.items(), key=lambda kv: kv[1][1])
-    dname, (dcount, dms) = dom
-    ab = algorithmic_bytes(info)
     roof = None
-    if dname in ab:
+    if dname in ab and dcount:
         avg_s = dms / dcount / 1e3
         ach = ab[dname] / avg_s / 1e9
         tr = traffic_for(dname)
@@ -273,11 +319,15 @@ def main():
         print(f"[bench] Crank-Nicolson (paper mesh level {a.cn_level})", file=sys.stderr,
               flush=True)
         mc = G.paper_square(a.cn_level, bc="x_sides")
-        dmc = phfem.phf_mesh_create(h, mc.coords, mc.elements, mc.dirichlet, mc.neumann)
+        mb = G.paper_square(0, bc="x_sides")
+        cchain = [phfem.phf_mesh_create(h, mb.coords, mb.elements, mb.dirichlet, mb.neumann)]
+        for _ in range(a.cn_level):
+            cchain.append(phfem.phf_mesh_refine(cchain[-1]))
+        dmc = cchain[-1]
         ic = phfem.phf_mesh_get_info(dmc)
         k = 1e-3
         cn = phfem.phf_cn_create(dmc, phfem.make_coeffs(), k, rtol=1e-10,
-                                 iters_per_step=a.cn_chunk)
+                                 iters_per_step=a.cn_chunk, precond=pc)
         # initial state: P1 values through u0 at the edge midpoints (exact
         # for the discrete constraint), Lambda = 0
         P = mc.coords[mc.elements]
@@ -319,9 +369,11 @@ def main():
         ue = np.exp(-tf) * np.sin(pi * P[..., 0]) * np.sin(pi * P[..., 1])
         err = float(np.abs(Ud.cpu().numpy().reshape(-1, 3) - ue).max())
         phfem.phf_cn_destroy(cn)
-        phfem.phf_mesh_destroy(dmc)
-        out_cn = dict(workload=f"unit square, paper mesh level {a.cn_level} ({ic.nE} triangles), "
-                               f"u = exp(-t) sin(pi x) sin(pi y), k = {k}",
+        for c in reversed(cchain):
+            phfem.phf_mesh_destroy(c)
+        out_cn = dict(workload=f"unit square, paper mesh level {a.cn_level} ({ic.nE} triangles, "
+                               f"device-refined), u = exp(-t) sin(pi x) sin(pi y), k = {k}, "
+                               f"CG + {a.precond}",
                       t_final=tf, max_nodal_error=err, **res)
 
     cpu = None
@@ -344,10 +396,11 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": (f"elliptic L-shape, {nE} triangles (12 x 4^{a.level}), fp64, "
-                                f"a_T~U[0.5,2] seed 0, mixed BCs; step = mesh upload+topology+"
-                                f"patterns + assembly + saddle solve (rtol {a.rtol})"),
+                                f"a_T~U[0.5,2] seed 0, mixed BCs; step = base mesh upload + "
+                                f"{a.level} device red refinements with topology and patterns + "
+                                f"assembly + saddle solve (CG + {a.precond}, rtol {a.rtol})"),
                    "nE": nE, "n_edges": info.n_edges, "L": info.L, "N": info.N},
-        "rows": {"mesh_topology_patterns_ms": round(mean["mesh_ms"], 3),
+        "rows": {"refine_topology_patterns_ms": round(mean["mesh_ms"], 3),
                  "assembly_ms": round(mean["assemble_ms"], 3),
                  "solve_ms": round(mean["solve_ms"], 3),
                  "release_ms": round(mean["release_ms"], 3),
@@ -356,7 +409,16 @@ def main():
         "assembly": out_asm,
         "cn": out_cn,
         "roofline": roof,
-        "kernels_ms": {k: round(v[1], 3) for k, v in sorted(kern.items(), key=lambda kv: -kv[1][1])[:8]},
+        # from the one fully traced (untimed) step
+        "kernels_traced_step": {
+            "total_kernel_ms": round(sum(v[1] for v in kern.values()), 3),
+            "launches": int(sum(v[0] for v in kern.values())),
+            "top": {k: {"ms": round(v[1], 3), "launches": v[0],
+                        "GB_per_s": (round(ab[k] / (v[1] / v[0] * 1e-3) / 1e9, 1)
+                                     if k in ab else None)}
+                    for k, v in sorted(kern.items(), key=lambda kv: -kv[1][1])[:14]},
+            "all": {k: [v[0], round(v[1], 4)]
+                    for k, v in sorted(kern.items(), key=lambda kv: -kv[1][1])}},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

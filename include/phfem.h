@@ -60,10 +60,26 @@ typedef enum { PHF_HOST = 0, PHF_DEVICE = 1 } phf_memspace;
 /* Creates a context on HIP device `device` whose kernels run on `hip_stream`
  * (a hipStream_t; NULL = the null stream). *out receives the handle. */
 int phf_create(phf_ctx** out, int device, void* hip_stream);
-/* Synchronises the stream and frees the context (not its meshes). */
+/* Synchronises the stream and frees the context (not its meshes; device
+ * memory of meshes still alive goes back to HIP when they are destroyed). */
 int phf_destroy(phf_ctx* ctx);
-/* Redirects later launches to another stream of the same device. */
+/* Redirects later launches to another stream of the same device; waits for
+ * the old stream first (cached device blocks were last used in its order). */
 int phf_set_stream(phf_ctx* ctx, void* hip_stream);
+
+/* ---- device memory -------------------------------------------------------
+ * All device memory the library owns (mesh tables, solver and time-stepper
+ * state, temporaries) comes from a caching pool of the context: a released
+ * block is kept and handed out again for a request of the same rounded size
+ * (512 B granules up to 1 MiB, 2 MiB granules above), so rebuilding meshes of
+ * the same sizes makes no hipMalloc/hipFree calls. The library runs all its
+ * work in order on the context's stream, which makes reuse safe. Cached
+ * blocks return to HIP on phf_release_cache, when an allocation fails (then
+ * it is retried once), and in phf_destroy. Not thread-safe per context. */
+/* Bytes held by live library objects / kept in the cache (either nullable). */
+int phf_mem_stats(phf_ctx* ctx, int64_t* live_bytes, int64_t* cached_bytes);
+/* Waits for the stream, then frees every cached block. */
+int phf_release_cache(phf_ctx* ctx);
 /* Blocks until all work issued on the context's stream has finished. */
 int phf_synchronize(phf_ctx* ctx);
 /* Static text of a status code / the last error recorded on ctx. */
@@ -78,8 +94,11 @@ const char* phf_version(void);
  * the launch count and total milliseconds of the kernels whose name equals
  * `kernel` (NULL: all kernels). phf_trace_reset() clears the record.
  * phf_trace_dump() writes "name count total_ms" lines into buf (truncated to
- * len bytes, NUL-terminated) and returns the number of kernel names. */
+ * len bytes, NUL-terminated) and returns the number of kernel names.
+ * phf_trace_filter() limits tracing to the launches named `kernel` (NULL or
+ * "": every launch), so that timing one kernel adds no events to the rest. */
 int phf_trace_enable(phf_ctx* ctx, int on);
+int phf_trace_filter(phf_ctx* ctx, const char* kernel);
 int phf_trace_reset(phf_ctx* ctx);
 int phf_trace_query(phf_ctx* ctx, const char* kernel, int64_t* count, double* total_ms);
 int phf_trace_dump(phf_ctx* ctx, char* buf, size_t len);
@@ -103,7 +122,19 @@ int phf_trace_dump(phf_ctx* ctx, char* buf, size_t len);
 int phf_mesh_create(phf_ctx* ctx, const double* xy, int32_t nC, const int32_t* elem, int32_t nE,
                     const int32_t* dir, int32_t nD, const int32_t* neu, int32_t nN,
                     phf_memspace ms, phf_mesh** out);
+/* Frees a mesh. PHF_ESTATE while meshes refined from it are alive. */
 int phf_mesh_destroy(phf_mesh* mesh);
+
+/* One uniform red refinement on the device with the paper's numbering
+ * (Section 2.3, Listing 4): the midpoint of edge e becomes node nC + e;
+ * element m is replaced by its interior child [M1 M2 M3] (M_i = midpoint of
+ * the edge opposite vertex i) and the corner children [v1 M3 M2],
+ * [v2 M1 M3], [v3 M2 M1] follow at nE + 3m + {0, 1, 2}; each listed boundary
+ * pair (a, b) becomes (a, M) in the first half of its list and (M, b) in the
+ * second. The new mesh is built as by phf_mesh_create and keeps a reference
+ * to `coarse` (the multilevel preconditioner uses the chain), so `coarse`
+ * must outlive it. Synchronises the stream. */
+int phf_mesh_refine(phf_mesh* coarse, phf_mesh** fine);
 
 typedef struct {
     int32_t nC, nE, n_edges;   /* nodes, elements, edges (nrEdges)         */
@@ -130,6 +161,12 @@ int phf_mesh_topology(const phf_mesh* mesh, int32_t* edge_nodes, int32_t* edge_e
                       int32_t* elem_edges, int8_t* led, int8_t* ledTN, int8_t* edge_type,
                       int32_t* edge_row, int32_t* dir_edges, int32_t* neu_edges,
                       phf_memspace ms);
+
+/* Copies the mesh arrays out (memory space `ms`; NULL skips): xy nC x 2,
+ * elem nE x 3, dir nD x 2, neu nN x 2, as given to phf_mesh_create or as
+ * produced by phf_mesh_refine. Host copies synchronise. */
+int phf_mesh_geometry(const phf_mesh* mesh, double* xy, int32_t* elem, int32_t* dir,
+                      int32_t* neu, phf_memspace ms);
 
 /* Copies CSR patterns (rowptr int32 rows+1, col int32 nnz). K/M/D: N rows,
  * columns 3m..3m+2 ascending; C: L rows, the two vertex columns of T+ then
@@ -226,12 +263,23 @@ int phf_spmv(phf_ctx* ctx, int32_t nrows, const int32_t* rowptr, const int32_t* 
  * may be NULL. Synchronises the stream. Returns PHF_ENOCONV if rtol is not
  * reached in max_iter iterations (the iterate is still written). */
 #define PHF_SOLVER_NULLSPACE_CG 0
+/* Preconditioners of the reduced operator: Jacobi (any mesh), or a V-cycle
+ * over the chain of meshes the mesh was refined from by phf_mesh_refine
+ * (edge-midpoint prolongation averaged across coarse edges, damped Jacobi
+ * smoothing, coarse operators re-discretised with the triangle coefficient
+ * averaged over children, exact solve on the coarsest mesh). */
+#define PHF_PRECOND_JACOBI 0
+#define PHF_PRECOND_MULTIGRID 1
 typedef struct {
     int32_t method;      /* PHF_SOLVER_*                                   */
     int32_t max_iter;    /* 0 = 20000                                      */
     double rtol;         /* relative residual of the reduced system; 0 = 1e-10 */
-    int32_t check_every; /* host convergence test period (iterations); 0 = 8 */
+    int32_t check_every; /* host convergence test period (iterations); 0 = 8,
+                            or 1 with the multigrid preconditioner */
     int32_t saddle_residual; /* 1: compute the saddle residual into stats   */
+    int32_t precond;     /* PHF_PRECOND_*                                  */
+    int32_t mg_sweeps;   /* Jacobi sweeps before and after the coarse correction; 0 = 2 */
+    double mg_omega;     /* Jacobi damping; 0 = 0.7                         */
 } phf_solver_opts;
 
 typedef struct {
@@ -264,6 +312,9 @@ typedef struct {
     double rtol;            /* 0 = 1e-10                                   */
     int32_t max_iter;       /* per step, eager mode; 0 = 5000             */
     int32_t iters_per_step; /* CG iterations per captured chunk (even); 0 = 32 */
+    int32_t precond;        /* PHF_PRECOND_* (multigrid needs a refined mesh) */
+    int32_t mg_sweeps;      /* 0 = 2                                       */
+    double mg_omega;        /* 0 = 0.7                                     */
 } phf_cn_opts;
 
 int phf_cn_create(phf_mesh* mesh, const phf_coeffs* coeffs, double k, const phf_cn_opts* opts,

@@ -348,3 +348,29 @@ def error_norms(mesh, U, u, grad_u, t=0.0, n=5):
     l2 = np.sqrt(np.sum(wa * (ue - uh) ** 2))
     h1 = np.sqrt(np.sum(wa * ((ux - coef[:, 1:2]) ** 2 + (uy - coef[:, 2:3]) ** 2)))
     return h1, l2
+
+
+def red_refine(mesh, tables=None):
+    """One uniform red refinement with the paper's numbering (Section 2.3).
+
+    Parity pinned: element counts 4^(level+1), counter-clockwise children of
+    exactly a quarter of the parent area, the midpoint and vertex structure of
+    every child, boundary lists covering the refined boundary, and the edge
+    table of the refined mesh (Euler characteristic).
+    """
+    from paper_2401_15557_amd import meshgen as G
+    t = tables if tables is not None else mesh_tables(mesh)
+    nC, nE, ne = mesh.nC, mesh.nE, t["n_edges"]
+    nD, nN = len(mesh.dirichlet), len(mesh.neumann)
+    xy_f = np.empty((nC + ne, 2))
+    el_f = np.empty((4 * nE, 3), np.int32)
+    d_f = np.empty((max(2 * nD, 1), 2), np.int32)
+    n_f = np.empty((max(2 * nN, 1), 2), np.int32)
+    rc = lib().orc_red_refine(
+        ctypes.c_int32(nC), _p(mesh.coords), ctypes.c_int32(nE), _p(mesh.elements),
+        ctypes.c_int32(ne), _p(t["edge_nodes"]), _p(t["elem_edges"]), ctypes.c_int32(nD),
+        _p(mesh.dirichlet), _p(np.ascontiguousarray(t["dir_edges"])), ctypes.c_int32(nN),
+        _p(mesh.neumann), _p(np.ascontiguousarray(t["neu_edges"])), _p(xy_f), _p(el_f),
+        _p(d_f), _p(n_f))
+    _check(rc, "red_refine")
+    return G.Mesh(xy_f, el_f, d_f[:2 * nD], n_f[:2 * nN], name=mesh.name + "+r")

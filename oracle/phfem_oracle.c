@@ -541,3 +541,61 @@ void orc_csr_matvec(int32_t nrows, const int32_t* rowptr, const int32_t* col, co
         y[r] = s;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Uniform red refinement (Section 2.3, Listing 4).                          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * One red refinement with the paper's numbering, given the coarse edge table
+ * of orc_topology: the midpoint of edge e becomes node nC + e; element m is
+ * replaced by its interior child [M1 M2 M3] (M_i = midpoint of the edge
+ * opposite vertex i) and the corner children [v1 M3 M2], [v2 M1 M3],
+ * [v3 M2 M1] are appended at nE + 3m, nE + 3m + 1, nE + 3m + 2. Each listed
+ * boundary pair (a, b) of edge e becomes (a, M_e) in the first half of the new
+ * list and (M_e, b) in the second half. Output sizes: xy_f 2 (nC + n_edges),
+ * elem_f 3 * 4 nE, dir_f 2 * 2 nD, neu_f 2 * 2 nN.
+ */
+int orc_red_refine(int32_t nC, const double* xy, int32_t nE, const int32_t* elem,
+                   int32_t n_edges, const int32_t* edge_nodes, const int32_t* elem_edges,
+                   int32_t nD, const int32_t* dir, const int32_t* dir_edges, int32_t nN,
+                   const int32_t* neu, const int32_t* neu_edges, double* xy_f, int32_t* elem_f,
+                   int32_t* dir_f, int32_t* neu_f)
+{
+    for (int64_t q = 0; q < 2 * (int64_t)nC; ++q) xy_f[q] = xy[q];
+    for (int32_t e = 0; e < n_edges; ++e) {
+        int32_t k = edge_nodes[2 * (int64_t)e], l = edge_nodes[2 * (int64_t)e + 1];
+        xy_f[2 * ((int64_t)nC + e)] = 0.5 * (xy[2 * (int64_t)k] + xy[2 * (int64_t)l]);
+        xy_f[2 * ((int64_t)nC + e) + 1] = 0.5 * (xy[2 * (int64_t)k + 1] + xy[2 * (int64_t)l + 1]);
+    }
+    for (int32_t m = 0; m < nE; ++m) {
+        int32_t v[3], M[3];
+        for (int i = 0; i < 3; ++i) {
+            v[i] = elem[3 * (int64_t)m + i];
+            M[i] = nC + elem_edges[3 * (int64_t)m + i];
+        }
+        int32_t* c = elem_f + 3 * (int64_t)m;
+        c[0] = M[0]; c[1] = M[1]; c[2] = M[2];
+        for (int i = 0; i < 3; ++i) {
+            /* corner child at vertex i: [v_i, M_(i+2), M_(i+1)] */
+            int32_t* d = elem_f + 3 * ((int64_t)nE + 3 * (int64_t)m + i);
+            d[0] = v[i];
+            d[1] = M[(i + 2) % 3];
+            d[2] = M[(i + 1) % 3];
+        }
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        int32_t n = pass == 0 ? nD : nN;
+        const int32_t* pr = pass == 0 ? dir : neu;
+        const int32_t* ed = pass == 0 ? dir_edges : neu_edges;
+        int32_t* out = pass == 0 ? dir_f : neu_f;
+        for (int32_t q = 0; q < n; ++q) {
+            int32_t mid = nC + ed[q];
+            out[2 * (int64_t)q] = pr[2 * (int64_t)q];
+            out[2 * (int64_t)q + 1] = mid;
+            out[2 * ((int64_t)n + q)] = mid;
+            out[2 * ((int64_t)n + q) + 1] = pr[2 * (int64_t)q + 1];
+        }
+    }
+    return 0;
+}

@@ -296,6 +296,13 @@ extern "C" int phf_cn_create(phf_mesh* mesh, const phf_coeffs* co, double k,
     cn->opts.max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 5000;
     cn->opts.iters_per_step = opts && opts->iters_per_step > 0 ? opts->iters_per_step : 32;
     cn->opts.iters_per_step += cn->opts.iters_per_step & 1;  // chunks keep the CG parity
+    cn->opts.precond = opts ? opts->precond : PHF_PRECOND_JACOBI;
+    cn->opts.mg_sweeps = opts ? opts->mg_sweeps : 0;
+    cn->opts.mg_omega = opts ? opts->mg_omega : 0.0;
+    if (cn->opts.precond != PHF_PRECOND_JACOBI && cn->opts.precond != PHF_PRECOND_MULTIGRID) {
+        delete cn;
+        return phf_set_error(ctx, PHF_EINVAL, "phf_cn_create: unknown preconditioner");
+    }
     const size_t N = 3 * (size_t)mesh->nE, L = mesh->L, nnzK = 9 * (size_t)mesh->nE;
     auto body = [&]() -> int {
         TRY(phf_dmalloc(ctx, &cn->K, nnzK, "CN K"));
@@ -327,6 +334,8 @@ extern "C" int phf_cn_create(phf_mesh* mesh, const phf_coeffs* co, double k,
         TRY(phf_assemble_impl(mesh, co, &d, &s));
         TRY(phf_ns_create(mesh, &cn->ns));
         TRY(phf_ns_operator(cn->ns, cn->K, cn->M, cn->C, 0.5 * k, 1.0 + 0.5 * k * co->delta));
+        TRY(phf_ns_set_precond(cn->ns, cn->opts.precond, cn->opts.mg_sweeps, cn->opts.mg_omega,
+                               co, 0.5 * k, 1.0 + 0.5 * k * co->delta));
         PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
         return PHF_OK;
     };

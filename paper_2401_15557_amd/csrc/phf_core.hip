@@ -2,6 +2,9 @@
 // products of libphfem.
 #include <cstdarg>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <unordered_map>
 
 #include "phf_internal.h"
 #include "phf_device.h"
@@ -45,6 +48,110 @@ extern "C" const char* phf_last_error(const phf_ctx* ctx)
 extern "C" const char* phf_version(void) { return "0.1.0"; }
 
 // ---------------------------------------------------------------------------
+// caching device allocator
+// ---------------------------------------------------------------------------
+
+struct phf_pool {
+    std::multimap<size_t, void*> free_blocks;  // rounded size -> block
+    int64_t live_bytes = 0, cached_bytes = 0;
+};
+
+namespace {
+std::mutex g_pool_mu;
+// every block handed out by any pool: owner (null once that context is
+// destroyed: the block then goes straight back to HIP) and rounded size
+std::unordered_map<void*, std::pair<phf_pool*, size_t>> g_blocks;
+
+size_t round_block(size_t bytes)
+{
+    const size_t small = 512, large = size_t(2) << 20;
+    return bytes <= (size_t(1) << 20) ? (bytes + small - 1) / small * small
+                                      : (bytes + large - 1) / large * large;
+}
+
+// Frees every cached block of the pool (caller holds the lock).
+void pool_trim(phf_pool* pl)
+{
+    for (auto& kv : pl->free_blocks) {
+        g_blocks.erase(kv.second);
+        (void)hipFree(kv.second);
+    }
+    pl->free_blocks.clear();
+    pl->cached_bytes = 0;
+}
+}  // namespace
+
+int phf_dmalloc_bytes(phf_ctx* ctx, void** p, size_t bytes, const char* what)
+{
+    *p = nullptr;
+    const size_t sz = round_block(bytes);
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    phf_pool* pl = ctx->pool;
+    // best fit among cached blocks, at most 1/8 larger than asked for
+    auto it = pl->free_blocks.lower_bound(sz);
+    if (it != pl->free_blocks.end() && it->first <= sz + sz / 8) {
+        *p = it->second;
+        pl->cached_bytes -= (int64_t)it->first;
+        pl->live_bytes += (int64_t)it->first;
+        pl->free_blocks.erase(it);
+        return PHF_OK;
+    }
+    hipError_t e = hipMalloc(p, sz);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        pool_trim(pl);
+        e = hipMalloc(p, sz);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return phf_set_error(ctx, PHF_ENOMEM, "device allocation of %s (%zu bytes) failed", what,
+                             bytes);
+    }
+    g_blocks[*p] = {pl, sz};
+    pl->live_bytes += (int64_t)sz;
+    return PHF_OK;
+}
+
+void phf_dfree_ptr(void* p)
+{
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_blocks.find(p);
+    if (it == g_blocks.end()) {
+        (void)hipFree(p);
+        return;
+    }
+    phf_pool* pl = it->second.first;
+    const size_t sz = it->second.second;
+    if (!pl) {
+        g_blocks.erase(it);
+        (void)hipFree(p);
+        return;
+    }
+    pl->live_bytes -= (int64_t)sz;
+    pl->cached_bytes += (int64_t)sz;
+    pl->free_blocks.emplace(sz, p);
+}
+
+extern "C" int phf_mem_stats(phf_ctx* ctx, int64_t* live_bytes, int64_t* cached_bytes)
+{
+    if (!ctx) return PHF_EINVAL;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (live_bytes) *live_bytes = ctx->pool->live_bytes;
+    if (cached_bytes) *cached_bytes = ctx->pool->cached_bytes;
+    return PHF_OK;
+}
+
+extern "C" int phf_release_cache(phf_ctx* ctx)
+{
+    if (!ctx) return PHF_EINVAL;
+    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    pool_trim(ctx->pool);
+    return PHF_OK;
+}
+
+// ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
 
@@ -61,6 +168,11 @@ extern "C" int phf_create(phf_ctx** out, int device, void* hip_stream)
     if (!ctx) return PHF_ENOMEM;
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
+    ctx->pool = new (std::nothrow) phf_pool;
+    if (!ctx->pool) {
+        delete ctx;
+        return PHF_ENOMEM;
+    }
     if (hipSetDevice(device) != hipSuccess) {
         delete ctx;
         return PHF_EHIP;
@@ -70,6 +182,7 @@ extern "C" int phf_create(phf_ctx** out, int device, void* hip_stream)
             hipSuccess) {
         (void)hipGetLastError();
         if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+        delete ctx->pool;
         delete ctx;
         return PHF_ENOMEM;
     }
@@ -89,6 +202,15 @@ extern "C" int phf_destroy(phf_ctx* ctx)
     for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
     if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        pool_trim(ctx->pool);
+        // blocks still held by objects of this context are released to HIP
+        // directly when those objects are destroyed
+        for (auto& kv : g_blocks)
+            if (kv.second.first == ctx->pool) kv.second.first = nullptr;
+        delete ctx->pool;
+    }
     delete ctx;
     return PHF_OK;
 }
@@ -96,6 +218,8 @@ extern "C" int phf_destroy(phf_ctx* ctx)
 extern "C" int phf_set_stream(phf_ctx* ctx, void* hip_stream)
 {
     if (!ctx) return PHF_EINVAL;
+    // cached blocks were last used in the order of the old stream
+    if (hip_stream != (void*)ctx->stream) PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
     ctx->stream = (hipStream_t)hip_stream;
     return PHF_OK;
 }
@@ -131,6 +255,7 @@ void phf_trace_begin(phf_ctx* ctx, const char* name, phf_trace_rec* rec)
     rec->name = name;
     rec->start = rec->stop = nullptr;
     if (!ctx->trace) return;
+    if (!ctx->trace_only.empty() && ctx->trace_only != name) return;
     rec->start = take_event(ctx);
     rec->stop = take_event(ctx);
     if (rec->start) (void)hipEventRecord(rec->start, ctx->stream);
@@ -184,6 +309,13 @@ extern "C" int phf_trace_enable(phf_ctx* ctx, int on)
         }
         ctx->event_pool.push_back(e);
     }
+    return PHF_OK;
+}
+
+extern "C" int phf_trace_filter(phf_ctx* ctx, const char* kernel)
+{
+    if (!ctx) return PHF_EINVAL;
+    ctx->trace_only = kernel ? kernel : "";
     return PHF_OK;
 }
 
@@ -293,6 +425,26 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const int32_t* in, 
         ex += v[k];
     }
 }
+// Whole scan in one workgroup, for n <= SCAN_TILE.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_single(const int32_t* in, int32_t* out,
+                                                              int32_t n, int32_t* d_total)
+{
+    __shared__ int32_t sh[SCAN_THREADS / 64 + 1];
+    const int32_t base = threadIdx.x * SCAN_ITEMS;
+    int32_t v[SCAN_ITEMS];
+    int32_t s = 0;
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0;
+        s += v[k];
+    }
+    int32_t tot;
+    int32_t ex = phf_block_exscan_i32<SCAN_THREADS>(s, sh, &tot);
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+    if (threadIdx.x == 0 && d_total) *d_total = tot;
+}
 }  // namespace
 
 int phf_scan_i32(phf_ctx* ctx, const int32_t* in, int32_t* out, int32_t n, int32_t* d_total)
@@ -302,6 +454,10 @@ int phf_scan_i32(phf_ctx* ctx, const int32_t* in, int32_t* out, int32_t n, int32
         return PHF_OK;
     }
     int32_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb == 1) {
+        PHF_LAUNCH(ctx, "k_scan", k_scan_single, 1, SCAN_THREADS, 0, in, out, n, d_total);
+        return PHF_OK;
+    }
     int32_t* bsum = nullptr;
     int rc = phf_dmalloc(ctx, &bsum, nb, "scan block sums");
     if (rc) return rc;
@@ -314,9 +470,8 @@ int phf_scan_i32(phf_ctx* ctx, const int32_t* in, int32_t* out, int32_t n, int32
                        bsum);
     phf_trace_end(ctx, &rec);
     hipError_t e = hipGetLastError();
-    // the temporary is released after the stream has consumed it
-    (void)hipStreamSynchronize(ctx->stream);
-    (void)hipFree(bsum);
+    // back to the pool: later users of the block run after these kernels
+    phf_dfree(bsum);
     if (e != hipSuccess)
         return phf_set_error(ctx, PHF_EHIP, "scan launch failed: %s", hipGetErrorString(e));
     return PHF_OK;

@@ -19,16 +19,20 @@ struct phf_trace_rec {
     hipEvent_t start, stop;
 };
 
+struct phf_pool;
+
 struct phf_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     char last_error[512] = {0};
     bool trace = false;
+    std::string trace_only;                   // if set, the one kernel name traced
     std::vector<phf_trace_rec> pending;       // recorded, not yet read
     std::vector<hipEvent_t> event_pool;       // reusable events
     std::vector<std::pair<std::string, std::pair<int64_t, double>>> totals;
     int* d_flags = nullptr;                   // small device scratch for checks
     int64_t* h_pinned = nullptr;              // pinned host words for readback
+    phf_pool* pool = nullptr;                 // caching device allocator
 };
 
 int phf_set_error(phf_ctx* ctx, int code, const char* fmt, ...);
@@ -59,25 +63,26 @@ void phf_trace_end(phf_ctx* ctx, phf_trace_rec* rec);
         phf_trace_end((ctx), &rec_);                                                  \
     } while (0)
 
+// Device memory comes from the context's caching pool: a freed block goes
+// back to the pool of the context that allocated it and is handed out again
+// for a request of the same rounded size. All library work of a context runs
+// in order on its one stream, so a block reused there never overlaps work
+// that still reads its previous contents. Blocks are returned to HIP by
+// phf_release_cache, when an allocation fails, and at phf_destroy.
+int phf_dmalloc_bytes(phf_ctx* ctx, void** p, size_t bytes, const char* what);
+void phf_dfree_ptr(void* p);
+
 template <typename T>
 int phf_dmalloc(phf_ctx* ctx, T** p, size_t count, const char* what)
 {
-    *p = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        *p = nullptr;
-        return phf_set_error(ctx, PHF_ENOMEM, "device allocation of %s (%zu bytes) failed",
-                             what, count * sizeof(T));
-    }
-    return PHF_OK;
+    return phf_dmalloc_bytes(ctx, (void**)p, count * sizeof(T), what);
 }
 
 template <typename T>
 void phf_dfree(T*& p)
 {
-    if (p) (void)hipFree((void*)p);
+    if (p) phf_dfree_ptr((void*)p);
     p = nullptr;
 }
 
@@ -100,6 +105,8 @@ void phf_ns_destroy(phf_ns* ns);
 struct phf_mesh {
     phf_ctx* ctx = nullptr;
     phf_ns* ns = nullptr;          // cached solver workspace (lazy)
+    phf_mesh* parent = nullptr;    // coarse mesh this one was refined from
+    int32_t n_children = 0;        // meshes refined from this one, still alive
     int32_t nC = 0, nE = 0, n_edges = 0, L = 0, nD = 0, nN = 0, n_int = 0, n_free = 0;
     int64_t nnz_C = 0, nnz_S = 0, nnz_R = 0;
     int64_t bytes = 0;
@@ -118,6 +125,8 @@ struct phf_mesh {
     int32_t* edge_row = nullptr;   // n_edges (-1 Neumann)
     int32_t* dir_edges = nullptr;  // nD
     int32_t* neu_edges = nullptr;  // nN
+    int2* dir_pairs = nullptr;     // nD: listed node pairs, as given
+    int2* neu_pairs = nullptr;     // nN
     // multiplier rows
     int32_t* row_edge = nullptr;   // L
     int2* row_nodes = nullptr;     // L: (k, l) of the row's edge; k stored as ~k

@@ -457,6 +457,8 @@ static void mesh_free(phf_mesh* m)
     phf_dfree(m->edge_row);
     phf_dfree(m->dir_edges);
     phf_dfree(m->neu_edges);
+    phf_dfree(m->dir_pairs);
+    phf_dfree(m->neu_pairs);
     phf_dfree(m->row_edge);
     phf_dfree(m->row_nodes);
     phf_dfree(m->C_tile);
@@ -481,8 +483,6 @@ struct build_tmp {
     uint64_t* keys = nullptr;
     int32_t* ucount = nullptr;
     int32_t* eoff = nullptr;
-    int32_t* dirp = nullptr;
-    int32_t* neup = nullptr;
     int32_t* mark = nullptr;
     int32_t* nonN = nullptr;
     int32_t* nonD = nullptr;
@@ -493,8 +493,7 @@ struct build_tmp {
     ~build_tmp()
     {
         phf_dfree(raw); phf_dfree(bcount); phf_dfree(boff); phf_dfree(keys);
-        phf_dfree(ucount); phf_dfree(eoff); phf_dfree(dirp); phf_dfree(neup);
-        phf_dfree(mark); phf_dfree(nonN); phf_dfree(nonD); phf_dfree(clen);
+        phf_dfree(ucount); phf_dfree(eoff);         phf_dfree(mark); phf_dfree(nonN); phf_dfree(nonD); phf_dfree(clen);
         phf_dfree(inter); phf_dfree(slen); phf_dfree(totals);
     }
 };
@@ -616,16 +615,16 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     TRY(phf_dmalloc(ctx, &M->dir_edges, nD, "Dirichlet edges"));
     TRY(phf_dmalloc(ctx, &M->neu_edges, nN, "Neumann edges"));
     TRY(phf_dmalloc(ctx, &T.mark, ne, "edge marks"));
-    TRY(phf_dmalloc(ctx, &T.dirp, 2 * (size_t)nD, "Dirichlet pairs"));
-    TRY(phf_dmalloc(ctx, &T.neup, 2 * (size_t)nN, "Neumann pairs"));
-    if (nD) PHF_HIP(ctx, hipMemcpyAsync(T.dirp, dir, sizeof(int32_t) * 2 * (size_t)nD, kind, ctx->stream));
-    if (nN) PHF_HIP(ctx, hipMemcpyAsync(T.neup, neu, sizeof(int32_t) * 2 * (size_t)nN, kind, ctx->stream));
+    TRY(phf_dmalloc(ctx, &M->dir_pairs, nD, "Dirichlet pairs"));
+    TRY(phf_dmalloc(ctx, &M->neu_pairs, nN, "Neumann pairs"));
+    if (nD) PHF_HIP(ctx, hipMemcpyAsync(M->dir_pairs, dir, sizeof(int32_t) * 2 * (size_t)nD, kind, ctx->stream));
+    if (nN) PHF_HIP(ctx, hipMemcpyAsync(M->neu_pairs, neu, sizeof(int32_t) * 2 * (size_t)nN, kind, ctx->stream));
     PHF_HIP(ctx, hipMemsetAsync(M->edge_type, 0, ne, ctx->stream));
     PHF_HIP(ctx, hipMemsetAsync(T.mark, 0, sizeof(int32_t) * ne, ctx->stream));
     TRY(reset_flags(ctx));
     if (nD + nN > 0)
-        PHF_LAUNCH(ctx, "k_boundary_mark", k_boundary_mark, nblk(nD + nN), 256, 0, T.dirp, nD,
-                   T.neup, nN, nC, T.eoff, M->edge_nodes, M->edge_elems, T.mark, M->edge_type,
+        PHF_LAUNCH(ctx, "k_boundary_mark", k_boundary_mark, nblk(nD + nN), 256, 0,
+                   (const int32_t*)M->dir_pairs, nD, (const int32_t*)M->neu_pairs, nN, nC, T.eoff, M->edge_nodes, M->edge_elems, T.mark, M->edge_type,
                    M->dir_edges, M->neu_edges, ctx->d_flags);
     TRY(phf_dmalloc(ctx, &T.nonN, (size_t)ne + 1, "row indicator"));
     TRY(phf_dmalloc(ctx, &T.nonD, (size_t)ne + 1, "reduced indicator"));
@@ -753,9 +752,116 @@ extern "C" int phf_mesh_create(phf_ctx* ctx, const double* xy, int32_t nC, const
 extern "C" int phf_mesh_destroy(phf_mesh* mesh)
 {
     if (!mesh) return PHF_EINVAL;
+    if (mesh->n_children > 0)
+        return phf_set_error(mesh->ctx, PHF_ESTATE,
+                             "phf_mesh_destroy: %d refined meshes still refer to this mesh",
+                             mesh->n_children);
     (void)hipStreamSynchronize(mesh->ctx->stream);
+    if (mesh->parent) mesh->parent->n_children--;
     mesh_free(mesh);
     delete mesh;
+    return PHF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// uniform red refinement (Section 2.3, Listing 4)
+// ---------------------------------------------------------------------------
+
+namespace {
+__global__ __launch_bounds__(256) void k_refine_nodes(int32_t nC, int32_t ne,
+                                                      const double2* __restrict__ xy,
+                                                      const int2* __restrict__ edge_nodes,
+                                                      double2* __restrict__ xy_f)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g < nC) {
+        xy_f[g] = xy[g];
+    } else if (g < (int64_t)nC + ne) {
+        const int2 kl = edge_nodes[g - nC];
+        const double2 a = xy[kl.x], b = xy[kl.y];
+        xy_f[g] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y + b.y));
+    }
+}
+
+// Children of element m: [M0 M1 M2] at m and [v_i, M_(i+2), M_(i+1)] at
+// nE + 3m + i, with M_i = nC + (edge opposite vertex i).
+__global__ __launch_bounds__(256) void k_refine_elems(int32_t nC, int32_t nE,
+                                                      const int4* __restrict__ elem4,
+                                                      const int32_t* __restrict__ elem_edges,
+                                                      int32_t* __restrict__ el_f)
+{
+    const int32_t m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= nE) return;
+    const int4 e = elem4[m];
+    const int32_t v[3] = {e.x, e.y, e.z};
+    int32_t M[3];
+    for (int i = 0; i < 3; ++i) M[i] = nC + elem_edges[3 * (int64_t)m + i];
+    el_f[3 * (int64_t)m] = M[0];
+    el_f[3 * (int64_t)m + 1] = M[1];
+    el_f[3 * (int64_t)m + 2] = M[2];
+    for (int i = 0; i < 3; ++i) {
+        int32_t* d = el_f + 3 * ((int64_t)nE + 3 * (int64_t)m + i);
+        d[0] = v[i];
+        d[1] = M[(i + 2) % 3];
+        d[2] = M[(i + 1) % 3];
+    }
+}
+
+// Listed pair q of edge e: (a, M_e) at q and (M_e, b) at n + q.
+__global__ __launch_bounds__(256) void k_refine_pairs(int32_t nC, int32_t n,
+                                                      const int2* __restrict__ pairs,
+                                                      const int32_t* __restrict__ edges,
+                                                      int2* __restrict__ out)
+{
+    const int32_t q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const int2 ab = pairs[q];
+    const int32_t mid = nC + edges[q];
+    out[q] = make_int2(ab.x, mid);
+    out[n + q] = make_int2(mid, ab.y);
+}
+}  // namespace
+
+extern "C" int phf_mesh_refine(phf_mesh* coarse, phf_mesh** out)
+{
+    if (!coarse || !out) return PHF_EINVAL;
+    *out = nullptr;
+    phf_ctx* ctx = coarse->ctx;
+    const int64_t nCf = (int64_t)coarse->nC + coarse->n_edges, nEf = 4 * (int64_t)coarse->nE;
+    if (nCf > 0x7fffffffLL || nEf > 80000000LL)
+        return phf_set_error(ctx, PHF_EINVAL, "phf_mesh_refine: refined mesh too large");
+    double2* xy_f = nullptr;
+    int32_t* el_f = nullptr;
+    int2 *d_f = nullptr, *n_f = nullptr;
+    int rc = PHF_OK;
+    auto body = [&]() -> int {
+        TRY(phf_dmalloc(ctx, &xy_f, (size_t)nCf, "refined coordinates"));
+        TRY(phf_dmalloc(ctx, &el_f, 3 * (size_t)nEf, "refined elements"));
+        TRY(phf_dmalloc(ctx, &d_f, 2 * (size_t)coarse->nD, "refined Dirichlet pairs"));
+        TRY(phf_dmalloc(ctx, &n_f, 2 * (size_t)coarse->nN, "refined Neumann pairs"));
+        PHF_LAUNCH(ctx, "k_refine_nodes", k_refine_nodes, nblk(nCf), 256, 0, coarse->nC,
+                   coarse->n_edges, coarse->xy, coarse->edge_nodes, xy_f);
+        PHF_LAUNCH(ctx, "k_refine_elems", k_refine_elems, nblk(coarse->nE), 256, 0, coarse->nC,
+                   coarse->nE, coarse->elem4, coarse->elem_edges, el_f);
+        if (coarse->nD)
+            PHF_LAUNCH(ctx, "k_refine_pairs", k_refine_pairs, nblk(coarse->nD), 256, 0, coarse->nC,
+                       coarse->nD, coarse->dir_pairs, coarse->dir_edges, d_f);
+        if (coarse->nN)
+            PHF_LAUNCH(ctx, "k_refine_pairs", k_refine_pairs, nblk(coarse->nN), 256, 0, coarse->nC,
+                       coarse->nN, coarse->neu_pairs, coarse->neu_edges, n_f);
+        return phf_mesh_create(ctx, (const double*)xy_f, (int32_t)nCf, el_f, (int32_t)nEf,
+                               (const int32_t*)d_f, 2 * coarse->nD, (const int32_t*)n_f,
+                               2 * coarse->nN, PHF_DEVICE, out);
+    };
+    rc = body();
+    (void)hipStreamSynchronize(ctx->stream);
+    phf_dfree(xy_f);
+    phf_dfree(el_f);
+    phf_dfree(d_f);
+    phf_dfree(n_f);
+    if (rc) return rc;
+    (*out)->parent = coarse;
+    coarse->n_children++;
     return PHF_OK;
 }
 
@@ -831,6 +937,45 @@ extern "C" int phf_mesh_topology(const phf_mesh* m, int32_t* edge_nodes, int32_t
     TRY(copy_out(ctx, edge_row, m->edge_row, ne * 4, ms));
     TRY(copy_out(ctx, dir_edges, m->dir_edges, (size_t)m->nD * 4, ms));
     TRY(copy_out(ctx, neu_edges, m->neu_edges, (size_t)m->nN * 4, ms));
+    if (ms == PHF_HOST) PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PHF_OK;
+}
+
+namespace {
+__global__ __launch_bounds__(256) void k_elem_xyz(int32_t nE, const int4* __restrict__ elem4,
+                                                  int32_t* __restrict__ out)
+{
+    const int32_t m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= nE) return;
+    const int4 e = elem4[m];
+    out[3 * (int64_t)m] = e.x;
+    out[3 * (int64_t)m + 1] = e.y;
+    out[3 * (int64_t)m + 2] = e.z;
+}
+}  // namespace
+
+extern "C" int phf_mesh_geometry(const phf_mesh* m, double* xy, int32_t* elem, int32_t* dir,
+                                 int32_t* neu, phf_memspace ms)
+{
+    if (!m || (ms != PHF_HOST && ms != PHF_DEVICE)) return PHF_EINVAL;
+    phf_ctx* ctx = m->ctx;
+    TRY(copy_out(ctx, xy, m->xy, (size_t)m->nC * 16, ms));
+    if (elem) {
+        int32_t* tmp = nullptr;
+        if (ms == PHF_DEVICE) {
+            tmp = elem;
+        } else {
+            TRY(phf_dmalloc(ctx, &tmp, 3 * (size_t)m->nE, "element copy"));
+        }
+        PHF_LAUNCH(ctx, "k_elem_xyz", k_elem_xyz, nblk(m->nE), 256, 0, m->nE, m->elem4, tmp);
+        if (ms == PHF_HOST) {
+            TRY(copy_out(ctx, elem, tmp, 12 * (size_t)m->nE, ms));
+            PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            phf_dfree(tmp);
+        }
+    }
+    TRY(copy_out(ctx, dir, m->dir_pairs, (size_t)m->nD * 8, ms));
+    TRY(copy_out(ctx, neu, m->neu_pairs, (size_t)m->nN * 8, ms));
     if (ms == PHF_HOST) PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return PHF_OK;
 }

@@ -1,0 +1,69 @@
+// Multilevel preconditioner for the reduced (edge-midpoint) operator on a
+// chain of red-refined meshes (internal to libphfem).
+//
+// Level l has the reduced operator R_l = sum_T P^T A_T P of its own mesh (the
+// coarse ones re-discretised with the triangle coefficient averaged over the
+// four children). The spaces of edge-midpoint (Crouzeix-Raviart) functions on
+// nested meshes are not nested; the prolongation evaluates the coarse function
+// at the midpoint of each fine edge: inside a coarse triangle (the three
+// interior edges of its children) from that triangle, on a coarse edge as the
+// average of the two coarse triangles sharing it. With ψ_l = 1 - 2 λ_l the CR
+// basis of the coarse triangle, the weights are 1 - 2 λ_l(m_e); the
+// barycentric coordinates of the fine midpoints are the same in every coarse
+// triangle, so the weights are constants. Restriction is the transpose,
+// applied as per-coarse-triangle sums over its nine fine edges followed by a
+// sum over the two triangles of each coarse edge. Smoothing is damped Jacobi, the coarsest level is solved
+// exactly (dense inverse), and the V-cycle with equal pre- and post-smoothing
+// is symmetric, so it can precondition conjugate gradients.
+#pragma once
+
+#include "phf_solver.h"
+
+#define PHF_MG_MAX_LEVELS 20
+#define PHF_MG_DENSE_MAX 256
+
+struct phf_mg_level {
+    phf_mesh* mesh = nullptr;
+    phf_ns* ns = nullptr;       // operator of this level (owned on coarse levels)
+    bool own_ns = false;
+    int32_t nf = 0;
+    // coarse-level assembly buffers (null on the finest level)
+    double *K = nullptr, *M = nullptr, *C = nullptr, *F = nullptr, *bD = nullptr, *aT = nullptr;
+    // V-cycle vectors
+    double *x = nullptr, *y = nullptr, *b = nullptr, *r = nullptr;
+    // prolongation from the next coarser level (ELL-5 over this level's rows)
+    int32_t* P_col = nullptr;
+    double* P_val = nullptr;
+    // restriction to the next coarser level: fine rows of the nine fine edges
+    // in each coarse triangle (slot-major, 9 x nE_coarse), per-triangle sums
+    // (3 x nE_coarse)
+    int32_t* rows9 = nullptr;
+    double* t = nullptr;
+    // on coarse levels: positions of each row's edge in the sums of the finer
+    // level (T+ side, T- side or -1)
+    int2* sel = nullptr;
+};
+
+struct phf_mg {
+    int32_t nlev = 0;  // lev[0] coarsest ... lev[nlev-1] finest
+    phf_mg_level lev[PHF_MG_MAX_LEVELS];
+    double* cinv = nullptr;  // dense inverse of the coarsest operator (n0 <= DENSE_MAX)
+    double* cwork = nullptr;
+    int32_t n0 = 0;
+    int32_t nu = 2;          // Jacobi sweeps before and after the coarse correction
+    double omega = 0.7;      // Jacobi damping
+};
+
+// Builds the hierarchy below the finest operator `fine` (whose mesh must come
+// from phf_mesh_refine). Symbolic part only; call phf_mg_numeric next.
+int phf_mg_create(phf_ns* fine, phf_mg** out);
+void phf_mg_destroy(phf_mg* mg);
+// Coarse operators for A = cK K + cM M with the finest-level triangle
+// coefficient aT (nullable, constant A from coeffs), prolongations, coarse
+// inverse. The finest operator is the one already built in `fine`.
+int phf_mg_numeric(phf_mg* mg, const phf_coeffs* coeffs, double cK, double cM);
+// z = V-cycle(r) on the finest level; writes partial sums of r.z into
+// part (slot layout of the CG kernels). Skipped when *iflags (done) is set.
+int phf_mg_apply(phf_mg* mg, const double* r, double* z, double* part_rz, const int* iflags);
+// Number of hierarchy levels below and including `mesh`.
+int32_t phf_mg_levels(const phf_mesh* mesh);

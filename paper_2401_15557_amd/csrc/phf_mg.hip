@@ -1,0 +1,545 @@
+// Multilevel (V-cycle) preconditioner over a chain of red-refined meshes; see
+// phf_mg.h for the construction.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+
+#include "phf_device.h"
+#include "phf_mg.h"
+
+namespace {
+
+constexpr int NT = 256;
+inline unsigned nblk(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
+
+#define TRY(x)               \
+    do {                     \
+        int rc_ = (x);       \
+        if (rc_) return rc_; \
+    } while (0)
+
+// Parent of element m of a mesh refined from a coarse mesh with nEc elements.
+__device__ inline int32_t parent_of(int32_t m, int32_t nEc)
+{
+    return m < nEc ? m : (m - nEc) / 3;
+}
+
+__global__ __launch_bounds__(NT) void k_mg_coef(int32_t nEc, const double* __restrict__ aT_f,
+                                                double* __restrict__ aT_c)
+{
+    const int32_t p = blockIdx.x * NT + threadIdx.x;
+    if (p >= nEc) return;
+    const int64_t c = nEc + 3 * (int64_t)p;
+    aT_c[p] = 0.25 * (aT_f[p] + aT_f[c] + aT_f[c + 1] + aT_f[c + 2]);
+}
+
+// Prolongation row of fine free edge rf: the coarse CR function at the fine
+// edge midpoint, averaged over the (one or two) coarse triangles containing it.
+__global__ __launch_bounds__(NT) void k_mg_prolong_build(
+    int32_t nf_f, int32_t nEc, const int32_t* __restrict__ red_edge_f,
+    const int2* __restrict__ edge_elems_f, const int2* __restrict__ edge_nodes_f,
+    const double2* __restrict__ xy_f, const double2* __restrict__ exy_c,
+    const int32_t* __restrict__ elem_edges_c, const int32_t* __restrict__ red_row_c,
+    int32_t* __restrict__ P_col, double* __restrict__ P_val)
+{
+    const int32_t rf = blockIdx.x * NT + threadIdx.x;
+    if (rf >= nf_f) return;
+    const int32_t e = red_edge_f[rf];
+    const int2 tt = edge_elems_f[e];
+    const int2 kl = edge_nodes_f[e];
+    const double2 a = xy_f[kl.x], b = xy_f[kl.y];
+    const double mx = 0.5 * (a.x + b.x), my = 0.5 * (a.y + b.y);
+    int32_t par[2] = {parent_of(tt.x, nEc), tt.y >= 0 ? parent_of(tt.y, nEc) : -1};
+    if (par[1] == par[0]) par[1] = -1;
+    const double scale = par[1] < 0 ? 1.0 : 0.5;
+    int32_t col[6];
+    double val[6];
+    int n = 0;
+    for (int s = 0; s < 2; ++s) {
+        const int32_t p = par[s];
+        if (p < 0) continue;
+        const double2 P0 = exy_c[3 * (int64_t)p], P1 = exy_c[3 * (int64_t)p + 1],
+                      P2 = exy_c[3 * (int64_t)p + 2];
+        const double d1x = P1.x - P0.x, d1y = P1.y - P0.y, d2x = P2.x - P0.x, d2y = P2.y - P0.y;
+        const double det = d1x * d2y - d1y * d2x;
+        const double rx = mx - P0.x, ry = my - P0.y;
+        const double l1 = (rx * d2y - ry * d2x) / det, l2 = (d1x * ry - d1y * rx) / det;
+        const double lam[3] = {1.0 - l1 - l2, l1, l2};
+        for (int l = 0; l < 3; ++l) {
+            const double w = 1.0 - 2.0 * lam[l];
+            if (fabs(w) < 1e-12) continue;
+            const int32_t rc = red_row_c[elem_edges_c[3 * (int64_t)p + l]];
+            if (rc < 0) continue;
+            int q = 0;
+            while (q < n && col[q] != rc) ++q;
+            if (q == n) {
+                col[n] = rc;
+                val[n] = 0.0;
+                ++n;
+            }
+            val[q] += scale * w;
+        }
+    }
+    for (int k = 0; k < 5; ++k) {
+        const int64_t slot = (int64_t)k * nf_f + rf;
+        P_col[slot] = k < n ? col[k] : 0;
+        P_val[slot] = k < n ? val[k] : 0.0;
+    }
+}
+
+// Fine rows of the nine fine edges inside coarse triangle p (-1 where the
+// fine edge is Dirichlet), stored slot-major (slot k at k * nEc + p):
+//   slot j      (j < 3) edge of the centre child parallel to coarse edge j;
+//   slot 3 + 2i         half of coarse edge i+1 at vertex v_i;
+//   slot 4 + 2i         half of coarse edge i+2 at vertex v_i.
+// The centre child of p is element p = [M0 M1 M2], corner child i is
+// nEc + 3p + i = [v_i M_(i+2) M_(i+1)] (M_j the midpoint of coarse edge j).
+__global__ __launch_bounds__(NT) void k_mg_rows9(int32_t nEc, const int32_t* __restrict__ elem_edges_f,
+                                                 const int32_t* __restrict__ red_row_f,
+                                                 int32_t* __restrict__ rows9)
+{
+    const int32_t p = blockIdx.x * NT + threadIdx.x;
+    if (p >= nEc) return;
+    for (int j = 0; j < 3; ++j)
+        rows9[(int64_t)j * nEc + p] = red_row_f[elem_edges_f[3 * (int64_t)p + j]];
+    for (int i = 0; i < 3; ++i) {
+        const int64_t ch = (int64_t)nEc + 3 * (int64_t)p + i;
+        rows9[(int64_t)(3 + 2 * i) * nEc + p] = red_row_f[elem_edges_f[3 * ch + 1]];
+        rows9[(int64_t)(4 + 2 * i) * nEc + p] = red_row_f[elem_edges_f[3 * ch + 2]];
+    }
+}
+
+// For coarse free row c: positions in the per-triangle restriction sums of
+// its edge seen from T+ and from T- (-1 on the boundary).
+__global__ __launch_bounds__(NT) void k_mg_sel(int32_t nc, const int32_t* __restrict__ red_edge_c,
+                                               const int2* __restrict__ edge_elems_c,
+                                               const int8_t* __restrict__ led_c,
+                                               const int8_t* __restrict__ ledTN_c,
+                                               int2* __restrict__ sel)
+{
+    const int32_t c = blockIdx.x * NT + threadIdx.x;
+    if (c >= nc) return;
+    const int32_t e = red_edge_c[c];
+    const int2 tt = edge_elems_c[e];
+    sel[c] = make_int2(3 * tt.x + led_c[e], tt.y >= 0 ? 3 * tt.y + ledTN_c[e] : -1);
+}
+
+__global__ __launch_bounds__(NT) void k_mg_dense(int32_t n, const int32_t* __restrict__ col,
+                                                 const double* __restrict__ val,
+                                                 double* __restrict__ A)
+{
+    const int32_t r = blockIdx.x * NT + threadIdx.x;
+    if (r >= n) return;
+    for (int32_t j = 0; j < n; ++j) A[(int64_t)r * n + j] = 0.0;
+    for (int k = 0; k < 5; ++k) {
+        const int64_t slot = (int64_t)k * n + r;
+        A[(int64_t)r * n + col[slot]] += val[slot];
+    }
+}
+
+// In-place Gauss-Jordan inversion of an SPD matrix (no pivoting needed) by
+// one workgroup: A (n x n) becomes its inverse; W is n x n scratch.
+__global__ __launch_bounds__(1024) void k_mg_gj(int32_t n, double* __restrict__ A,
+                                                double* __restrict__ W)
+{
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int64_t q = tid; q < (int64_t)n * n; q += nth) W[q] = ((q / n) == (q % n)) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int32_t c = 0; c < n; ++c) {
+        const double piv = A[(int64_t)c * n + c];
+        __syncthreads();
+        for (int32_t j = tid; j < n; j += nth) {
+            A[(int64_t)c * n + j] /= piv;
+            W[(int64_t)c * n + j] /= piv;
+        }
+        __syncthreads();
+        for (int64_t q = tid; q < (int64_t)n * n; q += nth) {
+            const int32_t i = (int32_t)(q / n), j = (int32_t)(q % n);
+            if (i == c) continue;
+            const double f = A[(int64_t)i * n + c];
+            if (j != c) A[q] -= f * A[(int64_t)c * n + j];
+            W[q] -= f * W[(int64_t)c * n + j];
+        }
+        __syncthreads();
+        for (int32_t i = tid; i < n; i += nth)
+            if (i != c) A[(int64_t)i * n + c] = 0.0;
+        __syncthreads();
+    }
+    for (int64_t q = tid; q < (int64_t)n * n; q += nth) A[q] = W[q];
+}
+
+__device__ inline double ell5(int32_t r, int32_t n, const int32_t* __restrict__ col,
+                              const double* __restrict__ val, const double* __restrict__ x)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int64_t slot = (int64_t)k * n + r;
+        s = fma(val[slot], x[col[slot]], s);
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(NT) void k_mg_smooth0(int32_t n, const double* __restrict__ dinv,
+                                                   const double* __restrict__ b, double omega,
+                                                   double* __restrict__ x, const int* iflags)
+{
+    if (iflags && iflags[0]) return;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
+        x[i] = omega * dinv[i] * b[i];
+}
+
+__global__ __launch_bounds__(NT) void k_mg_smooth(int32_t n, const int32_t* __restrict__ col,
+                                                  const double* __restrict__ val,
+                                                  const double* __restrict__ dinv,
+                                                  const double* __restrict__ b, double omega,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ y, const int* iflags)
+{
+    if (iflags && iflags[0]) return;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
+        y[i] = x[i] + omega * dinv[i] * (b[i] - ell5(i, n, col, val, x));
+}
+
+__global__ __launch_bounds__(NT) void k_mg_resid(int32_t n, const int32_t* __restrict__ col,
+                                                 const double* __restrict__ val,
+                                                 const double* __restrict__ b,
+                                                 const double* __restrict__ x,
+                                                 double* __restrict__ r, const int* iflags)
+{
+    if (iflags && iflags[0]) return;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
+        r[i] = b[i] - ell5(i, n, col, val, x);
+}
+
+// Restriction, first half: for each coarse triangle p and each of its edges
+// l, the sum over the nine fine edges e inside p of s_e psi_l(m_e) r[e],
+// where psi_l = 1 - 2 lambda_l is the coarse edge-midpoint basis function,
+// m_e the fine edge midpoint and s_e = 1/2 on halves of a coarse edge shared
+// with a second coarse triangle (the prolongation averages the two sides
+// there), 1 otherwise. The barycentric coordinates of the fine midpoints do
+// not depend on the shape of p, so the weights are the constants below.
+__global__ __launch_bounds__(NT) void k_mg_restrict(int32_t nEc, const int32_t* __restrict__ rows9,
+                                                    const int32_t* __restrict__ ecode_c,
+                                                    const double* __restrict__ rf,
+                                                    double* __restrict__ t, const int* iflags)
+{
+    if (iflags && iflags[0]) return;
+    for (int32_t p = blockIdx.x * NT + threadIdx.x; p < nEc; p += gridDim.x * NT) {
+        double v[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int32_t row = rows9[(int64_t)k * nEc + p];
+            v[k] = row >= 0 ? rf[row] : 0.0;
+        }
+        const int32_t code = ecode_c[p];
+        double s[3];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) s[e] = PHF_CODE_TYPE(code, e) == 0 ? 0.5 : 1.0;
+        double acc[3];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            // centre edges: parallel to l -> 0, the other two -> 1/2
+            double a = 0.5 * (v[(l + 1) % 3] + v[(l + 2) % 3]);
+            // halves at vertex i of edge e: psi_e = 1, psi_i = -1/2, psi_(third) = 1/2
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int e1 = (i + 1) % 3, e2 = (i + 2) % 3;
+                const double h1 = s[e1] * v[3 + 2 * i], h2 = s[e2] * v[4 + 2 * i];
+                if (l == i) a += -0.5 * (h1 + h2);
+                else if (l == e1) a += h1 + 0.5 * h2;
+                else a += 0.5 * h1 + h2;
+            }
+            acc[l] = a;
+        }
+        t[3 * (int64_t)p] = acc[0];
+        t[3 * (int64_t)p + 1] = acc[1];
+        t[3 * (int64_t)p + 2] = acc[2];
+    }
+}
+
+// Restriction, second half: coarse row c sums its edge's entries from T+
+// and T- (in that order).
+__global__ __launch_bounds__(NT) void k_mg_collect(int32_t nc, const int2* __restrict__ sel,
+                                                   const double* __restrict__ t,
+                                                   double* __restrict__ bc, const int* iflags)
+{
+    if (iflags && iflags[0]) return;
+    for (int32_t c = blockIdx.x * NT + threadIdx.x; c < nc; c += gridDim.x * NT) {
+        const int2 q = sel[c];
+        bc[c] = q.y >= 0 ? t[q.x] + t[q.y] : t[q.x];
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_mg_prolong(int32_t n, const int32_t* __restrict__ P_col,
+                                                   const double* __restrict__ P_val,
+                                                   const double* __restrict__ xc,
+                                                   double* __restrict__ x, const int* iflags)
+{
+    if (iflags && iflags[0]) return;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
+        x[i] += ell5(i, n, P_col, P_val, xc);
+}
+
+__global__ __launch_bounds__(NT) void k_mg_coarse(int32_t n, const double* __restrict__ Ainv,
+                                                  const double* __restrict__ b,
+                                                  double* __restrict__ x, const int* iflags)
+{
+    if (iflags && iflags[0]) return;
+    for (int32_t i = threadIdx.x; i < n; i += NT) {
+        double s = 0.0;
+        for (int32_t j = 0; j < n; ++j) s = fma(Ainv[(int64_t)i * n + j], b[j], s);
+        x[i] = s;
+    }
+}
+
+// z = x; partial sums of r.z (fixed order within the block).
+__global__ __launch_bounds__(NT) void k_mg_finish(int32_t n, const double* __restrict__ x,
+                                                  const double* __restrict__ r,
+                                                  double* __restrict__ z,
+                                                  double* __restrict__ part, const int* iflags)
+{
+    if (iflags && iflags[0]) return;
+    __shared__ double sh[NT / 64];
+    double s = 0.0;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+        const double zi = x[i];
+        z[i] = zi;
+        s = fma(r[i], zi, s);
+    }
+    const double t = phf_block_sum_f64<NT>(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+unsigned grid_for(int32_t n) { return (unsigned)std::min<int64_t>(std::max<int64_t>(nblk(n), 1), 1024); }
+
+// Trace names carry the level ("k_mg_smooth.L9"), counted from the coarsest
+// mesh, so per-launch byte counts can be attributed to a level.
+enum { NM_SMOOTH0, NM_SMOOTH, NM_RESID, NM_RESTRICT, NM_COLLECT, NM_PROLONG, NM_FINISH, NM_COUNT };
+struct mg_names {
+    char s[NM_COUNT][PHF_MG_MAX_LEVELS][32];
+    mg_names()
+    {
+        static const char* base[NM_COUNT] = {"k_mg_smooth0", "k_mg_smooth", "k_mg_resid",
+                                             "k_mg_restrict", "k_mg_collect", "k_mg_prolong",
+                                             "k_mg_finish"};
+        for (int k = 0; k < NM_COUNT; ++k)
+            for (int l = 0; l < PHF_MG_MAX_LEVELS; ++l)
+                snprintf(s[k][l], sizeof(s[k][l]), "%s.L%d", base[k], l);
+    }
+};
+const char* mg_name(int kind, int level)
+{
+    static const mg_names names;  // initialised once, thread-safe
+    return names.s[kind][level];
+}
+
+}  // namespace
+
+int32_t phf_mg_levels(const phf_mesh* mesh)
+{
+    int32_t n = 0;
+    for (const phf_mesh* m = mesh; m; m = m->parent) ++n;
+    return n;
+}
+
+void phf_mg_destroy(phf_mg* mg)
+{
+    if (!mg) return;
+    for (int l = 0; l < mg->nlev; ++l) {
+        phf_mg_level& L = mg->lev[l];
+        if (L.own_ns && L.ns) phf_ns_destroy(L.ns);
+        double* d[] = {L.K, L.M, L.C, L.F, L.bD, L.aT, L.x, L.y, L.b, L.r, L.P_val, L.t};
+        for (double* p : d) phf_dfree(p);
+        phf_dfree(L.P_col);
+        phf_dfree(L.rows9);
+        phf_dfree(L.sel);
+    }
+    phf_dfree(mg->cinv);
+    phf_dfree(mg->cwork);
+    delete mg;
+}
+
+int phf_mg_create(phf_ns* fine, phf_mg** out)
+{
+    phf_mesh* fm = fine->mesh;
+    phf_ctx* ctx = fm->ctx;
+    *out = nullptr;
+    const int32_t nlev = phf_mg_levels(fm);
+    if (nlev < 2 || nlev > PHF_MG_MAX_LEVELS)
+        return phf_set_error(ctx, PHF_EINVAL,
+                             "multigrid needs a mesh made by phf_mesh_refine (1..%d refinements)",
+                             PHF_MG_MAX_LEVELS - 1);
+    phf_mg* mg = new (std::nothrow) phf_mg;
+    if (!mg) return phf_set_error(ctx, PHF_ENOMEM, "host allocation failed");
+    mg->nlev = nlev;
+    auto body = [&]() -> int {
+        phf_mesh* m = fm;
+        for (int l = nlev - 1; l >= 0; --l, m = m->parent) mg->lev[l].mesh = m;
+        for (int l = 0; l < nlev; ++l) {
+            phf_mg_level& L = mg->lev[l];
+            phf_mesh* ms = L.mesh;
+            if (l == nlev - 1) {
+                L.ns = fine;
+                L.own_ns = false;
+            } else {
+                TRY(phf_ns_create(ms, &L.ns));
+                L.own_ns = true;
+                const size_t e9 = 9 * (size_t)ms->nE;
+                TRY(phf_dmalloc(ctx, &L.K, e9, "multigrid K"));
+                TRY(phf_dmalloc(ctx, &L.M, e9, "multigrid M"));
+                TRY(phf_dmalloc(ctx, &L.C, (size_t)ms->nnz_C, "multigrid C"));
+                TRY(phf_dmalloc(ctx, &L.F, 3 * (size_t)ms->nE, "multigrid F"));
+                TRY(phf_dmalloc(ctx, &L.bD, (size_t)ms->L, "multigrid bD"));
+                TRY(phf_dmalloc(ctx, &L.aT, (size_t)ms->nE, "multigrid coefficient"));
+            }
+            L.nf = ms->n_free;
+            const size_t nf = std::max<int32_t>(L.nf, 1);
+            TRY(phf_dmalloc(ctx, &L.x, nf, "multigrid x"));
+            TRY(phf_dmalloc(ctx, &L.y, nf, "multigrid y"));
+            TRY(phf_dmalloc(ctx, &L.b, nf, "multigrid b"));
+            TRY(phf_dmalloc(ctx, &L.r, nf, "multigrid r"));
+            if (l == 0) continue;
+            // prolongation from level l-1
+            phf_mg_level& Cl = mg->lev[l - 1];
+            TRY(phf_dmalloc(ctx, &L.P_col, 5 * nf, "multigrid P columns"));
+            TRY(phf_dmalloc(ctx, &L.P_val, 5 * nf, "multigrid P values"));
+            if (L.nf > 0)
+                PHF_LAUNCH(ctx, "k_mg_prolong_build", k_mg_prolong_build, nblk(L.nf), NT, 0, L.nf,
+                           Cl.mesh->nE, ms->red_edge, ms->edge_elems, ms->edge_nodes, ms->xy,
+                           Cl.mesh->exy, Cl.mesh->elem_edges, Cl.mesh->red_row, L.P_col, L.P_val);
+            // restriction tables
+            const int32_t nEc = Cl.mesh->nE, nc = Cl.mesh->n_free;
+            TRY(phf_dmalloc(ctx, &L.rows9, 9 * (size_t)nEc, "multigrid restriction rows"));
+            TRY(phf_dmalloc(ctx, &L.t, 3 * (size_t)nEc, "multigrid restriction sums"));
+            TRY(phf_dmalloc(ctx, &Cl.sel, (size_t)std::max(nc, 1), "multigrid restriction map"));
+            PHF_LAUNCH(ctx, "k_mg_rows9", k_mg_rows9, nblk(nEc), NT, 0, nEc, ms->elem_edges,
+                       ms->red_row, L.rows9);
+            if (nc > 0)
+                PHF_LAUNCH(ctx, "k_mg_sel", k_mg_sel, nblk(nc), NT, 0, nc, Cl.mesh->red_edge,
+                           Cl.mesh->edge_elems, Cl.mesh->led, Cl.mesh->ledTN, Cl.sel);
+        }
+        mg->n0 = mg->lev[0].nf;
+        if (mg->n0 > 0 && mg->n0 <= PHF_MG_DENSE_MAX) {
+            TRY(phf_dmalloc(ctx, &mg->cinv, (size_t)mg->n0 * mg->n0, "coarse inverse"));
+            TRY(phf_dmalloc(ctx, &mg->cwork, (size_t)mg->n0 * mg->n0, "coarse work"));
+        }
+        return PHF_OK;
+    };
+    int rc = body();
+    if (rc) {
+        (void)hipStreamSynchronize(ctx->stream);
+        phf_mg_destroy(mg);
+        return rc;
+    }
+    *out = mg;
+    return PHF_OK;
+}
+
+int phf_mg_numeric(phf_mg* mg, const phf_coeffs* co, double cK, double cM)
+{
+    phf_ctx* ctx = mg->lev[0].mesh->ctx;
+    const int top = mg->nlev - 1;
+    // triangle coefficients, finest to coarsest
+    const double* aT_prev = co->a_T;
+    for (int l = top - 1; l >= 0; --l) {
+        phf_mg_level& L = mg->lev[l];
+        if (aT_prev) {
+            PHF_LAUNCH(ctx, "k_mg_coef", k_mg_coef, nblk(L.mesh->nE), NT, 0, L.mesh->nE, aT_prev,
+                       L.aT);
+            aT_prev = L.aT;
+        }
+    }
+    for (int l = 0; l < top; ++l) {
+        phf_mg_level& L = mg->lev[l];
+        phf_coeffs c = *co;
+        c.a_T = co->a_T ? L.aT : nullptr;
+        c.p[0] = c.p[1] = 0.0;
+        phf_data d{};
+        phf_system s{};
+        s.K = L.K;
+        s.M = L.M;
+        s.C = L.C;
+        s.F = L.F;
+        s.bD = L.bD;
+        TRY(phf_assemble_impl(L.mesh, &c, &d, &s));
+        TRY(phf_ns_operator(L.ns, L.K, L.M, L.C, cK, cM));
+    }
+    if (mg->cinv) {
+        const int32_t n0 = mg->n0;
+        PHF_LAUNCH(ctx, "k_mg_dense", k_mg_dense, nblk(n0), NT, 0, n0, mg->lev[0].ns->ell_col,
+                   mg->lev[0].ns->ell_val, mg->cinv);
+        PHF_LAUNCH(ctx, "k_mg_gj", k_mg_gj, 1, 1024, 0, n0, mg->cinv, mg->cwork);
+    }
+    return PHF_OK;
+}
+
+namespace {
+int vcycle(phf_mg* mg, int l, const int* iflags)
+{
+    phf_mg_level& L = mg->lev[l];
+    phf_ctx* ctx = L.mesh->ctx;
+    const int32_t n = L.nf;
+    if (n == 0) return PHF_OK;
+    const unsigned g = grid_for(n);
+    phf_ns* ns = L.ns;
+    if (l == 0) {
+        if (mg->cinv) {
+            PHF_LAUNCH(ctx, "k_mg_coarse", k_mg_coarse, 1, NT, 0, n, mg->cinv, L.b, L.x, iflags);
+        } else {
+            // no dense inverse: many damped Jacobi sweeps
+            PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0, g, NT, 0, n, ns->dinv, L.b,
+                       mg->omega, L.x, iflags);
+            for (int s = 0; s < 40; ++s) {
+                PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth, g, NT, 0, n, ns->ell_col, ns->ell_val,
+                           ns->dinv, L.b, mg->omega, L.x, L.y, iflags);
+                std::swap(L.x, L.y);
+            }
+        }
+        return PHF_OK;
+    }
+    // pre-smoothing from x = 0
+    PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0, g, NT, 0, n, ns->dinv, L.b, mg->omega,
+               L.x, iflags);
+    for (int s = 1; s < mg->nu; ++s) {
+        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth, g, NT, 0, n, ns->ell_col, ns->ell_val,
+                   ns->dinv, L.b, mg->omega, L.x, L.y, iflags);
+        std::swap(L.x, L.y);
+    }
+    phf_mg_level& C = mg->lev[l - 1];
+    if (C.nf > 0) {
+        PHF_LAUNCH(ctx, mg_name(NM_RESID, l), k_mg_resid, g, NT, 0, n, ns->ell_col, ns->ell_val, L.b, L.x,
+                   L.r, iflags);
+        PHF_LAUNCH(ctx, mg_name(NM_RESTRICT, l), k_mg_restrict, grid_for(C.mesh->nE), NT, 0,
+                   C.mesh->nE, L.rows9, C.mesh->ecode, L.r, L.t, iflags);
+        PHF_LAUNCH(ctx, mg_name(NM_COLLECT, l), k_mg_collect, grid_for(C.nf), NT, 0, C.nf, C.sel,
+                   L.t, C.b, iflags);
+        TRY(vcycle(mg, l - 1, iflags));
+        PHF_LAUNCH(ctx, mg_name(NM_PROLONG, l), k_mg_prolong, g, NT, 0, n, L.P_col, L.P_val, C.x, L.x,
+                   iflags);
+    }
+    for (int s = 0; s < mg->nu; ++s) {
+        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth, g, NT, 0, n, ns->ell_col, ns->ell_val,
+                   ns->dinv, L.b, mg->omega, L.x, L.y, iflags);
+        std::swap(L.x, L.y);
+    }
+    return PHF_OK;
+}
+}  // namespace
+
+int phf_mg_apply(phf_mg* mg, const double* r, double* z, double* part_rz, const int* iflags)
+{
+    const int top = mg->nlev - 1;
+    phf_mg_level& F = mg->lev[top];
+    phf_ctx* ctx = F.mesh->ctx;
+    if (F.nf == 0) return PHF_OK;
+    // the finest right-hand side is the CG residual itself
+    double* saved_b = F.b;
+    F.b = const_cast<double*>(r);
+    int rc = vcycle(mg, top, iflags);
+    F.b = saved_b;
+    if (rc) return rc;
+    PHF_LAUNCH(ctx, mg_name(NM_FINISH, top), k_mg_finish, grid_for(F.nf), NT, 0, F.nf, F.x, r, z, part_rz,
+               iflags);
+    return PHF_OK;
+}

@@ -20,8 +20,12 @@
 
 #include "phf_internal.h"
 
+struct phf_mg;
+
 struct phf_ns {
     phf_mesh* mesh = nullptr;
+    phf_mg* mg = nullptr;         // multilevel preconditioner (owned)
+    bool mg_on = false;           // use it (else Jacobi)
     int32_t nE = 0, nf = 0, L = 0, nbv = 0;
     // symbolic (per mesh)
     int32_t* elem_red = nullptr;  // 3 nE: reduced row of local edge l (-1 Dirichlet)
@@ -70,5 +74,9 @@ int phf_ns_zero_w(phf_ns* ns);
 // Host convergence loop: cg_start + batches of check_every iterations.
 int phf_ns_cg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_every,
                     int32_t* iters_out, double* relres_out, int* converged);
+// Chooses Jacobi or the multilevel preconditioner (built on first use, its
+// coarse operators recomputed for A = cK K + cM M and coeffs' a_T).
+int phf_ns_set_precond(phf_ns* ns, int32_t precond, int32_t sweeps, double omega,
+                       const phf_coeffs* co, double cK, double cM);
 // The mesh's cached workspace (created on first use).
 int phf_ns_get(phf_mesh* mesh, phf_ns** out);

@@ -1,6 +1,7 @@
 // Null-space conjugate-gradient solve of the saddle system of Section 3.5
 // (see phf_solver.h for the reduction) and the phf_solve entry point.
 #include "phf_device.h"
+#include "phf_mg.h"
 #include "phf_solver.h"
 
 namespace {
@@ -210,6 +211,7 @@ __device__ inline double block_reduce_partials(const double* __restrict__ part, 
     return phf_block_sum_f64<NT>(s, sh);
 }
 
+template <bool JAC>
 __global__ __launch_bounds__(NT) void k_cg_init(int32_t nf, const int32_t* __restrict__ col,
                                                 const double* __restrict__ val,
                                                 const double* __restrict__ dinv,
@@ -223,12 +225,14 @@ __global__ __launch_bounds__(NT) void k_cg_init(int32_t nf, const int32_t* __res
     double s_rz = 0.0, s_rr = 0.0, s_bb = 0.0;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
         double ri = b[i] - ell_row(i, nf, col, val, w);
-        double zi = dinv[i] * ri;
         r[i] = ri;
-        z[i] = zi;
         p[i] = 0.0;
         q[i] = 0.0;
-        s_rz = fma(ri, zi, s_rz);
+        if (JAC) {
+            double zi = dinv[i] * ri;
+            z[i] = zi;
+            s_rz = fma(ri, zi, s_rz);
+        }
         s_rr = fma(ri, ri, s_rr);
         s_bb = fma(b[i], b[i], s_bb);
     }
@@ -236,7 +240,7 @@ __global__ __launch_bounds__(NT) void k_cg_init(int32_t nf, const int32_t* __res
     double t1 = phf_block_sum_f64<NT>(s_rr, sh);
     double t2 = phf_block_sum_f64<NT>(s_bb, sh);
     if (threadIdx.x == 0) {
-        part[P_RZ0 * MAXB + blockIdx.x] = t0;
+        if (JAC) part[P_RZ0 * MAXB + blockIdx.x] = t0;
         part[P_RR * MAXB + blockIdx.x] = t1;
         part[P_BB * MAXB + blockIdx.x] = t2;
     }
@@ -295,6 +299,7 @@ __global__ __launch_bounds__(NT) void k_cg_dir(int32_t nf, int32_t it, int32_t n
     if (threadIdx.x == 0) part[P_PQ * MAXB + blockIdx.x] = t;
 }
 
+template <bool JAC>
 __global__ __launch_bounds__(NT) void k_cg_upd(int32_t nf, int32_t it, int32_t nb,
                                                double* __restrict__ w, double* __restrict__ r,
                                                double* __restrict__ z,
@@ -312,16 +317,18 @@ __global__ __launch_bounds__(NT) void k_cg_upd(int32_t nf, int32_t it, int32_t n
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
         w[i] = fma(alpha, p[i], w[i]);
         const double ri = fma(-alpha, q[i], r[i]);
-        const double zi = dinv[i] * ri;
         r[i] = ri;
-        z[i] = zi;
-        s_rz = fma(ri, zi, s_rz);
+        if (JAC) {
+            const double zi = dinv[i] * ri;
+            z[i] = zi;
+            s_rz = fma(ri, zi, s_rz);
+        }
         s_rr = fma(ri, ri, s_rr);
     }
     const double t0 = phf_block_sum_f64<NT>(s_rz, sh);
     const double t1 = phf_block_sum_f64<NT>(s_rr, sh);
     if (threadIdx.x == 0) {
-        part[((it & 1) ? P_RZ0 : P_RZ1) * MAXB + blockIdx.x] = t0;
+        if (JAC) part[((it & 1) ? P_RZ0 : P_RZ1) * MAXB + blockIdx.x] = t0;
         part[P_RR * MAXB + blockIdx.x] = t1;
         if (blockIdx.x == 0) iflags[1] += 1;
     }
@@ -400,6 +407,7 @@ __global__ __launch_bounds__(NT) void k_ns_recover_mu(int32_t L, const int32_t* 
 void phf_ns_destroy(phf_ns* ns)
 {
     if (!ns) return;
+    if (ns->mg) phf_mg_destroy(ns->mg);
     phf_dfree(ns->elem_red); phf_dfree(ns->elem_row); phf_dfree(ns->ell_col);
     phf_dfree(ns->ell_src); phf_dfree(ns->row_h); phf_dfree(ns->B); phf_dfree(ns->Ablk);
     phf_dfree(ns->ell_val); phf_dfree(ns->dinv); phf_dfree(ns->kv); phf_dfree(ns->cs);
@@ -508,10 +516,16 @@ int phf_ns_cg_start(phf_ns* ns, double rtol)
         PHF_HIP(ctx, hipMemsetAsync(ns->iflags, 0, 4 * sizeof(int), ctx->stream));
         return PHF_OK;
     }
-    PHF_LAUNCH(ctx, "k_cg_init", k_cg_init, ns->nbv, NT, 0, ns->nf, ns->ell_col, ns->ell_val,
-               ns->dinv, ns->b, ns->w, ns->r, ns->z, ns->p, ns->q, ns->part);
+    if (ns->mg && ns->mg_on)
+        PHF_LAUNCH(ctx, "k_cg_init", k_cg_init<false>, ns->nbv, NT, 0, ns->nf, ns->ell_col,
+                   ns->ell_val, ns->dinv, ns->b, ns->w, ns->r, ns->z, ns->p, ns->q, ns->part);
+    else
+        PHF_LAUNCH(ctx, "k_cg_init", k_cg_init<true>, ns->nbv, NT, 0, ns->nf, ns->ell_col,
+                   ns->ell_val, ns->dinv, ns->b, ns->w, ns->r, ns->z, ns->p, ns->q, ns->part);
     PHF_LAUNCH(ctx, "k_cg_init_final", k_cg_init_final, 1, NT, 0, ns->part, ns->nbv, rtol * rtol,
                ns->scal, ns->iflags);
+    if (ns->mg && ns->mg_on)
+        TRY(phf_mg_apply(ns->mg, ns->r, ns->z, ns->part + P_RZ0 * MAXB, ns->iflags));
     return PHF_OK;
 }
 
@@ -525,8 +539,15 @@ int phf_ns_cg_iterate(phf_ns* ns, int32_t iters)
         ns->next_it = it + 1 >= 2 ? 2 + ((it + 1) & 1) : it + 1;
         PHF_LAUNCH(ctx, "k_cg_dir", k_cg_dir, ns->nbv, NT, 0, ns->nf, it, ns->nbv, ns->ell_col,
                    ns->ell_val, ns->z, ns->p, ns->q, ns->part, ns->scal, ns->iflags);
-        PHF_LAUNCH(ctx, "k_cg_upd", k_cg_upd, ns->nbv, NT, 0, ns->nf, it, ns->nbv, ns->w, ns->r,
-                   ns->z, ns->p, ns->q, ns->dinv, ns->part, ns->iflags);
+        if (ns->mg && ns->mg_on) {
+            PHF_LAUNCH(ctx, "k_cg_upd", k_cg_upd<false>, ns->nbv, NT, 0, ns->nf, it, ns->nbv, ns->w,
+                       ns->r, ns->z, ns->p, ns->q, ns->dinv, ns->part, ns->iflags);
+            TRY(phf_mg_apply(ns->mg, ns->r, ns->z,
+                             ns->part + ((it & 1) ? P_RZ0 : P_RZ1) * MAXB, ns->iflags));
+        } else {
+            PHF_LAUNCH(ctx, "k_cg_upd", k_cg_upd<true>, ns->nbv, NT, 0, ns->nf, it, ns->nbv, ns->w,
+                       ns->r, ns->z, ns->p, ns->q, ns->dinv, ns->part, ns->iflags);
+        }
     }
     PHF_LAUNCH(ctx, "k_cg_check", k_cg_check, 1, NT, 0, ns->nbv, ns->part, ns->scal, ns->iflags);
     return PHF_OK;
@@ -573,6 +594,19 @@ int phf_ns_cg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_eve
     return PHF_OK;
 }
 
+int phf_ns_set_precond(phf_ns* ns, int32_t precond, int32_t sweeps, double omega,
+                       const phf_coeffs* co, double cK, double cM)
+{
+    ns->mg_on = false;
+    if (precond != PHF_PRECOND_MULTIGRID) return PHF_OK;
+    if (!ns->mg) TRY(phf_mg_create(ns, &ns->mg));
+    ns->mg->nu = sweeps > 0 ? sweeps : 2;
+    ns->mg->omega = omega > 0 ? omega : 0.7;
+    TRY(phf_mg_numeric(ns->mg, co, cK, cM));
+    ns->mg_on = true;
+    return PHF_OK;
+}
+
 int phf_ns_get(phf_mesh* mesh, phf_ns** out)
 {
     if (!mesh->ns) TRY(phf_ns_create(mesh, &mesh->ns));
@@ -602,18 +636,22 @@ extern "C" int phf_solve(phf_mesh* mesh, const phf_coeffs* co, const phf_system*
     if (co->p[0] != 0.0 || co->p[1] != 0.0)
         return phf_set_error(ctx, PHF_EINVAL,
                              "phf_solve: the conjugate-gradient method needs p = 0 (symmetric system)");
-    phf_solver_opts o = {PHF_SOLVER_NULLSPACE_CG, 20000, 1e-10, 8, 0};
-    if (opts) {
-        o = *opts;
-        if (o.max_iter <= 0) o.max_iter = 20000;
-        if (o.rtol <= 0) o.rtol = 1e-10;
-        if (o.check_every <= 0) o.check_every = 8;
-    }
+    phf_solver_opts o{};
+    o.method = PHF_SOLVER_NULLSPACE_CG;
+    if (opts) o = *opts;
+    if (o.max_iter <= 0) o.max_iter = 20000;
+    if (o.rtol <= 0) o.rtol = 1e-10;
+    // a V-cycle iteration is long enough that testing after each one costs
+    // less than the launches it would otherwise queue past convergence
+    if (o.check_every <= 0) o.check_every = o.precond == PHF_PRECOND_MULTIGRID ? 1 : 8;
     if (o.method != PHF_SOLVER_NULLSPACE_CG)
         return phf_set_error(ctx, PHF_EINVAL, "phf_solve: unknown method %d", o.method);
+    if (o.precond != PHF_PRECOND_JACOBI && o.precond != PHF_PRECOND_MULTIGRID)
+        return phf_set_error(ctx, PHF_EINVAL, "phf_solve: unknown preconditioner %d", o.precond);
     phf_ns* ns = nullptr;
     TRY(phf_ns_get(mesh, &ns));
     TRY(phf_ns_operator(ns, sys->K, sys->M, sys->C, 1.0, co->delta));
+    TRY(phf_ns_set_precond(ns, o.precond, o.mg_sweeps, o.mg_omega, co, 1.0, co->delta));
     TRY(phf_ns_rhs(ns, sys->F, sys->bD));
     TRY(phf_ns_zero_w(ns));
     int32_t iters = 0;

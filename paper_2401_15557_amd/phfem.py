@@ -26,11 +26,14 @@ PHF_FN_GRAD_SIN_COS, PHF_FN_GRAD_SIN_SIN = 4, 5
 PHF_FN_PAPER_U, PHF_FN_PAPER_F, PHF_FN_PAPER_FLUX = 6, 7, 8
 PHF_FN_EDGE_ARRAY = 100
 PHF_SOLVER_NULLSPACE_CG = 0
+PHF_PRECOND_JACOBI, PHF_PRECOND_MULTIGRID = 0, 1
 
 EXPORTED = (
-    "phf_create", "phf_destroy", "phf_set_stream", "phf_synchronize", "phf_status_str",
-    "phf_last_error", "phf_version", "phf_trace_enable", "phf_trace_reset", "phf_trace_query",
-    "phf_trace_dump", "phf_mesh_create", "phf_mesh_destroy", "phf_mesh_get_info",
+    "phf_create", "phf_destroy", "phf_set_stream", "phf_synchronize", "phf_mem_stats",
+    "phf_release_cache", "phf_status_str",
+    "phf_last_error", "phf_version", "phf_trace_enable", "phf_trace_filter", "phf_trace_reset", "phf_trace_query",
+    "phf_trace_dump", "phf_mesh_create", "phf_mesh_destroy", "phf_mesh_refine", "phf_mesh_geometry",
+    "phf_mesh_get_info",
     "phf_mesh_topology", "phf_mesh_pattern", "phf_assemble", "phf_spmv", "phf_solve",
     "phf_cn_create", "phf_cn_set_state", "phf_cn_run", "phf_cn_get_state", "phf_cn_destroy",
 )
@@ -78,7 +81,8 @@ class phf_system(ctypes.Structure):
 class phf_solver_opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("check_every", ctypes.c_int32),
-                ("saddle_residual", ctypes.c_int32)]
+                ("saddle_residual", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("mg_sweeps", ctypes.c_int32), ("mg_omega", ctypes.c_double)]
 
 
 class phf_solve_stats(ctypes.Structure):
@@ -88,7 +92,8 @@ class phf_solve_stats(ctypes.Structure):
 
 class phf_cn_opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("iters_per_step", ctypes.c_int32)]
+                ("iters_per_step", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("mg_sweeps", ctypes.c_int32), ("mg_omega", ctypes.c_double)]
 
 
 _lib = None
@@ -98,16 +103,21 @@ _SIGS = {
     "phf_destroy": [_VP],
     "phf_set_stream": [_VP, _VP],
     "phf_synchronize": [_VP],
+    "phf_mem_stats": [_VP, ctypes.POINTER(_I64), ctypes.POINTER(_I64)],
+    "phf_release_cache": [_VP],
     "phf_status_str": [ctypes.c_int],
     "phf_last_error": [_VP],
     "phf_version": [],
     "phf_trace_enable": [_VP, ctypes.c_int],
+    "phf_trace_filter": [_VP, ctypes.c_char_p],
     "phf_trace_reset": [_VP],
     "phf_trace_query": [_VP, ctypes.c_char_p, ctypes.POINTER(_I64), ctypes.POINTER(_D)],
     "phf_trace_dump": [_VP, ctypes.c_char_p, ctypes.c_size_t],
     "phf_mesh_create": [_VP, _VP, _I32, _VP, _I32, _VP, _I32, _VP, _I32, ctypes.c_int,
                         ctypes.POINTER(_VP)],
     "phf_mesh_destroy": [_VP],
+    "phf_mesh_refine": [_VP, ctypes.POINTER(_VP)],
+    "phf_mesh_geometry": [_VP, _VP, _VP, _VP, _VP, ctypes.c_int],
     "phf_mesh_get_info": [_VP, ctypes.POINTER(phf_mesh_info)],
     "phf_mesh_topology": [_VP] + [_VP] * 9 + [ctypes.c_int],
     "phf_mesh_pattern": [_VP] + [_VP] * 6 + [ctypes.c_int],
@@ -202,12 +212,28 @@ def phf_synchronize(ctx):
     _call("phf_synchronize", ctx, ctx)
 
 
+def phf_mem_stats(ctx):
+    """(live_bytes, cached_bytes) of the context's device memory pool."""
+    live, cached = _I64(), _I64()
+    _call("phf_mem_stats", ctx, ctx, ctypes.byref(live), ctypes.byref(cached))
+    return live.value, cached.value
+
+
+def phf_release_cache(ctx):
+    _call("phf_release_cache", ctx, ctx)
+
+
 def phf_last_error(ctx):
     return load().phf_last_error(ctx).decode()
 
 
 def phf_trace_enable(ctx, on=True):
     _call("phf_trace_enable", ctx, ctx, 1 if on else 0)
+
+
+def phf_trace_filter(ctx, kernel=None):
+    """Trace only launches named ``kernel`` (None: every launch)."""
+    _call("phf_trace_filter", ctx, ctx, kernel.encode() if kernel else None)
 
 
 def phf_trace_reset(ctx):
@@ -244,6 +270,19 @@ def phf_mesh_create(ctx, xy, elem, dirichlet, neumann, memspace=PHF_HOST):
 
 def phf_mesh_destroy(mesh):
     _call("phf_mesh_destroy", None, mesh)
+
+
+def phf_mesh_refine(mesh):
+    """Red-refined device mesh (Listing 4 numbering); keeps a reference to mesh."""
+    h = _VP()
+    _call("phf_mesh_refine", None, mesh, ctypes.byref(h))
+    return h.value
+
+
+def phf_mesh_geometry(mesh, xy=None, elem=None, dirichlet=None, neumann=None,
+                      memspace=PHF_DEVICE):
+    _call("phf_mesh_geometry", None, mesh, _ptr(xy), _ptr(elem), _ptr(dirichlet), _ptr(neumann),
+          int(memspace))
 
 
 def phf_mesh_get_info(mesh):
@@ -307,10 +346,12 @@ def phf_spmv(ctx, nrows, rowptr, col, val, alpha, x, beta, y):
           _ptr(x), float(beta), _ptr(y))
 
 
-def phf_solve(mesh, coeffs, system, U, Lam=None, rtol=1e-10, max_iter=20000, check_every=8,
-              saddle_residual=False, raise_on_noconv=True):
+def phf_solve(mesh, coeffs, system, U, Lam=None, rtol=1e-10, max_iter=20000, check_every=0,
+              saddle_residual=False, raise_on_noconv=True, precond=PHF_PRECOND_JACOBI,
+              mg_sweeps=0, mg_omega=0.0):
     o = phf_solver_opts(PHF_SOLVER_NULLSPACE_CG, int(max_iter), float(rtol), int(check_every),
-                        1 if saddle_residual else 0)
+                        1 if saddle_residual else 0, int(precond), int(mg_sweeps),
+                        float(mg_omega))
     st = phf_solve_stats()
     rc = load().phf_solve(mesh, ctypes.byref(coeffs), ctypes.byref(system), ctypes.byref(o),
                           _ptr(U), _ptr(Lam), ctypes.byref(st))
@@ -319,9 +360,11 @@ def phf_solve(mesh, coeffs, system, U, Lam=None, rtol=1e-10, max_iter=20000, che
     return st
 
 
-def phf_cn_create(mesh, coeffs, k, rtol=1e-10, max_iter=5000, iters_per_step=64):
+def phf_cn_create(mesh, coeffs, k, rtol=1e-10, max_iter=5000, iters_per_step=32,
+                  precond=PHF_PRECOND_JACOBI, mg_sweeps=0, mg_omega=0.0):
     h = _VP()
-    o = phf_cn_opts(float(rtol), int(max_iter), int(iters_per_step))
+    o = phf_cn_opts(float(rtol), int(max_iter), int(iters_per_step), int(precond),
+                    int(mg_sweeps), float(mg_omega))
     _call("phf_cn_create", None, mesh, ctypes.byref(coeffs), float(k), ctypes.byref(o),
           ctypes.byref(h))
     return h.value
@@ -382,13 +425,20 @@ class Context:
 
 
 class Mesh:
-    """Device mesh built from a meshgen.Mesh (host arrays)."""
+    """Device mesh built from a meshgen.Mesh (host arrays), or by refinement."""
 
-    def __init__(self, ctx: Context, m):
+    def __init__(self, ctx: Context, m=None, handle=None, parent=None):
         self.ctx = ctx
-        self.handle = phf_mesh_create(ctx.handle, m.coords, m.elements, m.dirichlet, m.neumann,
-                                      PHF_HOST)
+        self.parent = parent
+        if handle is None:
+            handle = phf_mesh_create(ctx.handle, m.coords, m.elements, m.dirichlet, m.neumann,
+                                     PHF_HOST)
+        self.handle = handle
         self.info = phf_mesh_get_info(self.handle)
+
+    def refine(self):
+        """One device red refinement; the result keeps this mesh alive."""
+        return Mesh(self.ctx, handle=phf_mesh_refine(self.handle), parent=self)
 
     def close(self):
         if self.handle:
@@ -400,6 +450,15 @@ class Mesh:
             self.close()
         except Exception:
             pass
+
+    def geometry(self):
+        """(xy, elements, dirichlet, neumann) copied to host numpy arrays."""
+        import numpy as np
+        i = self.info
+        xy = np.empty((i.nC, 2)); el = np.empty((i.nE, 3), np.int32)
+        d = np.empty((i.nD, 2), np.int32); n = np.empty((i.nN, 2), np.int32)
+        phf_mesh_geometry(self.handle, xy, el, d, n, PHF_HOST)
+        return xy, el, d, n
 
     def topology(self):
         """Topology tables as host numpy arrays."""

@@ -195,3 +195,56 @@ def test_mesh_errors(ctx):
     # the context is still usable after errors
     dm = phfem.Mesh(ctx, m)
     assert dm.info.nE == m.nE
+
+
+@pytest.mark.parametrize("base", ["paper", "lshape"])
+def test_refine_parity(ctx, oracle, base):
+    """Device red refinement against the oracle's (Listing 4): coordinates,
+    elements and boundary lists bit for bit, then the refined mesh's topology."""
+    from paper_2401_15557_amd import phfem
+    m = G.paper_square(0) if base == "paper" else G.lshape(0)
+    dm = phfem.Mesh(ctx, m)
+    chain = [dm]
+    for lev in range(1, 5):
+        m = oracle.red_refine(m)
+        dm = dm.refine()
+        chain.append(dm)
+        print(f"{base} level {lev}: nE={m.nE}", flush=True)
+        xy, el, d, n = dm.geometry()
+        np.testing.assert_array_equal(xy, m.coords)
+        np.testing.assert_array_equal(el, m.elements)
+        np.testing.assert_array_equal(d, m.dirichlet)
+        np.testing.assert_array_equal(n, m.neumann)
+    compare_topology(dm.topology(), oracle.mesh_tables(m))
+    # a parent cannot be released before its refinements
+    with pytest.raises(phfem.PhfError) as ei:
+        phfem.phf_mesh_destroy(chain[0].handle)
+    assert ei.value.code == phfem.PHF_ESTATE
+    for c in reversed(chain):
+        c.close()
+
+
+def test_memory_pool_reuse(ctx):
+    """Device memory of a released mesh is cached and reused: rebuilding the
+    same mesh takes no new device memory and gives the same tables."""
+    from paper_2401_15557_amd import phfem
+    h = ctx.handle
+    m = G.lshape(3)
+    phfem.phf_release_cache(h)
+    live0, cached0 = phfem.phf_mem_stats(h)
+    assert cached0 == 0
+    tops, totals = [], []
+    for _ in range(3):
+        dm = phfem.Mesh(ctx, m)
+        live, _ = phfem.phf_mem_stats(h)
+        assert live > live0
+        tops.append(dm.topology())
+        dm.close()
+        live, cached = phfem.phf_mem_stats(h)
+        assert live == live0 and cached > 0
+        totals.append(live + cached)
+    assert totals[2] == totals[1]
+    for k in tops[0]:
+        np.testing.assert_array_equal(tops[2][k], tops[0][k])
+    phfem.phf_release_cache(h)
+    assert phfem.phf_mem_stats(h) == (live0, 0)

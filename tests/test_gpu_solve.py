@@ -188,3 +188,87 @@ def test_cn_steady_state(ctx, oracle):
     assert _rel(Ug, U0) < 1e-10
     assert _rel(Lg, L0) < 1e-8
     phfem.phf_cn_destroy(cn)
+
+
+def _refined_pair(ctx, oracle, base, levels):
+    """Device mesh refined `levels` times from `base`, and the oracle's copy."""
+    from paper_2401_15557_amd import phfem
+    dm = phfem.Mesh(ctx, base)
+    m = base
+    for _ in range(levels):
+        dm = dm.refine()
+        m = oracle.red_refine(m)
+    return dm, m
+
+
+@pytest.mark.parametrize("levels", [1, 3, 5])
+def test_multigrid_solve_parity(ctx, oracle, levels):
+    """CG with the V-cycle preconditioner on a device-refined L-shape with a
+    random per-triangle coefficient: same solution as the oracle's sparse LU,
+    in a number of iterations that does not grow with the level."""
+    import torch
+    from paper_2401_15557_amd import phfem
+    dm, m = _refined_pair(ctx, oracle, G.lshape(0), levels)
+    print(f"levels {levels}: nE={m.nE}", flush=True)
+    aT = G.per_triangle_coefficient(m.nE, 5)
+    od, gd = _both(oracle, phfem, "const")
+    co = phfem.make_coeffs(a_T=torch.tensor(aT, device=ctx.device))
+    s, t = phfem.alloc_system(dm, with_S=True)
+    phfem.phf_assemble(dm.handle, co, gd, s)
+    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    Lam = torch.empty(dm.info.L, dtype=torch.float64, device=ctx.device)
+    st = phfem.phf_solve(dm.handle, co, s, U, Lam, rtol=1e-13, saddle_residual=True,
+                         precond=phfem.PHF_PRECOND_MULTIGRID)
+    print(f"  iterations {st.iterations}", flush=True)
+    assert st.converged and st.iterations <= 45
+    tables = oracle.mesh_tables(m)
+    asm = oracle.assemble(m, tables, aT=aT, **od)
+    Uo, Lo = oracle.solve_saddle(asm)
+    assert _rel(U.cpu().numpy(), Uo) < 1e-9
+    assert _rel(Lam.cpu().numpy(), Lo) < 1e-8
+    assert 0 <= st.saddle_rel_residual < 1e-11
+    # Jacobi on the same system reaches the same solution
+    U2 = torch.empty_like(U)
+    st2 = phfem.phf_solve(dm.handle, co, s, U2, None, rtol=1e-13, max_iter=50000)
+    assert _rel(U2.cpu().numpy(), Uo) < 1e-9
+    print(f"  jacobi iterations {st2.iterations}", flush=True)
+
+
+def test_multigrid_needs_hierarchy(ctx):
+    import torch
+    from paper_2401_15557_amd import phfem
+    dm = phfem.Mesh(ctx, G.lshape(2))
+    co = phfem.make_coeffs()
+    s, t = phfem.alloc_system(dm)
+    phfem.phf_assemble(dm.handle, co, phfem.make_data(phfem.make_fn(phfem.PHF_FN_CONST, 1)), s)
+    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    with pytest.raises(phfem.PhfError) as ei:
+        phfem.phf_solve(dm.handle, co, s, U, precond=phfem.PHF_PRECOND_MULTIGRID)
+    assert ei.value.code == phfem.PHF_EINVAL
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_cn_multigrid_parity(ctx, oracle, use_graph):
+    import torch
+    from paper_2401_15557_amd import phfem
+    dm, m = _refined_pair(ctx, oracle, G.paper_square(0, bc="x_sides"), 4)
+    k, nst = 0.01, 5
+    tables = oracle.mesh_tables(m)
+    U0 = oracle.cr_interpolant(m, lambda x, y, t: np.sin(PI * x) * np.sin(PI * y))
+    L0 = np.zeros(tables["L"])
+    od = dict(f=oracle.fn(oracle.FN_SIN_SIN, 2 * PI * PI - 1, -1),
+              g=oracle.fn(oracle.FN_GRAD_SIN_SIN, 1, -1), uD=oracle.fn(oracle.FN_SIN_SIN, 1, -1))
+    gd = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_SIN, 2 * PI * PI - 1, -1),
+                         phfem.make_fn(phfem.PHF_FN_GRAD_SIN_SIN, 1, -1),
+                         phfem.make_fn(phfem.PHF_FN_SIN_SIN, 1, -1))
+    cn = phfem.phf_cn_create(dm.handle, phfem.make_coeffs(), k, rtol=1e-13, iters_per_step=8,
+                             precond=phfem.PHF_PRECOND_MULTIGRID)
+    phfem.phf_cn_set_state(cn, torch.tensor(U0, device=ctx.device),
+                           torch.tensor(L0, device=ctx.device), 0.0)
+    st = phfem.phf_cn_run(cn, gd, nst, use_graph=use_graph)
+    assert st.converged and st.iterations <= 30 * nst
+    Ug, Lg, t = _get(ctx, cn, dm)
+    Uo, Lo, _ = oracle.cn_run(m, tables, k, nst, U0, L0, **od)
+    assert _rel(Ug, Uo) < 1e-9
+    assert _rel(Lg, Lo) < 1e-8
+    phfem.phf_cn_destroy(cn)
