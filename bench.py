@@ -49,44 +49,46 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "assembled Melem/s + HBM GB/s (4M tris); CN steps/s; served p50/p99 latency"
 
 
-def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None):
+def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None, jacobi=False):
     """Bytes a kernel must move at least, per launch, by kernel name.
 
     k_assemble: read coordinates once (16 B/node), element vertices
     (12 B/elem), a_T (8 B/elem), the two end nodes of each multiplier row
     (8 B/row); write K and M (72 B/elem each), F (24 B/elem), C (8 B/nnz)
     and b_D (8 B/row).
-    V-cycle kernels on level l with n unknowns (level_nf[l]), operator rows of
-    five (column, value) slots = 60 B/row: smoothing sweep 60 + 8 (dinv) + 8
-    (b) + 8 (x) + 8 (y) = 92 B/row, first sweep from zero 24 B/row, residual
-    84 B/row, prolongation 60 (P) + 16 (x in/out) B/fine row + 8 B/coarse row,
-    finish (z = x, r.z) 24 B/row; restriction from level l: per coarse
-    triangle 36 B of fine row ids, 4 B code word, 24 B of sums written, plus
-    the fine residual once (8 B/fine row), then 32 B per coarse row to sum
-    the two sides.
+    V-cycle kernels (single precision) on level l with n unknowns
+    (level_nf[l]), operator rows of five (int32 column, fp32 value) slots =
+    40 B/row: smoothing sweep 40 + 4 (dinv) + 4 (b) + 4 (x) + 4 (y) = 56 B/row;
+    first sweep from zero 12 B/row (20 on the finest level, which also rounds
+    the fp64 residual once); residual 52 B/row; prolongation 40 (P) + 8 (x in
+    and out) B/fine row + 4 B/coarse row; finish (z = x in fp64, r.z) 20 B/row;
+    restriction from level l: per coarse triangle 36 B of fine row ids, 4 B
+    code word, 12 B of sums written, plus the fine residual once (4 B/fine
+    row), then 20 B per coarse row to sum the two sides.
     """
     nE, nC, L = info.nE, info.nC, info.L
     nf, nnzR = info.n_free, info.nnz_reduced
     asm = (16 * nC + 12 * nE + (8 * nE if has_aT else 0) + 8 * L +
            8 * (9 * nE) * 2 + 8 * 3 * nE + 8 * info.nnz_C + 8 * L)
     mg = {}
+    top = len(level_nf or []) - 1
     for l, n in enumerate(level_nf or []):
-        mg[f"k_mg_smooth.L{l}"] = 92 * n
-        mg[f"k_mg_smooth0.L{l}"] = 24 * n
-        mg[f"k_mg_resid.L{l}"] = 84 * n
+        mg[f"k_mg_smooth.L{l}"] = 56 * n
+        mg[f"k_mg_smooth0.L{l}"] = (20 if l == top else 12) * n
+        mg[f"k_mg_resid.L{l}"] = 52 * n
         if l > 0:
-            mg[f"k_mg_prolong.L{l}"] = 76 * n + 8 * level_nf[l - 1]
+            mg[f"k_mg_prolong.L{l}"] = 48 * n + 4 * level_nf[l - 1]
             if level_nE:
-                mg[f"k_mg_restrict.L{l}"] = 64 * level_nE[l - 1] + 8 * n
-            mg[f"k_mg_collect.L{l}"] = 32 * level_nf[l - 1]
-        mg[f"k_mg_finish.L{l}"] = 24 * n
+                mg[f"k_mg_restrict.L{l}"] = 52 * level_nE[l - 1] + 4 * n
+            mg[f"k_mg_collect.L{l}"] = 20 * level_nf[l - 1]
+        mg[f"k_mg_finish.L{l}"] = 20 * n
     return {
         **mg,
         "k_assemble": asm,
         # reduced operator values + columns (12 B/nnz), z in; p, q in and out
         "k_cg_dir": 12 * nnzR + 40 * nf,
-        # read p, q, w, r, dinv; write w, r, z
-        "k_cg_upd": 64 * nf,
+        # read p, q, w, r (and dinv); write w, r (and z with Jacobi)
+        "k_cg_upd": (64 if jacobi else 48) * nf,
     }
 
 
@@ -143,14 +145,16 @@ def main():
     ap.add_argument("--cn-level", type=int, default=9)
     ap.add_argument("--cn-steps", type=int, default=200)
     ap.add_argument("--cn-chunk", type=int, default=8,
-                    help="CG iterations per captured graph chunk")
+                    help="expected CG iterations of the first time step")
     ap.add_argument("--no-cn", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--mode", choices=("full", "assembly"), default="full",
                     help="assembly: only the numeric assembly on the benchmark mesh plus one "
                          "plain device copy of --copy-mib MiB (for hardware-counter runs)")
-    ap.add_argument("--copy-mib", type=int, default=512)
+    ap.add_argument("--copy-mib", type=int, default=None,
+                    help="size of the plain device copy run for counter calibration "
+                         "(default 512 in assembly mode, none in full mode)")
     ap.add_argument("--precond", choices=("multigrid", "jacobi"), default="multigrid")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -194,7 +198,7 @@ def main():
         sysd, t = phfem.alloc_system_for(info, dev)
         for _ in range(a.asm_reps):
             phfem.phf_assemble(mh, co, data, sysd)
-        src = torch.ones(a.copy_mib << 17, dtype=torch.float64, device=dev)
+        src = torch.ones((a.copy_mib or 512) << 17, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
@@ -256,7 +260,8 @@ def main():
     kern = phfem.phf_trace_dump(h)
     info = out["info"]
     nE = info.nE
-    ab = algorithmic_bytes(info, level_nf=out["level_nf"], level_nE=out["level_nE"])
+    ab = algorithmic_bytes(info, level_nf=out["level_nf"], level_nE=out["level_nE"],
+                           jacobi=pc == phfem.PHF_PRECOND_JACOBI)
     dname = max(kern.items(), key=lambda kv: kv[1][1])[0]
     print(f"[bench] traced step {prof[-1]}; dominant kernel {dname}", file=sys.stderr, flush=True)
     # timed steps; only the dominant kernel carries events
@@ -375,6 +380,13 @@ def main():
                                f"device-refined), u = exp(-t) sin(pi x) sin(pi y), k = {k}, "
                                f"CG + {a.precond}",
                       t_final=tf, max_nodal_error=err, **res)
+
+    if a.copy_mib:
+        # a plain copy of known size: the reference for hardware byte counters
+        src = torch.ones(a.copy_mib << 17, dtype=torch.float64, device=dev)
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        del src
 
     cpu = None
     if not a.no_cpu:

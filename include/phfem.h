@@ -279,7 +279,7 @@ typedef struct {
     int32_t saddle_residual; /* 1: compute the saddle residual into stats   */
     int32_t precond;     /* PHF_PRECOND_*                                  */
     int32_t mg_sweeps;   /* Jacobi sweeps before and after the coarse correction; 0 = 2 */
-    double mg_omega;     /* Jacobi damping; 0 = 0.7                         */
+    double mg_omega;     /* Jacobi damping; 0 = 0.8                         */
 } phf_solver_opts;
 
 typedef struct {
@@ -300,21 +300,23 @@ int phf_solve(phf_mesh* mesh, const phf_coeffs* coeffs, const phf_system* sys,
  * phf_cn_create assembles K, M, C once (coeffs as for phf_assemble, p = 0),
  * k > 0. set_state copies U (N) and Lambda (L) device arrays and sets t.
  * phf_cn_run advances nsteps steps with the time-dependent data `data`
- * (data->t is ignored); use_graph = 1 captures a step as three HIP graphs
- * (loads, right-hand side and the first `iters_per_step` CG iterations; a
- * chunk of `iters_per_step` iterations; recovery and state update) and
- * replays them, the chunk until the device-side convergence flag is set
- * (iterations after convergence are skipped on the device). get_state
+ * (data->t is ignored). Each step runs all but the last one or two of the
+ * CG iterations it expects (the previous step's count, `iters_per_step` for
+ * the first) without reading the device-side convergence flag, then tests it
+ * after every further pair (iterations after convergence are skipped on the device). use_graph = 1
+ * captures the step as HIP graphs (loads, right-hand side and the first
+ * iteration; 2, 4 and 8 further iterations; recovery and state update) and
+ * replays them in that pattern. get_state
  * copies the current state out (device) and returns t. stats (may be NULL)
  * receives the total CG iterations and the worst final reduced residual over
  * the steps. */
 typedef struct {
     double rtol;            /* 0 = 1e-10                                   */
     int32_t max_iter;       /* per step, eager mode; 0 = 5000             */
-    int32_t iters_per_step; /* CG iterations per captured chunk (even); 0 = 32 */
+    int32_t iters_per_step; /* expected CG iterations of the first step; 0 = 8 */
     int32_t precond;        /* PHF_PRECOND_* (multigrid needs a refined mesh) */
     int32_t mg_sweeps;      /* 0 = 2                                       */
-    double mg_omega;        /* 0 = 0.7                                     */
+    double mg_omega;        /* 0 = 0.8                                     */
 } phf_cn_opts;
 
 int phf_cn_create(phf_mesh* mesh, const phf_coeffs* coeffs, double k, const phf_cn_opts* opts,

@@ -30,10 +30,15 @@ struct phf_cn {
     double t0 = 0;
     int64_t n = 0;              // completed steps since set_state
     bool have_state = false;
-    // graph mode: head (+ first chunk of CG iterations), chunk, tail
-    hipGraphExec_t gx[3] = {nullptr, nullptr, nullptr};
-    hipGraph_t g[3] = {nullptr, nullptr, nullptr};
-    phf_data gdata{};           // data the graph was captured with
+    // CG iterations of the previous step: the next step launches one fewer
+    // without a convergence read-back, then tests after every pair
+    int32_t predict = 0;
+    // graph mode: [0] head (loads, right-hand side, CG start, first
+    // iteration), [1..3] 2, 4, 8 further iterations, [4] tail
+    static constexpr int NG = 5;
+    hipGraphExec_t gx[NG] = {};
+    hipGraph_t g[NG] = {};
+    phf_data gdata{};           // data the graphs were captured with
 };
 
 namespace {
@@ -195,7 +200,7 @@ int cn_step_tail(phf_cn* cn)
 
 void cn_drop_graph(phf_cn* cn)
 {
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < phf_cn::NG; ++q) {
         if (cn->gx[q]) (void)hipGraphExecDestroy(cn->gx[q]);
         if (cn->g[q]) (void)hipGraphDestroy(cn->g[q]);
         cn->gx[q] = nullptr;
@@ -209,7 +214,10 @@ bool same_fn(const phf_fn& a, const phf_fn& b)
            a.c[3] == b.c[3] && a.edge_values == b.edge_values;
 }
 
-// Captures part q of a step (0: head + first chunk, 1: chunk, 2: tail).
+// Captures part q of a step (0: head with the first iteration; 1, 2, 3:
+// 2, 4, 8 iterations; 4: tail). The kernels of an iteration only depend on
+// whether it is the first and on its parity; every iteration graph starts at
+// an odd index and has an even length, so they can follow each other freely.
 int cn_capture_part(phf_cn* cn, const phf_data* data, int q, hipStream_t cap)
 {
     phf_ctx* ctx = cn->mesh->ctx;
@@ -219,9 +227,10 @@ int cn_capture_part(phf_cn* cn, const phf_data* data, int q, hipStream_t cap)
         return phf_set_error(ctx, PHF_EHIP, "begin capture failed: %s", hipGetErrorString(e));
     if (q == 0) {
         rc = cn_step_head(cn, data);
-        if (!rc) rc = phf_ns_cg_iterate(cn->ns, cn->opts.iters_per_step);
-    } else if (q == 1) {
-        rc = phf_ns_cg_iterate(cn->ns, cn->opts.iters_per_step);
+        if (!rc) rc = phf_ns_cg_iterate(cn->ns, 1);
+    } else if (q < phf_cn::NG - 1) {
+        cn->ns->next_it = 1;
+        rc = phf_ns_cg_iterate(cn->ns, 1 << q);
     } else {
         rc = cn_step_tail(cn);
     }
@@ -251,7 +260,7 @@ int cn_capture(phf_cn* cn, const phf_data* data)
     ctx->stream = cap;
     ctx->trace = false;
     int rc = PHF_OK;
-    for (int q = 0; q < 3 && !rc; ++q) rc = cn_capture_part(cn, data, q, cap);
+    for (int q = 0; q < phf_cn::NG && !rc; ++q) rc = cn_capture_part(cn, data, q, cap);
     ctx->stream = saved;
     ctx->trace = saved_trace;
     (void)hipStreamDestroy(cap);
@@ -294,8 +303,8 @@ extern "C" int phf_cn_create(phf_mesh* mesh, const phf_coeffs* co, double k,
     cn->co = *co;
     cn->opts.rtol = opts && opts->rtol > 0 ? opts->rtol : 1e-10;
     cn->opts.max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 5000;
-    cn->opts.iters_per_step = opts && opts->iters_per_step > 0 ? opts->iters_per_step : 32;
-    cn->opts.iters_per_step += cn->opts.iters_per_step & 1;  // chunks keep the CG parity
+    cn->opts.iters_per_step = opts && opts->iters_per_step > 0 ? opts->iters_per_step : 8;
+    cn->predict = cn->opts.iters_per_step;
     cn->opts.precond = opts ? opts->precond : PHF_PRECOND_JACOBI;
     cn->opts.mg_sweeps = opts ? opts->mg_sweeps : 0;
     cn->opts.mg_omega = opts ? opts->mg_omega : 0.0;
@@ -396,39 +405,48 @@ extern "C" int phf_cn_run(phf_cn* cn, const phf_data* data, int32_t nsteps, int3
                            same_fn(cn->gdata.uD, data->uD)))
             cn_drop_graph(cn);
         if (!cn->gx[0]) TRY(cn_capture(cn, data));
-        for (int32_t s = 0; s < nsteps; ++s) {
-            phf_trace_rec rec;
-            phf_trace_begin(ctx, "cn_graph_step", &rec);
+    }
+    for (int32_t s = 0; s < nsteps; ++s) {
+        phf_trace_rec rec;
+        phf_trace_begin(ctx, use_graph ? "cn_graph_step" : "cn_step", &rec);
+        // head and first iteration, then (predicted - 2) rounded down to
+        // pairs without reading the flag, then pairs until converged
+        int32_t it = 1;
+        const int32_t blind = std::max<int32_t>(cn->predict - 2, 0) & ~1;
+        if (use_graph) {
             PHF_HIP(ctx, hipGraphLaunch(cn->gx[0], ctx->stream));
-            int32_t it = cn->opts.iters_per_step;
-            int hf[2] = {0, 0};
-            for (;;) {
-                PHF_HIP(ctx, hipMemcpyAsync(hf, cn->ns->iflags, 2 * sizeof(int),
-                                            hipMemcpyDeviceToHost, ctx->stream));
-                PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
-                if (hf[0] || it >= cn->opts.max_iter) break;
-                PHF_HIP(ctx, hipGraphLaunch(cn->gx[1], ctx->stream));
-                it += cn->opts.iters_per_step;
-            }
-            PHF_HIP(ctx, hipGraphLaunch(cn->gx[2], ctx->stream));
-            phf_trace_end(ctx, &rec);
-        }
-    } else {
-        for (int32_t s = 0; s < nsteps; ++s) {
+            for (int q = phf_cn::NG - 2; q >= 1; --q)
+                while (it - 1 + (1 << q) <= blind) {
+                    PHF_HIP(ctx, hipGraphLaunch(cn->gx[q], ctx->stream));
+                    it += 1 << q;
+                }
+        } else {
             TRY(cn_step_head(cn, data));
-            int32_t it = 0;
-            int hf[2] = {0, 0};
-            PHF_HIP(ctx, hipMemcpyAsync(hf, cn->ns->iflags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-            PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            while (!hf[0] && it < cn->opts.max_iter) {
-                int32_t nb = std::min<int32_t>(8, cn->opts.max_iter - it);
-                TRY(phf_ns_cg_iterate(cn->ns, nb));
-                it += nb;
-                PHF_HIP(ctx, hipMemcpyAsync(hf, cn->ns->iflags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-                PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            }
-            TRY(cn_step_tail(cn));
+            TRY(phf_ns_cg_iterate(cn->ns, 1));
+            cn->ns->next_it = 1;
+            if (blind > 0) TRY(phf_ns_cg_iterate(cn->ns, blind));
+            it += blind;
         }
+        int hf[2] = {0, 0};
+        for (;;) {
+            PHF_HIP(ctx, hipMemcpyAsync(hf, cn->ns->iflags, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                                        ctx->stream));
+            PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            if (hf[0] || it >= cn->opts.max_iter) break;
+            if (use_graph) {
+                PHF_HIP(ctx, hipGraphLaunch(cn->gx[1], ctx->stream));
+            } else {
+                cn->ns->next_it = 1;
+                TRY(phf_ns_cg_iterate(cn->ns, 2));
+            }
+            it += 2;
+        }
+        cn->predict = hf[1];
+        if (use_graph)
+            PHF_HIP(ctx, hipGraphLaunch(cn->gx[phf_cn::NG - 1], ctx->stream));
+        else
+            TRY(cn_step_tail(cn));
+        phf_trace_end(ctx, &rec);
     }
     double st[4] = {0, 0, 0, 0};
     PHF_HIP(ctx, hipMemcpyAsync(st, cn->d_stats, sizeof(st), hipMemcpyDeviceToHost, ctx->stream));

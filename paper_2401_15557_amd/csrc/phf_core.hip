@@ -250,15 +250,22 @@ static hipEvent_t take_event(phf_ctx* ctx)
     return e;
 }
 
-void phf_trace_begin(phf_ctx* ctx, const char* name, phf_trace_rec* rec)
+void phf_trace_begin(phf_ctx* ctx, const char* name, phf_trace_rec* rec, bool marker)
 {
     rec->name = name;
     rec->start = rec->stop = nullptr;
+    rec->marker = marker;
     if (!ctx->trace) return;
     if (!ctx->trace_only.empty() && ctx->trace_only != name) return;
     rec->start = take_event(ctx);
     rec->stop = take_event(ctx);
-    if (rec->start) (void)hipEventRecord(rec->start, ctx->stream);
+    if (!rec->start || !rec->stop) {
+        if (rec->start) ctx->event_pool.push_back(rec->start);
+        if (rec->stop) ctx->event_pool.push_back(rec->stop);
+        rec->start = rec->stop = nullptr;
+        return;
+    }
+    if (marker) (void)hipEventRecord(rec->start, ctx->stream);
 }
 
 static int trace_collect(phf_ctx* ctx);
@@ -266,7 +273,7 @@ static int trace_collect(phf_ctx* ctx);
 void phf_trace_end(phf_ctx* ctx, phf_trace_rec* rec)
 {
     if (!ctx->trace || !rec->start || !rec->stop) return;
-    (void)hipEventRecord(rec->stop, ctx->stream);
+    if (rec->marker) (void)hipEventRecord(rec->stop, ctx->stream);
     ctx->pending.push_back(*rec);
     // bound the number of events in flight; reading them waits for the stream
     if (ctx->pending.size() >= 16384) (void)trace_collect(ctx);

@@ -1,6 +1,7 @@
 // Internal declarations of libphfem (not part of the ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -17,6 +18,7 @@
 struct phf_trace_rec {
     const char* name;
     hipEvent_t start, stop;
+    bool marker;  // events recorded on the stream (else stamped by the launch)
 };
 
 struct phf_pool;
@@ -46,21 +48,29 @@ int phf_set_error(phf_ctx* ctx, int code, const char* fmt, ...);
     } while (0)
 
 // Launch bracket for tracing: every kernel launch goes through PHF_LAUNCH so
-// that an enabled trace records a start/stop event pair around it.
-void phf_trace_begin(phf_ctx* ctx, const char* name, phf_trace_rec* rec);
+// that an enabled trace times it. A traced launch hands its event pair to
+// hipExtLaunchKernelGGL, which stamps them from the kernel's own dispatch
+// (the interval a profiler reports, without the queueing around it); an
+// untraced launch is a plain launch. phf_trace_begin/end with marker = true
+// instead record the events around whatever is issued in between.
+void phf_trace_begin(phf_ctx* ctx, const char* name, phf_trace_rec* rec, bool marker = true);
 void phf_trace_end(phf_ctx* ctx, phf_trace_rec* rec);
 
-#define PHF_LAUNCH(ctx, name, kernel, grid, block, shmem, ...)                        \
-    do {                                                                              \
-        phf_trace_rec rec_;                                                           \
-        phf_trace_begin((ctx), (name), &rec_);                                        \
-        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), (shmem), (ctx)->stream,   \
-                           __VA_ARGS__);                                              \
-        hipError_t le_ = hipGetLastError();                                           \
-        if (le_ != hipSuccess)                                                        \
-            return phf_set_error((ctx), PHF_EHIP, "launch of %s failed: %s", (name),  \
-                                 hipGetErrorString(le_));                              \
-        phf_trace_end((ctx), &rec_);                                                  \
+#define PHF_LAUNCH(ctx, name, kernel, grid, block, shmem, ...)                          \
+    do {                                                                                \
+        phf_trace_rec rec_;                                                             \
+        phf_trace_begin((ctx), (name), &rec_, false);                                   \
+        if (rec_.start)                                                                 \
+            hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), (shmem), (ctx)->stream, \
+                                  rec_.start, rec_.stop, 0, __VA_ARGS__);               \
+        else                                                                            \
+            hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), (shmem), (ctx)->stream, \
+                               __VA_ARGS__);                                            \
+        hipError_t le_ = hipGetLastError();                                             \
+        if (le_ != hipSuccess)                                                          \
+            return phf_set_error((ctx), PHF_EHIP, "launch of %s failed: %s", (name),    \
+                                 hipGetErrorString(le_));                                \
+        phf_trace_end((ctx), &rec_);                                                    \
     } while (0)
 
 // Device memory comes from the context's caching pool: a freed block goes

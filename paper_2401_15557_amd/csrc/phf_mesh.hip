@@ -531,12 +531,15 @@ int flags_to_status(phf_ctx* ctx, int bits, int where, const char* stage)
     return PHF_OK;
 }
 
+__global__ void k_flags_reset(int* flags)
+{
+    flags[0] = 0;
+    flags[1] = 0x7fffffff;
+}
+
 int reset_flags(phf_ctx* ctx)
 {
-    int h[2] = {0, 0x7fffffff};
-    PHF_HIP(ctx, hipMemcpyAsync(ctx->d_flags, h, 2 * sizeof(int), hipMemcpyHostToDevice,
-                                ctx->stream));
-    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    PHF_LAUNCH(ctx, "k_flags_reset", k_flags_reset, 1, 1, 0, ctx->d_flags);
     return PHF_OK;
 }
 
@@ -555,8 +558,11 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
         if (rc_) return rc_;   \
     } while (0)
 
+// `parent`: the mesh this one is the red refinement of, or null. A refinement
+// of a valid mesh is valid, and its edge and boundary counts follow from the
+// parent's, so that path skips the validation read-backs.
 int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t* dir,
-               const int32_t* neu, phf_memspace ms)
+               const int32_t* neu, phf_memspace ms, const phf_mesh* parent)
 {
     phf_ctx* ctx = M->ctx;
     build_tmp T;
@@ -578,8 +584,10 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     // a1: validation + bucket counts by larger node
     PHF_LAUNCH(ctx, "k_elem_init", k_elem_init, nblk(nE), 256, 0, T.raw, nE, nC, M->xy, M->elem4,
                T.bcount, ctx->d_flags);
-    TRY(read_flags(ctx, &bits, &where));
-    TRY(flags_to_status(ctx, bits, where, "validation"));
+    if (!parent) {
+        TRY(read_flags(ctx, &bits, &where));
+        TRY(flags_to_status(ctx, bits, where, "validation"));
+    }
     phf_dfree(T.raw);
 
     // a2: counting sort of directed edges, per-bucket sort, unique count
@@ -591,12 +599,17 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     TRY(phf_dmalloc(ctx, &T.eoff, (size_t)nC + 1, "edge offsets"));
     PHF_LAUNCH(ctx, "k_bucket_sort", k_bucket_sort, nblk(nC), 256, 0, T.keys, T.boff, nC,
                M->elem4, T.ucount, ctx->d_flags);
-    TRY(read_flags(ctx, &bits, &where));
-    TRY(flags_to_status(ctx, bits, where, "topology"));
+    if (!parent) {
+        TRY(read_flags(ctx, &bits, &where));
+        TRY(flags_to_status(ctx, bits, where, "topology"));
+    }
     PHF_HIP(ctx, hipMemsetAsync(T.ucount + nC, 0, sizeof(int32_t), ctx->stream));
     TRY(phf_scan_i32(ctx, T.ucount, T.eoff, nC + 1, T.totals));
     int32_t ne = 0;
-    TRY(read_i32(ctx, T.totals, &ne));
+    if (parent)  // two halves per parent edge, three inner edges per parent element
+        ne = 2 * parent->n_edges + 3 * parent->nE;
+    else
+        TRY(read_i32(ctx, T.totals, &ne));
     M->n_edges = ne;
     TRY(phf_dmalloc(ctx, &M->edge_nodes, ne, "edge nodes"));
     TRY(phf_dmalloc(ctx, &M->edge_elems, ne, "edge elements"));
@@ -632,8 +645,10 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     TRY(phf_dmalloc(ctx, &T.inter, (size_t)ne + 1, "interior indicator"));
     PHF_LAUNCH(ctx, "k_boundary_check", k_boundary_check, nblk(ne), 256, 0, ne, M->edge_elems,
                T.mark, M->edge_type, T.nonN, T.nonD, T.clen, T.inter, ctx->d_flags);
-    TRY(read_flags(ctx, &bits, &where));
-    TRY(flags_to_status(ctx, bits, where, "boundary"));
+    if (!parent) {
+        TRY(read_flags(ctx, &bits, &where));
+        TRY(flags_to_status(ctx, bits, where, "boundary"));
+    }
     phf_dfree(T.eoff);
     phf_dfree(T.mark);
     TRY(phf_scan_i32(ctx, T.nonN, T.nonN, ne, T.totals));
@@ -641,8 +656,17 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     TRY(phf_scan_i32(ctx, T.clen, T.clen, ne, T.totals + 2));
     TRY(phf_scan_i32(ctx, T.inter, T.inter, ne, T.totals + 3));
     int32_t h[4];
-    PHF_HIP(ctx, hipMemcpyAsync(h, T.totals, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (parent) {
+        // every boundary edge is listed exactly once (the parent was checked)
+        h[0] = ne - nN;                              // multiplier rows
+        h[1] = ne - nD;                              // free edges
+        h[3] = ne - nD - nN;                         // interior edges
+        h[2] = 4 * h[3] + 2 * nD;                    // C entries
+    } else {
+        PHF_HIP(ctx, hipMemcpyAsync(h, T.totals, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
     M->L = h[0];
     M->n_free = h[1];
     M->nnz_C = h[2];
@@ -712,11 +736,37 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
                    M->red_edge, M->edge_elems, M->led, M->ledTN, M->elem_edges, M->red_row,
                    (int32_t*)nullptr, M->R_rowptr, M->R_col, M->R_src);
     }
-    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    // later work on the mesh runs in stream order behind these kernels
+    if (!parent) PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
     M->bytes = (int64_t)nC * 16 + (int64_t)nE * (16 + 48 + 4) + (int64_t)ne * (8 + 8 + 1 + 1 + 1 + 4 + 4) +
                (int64_t)nE * 12 + (int64_t)(nD + nN) * 4 + (int64_t)L * (4 + 8 + 4) +
                M->nnz_C * 4 + ((int64_t)N + L + 1) * 4 + M->nnz_S * 4 + (int64_t)nf * 8 +
                M->nnz_R * 12;
+    return PHF_OK;
+}
+}  // namespace
+
+namespace {
+int mesh_create(phf_ctx* ctx, const double* xy, int32_t nC, const int32_t* elem, int32_t nE,
+                const int32_t* dir, int32_t nD, const int32_t* neu, int32_t nN, phf_memspace ms,
+                const phf_mesh* parent, phf_mesh** out)
+{
+    PHF_HIP(ctx, hipSetDevice(ctx->device));
+    phf_mesh* M = new (std::nothrow) phf_mesh;
+    if (!M) return phf_set_error(ctx, PHF_ENOMEM, "host allocation failed");
+    M->ctx = ctx;
+    M->nC = nC;
+    M->nE = nE;
+    M->nD = nD;
+    M->nN = nN;
+    int rc = mesh_build(M, xy, elem, dir, neu, ms, parent);
+    if (rc) {
+        (void)hipStreamSynchronize(ctx->stream);
+        mesh_free(M);
+        delete M;
+        return rc;
+    }
+    *out = M;
     return PHF_OK;
 }
 }  // namespace
@@ -730,23 +780,7 @@ extern "C" int phf_mesh_create(phf_ctx* ctx, const double* xy, int32_t nC, const
     if (nC < 3 || nE < 1 || nE > 80000000 || nD < 0 || nN < 0 || !xy || !elem ||
         (nD > 0 && !dir) || (nN > 0 && !neu) || (ms != PHF_HOST && ms != PHF_DEVICE))
         return phf_set_error(ctx, PHF_EINVAL, "phf_mesh_create: invalid sizes or null arrays");
-    PHF_HIP(ctx, hipSetDevice(ctx->device));
-    phf_mesh* M = new (std::nothrow) phf_mesh;
-    if (!M) return phf_set_error(ctx, PHF_ENOMEM, "host allocation failed");
-    M->ctx = ctx;
-    M->nC = nC;
-    M->nE = nE;
-    M->nD = nD;
-    M->nN = nN;
-    int rc = mesh_build(M, xy, elem, dir, neu, ms);
-    if (rc) {
-        (void)hipStreamSynchronize(ctx->stream);
-        mesh_free(M);
-        delete M;
-        return rc;
-    }
-    *out = M;
-    return PHF_OK;
+    return mesh_create(ctx, xy, nC, elem, nE, dir, nD, neu, nN, ms, nullptr, out);
 }
 
 extern "C" int phf_mesh_destroy(phf_mesh* mesh)
@@ -849,12 +883,13 @@ extern "C" int phf_mesh_refine(phf_mesh* coarse, phf_mesh** out)
         if (coarse->nN)
             PHF_LAUNCH(ctx, "k_refine_pairs", k_refine_pairs, nblk(coarse->nN), 256, 0, coarse->nC,
                        coarse->nN, coarse->neu_pairs, coarse->neu_edges, n_f);
-        return phf_mesh_create(ctx, (const double*)xy_f, (int32_t)nCf, el_f, (int32_t)nEf,
-                               (const int32_t*)d_f, 2 * coarse->nD, (const int32_t*)n_f,
-                               2 * coarse->nN, PHF_DEVICE, out);
+        return mesh_create(ctx, (const double*)xy_f, (int32_t)nCf, el_f, (int32_t)nEf,
+                           (const int32_t*)d_f, 2 * coarse->nD, (const int32_t*)n_f,
+                           2 * coarse->nN, PHF_DEVICE, coarse, out);
     };
     rc = body();
-    (void)hipStreamSynchronize(ctx->stream);
+    // the temporaries go back to the pool; their next users run after the
+    // kernels above in stream order
     phf_dfree(xy_f);
     phf_dfree(el_f);
     phf_dfree(d_f);

@@ -14,7 +14,11 @@
 // applied as per-coarse-triangle sums over its nine fine edges followed by a
 // sum over the two triangles of each coarse edge. Smoothing is damped Jacobi, the coarsest level is solved
 // exactly (dense inverse), and the V-cycle with equal pre- and post-smoothing
-// is symmetric, so it can precondition conjugate gradients.
+// is symmetric, so it can precondition conjugate gradients. The cycle runs in
+// single precision (operator copies, vectors, transfer weights; the coarsest
+// solve accumulates in double): it only has to approximate the inverse, while
+// the outer conjugate-gradient iteration keeps double precision, so the
+// reached residual is unaffected and the cycle moves about 40% fewer bytes.
 #pragma once
 
 #include "phf_solver.h"
@@ -29,16 +33,19 @@ struct phf_mg_level {
     int32_t nf = 0;
     // coarse-level assembly buffers (null on the finest level)
     double *K = nullptr, *M = nullptr, *C = nullptr, *F = nullptr, *bD = nullptr, *aT = nullptr;
-    // V-cycle vectors
-    double *x = nullptr, *y = nullptr, *b = nullptr, *r = nullptr;
+    // single-precision copies of this level's operator values (ELL-5, the
+    // columns are the operator's own) and inverse diagonal
+    float *val32 = nullptr, *dinv32 = nullptr;
+    // V-cycle vectors (single precision)
+    float *x = nullptr, *y = nullptr, *b = nullptr, *r = nullptr;
     // prolongation from the next coarser level (ELL-5 over this level's rows)
     int32_t* P_col = nullptr;
-    double* P_val = nullptr;
+    float* P_val = nullptr;
     // restriction to the next coarser level: fine rows of the nine fine edges
     // in each coarse triangle (slot-major, 9 x nE_coarse), per-triangle sums
     // (3 x nE_coarse)
     int32_t* rows9 = nullptr;
-    double* t = nullptr;
+    float* t = nullptr;
     // on coarse levels: positions of each row's edge in the sums of the finer
     // level (T+ side, T- side or -1)
     int2* sel = nullptr;
@@ -51,7 +58,7 @@ struct phf_mg {
     double* cwork = nullptr;
     int32_t n0 = 0;
     int32_t nu = 2;          // Jacobi sweeps before and after the coarse correction
-    double omega = 0.7;      // Jacobi damping
+    double omega = 0.8;      // Jacobi damping
 };
 
 // Builds the hierarchy below the finest operator `fine` (whose mesh must come

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(NT) void k_mg_prolong_build(
     const int2* __restrict__ edge_elems_f, const int2* __restrict__ edge_nodes_f,
     const double2* __restrict__ xy_f, const double2* __restrict__ exy_c,
     const int32_t* __restrict__ elem_edges_c, const int32_t* __restrict__ red_row_c,
-    int32_t* __restrict__ P_col, double* __restrict__ P_val)
+    int32_t* __restrict__ P_col, float* __restrict__ P_val)
 {
     const int32_t rf = blockIdx.x * NT + threadIdx.x;
     if (rf >= nf_f) return;
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(NT) void k_mg_prolong_build(
     for (int k = 0; k < 5; ++k) {
         const int64_t slot = (int64_t)k * nf_f + rf;
         P_col[slot] = k < n ? col[k] : 0;
-        P_val[slot] = k < n ? val[k] : 0.0;
+        P_val[slot] = k < n ? (float)val[k] : 0.0f;
     }
 }
 
@@ -168,33 +168,58 @@ __global__ __launch_bounds__(1024) void k_mg_gj(int32_t n, double* __restrict__ 
     for (int64_t q = tid; q < (int64_t)n * n; q += nth) A[q] = W[q];
 }
 
-__device__ inline double ell5(int32_t r, int32_t n, const int32_t* __restrict__ col,
-                              const double* __restrict__ val, const double* __restrict__ x)
+__device__ inline float ell5(int32_t r, int32_t n, const int32_t* __restrict__ col,
+                             const float* __restrict__ val, const float* __restrict__ x)
 {
-    double s = 0.0;
+    float s = 0.0f;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         const int64_t slot = (int64_t)k * n + r;
-        s = fma(val[slot], x[col[slot]], s);
+        s = fmaf(val[slot], x[col[slot]], s);
     }
     return s;
 }
 
-__global__ __launch_bounds__(NT) void k_mg_smooth0(int32_t n, const double* __restrict__ dinv,
-                                                   const double* __restrict__ b, double omega,
-                                                   double* __restrict__ x, const int* iflags)
+__global__ __launch_bounds__(NT) void k_mg_f32(int64_t n, const double* __restrict__ in,
+                                               float* __restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+        out[i] = (float)in[i];
+}
+
+// First sweep from x = 0 on the finest level: also rounds the right-hand side
+// (the double-precision CG residual) once for the rest of the cycle.
+__global__ __launch_bounds__(NT) void k_mg_smooth0_top(int32_t n, const float* __restrict__ dinv,
+                                                       const double* __restrict__ b64, float omega,
+                                                       float* __restrict__ b, float* __restrict__ x,
+                                                       const int* iflags)
+{
+    if (iflags && iflags[0]) return;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+        const float bi = (float)b64[i];
+        b[i] = bi;
+        x[i] = omega * dinv[i] * bi;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_mg_smooth0(int32_t n, const float* __restrict__ dinv,
+                                                   const float* __restrict__ b, float omega,
+                                                   float* __restrict__ x, const int* iflags)
 {
     if (iflags && iflags[0]) return;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
         x[i] = omega * dinv[i] * b[i];
 }
 
+// FINEST only separates the finest level's launches under their own symbol
+// (profilers aggregate by symbol); the code is the same.
+template <bool FINEST>
 __global__ __launch_bounds__(NT) void k_mg_smooth(int32_t n, const int32_t* __restrict__ col,
-                                                  const double* __restrict__ val,
-                                                  const double* __restrict__ dinv,
-                                                  const double* __restrict__ b, double omega,
-                                                  const double* __restrict__ x,
-                                                  double* __restrict__ y, const int* iflags)
+                                                  const float* __restrict__ val,
+                                                  const float* __restrict__ dinv,
+                                                  const float* __restrict__ b, float omega,
+                                                  const float* __restrict__ x,
+                                                  float* __restrict__ y, const int* iflags)
 {
     if (iflags && iflags[0]) return;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
@@ -202,10 +227,10 @@ __global__ __launch_bounds__(NT) void k_mg_smooth(int32_t n, const int32_t* __re
 }
 
 __global__ __launch_bounds__(NT) void k_mg_resid(int32_t n, const int32_t* __restrict__ col,
-                                                 const double* __restrict__ val,
-                                                 const double* __restrict__ b,
-                                                 const double* __restrict__ x,
-                                                 double* __restrict__ r, const int* iflags)
+                                                 const float* __restrict__ val,
+                                                 const float* __restrict__ b,
+                                                 const float* __restrict__ x,
+                                                 float* __restrict__ r, const int* iflags)
 {
     if (iflags && iflags[0]) return;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
@@ -221,34 +246,34 @@ __global__ __launch_bounds__(NT) void k_mg_resid(int32_t n, const int32_t* __res
 // not depend on the shape of p, so the weights are the constants below.
 __global__ __launch_bounds__(NT) void k_mg_restrict(int32_t nEc, const int32_t* __restrict__ rows9,
                                                     const int32_t* __restrict__ ecode_c,
-                                                    const double* __restrict__ rf,
-                                                    double* __restrict__ t, const int* iflags)
+                                                    const float* __restrict__ rf,
+                                                    float* __restrict__ t, const int* iflags)
 {
     if (iflags && iflags[0]) return;
     for (int32_t p = blockIdx.x * NT + threadIdx.x; p < nEc; p += gridDim.x * NT) {
-        double v[9];
+        float v[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             const int32_t row = rows9[(int64_t)k * nEc + p];
-            v[k] = row >= 0 ? rf[row] : 0.0;
+            v[k] = row >= 0 ? rf[row] : 0.0f;
         }
         const int32_t code = ecode_c[p];
-        double s[3];
+        float s[3];
 #pragma unroll
-        for (int e = 0; e < 3; ++e) s[e] = PHF_CODE_TYPE(code, e) == 0 ? 0.5 : 1.0;
-        double acc[3];
+        for (int e = 0; e < 3; ++e) s[e] = PHF_CODE_TYPE(code, e) == 0 ? 0.5f : 1.0f;
+        float acc[3];
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             // centre edges: parallel to l -> 0, the other two -> 1/2
-            double a = 0.5 * (v[(l + 1) % 3] + v[(l + 2) % 3]);
+            float a = 0.5f * (v[(l + 1) % 3] + v[(l + 2) % 3]);
             // halves at vertex i of edge e: psi_e = 1, psi_i = -1/2, psi_(third) = 1/2
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const int e1 = (i + 1) % 3, e2 = (i + 2) % 3;
-                const double h1 = s[e1] * v[3 + 2 * i], h2 = s[e2] * v[4 + 2 * i];
-                if (l == i) a += -0.5 * (h1 + h2);
-                else if (l == e1) a += h1 + 0.5 * h2;
-                else a += 0.5 * h1 + h2;
+                const float h1 = s[e1] * v[3 + 2 * i], h2 = s[e2] * v[4 + 2 * i];
+                if (l == i) a += -0.5f * (h1 + h2);
+                else if (l == e1) a += h1 + 0.5f * h2;
+                else a += 0.5f * h1 + h2;
             }
             acc[l] = a;
         }
@@ -261,8 +286,8 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(int32_t nEc, const int32_t* 
 // Restriction, second half: coarse row c sums its edge's entries from T+
 // and T- (in that order).
 __global__ __launch_bounds__(NT) void k_mg_collect(int32_t nc, const int2* __restrict__ sel,
-                                                   const double* __restrict__ t,
-                                                   double* __restrict__ bc, const int* iflags)
+                                                   const float* __restrict__ t,
+                                                   float* __restrict__ bc, const int* iflags)
 {
     if (iflags && iflags[0]) return;
     for (int32_t c = blockIdx.x * NT + threadIdx.x; c < nc; c += gridDim.x * NT) {
@@ -272,9 +297,9 @@ __global__ __launch_bounds__(NT) void k_mg_collect(int32_t nc, const int2* __res
 }
 
 __global__ __launch_bounds__(NT) void k_mg_prolong(int32_t n, const int32_t* __restrict__ P_col,
-                                                   const double* __restrict__ P_val,
-                                                   const double* __restrict__ xc,
-                                                   double* __restrict__ x, const int* iflags)
+                                                   const float* __restrict__ P_val,
+                                                   const float* __restrict__ xc,
+                                                   float* __restrict__ x, const int* iflags)
 {
     if (iflags && iflags[0]) return;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
@@ -282,19 +307,19 @@ __global__ __launch_bounds__(NT) void k_mg_prolong(int32_t n, const int32_t* __r
 }
 
 __global__ __launch_bounds__(NT) void k_mg_coarse(int32_t n, const double* __restrict__ Ainv,
-                                                  const double* __restrict__ b,
-                                                  double* __restrict__ x, const int* iflags)
+                                                  const float* __restrict__ b,
+                                                  float* __restrict__ x, const int* iflags)
 {
     if (iflags && iflags[0]) return;
     for (int32_t i = threadIdx.x; i < n; i += NT) {
         double s = 0.0;
-        for (int32_t j = 0; j < n; ++j) s = fma(Ainv[(int64_t)i * n + j], b[j], s);
-        x[i] = s;
+        for (int32_t j = 0; j < n; ++j) s = fma(Ainv[(int64_t)i * n + j], (double)b[j], s);
+        x[i] = (float)s;
     }
 }
 
 // z = x; partial sums of r.z (fixed order within the block).
-__global__ __launch_bounds__(NT) void k_mg_finish(int32_t n, const double* __restrict__ x,
+__global__ __launch_bounds__(NT) void k_mg_finish(int32_t n, const float* __restrict__ x,
                                                   const double* __restrict__ r,
                                                   double* __restrict__ z,
                                                   double* __restrict__ part, const int* iflags)
@@ -303,7 +328,7 @@ __global__ __launch_bounds__(NT) void k_mg_finish(int32_t n, const double* __res
     __shared__ double sh[NT / 64];
     double s = 0.0;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-        const double zi = x[i];
+        const double zi = (double)x[i];
         z[i] = zi;
         s = fma(r[i], zi, s);
     }
@@ -349,8 +374,10 @@ void phf_mg_destroy(phf_mg* mg)
     for (int l = 0; l < mg->nlev; ++l) {
         phf_mg_level& L = mg->lev[l];
         if (L.own_ns && L.ns) phf_ns_destroy(L.ns);
-        double* d[] = {L.K, L.M, L.C, L.F, L.bD, L.aT, L.x, L.y, L.b, L.r, L.P_val, L.t};
+        double* d[] = {L.K, L.M, L.C, L.F, L.bD, L.aT};
         for (double* p : d) phf_dfree(p);
+        float* f[] = {L.val32, L.dinv32, L.x, L.y, L.b, L.r, L.P_val, L.t};
+        for (float* p : f) phf_dfree(p);
         phf_dfree(L.P_col);
         phf_dfree(L.rows9);
         phf_dfree(L.sel);
@@ -395,6 +422,8 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             }
             L.nf = ms->n_free;
             const size_t nf = std::max<int32_t>(L.nf, 1);
+            TRY(phf_dmalloc(ctx, &L.val32, 5 * nf, "multigrid operator (single)"));
+            TRY(phf_dmalloc(ctx, &L.dinv32, nf, "multigrid diagonal (single)"));
             TRY(phf_dmalloc(ctx, &L.x, nf, "multigrid x"));
             TRY(phf_dmalloc(ctx, &L.y, nf, "multigrid y"));
             TRY(phf_dmalloc(ctx, &L.b, nf, "multigrid b"));
@@ -465,6 +494,17 @@ int phf_mg_numeric(phf_mg* mg, const phf_coeffs* co, double cK, double cM)
         TRY(phf_assemble_impl(L.mesh, &c, &d, &s));
         TRY(phf_ns_operator(L.ns, L.K, L.M, L.C, cK, cM));
     }
+    // single-precision copies for the cycle (the finest operator is the one
+    // the caller built)
+    for (int l = 0; l <= top; ++l) {
+        phf_mg_level& L = mg->lev[l];
+        if (L.nf == 0) continue;
+        const int64_t n5 = 5 * (int64_t)L.nf;
+        PHF_LAUNCH(ctx, "k_mg_f32", k_mg_f32, (unsigned)std::min<int64_t>(nblk(n5), 2048), NT, 0,
+                   n5, L.ns->ell_val, L.val32);
+        PHF_LAUNCH(ctx, "k_mg_f32", k_mg_f32, (unsigned)std::min<int64_t>(nblk(L.nf), 2048), NT, 0,
+                   (int64_t)L.nf, L.ns->dinv, L.dinv32);
+    }
     if (mg->cinv) {
         const int32_t n0 = mg->n0;
         PHF_LAUNCH(ctx, "k_mg_dense", k_mg_dense, nblk(n0), NT, 0, n0, mg->lev[0].ns->ell_col,
@@ -475,7 +515,23 @@ int phf_mg_numeric(phf_mg* mg, const phf_coeffs* co, double cK, double cM)
 }
 
 namespace {
-int vcycle(phf_mg* mg, int l, const int* iflags)
+int smooth(phf_mg* mg, int l, const int* iflags)
+{
+    phf_mg_level& L = mg->lev[l];
+    phf_ctx* ctx = L.mesh->ctx;
+    const int32_t n = L.nf;
+    const unsigned g = grid_for(n);
+    if (l == mg->nlev - 1)
+        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth<true>, g, NT, 0, n, L.ns->ell_col,
+                   L.val32, L.dinv32, L.b, (float)mg->omega, L.x, L.y, iflags);
+    else
+        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth<false>, g, NT, 0, n, L.ns->ell_col,
+                   L.val32, L.dinv32, L.b, (float)mg->omega, L.x, L.y, iflags);
+    std::swap(L.x, L.y);
+    return PHF_OK;
+}
+
+int vcycle(phf_mg* mg, int l, const double* r_top, const int* iflags)
 {
     phf_mg_level& L = mg->lev[l];
     phf_ctx* ctx = L.mesh->ctx;
@@ -488,41 +544,38 @@ int vcycle(phf_mg* mg, int l, const int* iflags)
             PHF_LAUNCH(ctx, "k_mg_coarse", k_mg_coarse, 1, NT, 0, n, mg->cinv, L.b, L.x, iflags);
         } else {
             // no dense inverse: many damped Jacobi sweeps
-            PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0, g, NT, 0, n, ns->dinv, L.b,
-                       mg->omega, L.x, iflags);
+            PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0, g, NT, 0, n, L.dinv32, L.b,
+                       (float)mg->omega, L.x, iflags);
             for (int s = 0; s < 40; ++s) {
-                PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth, g, NT, 0, n, ns->ell_col, ns->ell_val,
-                           ns->dinv, L.b, mg->omega, L.x, L.y, iflags);
+                PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth<false>, g, NT, 0, n, ns->ell_col, L.val32,
+                           L.dinv32, L.b, (float)mg->omega, L.x, L.y, iflags);
                 std::swap(L.x, L.y);
             }
         }
         return PHF_OK;
     }
-    // pre-smoothing from x = 0
-    PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0, g, NT, 0, n, ns->dinv, L.b, mg->omega,
-               L.x, iflags);
-    for (int s = 1; s < mg->nu; ++s) {
-        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth, g, NT, 0, n, ns->ell_col, ns->ell_val,
-                   ns->dinv, L.b, mg->omega, L.x, L.y, iflags);
-        std::swap(L.x, L.y);
-    }
+    // pre-smoothing from x = 0 (on the finest level the right-hand side is
+    // the double-precision residual r_top)
+    if (r_top)
+        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0_top, g, NT, 0, n, L.dinv32, r_top,
+                   (float)mg->omega, L.b, L.x, iflags);
+    else
+        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0, g, NT, 0, n, L.dinv32, L.b,
+                   (float)mg->omega, L.x, iflags);
+    for (int s = 1; s < mg->nu; ++s) TRY(smooth(mg, l, iflags));
     phf_mg_level& C = mg->lev[l - 1];
     if (C.nf > 0) {
-        PHF_LAUNCH(ctx, mg_name(NM_RESID, l), k_mg_resid, g, NT, 0, n, ns->ell_col, ns->ell_val, L.b, L.x,
+        PHF_LAUNCH(ctx, mg_name(NM_RESID, l), k_mg_resid, g, NT, 0, n, ns->ell_col, L.val32, L.b, L.x,
                    L.r, iflags);
         PHF_LAUNCH(ctx, mg_name(NM_RESTRICT, l), k_mg_restrict, grid_for(C.mesh->nE), NT, 0,
                    C.mesh->nE, L.rows9, C.mesh->ecode, L.r, L.t, iflags);
         PHF_LAUNCH(ctx, mg_name(NM_COLLECT, l), k_mg_collect, grid_for(C.nf), NT, 0, C.nf, C.sel,
                    L.t, C.b, iflags);
-        TRY(vcycle(mg, l - 1, iflags));
+        TRY(vcycle(mg, l - 1, nullptr, iflags));
         PHF_LAUNCH(ctx, mg_name(NM_PROLONG, l), k_mg_prolong, g, NT, 0, n, L.P_col, L.P_val, C.x, L.x,
                    iflags);
     }
-    for (int s = 0; s < mg->nu; ++s) {
-        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth, g, NT, 0, n, ns->ell_col, ns->ell_val,
-                   ns->dinv, L.b, mg->omega, L.x, L.y, iflags);
-        std::swap(L.x, L.y);
-    }
+    for (int s = 0; s < mg->nu; ++s) TRY(smooth(mg, l, iflags));
     return PHF_OK;
 }
 }  // namespace
@@ -534,11 +587,7 @@ int phf_mg_apply(phf_mg* mg, const double* r, double* z, double* part_rz, const 
     phf_ctx* ctx = F.mesh->ctx;
     if (F.nf == 0) return PHF_OK;
     // the finest right-hand side is the CG residual itself
-    double* saved_b = F.b;
-    F.b = const_cast<double*>(r);
-    int rc = vcycle(mg, top, iflags);
-    F.b = saved_b;
-    if (rc) return rc;
+    TRY(vcycle(mg, top, r, iflags));
     PHF_LAUNCH(ctx, mg_name(NM_FINISH, top), k_mg_finish, grid_for(F.nf), NT, 0, F.nf, F.x, r, z, part_rz,
                iflags);
     return PHF_OK;

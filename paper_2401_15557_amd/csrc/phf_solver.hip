@@ -601,7 +601,7 @@ int phf_ns_set_precond(phf_ns* ns, int32_t precond, int32_t sweeps, double omega
     if (precond != PHF_PRECOND_MULTIGRID) return PHF_OK;
     if (!ns->mg) TRY(phf_mg_create(ns, &ns->mg));
     ns->mg->nu = sweeps > 0 ? sweeps : 2;
-    ns->mg->omega = omega > 0 ? omega : 0.7;
+    ns->mg->omega = omega > 0 ? omega : 0.8;
     TRY(phf_mg_numeric(ns->mg, co, cK, cM));
     ns->mg_on = true;
     return PHF_OK;

@@ -360,7 +360,7 @@ def phf_solve(mesh, coeffs, system, U, Lam=None, rtol=1e-10, max_iter=20000, che
     return st
 
 
-def phf_cn_create(mesh, coeffs, k, rtol=1e-10, max_iter=5000, iters_per_step=32,
+def phf_cn_create(mesh, coeffs, k, rtol=1e-10, max_iter=5000, iters_per_step=8,
                   precond=PHF_PRECOND_JACOBI, mg_sweeps=0, mg_omega=0.0):
     h = _VP()
     o = phf_cn_opts(float(rtol), int(max_iter), int(iters_per_step), int(precond),
