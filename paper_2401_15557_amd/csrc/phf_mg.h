@@ -25,6 +25,23 @@
 
 #define PHF_MG_MAX_LEVELS 20
 #define PHF_MG_DENSE_MAX 256
+// Levels with at most this many unknowns (below the finest) run their part of
+// the cycle in one single-workgroup launch.
+#define PHF_MG_TAIL_MAX 8192
+
+// Device view of one level, for the single-workgroup cycle.
+struct phf_mg_dev_level {
+    int32_t n = 0, nEc = 0;  // unknowns; elements of the next coarser mesh
+    const int32_t* col = nullptr;
+    const float *val = nullptr, *dinv = nullptr;
+    float *x = nullptr, *y = nullptr, *b = nullptr, *r = nullptr;
+    const int32_t* P_col = nullptr;  // prolongation from the next coarser level
+    const float* P_val = nullptr;
+    const int32_t* rows9 = nullptr;  // restriction to the next coarser level
+    float* t = nullptr;
+    const int32_t* ecode_c = nullptr;  // element codes of the next coarser mesh
+    const int2* sel = nullptr;         // own gather map (from the finer level's sums)
+};
 
 struct phf_mg_level {
     phf_mesh* mesh = nullptr;
@@ -57,6 +74,9 @@ struct phf_mg {
     double* cinv = nullptr;  // dense inverse of the coarsest operator (n0 <= DENSE_MAX)
     double* cwork = nullptr;
     int32_t n0 = 0;
+    int32_t tail_top = -1;   // levels 0..tail_top run in the single-workgroup kernel
+    phf_mg_dev_level h_lv[PHF_MG_MAX_LEVELS];
+    phf_mg_dev_level* d_lv = nullptr;
     int32_t nu = 2;          // Jacobi sweeps before and after the coarse correction
     double omega = 0.8;      // Jacobi damping
 };

@@ -180,6 +180,96 @@ __device__ inline float ell5(int32_t r, int32_t n, const int32_t* __restrict__ c
     return s;
 }
 
+// Per-row (per-triangle) steps of the cycle, shared by the one-launch-per-step
+// kernels of the large levels and the single-workgroup kernel of the small
+// ones, so both compute the same values.
+__device__ inline void row_smooth0(int32_t i, const float* __restrict__ dinv,
+                                   const float* __restrict__ b, float omega, float* __restrict__ x)
+{
+    x[i] = omega * dinv[i] * b[i];
+}
+
+__device__ inline void row_smooth(int32_t i, int32_t n, const int32_t* __restrict__ col,
+                                  const float* __restrict__ val, const float* __restrict__ dinv,
+                                  const float* __restrict__ b, float omega,
+                                  const float* __restrict__ x, float* __restrict__ y)
+{
+    y[i] = x[i] + omega * dinv[i] * (b[i] - ell5(i, n, col, val, x));
+}
+
+__device__ inline void row_resid(int32_t i, int32_t n, const int32_t* __restrict__ col,
+                                 const float* __restrict__ val, const float* __restrict__ b,
+                                 const float* __restrict__ x, float* __restrict__ r)
+{
+    r[i] = b[i] - ell5(i, n, col, val, x);
+}
+
+// Restriction, first half: for coarse triangle p and each of its edges l, the
+// sum over the nine fine edges e inside p of s_e psi_l(m_e) r[e], where
+// psi_l = 1 - 2 lambda_l is the coarse edge-midpoint basis function, m_e the
+// fine edge midpoint and s_e = 1/2 on halves of a coarse edge shared with a
+// second coarse triangle (the prolongation averages the two sides there), 1
+// otherwise. The barycentric coordinates of the fine midpoints do not depend
+// on the shape of p, so the weights are the constants below.
+__device__ inline void tri_restrict(int32_t p, int32_t nEc, const int32_t* __restrict__ rows9,
+                                    const int32_t* __restrict__ ecode_c,
+                                    const float* __restrict__ rf, float* __restrict__ t)
+{
+    float v[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int32_t row = rows9[(int64_t)k * nEc + p];
+        v[k] = row >= 0 ? rf[row] : 0.0f;
+    }
+    const int32_t code = ecode_c[p];
+    float s[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) s[e] = PHF_CODE_TYPE(code, e) == 0 ? 0.5f : 1.0f;
+    float acc[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        // centre edges: parallel to l -> 0, the other two -> 1/2
+        float a = 0.5f * (v[(l + 1) % 3] + v[(l + 2) % 3]);
+        // halves at vertex i of edge e: psi_e = 1, psi_i = -1/2, psi_(third) = 1/2
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int e1 = (i + 1) % 3, e2 = (i + 2) % 3;
+            const float h1 = s[e1] * v[3 + 2 * i], h2 = s[e2] * v[4 + 2 * i];
+            if (l == i) a += -0.5f * (h1 + h2);
+            else if (l == e1) a += h1 + 0.5f * h2;
+            else a += 0.5f * h1 + h2;
+        }
+        acc[l] = a;
+    }
+    t[3 * (int64_t)p] = acc[0];
+    t[3 * (int64_t)p + 1] = acc[1];
+    t[3 * (int64_t)p + 2] = acc[2];
+}
+
+// Restriction, second half: coarse row c sums its edge's entries from T+ and
+// T- (in that order).
+__device__ inline void row_collect(int32_t c, const int2* __restrict__ sel,
+                                   const float* __restrict__ t, float* __restrict__ bc)
+{
+    const int2 q = sel[c];
+    bc[c] = q.y >= 0 ? t[q.x] + t[q.y] : t[q.x];
+}
+
+__device__ inline void row_prolong(int32_t i, int32_t n, const int32_t* __restrict__ P_col,
+                                   const float* __restrict__ P_val, const float* __restrict__ xc,
+                                   float* __restrict__ x)
+{
+    x[i] += ell5(i, n, P_col, P_val, xc);
+}
+
+__device__ inline void row_coarse(int32_t i, int32_t n, const double* __restrict__ Ainv,
+                                  const float* __restrict__ b, float* __restrict__ x)
+{
+    double s = 0.0;
+    for (int32_t j = 0; j < n; ++j) s = fma(Ainv[(int64_t)i * n + j], (double)b[j], s);
+    x[i] = (float)s;
+}
+
 __global__ __launch_bounds__(NT) void k_mg_f32(int64_t n, const double* __restrict__ in,
                                                float* __restrict__ out)
 {
@@ -196,9 +286,8 @@ __global__ __launch_bounds__(NT) void k_mg_smooth0_top(int32_t n, const float* _
 {
     if (iflags && iflags[0]) return;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-        const float bi = (float)b64[i];
-        b[i] = bi;
-        x[i] = omega * dinv[i] * bi;
+        b[i] = (float)b64[i];
+        row_smooth0(i, dinv, b, omega, x);
     }
 }
 
@@ -208,7 +297,7 @@ __global__ __launch_bounds__(NT) void k_mg_smooth0(int32_t n, const float* __res
 {
     if (iflags && iflags[0]) return;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
-        x[i] = omega * dinv[i] * b[i];
+        row_smooth0(i, dinv, b, omega, x);
 }
 
 // FINEST only separates the finest level's launches under their own symbol
@@ -223,7 +312,7 @@ __global__ __launch_bounds__(NT) void k_mg_smooth(int32_t n, const int32_t* __re
 {
     if (iflags && iflags[0]) return;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
-        y[i] = x[i] + omega * dinv[i] * (b[i] - ell5(i, n, col, val, x));
+        row_smooth(i, n, col, val, dinv, b, omega, x, y);
 }
 
 __global__ __launch_bounds__(NT) void k_mg_resid(int32_t n, const int32_t* __restrict__ col,
@@ -234,66 +323,26 @@ __global__ __launch_bounds__(NT) void k_mg_resid(int32_t n, const int32_t* __res
 {
     if (iflags && iflags[0]) return;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
-        r[i] = b[i] - ell5(i, n, col, val, x);
+        row_resid(i, n, col, val, b, x, r);
 }
 
-// Restriction, first half: for each coarse triangle p and each of its edges
-// l, the sum over the nine fine edges e inside p of s_e psi_l(m_e) r[e],
-// where psi_l = 1 - 2 lambda_l is the coarse edge-midpoint basis function,
-// m_e the fine edge midpoint and s_e = 1/2 on halves of a coarse edge shared
-// with a second coarse triangle (the prolongation averages the two sides
-// there), 1 otherwise. The barycentric coordinates of the fine midpoints do
-// not depend on the shape of p, so the weights are the constants below.
 __global__ __launch_bounds__(NT) void k_mg_restrict(int32_t nEc, const int32_t* __restrict__ rows9,
                                                     const int32_t* __restrict__ ecode_c,
                                                     const float* __restrict__ rf,
                                                     float* __restrict__ t, const int* iflags)
 {
     if (iflags && iflags[0]) return;
-    for (int32_t p = blockIdx.x * NT + threadIdx.x; p < nEc; p += gridDim.x * NT) {
-        float v[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const int32_t row = rows9[(int64_t)k * nEc + p];
-            v[k] = row >= 0 ? rf[row] : 0.0f;
-        }
-        const int32_t code = ecode_c[p];
-        float s[3];
-#pragma unroll
-        for (int e = 0; e < 3; ++e) s[e] = PHF_CODE_TYPE(code, e) == 0 ? 0.5f : 1.0f;
-        float acc[3];
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-            // centre edges: parallel to l -> 0, the other two -> 1/2
-            float a = 0.5f * (v[(l + 1) % 3] + v[(l + 2) % 3]);
-            // halves at vertex i of edge e: psi_e = 1, psi_i = -1/2, psi_(third) = 1/2
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const int e1 = (i + 1) % 3, e2 = (i + 2) % 3;
-                const float h1 = s[e1] * v[3 + 2 * i], h2 = s[e2] * v[4 + 2 * i];
-                if (l == i) a += -0.5f * (h1 + h2);
-                else if (l == e1) a += h1 + 0.5f * h2;
-                else a += 0.5f * h1 + h2;
-            }
-            acc[l] = a;
-        }
-        t[3 * (int64_t)p] = acc[0];
-        t[3 * (int64_t)p + 1] = acc[1];
-        t[3 * (int64_t)p + 2] = acc[2];
-    }
+    for (int32_t p = blockIdx.x * NT + threadIdx.x; p < nEc; p += gridDim.x * NT)
+        tri_restrict(p, nEc, rows9, ecode_c, rf, t);
 }
 
-// Restriction, second half: coarse row c sums its edge's entries from T+
-// and T- (in that order).
 __global__ __launch_bounds__(NT) void k_mg_collect(int32_t nc, const int2* __restrict__ sel,
                                                    const float* __restrict__ t,
                                                    float* __restrict__ bc, const int* iflags)
 {
     if (iflags && iflags[0]) return;
-    for (int32_t c = blockIdx.x * NT + threadIdx.x; c < nc; c += gridDim.x * NT) {
-        const int2 q = sel[c];
-        bc[c] = q.y >= 0 ? t[q.x] + t[q.y] : t[q.x];
-    }
+    for (int32_t c = blockIdx.x * NT + threadIdx.x; c < nc; c += gridDim.x * NT)
+        row_collect(c, sel, t, bc);
 }
 
 __global__ __launch_bounds__(NT) void k_mg_prolong(int32_t n, const int32_t* __restrict__ P_col,
@@ -303,7 +352,7 @@ __global__ __launch_bounds__(NT) void k_mg_prolong(int32_t n, const int32_t* __r
 {
     if (iflags && iflags[0]) return;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
-        x[i] += ell5(i, n, P_col, P_val, xc);
+        row_prolong(i, n, P_col, P_val, xc, x);
 }
 
 __global__ __launch_bounds__(NT) void k_mg_coarse(int32_t n, const double* __restrict__ Ainv,
@@ -311,10 +360,91 @@ __global__ __launch_bounds__(NT) void k_mg_coarse(int32_t n, const double* __res
                                                   float* __restrict__ x, const int* iflags)
 {
     if (iflags && iflags[0]) return;
-    for (int32_t i = threadIdx.x; i < n; i += NT) {
-        double s = 0.0;
-        for (int32_t j = 0; j < n; ++j) s = fma(Ainv[(int64_t)i * n + j], (double)b[j], s);
-        x[i] = (float)s;
+    for (int32_t i = threadIdx.x; i < n; i += NT) row_coarse(i, n, Ainv, b, x);
+}
+
+// The whole V-cycle on levels 0..top of the descriptor table in one
+// workgroup: every step is a loop over its rows followed by a workgroup
+// barrier (the barrier orders the global-memory writes of the step before
+// the reads of the next one within the workgroup). Each level's result ends
+// in its descriptor's x buffer: the sweeps alternate between x and y, the
+// first one writing to whichever makes the last one land in x.
+constexpr int TAIL_NT = 1024;
+__global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __restrict__ lv,
+                                                     int32_t top, int32_t nu, float omega,
+                                                     const double* __restrict__ cinv,
+                                                     int32_t dense, const int* iflags)
+{
+    if (iflags && iflags[0]) return;
+    const int32_t tid = threadIdx.x;
+    // down: pre-smoothing, residual, restriction
+    for (int32_t l = top; l >= 1; --l) {
+        const phf_mg_dev_level L = lv[l];
+        const phf_mg_dev_level C = lv[l - 1];
+        // 2 nu - 1 sweeps follow the first: it writes y when that count is odd
+        float* u = ((2 * nu - 1) & 1) ? L.y : L.x;
+        float* v = u == L.x ? L.y : L.x;
+        for (int32_t i = tid; i < L.n; i += TAIL_NT) row_smooth0(i, L.dinv, L.b, omega, u);
+        __syncthreads();
+        for (int32_t s = 1; s < nu; ++s) {
+            for (int32_t i = tid; i < L.n; i += TAIL_NT)
+                row_smooth(i, L.n, L.col, L.val, L.dinv, L.b, omega, u, v);
+            __syncthreads();
+            float* w = u;
+            u = v;
+            v = w;
+        }
+        for (int32_t i = tid; i < L.n; i += TAIL_NT) row_resid(i, L.n, L.col, L.val, L.b, u, L.r);
+        __syncthreads();
+        for (int32_t p = tid; p < L.nEc; p += TAIL_NT)
+            tri_restrict(p, L.nEc, L.rows9, L.ecode_c, L.r, L.t);
+        __syncthreads();
+        for (int32_t c = tid; c < C.n; c += TAIL_NT) row_collect(c, C.sel, L.t, C.b);
+        __syncthreads();
+    }
+    // coarsest level
+    {
+        const phf_mg_dev_level L = lv[0];
+        if (dense) {
+            for (int32_t i = tid; i < L.n; i += TAIL_NT) row_coarse(i, L.n, cinv, L.b, L.x);
+            __syncthreads();
+        } else {
+            // 1 + 40 sweeps from zero; 40 is even, so starting in x ends in x
+            float *u = L.x, *v = L.y;
+            for (int32_t i = tid; i < L.n; i += TAIL_NT) row_smooth0(i, L.dinv, L.b, omega, u);
+            __syncthreads();
+            for (int32_t s = 0; s < 40; ++s) {
+                for (int32_t i = tid; i < L.n; i += TAIL_NT)
+                    row_smooth(i, L.n, L.col, L.val, L.dinv, L.b, omega, u, v);
+                __syncthreads();
+                float* w = u;
+                u = v;
+                v = w;
+            }
+        }
+    }
+    // up: prolongation, post-smoothing
+    for (int32_t l = 1; l <= top; ++l) {
+        const phf_mg_dev_level L = lv[l];
+        const phf_mg_dev_level C = lv[l - 1];
+        // after the pre-smoothing the iterate is in the buffer nu - 1 swaps
+        // away from the first sweep's
+        float* u = ((2 * nu - 1) & 1) ? L.y : L.x;
+        if ((nu - 1) & 1) u = u == L.x ? L.y : L.x;
+        float* v = u == L.x ? L.y : L.x;
+        if (C.n > 0) {  // (uniform branch) no coarse unknowns: no correction
+            for (int32_t i = tid; i < L.n; i += TAIL_NT)
+                row_prolong(i, L.n, L.P_col, L.P_val, C.x, u);
+            __syncthreads();
+        }
+        for (int32_t s = 0; s < nu; ++s) {
+            for (int32_t i = tid; i < L.n; i += TAIL_NT)
+                row_smooth(i, L.n, L.col, L.val, L.dinv, L.b, omega, u, v);
+            __syncthreads();
+            float* w = u;
+            u = v;
+            v = w;
+        }
     }
 }
 
@@ -384,6 +514,7 @@ void phf_mg_destroy(phf_mg* mg)
     }
     phf_dfree(mg->cinv);
     phf_dfree(mg->cwork);
+    phf_dfree(mg->d_lv);
     delete mg;
 }
 
@@ -453,6 +584,34 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             TRY(phf_dmalloc(ctx, &mg->cinv, (size_t)mg->n0 * mg->n0, "coarse inverse"));
             TRY(phf_dmalloc(ctx, &mg->cwork, (size_t)mg->n0 * mg->n0, "coarse work"));
         }
+        // the small levels below the finest: one workgroup runs their cycle
+        mg->tail_top = 0;
+        while (mg->tail_top + 1 < nlev - 1 && mg->lev[mg->tail_top + 1].nf <= PHF_MG_TAIL_MAX)
+            ++mg->tail_top;
+        for (int l = 0; l <= mg->tail_top; ++l) {
+            const phf_mg_level& L = mg->lev[l];
+            phf_mg_dev_level& d = mg->h_lv[l];
+            d.n = L.nf;
+            d.col = L.ns->ell_col;
+            d.val = L.val32;
+            d.dinv = L.dinv32;
+            d.x = L.x;
+            d.y = L.y;
+            d.b = L.b;
+            d.r = L.r;
+            d.sel = L.sel;
+            if (l > 0) {
+                d.nEc = mg->lev[l - 1].mesh->nE;
+                d.P_col = L.P_col;
+                d.P_val = L.P_val;
+                d.rows9 = L.rows9;
+                d.t = L.t;
+                d.ecode_c = mg->lev[l - 1].mesh->ecode;
+            }
+        }
+        TRY(phf_dmalloc(ctx, &mg->d_lv, (size_t)mg->tail_top + 1, "multigrid level table"));
+        PHF_HIP(ctx, hipMemcpyAsync(mg->d_lv, mg->h_lv, sizeof(phf_mg_dev_level) * (mg->tail_top + 1),
+                                    hipMemcpyHostToDevice, ctx->stream));
         return PHF_OK;
     };
     int rc = body();
@@ -535,6 +694,12 @@ int vcycle(phf_mg* mg, int l, const double* r_top, const int* iflags)
 {
     phf_mg_level& L = mg->lev[l];
     phf_ctx* ctx = L.mesh->ctx;
+    if (l <= mg->tail_top) {
+        // this level and all below in one workgroup; the result is in L.x
+        PHF_LAUNCH(ctx, "k_mg_tail", k_mg_tail, 1, TAIL_NT, 0, mg->d_lv, (int32_t)l, mg->nu,
+                   (float)mg->omega, mg->cinv, mg->cinv ? 1 : 0, iflags);
+        return PHF_OK;
+    }
     const int32_t n = L.nf;
     if (n == 0) return PHF_OK;
     const unsigned g = grid_for(n);
