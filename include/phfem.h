@@ -252,17 +252,21 @@ int phf_spmv(phf_ctx* ctx, int32_t nrows, const int32_t* rowptr, const int32_t* 
 
 /* ---- saddle-point solve -------------------------------------------------
  * Solves M_vec W = F_vec, i.e. (K + D + delta M) U - C^T Lambda = F and
- * -C U = b_D (Section 3.5), for the system assembled into `sys`
- * (K, M, C, F, bD required; D if p != 0 -- only p = 0 is supported by the
- * conjugate-gradient method). The method is the null-space reduction of the
- * saddle system: the constraint -C U = b_D is parametrised by edge-midpoint
- * values (the lowest-order primal hybrid space is the Crouzeix-Raviart space,
- * Section 1), the projected operator is symmetric positive definite and is
- * solved by Jacobi-preconditioned CG with CSR SpMV kernels, and Lambda is
- * recovered element by element. U, Lambda: device, N and L doubles; Lambda
- * may be NULL. Synchronises the stream. Returns PHF_ENOCONV if rtol is not
- * reached in max_iter iterations (the iterate is still written). */
+ * -C U = b_D (Section 3.5), for the system assembled into `sys` (K, M, C, F,
+ * bD required; D as well when p != 0). The method is the null-space
+ * reduction of the saddle system: the constraint -C U = b_D is parametrised
+ * by edge-midpoint values (the lowest-order primal hybrid space is the
+ * Crouzeix-Raviart space, Section 1), the projected operator is assembled as
+ * a sparse matrix with five entries per row, and Lambda is recovered element
+ * by element. With p = 0 the projected operator is symmetric positive
+ * definite and conjugate gradients apply; p != 0 (convection) makes it
+ * nonsymmetric and needs BiCGSTAB (right-preconditioned). U, Lambda: device,
+ * N and L doubles; Lambda may be NULL. Synchronises the stream. Returns
+ * PHF_ENOCONV if rtol is not reached in max_iter iterations or BiCGSTAB
+ * breaks down (the iterate is still written), PHF_EINVAL for CG with p != 0
+ * or p != 0 without D. */
 #define PHF_SOLVER_NULLSPACE_CG 0
+#define PHF_SOLVER_NULLSPACE_BICGSTAB 1
 /* Preconditioners of the reduced operator: Jacobi (any mesh), or a V-cycle
  * over the chain of meshes the mesh was refined from by phf_mesh_refine
  * (edge-midpoint prolongation averaged across coarse edges, damped Jacobi
@@ -291,6 +295,18 @@ typedef struct {
 
 int phf_solve(phf_mesh* mesh, const phf_coeffs* coeffs, const phf_system* sys,
               const phf_solver_opts* opts, double* U, double* Lambda, phf_solve_stats* stats);
+
+/* ---- error norms ------------------------------------------------------------
+ * Broken H^1 seminorm and L^2 norm of u - U_h (the error columns of the
+ * tables of Sections 3.7 and 4.2): U_h is the discontinuous piecewise-linear
+ * function with vertex values U (device, N doubles; element m at 3m..3m+2),
+ * u the exact solution given by `u` at time t, of a kind with a closed-form
+ * gradient (PHF_FN_ZERO, CONST, SIN_COS, SIN_SIN, PAPER_U; others give
+ * PHF_EINVAL). Each triangle is integrated with a collapsed Gauss-Legendre
+ * rule of 5 x 5 points (exact for degree 8); the sums are reduced in a fixed
+ * order (deterministic). h1, l2: host outputs. Synchronises the stream. */
+int phf_error_norms(phf_mesh* mesh, const double* U, const phf_fn* u, double t, double* h1,
+                    double* l2);
 
 /* ---- Crank-Nicolson (Section 4) -----------------------------------------
  * M+ W^n = M- W^{n-1} + [k F^{n-1/2}; b_D^{n-1/2}] with

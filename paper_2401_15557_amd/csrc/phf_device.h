@@ -120,3 +120,33 @@ __device__ inline double phf_fn_eval(const phf_fn_dev& f, double x, double y, do
     default: return 0.0;
     }
 }
+
+// Gradient of the kinds that have one in closed form (ZERO, CONST, SIN_COS,
+// SIN_SIN, PAPER_U); the error norms accept only these.
+__device__ inline void phf_fn_grad(const phf_fn_dev& f, double x, double y, double t, double* gx,
+                                   double* gy)
+{
+    switch (f.kind) {
+    case PHF_FN_SIN_COS: {
+        const double a = f.c0 * exp(f.c1 * t) * PHF_PI;
+        *gx = a * cos(PHF_PI * x) * cos(PHF_PI * y);
+        *gy = -a * sin(PHF_PI * x) * sin(PHF_PI * y);
+        return;
+    }
+    case PHF_FN_SIN_SIN: {
+        const double a = f.c0 * exp(f.c1 * t) * PHF_PI;
+        *gx = a * cos(PHF_PI * x) * sin(PHF_PI * y);
+        *gy = a * sin(PHF_PI * x) * cos(PHF_PI * y);
+        return;
+    }
+    case PHF_FN_PAPER_U: {
+        const double tau = f.c0 + f.c1 * t;
+        *gx = tau * (1.0 - 2.0 * x) * (y - y * y);
+        *gy = tau * (x - x * x) * (1.0 - 2.0 * y);
+        return;
+    }
+    default:
+        *gx = 0.0;
+        *gy = 0.0;
+    }
+}

@@ -46,7 +46,10 @@ struct phf_ns {
     double* z = nullptr;
     double* p = nullptr;
     double* q = nullptr;
-    double* part = nullptr;       // 5 x 1024 partial sums
+    double* part = nullptr;       // P_NARR x 1024 partial sums
+    // BiCGSTAB only (allocated on first use): shadow residual, s, the
+    // preconditioned s, t
+    double *rh = nullptr, *s = nullptr, *sh = nullptr, *t = nullptr;
     double* scal = nullptr;       // device scalars
     int* iflags = nullptr;        // [0] done, [1] iterations
     bool have_operator = false;
@@ -58,10 +61,10 @@ enum { NS_RR = 0, NS_BB, NS_TOL2, NS_NSCAL = 8 };
 
 int phf_ns_create(phf_mesh* mesh, phf_ns** out);
 void phf_ns_destroy(phf_ns* ns);
-// Builds A_T, B, the ELL values, the Jacobi diagonal for A = cK K + cM M,
+// Builds A_T, B, the ELL values, the Jacobi diagonal for A = cK K + cD D + cM M,
 // and |E|/2 per multiplier row from the assembled C.
 int phf_ns_operator(phf_ns* ns, const double* K, const double* M, const double* C, double cK,
-                    double cM);
+                    double cM, const double* D = nullptr, double cD = 0.0);
 // Right-hand side reduction (rhs2 is the right-hand side of -C U = rhs2).
 int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2);
 // Starts CG from the current w (zero it first for a cold start).
@@ -71,6 +74,11 @@ int phf_ns_cg_iterate(phf_ns* ns, int32_t iters);
 // U = P (w + kv); mu = mu_scale * element-local multiplier recovery.
 int phf_ns_recover(phf_ns* ns, const double* rhs1, double* U, double* mu, double mu_scale);
 int phf_ns_zero_w(phf_ns* ns);
+// Right-preconditioned BiCGSTAB on the same reduced system (any A, also
+// nonsymmetric), with the same device-side scalars and convergence flag;
+// iflags[2] is set on a breakdown.
+int phf_ns_bicg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_every,
+                      int32_t* iters_out, double* relres_out, int* converged, int* breakdown);
 // Host convergence loop: cg_start + batches of check_every iterations.
 int phf_ns_cg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_every,
                     int32_t* iters_out, double* relres_out, int* converged);

@@ -56,10 +56,12 @@ __global__ __launch_bounds__(NT) void k_ns_ell(int32_t nf, const int32_t* __rest
     }
 }
 
-// A_T = cK K_T + cM M_T and B_T = P^T A_T P.
+// A_T = cK K_T + cD D_T + cM M_T (D nullable) and B_T = P^T A_T P; A_T need
+// not be symmetric.
 __global__ __launch_bounds__(NT) void k_ns_blocks(int32_t nE, const double* __restrict__ K,
-                                                  const double* __restrict__ M, double cK,
-                                                  double cM, double* __restrict__ Ablk,
+                                                  const double* __restrict__ M,
+                                                  const double* __restrict__ D, double cK,
+                                                  double cM, double cD, double* __restrict__ Ablk,
                                                   double* __restrict__ B)
 {
     int32_t m = blockIdx.x * NT + threadIdx.x;
@@ -68,6 +70,7 @@ __global__ __launch_bounds__(NT) void k_ns_blocks(int32_t nE, const double* __re
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         A[q] = cK * K[9 * (int64_t)m + q] + cM * M[9 * (int64_t)m + q];
+        if (D) A[q] += cD * D[9 * (int64_t)m + q];
         Ablk[9 * (int64_t)m + q] = A[q];
     }
     // AP[i][l] = rowsum_i(A) - 2 A[i][l]
@@ -200,7 +203,12 @@ __device__ inline double ell_row(int32_t r, int32_t nf, const int32_t* __restric
 }
 
 // Partial-sum layout in phf_ns::part (MAXB slots each).
-enum { P_RZ0 = 0, P_RZ1 = 1, P_PQ = 2, P_RR = 3, P_BB = 4, P_NARR = 5 };
+enum {
+    P_RZ0 = 0, P_RZ1 = 1, P_PQ = 2, P_RR = 3, P_BB = 4,
+    // BiCGSTAB: two parities each of (rh, r), (rh, v), (t, s), (t, t); scratch
+    P_RHO0 = 5, P_RV0 = 7, P_TS0 = 9, P_TT0 = 11, P_SCR = 13,
+    P_NARR = 14
+};
 
 // Sum of nb partials in a fixed order, broadcast to the whole block.
 __device__ inline double block_reduce_partials(const double* __restrict__ part, int32_t nb,
@@ -258,6 +266,7 @@ __global__ __launch_bounds__(NT) void k_cg_init_final(const double* __restrict__
         scal[NS_TOL2] = tol2;
         iflags[0] = (rr <= tol2 * bb) ? 1 : 0;
         iflags[1] = 0;
+        iflags[2] = 0;
     }
 }
 
@@ -400,6 +409,185 @@ __global__ __launch_bounds__(NT) void k_ns_recover_mu(int32_t L, const int32_t* 
         if (rc_) return rc_; \
     } while (0)
 
+
+// ---- BiCGSTAB (right-preconditioned), for nonsymmetric reduced operators ---
+//
+// Iteration i with parity k = i & 1; slot X[k] holds a partial sum of
+// iteration i, X[k ^ 1] the one of iteration i - 1:
+//   dir(i): (i > 0) test ||r_i||; rho_i = (rh, r_i) from RHO[k]; beta =
+//           (rho_i / rho_{i-1}) (alpha_{i-1} / omega_{i-1}); p = r + beta (p -
+//           omega_{i-1} v); with Jacobi ph = D^-1 p (else the V-cycle follows).
+//   v(i):   v = A ph; partial (rh, v) -> RV[k].
+//   s(i):   alpha_i = rho_i / (rh, v); s = r - alpha_i v; with Jacobi sh = D^-1 s.
+//   t(i):   t = A sh; partials (t, s) -> TS[k], (t, t) -> TT[k].
+//   x(i):   omega_i = (t, s) / (t, t); w += alpha_i ph + omega_i sh;
+//           r = s - omega_i t; partials (rh, r) -> RHO[k ^ 1], (r, r) -> RR.
+// A zero rho, (rh, v) or omega is a breakdown: every block sees the same
+// scalars, block 0 raises done and iflags[2], and the chain stops.
+
+__global__ __launch_bounds__(NT) void k_bi_init(int32_t nf, const int32_t* __restrict__ col,
+                                                const double* __restrict__ val,
+                                                const double* __restrict__ b,
+                                                const double* __restrict__ w,
+                                                double* __restrict__ r, double* __restrict__ rh,
+                                                double* __restrict__ p, double* __restrict__ v,
+                                                double* __restrict__ part)
+{
+    __shared__ double sh[NT / 64];
+    double s_rr = 0.0, s_bb = 0.0;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
+        const double ri = b[i] - ell_row(i, nf, col, val, w);
+        r[i] = ri;
+        rh[i] = ri;
+        p[i] = 0.0;
+        v[i] = 0.0;
+        s_rr = fma(ri, ri, s_rr);
+        s_bb = fma(b[i], b[i], s_bb);
+    }
+    const double t1 = phf_block_sum_f64<NT>(s_rr, sh);
+    const double t2 = phf_block_sum_f64<NT>(s_bb, sh);
+    if (threadIdx.x == 0) {
+        part[P_RHO0 * MAXB + blockIdx.x] = t1;
+        part[P_RR * MAXB + blockIdx.x] = t1;
+        part[P_BB * MAXB + blockIdx.x] = t2;
+    }
+}
+
+template <bool JAC>
+__global__ __launch_bounds__(NT) void k_bi_dir(int32_t nf, int32_t it, int32_t nb,
+                                               const double* __restrict__ r,
+                                               double* __restrict__ p, const double* __restrict__ v,
+                                               const double* __restrict__ dinv,
+                                               double* __restrict__ ph, const double* __restrict__ part,
+                                               double* scal, int* iflags)
+{
+    if (iflags[0]) return;
+    __shared__ double shm[NT / 64];
+    const int k = it & 1;
+    double beta = 0.0, om = 0.0;
+    const double rho = block_reduce_partials(part + (P_RHO0 + k) * MAXB, nb, shm);
+    bool brk = rho == 0.0;
+    if (it > 0) {
+        const double rr = block_reduce_partials(part + P_RR * MAXB, nb, shm);
+        const double bb = scal[NS_BB], tol2 = scal[NS_TOL2];
+        if (rr <= tol2 * bb) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                iflags[0] = 1;
+                scal[NS_RR] = rr;
+            }
+            return;
+        }
+        const double rho_o = block_reduce_partials(part + (P_RHO0 + (k ^ 1)) * MAXB, nb, shm);
+        const double rv_o = block_reduce_partials(part + (P_RV0 + (k ^ 1)) * MAXB, nb, shm);
+        const double ts_o = block_reduce_partials(part + (P_TS0 + (k ^ 1)) * MAXB, nb, shm);
+        const double tt_o = block_reduce_partials(part + (P_TT0 + (k ^ 1)) * MAXB, nb, shm);
+        om = tt_o != 0.0 ? ts_o / tt_o : 0.0;
+        brk = brk || om == 0.0 || rho_o == 0.0 || rv_o == 0.0;
+        if (!brk) beta = (rho / rho_o) * ((rho_o / rv_o) / om);
+        if (blockIdx.x == 0 && threadIdx.x == 0) scal[NS_RR] = rr;
+    }
+    if (brk) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            iflags[0] = 1;
+            iflags[2] = 1;
+        }
+        return;
+    }
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
+        const double pi = it > 0 ? fma(beta, fma(-om, v[i], p[i]), r[i]) : r[i];
+        p[i] = pi;
+        if (JAC) ph[i] = dinv[i] * pi;
+    }
+}
+
+// y = A x with one partial inner product (a, y) -> slot0, and optionally
+// (c, y) -> slot1 and (y, y) -> slot2.
+__global__ __launch_bounds__(NT) void k_bi_spmv(int32_t nf, const int32_t* __restrict__ col,
+                                                const double* __restrict__ val,
+                                                const double* __restrict__ x,
+                                                double* __restrict__ y, const double* __restrict__ a,
+                                                double* __restrict__ part, int slot0, int slot1,
+                                                const int* iflags)
+{
+    if (iflags[0]) return;
+    __shared__ double sh[NT / 64];
+    double s0 = 0.0, s1 = 0.0;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
+        const double yi = ell_row(i, nf, col, val, x);
+        y[i] = yi;
+        s0 = fma(a[i], yi, s0);
+        s1 = fma(yi, yi, s1);
+    }
+    const double t0 = phf_block_sum_f64<NT>(s0, sh);
+    const double t1 = phf_block_sum_f64<NT>(s1, sh);
+    if (threadIdx.x == 0) {
+        part[slot0 * MAXB + blockIdx.x] = t0;
+        if (slot1 >= 0) part[slot1 * MAXB + blockIdx.x] = t1;
+    }
+}
+
+template <bool JAC>
+__global__ __launch_bounds__(NT) void k_bi_s(int32_t nf, int32_t it, int32_t nb,
+                                             const double* __restrict__ r,
+                                             const double* __restrict__ v,
+                                             const double* __restrict__ dinv,
+                                             double* __restrict__ s, double* __restrict__ sh,
+                                             const double* __restrict__ part, int* iflags)
+{
+    if (iflags[0]) return;
+    __shared__ double shm[NT / 64];
+    const int k = it & 1;
+    const double rho = block_reduce_partials(part + (P_RHO0 + k) * MAXB, nb, shm);
+    const double rv = block_reduce_partials(part + (P_RV0 + k) * MAXB, nb, shm);
+    if (rv == 0.0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            iflags[0] = 1;
+            iflags[2] = 1;
+        }
+        return;
+    }
+    const double alpha = rho / rv;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
+        const double si = fma(-alpha, v[i], r[i]);
+        s[i] = si;
+        if (JAC) sh[i] = dinv[i] * si;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_bi_x(int32_t nf, int32_t it, int32_t nb,
+                                             double* __restrict__ w, double* __restrict__ r,
+                                             const double* __restrict__ rh,
+                                             const double* __restrict__ ph,
+                                             const double* __restrict__ s,
+                                             const double* __restrict__ sh,
+                                             const double* __restrict__ t,
+                                             double* __restrict__ part, int* iflags)
+{
+    if (iflags[0]) return;
+    __shared__ double shm[NT / 64];
+    const int k = it & 1;
+    const double rho = block_reduce_partials(part + (P_RHO0 + k) * MAXB, nb, shm);
+    const double rv = block_reduce_partials(part + (P_RV0 + k) * MAXB, nb, shm);
+    const double ts = block_reduce_partials(part + (P_TS0 + k) * MAXB, nb, shm);
+    const double tt = block_reduce_partials(part + (P_TT0 + k) * MAXB, nb, shm);
+    const double alpha = rho / rv, om = tt != 0.0 ? ts / tt : 0.0;
+    double s_rho = 0.0, s_rr = 0.0;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
+        w[i] = fma(om, sh[i], fma(alpha, ph[i], w[i]));
+        const double ri = fma(-om, t[i], s[i]);
+        r[i] = ri;
+        s_rho = fma(rh[i], ri, s_rho);
+        s_rr = fma(ri, ri, s_rr);
+    }
+    const double t0 = phf_block_sum_f64<NT>(s_rho, shm);
+    const double t1 = phf_block_sum_f64<NT>(s_rr, shm);
+    if (threadIdx.x == 0) {
+        part[(P_RHO0 + (k ^ 1)) * MAXB + blockIdx.x] = t0;
+        part[P_RR * MAXB + blockIdx.x] = t1;
+        if (blockIdx.x == 0) iflags[1] += 1;
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -414,6 +602,7 @@ void phf_ns_destroy(phf_ns* ns)
     phf_dfree(ns->b); phf_dfree(ns->w); phf_dfree(ns->r); phf_dfree(ns->z);
     phf_dfree(ns->p); phf_dfree(ns->q); phf_dfree(ns->part); phf_dfree(ns->scal);
     phf_dfree(ns->iflags);
+    phf_dfree(ns->rh); phf_dfree(ns->s); phf_dfree(ns->sh); phf_dfree(ns->t);
     delete ns;
 }
 
@@ -473,11 +662,11 @@ int phf_ns_create(phf_mesh* mesh, phf_ns** out)
 }
 
 int phf_ns_operator(phf_ns* ns, const double* K, const double* M, const double* C, double cK,
-                    double cM)
+                    double cM, const double* D, double cD)
 {
     phf_mesh* mesh = ns->mesh;
     phf_ctx* ctx = mesh->ctx;
-    PHF_LAUNCH(ctx, "k_ns_blocks", k_ns_blocks, nblk(ns->nE), NT, 0, ns->nE, K, M, cK, cM,
+    PHF_LAUNCH(ctx, "k_ns_blocks", k_ns_blocks, nblk(ns->nE), NT, 0, ns->nE, K, M, D, cK, cM, cD,
                ns->Ablk, ns->B);
     if (ns->nf > 0)
         PHF_LAUNCH(ctx, "k_ns_ellval", k_ns_ellval, nblk(ns->nf), NT, 0, ns->nf, ns->ell_col,
@@ -594,6 +783,94 @@ int phf_ns_cg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_eve
     return PHF_OK;
 }
 
+namespace {
+int bicg_start(phf_ns* ns, double rtol)
+{
+    phf_ctx* ctx = ns->mesh->ctx;
+    ns->next_it = 0;
+    if (ns->nf == 0) {
+        PHF_HIP(ctx, hipMemsetAsync(ns->iflags, 0, 4 * sizeof(int), ctx->stream));
+        return PHF_OK;
+    }
+    const size_t nf = ns->nf;
+    if (!ns->rh) {
+        TRY(phf_dmalloc(ctx, &ns->rh, nf, "solver shadow residual"));
+        TRY(phf_dmalloc(ctx, &ns->s, nf, "solver s"));
+        TRY(phf_dmalloc(ctx, &ns->sh, nf, "solver preconditioned s"));
+        TRY(phf_dmalloc(ctx, &ns->t, nf, "solver t"));
+    }
+    // p -> ns->p, ph -> ns->z, v -> ns->q
+    PHF_LAUNCH(ctx, "k_bi_init", k_bi_init, ns->nbv, NT, 0, ns->nf, ns->ell_col, ns->ell_val,
+               ns->b, ns->w, ns->r, ns->rh, ns->p, ns->q, ns->part);
+    PHF_LAUNCH(ctx, "k_cg_init_final", k_cg_init_final, 1, NT, 0, ns->part, ns->nbv, rtol * rtol,
+               ns->scal, ns->iflags);
+    return PHF_OK;
+}
+
+int bicg_iterate(phf_ns* ns, int32_t iters)
+{
+    phf_ctx* ctx = ns->mesh->ctx;
+    if (ns->nf == 0) return PHF_OK;
+    const bool mg = ns->mg && ns->mg_on;
+    for (int32_t q = 0; q < iters; ++q) {
+        const int32_t it = ns->next_it;
+        ns->next_it = it + 1 >= 2 ? 2 + ((it + 1) & 1) : it + 1;
+        const int k = it & 1;
+        if (mg)
+            PHF_LAUNCH(ctx, "k_bi_dir", k_bi_dir<false>, ns->nbv, NT, 0, ns->nf, it, ns->nbv,
+                       ns->r, ns->p, ns->q, ns->dinv, ns->z, ns->part, ns->scal, ns->iflags);
+        else
+            PHF_LAUNCH(ctx, "k_bi_dir", k_bi_dir<true>, ns->nbv, NT, 0, ns->nf, it, ns->nbv,
+                       ns->r, ns->p, ns->q, ns->dinv, ns->z, ns->part, ns->scal, ns->iflags);
+        if (mg) TRY(phf_mg_apply(ns->mg, ns->p, ns->z, ns->part + P_SCR * MAXB, ns->iflags));
+        PHF_LAUNCH(ctx, "k_bi_spmv", k_bi_spmv, ns->nbv, NT, 0, ns->nf, ns->ell_col, ns->ell_val,
+                   ns->z, ns->q, ns->rh, ns->part, P_RV0 + k, -1, ns->iflags);
+        if (mg)
+            PHF_LAUNCH(ctx, "k_bi_s", k_bi_s<false>, ns->nbv, NT, 0, ns->nf, it, ns->nbv, ns->r,
+                       ns->q, ns->dinv, ns->s, ns->sh, ns->part, ns->iflags);
+        else
+            PHF_LAUNCH(ctx, "k_bi_s", k_bi_s<true>, ns->nbv, NT, 0, ns->nf, it, ns->nbv, ns->r,
+                       ns->q, ns->dinv, ns->s, ns->sh, ns->part, ns->iflags);
+        if (mg) TRY(phf_mg_apply(ns->mg, ns->s, ns->sh, ns->part + P_SCR * MAXB, ns->iflags));
+        PHF_LAUNCH(ctx, "k_bi_spmv", k_bi_spmv, ns->nbv, NT, 0, ns->nf, ns->ell_col, ns->ell_val,
+                   ns->sh, ns->t, ns->s, ns->part, P_TS0 + k, P_TT0 + k, ns->iflags);
+        PHF_LAUNCH(ctx, "k_bi_x", k_bi_x, ns->nbv, NT, 0, ns->nf, it, ns->nbv, ns->w, ns->r,
+                   ns->rh, ns->z, ns->s, ns->sh, ns->t, ns->part, ns->iflags);
+    }
+    PHF_LAUNCH(ctx, "k_cg_check", k_cg_check, 1, NT, 0, ns->nbv, ns->part, ns->scal, ns->iflags);
+    return PHF_OK;
+}
+}  // namespace
+
+int phf_ns_bicg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_every,
+                      int32_t* iters_out, double* relres_out, int* converged, int* breakdown)
+{
+    phf_ctx* ctx = ns->mesh->ctx;
+    TRY(bicg_start(ns, rtol));
+    int32_t done_iters = 0;
+    int hf[3] = {0, 0, 0};
+    PHF_HIP(ctx, hipMemcpyAsync(hf, ns->iflags, 3 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    while (!hf[0] && done_iters < max_iter) {
+        int32_t n = std::min(check_every, max_iter - done_iters);
+        TRY(bicg_iterate(ns, n));
+        done_iters += n;
+        PHF_HIP(ctx, hipMemcpyAsync(hf, ns->iflags, 3 * sizeof(int), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    double sc[NS_NSCAL] = {0};
+    if (ns->nf > 0) {
+        PHF_HIP(ctx, hipMemcpyAsync(sc, ns->scal, sizeof(sc), hipMemcpyDeviceToHost, ctx->stream));
+        PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    if (iters_out) *iters_out = hf[1];
+    if (relres_out) *relres_out = sc[NS_BB] > 0 ? std::sqrt(sc[NS_RR] / sc[NS_BB]) : 0.0;
+    if (breakdown) *breakdown = ns->nf == 0 ? 0 : hf[2];
+    if (converged) *converged = ns->nf == 0 ? 1 : (hf[0] && !hf[2]);
+    return PHF_OK;
+}
+
 int phf_ns_set_precond(phf_ns* ns, int32_t precond, int32_t sweeps, double omega,
                        const phf_coeffs* co, double cK, double cM)
 {
@@ -633,9 +910,7 @@ extern "C" int phf_solve(phf_mesh* mesh, const phf_coeffs* co, const phf_system*
     phf_ctx* ctx = mesh->ctx;
     if (!co || !sys || !U || !sys->K || !sys->M || !sys->C || !sys->F || !sys->bD)
         return phf_set_error(ctx, PHF_EINVAL, "phf_solve: K, M, C, F, bD and U are required");
-    if (co->p[0] != 0.0 || co->p[1] != 0.0)
-        return phf_set_error(ctx, PHF_EINVAL,
-                             "phf_solve: the conjugate-gradient method needs p = 0 (symmetric system)");
+    const bool conv_term = co->p[0] != 0.0 || co->p[1] != 0.0;
     phf_solver_opts o{};
     o.method = PHF_SOLVER_NULLSPACE_CG;
     if (opts) o = *opts;
@@ -644,20 +919,30 @@ extern "C" int phf_solve(phf_mesh* mesh, const phf_coeffs* co, const phf_system*
     // a V-cycle iteration is long enough that testing after each one costs
     // less than the launches it would otherwise queue past convergence
     if (o.check_every <= 0) o.check_every = o.precond == PHF_PRECOND_MULTIGRID ? 1 : 8;
-    if (o.method != PHF_SOLVER_NULLSPACE_CG)
+    if (o.method != PHF_SOLVER_NULLSPACE_CG && o.method != PHF_SOLVER_NULLSPACE_BICGSTAB)
         return phf_set_error(ctx, PHF_EINVAL, "phf_solve: unknown method %d", o.method);
+    if (conv_term && o.method == PHF_SOLVER_NULLSPACE_CG)
+        return phf_set_error(ctx, PHF_EINVAL,
+                             "phf_solve: p != 0 makes the system nonsymmetric; use "
+                             "PHF_SOLVER_NULLSPACE_BICGSTAB");
+    if (conv_term && !sys->D)
+        return phf_set_error(ctx, PHF_EINVAL, "phf_solve: p != 0 needs the assembled D");
     if (o.precond != PHF_PRECOND_JACOBI && o.precond != PHF_PRECOND_MULTIGRID)
         return phf_set_error(ctx, PHF_EINVAL, "phf_solve: unknown preconditioner %d", o.precond);
     phf_ns* ns = nullptr;
     TRY(phf_ns_get(mesh, &ns));
-    TRY(phf_ns_operator(ns, sys->K, sys->M, sys->C, 1.0, co->delta));
+    TRY(phf_ns_operator(ns, sys->K, sys->M, sys->C, 1.0, co->delta, conv_term ? sys->D : nullptr,
+                        1.0));
     TRY(phf_ns_set_precond(ns, o.precond, o.mg_sweeps, o.mg_omega, co, 1.0, co->delta));
     TRY(phf_ns_rhs(ns, sys->F, sys->bD));
     TRY(phf_ns_zero_w(ns));
     int32_t iters = 0;
     double relres = 0;
-    int conv = 0;
-    TRY(phf_ns_cg_solve(ns, o.rtol, o.max_iter, o.check_every, &iters, &relres, &conv));
+    int conv = 0, brk = 0;
+    if (o.method == PHF_SOLVER_NULLSPACE_BICGSTAB)
+        TRY(phf_ns_bicg_solve(ns, o.rtol, o.max_iter, o.check_every, &iters, &relres, &conv, &brk));
+    else
+        TRY(phf_ns_cg_solve(ns, o.rtol, o.max_iter, o.check_every, &iters, &relres, &conv));
     TRY(phf_ns_recover(ns, sys->F, U, Lambda, 1.0));
     double srel = -1.0;
     if (o.saddle_residual && sys->S && Lambda) {
@@ -694,6 +979,11 @@ extern "C" int phf_solve(phf_mesh* mesh, const phf_coeffs* co, const phf_system*
         stats->rel_residual = relres;
         stats->saddle_rel_residual = srel;
     }
+    if (brk)
+        return phf_set_error(ctx, PHF_ENOCONV,
+                             "phf_solve: BiCGSTAB breakdown after %d iterations, relative "
+                             "residual %.3e",
+                             iters, relres);
     if (!conv)
         return phf_set_error(ctx, PHF_ENOCONV, "phf_solve: %d iterations, relative residual %.3e",
                              iters, relres);

@@ -26,6 +26,7 @@ PHF_FN_GRAD_SIN_COS, PHF_FN_GRAD_SIN_SIN = 4, 5
 PHF_FN_PAPER_U, PHF_FN_PAPER_F, PHF_FN_PAPER_FLUX = 6, 7, 8
 PHF_FN_EDGE_ARRAY = 100
 PHF_SOLVER_NULLSPACE_CG = 0
+PHF_SOLVER_NULLSPACE_BICGSTAB = 1
 PHF_PRECOND_JACOBI, PHF_PRECOND_MULTIGRID = 0, 1
 
 EXPORTED = (
@@ -36,6 +37,7 @@ EXPORTED = (
     "phf_mesh_get_info",
     "phf_mesh_topology", "phf_mesh_pattern", "phf_assemble", "phf_spmv", "phf_solve",
     "phf_cn_create", "phf_cn_set_state", "phf_cn_run", "phf_cn_get_state", "phf_cn_destroy",
+    "phf_error_norms",
 )
 
 
@@ -132,6 +134,8 @@ _SIGS = {
     "phf_cn_run": [_VP, ctypes.POINTER(phf_data), _I32, _I32, ctypes.POINTER(phf_solve_stats)],
     "phf_cn_get_state": [_VP, _VP, _VP, ctypes.POINTER(_D)],
     "phf_cn_destroy": [_VP],
+    "phf_error_norms": [_VP, _VP, ctypes.POINTER(phf_fn), _D, ctypes.POINTER(_D),
+                        ctypes.POINTER(_D)],
 }
 
 
@@ -348,8 +352,8 @@ def phf_spmv(ctx, nrows, rowptr, col, val, alpha, x, beta, y):
 
 def phf_solve(mesh, coeffs, system, U, Lam=None, rtol=1e-10, max_iter=20000, check_every=0,
               saddle_residual=False, raise_on_noconv=True, precond=PHF_PRECOND_JACOBI,
-              mg_sweeps=0, mg_omega=0.0):
-    o = phf_solver_opts(PHF_SOLVER_NULLSPACE_CG, int(max_iter), float(rtol), int(check_every),
+              mg_sweeps=0, mg_omega=0.0, method=PHF_SOLVER_NULLSPACE_CG):
+    o = phf_solver_opts(int(method), int(max_iter), float(rtol), int(check_every),
                         1 if saddle_residual else 0, int(precond), int(mg_sweeps),
                         float(mg_omega))
     st = phf_solve_stats()
@@ -358,6 +362,16 @@ def phf_solve(mesh, coeffs, system, U, Lam=None, rtol=1e-10, max_iter=20000, che
     if rc < 0 and (rc != PHF_ENOCONV or raise_on_noconv):
         raise PhfError(rc, "phf_solve", "")
     return st
+
+
+def phf_error_norms(mesh, U, u, t=0.0):
+    """(broken H1 seminorm, L2 norm) of u - U_h; u is a phf_fn."""
+    h1, l2 = _D(), _D()
+    rc = load().phf_error_norms(mesh, _ptr(U), ctypes.byref(u), float(t), ctypes.byref(h1),
+                                ctypes.byref(l2))
+    if rc < 0:
+        raise PhfError(rc, "phf_error_norms", "")
+    return h1.value, l2.value
 
 
 def phf_cn_create(mesh, coeffs, k, rtol=1e-10, max_iter=5000, iters_per_step=8,

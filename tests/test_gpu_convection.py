@@ -1,0 +1,185 @@
+"""GPU path with convection (p != 0, nonsymmetric reduced system, BiCGSTAB)
+and the device error norms: parity with the oracle, and the paper's Table 4
+reproduced end to end on the device."""
+import numpy as np
+import pytest
+
+from conftest import read_golden
+from paper_2401_15557_amd import meshgen as G
+
+pytestmark = pytest.mark.gpu
+PI = np.pi
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2401_15557_amd import phfem
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = phfem.Context(0)
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _u1(x, y, t):
+    return (x - x * x) * (y - y * y)
+
+
+def _gu1(x, y, t):
+    return (1 - 2 * x) * (y - y * y), (x - x * x) * (1 - 2 * y)
+
+
+def _example1(phfem):
+    """Example 1 of Section 3.7: A = I, p = [1, 1], delta = 1, u = (x-x^2)(y-y^2)."""
+    co = phfem.make_coeffs(p=(1.0, 1.0), delta=1.0)
+    d = phfem.make_data(phfem.make_fn(phfem.PHF_FN_PAPER_F, 1.0, 0.0),
+                        phfem.make_fn(phfem.PHF_FN_PAPER_FLUX, 1.0, 0.0),
+                        phfem.make_fn(phfem.PHF_FN_ZERO))
+    return co, d
+
+
+def _solve(ctx, phfem, dm, co, d, precond, rtol=1e-13):
+    import torch
+    s, t = phfem.alloc_system(dm, with_D=True, with_S=True)
+    phfem.phf_assemble(dm.handle, co, d, s)
+    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    Lam = torch.empty(max(dm.info.L, 1), dtype=torch.float64, device=ctx.device)
+    st = phfem.phf_solve(dm.handle, co, s, U, Lam, rtol=rtol, saddle_residual=True,
+                         method=phfem.PHF_SOLVER_NULLSPACE_BICGSTAB, precond=precond)
+    return st, U, Lam
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "multigrid"])
+def test_convection_solve_parity(ctx, oracle, precond):
+    """BiCGSTAB on the nonsymmetric reduced system against the oracle's LU of
+    the saddle system with K + D + delta M (paper mesh level 4)."""
+    from paper_2401_15557_amd import phfem
+    pc = phfem.PHF_PRECOND_MULTIGRID if precond == "multigrid" else phfem.PHF_PRECOND_JACOBI
+    m = G.paper_square(4)
+    base = G.paper_square(0)
+    chain = [phfem.Mesh(ctx, base)]
+    for _ in range(4):
+        chain.append(chain[-1].refine())
+    dm = chain[-1]
+    co, d = _example1(phfem)
+    st, U, Lam = _solve(ctx, phfem, dm, co, d, pc)
+    print(f"{precond}: iterations {st.iterations} rel {st.rel_residual:.2e}", flush=True)
+    assert st.converged
+    Ug, Lg = U.cpu().numpy(), Lam.cpu().numpy()[:dm.info.L]
+    asm = oracle.assemble(m, oracle.mesh_tables(m), p=(1, 1),
+                          f=oracle.fn(oracle.FN_PAPER_F, 1, 0),
+                          g=oracle.fn(oracle.FN_PAPER_FLUX, 1, 0))
+    Uo, Lo = oracle.solve_saddle(asm, delta=1.0)
+    assert _rel(Ug, Uo) < 1e-9, _rel(Ug, Uo)
+    assert _rel(Lg, Lo) < 1e-8, _rel(Lg, Lo)
+    rp, col, val = oracle.saddle(asm, 1.0)
+    Fv = np.concatenate([asm["F"], asm["bD"]])
+    r = oracle.csr_matvec(rp, col, val, np.concatenate([Ug, Lg])) - Fv
+    assert np.linalg.norm(r) / np.linalg.norm(Fv) < 1e-11
+    assert 0 <= st.saddle_rel_residual < 1e-11
+    for c in reversed(chain):
+        c.close()
+
+
+def test_convection_needs_bicgstab_and_D(ctx):
+    import torch
+    from paper_2401_15557_amd import phfem
+    dm = phfem.Mesh(ctx, G.paper_square(2))
+    co, d = _example1(phfem)
+    s, t = phfem.alloc_system(dm, with_D=True)
+    phfem.phf_assemble(dm.handle, co, d, s)
+    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    with pytest.raises(phfem.PhfError) as ei:
+        phfem.phf_solve(dm.handle, co, s, U)  # conjugate gradients
+    assert ei.value.code == phfem.PHF_EINVAL
+    s.D = None
+    with pytest.raises(phfem.PhfError) as ei:
+        phfem.phf_solve(dm.handle, co, s, U, method=phfem.PHF_SOLVER_NULLSPACE_BICGSTAB)
+    assert ei.value.code == phfem.PHF_EINVAL
+    dm.close()
+
+
+def test_bicgstab_symmetric_matches_cg(ctx):
+    """On a symmetric system BiCGSTAB reaches the same solution as CG."""
+    import torch
+    from paper_2401_15557_amd import phfem
+    dm = phfem.Mesh(ctx, G.lshape(3))
+    co = phfem.make_coeffs(delta=0.5)
+    d = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * PI * PI, 0),
+                        phfem.make_fn(phfem.PHF_FN_CONST, 1), phfem.make_fn(phfem.PHF_FN_CONST, 1))
+    s, t = phfem.alloc_system(dm)
+    phfem.phf_assemble(dm.handle, co, d, s)
+    out = []
+    for meth in (phfem.PHF_SOLVER_NULLSPACE_CG, phfem.PHF_SOLVER_NULLSPACE_BICGSTAB):
+        U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+        st = phfem.phf_solve(dm.handle, co, s, U, rtol=1e-13, method=meth)
+        assert st.converged
+        out.append(U.cpu().numpy())
+    assert _rel(out[1], out[0]) < 1e-10
+    dm.close()
+
+
+def test_error_norms_parity(ctx, oracle):
+    """Device norms of a given U_h against the oracle's (same rule written
+    independently; they differ by rounding only)."""
+    import torch
+    from paper_2401_15557_amd import phfem
+    m = G.jittered_square(12, np.random.default_rng(5), 0.2)
+    rng = np.random.default_rng(6)
+    P = m.coords[m.elements]
+    U = (_u1(P[..., 0], P[..., 1], 0) + 1e-3 * rng.standard_normal(P.shape[:2])).ravel()
+    dm = phfem.Mesh(ctx, m)
+    Ud = torch.tensor(U, device=ctx.device)
+    h1, l2 = phfem.phf_error_norms(dm.handle, Ud, phfem.make_fn(phfem.PHF_FN_PAPER_U, 1.0, 0.0))
+    h1o, l2o = oracle.error_norms(m, U, _u1, _gu1)
+    assert h1 == pytest.approx(h1o, rel=1e-12)
+    assert l2 == pytest.approx(l2o, rel=1e-12)
+    # sin sin at t = 0.3 with the exp(c1 t) factor, against the oracle
+    c1 = -1.0
+    Us = (np.exp(c1 * 0.3) * np.sin(PI * P[..., 0]) * np.sin(PI * P[..., 1])).ravel()
+    h1, l2 = phfem.phf_error_norms(dm.handle, torch.tensor(Us, device=ctx.device),
+                                   phfem.make_fn(phfem.PHF_FN_SIN_SIN, 1.0, c1), t=0.3)
+    ue = lambda x, y, t: np.exp(c1 * t) * np.sin(PI * x) * np.sin(PI * y)
+    ge = lambda x, y, t: (np.exp(c1 * t) * PI * np.cos(PI * x) * np.sin(PI * y),
+                          np.exp(c1 * t) * PI * np.sin(PI * x) * np.cos(PI * y))
+    h1o, l2o = oracle.error_norms(m, Us, ue, ge, t=0.3)
+    assert h1 == pytest.approx(h1o, rel=1e-12)
+    assert l2 == pytest.approx(l2o, rel=1e-12)
+    with pytest.raises(phfem.PhfError):
+        phfem.phf_error_norms(dm.handle, Ud, phfem.make_fn(phfem.PHF_FN_PAPER_F, 1.0, 0.0))
+    dm.close()
+
+
+def test_table4_on_device(ctx):
+    """Example 1 on the device (refinement, assembly with convection and
+    reaction, BiCGSTAB + multigrid, device norms) reproduces Table 4: errors
+    within one unit of the printed digit, orders to 5e-5."""
+    from paper_2401_15557_amd import phfem
+    gold = np.array(read_golden("paper_table4.txt")[None])
+    co, d = _example1(phfem)
+    chain = [phfem.Mesh(ctx, G.paper_square(0))]
+    res = []
+    for lev in range(1, 6):
+        chain.append(chain[-1].refine())
+        dm = chain[-1]
+        st, U, _ = _solve(ctx, phfem, dm, co, d, phfem.PHF_PRECOND_MULTIGRID)
+        assert st.converged
+        h1, l2 = phfem.phf_error_norms(dm.handle, U, phfem.make_fn(phfem.PHF_FN_PAPER_U, 1.0, 0.0))
+        h = 2 * np.sqrt(1.0 / dm.info.nE)  # h = 2 sqrt|T| with |T| = 1/nE
+        print(f"level {lev}: its {st.iterations} H1 {h1:.6e} L2 {l2:.6e}", flush=True)
+        res.append((h, h1, l2))
+    for q, (h, h1, l2) in enumerate(res):
+        row = gold[q]
+        assert abs(h1 - row[1]) < 1e-4
+        ulp = 1e-4 if row[3] >= 1e-3 else 10.0 ** (np.floor(np.log10(row[3])) - 2)
+        assert abs(l2 - row[3]) < ulp
+        if q > 0:
+            hp, h1p, l2p = res[q - 1]
+            assert np.log(h1p / h1) / np.log(hp / h) == pytest.approx(row[2], abs=5e-5)
+            assert np.log(l2p / l2) / np.log(hp / h) == pytest.approx(row[4], abs=5e-5)
+    for c in reversed(chain):
+        c.close()
