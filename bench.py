@@ -156,6 +156,9 @@ def main():
                     help="size of the plain device copy run for counter calibration "
                          "(default 512 in assembly mode, none in full mode)")
     ap.add_argument("--precond", choices=("multigrid", "jacobi"), default="multigrid")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-reps", type=int, default=20)
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -381,6 +384,67 @@ def main():
                                f"CG + {a.precond}",
                       t_final=tf, max_nodal_error=err, **res)
 
+    # batched assembly (many uneven meshes in one launch) against one
+    # phf_assemble launch per mesh
+    out_batch = None
+    if not a.no_batch:
+        print(f"[bench] batched assembly ({a.batch_count} instances)", file=sys.stderr,
+              flush=True)
+        inst = G.batch_instances(a.batch_count, 1)
+        bm = [phfem.phf_mesh_create(h, mm.coords, mm.elements, mm.dirichlet, mm.neumann)
+              for mm, _ in inst]
+        binfo = [phfem.phf_mesh_get_info(x) for x in bm]
+        bco = [phfem.make_coeffs(A=(av, 0.0, 0.0, av)) for _, av in inst]
+        bdat = [phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * pi * pi * av, 0),
+                                phfem.make_fn(phfem.PHF_FN_GRAD_SIN_COS, av, 0),
+                                phfem.make_fn(phfem.PHF_FN_SIN_COS, 1, 0)) for _, av in inst]
+        bsys = [phfem.alloc_system_for(bi, dev)[0] for bi in binfo]
+        nE_tot = sum(bi.nE for bi in binfo)
+        bytes_tot = sum(algorithmic_bytes(bi, has_aT=False)["k_assemble"] for bi in binfo)
+        batch = phfem.phf_batch_create(h, bm)
+        tuning = phfem.phf_batch_tune(batch, bco, bdat, bsys, reps=5)
+        cfg = phfem.phf_batch_get_config(batch)
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            w0 = time.perf_counter()
+            e0.record()
+            for _ in range(a.batch_reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            w1 = time.perf_counter()
+            return e0.elapsed_time(e1) / a.batch_reps, 1e3 * (w1 - w0) / a.batch_reps
+
+        def per_mesh():
+            for x, co_i, d_i, s_i in zip(bm, bco, bdat, bsys):
+                phfem.phf_assemble(x, co_i, d_i, s_i)
+
+        ms_b, wall_b = timed(lambda: phfem.phf_batch_assemble(batch, bco, bdat, bsys))
+        ms_p, wall_p = timed(per_mesh)
+        phfem.phf_batch_destroy(batch)
+        for x in bm:
+            phfem.phf_mesh_destroy(x)
+        del bsys
+        out_batch = dict(
+            workload=(f"{a.batch_count} jittered unit squares, triangles log-uniform in "
+                      f"[2e3, 2e5] (seed 1), {nE_tot} triangles in total, per-instance "
+                      f"coefficient a ~ U[0.5, 2], fp64"),
+            nE_total=nE_tot, config={"tile": cfg[0], "blocks_per_cu": cfg[1]},
+            batched=dict(ms=round(ms_b, 4), Melem_per_s=round(nE_tot / ms_b / 1e3, 1),
+                         GB_per_s=round(bytes_tot / ms_b / 1e6, 1),
+                         frac_of_hbm_peak=round(bytes_tot / ms_b / 1e6 / HBM_PEAK_GBS, 4),
+                         host_wall_ms=round(wall_b, 4)),
+            one_launch_per_mesh=dict(ms=round(ms_p, 4), Melem_per_s=round(nE_tot / ms_p / 1e3, 1),
+                                     host_wall_ms=round(wall_p, 4)),
+            speedup=round(ms_p / ms_b, 2),
+            algorithmic_bytes=bytes_tot,
+            tuning=[{"tile": t_, "blocks_per_cu": b_, "ms": round(m_, 4)} for t_, b_, m_ in tuning])
+        print(f"[bench] batch: {out_batch['batched']} vs per mesh {out_batch['one_launch_per_mesh']}",
+              file=sys.stderr, flush=True)
+
     if a.copy_mib:
         # a plain copy of known size: the reference for hardware byte counters
         src = torch.ones(a.copy_mib << 17, dtype=torch.float64, device=dev)
@@ -420,6 +484,7 @@ def main():
                  "solve_rel_residual": mean["rel_residual"]},
         "assembly": out_asm,
         "cn": out_cn,
+        "batch": out_batch,
         "roofline": roof,
         # from the one fully traced (untimed) step
         "kernels_traced_step": {

@@ -245,6 +245,39 @@ typedef struct {
 int phf_assemble(phf_mesh* mesh, const phf_coeffs* coeffs, const phf_data* data,
                  const phf_system* out);
 
+/* ---- batched assembly --------------------------------------------------
+ * Many independent meshes of one context assembled in one launch (the
+ * per-triangle work of Definition 3.1 and Sections 3.4-3.5 is independent
+ * across meshes). The launch walks a work list of (mesh, tile) items, element
+ * tiles then multiplier-row tiles of each mesh; its shape is the batch's
+ * configuration: the tile size (64, 128 or 256 triangles or rows per
+ * workgroup) and the grid (blocks_per_cu = 0: one workgroup per item; k > 0:
+ * a persistent grid of k workgroups per compute unit striding over the list).
+ * phf_batch_assemble: coeffs[i], data[i], out[i] as for phf_assemble of
+ * meshes[i] (K, M, C, F, bD required; D and a_T given for all instances or
+ * none; S is not written). The outputs are bit-identical to phf_assemble of
+ * each mesh. phf_batch_tune times every candidate shape on the given
+ * arguments (a warm-up and `reps` launches each, HIP events on the context's
+ * stream), keeps the fastest as the batch's configuration and returns the
+ * candidates' average milliseconds in results (up to max_results; 12
+ * candidates); it writes the outputs as phf_batch_assemble does. The meshes
+ * must outlive the batch; the caller keeps ownership. */
+typedef struct phf_batch phf_batch;
+typedef struct {
+    int32_t tile;          /* 64, 128 or 256                                 */
+    int32_t blocks_per_cu; /* 0 = one workgroup per work item; else 1..64     */
+    double ms;             /* tuning: average milliseconds per launch        */
+} phf_batch_config;
+int phf_batch_create(phf_ctx* ctx, phf_mesh* const* meshes, int32_t n, phf_batch** out);
+int phf_batch_destroy(phf_batch* batch);
+int phf_batch_assemble(phf_batch* batch, const phf_coeffs* coeffs, const phf_data* data,
+                       const phf_system* out);
+int phf_batch_tune(phf_batch* batch, const phf_coeffs* coeffs, const phf_data* data,
+                   const phf_system* out, int32_t reps, phf_batch_config* results,
+                   int32_t max_results, int32_t* n_results);
+int phf_batch_get_config(const phf_batch* batch, phf_batch_config* cfg);
+int phf_batch_set_config(phf_batch* batch, const phf_batch_config* cfg);
+
 /* y = alpha * A x + beta * y for a CSR matrix (device arrays, int32 rowptr /
  * col, nrows rows). Used for residuals of the assembled operators. */
 int phf_spmv(phf_ctx* ctx, int32_t nrows, const int32_t* rowptr, const int32_t* col,

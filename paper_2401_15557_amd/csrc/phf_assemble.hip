@@ -15,6 +15,8 @@
 // 16-byte stores; M is regenerated from the staged areas; F from a staged
 // 3-value record. Multiplier rows gather their two end nodes (rows are in
 // edge-id order, so the larger end node is monotone).
+#include <algorithm>
+
 #include "phf_device.h"
 #include "phf_internal.h"
 
@@ -31,7 +33,8 @@ struct AsmArgs {
     const int32_t* elem_edges;
     const int2* row_nodes;
     const int32_t* row_edge;
-    const int32_t* C_tile;
+    const int32_t* C_tile;   // row pointer of every 256th row
+    const int32_t* C_rowptr;
     const uint64_t* neu_mask;
     double A00, A01, A10, A11, p0, p1;
     phf_fn_dev f, g, uD;
@@ -65,13 +68,13 @@ __device__ inline void fused_tile(int32_t b, int32_t nbE, int32_t nbR, bool* is_
     }
 }
 
-template <bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A>
+template <int TN, bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A>
 __device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK, double* shD,
                                     double* shA, double* shF)
 {
     const int tid = threadIdx.x;
-    const int32_t m0 = tile * TILE;
-    const int32_t nt = min(TILE, a.nE - m0);
+    const int32_t m0 = tile * TN;
+    const int32_t nt = min(TN, a.nE - m0);
     if (tid < nt) {
         const int32_t m = m0 + tid;
         const double2 P0 = a.exy[3 * (int64_t)m], P1 = a.exy[3 * (int64_t)m + 1];
@@ -179,7 +182,7 @@ __device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK,
         double2* K2 = reinterpret_cast<double2*>(a.K + 9 * (int64_t)m0);
         double2* M2 = reinterpret_cast<double2*>(a.M + 9 * (int64_t)m0);
         const double2* sK2 = reinterpret_cast<const double2*>(shK);
-        for (int32_t q = tid; q < cnt / 2; q += TILE) {
+        for (int32_t q = tid; q < cnt / 2; q += TN) {
             K2[q] = sK2[q];
             const int32_t v0 = 2 * q, v1 = 2 * q + 1;
             const int32_t el0 = v0 / 9, el1 = v1 / 9;
@@ -195,7 +198,7 @@ __device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK,
         if (WITH_D) {
             double2* D2 = reinterpret_cast<double2*>(a.D + 9 * (int64_t)m0);
             const double2* sD2 = reinterpret_cast<const double2*>(shD);
-            for (int32_t q = tid; q < cnt / 2; q += TILE) D2[q] = sD2[q];
+            for (int32_t q = tid; q < cnt / 2; q += TN) D2[q] = sD2[q];
             if ((cnt & 1) && tid == 0) a.D[9 * (int64_t)m0 + cnt - 1] = shD[cnt - 1];
         }
     }
@@ -203,19 +206,19 @@ __device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK,
         const int32_t cnt = 3 * nt;
         double2* F2 = reinterpret_cast<double2*>(a.F + 3 * (int64_t)m0);
         const double2* sF2 = reinterpret_cast<const double2*>(shF);
-        for (int32_t q = tid; q < cnt / 2; q += TILE) F2[q] = sF2[q];
+        for (int32_t q = tid; q < cnt / 2; q += TN) F2[q] = sF2[q];
         if ((cnt & 1) && tid == 0) a.F[3 * (int64_t)m0 + cnt - 1] = shF[cnt - 1];
     }
 }
 
-// A row tile: 256 consecutive multiplier rows. Their C values are one
+// A row tile: TN consecutive multiplier rows. Their C values are one
 // contiguous run starting at the tile's base pointer; each row's offset in it
 // is an exclusive scan of the row lengths (4 interior, 2 Dirichlet), the
 // Dirichlet rows being flagged by a negative first end node.
-template <bool MATS>
+template <int TN, bool MATS>
 __device__ inline void row_tile(const AsmArgs& a, int32_t tile, int32_t* shs)
 {
-    const int32_t r = tile * TILE + threadIdx.x;
+    const int32_t r = tile * TN + threadIdx.x;
     int2 kl = make_int2(0, 0);
     int32_t len = 0;
     if (r < a.L) {
@@ -223,10 +226,10 @@ __device__ inline void row_tile(const AsmArgs& a, int32_t tile, int32_t* shs)
         len = kl.x < 0 ? 2 : 4;
     }
     int32_t tot;
-    const int32_t off = phf_block_exscan_i32<TILE>(len, shs, &tot);
+    const int32_t off = phf_block_exscan_i32<TN>(len, shs, &tot);
     if (r >= a.L) return;
     const bool dirichlet = kl.x < 0;
-    const int32_t c0 = a.C_tile[tile] + off;
+    const int32_t c0 = (TN == 256 ? a.C_tile[tile] : a.C_rowptr[tile * TN]) + off;
     const double2 Pk = a.xy[dirichlet ? ~kl.x : kl.x], Pl = a.xy[kl.y];
     const double dx = Pl.x - Pk.x, dy = Pl.y - Pk.y;
     const double len_e = sqrt(dx * dx + dy * dy);
@@ -256,8 +259,42 @@ __global__ __launch_bounds__(TILE) void k_assemble(AsmArgs a)
     bool is_elem;
     int32_t tile;
     fused_tile(blockIdx.x, a.nbE, a.nbR, &is_elem, &tile);
-    if (is_elem) element_tile<HAS_AT, MATS, WITH_D, GEN_A>(a, tile, shK, shD, shA, shF);
-    else row_tile<MATS>(a, tile, shs);
+    if (is_elem) element_tile<TILE, HAS_AT, MATS, WITH_D, GEN_A>(a, tile, shK, shD, shA, shF);
+    else row_tile<TILE, MATS>(a, tile, shs);
+}
+
+// ---- batched assembly -------------------------------------------------------
+// One launch over a work list of (instance, tile) items of many meshes:
+// item.y >= 0 is element tile item.y of instance item.x, item.y < 0 row tile
+// ~item.y. PERSIST = false: one workgroup per item; PERSIST = true: each
+// workgroup takes items blockIdx.x, blockIdx.x + gridDim.x, ... (the loop
+// costs about 25 more VGPRs, one wave per SIMD of occupancy). The instance
+// record is staged in LDS. The tile code is the single-mesh kernel's, so the
+// outputs are bit-identical to it.
+template <int TN, bool PERSIST, bool HAS_AT, bool WITH_D, bool GEN_A>
+__global__ __launch_bounds__(TN) void k_assemble_batch(const AsmArgs* __restrict__ args,
+                                                       const int2* __restrict__ work,
+                                                       int32_t nwork)
+{
+    __shared__ __align__(16) double shK[TN * 9];
+    __shared__ __align__(16) double shD[WITH_D ? TN * 9 : 2];
+    __shared__ double shA[TN];
+    __shared__ __align__(16) double shF[TN * 3];
+    __shared__ int32_t shs[TN / 64 + 1];
+    __shared__ AsmArgs sa;
+    static_assert(sizeof(AsmArgs) % 8 == 0 && sizeof(AsmArgs) / 8 <= TN, "record copy");
+    for (int32_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const int2 item = work[w];
+        if (threadIdx.x < sizeof(AsmArgs) / 8)
+            reinterpret_cast<uint64_t*>(&sa)[threadIdx.x] =
+                reinterpret_cast<const uint64_t*>(args + item.x)[threadIdx.x];
+        __syncthreads();
+        const AsmArgs& a = sa;
+        if (item.y >= 0) element_tile<TN, HAS_AT, true, WITH_D, GEN_A>(a, item.y, shK, shD, shA, shF);
+        else row_tile<TN, true>(a, ~item.y, shs);
+        if (!PERSIST) break;
+        __syncthreads();  // the next item reuses the shared arrays
+    }
 }
 
 // ---- saddle-matrix values -------------------------------------------------
@@ -351,27 +388,34 @@ int launch_assemble(phf_ctx* ctx, const AsmArgs& a)
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
+#define TRY(x)               \
+    do {                     \
+        int rc_ = (x);       \
+        if (rc_) return rc_; \
+    } while (0)
+
 }  // namespace
 
-int phf_assemble_impl(phf_mesh* mesh, const phf_coeffs* co, const phf_data* data,
-                      const phf_system* out, const int64_t* t_step, double t0, double dt)
+namespace {
+// Checks the arguments of one assembly and fills its kernel record.
+int make_args(phf_mesh* mesh, const phf_coeffs* co, const phf_data* data, const phf_system* out,
+              const char* fn, AsmArgs* pa)
 {
     phf_ctx* ctx = mesh->ctx;
-    if (!co || !data || !out) return phf_set_error(ctx, PHF_EINVAL, "phf_assemble: null argument");
+    if (!co || !data || !out) return phf_set_error(ctx, PHF_EINVAL, "%s: null argument", fn);
     if (!phf_fn_valid(data->f) || !phf_fn_valid(data->g) || !phf_fn_valid(data->uD))
-        return phf_set_error(ctx, PHF_EINVAL, "phf_assemble: unknown function kind or missing edge array");
+        return phf_set_error(ctx, PHF_EINVAL, "%s: unknown function kind or missing edge array", fn);
     const bool mats = out->K || out->M || out->C;
     if (mats && !(out->K && out->M && out->C))
-        return phf_set_error(ctx, PHF_EINVAL, "phf_assemble: K, M and C are written together");
+        return phf_set_error(ctx, PHF_EINVAL, "%s: K, M and C are written together", fn);
     if (!out->F || !out->bD)
-        return phf_set_error(ctx, PHF_EINVAL, "phf_assemble: F and bD are required");
+        return phf_set_error(ctx, PHF_EINVAL, "%s: F and bD are required", fn);
     const void* ptrs[] = {out->K, out->M, out->D, out->C, out->F, out->bD};
     for (const void* p : ptrs)
         if (p && !aligned16(p))
-            return phf_set_error(ctx, PHF_EINVAL, "phf_assemble: output buffers must be 16-byte aligned");
-    if (out->D && !mats)
-        return phf_set_error(ctx, PHF_EINVAL, "phf_assemble: D needs K, M and C");
-    AsmArgs a;
+            return phf_set_error(ctx, PHF_EINVAL, "%s: output buffers must be 16-byte aligned", fn);
+    if (out->D && !mats) return phf_set_error(ctx, PHF_EINVAL, "%s: D needs K, M and C", fn);
+    AsmArgs& a = *pa;
     a.nE = mesh->nE;
     a.L = mesh->L;
     a.nbE = (mesh->nE + TILE - 1) / TILE;
@@ -384,6 +428,7 @@ int phf_assemble_impl(phf_mesh* mesh, const phf_coeffs* co, const phf_data* data
     a.row_nodes = mesh->row_nodes;
     a.row_edge = mesh->row_edge;
     a.C_tile = mesh->C_tile;
+    a.C_rowptr = mesh->C_rowptr;
     a.neu_mask = mesh->neu_mask;
     a.A00 = co->A[0];
     a.A01 = co->A[1];
@@ -395,16 +440,35 @@ int phf_assemble_impl(phf_mesh* mesh, const phf_coeffs* co, const phf_data* data
     a.g = phf_fn_to_dev(data->g);
     a.uD = phf_fn_to_dev(data->uD);
     a.t = data->t;
-    a.t_step = t_step;
-    a.t0 = t0;
-    a.dt = dt;
+    a.t_step = nullptr;
+    a.t0 = 0.0;
+    a.dt = 0.0;
     a.K = out->K;
     a.M = out->M;
     a.D = out->D;
     a.C = out->C;
     a.F = out->F;
     a.bD = out->bD;
-    const bool genA = !(co->A[0] == 1.0 && co->A[1] == 0.0 && co->A[2] == 0.0 && co->A[3] == 1.0);
+    return PHF_OK;
+}
+
+bool general_A(const phf_coeffs* co)
+{
+    return !(co->A[0] == 1.0 && co->A[1] == 0.0 && co->A[2] == 0.0 && co->A[3] == 1.0);
+}
+}  // namespace
+
+int phf_assemble_impl(phf_mesh* mesh, const phf_coeffs* co, const phf_data* data,
+                      const phf_system* out, const int64_t* t_step, double t0, double dt)
+{
+    phf_ctx* ctx = mesh->ctx;
+    AsmArgs a;
+    TRY(make_args(mesh, co, data, out, "phf_assemble", &a));
+    a.t_step = t_step;
+    a.t0 = t0;
+    a.dt = dt;
+    const bool mats = out->K != nullptr;
+    const bool genA = general_A(co);
     const bool hasAT = co->a_T != nullptr;
     const bool withD = out->D != nullptr;
     int rc;
@@ -450,4 +514,261 @@ extern "C" int phf_assemble(phf_mesh* mesh, const phf_coeffs* coeffs, const phf_
 {
     if (!mesh) return PHF_EINVAL;
     return phf_assemble_impl(mesh, coeffs, data, out);
+}
+
+// ---------------------------------------------------------------------------
+// batched assembly
+// ---------------------------------------------------------------------------
+
+struct phf_batch {
+    phf_ctx* ctx = nullptr;
+    std::vector<phf_mesh*> meshes;
+    AsmArgs* h_args = nullptr;  // pinned staging of the per-instance records
+    AsmArgs* d_args = nullptr;
+    hipEvent_t args_ev = nullptr;  // the last upload of h_args
+    bool args_pending = false;
+    int2* d_work[3] = {nullptr, nullptr, nullptr};  // work lists for tiles 64, 128, 256
+    int32_t nwork[3] = {0, 0, 0};
+    int32_t tile = 256, blocks_per_cu = 0, ncu = 256;
+};
+
+namespace {
+int tile_index(int32_t tile) { return tile == 64 ? 0 : (tile == 128 ? 1 : (tile == 256 ? 2 : -1)); }
+
+// Work list for one tile size: per instance its element and row tiles,
+// interleaved in proportion as in the single-mesh launch.
+int batch_work(phf_batch* b, int ti)
+{
+    if (b->d_work[ti]) return PHF_OK;
+    const int32_t tn = 64 << ti;
+    std::vector<int2> w;
+    for (size_t i = 0; i < b->meshes.size(); ++i) {
+        const phf_mesh* m = b->meshes[i];
+        const int64_t ne = (m->nE + tn - 1) / tn, nr = (m->L + tn - 1) / tn, T = ne + nr;
+        for (int64_t q = 0; q < T; ++q) {
+            const int64_t e0 = q * ne / T, e1 = (q + 1) * ne / T;
+            w.push_back(make_int2((int32_t)i, e1 > e0 ? (int32_t)e0 : ~(int32_t)(q - e0)));
+        }
+    }
+    phf_ctx* ctx = b->ctx;
+    TRY(phf_dmalloc(ctx, &b->d_work[ti], std::max<size_t>(w.size(), 1), "batch work list"));
+    PHF_HIP(ctx, hipMemcpyAsync(b->d_work[ti], w.data(), sizeof(int2) * w.size(),
+                                hipMemcpyHostToDevice, ctx->stream));
+    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));  // w is released on return
+    b->nwork[ti] = (int32_t)w.size();
+    return PHF_OK;
+}
+
+template <int TN, bool HAS_AT, bool WITH_D, bool GEN_A>
+int launch_batch_t(phf_batch* b, int ti)
+{
+    phf_ctx* ctx = b->ctx;
+    const int32_t nw = b->nwork[ti];
+    if (nw == 0) return PHF_OK;
+    if (b->blocks_per_cu > 0) {
+        const int64_t grid = std::min<int64_t>(nw, (int64_t)b->blocks_per_cu * b->ncu);
+        PHF_LAUNCH(ctx, "k_assemble_batch", (k_assemble_batch<TN, true, HAS_AT, WITH_D, GEN_A>),
+                   (unsigned)grid, TN, 0, b->d_args, b->d_work[ti], nw);
+    } else {
+        PHF_LAUNCH(ctx, "k_assemble_batch", (k_assemble_batch<TN, false, HAS_AT, WITH_D, GEN_A>),
+                   (unsigned)nw, TN, 0, b->d_args, b->d_work[ti], nw);
+    }
+    return PHF_OK;
+}
+
+template <int TN>
+int launch_batch_tn(phf_batch* b, int ti, bool hasAT, bool withD, bool genA)
+{
+    if (hasAT) {
+        if (withD) return genA ? launch_batch_t<TN, true, true, true>(b, ti)
+                               : launch_batch_t<TN, true, true, false>(b, ti);
+        return genA ? launch_batch_t<TN, true, false, true>(b, ti)
+                    : launch_batch_t<TN, true, false, false>(b, ti);
+    }
+    if (withD) return genA ? launch_batch_t<TN, false, true, true>(b, ti)
+                           : launch_batch_t<TN, false, true, false>(b, ti);
+    return genA ? launch_batch_t<TN, false, false, true>(b, ti)
+                : launch_batch_t<TN, false, false, false>(b, ti);
+}
+
+// Validates and uploads the per-instance records; returns the variant flags.
+int batch_prepare(phf_batch* b, const phf_coeffs* co, const phf_data* data, const phf_system* out,
+                  bool* hasAT, bool* withD, bool* genA)
+{
+    phf_ctx* ctx = b->ctx;
+    if (!co || !data || !out) return phf_set_error(ctx, PHF_EINVAL, "phf_batch_assemble: null argument");
+    const size_t n = b->meshes.size();
+    if (b->args_pending) {
+        PHF_HIP(ctx, hipEventSynchronize(b->args_ev));  // h_args is free again
+        b->args_pending = false;
+    }
+    *hasAT = n > 0 && co[0].a_T != nullptr;
+    *withD = n > 0 && out[0].D != nullptr;
+    *genA = false;
+    for (size_t i = 0; i < n; ++i) {
+        TRY(make_args(b->meshes[i], &co[i], &data[i], &out[i], "phf_batch_assemble", &b->h_args[i]));
+        if (!out[i].K)
+            return phf_set_error(ctx, PHF_EINVAL, "phf_batch_assemble: instance %zu: K, M, C required", i);
+        if ((co[i].a_T != nullptr) != *hasAT || (out[i].D != nullptr) != *withD)
+            return phf_set_error(ctx, PHF_EINVAL,
+                                 "phf_batch_assemble: a_T and D must be given for all instances or none");
+        *genA = *genA || general_A(&co[i]);
+    }
+    // the variant choice of phf_assemble (D implies the general-A form), so
+    // that the outputs are bit-identical to it
+    *genA = *genA || *withD;
+    PHF_HIP(ctx, hipMemcpyAsync(b->d_args, b->h_args, sizeof(AsmArgs) * n, hipMemcpyHostToDevice,
+                                ctx->stream));
+    PHF_HIP(ctx, hipEventRecord(b->args_ev, ctx->stream));
+    b->args_pending = true;
+    return PHF_OK;
+}
+
+int batch_launch(phf_batch* b, bool hasAT, bool withD, bool genA)
+{
+    const int ti = tile_index(b->tile);
+    TRY(batch_work(b, ti));
+    switch (b->tile) {
+    case 64: return launch_batch_tn<64>(b, ti, hasAT, withD, genA);
+    case 128: return launch_batch_tn<128>(b, ti, hasAT, withD, genA);
+    default: return launch_batch_tn<256>(b, ti, hasAT, withD, genA);
+    }
+}
+}  // namespace
+
+extern "C" int phf_batch_destroy(phf_batch* b)
+{
+    if (!b) return PHF_EINVAL;
+    (void)hipStreamSynchronize(b->ctx->stream);
+    for (auto& w : b->d_work) phf_dfree(w);
+    phf_dfree(b->d_args);
+    if (b->h_args) (void)hipHostFree(b->h_args);
+    if (b->args_ev) (void)hipEventDestroy(b->args_ev);
+    delete b;
+    return PHF_OK;
+}
+
+extern "C" int phf_batch_create(phf_ctx* ctx, phf_mesh* const* meshes, int32_t n, phf_batch** out)
+{
+    if (!ctx || !out || n < 1 || !meshes) return PHF_EINVAL;
+    *out = nullptr;
+    for (int32_t i = 0; i < n; ++i)
+        if (!meshes[i] || meshes[i]->ctx != ctx)
+            return phf_set_error(ctx, PHF_EINVAL,
+                                 "phf_batch_create: mesh %d is null or of another context", i);
+    phf_batch* b = new (std::nothrow) phf_batch;
+    if (!b) return phf_set_error(ctx, PHF_ENOMEM, "host allocation failed");
+    b->ctx = ctx;
+    b->meshes.assign(meshes, meshes + n);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) ==
+            hipSuccess && ncu > 0)
+        b->ncu = ncu;
+    auto body = [&]() -> int {
+        PHF_HIP(ctx, hipHostMalloc((void**)&b->h_args, sizeof(AsmArgs) * n, hipHostMallocDefault));
+        TRY(phf_dmalloc(ctx, &b->d_args, (size_t)n, "batch records"));
+        PHF_HIP(ctx, hipEventCreateWithFlags(&b->args_ev, hipEventDisableTiming));
+        return PHF_OK;
+    };
+    int rc = body();
+    if (rc) {
+        phf_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return PHF_OK;
+}
+
+extern "C" int phf_batch_assemble(phf_batch* b, const phf_coeffs* co, const phf_data* data,
+                                  const phf_system* out)
+{
+    if (!b) return PHF_EINVAL;
+    bool hasAT, withD, genA;
+    TRY(batch_prepare(b, co, data, out, &hasAT, &withD, &genA));
+    return batch_launch(b, hasAT, withD, genA);
+}
+
+extern "C" int phf_batch_get_config(const phf_batch* b, phf_batch_config* cfg)
+{
+    if (!b || !cfg) return PHF_EINVAL;
+    cfg->tile = b->tile;
+    cfg->blocks_per_cu = b->blocks_per_cu;
+    cfg->ms = -1.0;
+    return PHF_OK;
+}
+
+extern "C" int phf_batch_set_config(phf_batch* b, const phf_batch_config* cfg)
+{
+    if (!b || !cfg) return PHF_EINVAL;
+    if (tile_index(cfg->tile) < 0 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64)
+        return phf_set_error(b->ctx, PHF_EINVAL,
+                             "phf_batch_set_config: tile must be 64, 128 or 256 and "
+                             "blocks_per_cu 0..64");
+    b->tile = cfg->tile;
+    b->blocks_per_cu = cfg->blocks_per_cu;
+    return PHF_OK;
+}
+
+extern "C" int phf_batch_tune(phf_batch* b, const phf_coeffs* co, const phf_data* data,
+                              const phf_system* out, int32_t reps, phf_batch_config* results,
+                              int32_t max_results, int32_t* n_results)
+{
+    if (!b) return PHF_EINVAL;
+    phf_ctx* ctx = b->ctx;
+    if (reps < 1) reps = 5;
+    bool hasAT, withD, genA;
+    TRY(batch_prepare(b, co, data, out, &hasAT, &withD, &genA));
+    static const int32_t tiles[] = {64, 128, 256};
+    static const int32_t bpcs[] = {0, 2, 4, 8};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PHF_HIP(ctx, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return phf_set_error(ctx, PHF_EHIP, "phf_batch_tune: event creation failed");
+    }
+    const int32_t keep_tile = b->tile, keep_bpc = b->blocks_per_cu;
+    int32_t best_tile = keep_tile, best_bpc = keep_bpc, cnt = 0;
+    double best = 1e300;
+    int rc = PHF_OK;
+    for (int32_t tile : tiles) {
+        for (int32_t bpc : bpcs) {
+            b->tile = tile;
+            b->blocks_per_cu = bpc;
+            rc = batch_launch(b, hasAT, withD, genA);  // warm-up (and work list)
+            if (rc) break;
+            if (hipEventRecord(e0, ctx->stream) != hipSuccess) {
+                rc = phf_set_error(ctx, PHF_EHIP, "phf_batch_tune: event record failed");
+                break;
+            }
+            for (int32_t r = 0; r < reps && !rc; ++r) rc = batch_launch(b, hasAT, withD, genA);
+            if (rc) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, ctx->stream) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = phf_set_error(ctx, PHF_EHIP, "phf_batch_tune: timing failed");
+                break;
+            }
+            const double avg = (double)ms / reps;
+            if (results && cnt < max_results) results[cnt] = {tile, bpc, avg};
+            ++cnt;
+            if (avg < best) {
+                best = avg;
+                best_tile = tile;
+                best_bpc = bpc;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        b->tile = keep_tile;
+        b->blocks_per_cu = keep_bpc;
+        return rc;
+    }
+    b->tile = best_tile;
+    b->blocks_per_cu = best_bpc;
+    if (n_results) *n_results = std::min(cnt, max_results);
+    return PHF_OK;
 }

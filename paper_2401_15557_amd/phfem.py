@@ -37,7 +37,8 @@ EXPORTED = (
     "phf_mesh_get_info",
     "phf_mesh_topology", "phf_mesh_pattern", "phf_assemble", "phf_spmv", "phf_solve",
     "phf_cn_create", "phf_cn_set_state", "phf_cn_run", "phf_cn_get_state", "phf_cn_destroy",
-    "phf_error_norms",
+    "phf_error_norms", "phf_batch_create", "phf_batch_destroy", "phf_batch_assemble",
+    "phf_batch_tune", "phf_batch_get_config", "phf_batch_set_config",
 )
 
 
@@ -98,6 +99,11 @@ class phf_cn_opts(ctypes.Structure):
                 ("mg_sweeps", ctypes.c_int32), ("mg_omega", ctypes.c_double)]
 
 
+class phf_batch_config(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+
 _lib = None
 _VP, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 _SIGS = {
@@ -136,6 +142,15 @@ _SIGS = {
     "phf_cn_destroy": [_VP],
     "phf_error_norms": [_VP, _VP, ctypes.POINTER(phf_fn), _D, ctypes.POINTER(_D),
                         ctypes.POINTER(_D)],
+    "phf_batch_create": [_VP, ctypes.POINTER(_VP), _I32, ctypes.POINTER(_VP)],
+    "phf_batch_destroy": [_VP],
+    "phf_batch_assemble": [_VP, ctypes.POINTER(phf_coeffs), ctypes.POINTER(phf_data),
+                           ctypes.POINTER(phf_system)],
+    "phf_batch_tune": [_VP, ctypes.POINTER(phf_coeffs), ctypes.POINTER(phf_data),
+                       ctypes.POINTER(phf_system), _I32, ctypes.POINTER(phf_batch_config), _I32,
+                       ctypes.POINTER(_I32)],
+    "phf_batch_get_config": [_VP, ctypes.POINTER(phf_batch_config)],
+    "phf_batch_set_config": [_VP, ctypes.POINTER(phf_batch_config)],
 }
 
 
@@ -372,6 +387,65 @@ def phf_error_norms(mesh, U, u, t=0.0):
     if rc < 0:
         raise PhfError(rc, "phf_error_norms", "")
     return h1.value, l2.value
+
+
+def _struct_array(typ, items):
+    arr = (typ * len(items))()
+    for i, it in enumerate(items):
+        ctypes.memmove(ctypes.byref(arr, i * ctypes.sizeof(typ)), ctypes.byref(it),
+                       ctypes.sizeof(typ))
+    return arr
+
+
+def phf_batch_create(ctx, meshes):
+    """meshes: phf_mesh handles of one context."""
+    arr = (_VP * len(meshes))(*meshes)
+    out = _VP()
+    _call("phf_batch_create", ctx, ctx, arr, len(meshes), ctypes.byref(out))
+    return out.value
+
+
+def phf_batch_destroy(batch):
+    rc = load().phf_batch_destroy(batch)
+    if rc < 0:
+        raise PhfError(rc, "phf_batch_destroy", "")
+
+
+def phf_batch_assemble(batch, coeffs, data, systems):
+    """Lists of phf_coeffs, phf_data and phf_system, one per mesh."""
+    rc = load().phf_batch_assemble(batch, _struct_array(phf_coeffs, coeffs),
+                                   _struct_array(phf_data, data),
+                                   _struct_array(phf_system, systems))
+    if rc < 0:
+        raise PhfError(rc, "phf_batch_assemble", "")
+
+
+def phf_batch_tune(batch, coeffs, data, systems, reps=5):
+    """Times every launch shape; returns [(tile, blocks_per_cu, ms)] and keeps
+    the fastest as the batch's configuration."""
+    res = (phf_batch_config * 32)()
+    n = _I32()
+    rc = load().phf_batch_tune(batch, _struct_array(phf_coeffs, coeffs),
+                               _struct_array(phf_data, data), _struct_array(phf_system, systems),
+                               int(reps), res, 32, ctypes.byref(n))
+    if rc < 0:
+        raise PhfError(rc, "phf_batch_tune", "")
+    return [(res[i].tile, res[i].blocks_per_cu, res[i].ms) for i in range(n.value)]
+
+
+def phf_batch_get_config(batch):
+    c = phf_batch_config()
+    rc = load().phf_batch_get_config(batch, ctypes.byref(c))
+    if rc < 0:
+        raise PhfError(rc, "phf_batch_get_config", "")
+    return c.tile, c.blocks_per_cu
+
+
+def phf_batch_set_config(batch, tile, blocks_per_cu):
+    c = phf_batch_config(int(tile), int(blocks_per_cu), 0.0)
+    rc = load().phf_batch_set_config(batch, ctypes.byref(c))
+    if rc < 0:
+        raise PhfError(rc, "phf_batch_set_config", "")
 
 
 def phf_cn_create(mesh, coeffs, k, rtol=1e-10, max_iter=5000, iters_per_step=8,

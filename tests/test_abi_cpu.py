@@ -43,9 +43,9 @@ def test_struct_sizes_match_header():
 #include <stddef.h>
 #include "phfem.h"
 int main(void){
- printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(phf_mesh_info), sizeof(phf_coeffs),
+ printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(phf_mesh_info), sizeof(phf_coeffs),
    sizeof(phf_fn), sizeof(phf_data), sizeof(phf_system), sizeof(phf_solver_opts),
-   sizeof(phf_solve_stats), sizeof(phf_cn_opts));
+   sizeof(phf_solve_stats), sizeof(phf_cn_opts), sizeof(phf_batch_config));
  printf("%zu %zu %zu %zu\n", offsetof(phf_data, g), offsetof(phf_data, t),
    offsetof(phf_solver_opts, rtol), offsetof(phf_mesh_info, nnz_K));
  return 0;}
@@ -59,7 +59,8 @@ int main(void){
     sizes = [int(v) for v in out[0].split()]
     offs = [int(v) for v in out[1].split()]
     mirror = [phfem.phf_mesh_info, phfem.phf_coeffs, phfem.phf_fn, phfem.phf_data,
-              phfem.phf_system, phfem.phf_solver_opts, phfem.phf_solve_stats, phfem.phf_cn_opts]
+              phfem.phf_system, phfem.phf_solver_opts, phfem.phf_solve_stats, phfem.phf_cn_opts,
+              phfem.phf_batch_config]
     assert sizes == [ctypes.sizeof(s) for s in mirror]
     assert offs == [phfem.phf_data.g.offset, phfem.phf_data.t.offset,
                     phfem.phf_solver_opts.rtol.offset, phfem.phf_mesh_info.nnz_K.offset]
