@@ -135,6 +135,79 @@ def cpu_baseline(level=7, repeat=2):
                        f"saddle {o['saddle_s']:.3f} solve {o['solve_s']:.3f}")}
 
 
+def serve_requests(G, phfem, count, seed):
+    """Mixed request stream: 70% elliptic on refined structured unit squares,
+    30% Crank-Nicolson on the refined paper mesh with 10-100 steps; final
+    sizes log-uniform in [1e3, 1e6] triangles."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    pi = np.pi
+    reqs = []
+    for _ in range(count):
+        target = np.exp(rng.uniform(np.log(1e3), np.log(1e6)))
+        if rng.uniform() < 0.7:
+            r = max(0, int(round(np.log(target / 32.0) / np.log(4.0))))
+            n = max(2, int(round(np.sqrt(target / (2.0 * 4 ** r)))))
+            a = rng.uniform(0.5, 2.0)
+            d = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * pi * pi, 0),
+                                phfem.make_fn(phfem.PHF_FN_GRAD_SIN_COS, 1, 0),
+                                phfem.make_fn(phfem.PHF_FN_SIN_COS, 1, 0))
+            reqs.append(phfem.make_request(phfem.PHF_REQ_ELLIPTIC, G.unit_square_structured(n),
+                                           refine=r, coeffs=phfem.make_coeffs(A=(a, 0, 0, a)),
+                                           data=d, rtol=1e-10))
+        else:
+            lev = int(min(9, max(4, round(np.log(target / 4.0) / np.log(4.0)))))
+            steps = int(rng.integers(10, 101))
+            d = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_SIN, 2 * pi * pi - 1, -1),
+                                phfem.make_fn(phfem.PHF_FN_GRAD_SIN_SIN, 1, -1),
+                                phfem.make_fn(phfem.PHF_FN_SIN_SIN, 1, -1))
+            reqs.append(phfem.make_request(phfem.PHF_REQ_CN, G.paper_square(0, bc="x_sides"),
+                                           refine=lev, data=d,
+                                           u0=phfem.make_fn(phfem.PHF_FN_SIN_SIN, 1, -1),
+                                           rtol=1e-10, k=1e-3, steps=steps))
+    return reqs
+
+
+def serve_run(phfem, reqs, rate, slots, seed):
+    """Open-loop Poisson arrivals at `rate` requests/s into a server with
+    `slots` slots; returns latency percentiles and throughput."""
+    import threading
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=len(reqs))
+    srv = phfem.phf_server_create(0, slots=slots)
+    ids = [None] * len(reqs)
+    t0 = time.perf_counter()
+
+    def submit():
+        t = t0
+        for q, r in enumerate(reqs):
+            t += gaps[q]
+            dt = t - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            ids[q] = phfem.phf_server_submit(srv, r)
+
+    th = threading.Thread(target=submit)
+    th.start()
+    th.join()
+    res = [phfem.phf_server_wait(srv, i) for i in ids]
+    t1 = time.perf_counter()
+    st = phfem.phf_server_query(srv)
+    phfem.phf_server_destroy(srv)
+    bad = [r.status for r in res if r.status != 0]
+    lat = np.array([r.latency_ms for r in res])
+    q = np.array([r.queue_ms for r in res])
+    return dict(rate_per_s=rate, slots=slots, requests=len(reqs), failed=len(bad),
+                p50_ms=round(float(np.percentile(lat, 50)), 3),
+                p99_ms=round(float(np.percentile(lat, 99)), 3),
+                mean_ms=round(float(lat.mean()), 3),
+                mean_queue_ms=round(float(q.mean()), 3),
+                solves_per_s=round(len(reqs) / (t1 - t0), 2),
+                peak_concurrent=int(st.peak_running),
+                triangles_per_s=round(sum(r.nE for r in res) / (t1 - t0), 1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +230,11 @@ def main():
                          "(default 512 in assembly mode, none in full mode)")
     ap.add_argument("--precond", choices=("multigrid", "jacobi"), default="multigrid")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-rates", type=str, default="20,40,80",
+                    help="Poisson arrival rates (requests/s) to sweep")
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-reps", type=int, default=20)
     a = ap.parse_args()
@@ -445,6 +523,30 @@ def main():
         print(f"[bench] batch: {out_batch['batched']} vs per mesh {out_batch['one_launch_per_mesh']}",
               file=sys.stderr, flush=True)
 
+    # serving: continuous batching against one request at a time
+    out_serve = None
+    if not a.no_serve:
+        print(f"[bench] serving ({a.serve_requests} requests)", file=sys.stderr, flush=True)
+        reqs = serve_requests(G, phfem, a.serve_requests, 2)
+        # warm-up (code objects, pools)
+        w = phfem.phf_server_create(0, slots=2)
+        for r in reqs[:4]:
+            phfem.phf_server_wait(w, phfem.phf_server_submit(w, r))
+        phfem.phf_server_destroy(w)
+        runs = []
+        for rate in [float(x) for x in a.serve_rates.split(",") if x]:
+            for slots in (1, a.serve_slots):
+                rr = serve_run(phfem, reqs, rate, slots, 3)
+                print(f"[bench] serve {rr}", file=sys.stderr, flush=True)
+                runs.append(rr)
+        out_serve = dict(
+            workload=(f"{a.serve_requests} requests (seed 2): 70% elliptic on refined structured "
+                      f"unit squares, 30% Crank-Nicolson (paper mesh, k = 1e-3, 10-100 steps); "
+                      f"final sizes log-uniform in [1e3, 1e6] triangles; Poisson arrivals; "
+                      f"slots = 1 is one request at a time, slots = {a.serve_slots} continuous "
+                      f"batching"),
+            runs=runs)
+
     if a.copy_mib:
         # a plain copy of known size: the reference for hardware byte counters
         src = torch.ones(a.copy_mib << 17, dtype=torch.float64, device=dev)
@@ -485,6 +587,7 @@ def main():
         "assembly": out_asm,
         "cn": out_cn,
         "batch": out_batch,
+        "serve": out_serve,
         "roofline": roof,
         # from the one fully traced (untimed) step
         "kernels_traced_step": {

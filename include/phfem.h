@@ -48,6 +48,7 @@ extern "C" {
 #define PHF_ENOCONV -6   /* Krylov solver hit max_iter before rtol             */
 #define PHF_EHIP -7      /* a HIP runtime call failed                          */
 #define PHF_ESTATE -8    /* call out of order (e.g. solve before assemble)     */
+#define PHF_ETIMEDOUT -9 /* phf_server_wait: the request is not finished yet  */
 
 typedef struct phf_ctx phf_ctx;
 typedef struct phf_mesh phf_mesh;
@@ -375,6 +376,79 @@ int phf_cn_run(phf_cn* cn, const phf_data* data, int32_t nsteps, int32_t use_gra
                phf_solve_stats* stats);
 int phf_cn_get_state(phf_cn* cn, double* U, double* Lambda, double* t);
 int phf_cn_destroy(phf_cn* cn);
+
+/* ---- serving ---------------------------------------------------------------
+ * A request server on one device: continuous batching of elliptic solves
+ * (Section 3) and Crank-Nicolson runs (Section 4) from independent callers.
+ * The server has `slots` workers, each with its own context (HIP stream and
+ * device memory pool) and host thread. A submitted request is copied (the
+ * caller may free its arrays on return) and waits until a slot is free and
+ * its estimated device footprint (about 1.2 KB per triangle of the refined
+ * mesh for an elliptic solve, 1.6 KB for Crank-Nicolson) fits the memory
+ * budget beside the running requests; the first waiting request in arrival
+ * order that fits is admitted (a request larger than the budget runs alone).
+ * Admitted requests run concurrently on their slots' streams. A request:
+ * the base mesh (host arrays, as phf_mesh_create) refined `refine` times on
+ * the device; the elliptic kind assembles (coeffs with a_T = NULL, analytic
+ * data) and solves by CG (multigrid preconditioner when refine > 0, else
+ * Jacobi) to rtol; the Crank-Nicolson kind starts from the edge-midpoint
+ * interpolant of u0 at data.t with Lambda = 0 and runs `steps` steps of size
+ * k with captured graphs. Optional outputs: U (host buffer of 3 nE 4^refine
+ * doubles, written before the request completes) and the error norms of
+ * phf_error_norms against `exact` at the final time (when exact is not ZERO
+ * or want_norms is set). The result records the status, the triangles of the
+ * solved mesh, CG iterations, final relative residual, the slot, and the
+ * queueing, running and total (submit to completion) milliseconds. A
+ * request's kernels and reductions do not depend on the other requests: its
+ * result is the same alone and in a mix. phf_server_wait blocks up to
+ * timeout_ms (negative: no limit) and returns PHF_ETIMEDOUT if the request is
+ * still unfinished; a result is collected once. phf_server_destroy finishes
+ * the queued requests first. */
+#define PHF_REQ_ELLIPTIC 0
+#define PHF_REQ_CN 1
+typedef struct phf_server phf_server;
+typedef struct {
+    int32_t slots;         /* concurrent requests (1..16); 0 = 4             */
+    int32_t reserved_;
+    int64_t memory_bytes;  /* admission budget; 0 = half the free device memory */
+} phf_server_opts;
+typedef struct {
+    int32_t kind;          /* PHF_REQ_*                                      */
+    int32_t refine;        /* device red refinements of the base mesh (0..12) */
+    const double* xy;      /* base mesh, host arrays as for phf_mesh_create  */
+    const int32_t* elem;
+    const int32_t* dir;
+    const int32_t* neu;
+    int32_t nC, nE, nD, nN;
+    phf_coeffs coeffs;     /* a_T must be NULL                               */
+    phf_data data;         /* analytic kinds; data.t: start time              */
+    phf_fn u0;             /* Crank-Nicolson initial value                   */
+    phf_fn exact;          /* exact solution for the error norms             */
+    double rtol;           /* solver tolerance; 0 = 1e-10                    */
+    double k;              /* Crank-Nicolson time step                       */
+    int32_t steps;         /* Crank-Nicolson steps                           */
+    int32_t want_norms;
+    double* U_out;         /* optional host output                           */
+} phf_request;
+typedef struct {
+    int32_t status;        /* PHF_OK or the failing call's code              */
+    int32_t nE;
+    int32_t iterations;
+    int32_t slot;
+    double rel_residual;
+    double h1, l2;         /* -1 when not computed                           */
+    double queue_ms, run_ms, latency_ms;
+} phf_result;
+typedef struct {
+    int32_t slots, running, peak_running, queued;
+    int64_t completed;
+    double budget_bytes, reserved_bytes, peak_reserved_bytes;
+} phf_server_stats;
+int phf_server_create(int device, const phf_server_opts* opts, phf_server** out);
+int phf_server_destroy(phf_server* server);
+int phf_server_submit(phf_server* server, const phf_request* req, int64_t* id);
+int phf_server_wait(phf_server* server, int64_t id, double timeout_ms, phf_result* result);
+int phf_server_query(phf_server* server, phf_server_stats* stats);
 
 #ifdef __cplusplus
 }

@@ -36,6 +36,7 @@ extern "C" const char* phf_status_str(int code)
     case PHF_ENOCONV: return "solver did not converge";
     case PHF_EHIP: return "HIP runtime error";
     case PHF_ESTATE: return "call out of order";
+    case PHF_ETIMEDOUT: return "timed out";
     default: return "unknown status";
     }
 }

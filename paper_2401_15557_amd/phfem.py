@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libphfem.so")
 
 PHF_OK, PHF_EINVAL, PHF_EORIENT, PHF_EMESH = 0, -1, -2, -3
 PHF_EBOUNDARY, PHF_ENOMEM, PHF_ENOCONV, PHF_EHIP, PHF_ESTATE = -4, -5, -6, -7, -8
+PHF_ETIMEDOUT = -9
+PHF_REQ_ELLIPTIC, PHF_REQ_CN = 0, 1
 PHF_HOST, PHF_DEVICE = 0, 1
 
 PHF_FN_ZERO, PHF_FN_CONST, PHF_FN_SIN_COS, PHF_FN_SIN_SIN = 0, 1, 2, 3
@@ -39,6 +41,8 @@ EXPORTED = (
     "phf_cn_create", "phf_cn_set_state", "phf_cn_run", "phf_cn_get_state", "phf_cn_destroy",
     "phf_error_norms", "phf_batch_create", "phf_batch_destroy", "phf_batch_assemble",
     "phf_batch_tune", "phf_batch_get_config", "phf_batch_set_config",
+    "phf_server_create", "phf_server_destroy", "phf_server_submit", "phf_server_wait",
+    "phf_server_query",
 )
 
 
@@ -104,6 +108,36 @@ class phf_batch_config(ctypes.Structure):
                 ("ms", ctypes.c_double)]
 
 
+class phf_server_opts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("memory_bytes", ctypes.c_int64)]
+
+
+class phf_request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("xy", ctypes.c_void_p), ("elem", ctypes.c_void_p), ("dir", ctypes.c_void_p),
+                ("neu", ctypes.c_void_p), ("nC", ctypes.c_int32), ("nE", ctypes.c_int32),
+                ("nD", ctypes.c_int32), ("nN", ctypes.c_int32), ("coeffs", phf_coeffs),
+                ("data", phf_data), ("u0", phf_fn), ("exact", phf_fn), ("rtol", ctypes.c_double),
+                ("k", ctypes.c_double), ("steps", ctypes.c_int32), ("want_norms", ctypes.c_int32),
+                ("U_out", ctypes.c_void_p)]
+
+
+class phf_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("nE", ctypes.c_int32),
+                ("iterations", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("h1", ctypes.c_double), ("l2", ctypes.c_double),
+                ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double)]
+
+
+class phf_server_stats(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("running", ctypes.c_int32),
+                ("peak_running", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("completed", ctypes.c_int64), ("budget_bytes", ctypes.c_double),
+                ("reserved_bytes", ctypes.c_double), ("peak_reserved_bytes", ctypes.c_double)]
+
+
 _lib = None
 _VP, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 _SIGS = {
@@ -151,6 +185,11 @@ _SIGS = {
                        ctypes.POINTER(_I32)],
     "phf_batch_get_config": [_VP, ctypes.POINTER(phf_batch_config)],
     "phf_batch_set_config": [_VP, ctypes.POINTER(phf_batch_config)],
+    "phf_server_create": [ctypes.c_int, ctypes.POINTER(phf_server_opts), ctypes.POINTER(_VP)],
+    "phf_server_destroy": [_VP],
+    "phf_server_submit": [_VP, ctypes.POINTER(phf_request), ctypes.POINTER(_I64)],
+    "phf_server_wait": [_VP, _I64, _D, ctypes.POINTER(phf_result)],
+    "phf_server_query": [_VP, ctypes.POINTER(phf_server_stats)],
 }
 
 
@@ -446,6 +485,72 @@ def phf_batch_set_config(batch, tile, blocks_per_cu):
     rc = load().phf_batch_set_config(batch, ctypes.byref(c))
     if rc < 0:
         raise PhfError(rc, "phf_batch_set_config", "")
+
+
+def _check(rc, name):
+    if rc < 0:
+        raise PhfError(rc, name, "")
+
+
+def phf_server_create(device=0, slots=4, memory_bytes=0):
+    out = _VP()
+    _check(load().phf_server_create(int(device), ctypes.byref(phf_server_opts(int(slots), 0,
+                                                                               int(memory_bytes))),
+                                    ctypes.byref(out)), "phf_server_create")
+    return out.value
+
+
+def phf_server_destroy(server):
+    _check(load().phf_server_destroy(server), "phf_server_destroy")
+
+
+def make_request(kind, mesh, refine=0, coeffs=None, data=None, u0=None, exact=None, rtol=1e-10,
+                 k=0.0, steps=0, want_norms=False, U_out=None):
+    """A phf_request for a meshgen.Mesh base mesh (host arrays are copied by
+    phf_server_submit, so they only need to live until it returns)."""
+    import numpy as np
+    r = phf_request()
+    r.kind, r.refine = int(kind), int(refine)
+    xy = np.ascontiguousarray(mesh.coords, np.float64)
+    el = np.ascontiguousarray(mesh.elements, np.int32)
+    di = np.ascontiguousarray(mesh.dirichlet, np.int32).reshape(-1, 2)
+    ne = np.ascontiguousarray(mesh.neumann, np.int32).reshape(-1, 2)
+    r.xy, r.elem = xy.ctypes.data, el.ctypes.data
+    r.dir = di.ctypes.data if len(di) else None
+    r.neu = ne.ctypes.data if len(ne) else None
+    r.nC, r.nE, r.nD, r.nN = len(xy), len(el), len(di), len(ne)
+    r.coeffs = coeffs if coeffs is not None else make_coeffs()
+    r.data = data if data is not None else make_data()
+    r.u0 = u0 if u0 is not None else make_fn()
+    r.exact = exact if exact is not None else make_fn()
+    r.rtol, r.k, r.steps = float(rtol), float(k), int(steps)
+    r.want_norms = 1 if want_norms else 0
+    r.U_out = U_out.ctypes.data if U_out is not None else None
+    r._keep = (xy, el, di, ne, U_out)
+    return r
+
+
+def phf_server_submit(server, req):
+    i = _I64()
+    _check(load().phf_server_submit(server, ctypes.byref(req), ctypes.byref(i)),
+           "phf_server_submit")
+    return i.value
+
+
+def phf_server_wait(server, rid, timeout_ms=-1.0):
+    """The phf_result of request rid, or None on PHF_ETIMEDOUT."""
+    res = phf_result()
+    rc = load().phf_server_wait(server, int(rid), float(timeout_ms), ctypes.byref(res))
+    if rc == PHF_ETIMEDOUT:
+        return None
+    _check(rc, "phf_server_wait")
+    return res
+
+
+def phf_server_query(server):
+    st = phf_server_stats()
+    _check(load().phf_server_query(server, ctypes.byref(st)), "phf_server_query")
+    return st
 
 
 def phf_cn_create(mesh, coeffs, k, rtol=1e-10, max_iter=5000, iters_per_step=8,

@@ -43,9 +43,11 @@ def test_struct_sizes_match_header():
 #include <stddef.h>
 #include "phfem.h"
 int main(void){
- printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(phf_mesh_info), sizeof(phf_coeffs),
-   sizeof(phf_fn), sizeof(phf_data), sizeof(phf_system), sizeof(phf_solver_opts),
-   sizeof(phf_solve_stats), sizeof(phf_cn_opts), sizeof(phf_batch_config));
+ printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(phf_mesh_info),
+   sizeof(phf_coeffs), sizeof(phf_fn), sizeof(phf_data), sizeof(phf_system),
+   sizeof(phf_solver_opts), sizeof(phf_solve_stats), sizeof(phf_cn_opts),
+   sizeof(phf_batch_config), sizeof(phf_server_opts), sizeof(phf_request),
+   sizeof(phf_result), sizeof(phf_server_stats));
  printf("%zu %zu %zu %zu\n", offsetof(phf_data, g), offsetof(phf_data, t),
    offsetof(phf_solver_opts, rtol), offsetof(phf_mesh_info, nnz_K));
  return 0;}
@@ -60,7 +62,8 @@ int main(void){
     offs = [int(v) for v in out[1].split()]
     mirror = [phfem.phf_mesh_info, phfem.phf_coeffs, phfem.phf_fn, phfem.phf_data,
               phfem.phf_system, phfem.phf_solver_opts, phfem.phf_solve_stats, phfem.phf_cn_opts,
-              phfem.phf_batch_config]
+              phfem.phf_batch_config, phfem.phf_server_opts, phfem.phf_request,
+              phfem.phf_result, phfem.phf_server_stats]
     assert sizes == [ctypes.sizeof(s) for s in mirror]
     assert offs == [phfem.phf_data.g.offset, phfem.phf_data.t.offset,
                     phfem.phf_solver_opts.rtol.offset, phfem.phf_mesh_info.nnz_K.offset]
@@ -68,7 +71,7 @@ int main(void){
 
 def test_status_strings(lib):
     from paper_2401_15557_amd import phfem
-    for code in range(0, -9, -1):
+    for code in range(0, -10, -1):
         assert phfem.phf_status_str(code)
     assert phfem.phf_version().count(".") == 2
 
