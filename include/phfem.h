@@ -61,8 +61,9 @@ typedef enum { PHF_HOST = 0, PHF_DEVICE = 1 } phf_memspace;
 /* Creates a context on HIP device `device` whose kernels run on `hip_stream`
  * (a hipStream_t; NULL = the null stream). *out receives the handle. */
 int phf_create(phf_ctx** out, int device, void* hip_stream);
-/* Synchronises the stream and frees the context (not its meshes; device
- * memory of meshes still alive goes back to HIP when they are destroyed). */
+/* Synchronises the stream and frees the context. Returns PHF_ESTATE (and
+ * frees nothing) while meshes, Crank-Nicolson steppers or batches created on
+ * it are alive: destroy those first. */
 int phf_destroy(phf_ctx* ctx);
 /* Redirects later launches to another stream of the same device; waits for
  * the old stream first (cached device blocks were last used in its order). */
@@ -123,7 +124,8 @@ int phf_trace_dump(phf_ctx* ctx, char* buf, size_t len);
 int phf_mesh_create(phf_ctx* ctx, const double* xy, int32_t nC, const int32_t* elem, int32_t nE,
                     const int32_t* dir, int32_t nD, const int32_t* neu, int32_t nN,
                     phf_memspace ms, phf_mesh** out);
-/* Frees a mesh. PHF_ESTATE while meshes refined from it are alive. */
+/* Frees a mesh. PHF_ESTATE while meshes refined from it, Crank-Nicolson
+ * steppers or batches built on it are alive. */
 int phf_mesh_destroy(phf_mesh* mesh);
 
 /* One uniform red refinement on the device with the paper's numbering
@@ -270,6 +272,7 @@ typedef struct {
     double ms;             /* tuning: average milliseconds per launch        */
 } phf_batch_config;
 int phf_batch_create(phf_ctx* ctx, phf_mesh* const* meshes, int32_t n, phf_batch** out);
+/* (the meshes cannot be destroyed while the batch is alive: PHF_ESTATE) */
 int phf_batch_destroy(phf_batch* batch);
 int phf_batch_assemble(phf_batch* batch, const phf_coeffs* coeffs, const phf_data* data,
                        const phf_system* out);

@@ -530,6 +530,7 @@ struct phf_batch {
     int2* d_work[3] = {nullptr, nullptr, nullptr};  // work lists for tiles 64, 128, 256
     int32_t nwork[3] = {0, 0, 0};
     int32_t tile = 256, blocks_per_cu = 0, ncu = 256;
+    bool counted = false;  // registered with the meshes and context
 };
 
 namespace {
@@ -640,6 +641,10 @@ extern "C" int phf_batch_destroy(phf_batch* b)
 {
     if (!b) return PHF_EINVAL;
     (void)hipStreamSynchronize(b->ctx->stream);
+    if (b->counted) {
+        for (phf_mesh* m : b->meshes) m->n_users--;
+        b->ctx->n_objects--;
+    }
     for (auto& w : b->d_work) phf_dfree(w);
     phf_dfree(b->d_args);
     if (b->h_args) (void)hipHostFree(b->h_args);
@@ -675,6 +680,9 @@ extern "C" int phf_batch_create(phf_ctx* ctx, phf_mesh* const* meshes, int32_t n
         phf_batch_destroy(b);
         return rc;
     }
+    b->counted = true;
+    for (phf_mesh* m : b->meshes) m->n_users++;
+    ctx->n_objects++;
     *out = b;
     return PHF_OK;
 }

@@ -39,6 +39,7 @@ struct phf_cn {
     hipGraphExec_t gx[NG] = {};
     hipGraph_t g[NG] = {};
     phf_data gdata{};           // data the graphs were captured with
+    bool counted = false;       // registered with the mesh and context
 };
 
 namespace {
@@ -274,6 +275,10 @@ extern "C" int phf_cn_destroy(phf_cn* cn)
 {
     if (!cn) return PHF_EINVAL;
     (void)hipStreamSynchronize(cn->mesh->ctx->stream);
+    if (cn->counted) {
+        cn->mesh->n_users--;
+        cn->mesh->ctx->n_objects--;
+    }
     cn_drop_graph(cn);
     if (cn->ns) phf_ns_destroy(cn->ns);
     double* bufs[] = {cn->K, cn->M, cn->C, cn->Fs, cn->bs, cn->U, cn->Lam, cn->F0,
@@ -355,6 +360,9 @@ extern "C" int phf_cn_create(phf_mesh* mesh, const phf_coeffs* co, double k,
     }
     // the per-element coefficient is consumed by the assembly above
     cn->co.a_T = nullptr;
+    cn->counted = true;
+    mesh->n_users++;
+    ctx->n_objects++;
     *out = cn;
     return PHF_OK;
 }

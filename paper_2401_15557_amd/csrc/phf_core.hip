@@ -194,6 +194,11 @@ extern "C" int phf_create(phf_ctx** out, int device, void* hip_stream)
 extern "C" int phf_destroy(phf_ctx* ctx)
 {
     if (!ctx) return PHF_EINVAL;
+    if (ctx->n_objects > 0)
+        return phf_set_error(ctx, PHF_ESTATE,
+                             "phf_destroy: %lld meshes, steppers or batches of this context are "
+                             "still alive",
+                             (long long)ctx->n_objects);
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     for (auto& r : ctx->pending) {

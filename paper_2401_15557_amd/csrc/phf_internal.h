@@ -35,6 +35,7 @@ struct phf_ctx {
     int* d_flags = nullptr;                   // small device scratch for checks
     int64_t* h_pinned = nullptr;              // pinned host words for readback
     phf_pool* pool = nullptr;                 // caching device allocator
+    int64_t n_objects = 0;                    // live meshes, steppers, batches
 };
 
 int phf_set_error(phf_ctx* ctx, int code, const char* fmt, ...);
@@ -117,6 +118,7 @@ struct phf_mesh {
     phf_ns* ns = nullptr;          // cached solver workspace (lazy)
     phf_mesh* parent = nullptr;    // coarse mesh this one was refined from
     int32_t n_children = 0;        // meshes refined from this one, still alive
+    int32_t n_users = 0;           // Crank-Nicolson steppers and batches using it
     int32_t nC = 0, nE = 0, n_edges = 0, L = 0, nD = 0, nN = 0, n_int = 0, n_free = 0;
     int64_t nnz_C = 0, nnz_S = 0, nnz_R = 0;
     int64_t bytes = 0;

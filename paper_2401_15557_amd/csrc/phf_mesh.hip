@@ -766,6 +766,7 @@ int mesh_create(phf_ctx* ctx, const double* xy, int32_t nC, const int32_t* elem,
         delete M;
         return rc;
     }
+    ctx->n_objects++;
     *out = M;
     return PHF_OK;
 }
@@ -786,12 +787,14 @@ extern "C" int phf_mesh_create(phf_ctx* ctx, const double* xy, int32_t nC, const
 extern "C" int phf_mesh_destroy(phf_mesh* mesh)
 {
     if (!mesh) return PHF_EINVAL;
-    if (mesh->n_children > 0)
+    if (mesh->n_children > 0 || mesh->n_users > 0)
         return phf_set_error(mesh->ctx, PHF_ESTATE,
-                             "phf_mesh_destroy: %d refined meshes still refer to this mesh",
-                             mesh->n_children);
+                             "phf_mesh_destroy: %d refined meshes and %d steppers or batches "
+                             "still refer to this mesh",
+                             mesh->n_children, mesh->n_users);
     (void)hipStreamSynchronize(mesh->ctx->stream);
     if (mesh->parent) mesh->parent->n_children--;
+    mesh->ctx->n_objects--;
     mesh_free(mesh);
     delete mesh;
     return PHF_OK;

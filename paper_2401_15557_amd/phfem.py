@@ -598,9 +598,17 @@ class Context:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         self.handle = phf_create(device, stream.cuda_stream)
+        self._meshes = []  # weak references, in creation order
 
     def close(self):
+        """Destroys the context after the meshes made through it (newest
+        first, so refinements go before their parents)."""
         if self.handle:
+            for ref in reversed(self._meshes):
+                mesh = ref()
+                if mesh is not None:
+                    mesh.close()
+            self._meshes = []
             phf_destroy(self.handle)
             self.handle = None
 
@@ -621,12 +629,14 @@ class Mesh:
     """Device mesh built from a meshgen.Mesh (host arrays), or by refinement."""
 
     def __init__(self, ctx: Context, m=None, handle=None, parent=None):
+        import weakref
         self.ctx = ctx
-        self.parent = parent
         if handle is None:
             handle = phf_mesh_create(ctx.handle, m.coords, m.elements, m.dirichlet, m.neumann,
                                      PHF_HOST)
         self.handle = handle
+        self.parent = parent  # a refinement keeps its parent alive
+        ctx._meshes.append(weakref.ref(self))
         self.info = phf_mesh_get_info(self.handle)
 
     def refine(self):
