@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void k_boundary_check(
     int32_t e = blockIdx.x * 256 + threadIdx.x;
     if (e >= n_edges) return;
     bool bnd = edge_elems[e].y < 0;
-    if (bnd && mark[e] == 0) raise_flag(flags, FLAG_BOUNDARY, e);
+    if (mark && bnd && mark[e] == 0) raise_flag(flags, FLAG_BOUNDARY, e);
     int t = etype[e];
     nonN[e] = t != 2;
     nonD[e] = t != 1;
@@ -440,6 +440,200 @@ __global__ __launch_bounds__(256) void k_neu_mask(int32_t nE, const int32_t* __r
 
 // ---------------------------------------------------------------------------
 
+namespace {
+__global__ __launch_bounds__(256) void k_refine_nodes(int32_t nC, int32_t ne,
+                                                      const double2* __restrict__ xy,
+                                                      const int2* __restrict__ edge_nodes,
+                                                      double2* __restrict__ xy_f)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g < nC) {
+        xy_f[g] = xy[g];
+    } else if (g < (int64_t)nC + ne) {
+        const int2 kl = edge_nodes[g - nC];
+        const double2 a = xy[kl.x], b = xy[kl.y];
+        xy_f[g] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y + b.y));
+    }
+}
+
+// Children of element m: [M0 M1 M2] at m and [v_i, M_(i+2), M_(i+1)] at
+// nE + 3m + i, with M_i = nC + (edge opposite vertex i).
+__global__ __launch_bounds__(256) void k_refine_elems(int32_t nC, int32_t nE,
+                                                      const int4* __restrict__ elem4,
+                                                      const int32_t* __restrict__ elem_edges,
+                                                      int4* __restrict__ el_f)
+{
+    const int32_t m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= nE) return;
+    const int4 e = elem4[m];
+    const int32_t v[3] = {e.x, e.y, e.z};
+    int32_t M[3];
+    for (int i = 0; i < 3; ++i) M[i] = nC + elem_edges[3 * (int64_t)m + i];
+    el_f[m] = make_int4(M[0], M[1], M[2], 0);
+    for (int i = 0; i < 3; ++i)
+        el_f[(int64_t)nE + 3 * (int64_t)m + i] = make_int4(v[i], M[(i + 2) % 3], M[(i + 1) % 3], 0);
+}
+
+// Listed pair q of edge e: (a, M_e) at q and (M_e, b) at n + q.
+__global__ __launch_bounds__(256) void k_refine_pairs(int32_t nC, int32_t n,
+                                                      const int2* __restrict__ pairs,
+                                                      const int32_t* __restrict__ edges,
+                                                      int2* __restrict__ out)
+{
+    const int32_t q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const int2 ab = pairs[q];
+    const int32_t mid = nC + edges[q];
+    out[q] = make_int2(ab.x, mid);
+    out[n + q] = make_int2(mid, ab.y);
+}
+
+// ---- topology of a red-refined mesh from its parent's tables ----------------
+// Every fine edge has a midpoint node M_e = nC + e of a parent edge e as its
+// larger node (the parent's nodes keep their numbers, midpoints come after
+// them). Sorting by (larger node, smaller node) therefore groups the fine
+// edges by parent edge, in parent-edge order; within group e come first the
+// two halves of e (smaller node: the parent end nodes, in increasing order),
+// then the inner edges (M_e, M_e') of the parent triangles at e with e' < e,
+// in increasing e'. The children of parent p are p = [M0 M1 M2] and
+// nE + 3p + i = [v_i, M_(i+2), M_(i+1)]; an element's local edge l runs from
+// its vertex l+1 to vertex l+2. The fine element of lower number on a fine
+// edge (its T+) is the centre child for inner edges and the corner child of
+// the parent's T+ for halves.
+
+// Fine edges of group e (2 halves + inner edges with e' < e).
+__global__ __launch_bounds__(256) void k_rt_count(int32_t ne_c, const int2* __restrict__ edge_elems_c,
+                                                  const int8_t* __restrict__ led_c,
+                                                  const int8_t* __restrict__ ledTN_c,
+                                                  const int32_t* __restrict__ elem_edges_c,
+                                                  int32_t* __restrict__ cnt)
+{
+    const int32_t e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= ne_c) return;
+    const int2 tt = edge_elems_c[e];
+    int32_t c = 2;
+    for (int side = 0; side < 2; ++side) {
+        const int32_t T = side ? tt.y : tt.x;
+        if (T < 0) continue;
+        const int le = side ? ledTN_c[e] : led_c[e];
+        for (int d = 1; d <= 2; ++d)
+            if (elem_edges_c[3 * (int64_t)T + (le + d) % 3] < e) ++c;
+    }
+    cnt[e] = c;
+}
+
+__global__ __launch_bounds__(256) void k_rt_emit(
+    int32_t ne_c, int32_t nC_c, int32_t nE_c, const int2* __restrict__ edge_nodes_c,
+    const int2* __restrict__ edge_elems_c, const int8_t* __restrict__ led_c,
+    const int8_t* __restrict__ ledTN_c, const int32_t* __restrict__ elem_edges_c,
+    const int4* __restrict__ elem4_c, const int8_t* __restrict__ etype_c,
+    const int32_t* __restrict__ off, int2* __restrict__ edge_nodes, int2* __restrict__ edge_elems,
+    int32_t* __restrict__ elem_edges, int8_t* __restrict__ led, int8_t* __restrict__ ledTN,
+    int8_t* __restrict__ etype)
+{
+    const int32_t e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= ne_c) return;
+    const int32_t base = off[e], Me = nC_c + e;
+    const int2 tt = edge_elems_c[e];
+    const int2 kl = edge_nodes_c[e];
+    const int32_t lo = min(kl.x, kl.y);
+    const int8_t ty = etype_c[e];
+    // halves: per side the corner children at the two end vertices of e
+    int32_t he[2][2], hl[2][2];  // [half 0: at lo, 1: at hi][side]: fine element, local edge
+    int2 hdir[2] = {make_int2(0, 0), make_int2(0, 0)};  // direction in the T+ side's child
+    he[0][1] = he[1][1] = -1;
+    hl[0][1] = hl[1][1] = 0;
+    he[0][0] = he[1][0] = -1;
+    hl[0][0] = hl[1][0] = 0;
+    // inner edges of this group
+    int32_t ie[4], it[4], il[4];
+    int ni = 0;
+    for (int side = 0; side < 2; ++side) {
+        const int32_t T = side ? tt.y : tt.x;
+        if (T < 0) continue;
+        const int le = side ? ledTN_c[e] : led_c[e];
+        const int4 v4 = elem4_c[T];
+        const int32_t v[3] = {v4.x, v4.y, v4.z};
+        // vertex i1 = le+1: its corner child has e's half as local edge 2,
+        // running v_i1 -> M_e; vertex i2 = le+2: local edge 1, M_e -> v_i2
+        const int i1 = (le + 1) % 3, i2 = (le + 2) % 3;
+        const int h1 = v[i1] == lo ? 0 : 1, h2 = v[i2] == lo ? 0 : 1;
+        he[h1][side] = nE_c + 3 * T + i1;
+        hl[h1][side] = 2;
+        he[h2][side] = nE_c + 3 * T + i2;
+        hl[h2][side] = 1;
+        if (side == 0) {
+            hdir[h1] = make_int2(v[i1], Me);
+            hdir[h2] = make_int2(Me, v[i2]);
+        }
+        for (int d = 1; d <= 2; ++d) {
+            const int o = (le + d) % 3;
+            const int32_t e2 = elem_edges_c[3 * (int64_t)T + o];
+            if (e2 < e) {
+                ie[ni] = e2;
+                it[ni] = T;
+                il[ni] = 3 - le - o;  // the centre child's edge joining M_e and M_e2
+                ++ni;
+            }
+        }
+    }
+    for (int h = 0; h < 2; ++h) {
+        const int32_t f = base + h;
+        edge_nodes[f] = hdir[h];
+        edge_elems[f] = make_int2(he[h][0], he[h][1]);
+        led[f] = (int8_t)hl[h][0];
+        ledTN[f] = (int8_t)(he[h][1] >= 0 ? hl[h][1] : hl[h][0]);
+        etype[f] = ty;
+        elem_edges[3 * (int64_t)he[h][0] + hl[h][0]] = f;
+        if (he[h][1] >= 0) elem_edges[3 * (int64_t)he[h][1] + hl[h][1]] = f;
+    }
+    // inner edges in increasing e'
+    for (int a = 1; a < ni; ++a) {
+        const int32_t k0 = ie[a], k1 = it[a], k2 = il[a];
+        int b = a - 1;
+        while (b >= 0 && ie[b] > k0) {
+            ie[b + 1] = ie[b];
+            it[b + 1] = it[b];
+            il[b + 1] = il[b];
+            --b;
+        }
+        ie[b + 1] = k0;
+        it[b + 1] = k1;
+        il[b + 1] = k2;
+    }
+    for (int r = 0; r < ni; ++r) {
+        const int32_t f = base + 2 + r, T = it[r];
+        const int ls = il[r];
+        const int32_t corner = nE_c + 3 * T + ls;
+        edge_nodes[f] = make_int2(nC_c + elem_edges_c[3 * (int64_t)T + (ls + 1) % 3],
+                                  nC_c + elem_edges_c[3 * (int64_t)T + (ls + 2) % 3]);
+        edge_elems[f] = make_int2(T, corner);
+        led[f] = (int8_t)ls;
+        ledTN[f] = 0;
+        etype[f] = 0;
+        elem_edges[3 * (int64_t)T + ls] = f;
+        elem_edges[3 * (int64_t)corner] = f;
+    }
+}
+
+// Refined boundary edges in the refined pair order: pair q = (a, b) of parent
+// edge e becomes (a, M_e) at q and (M_e, b) at n + q.
+__global__ __launch_bounds__(256) void k_rt_bnd(int32_t n, const int2* __restrict__ pairs_c,
+                                                const int32_t* __restrict__ edges_c,
+                                                const int2* __restrict__ edge_nodes_c,
+                                                const int32_t* __restrict__ off,
+                                                int32_t* __restrict__ edges_f)
+{
+    const int32_t q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const int32_t e = edges_c[q];
+    const int2 ab = pairs_c[q], kl = edge_nodes_c[e];
+    const int32_t lo = min(kl.x, kl.y);
+    edges_f[q] = off[e] + (ab.x == lo ? 0 : 1);
+    edges_f[n + q] = off[e] + (ab.y == lo ? 0 : 1);
+}
+}  // namespace
+
 static void mesh_free(phf_mesh* m)
 {
     if (m->ns) phf_ns_destroy(m->ns);
@@ -558,6 +752,59 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
         if (rc_) return rc_;   \
     } while (0)
 
+// Coordinates, elements, boundary pairs, edge tables and edge types of the
+// red refinement of `P` (sizes already set in M), straight from P's tables.
+int refined_tables(phf_mesh* M, const phf_mesh* P, build_tmp* T, int32_t* ne_out)
+{
+    phf_ctx* ctx = M->ctx;
+    const int32_t ne_c = P->n_edges, nC_c = P->nC, nE_c = P->nE;
+    const int32_t nE = M->nE, nD = M->nD, nN = M->nN;
+    const int32_t ne = 2 * ne_c + 3 * nE_c;
+    TRY(phf_dmalloc(ctx, &M->xy, M->nC, "coordinates"));
+    TRY(phf_dmalloc(ctx, &M->elem4, nE, "elements"));
+    TRY(phf_dmalloc(ctx, &M->dir_pairs, nD, "Dirichlet pairs"));
+    TRY(phf_dmalloc(ctx, &M->neu_pairs, nN, "Neumann pairs"));
+    TRY(phf_dmalloc(ctx, &T->totals, 8, "totals"));
+    PHF_LAUNCH(ctx, "k_refine_nodes", k_refine_nodes, nblk((int64_t)M->nC), 256, 0, nC_c, ne_c,
+               P->xy, P->edge_nodes, M->xy);
+    PHF_LAUNCH(ctx, "k_refine_elems", k_refine_elems, nblk(nE_c), 256, 0, nC_c, nE_c, P->elem4,
+               P->elem_edges, M->elem4);
+    if (P->nD)
+        PHF_LAUNCH(ctx, "k_refine_pairs", k_refine_pairs, nblk(P->nD), 256, 0, nC_c, P->nD,
+                   P->dir_pairs, P->dir_edges, M->dir_pairs);
+    if (P->nN)
+        PHF_LAUNCH(ctx, "k_refine_pairs", k_refine_pairs, nblk(P->nN), 256, 0, nC_c, P->nN,
+                   P->neu_pairs, P->neu_edges, M->neu_pairs);
+    // edge groups per parent edge
+    TRY(phf_dmalloc(ctx, &T->ucount, (size_t)ne_c + 1, "group sizes"));
+    TRY(phf_dmalloc(ctx, &T->eoff, (size_t)ne_c + 1, "group offsets"));
+    PHF_LAUNCH(ctx, "k_rt_count", k_rt_count, nblk(ne_c), 256, 0, ne_c, P->edge_elems, P->led,
+               P->ledTN, P->elem_edges, T->ucount);
+    TRY(phf_scan_i32(ctx, T->ucount, T->eoff, ne_c, T->totals));
+    M->n_edges = ne;
+    TRY(phf_dmalloc(ctx, &M->edge_nodes, ne, "edge nodes"));
+    TRY(phf_dmalloc(ctx, &M->edge_elems, ne, "edge elements"));
+    TRY(phf_dmalloc(ctx, &M->elem_edges, 3 * (size_t)nE, "element edges"));
+    TRY(phf_dmalloc(ctx, &M->led, ne, "led"));
+    TRY(phf_dmalloc(ctx, &M->ledTN, ne, "ledTN"));
+    TRY(phf_dmalloc(ctx, &M->edge_type, ne, "edge types"));
+    TRY(phf_dmalloc(ctx, &M->dir_edges, nD, "Dirichlet edges"));
+    TRY(phf_dmalloc(ctx, &M->neu_edges, nN, "Neumann edges"));
+    PHF_LAUNCH(ctx, "k_rt_emit", k_rt_emit, nblk(ne_c), 256, 0, ne_c, nC_c, nE_c, P->edge_nodes,
+               P->edge_elems, P->led, P->ledTN, P->elem_edges, P->elem4, P->edge_type, T->eoff,
+               M->edge_nodes, M->edge_elems, M->elem_edges, M->led, M->ledTN, M->edge_type);
+    if (P->nD)
+        PHF_LAUNCH(ctx, "k_rt_bnd", k_rt_bnd, nblk(P->nD), 256, 0, P->nD, P->dir_pairs,
+                   P->dir_edges, P->edge_nodes, T->eoff, M->dir_edges);
+    if (P->nN)
+        PHF_LAUNCH(ctx, "k_rt_bnd", k_rt_bnd, nblk(P->nN), 256, 0, P->nN, P->neu_pairs,
+                   P->neu_edges, P->edge_nodes, T->eoff, M->neu_edges);
+    phf_dfree(T->ucount);
+    phf_dfree(T->eoff);
+    *ne_out = ne;
+    return PHF_OK;
+}
+
 // `parent`: the mesh this one is the red refinement of, or null. A refinement
 // of a valid mesh is valid, and its edge and boundary counts follow from the
 // parent's, so that path skips the validation read-backs.
@@ -570,75 +817,72 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     hipMemcpyKind kind = ms == PHF_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     int bits = 0, where = 0;
 
-    TRY(phf_dmalloc(ctx, &M->xy, nC, "coordinates"));
-    TRY(phf_dmalloc(ctx, &M->elem4, nE, "elements"));
-    TRY(phf_dmalloc(ctx, &T.raw, 3 * (size_t)nE, "element input"));
-    TRY(phf_dmalloc(ctx, &T.bcount, (size_t)nC + 1, "bucket counts"));
-    TRY(phf_dmalloc(ctx, &T.boff, (size_t)nC + 1, "bucket offsets"));
-    TRY(phf_dmalloc(ctx, &T.totals, 8, "totals"));
-    PHF_HIP(ctx, hipMemcpyAsync(M->xy, xy, sizeof(double2) * nC, kind, ctx->stream));
-    PHF_HIP(ctx, hipMemcpyAsync(T.raw, elem, sizeof(int32_t) * 3 * (size_t)nE, kind, ctx->stream));
-    PHF_HIP(ctx, hipMemsetAsync(T.bcount, 0, sizeof(int32_t) * ((size_t)nC + 1), ctx->stream));
-    TRY(reset_flags(ctx));
+    int32_t ne = 0;
+    if (parent) {
+        TRY(refined_tables(M, parent, &T, &ne));
+    } else {
+        TRY(phf_dmalloc(ctx, &M->xy, nC, "coordinates"));
+        TRY(phf_dmalloc(ctx, &M->elem4, nE, "elements"));
+        TRY(phf_dmalloc(ctx, &T.raw, 3 * (size_t)nE, "element input"));
+        TRY(phf_dmalloc(ctx, &T.bcount, (size_t)nC + 1, "bucket counts"));
+        TRY(phf_dmalloc(ctx, &T.boff, (size_t)nC + 1, "bucket offsets"));
+        TRY(phf_dmalloc(ctx, &T.totals, 8, "totals"));
+        PHF_HIP(ctx, hipMemcpyAsync(M->xy, xy, sizeof(double2) * nC, kind, ctx->stream));
+        PHF_HIP(ctx, hipMemcpyAsync(T.raw, elem, sizeof(int32_t) * 3 * (size_t)nE, kind, ctx->stream));
+        PHF_HIP(ctx, hipMemsetAsync(T.bcount, 0, sizeof(int32_t) * ((size_t)nC + 1), ctx->stream));
+        TRY(reset_flags(ctx));
 
-    // a1: validation + bucket counts by larger node
-    PHF_LAUNCH(ctx, "k_elem_init", k_elem_init, nblk(nE), 256, 0, T.raw, nE, nC, M->xy, M->elem4,
-               T.bcount, ctx->d_flags);
-    if (!parent) {
+        // a1: validation + bucket counts by larger node
+        PHF_LAUNCH(ctx, "k_elem_init", k_elem_init, nblk(nE), 256, 0, T.raw, nE, nC, M->xy, M->elem4,
+                   T.bcount, ctx->d_flags);
         TRY(read_flags(ctx, &bits, &where));
         TRY(flags_to_status(ctx, bits, where, "validation"));
-    }
-    phf_dfree(T.raw);
+        phf_dfree(T.raw);
 
-    // a2: counting sort of directed edges, per-bucket sort, unique count
-    TRY(phf_scan_i32(ctx, T.bcount, T.boff, nC + 1, nullptr));
-    TRY(phf_dmalloc(ctx, &T.keys, 3 * (size_t)nE, "edge keys"));
-    PHF_HIP(ctx, hipMemsetAsync(T.bcount, 0, sizeof(int32_t) * ((size_t)nC + 1), ctx->stream));
-    PHF_LAUNCH(ctx, "k_fill", k_fill, nblk(nE), 256, 0, M->elem4, nE, T.boff, T.bcount, T.keys);
-    TRY(phf_dmalloc(ctx, &T.ucount, (size_t)nC + 1, "unique counts"));
-    TRY(phf_dmalloc(ctx, &T.eoff, (size_t)nC + 1, "edge offsets"));
-    PHF_LAUNCH(ctx, "k_bucket_sort", k_bucket_sort, nblk(nC), 256, 0, T.keys, T.boff, nC,
-               M->elem4, T.ucount, ctx->d_flags);
-    if (!parent) {
+        // a2: counting sort of directed edges, per-bucket sort, unique count
+        TRY(phf_scan_i32(ctx, T.bcount, T.boff, nC + 1, nullptr));
+        TRY(phf_dmalloc(ctx, &T.keys, 3 * (size_t)nE, "edge keys"));
+        PHF_HIP(ctx, hipMemsetAsync(T.bcount, 0, sizeof(int32_t) * ((size_t)nC + 1), ctx->stream));
+        PHF_LAUNCH(ctx, "k_fill", k_fill, nblk(nE), 256, 0, M->elem4, nE, T.boff, T.bcount, T.keys);
+        TRY(phf_dmalloc(ctx, &T.ucount, (size_t)nC + 1, "unique counts"));
+        TRY(phf_dmalloc(ctx, &T.eoff, (size_t)nC + 1, "edge offsets"));
+        PHF_LAUNCH(ctx, "k_bucket_sort", k_bucket_sort, nblk(nC), 256, 0, T.keys, T.boff, nC,
+                   M->elem4, T.ucount, ctx->d_flags);
         TRY(read_flags(ctx, &bits, &where));
         TRY(flags_to_status(ctx, bits, where, "topology"));
-    }
-    PHF_HIP(ctx, hipMemsetAsync(T.ucount + nC, 0, sizeof(int32_t), ctx->stream));
-    TRY(phf_scan_i32(ctx, T.ucount, T.eoff, nC + 1, T.totals));
-    int32_t ne = 0;
-    if (parent)  // two halves per parent edge, three inner edges per parent element
-        ne = 2 * parent->n_edges + 3 * parent->nE;
-    else
+        PHF_HIP(ctx, hipMemsetAsync(T.ucount + nC, 0, sizeof(int32_t), ctx->stream));
+        TRY(phf_scan_i32(ctx, T.ucount, T.eoff, nC + 1, T.totals));
         TRY(read_i32(ctx, T.totals, &ne));
-    M->n_edges = ne;
-    TRY(phf_dmalloc(ctx, &M->edge_nodes, ne, "edge nodes"));
-    TRY(phf_dmalloc(ctx, &M->edge_elems, ne, "edge elements"));
-    TRY(phf_dmalloc(ctx, &M->elem_edges, 3 * (size_t)nE, "element edges"));
-    TRY(phf_dmalloc(ctx, &M->led, ne, "led"));
-    TRY(phf_dmalloc(ctx, &M->ledTN, ne, "ledTN"));
-    PHF_LAUNCH(ctx, "k_emit", k_emit, nblk(nC), 256, 0, T.keys, T.boff, T.eoff, nC, M->elem4,
-               M->edge_nodes, M->edge_elems, M->elem_edges, M->led, M->ledTN);
-    phf_dfree(T.keys);
-    phf_dfree(T.bcount);
-    phf_dfree(T.boff);
-    phf_dfree(T.ucount);
+        M->n_edges = ne;
+        TRY(phf_dmalloc(ctx, &M->edge_nodes, ne, "edge nodes"));
+        TRY(phf_dmalloc(ctx, &M->edge_elems, ne, "edge elements"));
+        TRY(phf_dmalloc(ctx, &M->elem_edges, 3 * (size_t)nE, "element edges"));
+        TRY(phf_dmalloc(ctx, &M->led, ne, "led"));
+        TRY(phf_dmalloc(ctx, &M->ledTN, ne, "ledTN"));
+        PHF_LAUNCH(ctx, "k_emit", k_emit, nblk(nC), 256, 0, T.keys, T.boff, T.eoff, nC, M->elem4,
+                   M->edge_nodes, M->edge_elems, M->elem_edges, M->led, M->ledTN);
+        phf_dfree(T.keys);
+        phf_dfree(T.bcount);
+        phf_dfree(T.boff);
+        phf_dfree(T.ucount);
 
-    // a3: boundary classification
-    TRY(phf_dmalloc(ctx, &M->edge_type, ne, "edge types"));
-    TRY(phf_dmalloc(ctx, &M->dir_edges, nD, "Dirichlet edges"));
-    TRY(phf_dmalloc(ctx, &M->neu_edges, nN, "Neumann edges"));
-    TRY(phf_dmalloc(ctx, &T.mark, ne, "edge marks"));
-    TRY(phf_dmalloc(ctx, &M->dir_pairs, nD, "Dirichlet pairs"));
-    TRY(phf_dmalloc(ctx, &M->neu_pairs, nN, "Neumann pairs"));
-    if (nD) PHF_HIP(ctx, hipMemcpyAsync(M->dir_pairs, dir, sizeof(int32_t) * 2 * (size_t)nD, kind, ctx->stream));
-    if (nN) PHF_HIP(ctx, hipMemcpyAsync(M->neu_pairs, neu, sizeof(int32_t) * 2 * (size_t)nN, kind, ctx->stream));
-    PHF_HIP(ctx, hipMemsetAsync(M->edge_type, 0, ne, ctx->stream));
-    PHF_HIP(ctx, hipMemsetAsync(T.mark, 0, sizeof(int32_t) * ne, ctx->stream));
-    TRY(reset_flags(ctx));
-    if (nD + nN > 0)
-        PHF_LAUNCH(ctx, "k_boundary_mark", k_boundary_mark, nblk(nD + nN), 256, 0,
-                   (const int32_t*)M->dir_pairs, nD, (const int32_t*)M->neu_pairs, nN, nC, T.eoff, M->edge_nodes, M->edge_elems, T.mark, M->edge_type,
-                   M->dir_edges, M->neu_edges, ctx->d_flags);
+        // a3: boundary classification
+        TRY(phf_dmalloc(ctx, &M->edge_type, ne, "edge types"));
+        TRY(phf_dmalloc(ctx, &M->dir_edges, nD, "Dirichlet edges"));
+        TRY(phf_dmalloc(ctx, &M->neu_edges, nN, "Neumann edges"));
+        TRY(phf_dmalloc(ctx, &T.mark, ne, "edge marks"));
+        TRY(phf_dmalloc(ctx, &M->dir_pairs, nD, "Dirichlet pairs"));
+        TRY(phf_dmalloc(ctx, &M->neu_pairs, nN, "Neumann pairs"));
+        if (nD) PHF_HIP(ctx, hipMemcpyAsync(M->dir_pairs, dir, sizeof(int32_t) * 2 * (size_t)nD, kind, ctx->stream));
+        if (nN) PHF_HIP(ctx, hipMemcpyAsync(M->neu_pairs, neu, sizeof(int32_t) * 2 * (size_t)nN, kind, ctx->stream));
+        PHF_HIP(ctx, hipMemsetAsync(M->edge_type, 0, ne, ctx->stream));
+        PHF_HIP(ctx, hipMemsetAsync(T.mark, 0, sizeof(int32_t) * ne, ctx->stream));
+        TRY(reset_flags(ctx));
+        if (nD + nN > 0)
+            PHF_LAUNCH(ctx, "k_boundary_mark", k_boundary_mark, nblk(nD + nN), 256, 0,
+                       (const int32_t*)M->dir_pairs, nD, (const int32_t*)M->neu_pairs, nN, nC, T.eoff, M->edge_nodes, M->edge_elems, T.mark, M->edge_type,
+                       M->dir_edges, M->neu_edges, ctx->d_flags);
+    }
     TRY(phf_dmalloc(ctx, &T.nonN, (size_t)ne + 1, "row indicator"));
     TRY(phf_dmalloc(ctx, &T.nonD, (size_t)ne + 1, "reduced indicator"));
     TRY(phf_dmalloc(ctx, &T.clen, (size_t)ne + 1, "C row lengths"));
@@ -801,63 +1045,9 @@ extern "C" int phf_mesh_destroy(phf_mesh* mesh)
 }
 
 // ---------------------------------------------------------------------------
-// uniform red refinement (Section 2.3, Listing 4)
+// uniform red refinement (Section 2.3, Listing 4); the kernels are with the
+// refined-mesh tables above
 // ---------------------------------------------------------------------------
-
-namespace {
-__global__ __launch_bounds__(256) void k_refine_nodes(int32_t nC, int32_t ne,
-                                                      const double2* __restrict__ xy,
-                                                      const int2* __restrict__ edge_nodes,
-                                                      double2* __restrict__ xy_f)
-{
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (g < nC) {
-        xy_f[g] = xy[g];
-    } else if (g < (int64_t)nC + ne) {
-        const int2 kl = edge_nodes[g - nC];
-        const double2 a = xy[kl.x], b = xy[kl.y];
-        xy_f[g] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y + b.y));
-    }
-}
-
-// Children of element m: [M0 M1 M2] at m and [v_i, M_(i+2), M_(i+1)] at
-// nE + 3m + i, with M_i = nC + (edge opposite vertex i).
-__global__ __launch_bounds__(256) void k_refine_elems(int32_t nC, int32_t nE,
-                                                      const int4* __restrict__ elem4,
-                                                      const int32_t* __restrict__ elem_edges,
-                                                      int32_t* __restrict__ el_f)
-{
-    const int32_t m = blockIdx.x * 256 + threadIdx.x;
-    if (m >= nE) return;
-    const int4 e = elem4[m];
-    const int32_t v[3] = {e.x, e.y, e.z};
-    int32_t M[3];
-    for (int i = 0; i < 3; ++i) M[i] = nC + elem_edges[3 * (int64_t)m + i];
-    el_f[3 * (int64_t)m] = M[0];
-    el_f[3 * (int64_t)m + 1] = M[1];
-    el_f[3 * (int64_t)m + 2] = M[2];
-    for (int i = 0; i < 3; ++i) {
-        int32_t* d = el_f + 3 * ((int64_t)nE + 3 * (int64_t)m + i);
-        d[0] = v[i];
-        d[1] = M[(i + 2) % 3];
-        d[2] = M[(i + 1) % 3];
-    }
-}
-
-// Listed pair q of edge e: (a, M_e) at q and (M_e, b) at n + q.
-__global__ __launch_bounds__(256) void k_refine_pairs(int32_t nC, int32_t n,
-                                                      const int2* __restrict__ pairs,
-                                                      const int32_t* __restrict__ edges,
-                                                      int2* __restrict__ out)
-{
-    const int32_t q = blockIdx.x * 256 + threadIdx.x;
-    if (q >= n) return;
-    const int2 ab = pairs[q];
-    const int32_t mid = nC + edges[q];
-    out[q] = make_int2(ab.x, mid);
-    out[n + q] = make_int2(mid, ab.y);
-}
-}  // namespace
 
 extern "C" int phf_mesh_refine(phf_mesh* coarse, phf_mesh** out)
 {
@@ -867,37 +1057,9 @@ extern "C" int phf_mesh_refine(phf_mesh* coarse, phf_mesh** out)
     const int64_t nCf = (int64_t)coarse->nC + coarse->n_edges, nEf = 4 * (int64_t)coarse->nE;
     if (nCf > 0x7fffffffLL || nEf > 80000000LL)
         return phf_set_error(ctx, PHF_EINVAL, "phf_mesh_refine: refined mesh too large");
-    double2* xy_f = nullptr;
-    int32_t* el_f = nullptr;
-    int2 *d_f = nullptr, *n_f = nullptr;
-    int rc = PHF_OK;
-    auto body = [&]() -> int {
-        TRY(phf_dmalloc(ctx, &xy_f, (size_t)nCf, "refined coordinates"));
-        TRY(phf_dmalloc(ctx, &el_f, 3 * (size_t)nEf, "refined elements"));
-        TRY(phf_dmalloc(ctx, &d_f, 2 * (size_t)coarse->nD, "refined Dirichlet pairs"));
-        TRY(phf_dmalloc(ctx, &n_f, 2 * (size_t)coarse->nN, "refined Neumann pairs"));
-        PHF_LAUNCH(ctx, "k_refine_nodes", k_refine_nodes, nblk(nCf), 256, 0, coarse->nC,
-                   coarse->n_edges, coarse->xy, coarse->edge_nodes, xy_f);
-        PHF_LAUNCH(ctx, "k_refine_elems", k_refine_elems, nblk(coarse->nE), 256, 0, coarse->nC,
-                   coarse->nE, coarse->elem4, coarse->elem_edges, el_f);
-        if (coarse->nD)
-            PHF_LAUNCH(ctx, "k_refine_pairs", k_refine_pairs, nblk(coarse->nD), 256, 0, coarse->nC,
-                       coarse->nD, coarse->dir_pairs, coarse->dir_edges, d_f);
-        if (coarse->nN)
-            PHF_LAUNCH(ctx, "k_refine_pairs", k_refine_pairs, nblk(coarse->nN), 256, 0, coarse->nC,
-                       coarse->nN, coarse->neu_pairs, coarse->neu_edges, n_f);
-        return mesh_create(ctx, (const double*)xy_f, (int32_t)nCf, el_f, (int32_t)nEf,
-                           (const int32_t*)d_f, 2 * coarse->nD, (const int32_t*)n_f,
-                           2 * coarse->nN, PHF_DEVICE, coarse, out);
-    };
-    rc = body();
-    // the temporaries go back to the pool; their next users run after the
-    // kernels above in stream order
-    phf_dfree(xy_f);
-    phf_dfree(el_f);
-    phf_dfree(d_f);
-    phf_dfree(n_f);
-    if (rc) return rc;
+    // every table of the refined mesh is built on the device from the parent's
+    TRY(mesh_create(ctx, nullptr, (int32_t)nCf, nullptr, (int32_t)nEf, nullptr, 2 * coarse->nD,
+                    nullptr, 2 * coarse->nN, PHF_DEVICE, coarse, out));
     (*out)->parent = coarse;
     coarse->n_children++;
     return PHF_OK;
