@@ -150,3 +150,52 @@ __device__ inline void phf_fn_grad(const phf_fn_dev& f, double x, double y, doub
         *gy = 0.0;
     }
 }
+
+// Row of free edge e of the reduced (edge-midpoint) operator: e couples with
+// the other free edges of T+ and T-. Writes the columns (ascending) and, per
+// entry, up to two sources in the element blocks B (9T + 3 a + b, -1 none);
+// returns the number of entries (at most 5).
+__device__ inline int phf_reduced_entries(int32_t e, const int2* edge_elems, const int8_t* led,
+                                      const int8_t* ledTN, const int32_t* elem_edges,
+                                      const int32_t* red_row, int32_t* col, int32_t* s0,
+                                      int32_t* s1)
+{
+    int n = 0;
+    int2 tt = edge_elems[e];
+    int lp = led[e];
+    // diagonal: block (lp, lp) of T+ plus (ln, ln) of T-
+    col[n] = red_row[e];
+    s0[n] = 9 * tt.x + 4 * lp;
+    s1[n] = tt.y >= 0 ? 9 * tt.y + 4 * ledTN[e] : -1;
+    ++n;
+    for (int side = 0; side < 2; ++side) {
+        int32_t T = side == 0 ? tt.x : tt.y;
+        if (T < 0) continue;
+        int le = side == 0 ? lp : ledTN[e];
+        for (int o = 0; o < 3; ++o) {
+            if (o == le) continue;
+            int32_t e2 = elem_edges[3 * (int64_t)T + o];
+            int32_t r2 = red_row[e2];
+            if (r2 < 0) continue;
+            col[n] = r2;
+            s0[n] = 9 * T + 3 * le + o;
+            s1[n] = -1;
+            ++n;
+        }
+    }
+    // sort by column (at most 5 entries)
+    for (int a = 1; a < n; ++a) {
+        int32_t c = col[a], x0 = s0[a], x1 = s1[a];
+        int b = a - 1;
+        while (b >= 0 && col[b] > c) {
+            col[b + 1] = col[b];
+            s0[b + 1] = s0[b];
+            s1[b + 1] = s1[b];
+            --b;
+        }
+        col[b + 1] = c;
+        s0[b + 1] = x0;
+        s1[b + 1] = x1;
+    }
+    return n;
+}

@@ -153,9 +153,7 @@ struct phf_mesh {
     // reduced (edge-midpoint) operator: rows = non-Dirichlet edges
     int32_t* red_row = nullptr;    // n_edges: reduced index, -1 for Dirichlet
     int32_t* red_edge = nullptr;   // n_free: edge of reduced row
-    int32_t* R_rowptr = nullptr;   // n_free + 1
-    int32_t* R_col = nullptr;      // nnz_R
-    int32_t* R_src = nullptr;      // 2 nnz_R: 9T + 3a + b block sources (-1 none)
+    unsigned long long* d_nnzR = nullptr;  // entries of the reduced operator (device)
 };
 
 // Exclusive scan of n int32 values (in may alias out); total -> *d_total.

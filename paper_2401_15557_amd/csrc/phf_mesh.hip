@@ -343,75 +343,25 @@ __global__ __launch_bounds__(256) void k_saddle_cols(
     }
 }
 
-// Reduced (edge-midpoint) operator pattern: row of free edge e couples e with
-// the other free edges of T+ and T-. Pass 0 counts, pass 1 fills.
-__device__ inline int reduced_entries(int32_t e, const int2* edge_elems, const int8_t* led,
-                                      const int8_t* ledTN, const int32_t* elem_edges,
-                                      const int32_t* red_row, int32_t* col, int32_t* s0,
-                                      int32_t* s1)
+// Off-diagonal entries of the reduced (edge-midpoint) operator: each
+// element couples its f free (non-Dirichlet) edges pairwise, f (f - 1)
+// entries; two distinct edges share at most one element, so the count is
+// exact. Per-block sums go to *total with integer atomics (order-independent;
+// a bounded grid keeps the atomics few).
+__global__ __launch_bounds__(256) void k_reduced_count(int32_t nE, const int32_t* __restrict__ ecode,
+                                                       unsigned long long* total)
 {
-    int n = 0;
-    int2 tt = edge_elems[e];
-    int lp = led[e];
-    // diagonal: block (lp, lp) of T+ plus (ln, ln) of T-
-    col[n] = red_row[e];
-    s0[n] = 9 * tt.x + 4 * lp;
-    s1[n] = tt.y >= 0 ? 9 * tt.y + 4 * ledTN[e] : -1;
-    ++n;
-    for (int side = 0; side < 2; ++side) {
-        int32_t T = side == 0 ? tt.x : tt.y;
-        if (T < 0) continue;
-        int le = side == 0 ? lp : ledTN[e];
-        for (int o = 0; o < 3; ++o) {
-            if (o == le) continue;
-            int32_t e2 = elem_edges[3 * (int64_t)T + o];
-            int32_t r2 = red_row[e2];
-            if (r2 < 0) continue;
-            col[n] = r2;
-            s0[n] = 9 * T + 3 * le + o;
-            s1[n] = -1;
-            ++n;
-        }
+    __shared__ int32_t sh[256 / 64 + 1];
+    int32_t n = 0;  // at most 6 per element, 6 nE < 2^31 per block
+    for (int32_t m = blockIdx.x * 256 + threadIdx.x; m < nE; m += gridDim.x * 256) {
+        const int32_t code = ecode[m];
+        int f = 0;
+        for (int i = 0; i < 3; ++i) f += PHF_CODE_TYPE(code, i) != 1;
+        n += f * (f - 1);
     }
-    // sort by column (at most 5 entries)
-    for (int a = 1; a < n; ++a) {
-        int32_t c = col[a], x0 = s0[a], x1 = s1[a];
-        int b = a - 1;
-        while (b >= 0 && col[b] > c) {
-            col[b + 1] = col[b];
-            s0[b + 1] = s0[b];
-            s1[b + 1] = s1[b];
-            --b;
-        }
-        col[b + 1] = c;
-        s0[b + 1] = x0;
-        s1[b + 1] = x1;
-    }
-    return n;
-}
-
-__global__ __launch_bounds__(256) void k_reduced_pattern(
-    int32_t n_free, int pass, const int32_t* __restrict__ red_edge,
-    const int2* __restrict__ edge_elems, const int8_t* __restrict__ led,
-    const int8_t* __restrict__ ledTN, const int32_t* __restrict__ elem_edges,
-    const int32_t* __restrict__ red_row, int32_t* __restrict__ rlen,
-    const int32_t* __restrict__ R_rowptr, int32_t* __restrict__ R_col,
-    int32_t* __restrict__ R_src)
-{
-    int32_t r = blockIdx.x * 256 + threadIdx.x;
-    if (r >= n_free) return;
-    int32_t col[5], s0[5], s1[5];
-    int n = reduced_entries(red_edge[r], edge_elems, led, ledTN, elem_edges, red_row, col, s0, s1);
-    if (pass == 0) {
-        rlen[r] = n;
-        return;
-    }
-    int32_t p = R_rowptr[r];
-    for (int q = 0; q < n; ++q) {
-        R_col[p + q] = col[q];
-        R_src[2 * (int64_t)(p + q)] = s0[q];
-        R_src[2 * (int64_t)(p + q) + 1] = s1[q];
-    }
+    int32_t tot;
+    (void)phf_block_exscan_i32<256>(n, sh, &tot);
+    if (threadIdx.x == 0 && tot) atomicAdd(total, (unsigned long long)tot);
 }
 
 __global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
@@ -663,9 +613,7 @@ static void mesh_free(phf_mesh* m)
     phf_dfree(m->S_col);
     phf_dfree(m->red_row);
     phf_dfree(m->red_edge);
-    phf_dfree(m->R_rowptr);
-    phf_dfree(m->R_col);
-    phf_dfree(m->R_src);
+    phf_dfree(m->d_nnzR);
 }
 
 namespace {
@@ -960,32 +908,18 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     TRY(phf_dmalloc(ctx, &M->neu_mask, ((size_t)nE + 63) / 64, "Neumann element mask"));
     PHF_LAUNCH(ctx, "k_neu_mask", k_neu_mask, nblk(nE), 256, 0, nE, M->ecode, M->neu_mask);
 
-    // reduced operator pattern
+    // size of the reduced operator (read when the mesh info is asked for)
     const int32_t nf = M->n_free;
-    TRY(phf_dmalloc(ctx, &M->R_rowptr, (size_t)nf + 1, "reduced rowptr"));
-    if (nf > 0) {
-        PHF_LAUNCH(ctx, "k_reduced_pattern", k_reduced_pattern, nblk(nf), 256, 0, nf, 0,
-                   M->red_edge, M->edge_elems, M->led, M->ledTN, M->elem_edges, M->red_row,
-                   M->R_rowptr, (const int32_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr);
-    }
-    PHF_HIP(ctx, hipMemsetAsync(M->R_rowptr + nf, 0, sizeof(int32_t), ctx->stream));
-    TRY(phf_scan_i32(ctx, M->R_rowptr, M->R_rowptr, nf + 1, T.totals + 5));
-    int32_t nnzR = 0;
-    TRY(read_i32(ctx, T.totals + 5, &nnzR));
-    M->nnz_R = nnzR;
-    TRY(phf_dmalloc(ctx, &M->R_col, nnzR, "reduced columns"));
-    TRY(phf_dmalloc(ctx, &M->R_src, 2 * (size_t)nnzR, "reduced sources"));
-    if (nf > 0) {
-        PHF_LAUNCH(ctx, "k_reduced_pattern", k_reduced_pattern, nblk(nf), 256, 0, nf, 1,
-                   M->red_edge, M->edge_elems, M->led, M->ledTN, M->elem_edges, M->red_row,
-                   (int32_t*)nullptr, M->R_rowptr, M->R_col, M->R_src);
-    }
+    TRY(phf_dmalloc(ctx, &M->d_nnzR, 1, "reduced count"));
+    PHF_HIP(ctx, hipMemsetAsync(M->d_nnzR, 0, sizeof(unsigned long long), ctx->stream));
+    PHF_LAUNCH(ctx, "k_reduced_count", k_reduced_count, (unsigned)std::min<int64_t>(nblk(nE), 1024),
+               256, 0, nE, M->ecode, M->d_nnzR);
+    M->nnz_R = -1;
     // later work on the mesh runs in stream order behind these kernels
     if (!parent) PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
     M->bytes = (int64_t)nC * 16 + (int64_t)nE * (16 + 48 + 4) + (int64_t)ne * (8 + 8 + 1 + 1 + 1 + 4 + 4) +
                (int64_t)nE * 12 + (int64_t)(nD + nN) * 4 + (int64_t)L * (4 + 8 + 4) +
-               M->nnz_C * 4 + ((int64_t)N + L + 1) * 4 + M->nnz_S * 4 + (int64_t)nf * 8 +
-               M->nnz_R * 12;
+               M->nnz_C * 4 + ((int64_t)N + L + 1) * 4 + M->nnz_S * 4 + (int64_t)nf * 8;
     return PHF_OK;
 }
 }  // namespace
@@ -1068,6 +1002,15 @@ extern "C" int phf_mesh_refine(phf_mesh* coarse, phf_mesh** out)
 extern "C" int phf_mesh_get_info(const phf_mesh* m, phf_mesh_info* o)
 {
     if (!m || !o) return PHF_EINVAL;
+    if (m->nnz_R < 0) {
+        // counted on the device during the build; read once (waits for it)
+        unsigned long long v = 0;
+        phf_mesh* mm = const_cast<phf_mesh*>(m);
+        PHF_HIP(mm->ctx, hipMemcpyAsync(&v, m->d_nnzR, sizeof(v), hipMemcpyDeviceToHost,
+                                        mm->ctx->stream));
+        PHF_HIP(mm->ctx, hipStreamSynchronize(mm->ctx->stream));
+        mm->nnz_R = (int64_t)v + m->n_free;  // the diagonal of every free row
+    }
     o->nC = m->nC;
     o->nE = m->nE;
     o->n_edges = m->n_edges;

@@ -33,21 +33,28 @@ __global__ __launch_bounds__(NT) void k_ns_symbolic(int32_t nE, const int32_t* _
     elem_row[g] = edge_row[e];
 }
 
-__global__ __launch_bounds__(NT) void k_ns_ell(int32_t nf, const int32_t* __restrict__ R_rowptr,
-                                               const int32_t* __restrict__ R_col,
-                                               const int32_t* __restrict__ R_src,
+// ELL-5 rows of the reduced operator straight from the edge tables (column
+// major; unused slots point at the diagonal with no source).
+__global__ __launch_bounds__(NT) void k_ns_ell(int32_t nf, const int32_t* __restrict__ red_edge,
+                                               const int2* __restrict__ edge_elems,
+                                               const int8_t* __restrict__ led,
+                                               const int8_t* __restrict__ ledTN,
+                                               const int32_t* __restrict__ elem_edges,
+                                               const int32_t* __restrict__ red_row,
                                                int32_t* __restrict__ ell_col,
                                                int32_t* __restrict__ ell_src)
 {
     int32_t r = blockIdx.x * NT + threadIdx.x;
     if (r >= nf) return;
-    int32_t q0 = R_rowptr[r], n = R_rowptr[r + 1] - q0;
+    int32_t col[5], s0[5], s1[5];
+    const int n = phf_reduced_entries(red_edge[r], edge_elems, led, ledTN, elem_edges, red_row,
+                                      col, s0, s1);
     for (int k = 0; k < 5; ++k) {
         int64_t slot = (int64_t)k * nf + r;
         if (k < n) {
-            ell_col[slot] = R_col[q0 + k];
-            ell_src[2 * slot] = R_src[2 * (int64_t)(q0 + k)];
-            ell_src[2 * slot + 1] = R_src[2 * (int64_t)(q0 + k) + 1];
+            ell_col[slot] = col[k];
+            ell_src[2 * slot] = s0[k];
+            ell_src[2 * slot + 1] = s1[k];
         } else {
             ell_col[slot] = r;
             ell_src[2 * slot] = -1;
@@ -57,36 +64,47 @@ __global__ __launch_bounds__(NT) void k_ns_ell(int32_t nf, const int32_t* __rest
 }
 
 // A_T = cK K_T + cD D_T + cM M_T (D nullable) and B_T = P^T A_T P; A_T need
-// not be symmetric.
+// not be symmetric. A tile of NT elements is staged in LDS so that the
+// 9-value element rows are read and written with coalesced accesses.
 __global__ __launch_bounds__(NT) void k_ns_blocks(int32_t nE, const double* __restrict__ K,
                                                   const double* __restrict__ M,
                                                   const double* __restrict__ D, double cK,
                                                   double cM, double cD, double* __restrict__ Ablk,
                                                   double* __restrict__ B)
 {
-    int32_t m = blockIdx.x * NT + threadIdx.x;
-    if (m >= nE) return;
-    double A[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        A[q] = cK * K[9 * (int64_t)m + q] + cM * M[9 * (int64_t)m + q];
-        if (D) A[q] += cD * D[9 * (int64_t)m + q];
-        Ablk[9 * (int64_t)m + q] = A[q];
+    __shared__ double sA[NT * 9], sB[NT * 9];
+    const int tid = threadIdx.x;
+    const int64_t m0 = (int64_t)blockIdx.x * NT;
+    const int32_t nt = (int32_t)min((int64_t)NT, (int64_t)nE - m0);
+    const int32_t cnt = 9 * nt;
+    for (int32_t q = tid; q < cnt; q += NT) {
+        double a = cK * K[9 * m0 + q] + cM * M[9 * m0 + q];
+        if (D) a += cD * D[9 * m0 + q];
+        sA[q] = a;
     }
-    // AP[i][l] = rowsum_i(A) - 2 A[i][l]
-    double AP[9];
+    __syncthreads();
+    if (tid < nt) {
+        const double* A = sA + 9 * tid;
+        // AP[i][l] = rowsum_i(A) - 2 A[i][l]
+        double AP[9];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        double rs = A[3 * i] + A[3 * i + 1] + A[3 * i + 2];
+        for (int i = 0; i < 3; ++i) {
+            const double rs = A[3 * i] + A[3 * i + 1] + A[3 * i + 2];
 #pragma unroll
-        for (int l = 0; l < 3; ++l) AP[3 * i + l] = rs - 2.0 * A[3 * i + l];
+            for (int l = 0; l < 3; ++l) AP[3 * i + l] = rs - 2.0 * A[3 * i + l];
+        }
+        // B[l][l'] = colsum_{l'}(AP) - 2 AP[l][l']
+#pragma unroll
+        for (int lp = 0; lp < 3; ++lp) {
+            const double cs = AP[lp] + AP[3 + lp] + AP[6 + lp];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) sB[9 * tid + 3 * l + lp] = cs - 2.0 * AP[3 * l + lp];
+        }
     }
-    // B[l][l'] = colsum_{l'}(AP) - 2 AP[l][l']
-#pragma unroll
-    for (int lp = 0; lp < 3; ++lp) {
-        double cs = AP[lp] + AP[3 + lp] + AP[6 + lp];
-#pragma unroll
-        for (int l = 0; l < 3; ++l) B[9 * (int64_t)m + 3 * l + lp] = cs - 2.0 * AP[3 * l + lp];
+    __syncthreads();
+    for (int32_t q = tid; q < cnt; q += NT) {
+        Ablk[9 * m0 + q] = sA[q];
+        B[9 * m0 + q] = sB[q];
     }
 }
 
@@ -646,8 +664,9 @@ int phf_ns_create(phf_mesh* mesh, phf_ns** out)
         PHF_LAUNCH(ctx, "k_ns_symbolic", k_ns_symbolic, nblk(3 * (int64_t)ns->nE), NT, 0, ns->nE,
                    mesh->elem_edges, mesh->red_row, mesh->edge_row, ns->elem_red, ns->elem_row);
         if (ns->nf > 0)
-            PHF_LAUNCH(ctx, "k_ns_ell", k_ns_ell, nblk(ns->nf), NT, 0, ns->nf, mesh->R_rowptr,
-                       mesh->R_col, mesh->R_src, ns->ell_col, ns->ell_src);
+            PHF_LAUNCH(ctx, "k_ns_ell", k_ns_ell, nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge,
+                       mesh->edge_elems, mesh->led, mesh->ledTN, mesh->elem_edges, mesh->red_row,
+                       ns->ell_col, ns->ell_src);
         PHF_HIP(ctx, hipMemsetAsync(ns->w, 0, sizeof(double) * std::max<size_t>(nf, 1), ctx->stream));
         PHF_HIP(ctx, hipMemsetAsync(ns->iflags, 0, 4 * sizeof(int), ctx->stream));
         return PHF_OK;

@@ -105,6 +105,18 @@ def test_topology_and_patterns(ctx, oracle, name):
     rp, col, _ = oracle.saddle(asm)
     np.testing.assert_array_equal(pat_g["S_rowptr"], rp)
     np.testing.assert_array_equal(pat_g["S_col"], col)
+    # entries of the reduced (edge-midpoint) operator, counted edge by edge:
+    # each non-Dirichlet edge couples with itself and the other
+    # non-Dirichlet edges of its elements
+    free = topo_o["edge_type"][:topo_o["n_edges"]] != 1
+    nnz = 0
+    for e in np.flatnonzero(free):
+        nb = {e}
+        for T in topo_o["edge_elems"][e]:
+            if T >= 0:
+                nb.update(x for x in topo_o["elem_edges"][T] if free[x])
+        nnz += len(nb)
+    assert i.n_free == int(free.sum()) and i.nnz_reduced == nnz
     dm.close()
 
 
