@@ -27,7 +27,7 @@
 #define PHF_MG_DENSE_MAX 256
 // Levels with at most this many unknowns (below the finest) run their part of
 // the cycle in one single-workgroup launch.
-#define PHF_MG_TAIL_MAX 8192
+#define PHF_MG_TAIL_MAX 2048
 
 // Device view of one level, for the single-workgroup cycle.
 struct phf_mg_dev_level {
