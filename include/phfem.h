@@ -306,11 +306,22 @@ int phf_spmv(phf_ctx* ctx, int32_t nrows, const int32_t* rowptr, const int32_t* 
 #define PHF_SOLVER_NULLSPACE_BICGSTAB 1
 /* Preconditioners of the reduced operator: Jacobi (any mesh), or a V-cycle
  * over the chain of meshes the mesh was refined from by phf_mesh_refine
- * (edge-midpoint prolongation averaged across coarse edges, damped Jacobi
+ * (edge-midpoint prolongation averaged across coarse edges, polynomial
  * smoothing, coarse operators re-discretised with the triangle coefficient
  * averaged over children, exact solve on the coarsest mesh). */
 #define PHF_PRECOND_JACOBI 0
 #define PHF_PRECOND_MULTIGRID 1
+/* Multigrid smoothers. Each sweep is x += w_k D^-1 (b - A x). JACOBI: every
+ * w_k = mg_omega. CHEBYSHEV: the mg_sweeps weights of a side are the
+ * reciprocal roots of the Chebyshev polynomial of that degree on
+ * [lmax / mg_range, lmax], lmax the level's Gershgorin bound of D^-1 A
+ * (computed on the device); with one sweep this is the damping
+ * 2 / (lmax (1 + 1 / mg_range)). Errors: mg_sweeps outside 0..8, an unknown
+ * smoother, 0 < mg_range <= 1 or mg_omega < 0 give PHF_EINVAL. 0 selects
+ * CHEBYSHEV. */
+#define PHF_MG_SMOOTH_DEFAULT 0
+#define PHF_MG_SMOOTH_JACOBI 1
+#define PHF_MG_SMOOTH_CHEBYSHEV 2
 typedef struct {
     int32_t method;      /* PHF_SOLVER_*                                   */
     int32_t max_iter;    /* 0 = 20000                                      */
@@ -319,8 +330,13 @@ typedef struct {
                             or 1 with the multigrid preconditioner */
     int32_t saddle_residual; /* 1: compute the saddle residual into stats   */
     int32_t precond;     /* PHF_PRECOND_*                                  */
-    int32_t mg_sweeps;   /* Jacobi sweeps before and after the coarse correction; 0 = 2 */
+    int32_t mg_sweeps;   /* sweeps before and after the coarse correction,
+                            1..8; 0 = 3 (Chebyshev) or 2 (Jacobi)           */
     double mg_omega;     /* Jacobi damping; 0 = 0.8                         */
+    int32_t mg_smoother; /* PHF_MG_SMOOTH_*                                 */
+    int32_t reserved_;   /* 0                                               */
+    double mg_range;     /* Chebyshev: lmax / lower end of the range (> 1);
+                            0 = 10                                          */
 } phf_solver_opts;
 
 typedef struct {
@@ -368,8 +384,11 @@ typedef struct {
     int32_t max_iter;       /* per step, eager mode; 0 = 5000             */
     int32_t iters_per_step; /* expected CG iterations of the first step; 0 = 8 */
     int32_t precond;        /* PHF_PRECOND_* (multigrid needs a refined mesh) */
-    int32_t mg_sweeps;      /* 0 = 2                                       */
+    int32_t mg_sweeps;      /* as for phf_solve                            */
     double mg_omega;        /* 0 = 0.8                                     */
+    int32_t mg_smoother;    /* PHF_MG_SMOOTH_*                             */
+    int32_t reserved_;      /* 0                                           */
+    double mg_range;        /* 0 = 10                                      */
 } phf_cn_opts;
 
 int phf_cn_create(phf_mesh* mesh, const phf_coeffs* coeffs, double k, const phf_cn_opts* opts,

@@ -313,6 +313,8 @@ extern "C" int phf_cn_create(phf_mesh* mesh, const phf_coeffs* co, double k,
     cn->opts.precond = opts ? opts->precond : PHF_PRECOND_JACOBI;
     cn->opts.mg_sweeps = opts ? opts->mg_sweeps : 0;
     cn->opts.mg_omega = opts ? opts->mg_omega : 0.0;
+    cn->opts.mg_smoother = opts ? opts->mg_smoother : 0;
+    cn->opts.mg_range = opts ? opts->mg_range : 0.0;
     if (cn->opts.precond != PHF_PRECOND_JACOBI && cn->opts.precond != PHF_PRECOND_MULTIGRID) {
         delete cn;
         return phf_set_error(ctx, PHF_EINVAL, "phf_cn_create: unknown preconditioner");
@@ -348,8 +350,13 @@ extern "C" int phf_cn_create(phf_mesh* mesh, const phf_coeffs* co, double k,
         TRY(phf_assemble_impl(mesh, co, &d, &s));
         TRY(phf_ns_create(mesh, &cn->ns));
         TRY(phf_ns_operator(cn->ns, cn->K, cn->M, cn->C, 0.5 * k, 1.0 + 0.5 * k * co->delta));
-        TRY(phf_ns_set_precond(cn->ns, cn->opts.precond, cn->opts.mg_sweeps, cn->opts.mg_omega,
-                               co, 0.5 * k, 1.0 + 0.5 * k * co->delta));
+        phf_mg_params mp;
+        mp.sweeps = cn->opts.mg_sweeps;
+        mp.smoother = cn->opts.mg_smoother;
+        mp.omega = cn->opts.mg_omega;
+        mp.range = cn->opts.mg_range;
+        TRY(phf_ns_set_precond(cn->ns, cn->opts.precond, mp, co, 0.5 * k,
+                               1.0 + 0.5 * k * co->delta));
         PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
         return PHF_OK;
     };

@@ -19,6 +19,14 @@
 // solve accumulates in double): it only has to approximate the inverse, while
 // the outer conjugate-gradient iteration keeps double precision, so the
 // reached residual is unaffected and the cycle moves about 40% fewer bytes.
+//
+// Each sweep is x += w_k D^-1 (b - A x). With the Jacobi smoother every w_k
+// is the damping omega; with the Chebyshev smoother the nu weights of a side
+// are the reciprocal roots of the degree-nu Chebyshev polynomial on
+// [lmax / range, lmax], lmax the Gershgorin bound max_i sum_j |a_ij| / a_ii of
+// the level (computed on the device), so the nu sweeps together minimise the
+// largest error factor over that upper part of the spectrum. Both are
+// polynomials in D^-1 A, so the cycle stays symmetric.
 #pragma once
 
 #include "phf_solver.h"
@@ -28,6 +36,10 @@
 // Levels with at most this many unknowns (below the finest) run their part of
 // the cycle in one single-workgroup launch.
 #define PHF_MG_TAIL_MAX 2048
+// Sweeps per side at most; each level keeps PHF_MG_MAX_SWEEPS sweep weights
+// and, last, the weight of the plain sweeps of an iterative coarsest solve.
+#define PHF_MG_MAX_SWEEPS 8
+#define PHF_MG_WSTRIDE (PHF_MG_MAX_SWEEPS + 1)
 
 // Device view of one level, for the single-workgroup cycle.
 struct phf_mg_dev_level {
@@ -41,6 +53,7 @@ struct phf_mg_dev_level {
     float* t = nullptr;
     const int32_t* ecode_c = nullptr;  // element codes of the next coarser mesh
     const int2* sel = nullptr;         // own gather map (from the finer level's sums)
+    const float* w = nullptr;          // sweep weights (PHF_MG_WSTRIDE)
 };
 
 struct phf_mg_level {
@@ -77,8 +90,12 @@ struct phf_mg {
     int32_t tail_top = -1;   // levels 0..tail_top run in the single-workgroup kernel
     phf_mg_dev_level h_lv[PHF_MG_MAX_LEVELS];
     phf_mg_dev_level* d_lv = nullptr;
-    int32_t nu = 2;          // Jacobi sweeps before and after the coarse correction
+    int32_t nu = 2;          // sweeps before and after the coarse correction
+    int32_t smoother = 0;    // PHF_MG_SMOOTH_JACOBI or PHF_MG_SMOOTH_CHEBYSHEV
     double omega = 0.8;      // Jacobi damping
+    double range = 4.0;      // Chebyshev: smoothing range [lmax / range, lmax]
+    uint32_t* lmax = nullptr;  // per level: Gershgorin bound (float bits)
+    float* wts = nullptr;      // per level: PHF_MG_WSTRIDE sweep weights
 };
 
 // Builds the hierarchy below the finest operator `fine` (whose mesh must come

@@ -280,11 +280,13 @@ __global__ __launch_bounds__(NT) void k_mg_f32(int64_t n, const double* __restri
 // First sweep from x = 0 on the finest level: also rounds the right-hand side
 // (the double-precision CG residual) once for the rest of the cycle.
 __global__ __launch_bounds__(NT) void k_mg_smooth0_top(int32_t n, const float* __restrict__ dinv,
-                                                       const double* __restrict__ b64, float omega,
+                                                       const double* __restrict__ b64,
+                                                       const float* __restrict__ w,
                                                        float* __restrict__ b, float* __restrict__ x,
                                                        const int* iflags)
 {
     if (iflags && iflags[0]) return;
+    const float omega = w[0];
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
         b[i] = (float)b64[i];
         row_smooth0(i, dinv, b, omega, x);
@@ -292,10 +294,12 @@ __global__ __launch_bounds__(NT) void k_mg_smooth0_top(int32_t n, const float* _
 }
 
 __global__ __launch_bounds__(NT) void k_mg_smooth0(int32_t n, const float* __restrict__ dinv,
-                                                   const float* __restrict__ b, float omega,
+                                                   const float* __restrict__ b,
+                                                   const float* __restrict__ w, int32_t k,
                                                    float* __restrict__ x, const int* iflags)
 {
     if (iflags && iflags[0]) return;
+    const float omega = w[k];
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
         row_smooth0(i, dinv, b, omega, x);
 }
@@ -306,11 +310,13 @@ template <bool FINEST>
 __global__ __launch_bounds__(NT) void k_mg_smooth(int32_t n, const int32_t* __restrict__ col,
                                                   const float* __restrict__ val,
                                                   const float* __restrict__ dinv,
-                                                  const float* __restrict__ b, float omega,
+                                                  const float* __restrict__ b,
+                                                  const float* __restrict__ w, int32_t k,
                                                   const float* __restrict__ x,
                                                   float* __restrict__ y, const int* iflags)
 {
     if (iflags && iflags[0]) return;
+    const float omega = w[k];
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
         row_smooth(i, n, col, val, dinv, b, omega, x, y);
 }
@@ -371,7 +377,7 @@ __global__ __launch_bounds__(NT) void k_mg_coarse(int32_t n, const double* __res
 // first one writing to whichever makes the last one land in x.
 constexpr int TAIL_NT = 1024;
 __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __restrict__ lv,
-                                                     int32_t top, int32_t nu, float omega,
+                                                     int32_t top, int32_t nu,
                                                      const double* __restrict__ cinv,
                                                      int32_t dense, const int* iflags)
 {
@@ -384,9 +390,10 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
         // 2 nu - 1 sweeps follow the first: it writes y when that count is odd
         float* u = ((2 * nu - 1) & 1) ? L.y : L.x;
         float* v = u == L.x ? L.y : L.x;
-        for (int32_t i = tid; i < L.n; i += TAIL_NT) row_smooth0(i, L.dinv, L.b, omega, u);
+        for (int32_t i = tid; i < L.n; i += TAIL_NT) row_smooth0(i, L.dinv, L.b, L.w[0], u);
         __syncthreads();
         for (int32_t s = 1; s < nu; ++s) {
+            const float omega = L.w[s];
             for (int32_t i = tid; i < L.n; i += TAIL_NT)
                 row_smooth(i, L.n, L.col, L.val, L.dinv, L.b, omega, u, v);
             __syncthreads();
@@ -411,6 +418,7 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
         } else {
             // 1 + 40 sweeps from zero; 40 is even, so starting in x ends in x
             float *u = L.x, *v = L.y;
+            const float omega = L.w[PHF_MG_MAX_SWEEPS];
             for (int32_t i = tid; i < L.n; i += TAIL_NT) row_smooth0(i, L.dinv, L.b, omega, u);
             __syncthreads();
             for (int32_t s = 0; s < 40; ++s) {
@@ -438,6 +446,7 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
             __syncthreads();
         }
         for (int32_t s = 0; s < nu; ++s) {
+            const float omega = L.w[s];
             for (int32_t i = tid; i < L.n; i += TAIL_NT)
                 row_smooth(i, L.n, L.col, L.val, L.dinv, L.b, omega, u, v);
             __syncthreads();
@@ -446,6 +455,59 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
             v = w;
         }
     }
+}
+
+// Gershgorin bound of D^-1 A on one level: max over rows of
+// sum_j |a_ij| / a_ii (the ELL padding holds zeros), merged into *lmax as
+// the bits of a non-negative float (which order like unsigned integers).
+__global__ __launch_bounds__(NT) void k_mg_gersh(int32_t n, const float* __restrict__ val,
+                                                 const float* __restrict__ dinv,
+                                                 uint32_t* __restrict__ lmax)
+{
+    __shared__ float sh[NT];
+    float m = 0.0f;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) s += fabsf(val[(int64_t)k * n + i]);
+        m = fmaxf(m, s * fabsf(dinv[i]));
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(lmax, __float_as_uint(sh[0]));
+}
+
+__global__ void k_mg_lmax_clear(int32_t nlev, uint32_t* __restrict__ lmax)
+{
+    if ((int32_t)threadIdx.x < nlev) lmax[threadIdx.x] = 0u;
+}
+
+// Sweep weights of every level (one thread per level): Jacobi -> omega for
+// every sweep; Chebyshev -> 1 / (c + h cos((2k + 1) pi / (2 nu))), the roots
+// of the degree-nu Chebyshev polynomial mapped to [lo, hi] = [lmax / range,
+// lmax] (c, h its centre and half-width), and 1 / c (the best single weight
+// for that interval) for the plain sweeps of an iterative coarsest solve.
+__global__ void k_mg_weights(int32_t nlev, int32_t nu, int32_t cheb, float omega, float range,
+                             const uint32_t* __restrict__ lmax, float* __restrict__ wts)
+{
+    const int32_t l = threadIdx.x;
+    if (l >= nlev) return;
+    float* w = wts + (int64_t)l * PHF_MG_WSTRIDE;
+    if (!cheb) {
+        for (int k = 0; k < PHF_MG_WSTRIDE; ++k) w[k] = omega;
+        return;
+    }
+    float hi = __uint_as_float(lmax[l]);
+    if (!(hi > 0.0f)) hi = 1.0f;  // level without unknowns
+    const double lo = (double)hi / range;
+    const double c = 0.5 * ((double)hi + lo), h = 0.5 * ((double)hi - lo);
+    for (int k = 0; k < PHF_MG_MAX_SWEEPS; ++k)
+        w[k] = k < nu ? (float)(1.0 / (c + h * cos(M_PI * (2 * k + 1) / (2.0 * nu)))) : 0.0f;
+    w[PHF_MG_MAX_SWEEPS] = (float)(1.0 / c);
 }
 
 // z = x; partial sums of r.z (fixed order within the block).
@@ -515,6 +577,8 @@ void phf_mg_destroy(phf_mg* mg)
     phf_dfree(mg->cinv);
     phf_dfree(mg->cwork);
     phf_dfree(mg->d_lv);
+    phf_dfree(mg->lmax);
+    phf_dfree(mg->wts);
     delete mg;
 }
 
@@ -609,6 +673,9 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
                 d.ecode_c = mg->lev[l - 1].mesh->ecode;
             }
         }
+        TRY(phf_dmalloc(ctx, &mg->lmax, (size_t)nlev, "multigrid spectral bounds"));
+        TRY(phf_dmalloc(ctx, &mg->wts, (size_t)nlev * PHF_MG_WSTRIDE, "multigrid sweep weights"));
+        for (int l = 0; l <= mg->tail_top; ++l) mg->h_lv[l].w = mg->wts + (size_t)l * PHF_MG_WSTRIDE;
         TRY(phf_dmalloc(ctx, &mg->d_lv, (size_t)mg->tail_top + 1, "multigrid level table"));
         PHF_HIP(ctx, hipMemcpyAsync(mg->d_lv, mg->h_lv, sizeof(phf_mg_dev_level) * (mg->tail_top + 1),
                                     hipMemcpyHostToDevice, ctx->stream));
@@ -664,6 +731,18 @@ int phf_mg_numeric(phf_mg* mg, const phf_coeffs* co, double cK, double cM)
         PHF_LAUNCH(ctx, "k_mg_f32", k_mg_f32, (unsigned)std::min<int64_t>(nblk(L.nf), 2048), NT, 0,
                    (int64_t)L.nf, L.ns->dinv, L.dinv32);
     }
+    // sweep weights
+    const bool cheb = mg->smoother == PHF_MG_SMOOTH_CHEBYSHEV;
+    PHF_LAUNCH(ctx, "k_mg_lmax_clear", k_mg_lmax_clear, 1, PHF_MG_MAX_LEVELS, 0, mg->nlev, mg->lmax);
+    if (cheb)
+        for (int l = 0; l <= top; ++l) {
+            phf_mg_level& L = mg->lev[l];
+            if (L.nf == 0) continue;
+            PHF_LAUNCH(ctx, "k_mg_gersh", k_mg_gersh, grid_for(L.nf), NT, 0, L.nf, L.val32,
+                       L.dinv32, mg->lmax + l);
+        }
+    PHF_LAUNCH(ctx, "k_mg_weights", k_mg_weights, 1, PHF_MG_MAX_LEVELS, 0, mg->nlev, mg->nu,
+               cheb ? 1 : 0, (float)mg->omega, (float)mg->range, mg->lmax, mg->wts);
     if (mg->cinv) {
         const int32_t n0 = mg->n0;
         PHF_LAUNCH(ctx, "k_mg_dense", k_mg_dense, nblk(n0), NT, 0, n0, mg->lev[0].ns->ell_col,
@@ -674,18 +753,22 @@ int phf_mg_numeric(phf_mg* mg, const phf_coeffs* co, double cK, double cM)
 }
 
 namespace {
-int smooth(phf_mg* mg, int l, const int* iflags)
+const float* level_weights(const phf_mg* mg, int l) { return mg->wts + (size_t)l * PHF_MG_WSTRIDE; }
+
+// One sweep with weight k of level l, from L.x into L.y (then swapped).
+int smooth(phf_mg* mg, int l, int k, const int* iflags)
 {
     phf_mg_level& L = mg->lev[l];
     phf_ctx* ctx = L.mesh->ctx;
     const int32_t n = L.nf;
     const unsigned g = grid_for(n);
+    const float* w = level_weights(mg, l);
     if (l == mg->nlev - 1)
         PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth<true>, g, NT, 0, n, L.ns->ell_col,
-                   L.val32, L.dinv32, L.b, (float)mg->omega, L.x, L.y, iflags);
+                   L.val32, L.dinv32, L.b, w, k, L.x, L.y, iflags);
     else
         PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth<false>, g, NT, 0, n, L.ns->ell_col,
-                   L.val32, L.dinv32, L.b, (float)mg->omega, L.x, L.y, iflags);
+                   L.val32, L.dinv32, L.b, w, k, L.x, L.y, iflags);
     std::swap(L.x, L.y);
     return PHF_OK;
 }
@@ -697,7 +780,7 @@ int vcycle(phf_mg* mg, int l, const double* r_top, const int* iflags)
     if (l <= mg->tail_top) {
         // this level and all below in one workgroup; the result is in L.x
         PHF_LAUNCH(ctx, "k_mg_tail", k_mg_tail, 1, TAIL_NT, 0, mg->d_lv, (int32_t)l, mg->nu,
-                   (float)mg->omega, mg->cinv, mg->cinv ? 1 : 0, iflags);
+                   mg->cinv, mg->cinv ? 1 : 0, iflags);
         return PHF_OK;
     }
     const int32_t n = L.nf;
@@ -709,11 +792,12 @@ int vcycle(phf_mg* mg, int l, const double* r_top, const int* iflags)
             PHF_LAUNCH(ctx, "k_mg_coarse", k_mg_coarse, 1, NT, 0, n, mg->cinv, L.b, L.x, iflags);
         } else {
             // no dense inverse: many damped Jacobi sweeps
-            PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0, g, NT, 0, n, L.dinv32, L.b,
-                       (float)mg->omega, L.x, iflags);
+            const float* w = level_weights(mg, l);
+            PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0, g, NT, 0, n, L.dinv32, L.b, w,
+                       PHF_MG_MAX_SWEEPS, L.x, iflags);
             for (int s = 0; s < 40; ++s) {
                 PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth<false>, g, NT, 0, n, ns->ell_col, L.val32,
-                           L.dinv32, L.b, (float)mg->omega, L.x, L.y, iflags);
+                           L.dinv32, L.b, w, PHF_MG_MAX_SWEEPS, L.x, L.y, iflags);
                 std::swap(L.x, L.y);
             }
         }
@@ -723,11 +807,11 @@ int vcycle(phf_mg* mg, int l, const double* r_top, const int* iflags)
     // the double-precision residual r_top)
     if (r_top)
         PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0_top, g, NT, 0, n, L.dinv32, r_top,
-                   (float)mg->omega, L.b, L.x, iflags);
+                   level_weights(mg, l), L.b, L.x, iflags);
     else
         PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0, g, NT, 0, n, L.dinv32, L.b,
-                   (float)mg->omega, L.x, iflags);
-    for (int s = 1; s < mg->nu; ++s) TRY(smooth(mg, l, iflags));
+                   level_weights(mg, l), 0, L.x, iflags);
+    for (int s = 1; s < mg->nu; ++s) TRY(smooth(mg, l, s, iflags));
     phf_mg_level& C = mg->lev[l - 1];
     if (C.nf > 0) {
         PHF_LAUNCH(ctx, mg_name(NM_RESID, l), k_mg_resid, g, NT, 0, n, ns->ell_col, L.val32, L.b, L.x,
@@ -740,7 +824,7 @@ int vcycle(phf_mg* mg, int l, const double* r_top, const int* iflags)
         PHF_LAUNCH(ctx, mg_name(NM_PROLONG, l), k_mg_prolong, g, NT, 0, n, L.P_col, L.P_val, C.x, L.x,
                    iflags);
     }
-    for (int s = 0; s < mg->nu; ++s) TRY(smooth(mg, l, iflags));
+    for (int s = 0; s < mg->nu; ++s) TRY(smooth(mg, l, s, iflags));
     return PHF_OK;
 }
 }  // namespace

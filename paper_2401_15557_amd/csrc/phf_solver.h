@@ -82,9 +82,14 @@ int phf_ns_bicg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_e
 // Host convergence loop: cg_start + batches of check_every iterations.
 int phf_ns_cg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_every,
                     int32_t* iters_out, double* relres_out, int* converged);
+// Multigrid smoothing as the public options give it (0 = default).
+struct phf_mg_params {
+    int32_t sweeps = 0, smoother = 0;
+    double omega = 0.0, range = 0.0;
+};
 // Chooses Jacobi or the multilevel preconditioner (built on first use, its
 // coarse operators recomputed for A = cK K + cM M and coeffs' a_T).
-int phf_ns_set_precond(phf_ns* ns, int32_t precond, int32_t sweeps, double omega,
+int phf_ns_set_precond(phf_ns* ns, int32_t precond, const phf_mg_params& mp,
                        const phf_coeffs* co, double cK, double cM);
 // The mesh's cached workspace (created on first use).
 int phf_ns_get(phf_mesh* mesh, phf_ns** out);

@@ -890,14 +890,28 @@ int phf_ns_bicg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_e
     return PHF_OK;
 }
 
-int phf_ns_set_precond(phf_ns* ns, int32_t precond, int32_t sweeps, double omega,
+int phf_ns_set_precond(phf_ns* ns, int32_t precond, const phf_mg_params& mp,
                        const phf_coeffs* co, double cK, double cM)
 {
     ns->mg_on = false;
     if (precond != PHF_PRECOND_MULTIGRID) return PHF_OK;
+    phf_ctx* ctx = ns->mesh->ctx;
+    if (mp.sweeps < 0 || mp.sweeps > PHF_MG_MAX_SWEEPS)
+        return phf_set_error(ctx, PHF_EINVAL, "multigrid sweeps %d outside 0..%d", mp.sweeps,
+                             PHF_MG_MAX_SWEEPS);
+    if (mp.smoother != PHF_MG_SMOOTH_DEFAULT && mp.smoother != PHF_MG_SMOOTH_JACOBI &&
+        mp.smoother != PHF_MG_SMOOTH_CHEBYSHEV)
+        return phf_set_error(ctx, PHF_EINVAL, "unknown multigrid smoother %d", mp.smoother);
+    if (mp.range != 0.0 && !(mp.range > 1.0))
+        return phf_set_error(ctx, PHF_EINVAL, "Chebyshev range must exceed 1 (got %g)", mp.range);
+    if (!(mp.omega >= 0.0))
+        return phf_set_error(ctx, PHF_EINVAL, "negative Jacobi damping %g", mp.omega);
     if (!ns->mg) TRY(phf_mg_create(ns, &ns->mg));
-    ns->mg->nu = sweeps > 0 ? sweeps : 2;
-    ns->mg->omega = omega > 0 ? omega : 0.8;
+    const bool jacobi = mp.smoother == PHF_MG_SMOOTH_JACOBI;
+    ns->mg->smoother = jacobi ? PHF_MG_SMOOTH_JACOBI : PHF_MG_SMOOTH_CHEBYSHEV;
+    ns->mg->nu = mp.sweeps > 0 ? mp.sweeps : jacobi ? 2 : 3;
+    ns->mg->omega = mp.omega > 0 ? mp.omega : 0.8;
+    ns->mg->range = mp.range > 0 ? mp.range : 10.0;
     TRY(phf_mg_numeric(ns->mg, co, cK, cM));
     ns->mg_on = true;
     return PHF_OK;
@@ -952,7 +966,12 @@ extern "C" int phf_solve(phf_mesh* mesh, const phf_coeffs* co, const phf_system*
     TRY(phf_ns_get(mesh, &ns));
     TRY(phf_ns_operator(ns, sys->K, sys->M, sys->C, 1.0, co->delta, conv_term ? sys->D : nullptr,
                         1.0));
-    TRY(phf_ns_set_precond(ns, o.precond, o.mg_sweeps, o.mg_omega, co, 1.0, co->delta));
+    phf_mg_params mp;
+    mp.sweeps = o.mg_sweeps;
+    mp.smoother = o.mg_smoother;
+    mp.omega = o.mg_omega;
+    mp.range = o.mg_range;
+    TRY(phf_ns_set_precond(ns, o.precond, mp, co, 1.0, co->delta));
     TRY(phf_ns_rhs(ns, sys->F, sys->bD));
     TRY(phf_ns_zero_w(ns));
     int32_t iters = 0;

@@ -30,6 +30,7 @@ PHF_FN_EDGE_ARRAY = 100
 PHF_SOLVER_NULLSPACE_CG = 0
 PHF_SOLVER_NULLSPACE_BICGSTAB = 1
 PHF_PRECOND_JACOBI, PHF_PRECOND_MULTIGRID = 0, 1
+PHF_MG_SMOOTH_DEFAULT, PHF_MG_SMOOTH_JACOBI, PHF_MG_SMOOTH_CHEBYSHEV = 0, 1, 2
 
 EXPORTED = (
     "phf_create", "phf_destroy", "phf_set_stream", "phf_synchronize", "phf_mem_stats",
@@ -89,7 +90,9 @@ class phf_solver_opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("check_every", ctypes.c_int32),
                 ("saddle_residual", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("mg_sweeps", ctypes.c_int32), ("mg_omega", ctypes.c_double)]
+                ("mg_sweeps", ctypes.c_int32), ("mg_omega", ctypes.c_double),
+                ("mg_smoother", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("mg_range", ctypes.c_double)]
 
 
 class phf_solve_stats(ctypes.Structure):
@@ -100,7 +103,9 @@ class phf_solve_stats(ctypes.Structure):
 class phf_cn_opts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("iters_per_step", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("mg_sweeps", ctypes.c_int32), ("mg_omega", ctypes.c_double)]
+                ("mg_sweeps", ctypes.c_int32), ("mg_omega", ctypes.c_double),
+                ("mg_smoother", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("mg_range", ctypes.c_double)]
 
 
 class phf_batch_config(ctypes.Structure):
@@ -406,10 +411,11 @@ def phf_spmv(ctx, nrows, rowptr, col, val, alpha, x, beta, y):
 
 def phf_solve(mesh, coeffs, system, U, Lam=None, rtol=1e-10, max_iter=20000, check_every=0,
               saddle_residual=False, raise_on_noconv=True, precond=PHF_PRECOND_JACOBI,
-              mg_sweeps=0, mg_omega=0.0, method=PHF_SOLVER_NULLSPACE_CG):
+              mg_sweeps=0, mg_omega=0.0, method=PHF_SOLVER_NULLSPACE_CG,
+              mg_smoother=PHF_MG_SMOOTH_DEFAULT, mg_range=0.0):
     o = phf_solver_opts(int(method), int(max_iter), float(rtol), int(check_every),
                         1 if saddle_residual else 0, int(precond), int(mg_sweeps),
-                        float(mg_omega))
+                        float(mg_omega), int(mg_smoother), 0, float(mg_range))
     st = phf_solve_stats()
     rc = load().phf_solve(mesh, ctypes.byref(coeffs), ctypes.byref(system), ctypes.byref(o),
                           _ptr(U), _ptr(Lam), ctypes.byref(st))
@@ -554,10 +560,11 @@ def phf_server_query(server):
 
 
 def phf_cn_create(mesh, coeffs, k, rtol=1e-10, max_iter=5000, iters_per_step=8,
-                  precond=PHF_PRECOND_JACOBI, mg_sweeps=0, mg_omega=0.0):
+                  precond=PHF_PRECOND_JACOBI, mg_sweeps=0, mg_omega=0.0,
+                  mg_smoother=PHF_MG_SMOOTH_DEFAULT, mg_range=0.0):
     h = _VP()
     o = phf_cn_opts(float(rtol), int(max_iter), int(iters_per_step), int(precond),
-                    int(mg_sweeps), float(mg_omega))
+                    int(mg_sweeps), float(mg_omega), int(mg_smoother), 0, float(mg_range))
     _call("phf_cn_create", None, mesh, ctypes.byref(coeffs), float(k), ctypes.byref(o),
           ctypes.byref(h))
     return h.value

@@ -201,15 +201,17 @@ def _refined_pair(ctx, oracle, base, levels):
     return dm, m
 
 
+@pytest.mark.parametrize("smoother", ["chebyshev", "jacobi"])
 @pytest.mark.parametrize("levels", [1, 3, 5])
-def test_multigrid_solve_parity(ctx, oracle, levels):
+def test_multigrid_solve_parity(ctx, oracle, levels, smoother):
     """CG with the V-cycle preconditioner on a device-refined L-shape with a
     random per-triangle coefficient: same solution as the oracle's sparse LU,
     in a number of iterations that does not grow with the level."""
     import torch
     from paper_2401_15557_amd import phfem
+    sm = dict(chebyshev=phfem.PHF_MG_SMOOTH_CHEBYSHEV, jacobi=phfem.PHF_MG_SMOOTH_JACOBI)[smoother]
     dm, m = _refined_pair(ctx, oracle, G.lshape(0), levels)
-    print(f"levels {levels}: nE={m.nE}", flush=True)
+    print(f"levels {levels}, {smoother}: nE={m.nE}", flush=True)
     aT = G.per_triangle_coefficient(m.nE, 5)
     od, gd = _both(oracle, phfem, "const")
     co = phfem.make_coeffs(a_T=torch.tensor(aT, device=ctx.device))
@@ -218,9 +220,9 @@ def test_multigrid_solve_parity(ctx, oracle, levels):
     U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
     Lam = torch.empty(dm.info.L, dtype=torch.float64, device=ctx.device)
     st = phfem.phf_solve(dm.handle, co, s, U, Lam, rtol=1e-13, saddle_residual=True,
-                         precond=phfem.PHF_PRECOND_MULTIGRID)
+                         precond=phfem.PHF_PRECOND_MULTIGRID, mg_smoother=sm)
     print(f"  iterations {st.iterations}", flush=True)
-    assert st.converged and st.iterations <= 45
+    assert st.converged and st.iterations <= (30 if smoother == "chebyshev" else 45)
     tables = oracle.mesh_tables(m)
     asm = oracle.assemble(m, tables, aT=aT, **od)
     Uo, Lo = oracle.solve_saddle(asm)
@@ -232,6 +234,63 @@ def test_multigrid_solve_parity(ctx, oracle, levels):
     st2 = phfem.phf_solve(dm.handle, co, s, U2, None, rtol=1e-13, max_iter=50000)
     assert _rel(U2.cpu().numpy(), Uo) < 1e-9
     print(f"  jacobi iterations {st2.iterations}", flush=True)
+
+
+def test_multigrid_smoothers_jittered(ctx, oracle):
+    """A jittered mesh (obtuse triangles: positive off-diagonal entries, a
+    Gershgorin bound of D^-1 A above 2) refined three times: both smoothers,
+    one to four sweeps, reach the oracle's solution; Chebyshev smoothing with
+    three or four sweeps stays within 40 iterations, fewer than two Jacobi
+    sweeps need."""
+    import torch
+    from paper_2401_15557_amd import phfem
+    base = G.jittered_square(6, np.random.default_rng(7), jitter=0.3)
+    dm, m = _refined_pair(ctx, oracle, base, 3)
+    aT = G.per_triangle_coefficient(m.nE, 9)
+    od, gd = _both(oracle, phfem, "const")
+    co = phfem.make_coeffs(a_T=torch.tensor(aT, device=ctx.device))
+    s, t = phfem.alloc_system(dm)
+    phfem.phf_assemble(dm.handle, co, gd, s)
+    Uo, _ = oracle.solve_saddle(oracle.assemble(m, oracle.mesh_tables(m), aT=aT, **od))
+    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    its = {}
+    for sm, nu, rg in ((phfem.PHF_MG_SMOOTH_JACOBI, 2, 0.0), (phfem.PHF_MG_SMOOTH_JACOBI, 1, 0.0),
+                       (phfem.PHF_MG_SMOOTH_CHEBYSHEV, 1, 0.0),
+                       (phfem.PHF_MG_SMOOTH_CHEBYSHEV, 3, 0.0),
+                       (phfem.PHF_MG_SMOOTH_CHEBYSHEV, 4, 30.0),
+                       (phfem.PHF_MG_SMOOTH_CHEBYSHEV, 2, 2.0)):
+        U.fill_(np.nan)
+        st = phfem.phf_solve(dm.handle, co, s, U, None, rtol=1e-13, mg_sweeps=nu,
+                             mg_smoother=sm, mg_range=rg, precond=phfem.PHF_PRECOND_MULTIGRID)
+        print(f"smoother {sm} sweeps {nu} range {rg}: {st.iterations} iterations, "
+              f"rel {_rel(U.cpu().numpy(), Uo):.2e}", flush=True)
+        its[(sm, nu)] = (st.converged, st.iterations, _rel(U.cpu().numpy(), Uo))
+    for (sm, nu), (conv, n, rel) in its.items():
+        assert conv and rel < 1e-9, (sm, nu, n, rel)
+    # a fixed damping of 0.8 over-corrects where lmax > 2.5 (about 200
+    # iterations here); the Chebyshev weights follow the bound
+    assert its[(phfem.PHF_MG_SMOOTH_CHEBYSHEV, 3)][1] <= 40
+    assert its[(phfem.PHF_MG_SMOOTH_CHEBYSHEV, 4)][1] <= 40
+    assert its[(phfem.PHF_MG_SMOOTH_CHEBYSHEV, 3)][1] < its[(phfem.PHF_MG_SMOOTH_JACOBI, 2)][1]
+
+
+def test_multigrid_option_errors(ctx):
+    import torch
+    from paper_2401_15557_amd import phfem
+    dm = phfem.Mesh(ctx, G.lshape(0)).refine()
+    co = phfem.make_coeffs()
+    s, t = phfem.alloc_system(dm)
+    phfem.phf_assemble(dm.handle, co, phfem.make_data(phfem.make_fn(phfem.PHF_FN_CONST, 1)), s)
+    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    for kw in (dict(mg_sweeps=9), dict(mg_sweeps=-1), dict(mg_smoother=3),
+               dict(mg_range=1.0), dict(mg_range=-2.0), dict(mg_omega=-0.5)):
+        with pytest.raises(phfem.PhfError) as ei:
+            phfem.phf_solve(dm.handle, co, s, U, precond=phfem.PHF_PRECOND_MULTIGRID, **kw)
+        assert ei.value.code == phfem.PHF_EINVAL, kw
+    # the largest sweep count is accepted
+    st = phfem.phf_solve(dm.handle, co, s, U, precond=phfem.PHF_PRECOND_MULTIGRID, mg_sweeps=8)
+    assert st.converged
+    dm.close()
 
 
 def test_multigrid_needs_hierarchy(ctx):
