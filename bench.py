@@ -57,14 +57,17 @@ def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None, jacobi=Fa
     (8 B/row); write K and M (72 B/elem each), F (24 B/elem), C (8 B/nnz)
     and b_D (8 B/row).
     V-cycle kernels (single precision) on level l with n unknowns
-    (level_nf[l]), operator rows of five (int32 column, fp32 value) slots =
-    40 B/row: smoothing sweep 40 + 4 (dinv) + 4 (b) + 4 (x) + 4 (y) = 56 B/row;
-    first sweep from zero 12 B/row (20 on the finest level, which also rounds
-    the fp64 residual once); residual 52 B/row; prolongation 40 (P) + 8 (x in
-    and out) B/fine row + 4 B/coarse row; finish (z = x in fp64, r.z) 20 B/row;
-    restriction from level l: per coarse triangle 36 B of fine row ids, 4 B
-    code word, 12 B of sums written, plus the fine residual once (4 B/fine
-    row), then 20 B per coarse row to sum the two sides.
+    (level_nf[l]), operator rows scaled by the inverse diagonal with four
+    off-diagonal (int32 column, fp32 value) slots = 32 B/row: smoothing sweep
+    32 + 4 (D^-1 b) + 4 (x) + 4 (y) = 44 B/row; first sweep from zero on the
+    finest level (rounds the fp64 residual once) 8 + 4 (dinv) + 4 + 4 =
+    20 B/row; last finest sweep, which also writes z in fp64 and reduces r.z,
+    32 + 4 + 4 + 8 (r) + 8 (z) = 56 B/row; residual 32 + 4 (diag) + 4 + 4 +
+    4 (r) = 48 B/row; prolongation 40 (P) + 8 (x in and out) B/fine row +
+    4 B/coarse row; restriction from level l: per coarse triangle 36 B of fine
+    row ids, 4 B code word, 12 B of sums written, plus the fine residual once
+    (4 B/fine row), then per coarse row 8 (positions) + 8 (two sums) + 4
+    (dinv) in, 4 (D^-1 b) + 4 (first sweep) out = 28 B.
     """
     nE, nC, L = info.nE, info.nC, info.L
     nf, nnzR = info.n_free, info.nnz_reduced
@@ -73,15 +76,16 @@ def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None, jacobi=Fa
     mg = {}
     top = len(level_nf or []) - 1
     for l, n in enumerate(level_nf or []):
-        mg[f"k_mg_smooth.L{l}"] = 56 * n
-        mg[f"k_mg_smooth0.L{l}"] = (20 if l == top else 12) * n
-        mg[f"k_mg_resid.L{l}"] = 52 * n
+        mg[f"k_mg_smooth.L{l}"] = 44 * n
+        if l == top:
+            mg[f"k_mg_smooth0.L{l}"] = 20 * n
+            mg[f"k_mg_smooth_z.L{l}"] = 56 * n
+        mg[f"k_mg_resid.L{l}"] = 48 * n
         if l > 0:
             mg[f"k_mg_prolong.L{l}"] = 48 * n + 4 * level_nf[l - 1]
             if level_nE:
                 mg[f"k_mg_restrict.L{l}"] = 52 * level_nE[l - 1] + 4 * n
-            mg[f"k_mg_collect.L{l}"] = 20 * level_nf[l - 1]
-        mg[f"k_mg_finish.L{l}"] = 20 * n
+            mg[f"k_mg_collect.L{l}"] = 28 * level_nf[l - 1]
     return {
         **mg,
         "k_assemble": asm,

@@ -44,9 +44,9 @@
 // Device view of one level, for the single-workgroup cycle.
 struct phf_mg_dev_level {
     int32_t n = 0, nEc = 0;  // unknowns; elements of the next coarser mesh
-    const int32_t* col = nullptr;
-    const float *val = nullptr, *dinv = nullptr;
-    float *x = nullptr, *y = nullptr, *b = nullptr, *r = nullptr;
+    const int32_t* col = nullptr;  // scaled operator (ELL-4 of D^-1 A off the diagonal)
+    const float *val = nullptr, *diag = nullptr, *dinv = nullptr;
+    float *x = nullptr, *y = nullptr, *b = nullptr, *r = nullptr;  // b holds D^-1 b
     const int32_t* P_col = nullptr;  // prolongation from the next coarser level
     const float* P_val = nullptr;
     const int32_t* rows9 = nullptr;  // restriction to the next coarser level
@@ -63,10 +63,12 @@ struct phf_mg_level {
     int32_t nf = 0;
     // coarse-level assembly buffers (null on the finest level)
     double *K = nullptr, *M = nullptr, *C = nullptr, *F = nullptr, *bD = nullptr, *aT = nullptr;
-    // single-precision copies of this level's operator values (ELL-5, the
-    // columns are the operator's own) and inverse diagonal
-    float *val32 = nullptr, *dinv32 = nullptr;
-    // V-cycle vectors (single precision)
+    // single-precision scaled operator: the off-diagonal entries of D^-1 A
+    // (ELL-4, slot-major; unused slots hold the row itself and 0), the
+    // diagonal D and its inverse
+    int32_t* col4 = nullptr;
+    float *val4 = nullptr, *diag32 = nullptr, *dinv32 = nullptr;
+    // V-cycle vectors (single precision); b holds the scaled D^-1 b
     float *x = nullptr, *y = nullptr, *b = nullptr, *r = nullptr;
     // prolongation from the next coarser level (ELL-5 over this level's rows)
     int32_t* P_col = nullptr;

@@ -180,28 +180,40 @@ __device__ inline float ell5(int32_t r, int32_t n, const int32_t* __restrict__ c
     return s;
 }
 
+// The cycle's operator rows are scaled by the inverse diagonal: four
+// off-diagonal slots of D^-1 A (ELL-4, slot-major; unused slots hold column r
+// and value 0) and an implicit unit diagonal; right-hand sides are kept as
+// D^-1 b. sres is then the scaled residual D^-1 (b - A x) of row i.
+__device__ inline float sres(int32_t i, int32_t n, const int32_t* __restrict__ col,
+                             const float* __restrict__ val, const float* __restrict__ bh,
+                             const float* __restrict__ x)
+{
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t slot = (int64_t)k * n + i;
+        s = fmaf(val[slot], x[col[slot]], s);
+    }
+    return bh[i] - x[i] - s;
+}
+
 // Per-row (per-triangle) steps of the cycle, shared by the one-launch-per-step
 // kernels of the large levels and the single-workgroup kernel of the small
 // ones, so both compute the same values.
-__device__ inline void row_smooth0(int32_t i, const float* __restrict__ dinv,
-                                   const float* __restrict__ b, float omega, float* __restrict__ x)
-{
-    x[i] = omega * dinv[i] * b[i];
-}
-
 __device__ inline void row_smooth(int32_t i, int32_t n, const int32_t* __restrict__ col,
-                                  const float* __restrict__ val, const float* __restrict__ dinv,
-                                  const float* __restrict__ b, float omega,
-                                  const float* __restrict__ x, float* __restrict__ y)
+                                  const float* __restrict__ val, const float* __restrict__ bh,
+                                  float omega, const float* __restrict__ x, float* __restrict__ y)
 {
-    y[i] = x[i] + omega * dinv[i] * (b[i] - ell5(i, n, col, val, x));
+    y[i] = x[i] + omega * sres(i, n, col, val, bh, x);
 }
 
+// Unscaled residual b - A x = D (D^-1 b - D^-1 A x).
 __device__ inline void row_resid(int32_t i, int32_t n, const int32_t* __restrict__ col,
-                                 const float* __restrict__ val, const float* __restrict__ b,
-                                 const float* __restrict__ x, float* __restrict__ r)
+                                 const float* __restrict__ val, const float* __restrict__ diag,
+                                 const float* __restrict__ bh, const float* __restrict__ x,
+                                 float* __restrict__ r)
 {
-    r[i] = b[i] - ell5(i, n, col, val, x);
+    r[i] = diag[i] * sres(i, n, col, val, bh, x);
 }
 
 // Restriction, first half: for coarse triangle p and each of its edges l, the
@@ -247,12 +259,17 @@ __device__ inline void tri_restrict(int32_t p, int32_t nEc, const int32_t* __res
 }
 
 // Restriction, second half: coarse row c sums its edge's entries from T+ and
-// T- (in that order).
+// T- (in that order), keeps the scaled right-hand side D^-1 b and takes the
+// coarse level's first sweep from zero, x = omega D^-1 b.
 __device__ inline void row_collect(int32_t c, const int2* __restrict__ sel,
-                                   const float* __restrict__ t, float* __restrict__ bc)
+                                   const float* __restrict__ t, const float* __restrict__ dinv,
+                                   float omega, float* __restrict__ bh, float* __restrict__ x)
 {
     const int2 q = sel[c];
-    bc[c] = q.y >= 0 ? t[q.x] + t[q.y] : t[q.x];
+    const float b = q.y >= 0 ? t[q.x] + t[q.y] : t[q.x];
+    const float h = b * dinv[c];
+    bh[c] = h;
+    x[c] = omega * h;
 }
 
 __device__ inline void row_prolong(int32_t i, int32_t n, const int32_t* __restrict__ P_col,
@@ -262,46 +279,71 @@ __device__ inline void row_prolong(int32_t i, int32_t n, const int32_t* __restri
     x[i] += ell5(i, n, P_col, P_val, xc);
 }
 
+// Coarsest level: x = A^-1 b with b = D (D^-1 b).
 __device__ inline void row_coarse(int32_t i, int32_t n, const double* __restrict__ Ainv,
-                                  const float* __restrict__ b, float* __restrict__ x)
+                                  const float* __restrict__ diag, const float* __restrict__ bh,
+                                  float* __restrict__ x)
 {
     double s = 0.0;
-    for (int32_t j = 0; j < n; ++j) s = fma(Ainv[(int64_t)i * n + j], (double)b[j], s);
+    for (int32_t j = 0; j < n; ++j)
+        s = fma(Ainv[(int64_t)i * n + j], (double)diag[j] * (double)bh[j], s);
     x[i] = (float)s;
 }
 
-__global__ __launch_bounds__(NT) void k_mg_f32(int64_t n, const double* __restrict__ in,
-                                               float* __restrict__ out)
+// Single-precision scaled copy of a level's operator: off-diagonal entries
+// of row r divided by its diagonal a_rr (1 where a_rr <= 0, as for the
+// double-precision inverse diagonal), the diagonal and its inverse.
+__global__ __launch_bounds__(NT) void k_mg_scale(int32_t n, const int32_t* __restrict__ col,
+                                                 const double* __restrict__ val,
+                                                 int32_t* __restrict__ col4,
+                                                 float* __restrict__ val4,
+                                                 float* __restrict__ diag,
+                                                 float* __restrict__ dinv)
 {
-    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
-        out[i] = (float)in[i];
+    for (int32_t r = blockIdx.x * NT + threadIdx.x; r < n; r += gridDim.x * NT) {
+        double d = 0.0;
+        int32_t c4[4] = {r, r, r, r};
+        double v4[4] = {0.0, 0.0, 0.0, 0.0};
+        int cnt = 0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const int64_t slot = (int64_t)k * n + r;
+            const int32_t c = col[slot];
+            const double v = val[slot];
+            if (c == r) {
+                d += v;  // the diagonal (unused slots add zero)
+            } else if (cnt < 4) {  // a free edge has at most four neighbours
+                c4[cnt] = c;
+                v4[cnt] = v;
+                ++cnt;
+            }
+        }
+        const double di = d > 0.0 ? 1.0 / d : 1.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            col4[(int64_t)k * n + r] = c4[k];
+            val4[(int64_t)k * n + r] = (float)(v4[k] * di);
+        }
+        diag[r] = d > 0.0 ? (float)d : 1.0f;
+        dinv[r] = (float)di;
+    }
 }
 
 // First sweep from x = 0 on the finest level: also rounds the right-hand side
-// (the double-precision CG residual) once for the rest of the cycle.
+// (the double-precision residual of the outer iteration) once, scaled.
 __global__ __launch_bounds__(NT) void k_mg_smooth0_top(int32_t n, const float* __restrict__ dinv,
                                                        const double* __restrict__ b64,
                                                        const float* __restrict__ w,
-                                                       float* __restrict__ b, float* __restrict__ x,
-                                                       const int* iflags)
+                                                       float* __restrict__ bh,
+                                                       float* __restrict__ x, const int* iflags)
 {
     if (iflags && iflags[0]) return;
     const float omega = w[0];
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-        b[i] = (float)b64[i];
-        row_smooth0(i, dinv, b, omega, x);
+        const float h = (float)b64[i] * dinv[i];
+        bh[i] = h;
+        x[i] = omega * h;
     }
-}
-
-__global__ __launch_bounds__(NT) void k_mg_smooth0(int32_t n, const float* __restrict__ dinv,
-                                                   const float* __restrict__ b,
-                                                   const float* __restrict__ w, int32_t k,
-                                                   float* __restrict__ x, const int* iflags)
-{
-    if (iflags && iflags[0]) return;
-    const float omega = w[k];
-    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
-        row_smooth0(i, dinv, b, omega, x);
 }
 
 // FINEST only separates the finest level's launches under their own symbol
@@ -309,8 +351,7 @@ __global__ __launch_bounds__(NT) void k_mg_smooth0(int32_t n, const float* __res
 template <bool FINEST>
 __global__ __launch_bounds__(NT) void k_mg_smooth(int32_t n, const int32_t* __restrict__ col,
                                                   const float* __restrict__ val,
-                                                  const float* __restrict__ dinv,
-                                                  const float* __restrict__ b,
+                                                  const float* __restrict__ bh,
                                                   const float* __restrict__ w, int32_t k,
                                                   const float* __restrict__ x,
                                                   float* __restrict__ y, const int* iflags)
@@ -318,18 +359,44 @@ __global__ __launch_bounds__(NT) void k_mg_smooth(int32_t n, const int32_t* __re
     if (iflags && iflags[0]) return;
     const float omega = w[k];
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
-        row_smooth(i, n, col, val, dinv, b, omega, x, y);
+        row_smooth(i, n, col, val, bh, omega, x, y);
+}
+
+// Last sweep on the finest level, which also hands the cycle's result to the
+// outer iteration: z = y in double precision and per-block partial sums of
+// r.z (fixed order within the block; the grid is the outer iteration's).
+__global__ __launch_bounds__(NT) void k_mg_smooth_z(int32_t n, const int32_t* __restrict__ col,
+                                                    const float* __restrict__ val,
+                                                    const float* __restrict__ bh,
+                                                    const float* __restrict__ w, int32_t k,
+                                                    const float* __restrict__ x,
+                                                    const double* __restrict__ r,
+                                                    double* __restrict__ z,
+                                                    double* __restrict__ part, const int* iflags)
+{
+    if (iflags && iflags[0]) return;
+    __shared__ double sh[NT / 64];
+    const float omega = w[k];
+    double s = 0.0;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+        const double zi = (double)(x[i] + omega * sres(i, n, col, val, bh, x));
+        z[i] = zi;
+        s = fma(r[i], zi, s);
+    }
+    const double t = phf_block_sum_f64<NT>(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 __global__ __launch_bounds__(NT) void k_mg_resid(int32_t n, const int32_t* __restrict__ col,
                                                  const float* __restrict__ val,
-                                                 const float* __restrict__ b,
+                                                 const float* __restrict__ diag,
+                                                 const float* __restrict__ bh,
                                                  const float* __restrict__ x,
                                                  float* __restrict__ r, const int* iflags)
 {
     if (iflags && iflags[0]) return;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
-        row_resid(i, n, col, val, b, x, r);
+        row_resid(i, n, col, val, diag, bh, x, r);
 }
 
 __global__ __launch_bounds__(NT) void k_mg_restrict(int32_t nEc, const int32_t* __restrict__ rows9,
@@ -344,11 +411,15 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(int32_t nEc, const int32_t* 
 
 __global__ __launch_bounds__(NT) void k_mg_collect(int32_t nc, const int2* __restrict__ sel,
                                                    const float* __restrict__ t,
-                                                   float* __restrict__ bc, const int* iflags)
+                                                   const float* __restrict__ dinv,
+                                                   const float* __restrict__ w, int32_t k,
+                                                   float* __restrict__ bh, float* __restrict__ x,
+                                                   const int* iflags)
 {
     if (iflags && iflags[0]) return;
+    const float omega = w[k];
     for (int32_t c = blockIdx.x * NT + threadIdx.x; c < nc; c += gridDim.x * NT)
-        row_collect(c, sel, t, bc);
+        row_collect(c, sel, t, dinv, omega, bh, x);
 }
 
 __global__ __launch_bounds__(NT) void k_mg_prolong(int32_t n, const int32_t* __restrict__ P_col,
@@ -361,20 +432,15 @@ __global__ __launch_bounds__(NT) void k_mg_prolong(int32_t n, const int32_t* __r
         row_prolong(i, n, P_col, P_val, xc, x);
 }
 
-__global__ __launch_bounds__(NT) void k_mg_coarse(int32_t n, const double* __restrict__ Ainv,
-                                                  const float* __restrict__ b,
-                                                  float* __restrict__ x, const int* iflags)
-{
-    if (iflags && iflags[0]) return;
-    for (int32_t i = threadIdx.x; i < n; i += NT) row_coarse(i, n, Ainv, b, x);
-}
-
 // The whole V-cycle on levels 0..top of the descriptor table in one
 // workgroup: every step is a loop over its rows followed by a workgroup
 // barrier (the barrier orders the global-memory writes of the step before
-// the reads of the next one within the workgroup). Each level's result ends
-// in its descriptor's x buffer: the sweeps alternate between x and y, the
-// first one writing to whichever makes the last one land in x.
+// the reads of the next one within the workgroup). On entry the top level
+// holds D^-1 b and its first sweep from zero in y (level 0: in x), written by
+// the restriction from the level above; lower levels receive theirs the same
+// way inside the kernel. Every level then takes 2 nu - 1 more sweeps, an odd
+// number, so its result ends in x; the coarsest level solves directly into
+// x, or takes 40 further sweeps (an even number) from its first one in x.
 constexpr int TAIL_NT = 1024;
 __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __restrict__ lv,
                                                      int32_t top, int32_t nu,
@@ -383,51 +449,46 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
 {
     if (iflags && iflags[0]) return;
     const int32_t tid = threadIdx.x;
-    // down: pre-smoothing, residual, restriction
+    // down: pre-smoothing, residual, restriction (with the coarse first sweep)
     for (int32_t l = top; l >= 1; --l) {
         const phf_mg_dev_level L = lv[l];
         const phf_mg_dev_level C = lv[l - 1];
-        // 2 nu - 1 sweeps follow the first: it writes y when that count is odd
-        float* u = ((2 * nu - 1) & 1) ? L.y : L.x;
-        float* v = u == L.x ? L.y : L.x;
-        for (int32_t i = tid; i < L.n; i += TAIL_NT) row_smooth0(i, L.dinv, L.b, L.w[0], u);
-        __syncthreads();
+        float *u = L.y, *v = L.x;
         for (int32_t s = 1; s < nu; ++s) {
             const float omega = L.w[s];
             for (int32_t i = tid; i < L.n; i += TAIL_NT)
-                row_smooth(i, L.n, L.col, L.val, L.dinv, L.b, omega, u, v);
+                row_smooth(i, L.n, L.col, L.val, L.b, omega, u, v);
             __syncthreads();
-            float* w = u;
+            float* q = u;
             u = v;
-            v = w;
+            v = q;
         }
-        for (int32_t i = tid; i < L.n; i += TAIL_NT) row_resid(i, L.n, L.col, L.val, L.b, u, L.r);
+        for (int32_t i = tid; i < L.n; i += TAIL_NT) row_resid(i, L.n, L.col, L.val, L.diag, L.b, u, L.r);
         __syncthreads();
         for (int32_t p = tid; p < L.nEc; p += TAIL_NT)
             tri_restrict(p, L.nEc, L.rows9, L.ecode_c, L.r, L.t);
         __syncthreads();
-        for (int32_t c = tid; c < C.n; c += TAIL_NT) row_collect(c, C.sel, L.t, C.b);
+        const float wc = l - 1 == 0 ? C.w[PHF_MG_MAX_SWEEPS] : C.w[0];
+        float* xc = l - 1 == 0 ? C.x : C.y;
+        for (int32_t c = tid; c < C.n; c += TAIL_NT) row_collect(c, C.sel, L.t, C.dinv, wc, C.b, xc);
         __syncthreads();
     }
     // coarsest level
     {
         const phf_mg_dev_level L = lv[0];
         if (dense) {
-            for (int32_t i = tid; i < L.n; i += TAIL_NT) row_coarse(i, L.n, cinv, L.b, L.x);
+            for (int32_t i = tid; i < L.n; i += TAIL_NT) row_coarse(i, L.n, cinv, L.diag, L.b, L.x);
             __syncthreads();
         } else {
-            // 1 + 40 sweeps from zero; 40 is even, so starting in x ends in x
             float *u = L.x, *v = L.y;
             const float omega = L.w[PHF_MG_MAX_SWEEPS];
-            for (int32_t i = tid; i < L.n; i += TAIL_NT) row_smooth0(i, L.dinv, L.b, omega, u);
-            __syncthreads();
             for (int32_t s = 0; s < 40; ++s) {
                 for (int32_t i = tid; i < L.n; i += TAIL_NT)
-                    row_smooth(i, L.n, L.col, L.val, L.dinv, L.b, omega, u, v);
+                    row_smooth(i, L.n, L.col, L.val, L.b, omega, u, v);
                 __syncthreads();
-                float* w = u;
+                float* q = u;
                 u = v;
-                v = w;
+                v = q;
             }
         }
     }
@@ -435,10 +496,8 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
     for (int32_t l = 1; l <= top; ++l) {
         const phf_mg_dev_level L = lv[l];
         const phf_mg_dev_level C = lv[l - 1];
-        // after the pre-smoothing the iterate is in the buffer nu - 1 swaps
-        // away from the first sweep's
-        float* u = ((2 * nu - 1) & 1) ? L.y : L.x;
-        if ((nu - 1) & 1) u = u == L.x ? L.y : L.x;
+        // the pre-smoothing ended nu - 1 swaps away from y
+        float* u = ((nu - 1) & 1) ? L.x : L.y;
         float* v = u == L.x ? L.y : L.x;
         if (C.n > 0) {  // (uniform branch) no coarse unknowns: no correction
             for (int32_t i = tid; i < L.n; i += TAIL_NT)
@@ -448,29 +507,29 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
         for (int32_t s = 0; s < nu; ++s) {
             const float omega = L.w[s];
             for (int32_t i = tid; i < L.n; i += TAIL_NT)
-                row_smooth(i, L.n, L.col, L.val, L.dinv, L.b, omega, u, v);
+                row_smooth(i, L.n, L.col, L.val, L.b, omega, u, v);
             __syncthreads();
-            float* w = u;
+            float* q = u;
             u = v;
-            v = w;
+            v = q;
         }
     }
 }
 
 // Gershgorin bound of D^-1 A on one level: max over rows of
-// sum_j |a_ij| / a_ii (the ELL padding holds zeros), merged into *lmax as
-// the bits of a non-negative float (which order like unsigned integers).
+// 1 + sum_j |a_ij| / a_ii (the off-diagonal slots of the scaled rows),
+// merged into *lmax as the bits of a non-negative float (which order like
+// unsigned integers).
 __global__ __launch_bounds__(NT) void k_mg_gersh(int32_t n, const float* __restrict__ val,
-                                                 const float* __restrict__ dinv,
                                                  uint32_t* __restrict__ lmax)
 {
     __shared__ float sh[NT];
     float m = 0.0f;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-        float s = 0.0f;
+        float s = 1.0f;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) s += fabsf(val[(int64_t)k * n + i]);
-        m = fmaxf(m, s * fabsf(dinv[i]));
+        for (int k = 0; k < 4; ++k) s += fabsf(val[(int64_t)k * n + i]);
+        m = fmaxf(m, s);
     }
     sh[threadIdx.x] = m;
     __syncthreads();
@@ -510,36 +569,18 @@ __global__ void k_mg_weights(int32_t nlev, int32_t nu, int32_t cheb, float omega
     w[PHF_MG_MAX_SWEEPS] = (float)(1.0 / c);
 }
 
-// z = x; partial sums of r.z (fixed order within the block).
-__global__ __launch_bounds__(NT) void k_mg_finish(int32_t n, const float* __restrict__ x,
-                                                  const double* __restrict__ r,
-                                                  double* __restrict__ z,
-                                                  double* __restrict__ part, const int* iflags)
-{
-    if (iflags && iflags[0]) return;
-    __shared__ double sh[NT / 64];
-    double s = 0.0;
-    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-        const double zi = (double)x[i];
-        z[i] = zi;
-        s = fma(r[i], zi, s);
-    }
-    const double t = phf_block_sum_f64<NT>(s, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
-
 unsigned grid_for(int32_t n) { return (unsigned)std::min<int64_t>(std::max<int64_t>(nblk(n), 1), 1024); }
 
 // Trace names carry the level ("k_mg_smooth.L9"), counted from the coarsest
 // mesh, so per-launch byte counts can be attributed to a level.
-enum { NM_SMOOTH0, NM_SMOOTH, NM_RESID, NM_RESTRICT, NM_COLLECT, NM_PROLONG, NM_FINISH, NM_COUNT };
+enum { NM_SMOOTH0, NM_SMOOTH, NM_SMOOTHZ, NM_RESID, NM_RESTRICT, NM_COLLECT, NM_PROLONG, NM_COUNT };
 struct mg_names {
     char s[NM_COUNT][PHF_MG_MAX_LEVELS][32];
     mg_names()
     {
-        static const char* base[NM_COUNT] = {"k_mg_smooth0", "k_mg_smooth", "k_mg_resid",
-                                             "k_mg_restrict", "k_mg_collect", "k_mg_prolong",
-                                             "k_mg_finish"};
+        static const char* base[NM_COUNT] = {"k_mg_smooth0", "k_mg_smooth", "k_mg_smooth_z",
+                                             "k_mg_resid", "k_mg_restrict", "k_mg_collect",
+                                             "k_mg_prolong"};
         for (int k = 0; k < NM_COUNT; ++k)
             for (int l = 0; l < PHF_MG_MAX_LEVELS; ++l)
                 snprintf(s[k][l], sizeof(s[k][l]), "%s.L%d", base[k], l);
@@ -568,8 +609,9 @@ void phf_mg_destroy(phf_mg* mg)
         if (L.own_ns && L.ns) phf_ns_destroy(L.ns);
         double* d[] = {L.K, L.M, L.C, L.F, L.bD, L.aT};
         for (double* p : d) phf_dfree(p);
-        float* f[] = {L.val32, L.dinv32, L.x, L.y, L.b, L.r, L.P_val, L.t};
+        float* f[] = {L.val4, L.diag32, L.dinv32, L.x, L.y, L.b, L.r, L.P_val, L.t};
         for (float* p : f) phf_dfree(p);
+        phf_dfree(L.col4);
         phf_dfree(L.P_col);
         phf_dfree(L.rows9);
         phf_dfree(L.sel);
@@ -617,8 +659,10 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             }
             L.nf = ms->n_free;
             const size_t nf = std::max<int32_t>(L.nf, 1);
-            TRY(phf_dmalloc(ctx, &L.val32, 5 * nf, "multigrid operator (single)"));
-            TRY(phf_dmalloc(ctx, &L.dinv32, nf, "multigrid diagonal (single)"));
+            TRY(phf_dmalloc(ctx, &L.col4, 4 * nf, "multigrid operator columns"));
+            TRY(phf_dmalloc(ctx, &L.val4, 4 * nf, "multigrid operator (single)"));
+            TRY(phf_dmalloc(ctx, &L.diag32, nf, "multigrid diagonal (single)"));
+            TRY(phf_dmalloc(ctx, &L.dinv32, nf, "multigrid inverse diagonal (single)"));
             TRY(phf_dmalloc(ctx, &L.x, nf, "multigrid x"));
             TRY(phf_dmalloc(ctx, &L.y, nf, "multigrid y"));
             TRY(phf_dmalloc(ctx, &L.b, nf, "multigrid b"));
@@ -656,8 +700,9 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             const phf_mg_level& L = mg->lev[l];
             phf_mg_dev_level& d = mg->h_lv[l];
             d.n = L.nf;
-            d.col = L.ns->ell_col;
-            d.val = L.val32;
+            d.col = L.col4;
+            d.val = L.val4;
+            d.diag = L.diag32;
             d.dinv = L.dinv32;
             d.x = L.x;
             d.y = L.y;
@@ -720,16 +765,13 @@ int phf_mg_numeric(phf_mg* mg, const phf_coeffs* co, double cK, double cM)
         TRY(phf_assemble_impl(L.mesh, &c, &d, &s));
         TRY(phf_ns_operator(L.ns, L.K, L.M, L.C, cK, cM));
     }
-    // single-precision copies for the cycle (the finest operator is the one
-    // the caller built)
+    // single-precision scaled operators for the cycle (the finest operator
+    // is the one the caller built)
     for (int l = 0; l <= top; ++l) {
         phf_mg_level& L = mg->lev[l];
         if (L.nf == 0) continue;
-        const int64_t n5 = 5 * (int64_t)L.nf;
-        PHF_LAUNCH(ctx, "k_mg_f32", k_mg_f32, (unsigned)std::min<int64_t>(nblk(n5), 2048), NT, 0,
-                   n5, L.ns->ell_val, L.val32);
-        PHF_LAUNCH(ctx, "k_mg_f32", k_mg_f32, (unsigned)std::min<int64_t>(nblk(L.nf), 2048), NT, 0,
-                   (int64_t)L.nf, L.ns->dinv, L.dinv32);
+        PHF_LAUNCH(ctx, "k_mg_scale", k_mg_scale, grid_for(L.nf), NT, 0, L.nf, L.ns->ell_col,
+                   L.ns->ell_val, L.col4, L.val4, L.diag32, L.dinv32);
     }
     // sweep weights
     const bool cheb = mg->smoother == PHF_MG_SMOOTH_CHEBYSHEV;
@@ -738,8 +780,8 @@ int phf_mg_numeric(phf_mg* mg, const phf_coeffs* co, double cK, double cM)
         for (int l = 0; l <= top; ++l) {
             phf_mg_level& L = mg->lev[l];
             if (L.nf == 0) continue;
-            PHF_LAUNCH(ctx, "k_mg_gersh", k_mg_gersh, grid_for(L.nf), NT, 0, L.nf, L.val32,
-                       L.dinv32, mg->lmax + l);
+            PHF_LAUNCH(ctx, "k_mg_gersh", k_mg_gersh, grid_for(L.nf), NT, 0, L.nf, L.val4,
+                       mg->lmax + l);
         }
     PHF_LAUNCH(ctx, "k_mg_weights", k_mg_weights, 1, PHF_MG_MAX_LEVELS, 0, mg->nlev, mg->nu,
                cheb ? 1 : 0, (float)mg->omega, (float)mg->range, mg->lmax, mg->wts);
@@ -764,16 +806,20 @@ int smooth(phf_mg* mg, int l, int k, const int* iflags)
     const unsigned g = grid_for(n);
     const float* w = level_weights(mg, l);
     if (l == mg->nlev - 1)
-        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth<true>, g, NT, 0, n, L.ns->ell_col,
-                   L.val32, L.dinv32, L.b, w, k, L.x, L.y, iflags);
+        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth<true>, g, NT, 0, n, L.col4, L.val4,
+                   L.b, w, k, L.x, L.y, iflags);
     else
-        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth<false>, g, NT, 0, n, L.ns->ell_col,
-                   L.val32, L.dinv32, L.b, w, k, L.x, L.y, iflags);
+        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth<false>, g, NT, 0, n, L.col4, L.val4,
+                   L.b, w, k, L.x, L.y, iflags);
     std::swap(L.x, L.y);
     return PHF_OK;
 }
 
-int vcycle(phf_mg* mg, int l, const double* r_top, const int* iflags)
+// Cycle on level l > tail_top. On entry L.b holds D^-1 b and L.x the first
+// sweep from zero, except on the finest level (r_top != null), where this
+// function starts from the double-precision residual r_top; there the last
+// sweep writes z and the partial sums of r.z instead of x.
+int vcycle(phf_mg* mg, int l, const double* r_top, double* z, double* part_rz, const int* iflags)
 {
     phf_mg_level& L = mg->lev[l];
     phf_ctx* ctx = L.mesh->ctx;
@@ -786,45 +832,34 @@ int vcycle(phf_mg* mg, int l, const double* r_top, const int* iflags)
     const int32_t n = L.nf;
     if (n == 0) return PHF_OK;
     const unsigned g = grid_for(n);
-    phf_ns* ns = L.ns;
-    if (l == 0) {
-        if (mg->cinv) {
-            PHF_LAUNCH(ctx, "k_mg_coarse", k_mg_coarse, 1, NT, 0, n, mg->cinv, L.b, L.x, iflags);
-        } else {
-            // no dense inverse: many damped Jacobi sweeps
-            const float* w = level_weights(mg, l);
-            PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0, g, NT, 0, n, L.dinv32, L.b, w,
-                       PHF_MG_MAX_SWEEPS, L.x, iflags);
-            for (int s = 0; s < 40; ++s) {
-                PHF_LAUNCH(ctx, mg_name(NM_SMOOTH, l), k_mg_smooth<false>, g, NT, 0, n, ns->ell_col, L.val32,
-                           L.dinv32, L.b, w, PHF_MG_MAX_SWEEPS, L.x, L.y, iflags);
-                std::swap(L.x, L.y);
-            }
-        }
-        return PHF_OK;
-    }
-    // pre-smoothing from x = 0 (on the finest level the right-hand side is
-    // the double-precision residual r_top)
+    const float* w = level_weights(mg, l);
     if (r_top)
-        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0_top, g, NT, 0, n, L.dinv32, r_top,
-                   level_weights(mg, l), L.b, L.x, iflags);
-    else
-        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0, g, NT, 0, n, L.dinv32, L.b,
-                   level_weights(mg, l), 0, L.x, iflags);
+        PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0_top, g, NT, 0, n, L.dinv32, r_top, w,
+                   L.b, L.x, iflags);
     for (int s = 1; s < mg->nu; ++s) TRY(smooth(mg, l, s, iflags));
     phf_mg_level& C = mg->lev[l - 1];
     if (C.nf > 0) {
-        PHF_LAUNCH(ctx, mg_name(NM_RESID, l), k_mg_resid, g, NT, 0, n, ns->ell_col, L.val32, L.b, L.x,
-                   L.r, iflags);
+        PHF_LAUNCH(ctx, mg_name(NM_RESID, l), k_mg_resid, g, NT, 0, n, L.col4, L.val4, L.diag32,
+                   L.b, L.x, L.r, iflags);
         PHF_LAUNCH(ctx, mg_name(NM_RESTRICT, l), k_mg_restrict, grid_for(C.mesh->nE), NT, 0,
                    C.mesh->nE, L.rows9, C.mesh->ecode, L.r, L.t, iflags);
+        // the coarse level's first sweep lands where its cycle expects it:
+        // the single-workgroup kernel in y (the coarsest level in x), the
+        // per-step launches in the current x
+        const bool in_tail = l - 1 <= mg->tail_top;
+        float* xc = in_tail && l - 1 > 0 ? C.y : C.x;
+        const int32_t kc = l - 1 == 0 ? PHF_MG_MAX_SWEEPS : 0;
         PHF_LAUNCH(ctx, mg_name(NM_COLLECT, l), k_mg_collect, grid_for(C.nf), NT, 0, C.nf, C.sel,
-                   L.t, C.b, iflags);
-        TRY(vcycle(mg, l - 1, nullptr, iflags));
-        PHF_LAUNCH(ctx, mg_name(NM_PROLONG, l), k_mg_prolong, g, NT, 0, n, L.P_col, L.P_val, C.x, L.x,
-                   iflags);
+                   L.t, C.dinv32, level_weights(mg, l - 1), kc, C.b, xc, iflags);
+        TRY(vcycle(mg, l - 1, nullptr, nullptr, nullptr, iflags));
+        PHF_LAUNCH(ctx, mg_name(NM_PROLONG, l), k_mg_prolong, g, NT, 0, n, L.P_col, L.P_val, C.x,
+                   L.x, iflags);
     }
-    for (int s = 0; s < mg->nu; ++s) TRY(smooth(mg, l, s, iflags));
+    const int last = r_top ? mg->nu - 1 : mg->nu;
+    for (int s = 0; s < last; ++s) TRY(smooth(mg, l, s, iflags));
+    if (r_top)
+        PHF_LAUNCH(ctx, mg_name(NM_SMOOTHZ, l), k_mg_smooth_z, g, NT, 0, n, L.col4, L.val4, L.b, w,
+                   mg->nu - 1, L.x, r_top, z, part_rz, iflags);
     return PHF_OK;
 }
 }  // namespace
@@ -833,11 +868,7 @@ int phf_mg_apply(phf_mg* mg, const double* r, double* z, double* part_rz, const 
 {
     const int top = mg->nlev - 1;
     phf_mg_level& F = mg->lev[top];
-    phf_ctx* ctx = F.mesh->ctx;
     if (F.nf == 0) return PHF_OK;
-    // the finest right-hand side is the CG residual itself
-    TRY(vcycle(mg, top, r, iflags));
-    PHF_LAUNCH(ctx, mg_name(NM_FINISH, top), k_mg_finish, grid_for(F.nf), NT, 0, F.nf, F.x, r, z, part_rz,
-               iflags);
-    return PHF_OK;
+    // the finest right-hand side is the residual of the outer iteration
+    return vcycle(mg, top, r, z, part_rz, iflags);
 }
