@@ -60,9 +60,10 @@ def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None, jacobi=Fa
     (level_nf[l]), operator rows scaled by the inverse diagonal with four
     off-diagonal (int32 column, fp32 value) slots = 32 B/row: smoothing sweep
     32 + 4 (D^-1 b) + 4 (x) + 4 (y) = 44 B/row; first sweep from zero on the
-    finest level (rounds the fp64 residual once) 8 + 4 (dinv) + 4 + 4 =
-    20 B/row; last finest sweep, which also writes z in fp64 and reduces r.z,
-    32 + 4 + 4 + 8 (r) + 8 (z) = 56 B/row; residual 32 + 4 (diag) + 4 + 4 +
+    finest level (rounds the fp64 residual once; only for the first cycle,
+    later ones get it from the CG update) 8 + 4 (dinv) + 4 + 4 = 20 B/row;
+    last finest sweep, which also writes z (fp32 for CG) and reduces r.z,
+    32 + 4 + 4 + 8 (r) + 4 (z) = 52 B/row; residual 32 + 4 (diag) + 4 + 4 +
     4 (r) = 48 B/row; prolongation 40 (P) + 8 (x in and out) B/fine row +
     4 B/coarse row; restriction from level l: per coarse triangle 36 B of fine
     row ids, 4 B code word, 12 B of sums written, plus the fine residual once
@@ -79,7 +80,7 @@ def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None, jacobi=Fa
         mg[f"k_mg_smooth.L{l}"] = 44 * n
         if l == top:
             mg[f"k_mg_smooth0.L{l}"] = 20 * n
-            mg[f"k_mg_smooth_z.L{l}"] = 56 * n
+            mg[f"k_mg_smooth_z.L{l}"] = 52 * n
         mg[f"k_mg_resid.L{l}"] = 48 * n
         if l > 0:
             mg[f"k_mg_prolong.L{l}"] = 48 * n + 4 * level_nf[l - 1]
@@ -89,10 +90,12 @@ def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None, jacobi=Fa
     return {
         **mg,
         "k_assemble": asm,
-        # reduced operator values + columns (12 B/nnz), z in; p, q in and out
-        "k_cg_dir": 12 * nnzR + 40 * nf,
-        # read p, q, w, r (and dinv); write w, r (and z with Jacobi)
-        "k_cg_upd": (64 if jacobi else 48) * nf,
+        # reduced operator values + columns (12 B/nnz), z in (fp64 with
+        # Jacobi, the cycle's fp32 result with multigrid); p, q in and out
+        "k_cg_dir": 12 * nnzR + (40 if jacobi else 36) * nf,
+        # read p, q, w, r; write w, r; Jacobi: dinv in, z out (fp64);
+        # multigrid: the first sweep, dinv (fp32) in, D^-1 r and x out (fp32)
+        "k_cg_upd": (64 if jacobi else 60) * nf,
     }
 
 

@@ -35,7 +35,9 @@
 #define PHF_MG_DENSE_MAX 256
 // Levels with at most this many unknowns (below the finest) run their part of
 // the cycle in one single-workgroup launch.
+#ifndef PHF_MG_TAIL_MAX
 #define PHF_MG_TAIL_MAX 2048
+#endif
 // Sweeps per side at most; each level keeps PHF_MG_MAX_SWEEPS sweep weights
 // and, last, the weight of the plain sweeps of an iterative coarsest solve.
 #define PHF_MG_MAX_SWEEPS 8
@@ -98,6 +100,17 @@ struct phf_mg {
     double range = 4.0;      // Chebyshev: smoothing range [lmax / range, lmax]
     uint32_t* lmax = nullptr;  // per level: Gershgorin bound (float bits)
     float* wts = nullptr;      // per level: PHF_MG_WSTRIDE sweep weights
+    float* z32 = nullptr;      // finest-level result for conjugate gradients
+};
+
+// Finest-level buffers through which the outer iteration's update can take
+// the cycle's first sweep from zero itself: bh = D^-1 r (single precision),
+// x = w[0] bh. Valid until the next cycle is queued.
+struct phf_mg_top {
+    float* bh;
+    float* x;
+    const float* dinv;
+    const float* w;
 };
 
 // Builds the hierarchy below the finest operator `fine` (whose mesh must come
@@ -111,5 +124,11 @@ int phf_mg_numeric(phf_mg* mg, const phf_coeffs* coeffs, double cK, double cM);
 // z = V-cycle(r) on the finest level; writes partial sums of r.z into
 // part (slot layout of the CG kernels). Skipped when *iflags (done) is set.
 int phf_mg_apply(phf_mg* mg, const double* r, double* z, double* part_rz, const int* iflags);
+// The same with the result in single precision in mg->z32 (it is the cycle's
+// single-precision iterate, so nothing is lost); first_done: the caller has
+// already written the first sweep through phf_mg_top_view.
+int phf_mg_apply32(phf_mg* mg, const double* r, bool first_done, double* part_rz,
+                   const int* iflags);
+phf_mg_top phf_mg_top_view(phf_mg* mg);
 // Number of hierarchy levels below and including `mesh`.
 int32_t phf_mg_levels(const phf_mesh* mesh);

@@ -363,15 +363,16 @@ __global__ __launch_bounds__(NT) void k_mg_smooth(int32_t n, const int32_t* __re
 }
 
 // Last sweep on the finest level, which also hands the cycle's result to the
-// outer iteration: z = y in double precision and per-block partial sums of
-// r.z (fixed order within the block; the grid is the outer iteration's).
+// outer iteration: z = y (stored as ZT) and per-block partial sums of r.z
+// (fixed order within the block; the grid is the outer iteration's).
+template <typename ZT>
 __global__ __launch_bounds__(NT) void k_mg_smooth_z(int32_t n, const int32_t* __restrict__ col,
                                                     const float* __restrict__ val,
                                                     const float* __restrict__ bh,
                                                     const float* __restrict__ w, int32_t k,
                                                     const float* __restrict__ x,
                                                     const double* __restrict__ r,
-                                                    double* __restrict__ z,
+                                                    ZT* __restrict__ z,
                                                     double* __restrict__ part, const int* iflags)
 {
     if (iflags && iflags[0]) return;
@@ -379,9 +380,9 @@ __global__ __launch_bounds__(NT) void k_mg_smooth_z(int32_t n, const int32_t* __
     const float omega = w[k];
     double s = 0.0;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-        const double zi = (double)(x[i] + omega * sres(i, n, col, val, bh, x));
-        z[i] = zi;
-        s = fma(r[i], zi, s);
+        const float zi = x[i] + omega * sres(i, n, col, val, bh, x);
+        z[i] = (ZT)zi;
+        s = fma(r[i], (double)zi, s);
     }
     const double t = phf_block_sum_f64<NT>(s, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -442,6 +443,14 @@ __global__ __launch_bounds__(NT) void k_mg_prolong(int32_t n, const int32_t* __r
 // number, so its result ends in x; the coarsest level solves directly into
 // x, or takes 40 further sweeps (an even number) from its first one in x.
 constexpr int TAIL_NT = 1024;
+// Rows 0..n-1 of one step of the single-workgroup cycle: row i gets
+// st(i, f(i)).
+template <typename F, typename S>
+__device__ inline void tail_rows(int32_t n, int32_t tid, F f, S st)
+{
+    for (int32_t i = tid; i < n; i += TAIL_NT) st(i, f(i));
+}
+
 __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __restrict__ lv,
                                                      int32_t top, int32_t nu,
                                                      const double* __restrict__ cinv,
@@ -456,14 +465,17 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
         float *u = L.y, *v = L.x;
         for (int32_t s = 1; s < nu; ++s) {
             const float omega = L.w[s];
-            for (int32_t i = tid; i < L.n; i += TAIL_NT)
-                row_smooth(i, L.n, L.col, L.val, L.b, omega, u, v);
+            tail_rows(
+                L.n, tid, [&](int32_t i) { return u[i] + omega * sres(i, L.n, L.col, L.val, L.b, u); },
+                [&](int32_t i, float y) { v[i] = y; });
             __syncthreads();
             float* q = u;
             u = v;
             v = q;
         }
-        for (int32_t i = tid; i < L.n; i += TAIL_NT) row_resid(i, L.n, L.col, L.val, L.diag, L.b, u, L.r);
+        tail_rows(
+            L.n, tid, [&](int32_t i) { return L.diag[i] * sres(i, L.n, L.col, L.val, L.b, u); },
+            [&](int32_t i, float y) { L.r[i] = y; });
         __syncthreads();
         for (int32_t p = tid; p < L.nEc; p += TAIL_NT)
             tri_restrict(p, L.nEc, L.rows9, L.ecode_c, L.r, L.t);
@@ -483,8 +495,10 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
             float *u = L.x, *v = L.y;
             const float omega = L.w[PHF_MG_MAX_SWEEPS];
             for (int32_t s = 0; s < 40; ++s) {
-                for (int32_t i = tid; i < L.n; i += TAIL_NT)
-                    row_smooth(i, L.n, L.col, L.val, L.b, omega, u, v);
+                tail_rows(
+                    L.n, tid,
+                    [&](int32_t i) { return u[i] + omega * sres(i, L.n, L.col, L.val, L.b, u); },
+                    [&](int32_t i, float y) { v[i] = y; });
                 __syncthreads();
                 float* q = u;
                 u = v;
@@ -500,14 +514,16 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
         float* u = ((nu - 1) & 1) ? L.x : L.y;
         float* v = u == L.x ? L.y : L.x;
         if (C.n > 0) {  // (uniform branch) no coarse unknowns: no correction
-            for (int32_t i = tid; i < L.n; i += TAIL_NT)
-                row_prolong(i, L.n, L.P_col, L.P_val, C.x, u);
+            tail_rows(
+                L.n, tid, [&](int32_t i) { return u[i] + ell5(i, L.n, L.P_col, L.P_val, C.x); },
+                [&](int32_t i, float y) { u[i] = y; });
             __syncthreads();
         }
         for (int32_t s = 0; s < nu; ++s) {
             const float omega = L.w[s];
-            for (int32_t i = tid; i < L.n; i += TAIL_NT)
-                row_smooth(i, L.n, L.col, L.val, L.b, omega, u, v);
+            tail_rows(
+                L.n, tid, [&](int32_t i) { return u[i] + omega * sres(i, L.n, L.col, L.val, L.b, u); },
+                [&](int32_t i, float y) { v[i] = y; });
             __syncthreads();
             float* q = u;
             u = v;
@@ -613,6 +629,7 @@ void phf_mg_destroy(phf_mg* mg)
         for (float* p : f) phf_dfree(p);
         phf_dfree(L.col4);
         phf_dfree(L.P_col);
+        if (l == mg->nlev - 1) phf_dfree(mg->z32);
         phf_dfree(L.rows9);
         phf_dfree(L.sel);
     }
@@ -667,6 +684,7 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             TRY(phf_dmalloc(ctx, &L.y, nf, "multigrid y"));
             TRY(phf_dmalloc(ctx, &L.b, nf, "multigrid b"));
             TRY(phf_dmalloc(ctx, &L.r, nf, "multigrid r"));
+            if (l == nlev - 1) TRY(phf_dmalloc(ctx, &mg->z32, nf, "multigrid result (single)"));
             if (l == 0) continue;
             // prolongation from level l-1
             phf_mg_level& Cl = mg->lev[l - 1];
@@ -817,9 +835,11 @@ int smooth(phf_mg* mg, int l, int k, const int* iflags)
 
 // Cycle on level l > tail_top. On entry L.b holds D^-1 b and L.x the first
 // sweep from zero, except on the finest level (r_top != null), where this
-// function starts from the double-precision residual r_top; there the last
-// sweep writes z and the partial sums of r.z instead of x.
-int vcycle(phf_mg* mg, int l, const double* r_top, double* z, double* part_rz, const int* iflags)
+// function starts from the double-precision residual r_top (unless
+// first_done) and the last sweep writes z (z64 or z32) and the partial sums
+// of r.z instead of x.
+int vcycle(phf_mg* mg, int l, const double* r_top, bool first_done, double* z64, float* z32,
+           double* part_rz, const int* iflags)
 {
     phf_mg_level& L = mg->lev[l];
     phf_ctx* ctx = L.mesh->ctx;
@@ -833,7 +853,7 @@ int vcycle(phf_mg* mg, int l, const double* r_top, double* z, double* part_rz, c
     if (n == 0) return PHF_OK;
     const unsigned g = grid_for(n);
     const float* w = level_weights(mg, l);
-    if (r_top)
+    if (r_top && !first_done)
         PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0_top, g, NT, 0, n, L.dinv32, r_top, w,
                    L.b, L.x, iflags);
     for (int s = 1; s < mg->nu; ++s) TRY(smooth(mg, l, s, iflags));
@@ -851,15 +871,18 @@ int vcycle(phf_mg* mg, int l, const double* r_top, double* z, double* part_rz, c
         const int32_t kc = l - 1 == 0 ? PHF_MG_MAX_SWEEPS : 0;
         PHF_LAUNCH(ctx, mg_name(NM_COLLECT, l), k_mg_collect, grid_for(C.nf), NT, 0, C.nf, C.sel,
                    L.t, C.dinv32, level_weights(mg, l - 1), kc, C.b, xc, iflags);
-        TRY(vcycle(mg, l - 1, nullptr, nullptr, nullptr, iflags));
+        TRY(vcycle(mg, l - 1, nullptr, false, nullptr, nullptr, nullptr, iflags));
         PHF_LAUNCH(ctx, mg_name(NM_PROLONG, l), k_mg_prolong, g, NT, 0, n, L.P_col, L.P_val, C.x,
                    L.x, iflags);
     }
     const int last = r_top ? mg->nu - 1 : mg->nu;
     for (int s = 0; s < last; ++s) TRY(smooth(mg, l, s, iflags));
-    if (r_top)
-        PHF_LAUNCH(ctx, mg_name(NM_SMOOTHZ, l), k_mg_smooth_z, g, NT, 0, n, L.col4, L.val4, L.b, w,
-                   mg->nu - 1, L.x, r_top, z, part_rz, iflags);
+    if (r_top && z32)
+        PHF_LAUNCH(ctx, mg_name(NM_SMOOTHZ, l), k_mg_smooth_z<float>, g, NT, 0, n, L.col4, L.val4,
+                   L.b, w, mg->nu - 1, L.x, r_top, z32, part_rz, iflags);
+    else if (r_top)
+        PHF_LAUNCH(ctx, mg_name(NM_SMOOTHZ, l), k_mg_smooth_z<double>, g, NT, 0, n, L.col4,
+                   L.val4, L.b, w, mg->nu - 1, L.x, r_top, z64, part_rz, iflags);
     return PHF_OK;
 }
 }  // namespace
@@ -870,5 +893,20 @@ int phf_mg_apply(phf_mg* mg, const double* r, double* z, double* part_rz, const 
     phf_mg_level& F = mg->lev[top];
     if (F.nf == 0) return PHF_OK;
     // the finest right-hand side is the residual of the outer iteration
-    return vcycle(mg, top, r, z, part_rz, iflags);
+    return vcycle(mg, top, r, false, z, nullptr, part_rz, iflags);
+}
+
+int phf_mg_apply32(phf_mg* mg, const double* r, bool first_done, double* part_rz,
+                   const int* iflags)
+{
+    const int top = mg->nlev - 1;
+    if (mg->lev[top].nf == 0) return PHF_OK;
+    return vcycle(mg, top, r, first_done, nullptr, mg->z32, part_rz, iflags);
+}
+
+phf_mg_top phf_mg_top_view(phf_mg* mg)
+{
+    const int top = mg->nlev - 1;
+    phf_mg_level& F = mg->lev[top];
+    return phf_mg_top{F.b, F.x, F.dinv32, level_weights(mg, top)};
 }

@@ -208,14 +208,15 @@ __global__ __launch_bounds__(NT) void k_ns_gather(int32_t nf, const int32_t* __r
 // a kernel argument, so an unrolled chain can be captured in a graph; once
 // done is set, the remaining kernels of the chain return immediately.
 
+template <typename XT>
 __device__ inline double ell_row(int32_t r, int32_t nf, const int32_t* __restrict__ col,
-                                 const double* __restrict__ val, const double* __restrict__ x)
+                                 const double* __restrict__ val, const XT* __restrict__ x)
 {
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         int64_t slot = (int64_t)k * nf + r;
-        s = fma(val[slot], x[col[slot]], s);
+        s = fma(val[slot], (double)x[col[slot]], s);
     }
     return s;
 }
@@ -288,10 +289,13 @@ __global__ __launch_bounds__(NT) void k_cg_init_final(const double* __restrict__
     }
 }
 
+// ZT: double, or float where z is the multigrid cycle's single-precision
+// result (converted exactly).
+template <typename ZT>
 __global__ __launch_bounds__(NT) void k_cg_dir(int32_t nf, int32_t it, int32_t nb,
                                                const int32_t* __restrict__ col,
                                                const double* __restrict__ val,
-                                               const double* __restrict__ z,
+                                               const ZT* __restrict__ z,
                                                double* __restrict__ p, double* __restrict__ q,
                                                double* __restrict__ part, double* scal,
                                                int* iflags)
@@ -316,7 +320,7 @@ __global__ __launch_bounds__(NT) void k_cg_dir(int32_t nf, int32_t it, int32_t n
     }
     double s = 0.0;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
-        const double pi = fma(beta, p[i], z[i]);
+        const double pi = fma(beta, p[i], (double)z[i]);
         const double qi = fma(beta, q[i], ell_row(i, nf, col, val, z));
         p[i] = pi;
         q[i] = qi;
@@ -356,6 +360,41 @@ __global__ __launch_bounds__(NT) void k_cg_upd(int32_t nf, int32_t it, int32_t n
     const double t1 = phf_block_sum_f64<NT>(s_rr, sh);
     if (threadIdx.x == 0) {
         if (JAC) part[((it & 1) ? P_RZ0 : P_RZ1) * MAXB + blockIdx.x] = t0;
+        part[P_RR * MAXB + blockIdx.x] = t1;
+        if (blockIdx.x == 0) iflags[1] += 1;
+    }
+}
+
+// The update with the multigrid preconditioner, which also takes the cycle's
+// first sweep from zero on the finest level: bh = D^-1 r rounded to single
+// precision, x = w[0] bh (the cycle then continues from its second sweep).
+__global__ __launch_bounds__(NT) void k_cg_upd_mg(int32_t nf, int32_t it, int32_t nb,
+                                                  double* __restrict__ w, double* __restrict__ r,
+                                                  const double* __restrict__ p,
+                                                  const double* __restrict__ q,
+                                                  double* __restrict__ part, int* iflags,
+                                                  const float* __restrict__ dinv32,
+                                                  const float* __restrict__ wts,
+                                                  float* __restrict__ bh, float* __restrict__ x)
+{
+    if (iflags[0]) return;
+    __shared__ double sh[NT / 64];
+    const double rz = block_reduce_partials(part + ((it & 1) ? P_RZ1 : P_RZ0) * MAXB, nb, sh);
+    const double pq = block_reduce_partials(part + P_PQ * MAXB, nb, sh);
+    const double alpha = rz / pq;
+    const float w0 = wts[0];
+    double s_rr = 0.0;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
+        w[i] = fma(alpha, p[i], w[i]);
+        const double ri = fma(-alpha, q[i], r[i]);
+        r[i] = ri;
+        s_rr = fma(ri, ri, s_rr);
+        const float h = (float)ri * dinv32[i];
+        bh[i] = h;
+        x[i] = w0 * h;
+    }
+    const double t1 = phf_block_sum_f64<NT>(s_rr, sh);
+    if (threadIdx.x == 0) {
         part[P_RR * MAXB + blockIdx.x] = t1;
         if (blockIdx.x == 0) iflags[1] += 1;
     }
@@ -733,7 +772,7 @@ int phf_ns_cg_start(phf_ns* ns, double rtol)
     PHF_LAUNCH(ctx, "k_cg_init_final", k_cg_init_final, 1, NT, 0, ns->part, ns->nbv, rtol * rtol,
                ns->scal, ns->iflags);
     if (ns->mg && ns->mg_on)
-        TRY(phf_mg_apply(ns->mg, ns->r, ns->z, ns->part + P_RZ0 * MAXB, ns->iflags));
+        TRY(phf_mg_apply32(ns->mg, ns->r, false, ns->part + P_RZ0 * MAXB, ns->iflags));
     return PHF_OK;
 }
 
@@ -745,14 +784,19 @@ int phf_ns_cg_iterate(phf_ns* ns, int32_t iters)
         // only the parity and "first or not" of the index matter to the kernels
         const int32_t it = ns->next_it;
         ns->next_it = it + 1 >= 2 ? 2 + ((it + 1) & 1) : it + 1;
-        PHF_LAUNCH(ctx, "k_cg_dir", k_cg_dir, ns->nbv, NT, 0, ns->nf, it, ns->nbv, ns->ell_col,
-                   ns->ell_val, ns->z, ns->p, ns->q, ns->part, ns->scal, ns->iflags);
         if (ns->mg && ns->mg_on) {
-            PHF_LAUNCH(ctx, "k_cg_upd", k_cg_upd<false>, ns->nbv, NT, 0, ns->nf, it, ns->nbv, ns->w,
-                       ns->r, ns->z, ns->p, ns->q, ns->dinv, ns->part, ns->iflags);
-            TRY(phf_mg_apply(ns->mg, ns->r, ns->z,
-                             ns->part + ((it & 1) ? P_RZ0 : P_RZ1) * MAXB, ns->iflags));
+            PHF_LAUNCH(ctx, "k_cg_dir", k_cg_dir<float>, ns->nbv, NT, 0, ns->nf, it, ns->nbv,
+                       ns->ell_col, ns->ell_val, ns->mg->z32, ns->p, ns->q, ns->part, ns->scal,
+                       ns->iflags);
+            const phf_mg_top top = phf_mg_top_view(ns->mg);
+            PHF_LAUNCH(ctx, "k_cg_upd", k_cg_upd_mg, ns->nbv, NT, 0, ns->nf, it, ns->nbv, ns->w,
+                       ns->r, ns->p, ns->q, ns->part, ns->iflags, top.dinv, top.w, top.bh, top.x);
+            TRY(phf_mg_apply32(ns->mg, ns->r, true, ns->part + ((it & 1) ? P_RZ0 : P_RZ1) * MAXB,
+                               ns->iflags));
         } else {
+            PHF_LAUNCH(ctx, "k_cg_dir", k_cg_dir<double>, ns->nbv, NT, 0, ns->nf, it, ns->nbv,
+                       ns->ell_col, ns->ell_val, ns->z, ns->p, ns->q, ns->part, ns->scal,
+                       ns->iflags);
             PHF_LAUNCH(ctx, "k_cg_upd", k_cg_upd<true>, ns->nbv, NT, 0, ns->nf, it, ns->nbv, ns->w,
                        ns->r, ns->z, ns->p, ns->q, ns->dinv, ns->part, ns->iflags);
         }
