@@ -16,6 +16,15 @@ namespace {
 
 enum : int { FLAG_RANGE = 1, FLAG_ORIENT = 2, FLAG_MESH = 4, FLAG_BOUNDARY = 8 };
 
+// Numbers of Dirichlet (d) and Neumann (n) edges.
+struct phf_cnt2 {
+    int32_t d, n;
+};
+__host__ __device__ inline phf_cnt2 operator+(phf_cnt2 a, phf_cnt2 b)
+{
+    return phf_cnt2{a.d + b.d, a.n + b.n};
+}
+
 __device__ inline void raise_flag(int* flags, int bit, int32_t where)
 {
     atomicOr(&flags[0], bit);
@@ -201,53 +210,97 @@ __global__ __launch_bounds__(256) void k_boundary_mark(
     else neu_edges[q - nD] = e;
 }
 
-// Checks that every boundary edge was listed; writes the 0/1 indicator and
-// row-length arrays scanned into row numbers and C row pointers.
-__global__ __launch_bounds__(256) void k_boundary_check(
-    int32_t n_edges, const int2* __restrict__ edge_elems, const int32_t* __restrict__ mark,
-    const int8_t* __restrict__ etype, int32_t* __restrict__ nonN, int32_t* __restrict__ nonD,
-    int32_t* __restrict__ clen, int32_t* __restrict__ interior, int* flags)
+// Per-tile (256 edges) numbers of Dirichlet and Neumann edges; with `mark`
+// (a mesh given by the caller) also checks that every boundary edge was
+// listed.
+__global__ __launch_bounds__(256) void k_rows_count(int32_t n_edges, const int8_t* __restrict__ etype,
+                                                    const int2* __restrict__ edge_elems,
+                                                    const int32_t* __restrict__ mark,
+                                                    phf_cnt2* __restrict__ tiles, int* flags)
 {
-    int32_t e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= n_edges) return;
-    bool bnd = edge_elems[e].y < 0;
-    if (mark && bnd && mark[e] == 0) raise_flag(flags, FLAG_BOUNDARY, e);
-    int t = etype[e];
-    nonN[e] = t != 2;
-    nonD[e] = t != 1;
-    clen[e] = t == 0 ? 4 : (t == 1 ? 2 : 0);
-    interior[e] = !bnd;
+    __shared__ phf_cnt2 sh[4];
+    const int32_t e = blockIdx.x * 256 + threadIdx.x;
+    int t = 0;
+    if (e < n_edges) {
+        t = etype[e];
+        if (mark && edge_elems[e].y < 0 && mark[e] == 0) raise_flag(flags, FLAG_BOUNDARY, e);
+    }
+    const uint64_t bd = __ballot(t == 1), bn = __ballot(t == 2);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = phf_cnt2{(int32_t)__popcll(bd), (int32_t)__popcll(bn)};
+    __syncthreads();
+    if (threadIdx.x == 0) tiles[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-// Multiplier-row tables and the C pattern (row = edge_row[e]).
+// Exclusive prefix sums, in place, of n per-tile values by one workgroup of
+// 1024 threads (each a contiguous run of tiles); *total (nullable) = the sum.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_tile_exscan(int32_t n, T* __restrict__ v,
+                                                      T* __restrict__ total)
+{
+    __shared__ T sh[1024];
+    const int32_t tid = threadIdx.x;
+    const int32_t per = (n + 1023) / 1024;
+    const int32_t b0 = min(n, tid * per), b1 = min(n, b0 + per);
+    T s{};
+    for (int32_t i = b0; i < b1; ++i) s = s + v[i];
+    sh[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan of the runs
+        const T a = tid >= off ? sh[tid - off] : T{};
+        __syncthreads();
+        sh[tid] = sh[tid] + a;
+        __syncthreads();
+    }
+    T run = tid > 0 ? sh[tid - 1] : T{};
+    for (int32_t i = b0; i < b1; ++i) {
+        const T x = v[i];
+        v[i] = run;
+        run = run + x;
+    }
+    if (tid == 1023 && total) *total = sh[1023];
+}
+
+// Multiplier-row tables and the C pattern. With D(e), N(e) the Dirichlet and
+// Neumann edges before e (tile base plus ballot prefix): multiplier row
+// e - N(e), free row e - D(e), C row pointer 4 (e - D(e) - N(e)) + 2 D(e).
 __global__ __launch_bounds__(256) void k_rows(
-    int32_t n_edges, const int8_t* __restrict__ etype, const int32_t* __restrict__ rowscan,
-    const int32_t* __restrict__ redscan, const int32_t* __restrict__ cptr,
+    int32_t n_edges, const int8_t* __restrict__ etype, const phf_cnt2* __restrict__ tiles,
     const int2* __restrict__ edge_nodes, const int2* __restrict__ edge_elems,
     const int8_t* __restrict__ led, const int8_t* __restrict__ ledTN,
     int32_t* __restrict__ edge_row, int32_t* __restrict__ red_row,
     int32_t* __restrict__ red_edge, int32_t* __restrict__ row_edge,
     int2* __restrict__ row_nodes, int32_t* __restrict__ C_rowptr, int32_t* __restrict__ C_col)
 {
-    int32_t e = blockIdx.x * 256 + threadIdx.x;
+    __shared__ phf_cnt2 sh[4];
+    const int32_t e = blockIdx.x * 256 + threadIdx.x;
+    const int t = e < n_edges ? etype[e] : 0;
+    const uint64_t bd = __ballot(t == 1), bn = __ballot(t == 2);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = phf_cnt2{(int32_t)__popcll(bd), (int32_t)__popcll(bn)};
+    __syncthreads();
+    phf_cnt2 before = tiles[blockIdx.x];
+    for (int w = 0; w < wid; ++w) before = before + sh[w];
+    const uint64_t below = lane == 0 ? 0ull : (1ull << lane) - 1ull;
+    const int32_t nd = before.d + (int32_t)__popcll(bd & below),
+                  nn = before.n + (int32_t)__popcll(bn & below);
     if (e >= n_edges) return;
-    int t = etype[e];
     if (t == 1) {
         red_row[e] = -1;
     } else {
-        red_row[e] = redscan[e];
-        red_edge[redscan[e]] = e;
+        const int32_t rr = e - nd;
+        red_row[e] = rr;
+        red_edge[rr] = e;
     }
     if (t == 2) {
         edge_row[e] = -1;
         return;
     }
-    int32_t r = rowscan[e];
+    const int32_t r = e - nn;
     edge_row[e] = r;
     row_edge[r] = e;
     const int2 kl = edge_nodes[e];
     row_nodes[r] = make_int2(t == 1 ? ~kl.x : kl.x, kl.y);
-    int32_t c = cptr[e];
+    const int32_t c = 4 * (e - nd - nn) + 2 * nd;
     C_rowptr[r] = c;
     int2 tt = edge_elems[e];
     // vertex DOFs of the edge in T+ (the two local vertices != led), ascending
@@ -263,8 +316,8 @@ __global__ __launch_bounds__(256) void k_rows(
     }
 }
 
-// Element code words, the element-major coordinate copy and the saddle row
-// lengths of the element's DOF rows.
+// Element code words, the element-major coordinate copy, and per tile (256
+// elements) the number of Neumann edge incidences.
 __global__ __launch_bounds__(256) void k_elem_codes(int32_t nE, int4* __restrict__ elem4,
                                                     const int32_t* __restrict__ elem_edges,
                                                     const int8_t* __restrict__ etype,
@@ -272,75 +325,104 @@ __global__ __launch_bounds__(256) void k_elem_codes(int32_t nE, int4* __restrict
                                                     const double2* __restrict__ xy,
                                                     double2* __restrict__ exy,
                                                     int32_t* __restrict__ ecode,
-                                                    int32_t* __restrict__ slen)
+                                                    int32_t* __restrict__ tiles)
 {
-    int32_t m = blockIdx.x * 256 + threadIdx.x;
-    if (m >= nE) return;
-    int32_t ed[3];
-    int tp[3];
-    int code = 0;
+    __shared__ int32_t sh[256 / 64];
+    const int32_t m = blockIdx.x * 256 + threadIdx.x;
+    int32_t nneu = 0;
+    if (m < nE) {
+        int32_t ed[3];
+        int code = 0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        ed[i] = elem_edges[3 * (int64_t)m + i];
-        tp[i] = etype[ed[i]];
-        code |= tp[i] << (2 * i);
-        if (edge_elems[ed[i]].x == m) code |= 1 << (6 + i);
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        int l1 = i == 0 ? 1 : 0, l2 = i == 2 ? 1 : 2;
-        if (ed[l1] > ed[l2]) code |= 1 << (9 + i);
-        slen[3 * (int64_t)m + i] = 3 + (tp[l1] != 2) + (tp[l2] != 2);
-    }
-    int4 e = elem4[m];
-    e.w = code;
-    elem4[m] = e;
-    ecode[m] = code;
-    exy[3 * (int64_t)m] = xy[e.x];
-    exy[3 * (int64_t)m + 1] = xy[e.y];
-    exy[3 * (int64_t)m + 2] = xy[e.z];
-}
-
-__global__ __launch_bounds__(256) void k_saddle_rowlen(int32_t L, const int32_t* __restrict__ C_rowptr,
-                                                       int32_t nnzC, int32_t* __restrict__ slen)
-{
-    int32_t r = blockIdx.x * 256 + threadIdx.x;
-    if (r >= L) return;
-    int32_t c1 = r + 1 < L ? C_rowptr[r + 1] : nnzC;
-    slen[r] = c1 - C_rowptr[r];
-}
-
-// Saddle pattern columns: DOF rows 3m+i then multiplier rows N + r.
-__global__ __launch_bounds__(256) void k_saddle_cols(
-    int32_t nE, int32_t L, const int4* __restrict__ elem4, const int32_t* __restrict__ elem_edges,
-    const int32_t* __restrict__ edge_row, const int32_t* __restrict__ C_rowptr,
-    const int32_t* __restrict__ C_col, const int32_t* __restrict__ S_rowptr,
-    int32_t* __restrict__ S_col)
-{
-    int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int32_t N = 3 * nE;
-    if (g < N) {
-        int32_t m = (int32_t)(g / 3), i = (int32_t)(g % 3);
-        int code = elem4[m].w;
-        int32_t s = S_rowptr[g];
-        S_col[s] = 3 * m;
-        S_col[s + 1] = 3 * m + 1;
-        S_col[s + 2] = 3 * m + 2;
-        int l1 = i == 0 ? 1 : 0, l2 = i == 2 ? 1 : 2;
-        if (PHF_CODE_SWAP(code, i)) {
-            int t = l1;
-            l1 = l2;
-            l2 = t;
+        for (int i = 0; i < 3; ++i) {
+            ed[i] = elem_edges[3 * (int64_t)m + i];
+            const int tp = etype[ed[i]];
+            nneu += tp == 2;
+            code |= tp << (2 * i);
+            if (edge_elems[ed[i]].x == m) code |= 1 << (6 + i);
         }
-        int32_t k = s + 3;
-        if (PHF_CODE_TYPE(code, l1) != 2) S_col[k++] = N + edge_row[elem_edges[3 * (int64_t)m + l1]];
-        if (PHF_CODE_TYPE(code, l2) != 2) S_col[k++] = N + edge_row[elem_edges[3 * (int64_t)m + l2]];
-    } else if (g < (int64_t)N + L) {
-        int32_t r = (int32_t)(g - N);
-        int32_t s = S_rowptr[g];
-        int32_t c0 = C_rowptr[r], c1 = C_rowptr[r + 1];
-        for (int32_t q = c0; q < c1; ++q) S_col[s + (q - c0)] = C_col[q];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            int l1 = i == 0 ? 1 : 0, l2 = i == 2 ? 1 : 2;
+            if (ed[l1] > ed[l2]) code |= 1 << (9 + i);
+        }
+        int4 e = elem4[m];
+        e.w = code;
+        elem4[m] = e;
+        ecode[m] = code;
+        exy[3 * (int64_t)m] = xy[e.x];
+        exy[3 * (int64_t)m + 1] = xy[e.y];
+        exy[3 * (int64_t)m + 2] = xy[e.z];
     }
+    const int32_t tot = phf_block_sum_i32<256>(nneu, sh);
+    if (threadIdx.x == 0) tiles[blockIdx.x] = tot;
+}
+
+// Saddle pattern, DOF rows of element m: 3 + (non-Neumann edges of m at
+// vertex i) entries in row 3m+i, the rows of m starting at 15 m - 2 (Neumann
+// incidences before m) (tile base plus block prefix). Columns: the element's
+// three DOFs, then the multiplier rows of its non-Neumann edges at vertex i
+// in ascending edge order. The block's rows and columns are contiguous in
+// S_rowptr and S_col: they are assembled in LDS and stored coalesced.
+__global__ __launch_bounds__(256) void k_saddle_dof(int32_t nE, const int32_t* __restrict__ ecode,
+                                                    const int32_t* __restrict__ tiles,
+                                                    const int32_t* __restrict__ elem_edges,
+                                                    const int32_t* __restrict__ edge_row,
+                                                    int32_t* __restrict__ S_rowptr,
+                                                    int32_t* __restrict__ S_col)
+{
+    __shared__ int32_t sh[256 / 64 + 1];
+    __shared__ int32_t scol[256 * 15];
+    __shared__ int32_t srow[256 * 3];
+    const int32_t m0 = blockIdx.x * 256, m = m0 + threadIdx.x;
+    const int32_t cnt = min(256, nE - m0);
+    const int code = m < nE ? ecode[m] : 0;
+    int nneu = 0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) nneu += PHF_CODE_TYPE(code, l) == 2;
+    int32_t tot;
+    const int32_t ex = phf_block_exscan_i32<256>(nneu, sh, &tot);
+    const int32_t base = 15 * m0 - 2 * tiles[blockIdx.x];  // first entry of the block
+    if (m < nE) {
+        const int32_t N = 3 * nE;
+        int32_t s = 15 * (int32_t)threadIdx.x - 2 * ex;  // offset in the block
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            srow[3 * threadIdx.x + i] = base + s;
+            scol[s] = 3 * m;
+            scol[s + 1] = 3 * m + 1;
+            scol[s + 2] = 3 * m + 2;
+            int l1 = i == 0 ? 1 : 0, l2 = i == 2 ? 1 : 2;
+            if (PHF_CODE_SWAP(code, i)) {
+                int t = l1;
+                l1 = l2;
+                l2 = t;
+            }
+            int32_t k = s + 3;
+            if (PHF_CODE_TYPE(code, l1) != 2) scol[k++] = N + edge_row[elem_edges[3 * (int64_t)m + l1]];
+            if (PHF_CODE_TYPE(code, l2) != 2) scol[k++] = N + edge_row[elem_edges[3 * (int64_t)m + l2]];
+            s = k;
+        }
+    }
+    __syncthreads();
+    const int32_t len = 15 * cnt - 2 * tot;
+    for (int32_t q = threadIdx.x; q < len; q += 256) S_col[(int64_t)base + q] = scol[q];
+    for (int32_t q = threadIdx.x; q < 3 * cnt; q += 256) S_rowptr[3 * (int64_t)m0 + q] = srow[q];
+}
+
+// Saddle pattern, multiplier rows (after the nnz_dof entries of the DOF
+// rows): row r is C's row r, so the pointers are shifted C row pointers and
+// the columns a copy of C's.
+__global__ __launch_bounds__(256) void k_saddle_mult(int32_t L, int32_t nnzC, int32_t nnz_dof,
+                                                     const int32_t* __restrict__ C_rowptr,
+                                                     const int32_t* __restrict__ C_col,
+                                                     int32_t* __restrict__ S_rowptr_m,
+                                                     int32_t* __restrict__ S_col_m)
+{
+    const int32_t g = blockIdx.x * 256 + threadIdx.x;
+    if (g < L) S_rowptr_m[g] = nnz_dof + C_rowptr[g];
+    else if (g == L) S_rowptr_m[g] = nnz_dof + nnzC;
+    if (g < nnzC) S_col_m[g] = C_col[g];
 }
 
 // Off-diagonal entries of the reduced (edge-midpoint) operator: each
@@ -626,17 +708,15 @@ struct build_tmp {
     int32_t* ucount = nullptr;
     int32_t* eoff = nullptr;
     int32_t* mark = nullptr;
-    int32_t* nonN = nullptr;
-    int32_t* nonD = nullptr;
-    int32_t* clen = nullptr;
-    int32_t* inter = nullptr;
-    int32_t* slen = nullptr;
+    phf_cnt2* tiles = nullptr;
+    phf_cnt2* tile_total = nullptr;
+    int32_t* etiles = nullptr;
     int32_t* totals = nullptr;
     ~build_tmp()
     {
         phf_dfree(raw); phf_dfree(bcount); phf_dfree(boff); phf_dfree(keys);
-        phf_dfree(ucount); phf_dfree(eoff);         phf_dfree(mark); phf_dfree(nonN); phf_dfree(nonD); phf_dfree(clen);
-        phf_dfree(inter); phf_dfree(slen); phf_dfree(totals);
+        phf_dfree(ucount); phf_dfree(eoff); phf_dfree(mark); phf_dfree(tiles);
+        phf_dfree(tile_total); phf_dfree(etiles); phf_dfree(totals);
     }
 };
 
@@ -831,38 +911,34 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
                        (const int32_t*)M->dir_pairs, nD, (const int32_t*)M->neu_pairs, nN, nC, T.eoff, M->edge_nodes, M->edge_elems, T.mark, M->edge_type,
                        M->dir_edges, M->neu_edges, ctx->d_flags);
     }
-    TRY(phf_dmalloc(ctx, &T.nonN, (size_t)ne + 1, "row indicator"));
-    TRY(phf_dmalloc(ctx, &T.nonD, (size_t)ne + 1, "reduced indicator"));
-    TRY(phf_dmalloc(ctx, &T.clen, (size_t)ne + 1, "C row lengths"));
-    TRY(phf_dmalloc(ctx, &T.inter, (size_t)ne + 1, "interior indicator"));
-    PHF_LAUNCH(ctx, "k_boundary_check", k_boundary_check, nblk(ne), 256, 0, ne, M->edge_elems,
-               T.mark, M->edge_type, T.nonN, T.nonD, T.clen, T.inter, ctx->d_flags);
+    // a3: multiplier rows, free rows and C row pointers from the numbers of
+    // Dirichlet and Neumann edges before each edge (per-tile counts, their
+    // exclusive scan, then per-edge ballots inside the tile)
+    const int32_t nt = (ne + 255) / 256;
+    TRY(phf_dmalloc(ctx, &T.tiles, (size_t)nt, "row tile counts"));
+    TRY(phf_dmalloc(ctx, &T.tile_total, 1, "row totals"));
+    PHF_LAUNCH(ctx, "k_rows_count", k_rows_count, nt, 256, 0, ne, M->edge_type, M->edge_elems,
+               parent ? nullptr : T.mark, T.tiles, ctx->d_flags);
     if (!parent) {
         TRY(read_flags(ctx, &bits, &where));
         TRY(flags_to_status(ctx, bits, where, "boundary"));
     }
     phf_dfree(T.eoff);
     phf_dfree(T.mark);
-    TRY(phf_scan_i32(ctx, T.nonN, T.nonN, ne, T.totals));
-    TRY(phf_scan_i32(ctx, T.nonD, T.nonD, ne, T.totals + 1));
-    TRY(phf_scan_i32(ctx, T.clen, T.clen, ne, T.totals + 2));
-    TRY(phf_scan_i32(ctx, T.inter, T.inter, ne, T.totals + 3));
-    int32_t h[4];
-    if (parent) {
-        // every boundary edge is listed exactly once (the parent was checked)
-        h[0] = ne - nN;                              // multiplier rows
-        h[1] = ne - nD;                              // free edges
-        h[3] = ne - nD - nN;                         // interior edges
-        h[2] = 4 * h[3] + 2 * nD;                    // C entries
-    } else {
-        PHF_HIP(ctx, hipMemcpyAsync(h, T.totals, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
+    PHF_LAUNCH(ctx, "k_tile_exscan", k_tile_exscan<phf_cnt2>, 1, 1024, 0, nt, T.tiles,
+               T.tile_total);
+    phf_cnt2 cnt{nD, nN};
+    if (!parent) {
+        // (every boundary edge of a refined mesh is listed exactly once: the
+        // parent was checked)
+        PHF_HIP(ctx, hipMemcpyAsync(&cnt, T.tile_total, sizeof(cnt), hipMemcpyDeviceToHost,
                                     ctx->stream));
         PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
     }
-    M->L = h[0];
-    M->n_free = h[1];
-    M->nnz_C = h[2];
-    M->n_int = h[3];
+    M->L = ne - cnt.n;                          // multiplier rows
+    M->n_free = ne - cnt.d;                     // free edges
+    M->n_int = ne - cnt.d - cnt.n;              // interior edges
+    M->nnz_C = 4 * M->n_int + 2 * cnt.d;        // C entries
     const int32_t L = M->L, N = 3 * nE;
     if ((int64_t)9 * nE + 2 * M->nnz_C > 0x7fffffffLL)
         return phf_set_error(ctx, PHF_EINVAL, "saddle matrix too large for int32 indices");
@@ -875,31 +951,31 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     TRY(phf_dmalloc(ctx, &M->row_nodes, L, "row nodes"));
     TRY(phf_dmalloc(ctx, &M->C_rowptr, (size_t)L + 1, "C rowptr"));
     TRY(phf_dmalloc(ctx, &M->C_col, M->nnz_C, "C columns"));
-    PHF_LAUNCH(ctx, "k_rows", k_rows, nblk(ne), 256, 0, ne, M->edge_type, T.nonN, T.nonD, T.clen,
-               M->edge_nodes, M->edge_elems, M->led, M->ledTN, M->edge_row, M->red_row,
-               M->red_edge, M->row_edge, M->row_nodes, M->C_rowptr, M->C_col);
+    PHF_LAUNCH(ctx, "k_rows", k_rows, nt, 256, 0, ne, M->edge_type, T.tiles, M->edge_nodes,
+               M->edge_elems, M->led, M->ledTN, M->edge_row, M->red_row, M->red_edge,
+               M->row_edge, M->row_nodes, M->C_rowptr, M->C_col);
     PHF_LAUNCH(ctx, "k_set", k_set_i32, 1, 1, 0, M->C_rowptr + L, (int32_t)M->nnz_C);
-    phf_dfree(T.nonN);
-    phf_dfree(T.nonD);
-    phf_dfree(T.clen);
-    phf_dfree(T.inter);
+    phf_dfree(T.tiles);
 
-    // element codes and the saddle pattern
-    TRY(phf_dmalloc(ctx, &T.slen, (size_t)N + L + 1, "saddle row lengths"));
+    // element codes and the saddle pattern: the DOF rows of element m start
+    // at 15 m - 2 (Neumann edge incidences of the elements before m)
+    const int32_t ntE = (nE + 255) / 256;
+    TRY(phf_dmalloc(ctx, &T.etiles, (size_t)ntE, "element tile counts"));
     TRY(phf_dmalloc(ctx, &M->exy, 3 * (size_t)nE, "element coordinates"));
     TRY(phf_dmalloc(ctx, &M->ecode, nE, "element codes"));
-    PHF_LAUNCH(ctx, "k_elem_codes", k_elem_codes, nblk(nE), 256, 0, nE, M->elem4, M->elem_edges,
-               M->edge_type, M->edge_elems, M->xy, M->exy, M->ecode, T.slen);
-    if (L > 0)
-        PHF_LAUNCH(ctx, "k_saddle_rowlen", k_saddle_rowlen, nblk(L), 256, 0, L, M->C_rowptr,
-                   (int32_t)M->nnz_C, T.slen + N);
+    PHF_LAUNCH(ctx, "k_elem_codes", k_elem_codes, ntE, 256, 0, nE, M->elem4, M->elem_edges,
+               M->edge_type, M->edge_elems, M->xy, M->exy, M->ecode, T.etiles);
+    PHF_LAUNCH(ctx, "k_tile_exscan", k_tile_exscan<int32_t>, 1, 1024, 0, ntE, T.etiles,
+               (int32_t*)nullptr);
     TRY(phf_dmalloc(ctx, &M->S_rowptr, (size_t)N + L + 1, "saddle rowptr"));
-    PHF_HIP(ctx, hipMemsetAsync(T.slen + N + L, 0, sizeof(int32_t), ctx->stream));
-    TRY(phf_scan_i32(ctx, T.slen, M->S_rowptr, N + L + 1, T.totals + 4));
     TRY(phf_dmalloc(ctx, &M->S_col, M->nnz_S, "saddle columns"));
-    PHF_LAUNCH(ctx, "k_saddle_cols", k_saddle_cols, nblk((int64_t)N + L), 256, 0, nE, L, M->elem4,
-               M->elem_edges, M->edge_row, M->C_rowptr, M->C_col, M->S_rowptr, M->S_col);
-    phf_dfree(T.slen);
+    PHF_LAUNCH(ctx, "k_saddle_dof", k_saddle_dof, ntE, 256, 0, nE, M->ecode, T.etiles,
+               M->elem_edges, M->edge_row, M->S_rowptr, M->S_col);
+    const int32_t nnz_dof = 9 * nE + M->nnz_C;
+    PHF_LAUNCH(ctx, "k_saddle_mult", k_saddle_mult, nblk(std::max<int64_t>((int64_t)L + 1, M->nnz_C)),
+               256, 0, L, (int32_t)M->nnz_C, nnz_dof, M->C_rowptr, M->C_col, M->S_rowptr + N,
+               M->S_col + nnz_dof);
+    phf_dfree(T.etiles);
 
     // tile bases of the C row pointers and the Neumann element mask
     TRY(phf_dmalloc(ctx, &M->C_tile, (size_t)(L + 255) / 256 + 1, "C tile bases"));
