@@ -31,7 +31,6 @@ struct phf_ns {
     int32_t* elem_red = nullptr;  // 3 nE: reduced row of local edge l (-1 Dirichlet)
     int32_t* elem_row = nullptr;  // 3 nE: multiplier row of local edge l (-1 Neumann)
     int32_t* ell_col = nullptr;   // 5 nf, column-major ELL of R
-    int32_t* ell_src = nullptr;   // 2 x 5 nf block sources
     double* row_h = nullptr;      // L: |E|/2 of each multiplier row
     // numeric
     double* B = nullptr;          // 9 nE: P^T A_T P

@@ -33,36 +33,6 @@ __global__ __launch_bounds__(NT) void k_ns_symbolic(int32_t nE, const int32_t* _
     elem_row[g] = edge_row[e];
 }
 
-// ELL-5 rows of the reduced operator straight from the edge tables (column
-// major; unused slots point at the diagonal with no source).
-__global__ __launch_bounds__(NT) void k_ns_ell(int32_t nf, const int32_t* __restrict__ red_edge,
-                                               const int2* __restrict__ edge_elems,
-                                               const int8_t* __restrict__ led,
-                                               const int8_t* __restrict__ ledTN,
-                                               const int32_t* __restrict__ elem_edges,
-                                               const int32_t* __restrict__ red_row,
-                                               int32_t* __restrict__ ell_col,
-                                               int32_t* __restrict__ ell_src)
-{
-    int32_t r = blockIdx.x * NT + threadIdx.x;
-    if (r >= nf) return;
-    int32_t col[5], s0[5], s1[5];
-    const int n = phf_reduced_entries(red_edge[r], edge_elems, led, ledTN, elem_edges, red_row,
-                                      col, s0, s1);
-    for (int k = 0; k < 5; ++k) {
-        int64_t slot = (int64_t)k * nf + r;
-        if (k < n) {
-            ell_col[slot] = col[k];
-            ell_src[2 * slot] = s0[k];
-            ell_src[2 * slot + 1] = s1[k];
-        } else {
-            ell_col[slot] = r;
-            ell_src[2 * slot] = -1;
-            ell_src[2 * slot + 1] = -1;
-        }
-    }
-}
-
 // A_T = cK K_T + cD D_T + cM M_T (D nullable) and B_T = P^T A_T P; A_T need
 // not be symmetric. A tile of NT elements is staged in LDS so that the
 // 9-value element rows are read and written with coalesced accesses.
@@ -108,21 +78,39 @@ __global__ __launch_bounds__(NT) void k_ns_blocks(int32_t nE, const double* __re
     }
 }
 
-__global__ __launch_bounds__(NT) void k_ns_ellval(int32_t nf, const int32_t* __restrict__ ell_col,
-                                                  const int32_t* __restrict__ ell_src,
+// ELL-5 rows of the reduced operator straight from the edge tables and the
+// element blocks B (column major; unused slots point at the diagonal with
+// value 0): columns, values B[s0] + B[s1] of each entry's sources, and the
+// inverse diagonal (1 where it is not positive).
+__global__ __launch_bounds__(NT) void k_ns_ellval(int32_t nf, const int32_t* __restrict__ red_edge,
+                                                  const int2* __restrict__ edge_elems,
+                                                  const int8_t* __restrict__ led,
+                                                  const int8_t* __restrict__ ledTN,
+                                                  const int32_t* __restrict__ elem_edges,
+                                                  const int32_t* __restrict__ red_row,
                                                   const double* __restrict__ B,
+                                                  int32_t* __restrict__ ell_col,
                                                   double* __restrict__ ell_val,
                                                   double* __restrict__ dinv)
 {
-    int32_t r = blockIdx.x * NT + threadIdx.x;
+    const int32_t r = blockIdx.x * NT + threadIdx.x;
     if (r >= nf) return;
+    int32_t col[5], s0[5], s1[5];
+    const int n = phf_reduced_entries(red_edge[r], edge_elems, led, ledTN, elem_edges, red_row,
+                                      col, s0, s1);
     double d = 0.0;
+#pragma unroll
     for (int k = 0; k < 5; ++k) {
-        int64_t slot = (int64_t)k * nf + r;
-        int32_t s0 = ell_src[2 * slot], s1 = ell_src[2 * slot + 1];
-        double v = (s0 >= 0 ? B[s0] : 0.0) + (s1 >= 0 ? B[s1] : 0.0);
-        ell_val[slot] = v;
-        if (ell_col[slot] == r && s0 >= 0) d = v;
+        const int64_t slot = (int64_t)k * nf + r;
+        if (k < n) {
+            const double v = B[s0[k]] + (s1[k] >= 0 ? B[s1[k]] : 0.0);
+            ell_col[slot] = col[k];
+            ell_val[slot] = v;
+            if (col[k] == r) d = v;
+        } else {
+            ell_col[slot] = r;
+            ell_val[slot] = 0.0;
+        }
     }
     dinv[r] = d > 0.0 ? 1.0 / d : 1.0;
 }
@@ -136,9 +124,22 @@ __global__ __launch_bounds__(NT) void k_ns_rowh(int32_t L, const int32_t* __rest
     row_h[r] = C[C_rowptr[r]];
 }
 
+// Element records of a tile of NT elements (W values each, element-major)
+// copied between global memory and LDS with coalesced accesses.
+template <int W, typename T>
+__device__ inline void tile_load(const T* __restrict__ g, int64_t m0, int32_t nt, T* s)
+{
+    for (int32_t q = threadIdx.x; q < W * nt; q += NT) s[q] = g[W * m0 + q];
+}
+template <int W, typename T>
+__device__ inline void tile_store(T* __restrict__ g, int64_t m0, int32_t nt, const T* s)
+{
+    for (int32_t q = threadIdx.x; q < W * nt; q += NT) g[W * m0 + q] = s[q];
+}
+
 // Known midpoint values (Dirichlet) and T+-side jumps (interior rows with a
 // non-zero right-hand side), and the element part of the reduced rhs,
-// c_T = P^T (rhs1_T - A_T P kv_T).
+// c_T = P^T (rhs1_T - A_T P kv_T). Element records go through LDS.
 __global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int32_t* __restrict__ ecode,
                                                  const int32_t* __restrict__ elem_row,
                                                  const double* __restrict__ row_h,
@@ -147,33 +148,45 @@ __global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int32_t* __re
                                                  const double* __restrict__ Ablk,
                                                  double* __restrict__ kv, double* __restrict__ cs)
 {
-    int32_t m = blockIdx.x * NT + threadIdx.x;
-    if (m >= nE) return;
-    const int code = ecode[m];
-    double k3[3];
+    __shared__ double sA[9 * NT], sR[3 * NT], sK[3 * NT], sC[3 * NT];
+    __shared__ int32_t sRow[3 * NT];
+    const int tid = threadIdx.x;
+    const int64_t m0 = (int64_t)blockIdx.x * NT;
+    const int32_t nt = (int32_t)min((int64_t)NT, (int64_t)nE - m0);
+    tile_load<9>(Ablk, m0, nt, sA);
+    tile_load<3>(rhs1, m0, nt, sR);
+    tile_load<3>(elem_row, m0, nt, sRow);
+    __syncthreads();
+    if (tid < nt) {
+        const int code = ecode[m0 + tid];
+        double k3[3];
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        const int t = PHF_CODE_TYPE(code, l);
-        double v = 0.0;
-        if (t == 1 || (t == 0 && PHF_CODE_TPLUS(code, l))) {
-            const int32_t r = elem_row[3 * (int64_t)m + l];
-            v = -rhs2[r] / (2.0 * row_h[r]);
+        for (int l = 0; l < 3; ++l) {
+            const int t = PHF_CODE_TYPE(code, l);
+            double v = 0.0;
+            if (t == 1 || (t == 0 && PHF_CODE_TPLUS(code, l))) {
+                const int32_t r = sRow[3 * tid + l];
+                v = -rhs2[r] / (2.0 * row_h[r]);
+            }
+            k3[l] = v;
+            sK[3 * tid + l] = v;
         }
-        k3[l] = v;
-        kv[3 * (int64_t)m + l] = v;
-    }
-    double Ub[3];
-    apply_P(k3, Ub);
-    double res[3];
+        double Ub[3];
+        apply_P(k3, Ub);
+        double res[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const double* a = Ablk + 9 * (int64_t)m + 3 * i;
-        res[i] = rhs1[3 * (int64_t)m + i] - (a[0] * Ub[0] + a[1] * Ub[1] + a[2] * Ub[2]);
-    }
-    double c[3];
-    apply_P(res, c);  // P is symmetric, so P^T v = P v
+        for (int i = 0; i < 3; ++i) {
+            const double* a = sA + 9 * tid + 3 * i;
+            res[i] = sR[3 * tid + i] - (a[0] * Ub[0] + a[1] * Ub[1] + a[2] * Ub[2]);
+        }
+        double c[3];
+        apply_P(res, c);  // P is symmetric, so P^T v = P v
 #pragma unroll
-    for (int l = 0; l < 3; ++l) cs[3 * (int64_t)m + l] = c[l];
+        for (int l = 0; l < 3; ++l) sC[3 * tid + l] = c[l];
+    }
+    __syncthreads();
+    tile_store<3>(kv, m0, nt, sK);
+    tile_store<3>(cs, m0, nt, sC);
 }
 
 __global__ __launch_bounds__(NT) void k_ns_gather(int32_t nf, const int32_t* __restrict__ red_edge,
@@ -415,6 +428,8 @@ __global__ __launch_bounds__(NT) void k_cg_check(int32_t nb, const double* __res
 
 // ---- recovery -------------------------------------------------------------
 
+// U_T = P (w_T + kv_T) and the element residual P^T (A_T U_T - rhs1_T) from
+// which the multipliers follow.
 __global__ __launch_bounds__(NT) void k_ns_recover_u(int32_t nE, const int32_t* __restrict__ elem_red,
                                                      const double* __restrict__ w,
                                                      const double* __restrict__ kv,
@@ -654,7 +669,7 @@ void phf_ns_destroy(phf_ns* ns)
     if (!ns) return;
     if (ns->mg) phf_mg_destroy(ns->mg);
     phf_dfree(ns->elem_red); phf_dfree(ns->elem_row); phf_dfree(ns->ell_col);
-    phf_dfree(ns->ell_src); phf_dfree(ns->row_h); phf_dfree(ns->B); phf_dfree(ns->Ablk);
+    phf_dfree(ns->row_h); phf_dfree(ns->B); phf_dfree(ns->Ablk);
     phf_dfree(ns->ell_val); phf_dfree(ns->dinv); phf_dfree(ns->kv); phf_dfree(ns->cs);
     phf_dfree(ns->b); phf_dfree(ns->w); phf_dfree(ns->r); phf_dfree(ns->z);
     phf_dfree(ns->p); phf_dfree(ns->q); phf_dfree(ns->part); phf_dfree(ns->scal);
@@ -678,7 +693,6 @@ int phf_ns_create(phf_mesh* mesh, phf_ns** out)
     rc = rc ? rc : phf_dmalloc(ctx, &ns->elem_red, e3, "solver element rows");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->elem_row, e3, "solver element rows");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_col, 5 * nf, "solver ELL columns");
-    rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_src, 10 * nf, "solver ELL sources");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->row_h, (size_t)ns->L, "solver row h");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->B, e9, "solver blocks");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->Ablk, e9, "solver blocks");
@@ -702,10 +716,6 @@ int phf_ns_create(phf_mesh* mesh, phf_ns** out)
     auto launch = [&]() -> int {
         PHF_LAUNCH(ctx, "k_ns_symbolic", k_ns_symbolic, nblk(3 * (int64_t)ns->nE), NT, 0, ns->nE,
                    mesh->elem_edges, mesh->red_row, mesh->edge_row, ns->elem_red, ns->elem_row);
-        if (ns->nf > 0)
-            PHF_LAUNCH(ctx, "k_ns_ell", k_ns_ell, nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge,
-                       mesh->edge_elems, mesh->led, mesh->ledTN, mesh->elem_edges, mesh->red_row,
-                       ns->ell_col, ns->ell_src);
         PHF_HIP(ctx, hipMemsetAsync(ns->w, 0, sizeof(double) * std::max<size_t>(nf, 1), ctx->stream));
         PHF_HIP(ctx, hipMemsetAsync(ns->iflags, 0, 4 * sizeof(int), ctx->stream));
         return PHF_OK;
@@ -727,8 +737,9 @@ int phf_ns_operator(phf_ns* ns, const double* K, const double* M, const double* 
     PHF_LAUNCH(ctx, "k_ns_blocks", k_ns_blocks, nblk(ns->nE), NT, 0, ns->nE, K, M, D, cK, cM, cD,
                ns->Ablk, ns->B);
     if (ns->nf > 0)
-        PHF_LAUNCH(ctx, "k_ns_ellval", k_ns_ellval, nblk(ns->nf), NT, 0, ns->nf, ns->ell_col,
-                   ns->ell_src, ns->B, ns->ell_val, ns->dinv);
+        PHF_LAUNCH(ctx, "k_ns_ellval", k_ns_ellval, nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge,
+                   mesh->edge_elems, mesh->led, mesh->ledTN, mesh->elem_edges, mesh->red_row,
+                   ns->B, ns->ell_col, ns->ell_val, ns->dinv);
     if (ns->L > 0)
         PHF_LAUNCH(ctx, "k_ns_rowh", k_ns_rowh, nblk(ns->L), NT, 0, ns->L, mesh->C_rowptr, C,
                    ns->row_h);
