@@ -331,7 +331,7 @@ typedef struct {
     int32_t saddle_residual; /* 1: compute the saddle residual into stats   */
     int32_t precond;     /* PHF_PRECOND_*                                  */
     int32_t mg_sweeps;   /* sweeps before and after the coarse correction,
-                            1..8; 0 = 3 (Chebyshev) or 2 (Jacobi)           */
+                            1..8; 0 = 4 (Chebyshev) or 2 (Jacobi)           */
     double mg_omega;     /* Jacobi damping; 0 = 0.8                         */
     int32_t mg_smoother; /* PHF_MG_SMOOTH_*                                 */
     int32_t reserved_;   /* 0                                               */

@@ -964,7 +964,7 @@ int phf_ns_set_precond(phf_ns* ns, int32_t precond, const phf_mg_params& mp,
     if (!ns->mg) TRY(phf_mg_create(ns, &ns->mg));
     const bool jacobi = mp.smoother == PHF_MG_SMOOTH_JACOBI;
     ns->mg->smoother = jacobi ? PHF_MG_SMOOTH_JACOBI : PHF_MG_SMOOTH_CHEBYSHEV;
-    ns->mg->nu = mp.sweeps > 0 ? mp.sweeps : jacobi ? 2 : 3;
+    ns->mg->nu = mp.sweeps > 0 ? mp.sweeps : jacobi ? 2 : 4;
     ns->mg->omega = mp.omega > 0 ? mp.omega : 0.8;
     ns->mg->range = mp.range > 0 ? mp.range : 10.0;
     TRY(phf_mg_numeric(ns->mg, co, cK, cM));
