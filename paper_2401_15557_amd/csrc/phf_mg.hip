@@ -35,55 +35,70 @@ __global__ __launch_bounds__(NT) void k_mg_coef(int32_t nEc, const double* __res
 
 // Prolongation row of fine free edge rf: the coarse CR function at the fine
 // edge midpoint, averaged over the (one or two) coarse triangles containing it.
+// With psi_l = 1 - 2 lambda_l, the values at the fine midpoints are fixed by
+// the red-refinement numbering (centre child p = [M0 M1 M2], corner child
+// nEc + 3p + i = [v_i M_(i+2) M_(i+1)], local edge l opposite local vertex l):
+//   - an edge of the centre child, local edge l, is parallel to coarse edge l
+//     and has lambda = 1/2 at v_l and 1/4 at the other two vertices: psi = 0
+//     on edge l, 1/2 on the other two;
+//   - local edge l (1 or 2) of corner child i is the half of coarse edge
+//     E = (i + l) mod 3 at v_i, lambda = 3/4 at v_i and 1/4 at the other end
+//     of E: psi = 1 on E, -1/2 on edge i, 1/2 on the third edge.
+// The fine edge's two triangles give the sides (a half of an interior coarse
+// edge lies in two coarse triangles, weighted 1/2 each); columns are merged
+// in side, then coarse-local-edge order.
 __global__ __launch_bounds__(NT) void k_mg_prolong_build(
     int32_t nf_f, int32_t nEc, const int32_t* __restrict__ red_edge_f,
-    const int2* __restrict__ edge_elems_f, const int2* __restrict__ edge_nodes_f,
-    const double2* __restrict__ xy_f, const double2* __restrict__ exy_c,
-    const int32_t* __restrict__ elem_edges_c, const int32_t* __restrict__ red_row_c,
-    int32_t* __restrict__ P_col, float* __restrict__ P_val)
+    const int2* __restrict__ edge_elems_f, const int8_t* __restrict__ led_f,
+    const int8_t* __restrict__ ledTN_f, const int32_t* __restrict__ elem_edges_c,
+    const int32_t* __restrict__ red_row_c, int32_t* __restrict__ P_col, float* __restrict__ P_val)
 {
     const int32_t rf = blockIdx.x * NT + threadIdx.x;
     if (rf >= nf_f) return;
     const int32_t e = red_edge_f[rf];
     const int2 tt = edge_elems_f[e];
-    const int2 kl = edge_nodes_f[e];
-    const double2 a = xy_f[kl.x], b = xy_f[kl.y];
-    const double mx = 0.5 * (a.x + b.x), my = 0.5 * (a.y + b.y);
+    const int32_t fine[2] = {tt.x, tt.y};
+    const int lloc[2] = {led_f[e], tt.y >= 0 ? (int)ledTN_f[e] : 0};
     int32_t par[2] = {parent_of(tt.x, nEc), tt.y >= 0 ? parent_of(tt.y, nEc) : -1};
     if (par[1] == par[0]) par[1] = -1;
-    const double scale = par[1] < 0 ? 1.0 : 0.5;
+    const float scale = par[1] < 0 ? 1.0f : 0.5f;
     int32_t col[6];
-    double val[6];
+    float val[6];
     int n = 0;
     for (int s = 0; s < 2; ++s) {
         const int32_t p = par[s];
         if (p < 0) continue;
-        const double2 P0 = exy_c[3 * (int64_t)p], P1 = exy_c[3 * (int64_t)p + 1],
-                      P2 = exy_c[3 * (int64_t)p + 2];
-        const double d1x = P1.x - P0.x, d1y = P1.y - P0.y, d2x = P2.x - P0.x, d2y = P2.y - P0.y;
-        const double det = d1x * d2y - d1y * d2x;
-        const double rx = mx - P0.x, ry = my - P0.y;
-        const double l1 = (rx * d2y - ry * d2x) / det, l2 = (d1x * ry - d1y * rx) / det;
-        const double lam[3] = {1.0 - l1 - l2, l1, l2};
-        for (int l = 0; l < 3; ++l) {
-            const double w = 1.0 - 2.0 * lam[l];
-            if (fabs(w) < 1e-12) continue;
-            const int32_t rc = red_row_c[elem_edges_c[3 * (int64_t)p + l]];
+        float w[3];
+        const int l = lloc[s];
+        if (fine[s] < nEc) {  // centre child: edge parallel to coarse edge l
+            w[l] = 0.0f;
+            w[(l + 1) % 3] = 0.5f;
+            w[(l + 2) % 3] = 0.5f;
+        } else {  // corner child i: half of coarse edge E at v_i
+            const int i = (fine[s] - nEc) % 3;
+            const int E = (i + l) % 3;
+            w[E] = 1.0f;
+            w[i] = -0.5f;
+            w[3 - E - i] = 0.5f;
+        }
+        for (int k = 0; k < 3; ++k) {
+            if (w[k] == 0.0f) continue;
+            const int32_t rc = red_row_c[elem_edges_c[3 * (int64_t)p + k]];
             if (rc < 0) continue;
             int q = 0;
             while (q < n && col[q] != rc) ++q;
             if (q == n) {
                 col[n] = rc;
-                val[n] = 0.0;
+                val[n] = 0.0f;
                 ++n;
             }
-            val[q] += scale * w;
+            val[q] += scale * w[k];
         }
     }
     for (int k = 0; k < 5; ++k) {
         const int64_t slot = (int64_t)k * nf_f + rf;
         P_col[slot] = k < n ? col[k] : 0;
-        P_val[slot] = k < n ? (float)val[k] : 0.0f;
+        P_val[slot] = k < n ? val[k] : 0.0f;
     }
 }
 
@@ -664,7 +679,7 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
                 L.ns = fine;
                 L.own_ns = false;
             } else {
-                TRY(phf_ns_create(ms, &L.ns));
+                TRY(phf_ns_create(ms, &L.ns, true));
                 L.own_ns = true;
                 const size_t e9 = 9 * (size_t)ms->nE;
                 TRY(phf_dmalloc(ctx, &L.K, e9, "multigrid K"));
@@ -692,8 +707,8 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             TRY(phf_dmalloc(ctx, &L.P_val, 5 * nf, "multigrid P values"));
             if (L.nf > 0)
                 PHF_LAUNCH(ctx, "k_mg_prolong_build", k_mg_prolong_build, nblk(L.nf), NT, 0, L.nf,
-                           Cl.mesh->nE, ms->red_edge, ms->edge_elems, ms->edge_nodes, ms->xy,
-                           Cl.mesh->exy, Cl.mesh->elem_edges, Cl.mesh->red_row, L.P_col, L.P_val);
+                           Cl.mesh->nE, ms->red_edge, ms->edge_elems, ms->led, ms->ledTN,
+                           Cl.mesh->elem_edges, Cl.mesh->red_row, L.P_col, L.P_val);
             // restriction tables
             const int32_t nEc = Cl.mesh->nE, nc = Cl.mesh->n_free;
             TRY(phf_dmalloc(ctx, &L.rows9, 9 * (size_t)nEc, "multigrid restriction rows"));

@@ -52,13 +52,17 @@ struct phf_ns {
     double* scal = nullptr;       // device scalars
     int* iflags = nullptr;        // [0] done, [1] iterations
     bool have_operator = false;
+    bool operator_only = false;   // only B and the ELL operator (coarse multigrid levels)
     int32_t next_it = 0;          // index of the next CG iteration issued
 };
 
 // Scalar slots in phf_ns::scal.
 enum { NS_RR = 0, NS_BB, NS_TOL2, NS_NSCAL = 8 };
 
-int phf_ns_create(phf_mesh* mesh, phf_ns** out);
+// operator_only: a workspace that only builds the reduced operator (the
+// coarse levels of the multigrid hierarchy): no element tables, multiplier
+// scales, iteration vectors or A_T blocks.
+int phf_ns_create(phf_mesh* mesh, phf_ns** out, bool operator_only = false);
 void phf_ns_destroy(phf_ns* ns);
 // Builds A_T, B, the ELL values, the Jacobi diagonal for A = cK K + cD D + cM M,
 // and |E|/2 per multiplier row from the assembled C.
@@ -66,8 +70,9 @@ int phf_ns_operator(phf_ns* ns, const double* K, const double* M, const double* 
                     double cM, const double* D = nullptr, double cD = 0.0);
 // Right-hand side reduction (rhs2 is the right-hand side of -C U = rhs2).
 int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2);
-// Starts CG from the current w (zero it first for a cold start).
-int phf_ns_cg_start(phf_ns* ns, double rtol);
+// Starts CG from the current w, or with zero_start from w = 0 (written by
+// the start itself).
+int phf_ns_cg_start(phf_ns* ns, double rtol, bool zero_start = false);
 // Issues `iters` CG iterations (skipped on the device once converged).
 int phf_ns_cg_iterate(phf_ns* ns, int32_t iters);
 // U = P (w + kv); mu = mu_scale * element-local multiplier recovery.
@@ -80,7 +85,8 @@ int phf_ns_bicg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_e
                       int32_t* iters_out, double* relres_out, int* converged, int* breakdown);
 // Host convergence loop: cg_start + batches of check_every iterations.
 int phf_ns_cg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_every,
-                    int32_t* iters_out, double* relres_out, int* converged);
+                    int32_t* iters_out, double* relres_out, int* converged,
+                    bool zero_start = false);
 // Multigrid smoothing as the public options give it (0 = default).
 struct phf_mg_params {
     int32_t sweeps = 0, smoother = 0;

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(NT) void k_ns_blocks(int32_t nE, const double* __re
     }
     __syncthreads();
     for (int32_t q = tid; q < cnt; q += NT) {
-        Ablk[9 * m0 + q] = sA[q];
+        if (Ablk) Ablk[9 * m0 + q] = sA[q];
         B[9 * m0 + q] = sB[q];
     }
 }
@@ -251,12 +251,14 @@ __device__ inline double block_reduce_partials(const double* __restrict__ part, 
     return phf_block_sum_f64<NT>(s, sh);
 }
 
-template <bool JAC>
+// ZERO: the iteration starts from w = 0, which the kernel writes; r = b
+// without a product.
+template <bool JAC, bool ZERO>
 __global__ __launch_bounds__(NT) void k_cg_init(int32_t nf, const int32_t* __restrict__ col,
                                                 const double* __restrict__ val,
                                                 const double* __restrict__ dinv,
                                                 const double* __restrict__ b,
-                                                const double* __restrict__ w,
+                                                double* __restrict__ w,
                                                 double* __restrict__ r, double* __restrict__ z,
                                                 double* __restrict__ p, double* __restrict__ q,
                                                 double* __restrict__ part)
@@ -264,7 +266,13 @@ __global__ __launch_bounds__(NT) void k_cg_init(int32_t nf, const int32_t* __res
     __shared__ double sh[NT / 64];
     double s_rz = 0.0, s_rr = 0.0, s_bb = 0.0;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
-        double ri = b[i] - ell_row(i, nf, col, val, w);
+        double ri;
+        if (ZERO) {
+            w[i] = 0.0;
+            ri = b[i];
+        } else {
+            ri = b[i] - ell_row(i, nf, col, val, w);
+        }
         r[i] = ri;
         p[i] = 0.0;
         q[i] = 0.0;
@@ -678,7 +686,7 @@ void phf_ns_destroy(phf_ns* ns)
     delete ns;
 }
 
-int phf_ns_create(phf_mesh* mesh, phf_ns** out)
+int phf_ns_create(phf_mesh* mesh, phf_ns** out, bool operator_only)
 {
     phf_ctx* ctx = mesh->ctx;
     phf_ns* ns = new (std::nothrow) phf_ns;
@@ -689,15 +697,21 @@ int phf_ns_create(phf_mesh* mesh, phf_ns** out)
     ns->L = mesh->L;
     ns->nbv = (int32_t)std::min<int64_t>(std::max<int64_t>(nblk(ns->nf), 1), MAXB);
     const size_t e3 = 3 * (size_t)ns->nE, e9 = 9 * (size_t)ns->nE, nf = ns->nf;
+    ns->operator_only = operator_only;
     int rc = 0;
-    rc = rc ? rc : phf_dmalloc(ctx, &ns->elem_red, e3, "solver element rows");
-    rc = rc ? rc : phf_dmalloc(ctx, &ns->elem_row, e3, "solver element rows");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_col, 5 * nf, "solver ELL columns");
-    rc = rc ? rc : phf_dmalloc(ctx, &ns->row_h, (size_t)ns->L, "solver row h");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->B, e9, "solver blocks");
-    rc = rc ? rc : phf_dmalloc(ctx, &ns->Ablk, e9, "solver blocks");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_val, 5 * nf, "solver ELL values");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->dinv, nf, "solver diagonal");
+    if (operator_only) {
+        if (rc) phf_ns_destroy(ns);
+        else *out = ns;
+        return rc;
+    }
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->elem_red, e3, "solver element rows");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->elem_row, e3, "solver element rows");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->row_h, (size_t)ns->L, "solver row h");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->Ablk, e9, "solver blocks");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->kv, e3, "solver known values");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->cs, e3, "solver element rhs");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->b, nf, "solver rhs");
@@ -740,7 +754,7 @@ int phf_ns_operator(phf_ns* ns, const double* K, const double* M, const double* 
         PHF_LAUNCH(ctx, "k_ns_ellval", k_ns_ellval, nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge,
                    mesh->edge_elems, mesh->led, mesh->ledTN, mesh->elem_edges, mesh->red_row,
                    ns->B, ns->ell_col, ns->ell_val, ns->dinv);
-    if (ns->L > 0)
+    if (ns->L > 0 && !ns->operator_only)
         PHF_LAUNCH(ctx, "k_ns_rowh", k_ns_rowh, nblk(ns->L), NT, 0, ns->L, mesh->C_rowptr, C,
                    ns->row_h);
     ns->have_operator = true;
@@ -766,7 +780,7 @@ int phf_ns_zero_w(phf_ns* ns)
     return PHF_OK;
 }
 
-int phf_ns_cg_start(phf_ns* ns, double rtol)
+int phf_ns_cg_start(phf_ns* ns, double rtol, bool zero_start)
 {
     phf_ctx* ctx = ns->mesh->ctx;
     ns->next_it = 0;
@@ -774,12 +788,11 @@ int phf_ns_cg_start(phf_ns* ns, double rtol)
         PHF_HIP(ctx, hipMemsetAsync(ns->iflags, 0, 4 * sizeof(int), ctx->stream));
         return PHF_OK;
     }
-    if (ns->mg && ns->mg_on)
-        PHF_LAUNCH(ctx, "k_cg_init", k_cg_init<false>, ns->nbv, NT, 0, ns->nf, ns->ell_col,
-                   ns->ell_val, ns->dinv, ns->b, ns->w, ns->r, ns->z, ns->p, ns->q, ns->part);
-    else
-        PHF_LAUNCH(ctx, "k_cg_init", k_cg_init<true>, ns->nbv, NT, 0, ns->nf, ns->ell_col,
-                   ns->ell_val, ns->dinv, ns->b, ns->w, ns->r, ns->z, ns->p, ns->q, ns->part);
+    const bool mg = ns->mg && ns->mg_on;
+    auto init = mg ? (zero_start ? k_cg_init<false, true> : k_cg_init<false, false>)
+                   : (zero_start ? k_cg_init<true, true> : k_cg_init<true, false>);
+    PHF_LAUNCH(ctx, "k_cg_init", init, ns->nbv, NT, 0, ns->nf, ns->ell_col, ns->ell_val, ns->dinv,
+               ns->b, ns->w, ns->r, ns->z, ns->p, ns->q, ns->part);
     PHF_LAUNCH(ctx, "k_cg_init_final", k_cg_init_final, 1, NT, 0, ns->part, ns->nbv, rtol * rtol,
                ns->scal, ns->iflags);
     if (ns->mg && ns->mg_on)
@@ -830,10 +843,10 @@ int phf_ns_recover(phf_ns* ns, const double* rhs1, double* U, double* mu, double
 
 // Host-side convergence loop shared by phf_solve and Crank-Nicolson.
 int phf_ns_cg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_every,
-                    int32_t* iters_out, double* relres_out, int* converged)
+                    int32_t* iters_out, double* relres_out, int* converged, bool zero_start)
 {
     phf_ctx* ctx = ns->mesh->ctx;
-    TRY(phf_ns_cg_start(ns, rtol));
+    TRY(phf_ns_cg_start(ns, rtol, zero_start));
     int32_t done_iters = 0;
     int hf[2] = {0, 0};
     PHF_HIP(ctx, hipMemcpyAsync(hf, ns->iflags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
@@ -1028,14 +1041,15 @@ extern "C" int phf_solve(phf_mesh* mesh, const phf_coeffs* co, const phf_system*
     mp.range = o.mg_range;
     TRY(phf_ns_set_precond(ns, o.precond, mp, co, 1.0, co->delta));
     TRY(phf_ns_rhs(ns, sys->F, sys->bD));
-    TRY(phf_ns_zero_w(ns));
+    // both iterations start from w = 0 (the CG initialisation writes it)
+    if (o.method == PHF_SOLVER_NULLSPACE_BICGSTAB) TRY(phf_ns_zero_w(ns));
     int32_t iters = 0;
     double relres = 0;
     int conv = 0, brk = 0;
     if (o.method == PHF_SOLVER_NULLSPACE_BICGSTAB)
         TRY(phf_ns_bicg_solve(ns, o.rtol, o.max_iter, o.check_every, &iters, &relres, &conv, &brk));
     else
-        TRY(phf_ns_cg_solve(ns, o.rtol, o.max_iter, o.check_every, &iters, &relres, &conv));
+        TRY(phf_ns_cg_solve(ns, o.rtol, o.max_iter, o.check_every, &iters, &relres, &conv, true));
     TRY(phf_ns_recover(ns, sys->F, U, Lambda, 1.0));
     double srel = -1.0;
     if (o.saddle_residual && sys->S && Lambda) {
