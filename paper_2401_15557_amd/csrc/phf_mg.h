@@ -60,11 +60,11 @@ struct phf_mg_dev_level {
 
 struct phf_mg_level {
     phf_mesh* mesh = nullptr;
-    phf_ns* ns = nullptr;       // operator of this level (owned on coarse levels)
-    bool own_ns = false;
+    phf_ns* ns = nullptr;       // the caller's operator (finest level only)
     int32_t nf = 0;
-    // coarse-level assembly buffers (null on the finest level)
-    double *K = nullptr, *M = nullptr, *C = nullptr, *F = nullptr, *bD = nullptr, *aT = nullptr;
+    // coarse levels: triangle coefficient (averaged from the finer level)
+    // and element blocks B_T = P^T A_T P of the re-discretised operator
+    double *aT = nullptr, *B = nullptr;
     // single-precision scaled operator: the off-diagonal entries of D^-1 A
     // (ELL-4, slot-major; unused slots hold the row itself and 0), the
     // diagonal D and its inverse
@@ -90,6 +90,8 @@ struct phf_mg {
     phf_mg_level lev[PHF_MG_MAX_LEVELS];
     double* cinv = nullptr;  // dense inverse of the coarsest operator (n0 <= DENSE_MAX)
     double* cwork = nullptr;
+    int32_t* col64 = nullptr;  // coarsest operator in double precision (ELL-5), for cinv
+    double* val64 = nullptr;
     int32_t n0 = 0;
     int32_t tail_top = -1;   // levels 0..tail_top run in the single-workgroup kernel
     phf_mg_dev_level h_lv[PHF_MG_MAX_LEVELS];

@@ -305,6 +305,102 @@ __device__ inline void row_coarse(int32_t i, int32_t n, const double* __restrict
     x[i] = (float)s;
 }
 
+// Element blocks of a coarse level's re-discretised operator,
+// B_T = P^T (cK K_T + cM M_T) P with K_T = a_T |T| (A grad lambda_j) . grad
+// lambda_i and the unit mass M_T = |T|/12 (1 + delta_ij) (Definition 3.1),
+// straight from the element coordinates. The tile's blocks are staged in LDS
+// and stored coalesced.
+__global__ __launch_bounds__(NT) void k_mg_cblocks(int32_t nE, const double2* __restrict__ exy,
+                                                   const double* __restrict__ aT, double A00,
+                                                   double A01, double A10, double A11, double cK,
+                                                   double cM, double* __restrict__ B)
+{
+    __shared__ double sB[9 * NT];
+    const int tid = threadIdx.x;
+    const int64_t m0 = (int64_t)blockIdx.x * NT;
+    const int32_t nt = (int32_t)min((int64_t)NT, (int64_t)nE - m0);
+    if (tid < nt) {
+        const int64_t m = m0 + tid;
+        const double2 P0 = exy[3 * m], P1 = exy[3 * m + 1], P2 = exy[3 * m + 2];
+        // g_i = 2|T| grad lambda_i (the edge opposite vertex i turned by 90 deg)
+        const double gx[3] = {P1.y - P2.y, P2.y - P0.y, P0.y - P1.y};
+        const double gy[3] = {P2.x - P1.x, P0.x - P2.x, P1.x - P0.x};
+        const double det = (P1.x - P0.x) * (P2.y - P0.y) - (P2.x - P0.x) * (P1.y - P0.y);
+        const double s = (aT ? aT[m] : 1.0) / (2.0 * det);
+        const double mass = det / 24.0;  // |T| / 12
+        double A[9];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double ax = A00 * gx[j] + A01 * gy[j], ay = A10 * gx[j] + A11 * gy[j];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                A[3 * j + i] = cK * s * (ax * gx[i] + ay * gy[i]) + cM * mass * (i == j ? 2.0 : 1.0);
+        }
+        // AP[i][l] = rowsum_i(A) - 2 A[i][l]; B[l][l'] = colsum_{l'}(AP) - 2 AP[l][l']
+        double AP[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double rs = A[3 * i] + A[3 * i + 1] + A[3 * i + 2];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) AP[3 * i + l] = rs - 2.0 * A[3 * i + l];
+        }
+#pragma unroll
+        for (int lp = 0; lp < 3; ++lp) {
+            const double cs = AP[lp] + AP[3 + lp] + AP[6 + lp];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) sB[9 * tid + 3 * l + lp] = cs - 2.0 * AP[3 * l + lp];
+        }
+    }
+    __syncthreads();
+    for (int32_t q = tid; q < 9 * nt; q += NT) B[9 * m0 + q] = sB[q];
+}
+
+// Coarse-level rows of the reduced operator: the ELL-5 entries of row r
+// (columns sorted, values B[s0] + B[s1]) scaled straight into the cycle's
+// rows (off-diagonals of D^-1 A in ELL-4, the diagonal and its inverse, as
+// k_mg_scale computes them from the double-precision rows). With col64 and
+// val64 (the coarsest level) also the double-precision ELL-5 rows.
+__global__ __launch_bounds__(NT) void k_mg_crows(
+    int32_t nf, const int32_t* __restrict__ red_edge, const int2* __restrict__ edge_elems,
+    const int8_t* __restrict__ led, const int8_t* __restrict__ ledTN,
+    const int32_t* __restrict__ elem_edges, const int32_t* __restrict__ red_row,
+    const double* __restrict__ B, int32_t* __restrict__ col4, float* __restrict__ val4,
+    float* __restrict__ diag, float* __restrict__ dinv, int32_t* __restrict__ col64,
+    double* __restrict__ val64)
+{
+    const int32_t r = blockIdx.x * NT + threadIdx.x;
+    if (r >= nf) return;
+    int32_t col[5], s0[5], s1[5];
+    const int n = phf_reduced_entries(red_edge[r], edge_elems, led, ledTN, elem_edges, red_row,
+                                      col, s0, s1);
+    double v[5];
+    double d = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        v[k] = k < n ? B[s0[k]] + (s1[k] >= 0 ? B[s1[k]] : 0.0) : 0.0;
+        if (k < n && col[k] == r) d = v[k];
+        if (col64) {
+            col64[(int64_t)k * nf + r] = k < n ? col[k] : r;
+            val64[(int64_t)k * nf + r] = v[k];
+        }
+    }
+    const double di = d > 0.0 ? 1.0 / d : 1.0;
+    int q = 0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        if (k >= n || col[k] == r || q >= 4) continue;
+        col4[(int64_t)q * nf + r] = col[k];
+        val4[(int64_t)q * nf + r] = (float)(v[k] * di);
+        ++q;
+    }
+    for (; q < 4; ++q) {
+        col4[(int64_t)q * nf + r] = r;
+        val4[(int64_t)q * nf + r] = 0.0f;
+    }
+    diag[r] = d > 0.0 ? (float)d : 1.0f;
+    dinv[r] = (float)di;
+}
+
 // Single-precision scaled copy of a level's operator: off-diagonal entries
 // of row r divided by its diagonal a_rr (1 where a_rr <= 0, as for the
 // double-precision inverse diagonal), the diagonal and its inverse.
@@ -637,9 +733,8 @@ void phf_mg_destroy(phf_mg* mg)
     if (!mg) return;
     for (int l = 0; l < mg->nlev; ++l) {
         phf_mg_level& L = mg->lev[l];
-        if (L.own_ns && L.ns) phf_ns_destroy(L.ns);
-        double* d[] = {L.K, L.M, L.C, L.F, L.bD, L.aT};
-        for (double* p : d) phf_dfree(p);
+        phf_dfree(L.aT);
+        phf_dfree(L.B);
         float* f[] = {L.val4, L.diag32, L.dinv32, L.x, L.y, L.b, L.r, L.P_val, L.t};
         for (float* p : f) phf_dfree(p);
         phf_dfree(L.col4);
@@ -650,6 +745,8 @@ void phf_mg_destroy(phf_mg* mg)
     }
     phf_dfree(mg->cinv);
     phf_dfree(mg->cwork);
+    phf_dfree(mg->col64);
+    phf_dfree(mg->val64);
     phf_dfree(mg->d_lv);
     phf_dfree(mg->lmax);
     phf_dfree(mg->wts);
@@ -677,16 +774,8 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             phf_mesh* ms = L.mesh;
             if (l == nlev - 1) {
                 L.ns = fine;
-                L.own_ns = false;
             } else {
-                TRY(phf_ns_create(ms, &L.ns, true));
-                L.own_ns = true;
-                const size_t e9 = 9 * (size_t)ms->nE;
-                TRY(phf_dmalloc(ctx, &L.K, e9, "multigrid K"));
-                TRY(phf_dmalloc(ctx, &L.M, e9, "multigrid M"));
-                TRY(phf_dmalloc(ctx, &L.C, (size_t)ms->nnz_C, "multigrid C"));
-                TRY(phf_dmalloc(ctx, &L.F, 3 * (size_t)ms->nE, "multigrid F"));
-                TRY(phf_dmalloc(ctx, &L.bD, (size_t)ms->L, "multigrid bD"));
+                TRY(phf_dmalloc(ctx, &L.B, 9 * (size_t)ms->nE, "multigrid element blocks"));
                 TRY(phf_dmalloc(ctx, &L.aT, (size_t)ms->nE, "multigrid coefficient"));
             }
             L.nf = ms->n_free;
@@ -724,6 +813,8 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
         if (mg->n0 > 0 && mg->n0 <= PHF_MG_DENSE_MAX) {
             TRY(phf_dmalloc(ctx, &mg->cinv, (size_t)mg->n0 * mg->n0, "coarse inverse"));
             TRY(phf_dmalloc(ctx, &mg->cwork, (size_t)mg->n0 * mg->n0, "coarse work"));
+            TRY(phf_dmalloc(ctx, &mg->col64, 5 * (size_t)mg->n0, "coarse operator columns"));
+            TRY(phf_dmalloc(ctx, &mg->val64, 5 * (size_t)mg->n0, "coarse operator values"));
         }
         // the small levels below the finest: one workgroup runs their cycle
         mg->tail_top = 0;
@@ -783,28 +874,26 @@ int phf_mg_numeric(phf_mg* mg, const phf_coeffs* co, double cK, double cM)
             aT_prev = L.aT;
         }
     }
+    // coarse levels: the re-discretised operator (no convection) straight
+    // into the cycle's scaled single-precision rows
     for (int l = 0; l < top; ++l) {
         phf_mg_level& L = mg->lev[l];
-        phf_coeffs c = *co;
-        c.a_T = co->a_T ? L.aT : nullptr;
-        c.p[0] = c.p[1] = 0.0;
-        phf_data d{};
-        phf_system s{};
-        s.K = L.K;
-        s.M = L.M;
-        s.C = L.C;
-        s.F = L.F;
-        s.bD = L.bD;
-        TRY(phf_assemble_impl(L.mesh, &c, &d, &s));
-        TRY(phf_ns_operator(L.ns, L.K, L.M, L.C, cK, cM));
-    }
-    // single-precision scaled operators for the cycle (the finest operator
-    // is the one the caller built)
-    for (int l = 0; l <= top; ++l) {
-        phf_mg_level& L = mg->lev[l];
+        const phf_mesh* ms = L.mesh;
+        PHF_LAUNCH(ctx, "k_mg_cblocks", k_mg_cblocks, nblk(ms->nE), NT, 0, ms->nE, ms->exy,
+                   co->a_T ? L.aT : nullptr, co->A[0], co->A[1], co->A[2], co->A[3], cK, cM, L.B);
         if (L.nf == 0) continue;
-        PHF_LAUNCH(ctx, "k_mg_scale", k_mg_scale, grid_for(L.nf), NT, 0, L.nf, L.ns->ell_col,
-                   L.ns->ell_val, L.col4, L.val4, L.diag32, L.dinv32);
+        const bool c64 = l == 0 && mg->cinv;
+        PHF_LAUNCH(ctx, "k_mg_crows", k_mg_crows, nblk(L.nf), NT, 0, L.nf, ms->red_edge,
+                   ms->edge_elems, ms->led, ms->ledTN, ms->elem_edges, ms->red_row, L.B, L.col4,
+                   L.val4, L.diag32, L.dinv32, c64 ? mg->col64 : nullptr,
+                   c64 ? mg->val64 : nullptr);
+    }
+    // finest level: from the operator the caller built
+    {
+        phf_mg_level& L = mg->lev[top];
+        if (L.nf > 0)
+            PHF_LAUNCH(ctx, "k_mg_scale", k_mg_scale, grid_for(L.nf), NT, 0, L.nf, L.ns->ell_col,
+                       L.ns->ell_val, L.col4, L.val4, L.diag32, L.dinv32);
     }
     // sweep weights
     const bool cheb = mg->smoother == PHF_MG_SMOOTH_CHEBYSHEV;
@@ -820,8 +909,8 @@ int phf_mg_numeric(phf_mg* mg, const phf_coeffs* co, double cK, double cM)
                cheb ? 1 : 0, (float)mg->omega, (float)mg->range, mg->lmax, mg->wts);
     if (mg->cinv) {
         const int32_t n0 = mg->n0;
-        PHF_LAUNCH(ctx, "k_mg_dense", k_mg_dense, nblk(n0), NT, 0, n0, mg->lev[0].ns->ell_col,
-                   mg->lev[0].ns->ell_val, mg->cinv);
+        PHF_LAUNCH(ctx, "k_mg_dense", k_mg_dense, nblk(n0), NT, 0, n0, mg->col64, mg->val64,
+                   mg->cinv);
         PHF_LAUNCH(ctx, "k_mg_gj", k_mg_gj, 1, 1024, 0, n0, mg->cinv, mg->cwork);
     }
     return PHF_OK;

@@ -52,17 +52,13 @@ struct phf_ns {
     double* scal = nullptr;       // device scalars
     int* iflags = nullptr;        // [0] done, [1] iterations
     bool have_operator = false;
-    bool operator_only = false;   // only B and the ELL operator (coarse multigrid levels)
     int32_t next_it = 0;          // index of the next CG iteration issued
 };
 
 // Scalar slots in phf_ns::scal.
 enum { NS_RR = 0, NS_BB, NS_TOL2, NS_NSCAL = 8 };
 
-// operator_only: a workspace that only builds the reduced operator (the
-// coarse levels of the multigrid hierarchy): no element tables, multiplier
-// scales, iteration vectors or A_T blocks.
-int phf_ns_create(phf_mesh* mesh, phf_ns** out, bool operator_only = false);
+int phf_ns_create(phf_mesh* mesh, phf_ns** out);
 void phf_ns_destroy(phf_ns* ns);
 // Builds A_T, B, the ELL values, the Jacobi diagonal for A = cK K + cD D + cM M,
 // and |E|/2 per multiplier row from the assembled C.

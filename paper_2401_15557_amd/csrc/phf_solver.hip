@@ -73,7 +73,7 @@ __global__ __launch_bounds__(NT) void k_ns_blocks(int32_t nE, const double* __re
     }
     __syncthreads();
     for (int32_t q = tid; q < cnt; q += NT) {
-        if (Ablk) Ablk[9 * m0 + q] = sA[q];
+        Ablk[9 * m0 + q] = sA[q];
         B[9 * m0 + q] = sB[q];
     }
 }
@@ -686,7 +686,7 @@ void phf_ns_destroy(phf_ns* ns)
     delete ns;
 }
 
-int phf_ns_create(phf_mesh* mesh, phf_ns** out, bool operator_only)
+int phf_ns_create(phf_mesh* mesh, phf_ns** out)
 {
     phf_ctx* ctx = mesh->ctx;
     phf_ns* ns = new (std::nothrow) phf_ns;
@@ -697,17 +697,11 @@ int phf_ns_create(phf_mesh* mesh, phf_ns** out, bool operator_only)
     ns->L = mesh->L;
     ns->nbv = (int32_t)std::min<int64_t>(std::max<int64_t>(nblk(ns->nf), 1), MAXB);
     const size_t e3 = 3 * (size_t)ns->nE, e9 = 9 * (size_t)ns->nE, nf = ns->nf;
-    ns->operator_only = operator_only;
     int rc = 0;
     rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_col, 5 * nf, "solver ELL columns");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->B, e9, "solver blocks");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_val, 5 * nf, "solver ELL values");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->dinv, nf, "solver diagonal");
-    if (operator_only) {
-        if (rc) phf_ns_destroy(ns);
-        else *out = ns;
-        return rc;
-    }
     rc = rc ? rc : phf_dmalloc(ctx, &ns->elem_red, e3, "solver element rows");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->elem_row, e3, "solver element rows");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->row_h, (size_t)ns->L, "solver row h");
@@ -754,7 +748,7 @@ int phf_ns_operator(phf_ns* ns, const double* K, const double* M, const double* 
         PHF_LAUNCH(ctx, "k_ns_ellval", k_ns_ellval, nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge,
                    mesh->edge_elems, mesh->led, mesh->ledTN, mesh->elem_edges, mesh->red_row,
                    ns->B, ns->ell_col, ns->ell_val, ns->dinv);
-    if (ns->L > 0 && !ns->operator_only)
+    if (ns->L > 0)
         PHF_LAUNCH(ctx, "k_ns_rowh", k_ns_rowh, nblk(ns->L), NT, 0, ns->L, mesh->C_rowptr, C,
                    ns->row_h);
     ns->have_operator = true;
