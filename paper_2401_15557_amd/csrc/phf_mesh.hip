@@ -213,13 +213,13 @@ __global__ __launch_bounds__(256) void k_boundary_mark(
 // Per-tile (256 edges) numbers of Dirichlet and Neumann edges; with `mark`
 // (a mesh given by the caller) also checks that every boundary edge was
 // listed.
-__global__ __launch_bounds__(256) void k_rows_count(int32_t n_edges, const int8_t* __restrict__ etype,
+__device__ inline void d_rows_count(int32_t bid, int32_t n_edges, const int8_t* __restrict__ etype,
                                                     const int2* __restrict__ edge_elems,
                                                     const int32_t* __restrict__ mark,
                                                     phf_cnt2* __restrict__ tiles, int* flags)
 {
     __shared__ phf_cnt2 sh[4];
-    const int32_t e = blockIdx.x * 256 + threadIdx.x;
+    const int32_t e = bid * 256 + threadIdx.x;
     int t = 0;
     if (e < n_edges) {
         t = etype[e];
@@ -228,14 +228,13 @@ __global__ __launch_bounds__(256) void k_rows_count(int32_t n_edges, const int8_
     const uint64_t bd = __ballot(t == 1), bn = __ballot(t == 2);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = phf_cnt2{(int32_t)__popcll(bd), (int32_t)__popcll(bn)};
     __syncthreads();
-    if (threadIdx.x == 0) tiles[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+    if (threadIdx.x == 0) tiles[bid] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 // Exclusive prefix sums, in place, of n per-tile values by one workgroup of
 // 1024 threads (each a contiguous run of tiles); *total (nullable) = the sum.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_tile_exscan(int32_t n, T* __restrict__ v,
-                                                      T* __restrict__ total)
+__device__ inline void d_tile_exscan(int32_t n, T* __restrict__ v, T* __restrict__ total)
 {
     __shared__ T sh[1024];
     const int32_t tid = threadIdx.x;
@@ -263,22 +262,28 @@ __global__ __launch_bounds__(1024) void k_tile_exscan(int32_t n, T* __restrict__
 // Multiplier-row tables and the C pattern. With D(e), N(e) the Dirichlet and
 // Neumann edges before e (tile base plus ballot prefix): multiplier row
 // e - N(e), free row e - D(e), C row pointer 4 (e - D(e) - N(e)) + 2 D(e).
-__global__ __launch_bounds__(256) void k_rows(
+__device__ inline void d_rows(int32_t bid, 
     int32_t n_edges, const int8_t* __restrict__ etype, const phf_cnt2* __restrict__ tiles,
     const int2* __restrict__ edge_nodes, const int2* __restrict__ edge_elems,
     const int8_t* __restrict__ led, const int8_t* __restrict__ ledTN,
     int32_t* __restrict__ edge_row, int32_t* __restrict__ red_row,
     int32_t* __restrict__ red_edge, int32_t* __restrict__ row_edge,
-    int2* __restrict__ row_nodes, int32_t* __restrict__ C_rowptr, int32_t* __restrict__ C_col)
+    int2* __restrict__ row_nodes, int32_t* __restrict__ C_rowptr, int32_t* __restrict__ C_col,
+    int32_t L, int32_t nnzC, int32_t nnz_dof, int32_t* __restrict__ S_rowptr_m,
+    int32_t* __restrict__ S_col_m)
 {
     __shared__ phf_cnt2 sh[4];
-    const int32_t e = blockIdx.x * 256 + threadIdx.x;
+    const int32_t e = bid * 256 + threadIdx.x;
+    if (e == 0) {  // the closing row pointers
+        C_rowptr[L] = nnzC;
+        S_rowptr_m[L] = nnz_dof + nnzC;
+    }
     const int t = e < n_edges ? etype[e] : 0;
     const uint64_t bd = __ballot(t == 1), bn = __ballot(t == 2);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) sh[wid] = phf_cnt2{(int32_t)__popcll(bd), (int32_t)__popcll(bn)};
     __syncthreads();
-    phf_cnt2 before = tiles[blockIdx.x];
+    phf_cnt2 before = tiles[bid];
     for (int w = 0; w < wid; ++w) before = before + sh[w];
     const uint64_t below = lane == 0 ? 0ull : (1ull << lane) - 1ull;
     const int32_t nd = before.d + (int32_t)__popcll(bd & below),
@@ -302,23 +307,30 @@ __global__ __launch_bounds__(256) void k_rows(
     row_nodes[r] = make_int2(t == 1 ? ~kl.x : kl.x, kl.y);
     const int32_t c = 4 * (e - nd - nn) + 2 * nd;
     C_rowptr[r] = c;
+    // saddle multiplier row r = C's row r, after the DOF rows' entries
+    S_rowptr_m[r] = nnz_dof + c;
     int2 tt = edge_elems[e];
     // vertex DOFs of the edge in T+ (the two local vertices != led), ascending
     int lp = led[e];
     int a = lp == 0 ? 1 : 0, b = lp == 2 ? 1 : 2;
-    C_col[c] = 3 * tt.x + a;
-    C_col[c + 1] = 3 * tt.x + b;
+    int32_t cc[4] = {3 * tt.x + a, 3 * tt.x + b, 0, 0};
+    int nc = 2;
     if (t == 0) {
         int ln = ledTN[e];
         int a2 = ln == 0 ? 1 : 0, b2 = ln == 2 ? 1 : 2;
-        C_col[c + 2] = 3 * tt.y + a2;
-        C_col[c + 3] = 3 * tt.y + b2;
+        cc[2] = 3 * tt.y + a2;
+        cc[3] = 3 * tt.y + b2;
+        nc = 4;
+    }
+    for (int k = 0; k < nc; ++k) {
+        C_col[c + k] = cc[k];
+        S_col_m[c + k] = cc[k];
     }
 }
 
 // Element code words, the element-major coordinate copy, and per tile (256
 // elements) the number of Neumann edge incidences.
-__global__ __launch_bounds__(256) void k_elem_codes(int32_t nE, int4* __restrict__ elem4,
+__device__ inline void d_elem_codes(int32_t bid, int32_t nE, int4* __restrict__ elem4,
                                                     const int32_t* __restrict__ elem_edges,
                                                     const int8_t* __restrict__ etype,
                                                     const int2* __restrict__ edge_elems,
@@ -328,7 +340,7 @@ __global__ __launch_bounds__(256) void k_elem_codes(int32_t nE, int4* __restrict
                                                     int32_t* __restrict__ tiles)
 {
     __shared__ int32_t sh[256 / 64];
-    const int32_t m = blockIdx.x * 256 + threadIdx.x;
+    const int32_t m = bid * 256 + threadIdx.x;
     int32_t nneu = 0;
     if (m < nE) {
         int32_t ed[3];
@@ -355,7 +367,7 @@ __global__ __launch_bounds__(256) void k_elem_codes(int32_t nE, int4* __restrict
         exy[3 * (int64_t)m + 2] = xy[e.z];
     }
     const int32_t tot = phf_block_sum_i32<256>(nneu, sh);
-    if (threadIdx.x == 0) tiles[blockIdx.x] = tot;
+    if (threadIdx.x == 0) tiles[bid] = tot;
 }
 
 // Saddle pattern, DOF rows of element m: 3 + (non-Neumann edges of m at
@@ -364,7 +376,7 @@ __global__ __launch_bounds__(256) void k_elem_codes(int32_t nE, int4* __restrict
 // three DOFs, then the multiplier rows of its non-Neumann edges at vertex i
 // in ascending edge order. The block's rows and columns are contiguous in
 // S_rowptr and S_col: they are assembled in LDS and stored coalesced.
-__global__ __launch_bounds__(256) void k_saddle_dof(int32_t nE, const int32_t* __restrict__ ecode,
+__device__ inline void d_saddle_dof(int32_t bid, int32_t nE, const int32_t* __restrict__ ecode,
                                                     const int32_t* __restrict__ tiles,
                                                     const int32_t* __restrict__ elem_edges,
                                                     const int32_t* __restrict__ edge_row,
@@ -374,7 +386,7 @@ __global__ __launch_bounds__(256) void k_saddle_dof(int32_t nE, const int32_t* _
     __shared__ int32_t sh[256 / 64 + 1];
     __shared__ int32_t scol[256 * 15];
     __shared__ int32_t srow[256 * 3];
-    const int32_t m0 = blockIdx.x * 256, m = m0 + threadIdx.x;
+    const int32_t m0 = bid * 256, m = m0 + threadIdx.x;
     const int32_t cnt = min(256, nE - m0);
     const int code = m < nE ? ecode[m] : 0;
     int nneu = 0;
@@ -382,7 +394,7 @@ __global__ __launch_bounds__(256) void k_saddle_dof(int32_t nE, const int32_t* _
     for (int l = 0; l < 3; ++l) nneu += PHF_CODE_TYPE(code, l) == 2;
     int32_t tot;
     const int32_t ex = phf_block_exscan_i32<256>(nneu, sh, &tot);
-    const int32_t base = 15 * m0 - 2 * tiles[blockIdx.x];  // first entry of the block
+    const int32_t base = 15 * m0 - 2 * tiles[bid];  // first entry of the block
     if (m < nE) {
         const int32_t N = 3 * nE;
         int32_t s = 15 * (int32_t)threadIdx.x - 2 * ex;  // offset in the block
@@ -410,32 +422,18 @@ __global__ __launch_bounds__(256) void k_saddle_dof(int32_t nE, const int32_t* _
     for (int32_t q = threadIdx.x; q < 3 * cnt; q += 256) S_rowptr[3 * (int64_t)m0 + q] = srow[q];
 }
 
-// Saddle pattern, multiplier rows (after the nnz_dof entries of the DOF
-// rows): row r is C's row r, so the pointers are shifted C row pointers and
-// the columns a copy of C's.
-__global__ __launch_bounds__(256) void k_saddle_mult(int32_t L, int32_t nnzC, int32_t nnz_dof,
-                                                     const int32_t* __restrict__ C_rowptr,
-                                                     const int32_t* __restrict__ C_col,
-                                                     int32_t* __restrict__ S_rowptr_m,
-                                                     int32_t* __restrict__ S_col_m)
-{
-    const int32_t g = blockIdx.x * 256 + threadIdx.x;
-    if (g < L) S_rowptr_m[g] = nnz_dof + C_rowptr[g];
-    else if (g == L) S_rowptr_m[g] = nnz_dof + nnzC;
-    if (g < nnzC) S_col_m[g] = C_col[g];
-}
 
 // Off-diagonal entries of the reduced (edge-midpoint) operator: each
 // element couples its f free (non-Dirichlet) edges pairwise, f (f - 1)
 // entries; two distinct edges share at most one element, so the count is
 // exact. Per-block sums go to *total with integer atomics (order-independent;
 // a bounded grid keeps the atomics few).
-__global__ __launch_bounds__(256) void k_reduced_count(int32_t nE, const int32_t* __restrict__ ecode,
+__device__ inline void d_reduced_count(int32_t bid, int32_t nblocks, int32_t nE, const int32_t* __restrict__ ecode,
                                                        unsigned long long* total)
 {
     __shared__ int32_t sh[256 / 64 + 1];
     int32_t n = 0;  // at most 6 per element, 6 nE < 2^31 per block
-    for (int32_t m = blockIdx.x * 256 + threadIdx.x; m < nE; m += gridDim.x * 256) {
+    for (int32_t m = bid * 256 + threadIdx.x; m < nE; m += nblocks * 256) {
         const int32_t code = ecode[m];
         int f = 0;
         for (int i = 0; i < 3; ++i) f += PHF_CODE_TYPE(code, i) != 1;
@@ -446,12 +444,11 @@ __global__ __launch_bounds__(256) void k_reduced_count(int32_t nE, const int32_t
     if (threadIdx.x == 0 && tot) atomicAdd(total, (unsigned long long)tot);
 }
 
-__global__ void k_set_i32(int32_t* p, int32_t v) { *p = v; }
 
-__global__ __launch_bounds__(256) void k_c_tiles(int32_t L, const int32_t* __restrict__ C_rowptr,
+__device__ inline void d_c_tiles(int32_t bid, int32_t L, const int32_t* __restrict__ C_rowptr,
                                                  int32_t* __restrict__ C_tile)
 {
-    int32_t t = blockIdx.x * 256 + threadIdx.x;
+    int32_t t = bid * 256 + threadIdx.x;
     int32_t nt = (L + 255) / 256;
     if (t > nt) return;
     C_tile[t] = C_rowptr[min(256 * t, L)];
@@ -459,10 +456,10 @@ __global__ __launch_bounds__(256) void k_c_tiles(int32_t L, const int32_t* __res
 
 // One bit per element: does it own a Neumann edge? Each wavefront packs the
 // bits of 64 consecutive elements with a ballot.
-__global__ __launch_bounds__(256) void k_neu_mask(int32_t nE, const int32_t* __restrict__ ecode,
+__device__ inline void d_neu_mask(int32_t bid, int32_t nE, const int32_t* __restrict__ ecode,
                                                   uint64_t* __restrict__ mask)
 {
-    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t m = (int64_t)bid * 256 + threadIdx.x;
     const bool f = m < nE && (ecode[m] & 0x2A) != 0;
     const uint64_t b = __ballot(f);
     if ((threadIdx.x & 63) == 0 && m < nE) mask[m >> 6] = b;
@@ -473,12 +470,12 @@ __global__ __launch_bounds__(256) void k_neu_mask(int32_t nE, const int32_t* __r
 // ---------------------------------------------------------------------------
 
 namespace {
-__global__ __launch_bounds__(256) void k_refine_nodes(int32_t nC, int32_t ne,
+__device__ inline void d_refine_nodes(int32_t bid, int32_t nC, int32_t ne,
                                                       const double2* __restrict__ xy,
                                                       const int2* __restrict__ edge_nodes,
                                                       double2* __restrict__ xy_f)
 {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t g = (int64_t)bid * 256 + threadIdx.x;
     if (g < nC) {
         xy_f[g] = xy[g];
     } else if (g < (int64_t)nC + ne) {
@@ -490,12 +487,12 @@ __global__ __launch_bounds__(256) void k_refine_nodes(int32_t nC, int32_t ne,
 
 // Children of element m: [M0 M1 M2] at m and [v_i, M_(i+2), M_(i+1)] at
 // nE + 3m + i, with M_i = nC + (edge opposite vertex i).
-__global__ __launch_bounds__(256) void k_refine_elems(int32_t nC, int32_t nE,
+__device__ inline void d_refine_elems(int32_t bid, int32_t nC, int32_t nE,
                                                       const int4* __restrict__ elem4,
                                                       const int32_t* __restrict__ elem_edges,
                                                       int4* __restrict__ el_f)
 {
-    const int32_t m = blockIdx.x * 256 + threadIdx.x;
+    const int32_t m = bid * 256 + threadIdx.x;
     if (m >= nE) return;
     const int4 e = elem4[m];
     const int32_t v[3] = {e.x, e.y, e.z};
@@ -507,12 +504,12 @@ __global__ __launch_bounds__(256) void k_refine_elems(int32_t nC, int32_t nE,
 }
 
 // Listed pair q of edge e: (a, M_e) at q and (M_e, b) at n + q.
-__global__ __launch_bounds__(256) void k_refine_pairs(int32_t nC, int32_t n,
+__device__ inline void d_refine_pairs(int32_t bid, int32_t nC, int32_t n,
                                                       const int2* __restrict__ pairs,
                                                       const int32_t* __restrict__ edges,
                                                       int2* __restrict__ out)
 {
-    const int32_t q = blockIdx.x * 256 + threadIdx.x;
+    const int32_t q = bid * 256 + threadIdx.x;
     if (q >= n) return;
     const int2 ab = pairs[q];
     const int32_t mid = nC + edges[q];
@@ -534,13 +531,13 @@ __global__ __launch_bounds__(256) void k_refine_pairs(int32_t nC, int32_t n,
 // the parent's T+ for halves.
 
 // Fine edges of group e (2 halves + inner edges with e' < e).
-__global__ __launch_bounds__(256) void k_rt_count(int32_t ne_c, const int2* __restrict__ edge_elems_c,
+__device__ inline void d_rt_count(int32_t bid, int32_t ne_c, const int2* __restrict__ edge_elems_c,
                                                   const int8_t* __restrict__ led_c,
                                                   const int8_t* __restrict__ ledTN_c,
                                                   const int32_t* __restrict__ elem_edges_c,
                                                   int32_t* __restrict__ cnt)
 {
-    const int32_t e = blockIdx.x * 256 + threadIdx.x;
+    const int32_t e = bid * 256 + threadIdx.x;
     if (e >= ne_c) return;
     const int2 tt = edge_elems_c[e];
     int32_t c = 2;
@@ -554,7 +551,7 @@ __global__ __launch_bounds__(256) void k_rt_count(int32_t ne_c, const int2* __re
     cnt[e] = c;
 }
 
-__global__ __launch_bounds__(256) void k_rt_emit(
+__device__ inline void d_rt_emit(int32_t bid, 
     int32_t ne_c, int32_t nC_c, int32_t nE_c, const int2* __restrict__ edge_nodes_c,
     const int2* __restrict__ edge_elems_c, const int8_t* __restrict__ led_c,
     const int8_t* __restrict__ ledTN_c, const int32_t* __restrict__ elem_edges_c,
@@ -563,7 +560,7 @@ __global__ __launch_bounds__(256) void k_rt_emit(
     int32_t* __restrict__ elem_edges, int8_t* __restrict__ led, int8_t* __restrict__ ledTN,
     int8_t* __restrict__ etype)
 {
-    const int32_t e = blockIdx.x * 256 + threadIdx.x;
+    const int32_t e = bid * 256 + threadIdx.x;
     if (e >= ne_c) return;
     const int32_t base = off[e], Me = nC_c + e;
     const int2 tt = edge_elems_c[e];
@@ -650,13 +647,13 @@ __global__ __launch_bounds__(256) void k_rt_emit(
 
 // Refined boundary edges in the refined pair order: pair q = (a, b) of parent
 // edge e becomes (a, M_e) at q and (M_e, b) at n + q.
-__global__ __launch_bounds__(256) void k_rt_bnd(int32_t n, const int2* __restrict__ pairs_c,
+__device__ inline void d_rt_bnd(int32_t bid, int32_t n, const int2* __restrict__ pairs_c,
                                                 const int32_t* __restrict__ edges_c,
                                                 const int2* __restrict__ edge_nodes_c,
                                                 const int32_t* __restrict__ off,
                                                 int32_t* __restrict__ edges_f)
 {
-    const int32_t q = blockIdx.x * 256 + threadIdx.x;
+    const int32_t q = bid * 256 + threadIdx.x;
     if (q >= n) return;
     const int32_t e = edges_c[q];
     const int2 ab = pairs_c[q], kl = edge_nodes_c[e];
@@ -700,6 +697,137 @@ static void mesh_free(phf_mesh* m)
 
 namespace {
 // Temporaries of the mesh build, freed on every exit path.
+// ---- launches ---------------------------------------------------------------
+// Steps of a build level that do not depend on each other share one launch:
+// consecutive block ranges run different steps, each block one step (so
+// block-level barriers inside a step stay uniform). On the small levels of a
+// refinement chain the launches, not the bytes, are the cost.
+
+// Refinement, first launch: child coordinates, children, refined boundary
+// pairs, and the fine-edge group sizes (all from the parent's tables).
+struct refine_a_args {
+    int32_t nC_c, ne_c, nE_c, nD_c, nN_c;
+    int32_t b1, b2, b3, b4;  // block range ends: nodes, elements, Dirichlet, Neumann
+    const double2* xy_c;
+    const int2* edge_nodes_c;
+    double2* xy_f;
+    const int4* elem4_c;
+    const int32_t* elem_edges_c;
+    int4* elem4_f;
+    const int2 *dir_pairs_c, *neu_pairs_c;
+    const int32_t *dir_edges_c, *neu_edges_c;
+    int2 *dir_pairs_f, *neu_pairs_f;
+    const int2* edge_elems_c;
+    const int8_t *led_c, *ledTN_c;
+    int32_t* ucount;
+};
+__global__ __launch_bounds__(256) void k_refine_a(refine_a_args a)
+{
+    const int32_t b = blockIdx.x;
+    if (b < a.b1) d_refine_nodes(b, a.nC_c, a.ne_c, a.xy_c, a.edge_nodes_c, a.xy_f);
+    else if (b < a.b2) d_refine_elems(b - a.b1, a.nC_c, a.nE_c, a.elem4_c, a.elem_edges_c, a.elem4_f);
+    else if (b < a.b3) d_refine_pairs(b - a.b2, a.nC_c, a.nD_c, a.dir_pairs_c, a.dir_edges_c, a.dir_pairs_f);
+    else if (b < a.b4) d_refine_pairs(b - a.b3, a.nC_c, a.nN_c, a.neu_pairs_c, a.neu_edges_c, a.neu_pairs_f);
+    else d_rt_count(b - a.b4, a.ne_c, a.edge_elems_c, a.led_c, a.ledTN_c, a.elem_edges_c, a.ucount);
+}
+
+// Refinement, second launch: the fine topology and the boundary edge lists.
+struct refine_b_args {
+    int32_t ne_c, nC_c, nE_c, nD_c, nN_c;
+    int32_t b1, b2;  // block range ends: topology, Dirichlet
+    const int2 *edge_nodes_c, *edge_elems_c;
+    const int8_t *led_c, *ledTN_c, *etype_c;
+    const int32_t* elem_edges_c;
+    const int4* elem4_c;
+    const int32_t* off;
+    int2 *edge_nodes, *edge_elems;
+    int32_t* elem_edges;
+    int8_t *led, *ledTN, *etype;
+    const int2 *dir_pairs_c, *neu_pairs_c;
+    const int32_t *dir_edges_c, *neu_edges_c;
+    int32_t *dir_edges, *neu_edges;
+};
+__global__ __launch_bounds__(256) void k_refine_b(refine_b_args a)
+{
+    const int32_t b = blockIdx.x;
+    if (b < a.b1)
+        d_rt_emit(b, a.ne_c, a.nC_c, a.nE_c, a.edge_nodes_c, a.edge_elems_c, a.led_c, a.ledTN_c,
+                  a.elem_edges_c, a.elem4_c, a.etype_c, a.off, a.edge_nodes, a.edge_elems,
+                  a.elem_edges, a.led, a.ledTN, a.etype);
+    else if (b < a.b2)
+        d_rt_bnd(b - a.b1, a.nD_c, a.dir_pairs_c, a.dir_edges_c, a.edge_nodes_c, a.off, a.dir_edges);
+    else
+        d_rt_bnd(b - a.b2, a.nN_c, a.neu_pairs_c, a.neu_edges_c, a.edge_nodes_c, a.off, a.neu_edges);
+}
+
+// Per-tile boundary counts of the edges (blocks [0, nt)) and the element codes
+// with their per-tile Neumann incidences (the rest).
+struct counts_args {
+    int32_t ne, nE, nt;
+    const int8_t* etype;
+    const int2* edge_elems;
+    const int32_t* mark;
+    phf_cnt2* tiles;
+    int* flags;
+    int4* elem4;
+    const int32_t* elem_edges;
+    const double2* xy;
+    double2* exy;
+    int32_t* ecode;
+    int32_t* etiles;
+};
+__global__ __launch_bounds__(256) void k_counts(counts_args a)
+{
+    const int32_t b = blockIdx.x;
+    if (b < a.nt) d_rows_count(b, a.ne, a.etype, a.edge_elems, a.mark, a.tiles, a.flags);
+    else d_elem_codes(b - a.nt, a.nE, a.elem4, a.elem_edges, a.etype, a.edge_elems, a.xy, a.exy,
+                      a.ecode, a.etiles);
+}
+
+// Both tile scans: block 0 the edge tiles, block 1 the element tiles.
+__global__ __launch_bounds__(1024) void k_tile_scans(int32_t nt, phf_cnt2* __restrict__ tiles,
+                                                     phf_cnt2* __restrict__ total, int32_t ntE,
+                                                     int32_t* __restrict__ etiles)
+{
+    if (blockIdx.x == 0) d_tile_exscan<phf_cnt2>(nt, tiles, total);
+    else d_tile_exscan<int32_t>(ntE, etiles, nullptr);
+}
+
+struct rows_args {
+    int32_t ne, L, nnzC, nnz_dof;
+    const int8_t* etype;
+    const phf_cnt2* tiles;
+    const int2 *edge_nodes, *edge_elems;
+    const int8_t *led, *ledTN;
+    int32_t *edge_row, *red_row, *red_edge, *row_edge;
+    int2* row_nodes;
+    int32_t *C_rowptr, *C_col, *S_rowptr_m, *S_col_m;
+};
+__global__ __launch_bounds__(256) void k_rows(rows_args a)
+{
+    d_rows(blockIdx.x, a.ne, a.etype, a.tiles, a.edge_nodes, a.edge_elems, a.led, a.ledTN,
+           a.edge_row, a.red_row, a.red_edge, a.row_edge, a.row_nodes, a.C_rowptr, a.C_col, a.L,
+           a.nnzC, a.nnz_dof, a.S_rowptr_m, a.S_col_m);
+}
+
+// The saddle DOF rows (blocks [0, ntE)), the C tile bases, the Neumann
+// element mask and the reduced-operator size (a bounded range of blocks).
+struct tail_args {
+    int32_t nE, L, ntE, b1, b2, nred;  // range ends: saddle rows, C tiles, Neumann mask; reduced-count blocks
+    const int32_t *ecode, *etiles, *elem_edges, *edge_row, *C_rowptr;
+    int32_t *S_rowptr, *S_col, *C_tile;
+    uint64_t* neu_mask;
+    unsigned long long* nnzR;
+};
+__global__ __launch_bounds__(256) void k_build_tail(tail_args a)
+{
+    const int32_t b = blockIdx.x;
+    if (b < a.ntE) d_saddle_dof(b, a.nE, a.ecode, a.etiles, a.elem_edges, a.edge_row, a.S_rowptr, a.S_col);
+    else if (b < a.b1) d_c_tiles(b - a.ntE, a.L, a.C_rowptr, a.C_tile);
+    else if (b < a.b2) d_neu_mask(b - a.b1, a.nE, a.ecode, a.neu_mask);
+    else d_reduced_count(b - a.b2, a.nred, a.nE, a.ecode, a.nnzR);
+}
+
 struct build_tmp {
     int32_t* raw = nullptr;
     int32_t* bcount = nullptr;
@@ -793,21 +921,38 @@ int refined_tables(phf_mesh* M, const phf_mesh* P, build_tmp* T, int32_t* ne_out
     TRY(phf_dmalloc(ctx, &M->dir_pairs, nD, "Dirichlet pairs"));
     TRY(phf_dmalloc(ctx, &M->neu_pairs, nN, "Neumann pairs"));
     TRY(phf_dmalloc(ctx, &T->totals, 8, "totals"));
-    PHF_LAUNCH(ctx, "k_refine_nodes", k_refine_nodes, nblk((int64_t)M->nC), 256, 0, nC_c, ne_c,
-               P->xy, P->edge_nodes, M->xy);
-    PHF_LAUNCH(ctx, "k_refine_elems", k_refine_elems, nblk(nE_c), 256, 0, nC_c, nE_c, P->elem4,
-               P->elem_edges, M->elem4);
-    if (P->nD)
-        PHF_LAUNCH(ctx, "k_refine_pairs", k_refine_pairs, nblk(P->nD), 256, 0, nC_c, P->nD,
-                   P->dir_pairs, P->dir_edges, M->dir_pairs);
-    if (P->nN)
-        PHF_LAUNCH(ctx, "k_refine_pairs", k_refine_pairs, nblk(P->nN), 256, 0, nC_c, P->nN,
-                   P->neu_pairs, P->neu_edges, M->neu_pairs);
-    // edge groups per parent edge
     TRY(phf_dmalloc(ctx, &T->ucount, (size_t)ne_c + 1, "group sizes"));
     TRY(phf_dmalloc(ctx, &T->eoff, (size_t)ne_c + 1, "group offsets"));
-    PHF_LAUNCH(ctx, "k_rt_count", k_rt_count, nblk(ne_c), 256, 0, ne_c, P->edge_elems, P->led,
-               P->ledTN, P->elem_edges, T->ucount);
+    {
+        refine_a_args a{};
+        a.nC_c = nC_c;
+        a.ne_c = ne_c;
+        a.nE_c = nE_c;
+        a.nD_c = P->nD;
+        a.nN_c = P->nN;
+        a.b1 = (int32_t)nblk((int64_t)M->nC);
+        a.b2 = a.b1 + (int32_t)nblk(nE_c);
+        a.b3 = a.b2 + (int32_t)nblk(P->nD);
+        a.b4 = a.b3 + (int32_t)nblk(P->nN);
+        a.xy_c = P->xy;
+        a.edge_nodes_c = P->edge_nodes;
+        a.xy_f = M->xy;
+        a.elem4_c = P->elem4;
+        a.elem_edges_c = P->elem_edges;
+        a.elem4_f = M->elem4;
+        a.dir_pairs_c = P->dir_pairs;
+        a.neu_pairs_c = P->neu_pairs;
+        a.dir_edges_c = P->dir_edges;
+        a.neu_edges_c = P->neu_edges;
+        a.dir_pairs_f = M->dir_pairs;
+        a.neu_pairs_f = M->neu_pairs;
+        a.edge_elems_c = P->edge_elems;
+        a.led_c = P->led;
+        a.ledTN_c = P->ledTN;
+        a.ucount = T->ucount;
+        PHF_LAUNCH(ctx, "k_refine_a", k_refine_a, a.b4 + (int32_t)nblk(ne_c), 256, 0, a);
+    }
+    // edge groups per parent edge
     TRY(phf_scan_i32(ctx, T->ucount, T->eoff, ne_c, T->totals));
     M->n_edges = ne;
     TRY(phf_dmalloc(ctx, &M->edge_nodes, ne, "edge nodes"));
@@ -818,15 +963,37 @@ int refined_tables(phf_mesh* M, const phf_mesh* P, build_tmp* T, int32_t* ne_out
     TRY(phf_dmalloc(ctx, &M->edge_type, ne, "edge types"));
     TRY(phf_dmalloc(ctx, &M->dir_edges, nD, "Dirichlet edges"));
     TRY(phf_dmalloc(ctx, &M->neu_edges, nN, "Neumann edges"));
-    PHF_LAUNCH(ctx, "k_rt_emit", k_rt_emit, nblk(ne_c), 256, 0, ne_c, nC_c, nE_c, P->edge_nodes,
-               P->edge_elems, P->led, P->ledTN, P->elem_edges, P->elem4, P->edge_type, T->eoff,
-               M->edge_nodes, M->edge_elems, M->elem_edges, M->led, M->ledTN, M->edge_type);
-    if (P->nD)
-        PHF_LAUNCH(ctx, "k_rt_bnd", k_rt_bnd, nblk(P->nD), 256, 0, P->nD, P->dir_pairs,
-                   P->dir_edges, P->edge_nodes, T->eoff, M->dir_edges);
-    if (P->nN)
-        PHF_LAUNCH(ctx, "k_rt_bnd", k_rt_bnd, nblk(P->nN), 256, 0, P->nN, P->neu_pairs,
-                   P->neu_edges, P->edge_nodes, T->eoff, M->neu_edges);
+    {
+        refine_b_args a{};
+        a.ne_c = ne_c;
+        a.nC_c = nC_c;
+        a.nE_c = nE_c;
+        a.nD_c = P->nD;
+        a.nN_c = P->nN;
+        a.b1 = (int32_t)nblk(ne_c);
+        a.b2 = a.b1 + (int32_t)nblk(P->nD);
+        a.edge_nodes_c = P->edge_nodes;
+        a.edge_elems_c = P->edge_elems;
+        a.led_c = P->led;
+        a.ledTN_c = P->ledTN;
+        a.etype_c = P->edge_type;
+        a.elem_edges_c = P->elem_edges;
+        a.elem4_c = P->elem4;
+        a.off = T->eoff;
+        a.edge_nodes = M->edge_nodes;
+        a.edge_elems = M->edge_elems;
+        a.elem_edges = M->elem_edges;
+        a.led = M->led;
+        a.ledTN = M->ledTN;
+        a.etype = M->edge_type;
+        a.dir_pairs_c = P->dir_pairs;
+        a.neu_pairs_c = P->neu_pairs;
+        a.dir_edges_c = P->dir_edges;
+        a.neu_edges_c = P->neu_edges;
+        a.dir_edges = M->dir_edges;
+        a.neu_edges = M->neu_edges;
+        PHF_LAUNCH(ctx, "k_refine_b", k_refine_b, a.b2 + (int32_t)nblk(P->nN), 256, 0, a);
+    }
     phf_dfree(T->ucount);
     phf_dfree(T->eoff);
     *ne_out = ne;
@@ -913,20 +1080,42 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     }
     // a3: multiplier rows, free rows and C row pointers from the numbers of
     // Dirichlet and Neumann edges before each edge (per-tile counts, their
-    // exclusive scan, then per-edge ballots inside the tile)
-    const int32_t nt = (ne + 255) / 256;
+    // exclusive scan, then per-edge ballots inside the tile). The element
+    // codes and their per-tile Neumann incidences (for the saddle pattern:
+    // the DOF rows of element m start at 15 m - 2 (incidences before m)) go in
+    // the same launches.
+    const int32_t nt = (ne + 255) / 256, ntE = (nE + 255) / 256;
     TRY(phf_dmalloc(ctx, &T.tiles, (size_t)nt, "row tile counts"));
     TRY(phf_dmalloc(ctx, &T.tile_total, 1, "row totals"));
-    PHF_LAUNCH(ctx, "k_rows_count", k_rows_count, nt, 256, 0, ne, M->edge_type, M->edge_elems,
-               parent ? nullptr : T.mark, T.tiles, ctx->d_flags);
+    TRY(phf_dmalloc(ctx, &T.etiles, (size_t)ntE, "element tile counts"));
+    TRY(phf_dmalloc(ctx, &M->exy, 3 * (size_t)nE, "element coordinates"));
+    TRY(phf_dmalloc(ctx, &M->ecode, nE, "element codes"));
+    {
+        counts_args a{};
+        a.ne = ne;
+        a.nE = nE;
+        a.nt = nt;
+        a.etype = M->edge_type;
+        a.edge_elems = M->edge_elems;
+        a.mark = parent ? nullptr : T.mark;
+        a.tiles = T.tiles;
+        a.flags = ctx->d_flags;
+        a.elem4 = M->elem4;
+        a.elem_edges = M->elem_edges;
+        a.xy = M->xy;
+        a.exy = M->exy;
+        a.ecode = M->ecode;
+        a.etiles = T.etiles;
+        PHF_LAUNCH(ctx, "k_counts", k_counts, nt + ntE, 256, 0, a);
+    }
     if (!parent) {
         TRY(read_flags(ctx, &bits, &where));
         TRY(flags_to_status(ctx, bits, where, "boundary"));
     }
     phf_dfree(T.eoff);
     phf_dfree(T.mark);
-    PHF_LAUNCH(ctx, "k_tile_exscan", k_tile_exscan<phf_cnt2>, 1, 1024, 0, nt, T.tiles,
-               T.tile_total);
+    PHF_LAUNCH(ctx, "k_tile_scans", k_tile_scans, 2, 1024, 0, nt, T.tiles, T.tile_total, ntE,
+               T.etiles);
     phf_cnt2 cnt{nD, nN};
     if (!parent) {
         // (every boundary edge of a refined mesh is listed exactly once: the
@@ -943,6 +1132,7 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     if ((int64_t)9 * nE + 2 * M->nnz_C > 0x7fffffffLL)
         return phf_set_error(ctx, PHF_EINVAL, "saddle matrix too large for int32 indices");
     M->nnz_S = (int64_t)9 * nE + 2 * M->nnz_C;
+    const int32_t nnz_dof = 9 * nE + M->nnz_C;  // entries of the saddle DOF rows
 
     TRY(phf_dmalloc(ctx, &M->edge_row, ne, "edge rows"));
     TRY(phf_dmalloc(ctx, &M->red_row, ne, "reduced rows"));
@@ -951,45 +1141,62 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     TRY(phf_dmalloc(ctx, &M->row_nodes, L, "row nodes"));
     TRY(phf_dmalloc(ctx, &M->C_rowptr, (size_t)L + 1, "C rowptr"));
     TRY(phf_dmalloc(ctx, &M->C_col, M->nnz_C, "C columns"));
-    PHF_LAUNCH(ctx, "k_rows", k_rows, nt, 256, 0, ne, M->edge_type, T.tiles, M->edge_nodes,
-               M->edge_elems, M->led, M->ledTN, M->edge_row, M->red_row, M->red_edge,
-               M->row_edge, M->row_nodes, M->C_rowptr, M->C_col);
-    PHF_LAUNCH(ctx, "k_set", k_set_i32, 1, 1, 0, M->C_rowptr + L, (int32_t)M->nnz_C);
-    phf_dfree(T.tiles);
-
-    // element codes and the saddle pattern: the DOF rows of element m start
-    // at 15 m - 2 (Neumann edge incidences of the elements before m)
-    const int32_t ntE = (nE + 255) / 256;
-    TRY(phf_dmalloc(ctx, &T.etiles, (size_t)ntE, "element tile counts"));
-    TRY(phf_dmalloc(ctx, &M->exy, 3 * (size_t)nE, "element coordinates"));
-    TRY(phf_dmalloc(ctx, &M->ecode, nE, "element codes"));
-    PHF_LAUNCH(ctx, "k_elem_codes", k_elem_codes, ntE, 256, 0, nE, M->elem4, M->elem_edges,
-               M->edge_type, M->edge_elems, M->xy, M->exy, M->ecode, T.etiles);
-    PHF_LAUNCH(ctx, "k_tile_exscan", k_tile_exscan<int32_t>, 1, 1024, 0, ntE, T.etiles,
-               (int32_t*)nullptr);
     TRY(phf_dmalloc(ctx, &M->S_rowptr, (size_t)N + L + 1, "saddle rowptr"));
     TRY(phf_dmalloc(ctx, &M->S_col, M->nnz_S, "saddle columns"));
-    PHF_LAUNCH(ctx, "k_saddle_dof", k_saddle_dof, ntE, 256, 0, nE, M->ecode, T.etiles,
-               M->elem_edges, M->edge_row, M->S_rowptr, M->S_col);
-    const int32_t nnz_dof = 9 * nE + M->nnz_C;
-    PHF_LAUNCH(ctx, "k_saddle_mult", k_saddle_mult, nblk(std::max<int64_t>((int64_t)L + 1, M->nnz_C)),
-               256, 0, L, (int32_t)M->nnz_C, nnz_dof, M->C_rowptr, M->C_col, M->S_rowptr + N,
-               M->S_col + nnz_dof);
-    phf_dfree(T.etiles);
+    {
+        rows_args a{};
+        a.ne = ne;
+        a.L = L;
+        a.nnzC = (int32_t)M->nnz_C;
+        a.nnz_dof = nnz_dof;
+        a.etype = M->edge_type;
+        a.tiles = T.tiles;
+        a.edge_nodes = M->edge_nodes;
+        a.edge_elems = M->edge_elems;
+        a.led = M->led;
+        a.ledTN = M->ledTN;
+        a.edge_row = M->edge_row;
+        a.red_row = M->red_row;
+        a.red_edge = M->red_edge;
+        a.row_edge = M->row_edge;
+        a.row_nodes = M->row_nodes;
+        a.C_rowptr = M->C_rowptr;
+        a.C_col = M->C_col;
+        a.S_rowptr_m = M->S_rowptr + N;
+        a.S_col_m = M->S_col + nnz_dof;
+        PHF_LAUNCH(ctx, "k_rows", k_rows, nt, 256, 0, a);
+    }
+    phf_dfree(T.tiles);
 
-    // tile bases of the C row pointers and the Neumann element mask
-    TRY(phf_dmalloc(ctx, &M->C_tile, (size_t)(L + 255) / 256 + 1, "C tile bases"));
-    PHF_LAUNCH(ctx, "k_c_tiles", k_c_tiles, nblk((L + 255) / 256 + 1), 256, 0, L, M->C_rowptr,
-               M->C_tile);
-    TRY(phf_dmalloc(ctx, &M->neu_mask, ((size_t)nE + 63) / 64, "Neumann element mask"));
-    PHF_LAUNCH(ctx, "k_neu_mask", k_neu_mask, nblk(nE), 256, 0, nE, M->ecode, M->neu_mask);
-
-    // size of the reduced operator (read when the mesh info is asked for)
+    // saddle DOF rows, tile bases of the C row pointers, the Neumann element
+    // mask and the size of the reduced operator (read when the mesh info is
+    // asked for)
     const int32_t nf = M->n_free;
+    TRY(phf_dmalloc(ctx, &M->C_tile, (size_t)(L + 255) / 256 + 1, "C tile bases"));
+    TRY(phf_dmalloc(ctx, &M->neu_mask, ((size_t)nE + 63) / 64, "Neumann element mask"));
     TRY(phf_dmalloc(ctx, &M->d_nnzR, 1, "reduced count"));
     PHF_HIP(ctx, hipMemsetAsync(M->d_nnzR, 0, sizeof(unsigned long long), ctx->stream));
-    PHF_LAUNCH(ctx, "k_reduced_count", k_reduced_count, (unsigned)std::min<int64_t>(nblk(nE), 1024),
-               256, 0, nE, M->ecode, M->d_nnzR);
+    {
+        tail_args a{};
+        a.nE = nE;
+        a.L = L;
+        a.ntE = ntE;
+        a.b1 = ntE + (int32_t)nblk((L + 255) / 256 + 1);
+        a.b2 = a.b1 + (int32_t)nblk(nE);
+        a.nred = (int32_t)std::min<int64_t>(nblk(nE), 1024);
+        a.ecode = M->ecode;
+        a.etiles = T.etiles;
+        a.elem_edges = M->elem_edges;
+        a.edge_row = M->edge_row;
+        a.C_rowptr = M->C_rowptr;
+        a.S_rowptr = M->S_rowptr;
+        a.S_col = M->S_col;
+        a.C_tile = M->C_tile;
+        a.neu_mask = M->neu_mask;
+        a.nnzR = M->d_nnzR;
+        PHF_LAUNCH(ctx, "k_build_tail", k_build_tail, a.b2 + a.nred, 256, 0, a);
+    }
+    phf_dfree(T.etiles);
     M->nnz_R = -1;
     // later work on the mesh runs in stream order behind these kernels
     if (!parent) PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
