@@ -104,6 +104,12 @@ int phf_trace_filter(phf_ctx* ctx, const char* kernel);
 int phf_trace_reset(phf_ctx* ctx);
 int phf_trace_query(phf_ctx* ctx, const char* kernel, int64_t* count, double* total_ms);
 int phf_trace_dump(phf_ctx* ctx, char* buf, size_t len);
+/* Per-launch milliseconds of the traced launches named `kernel` (required),
+ * in launch order: up to `cap` values into the host array ms (may be NULL
+ * when cap = 0); *count receives the number recorded since the last reset.
+ * Launches of an iteration that had already converged return at once on the
+ * device and show up here as near-empty launches. */
+int phf_trace_samples(phf_ctx* ctx, const char* kernel, float* ms, int64_t cap, int64_t* count);
 
 /* ---- mesh: upload, validation, topology, patterns ----------------------
  * Section 2.1 (data of Table 1) and Section 2.2 (edge_vec): builds on the

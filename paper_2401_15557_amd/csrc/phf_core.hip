@@ -302,6 +302,15 @@ static int trace_collect(phf_ctx* ctx)
             }
         }
         if (!found) ctx->totals.push_back({std::string(r.name), {1, (double)ms}});
+        found = false;
+        for (auto& t : ctx->samples) {
+            if (t.first == r.name) {
+                t.second.push_back(ms);
+                found = true;
+                break;
+            }
+        }
+        if (!found) ctx->samples.push_back({std::string(r.name), std::vector<float>(1, ms)});
         ctx->event_pool.push_back(r.start);
         ctx->event_pool.push_back(r.stop);
     }
@@ -337,7 +346,24 @@ extern "C" int phf_trace_reset(phf_ctx* ctx)
     if (!ctx) return PHF_EINVAL;
     int rc = trace_collect(ctx);
     ctx->totals.clear();
+    ctx->samples.clear();
     return rc;
+}
+
+extern "C" int phf_trace_samples(phf_ctx* ctx, const char* kernel, float* ms, int64_t cap,
+                                 int64_t* count)
+{
+    if (!ctx || !kernel || cap < 0 || (cap > 0 && !ms)) return PHF_EINVAL;
+    int rc = trace_collect(ctx);
+    if (rc) return rc;
+    int64_t n = 0;
+    for (auto& t : ctx->samples) {
+        if (t.first != kernel) continue;
+        n = (int64_t)t.second.size();
+        for (int64_t i = 0; i < n && i < cap; ++i) ms[i] = t.second[i];
+    }
+    if (count) *count = n;
+    return PHF_OK;
 }
 
 extern "C" int phf_trace_query(phf_ctx* ctx, const char* kernel, int64_t* count, double* total_ms)

@@ -32,6 +32,7 @@ struct phf_ctx {
     std::vector<phf_trace_rec> pending;       // recorded, not yet read
     std::vector<hipEvent_t> event_pool;       // reusable events
     std::vector<std::pair<std::string, std::pair<int64_t, double>>> totals;
+    std::vector<std::pair<std::string, std::vector<float>>> samples;  // per launch, ms
     int* d_flags = nullptr;                   // small device scratch for checks
     int64_t* h_pinned = nullptr;              // pinned host words for readback
     phf_pool* pool = nullptr;                 // caching device allocator

@@ -215,6 +215,9 @@ __global__ __launch_bounds__(NT) void k_ns_gather(int32_t nf, const int32_t* __r
 //              the done flag.
 //   upd(i):    alpha = rz_i / p.q; w += alpha p; r -= alpha q; z = D^-1 r;
 //              partial sums of r.z (into the slot of parity i+1) and r.r.
+//   check(i):  ||r|| of the update against the tolerance (one block); with
+//              the multigrid preconditioner it runs before the V-cycle, so the
+//              cycle of a converged iterate is skipped.
 // Every block reduces the partial-sum arrays itself in the same fixed order,
 // so all blocks see bitwise identical scalars and no kernel writes a value
 // that another block of the same launch reads. The iteration index arrives as
@@ -309,6 +312,7 @@ __global__ __launch_bounds__(NT) void k_cg_init_final(const double* __restrict__
         iflags[2] = 0;
     }
 }
+
 
 // ZT: double, or float where z is the multigrid cycle's single-precision
 // result (converted exactly).
@@ -808,7 +812,10 @@ int phf_ns_cg_iterate(phf_ns* ns, int32_t iters)
                        ns->iflags);
             const phf_mg_top top = phf_mg_top_view(ns->mg);
             PHF_LAUNCH(ctx, "k_cg_upd", k_cg_upd_mg, ns->nbv, NT, 0, ns->nf, it, ns->nbv, ns->w,
-                       ns->r, ns->p, ns->q, ns->part, ns->iflags, top.dinv, top.w, top.bh, top.x);
+                       ns->r, ns->p, ns->q, ns->part, ns->iflags, top.dinv, top.w, top.bh,
+                       top.x);
+            PHF_LAUNCH(ctx, "k_cg_check", k_cg_check, 1, NT, 0, ns->nbv, ns->part, ns->scal,
+                       ns->iflags);
             TRY(phf_mg_apply32(ns->mg, ns->r, true, ns->part + ((it & 1) ? P_RZ0 : P_RZ1) * MAXB,
                                ns->iflags));
         } else {
@@ -819,7 +826,9 @@ int phf_ns_cg_iterate(phf_ns* ns, int32_t iters)
                        ns->r, ns->z, ns->p, ns->q, ns->dinv, ns->part, ns->iflags);
         }
     }
-    PHF_LAUNCH(ctx, "k_cg_check", k_cg_check, 1, NT, 0, ns->nbv, ns->part, ns->scal, ns->iflags);
+    if (!(ns->mg && ns->mg_on))
+        PHF_LAUNCH(ctx, "k_cg_check", k_cg_check, 1, NT, 0, ns->nbv, ns->part, ns->scal,
+                   ns->iflags);
     return PHF_OK;
 }
 

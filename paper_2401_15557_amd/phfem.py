@@ -36,7 +36,7 @@ EXPORTED = (
     "phf_create", "phf_destroy", "phf_set_stream", "phf_synchronize", "phf_mem_stats",
     "phf_release_cache", "phf_status_str",
     "phf_last_error", "phf_version", "phf_trace_enable", "phf_trace_filter", "phf_trace_reset", "phf_trace_query",
-    "phf_trace_dump", "phf_mesh_create", "phf_mesh_destroy", "phf_mesh_refine", "phf_mesh_geometry",
+    "phf_trace_dump", "phf_trace_samples", "phf_mesh_create", "phf_mesh_destroy", "phf_mesh_refine", "phf_mesh_geometry",
     "phf_mesh_get_info",
     "phf_mesh_topology", "phf_mesh_pattern", "phf_assemble", "phf_spmv", "phf_solve",
     "phf_cn_create", "phf_cn_set_state", "phf_cn_run", "phf_cn_get_state", "phf_cn_destroy",
@@ -160,6 +160,8 @@ _SIGS = {
     "phf_trace_reset": [_VP],
     "phf_trace_query": [_VP, ctypes.c_char_p, ctypes.POINTER(_I64), ctypes.POINTER(_D)],
     "phf_trace_dump": [_VP, ctypes.c_char_p, ctypes.c_size_t],
+    "phf_trace_samples": [_VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_float), ctypes.c_int64,
+                          ctypes.POINTER(ctypes.c_int64)],
     "phf_mesh_create": [_VP, _VP, _I32, _VP, _I32, _VP, _I32, _VP, _I32, ctypes.c_int,
                         ctypes.POINTER(_VP)],
     "phf_mesh_destroy": [_VP],
@@ -308,6 +310,15 @@ def phf_trace_query(ctx, kernel=None):
     _call("phf_trace_query", ctx, ctx, kernel.encode() if kernel else None, ctypes.byref(c),
           ctypes.byref(ms))
     return c.value, ms.value
+
+
+def phf_trace_samples(ctx, kernel):
+    """Per-launch milliseconds of the traced launches named ``kernel``."""
+    n = _I64()
+    _call("phf_trace_samples", ctx, ctx, kernel.encode(), None, 0, ctypes.byref(n))
+    buf = (ctypes.c_float * max(n.value, 1))()
+    _call("phf_trace_samples", ctx, ctx, kernel.encode(), buf, n.value, ctypes.byref(n))
+    return [float(buf[i]) for i in range(n.value)]
 
 
 def phf_trace_dump(ctx):
