@@ -58,6 +58,33 @@ struct phf_mg_dev_level {
     const float* w = nullptr;          // sweep weights (PHF_MG_WSTRIDE)
 };
 
+// One level's entry in the table that drives the set-up launches over all
+// levels (built once per hierarchy).
+struct phf_mg_setup_level {
+    int32_t nf = 0, nEc = 0, nc = 0;  // own free rows; next coarser level's elements, free rows
+    // first blocks: prolongation, restriction rows, gather map (levels >= 1);
+    // scaled rows (every level)
+    int32_t b[4] = {0, 0, 0, 0};
+    const int32_t* red_edge = nullptr;  // this level's mesh tables
+    const int2* edge_elems = nullptr;
+    const int8_t *led = nullptr, *ledTN = nullptr;
+    const int32_t *elem_edges = nullptr, *red_row = nullptr;
+    const int32_t *elem_edges_c = nullptr, *red_row_c = nullptr, *red_edge_c = nullptr;  // coarser
+    const int2* edge_elems_c = nullptr;
+    const int8_t *led_c = nullptr, *ledTN_c = nullptr;
+    int32_t* P_col = nullptr;  // outputs of the tables
+    float* P_val = nullptr;
+    int32_t* rows9 = nullptr;
+    int2* sel_c = nullptr;
+    const double* B = nullptr;  // operator: element blocks (coarse levels) or
+    const int32_t* ell_col = nullptr;  // the caller's double-precision rows (finest)
+    const double* ell_val = nullptr;
+    int32_t* col4 = nullptr;  // the cycle's scaled rows
+    float *val4 = nullptr, *diag = nullptr, *dinv = nullptr;
+    int32_t* col64 = nullptr;  // coarsest level with a dense inverse
+    double* val64 = nullptr;
+};
+
 struct phf_mg_level {
     phf_mesh* mesh = nullptr;
     phf_ns* ns = nullptr;       // the caller's operator (finest level only)
@@ -96,6 +123,9 @@ struct phf_mg {
     int32_t tail_top = -1;   // levels 0..tail_top run in the single-workgroup kernel
     phf_mg_dev_level h_lv[PHF_MG_MAX_LEVELS];
     phf_mg_dev_level* d_lv = nullptr;
+    phf_mg_setup_level h_setup[PHF_MG_MAX_LEVELS];
+    phf_mg_setup_level* d_setup = nullptr;
+    int32_t setup_table_blocks = 0, setup_row_blocks = 0;
     int32_t nu = 2;          // sweeps before and after the coarse correction
     int32_t smoother = 0;    // PHF_MG_SMOOTH_JACOBI or PHF_MG_SMOOTH_CHEBYSHEV
     double omega = 0.8;      // Jacobi damping

@@ -24,14 +24,6 @@ __device__ inline int32_t parent_of(int32_t m, int32_t nEc)
     return m < nEc ? m : (m - nEc) / 3;
 }
 
-__global__ __launch_bounds__(NT) void k_mg_coef(int32_t nEc, const double* __restrict__ aT_f,
-                                                double* __restrict__ aT_c)
-{
-    const int32_t p = blockIdx.x * NT + threadIdx.x;
-    if (p >= nEc) return;
-    const int64_t c = nEc + 3 * (int64_t)p;
-    aT_c[p] = 0.25 * (aT_f[p] + aT_f[c] + aT_f[c + 1] + aT_f[c + 2]);
-}
 
 // Prolongation row of fine free edge rf: the coarse CR function at the fine
 // edge midpoint, averaged over the (one or two) coarse triangles containing it.
@@ -47,13 +39,12 @@ __global__ __launch_bounds__(NT) void k_mg_coef(int32_t nEc, const double* __res
 // The fine edge's two triangles give the sides (a half of an interior coarse
 // edge lies in two coarse triangles, weighted 1/2 each); columns are merged
 // in side, then coarse-local-edge order.
-__global__ __launch_bounds__(NT) void k_mg_prolong_build(
+__device__ inline void d_mg_prolong_build(int32_t rf, 
     int32_t nf_f, int32_t nEc, const int32_t* __restrict__ red_edge_f,
     const int2* __restrict__ edge_elems_f, const int8_t* __restrict__ led_f,
     const int8_t* __restrict__ ledTN_f, const int32_t* __restrict__ elem_edges_c,
     const int32_t* __restrict__ red_row_c, int32_t* __restrict__ P_col, float* __restrict__ P_val)
 {
-    const int32_t rf = blockIdx.x * NT + threadIdx.x;
     if (rf >= nf_f) return;
     const int32_t e = red_edge_f[rf];
     const int2 tt = edge_elems_f[e];
@@ -109,11 +100,10 @@ __global__ __launch_bounds__(NT) void k_mg_prolong_build(
 //   slot 4 + 2i         half of coarse edge i+2 at vertex v_i.
 // The centre child of p is element p = [M0 M1 M2], corner child i is
 // nEc + 3p + i = [v_i M_(i+2) M_(i+1)] (M_j the midpoint of coarse edge j).
-__global__ __launch_bounds__(NT) void k_mg_rows9(int32_t nEc, const int32_t* __restrict__ elem_edges_f,
+__device__ inline void d_mg_rows9(int32_t p, int32_t nEc, const int32_t* __restrict__ elem_edges_f,
                                                  const int32_t* __restrict__ red_row_f,
                                                  int32_t* __restrict__ rows9)
 {
-    const int32_t p = blockIdx.x * NT + threadIdx.x;
     if (p >= nEc) return;
     for (int j = 0; j < 3; ++j)
         rows9[(int64_t)j * nEc + p] = red_row_f[elem_edges_f[3 * (int64_t)p + j]];
@@ -126,13 +116,12 @@ __global__ __launch_bounds__(NT) void k_mg_rows9(int32_t nEc, const int32_t* __r
 
 // For coarse free row c: positions in the per-triangle restriction sums of
 // its edge seen from T+ and from T- (-1 on the boundary).
-__global__ __launch_bounds__(NT) void k_mg_sel(int32_t nc, const int32_t* __restrict__ red_edge_c,
+__device__ inline void d_mg_sel(int32_t c, int32_t nc, const int32_t* __restrict__ red_edge_c,
                                                const int2* __restrict__ edge_elems_c,
                                                const int8_t* __restrict__ led_c,
                                                const int8_t* __restrict__ ledTN_c,
                                                int2* __restrict__ sel)
 {
-    const int32_t c = blockIdx.x * NT + threadIdx.x;
     if (c >= nc) return;
     const int32_t e = red_edge_c[c];
     const int2 tt = edge_elems_c[e];
@@ -310,8 +299,11 @@ __device__ inline void row_coarse(int32_t i, int32_t n, const double* __restrict
 // lambda_i and the unit mass M_T = |T|/12 (1 + delta_ij) (Definition 3.1),
 // straight from the element coordinates. The tile's blocks are staged in LDS
 // and stored coalesced.
+// aT_f: the next finer level's triangle coefficient (null: 1); the level's
+// own, the average over the four children, is written to aT.
 __global__ __launch_bounds__(NT) void k_mg_cblocks(int32_t nE, const double2* __restrict__ exy,
-                                                   const double* __restrict__ aT, double A00,
+                                                   const double* __restrict__ aT_f,
+                                                   double* __restrict__ aT, double A00,
                                                    double A01, double A10, double A11, double cK,
                                                    double cM, double* __restrict__ B)
 {
@@ -326,7 +318,13 @@ __global__ __launch_bounds__(NT) void k_mg_cblocks(int32_t nE, const double2* __
         const double gx[3] = {P1.y - P2.y, P2.y - P0.y, P0.y - P1.y};
         const double gy[3] = {P2.x - P1.x, P0.x - P2.x, P1.x - P0.x};
         const double det = (P1.x - P0.x) * (P2.y - P0.y) - (P2.x - P0.x) * (P1.y - P0.y);
-        const double s = (aT ? aT[m] : 1.0) / (2.0 * det);
+        double a = 1.0;
+        if (aT_f) {
+            const int64_t c = nE + 3 * m;
+            a = 0.25 * (aT_f[m] + aT_f[c] + aT_f[c + 1] + aT_f[c + 2]);
+            aT[m] = a;
+        }
+        const double s = a / (2.0 * det);
         const double mass = det / 24.0;  // |T| / 12
         double A[9];
 #pragma unroll
@@ -360,7 +358,7 @@ __global__ __launch_bounds__(NT) void k_mg_cblocks(int32_t nE, const double2* __
 // rows (off-diagonals of D^-1 A in ELL-4, the diagonal and its inverse, as
 // k_mg_scale computes them from the double-precision rows). With col64 and
 // val64 (the coarsest level) also the double-precision ELL-5 rows.
-__global__ __launch_bounds__(NT) void k_mg_crows(
+__device__ inline void d_mg_crows(int32_t r, 
     int32_t nf, const int32_t* __restrict__ red_edge, const int2* __restrict__ edge_elems,
     const int8_t* __restrict__ led, const int8_t* __restrict__ ledTN,
     const int32_t* __restrict__ elem_edges, const int32_t* __restrict__ red_row,
@@ -368,7 +366,6 @@ __global__ __launch_bounds__(NT) void k_mg_crows(
     float* __restrict__ diag, float* __restrict__ dinv, int32_t* __restrict__ col64,
     double* __restrict__ val64)
 {
-    const int32_t r = blockIdx.x * NT + threadIdx.x;
     if (r >= nf) return;
     int32_t col[5], s0[5], s1[5];
     const int n = phf_reduced_entries(red_edge[r], edge_elems, led, ledTN, elem_edges, red_row,
@@ -404,14 +401,13 @@ __global__ __launch_bounds__(NT) void k_mg_crows(
 // Single-precision scaled copy of a level's operator: off-diagonal entries
 // of row r divided by its diagonal a_rr (1 where a_rr <= 0, as for the
 // double-precision inverse diagonal), the diagonal and its inverse.
-__global__ __launch_bounds__(NT) void k_mg_scale(int32_t n, const int32_t* __restrict__ col,
-                                                 const double* __restrict__ val,
-                                                 int32_t* __restrict__ col4,
-                                                 float* __restrict__ val4,
-                                                 float* __restrict__ diag,
-                                                 float* __restrict__ dinv)
+__device__ inline void d_mg_scale(int32_t r, int32_t n, const int32_t* __restrict__ col,
+                                  const double* __restrict__ val, int32_t* __restrict__ col4,
+                                  float* __restrict__ val4, float* __restrict__ diag,
+                                  float* __restrict__ dinv)
 {
-    for (int32_t r = blockIdx.x * NT + threadIdx.x; r < n; r += gridDim.x * NT) {
+    if (r >= n) return;
+    {
         double d = 0.0;
         int32_t c4[4] = {r, r, r, r};
         double v4[4] = {0.0, 0.0, 0.0, 0.0};
@@ -643,29 +639,6 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
     }
 }
 
-// Gershgorin bound of D^-1 A on one level: max over rows of
-// 1 + sum_j |a_ij| / a_ii (the off-diagonal slots of the scaled rows),
-// merged into *lmax as the bits of a non-negative float (which order like
-// unsigned integers).
-__global__ __launch_bounds__(NT) void k_mg_gersh(int32_t n, const float* __restrict__ val,
-                                                 uint32_t* __restrict__ lmax)
-{
-    __shared__ float sh[NT];
-    float m = 0.0f;
-    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-        float s = 1.0f;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s += fabsf(val[(int64_t)k * n + i]);
-        m = fmaxf(m, s);
-    }
-    sh[threadIdx.x] = m;
-    __syncthreads();
-    for (int h = NT / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + h]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicMax(lmax, __float_as_uint(sh[0]));
-}
 
 __global__ void k_mg_lmax_clear(int32_t nlev, uint32_t* __restrict__ lmax)
 {
@@ -694,6 +667,70 @@ __global__ void k_mg_weights(int32_t nlev, int32_t nu, int32_t cheb, float omega
     for (int k = 0; k < PHF_MG_MAX_SWEEPS; ++k)
         w[k] = k < nu ? (float)(1.0 / (c + h * cos(M_PI * (2 * k + 1) / (2.0 * nu)))) : 0.0f;
     w[PHF_MG_MAX_SWEEPS] = (float)(1.0 / c);
+}
+
+// ---- set-up launches over all levels ------------------------------------
+// Every level's prolongation, restriction rows and coarse gather map (one
+// launch), and every level's scaled single-precision rows with the Gershgorin
+// bound (one launch): consecutive block ranges per level and table, found by
+// each block from the level table.
+__device__ inline int find_level(const phf_mg_setup_level* lv, int32_t nlev, int32_t b, int part)
+{
+    int l = nlev - 1;
+    while (l > 0 && b < lv[l].b[part]) --l;
+    return l;
+}
+
+__global__ __launch_bounds__(NT) void k_mg_setup_tables(const phf_mg_setup_level* __restrict__ lv,
+                                                        int32_t nlev)
+{
+    const int32_t b = blockIdx.x;
+    // ranges in order: level 1..nlev-1, each prolongation | rows9 | gather map
+    const int l = find_level(lv, nlev, b, 0);
+    const phf_mg_setup_level& L = lv[l];
+    if (l == 0) return;
+    const int32_t t = threadIdx.x;
+    if (b < L.b[1]) {
+        d_mg_prolong_build((b - L.b[0]) * NT + t, L.nf, L.nEc, L.red_edge, L.edge_elems, L.led,
+                           L.ledTN, L.elem_edges_c, L.red_row_c, L.P_col, L.P_val);
+    } else if (b < L.b[2]) {
+        d_mg_rows9((b - L.b[1]) * NT + t, L.nEc, L.elem_edges, L.red_row, L.rows9);
+    } else {
+        d_mg_sel((b - L.b[2]) * NT + t, L.nc, L.red_edge_c, L.edge_elems_c, L.led_c, L.ledTN_c,
+                 L.sel_c);
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_mg_setup_rows(const phf_mg_setup_level* __restrict__ lv,
+                                                      int32_t nlev, int32_t gersh,
+                                                      uint32_t* __restrict__ lmax)
+{
+    __shared__ float sh[NT];
+    const int l = find_level(lv, nlev, blockIdx.x, 3);
+    const phf_mg_setup_level& L = lv[l];
+    const int32_t r = (blockIdx.x - L.b[3]) * NT + threadIdx.x;
+    if (L.B)
+        d_mg_crows(r, L.nf, L.red_edge, L.edge_elems, L.led, L.ledTN, L.elem_edges, L.red_row,
+                   L.B, L.col4, L.val4, L.diag, L.dinv, L.col64, L.val64);
+    else
+        d_mg_scale(r, L.nf, L.ell_col, L.ell_val, L.col4, L.val4, L.diag, L.dinv);
+    if (!gersh) return;
+    // Gershgorin bound of D^-1 A: max over rows of 1 + sum_j |a_ij| / a_ii,
+    // merged into lmax[l] as the bits of a non-negative float (which order
+    // like unsigned integers)
+    float m = 0.0f;
+    if (r < L.nf) {
+        m = 1.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) m += fabsf(L.val4[(int64_t)k * L.nf + r]);
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(lmax + l, __float_as_uint(sh[0]));
 }
 
 unsigned grid_for(int32_t n) { return (unsigned)std::min<int64_t>(std::max<int64_t>(nblk(n), 1), 1024); }
@@ -748,6 +785,7 @@ void phf_mg_destroy(phf_mg* mg)
     phf_dfree(mg->col64);
     phf_dfree(mg->val64);
     phf_dfree(mg->d_lv);
+    phf_dfree(mg->d_setup);
     phf_dfree(mg->lmax);
     phf_dfree(mg->wts);
     delete mg;
@@ -794,20 +832,11 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             phf_mg_level& Cl = mg->lev[l - 1];
             TRY(phf_dmalloc(ctx, &L.P_col, 5 * nf, "multigrid P columns"));
             TRY(phf_dmalloc(ctx, &L.P_val, 5 * nf, "multigrid P values"));
-            if (L.nf > 0)
-                PHF_LAUNCH(ctx, "k_mg_prolong_build", k_mg_prolong_build, nblk(L.nf), NT, 0, L.nf,
-                           Cl.mesh->nE, ms->red_edge, ms->edge_elems, ms->led, ms->ledTN,
-                           Cl.mesh->elem_edges, Cl.mesh->red_row, L.P_col, L.P_val);
             // restriction tables
             const int32_t nEc = Cl.mesh->nE, nc = Cl.mesh->n_free;
             TRY(phf_dmalloc(ctx, &L.rows9, 9 * (size_t)nEc, "multigrid restriction rows"));
             TRY(phf_dmalloc(ctx, &L.t, 3 * (size_t)nEc, "multigrid restriction sums"));
             TRY(phf_dmalloc(ctx, &Cl.sel, (size_t)std::max(nc, 1), "multigrid restriction map"));
-            PHF_LAUNCH(ctx, "k_mg_rows9", k_mg_rows9, nblk(nEc), NT, 0, nEc, ms->elem_edges,
-                       ms->red_row, L.rows9);
-            if (nc > 0)
-                PHF_LAUNCH(ctx, "k_mg_sel", k_mg_sel, nblk(nc), NT, 0, nc, Cl.mesh->red_edge,
-                           Cl.mesh->edge_elems, Cl.mesh->led, Cl.mesh->ledTN, Cl.sel);
         }
         mg->n0 = mg->lev[0].nf;
         if (mg->n0 > 0 && mg->n0 <= PHF_MG_DENSE_MAX) {
@@ -848,6 +877,71 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
         TRY(phf_dmalloc(ctx, &mg->d_lv, (size_t)mg->tail_top + 1, "multigrid level table"));
         PHF_HIP(ctx, hipMemcpyAsync(mg->d_lv, mg->h_lv, sizeof(phf_mg_dev_level) * (mg->tail_top + 1),
                                     hipMemcpyHostToDevice, ctx->stream));
+        // set-up table: per level the mesh tables, outputs and block ranges
+        int32_t blk = 0;
+        for (int l = 0; l < nlev; ++l) {
+            const phf_mg_level& L = mg->lev[l];
+            const phf_mesh* ms = L.mesh;
+            phf_mg_setup_level& d = mg->h_setup[l];
+            d.nf = L.nf;
+            d.red_edge = ms->red_edge;
+            d.edge_elems = ms->edge_elems;
+            d.led = ms->led;
+            d.ledTN = ms->ledTN;
+            d.elem_edges = ms->elem_edges;
+            d.red_row = ms->red_row;
+            d.col4 = L.col4;
+            d.val4 = L.val4;
+            d.diag = L.diag32;
+            d.dinv = L.dinv32;
+            if (l == nlev - 1) {
+                d.ell_col = fine->ell_col;
+                d.ell_val = fine->ell_val;
+            } else {
+                d.B = L.B;
+            }
+            if (l == 0 && mg->cinv) {
+                d.col64 = mg->col64;
+                d.val64 = mg->val64;
+            }
+            if (l == 0) {
+                d.b[0] = d.b[1] = d.b[2] = blk;
+                continue;
+            }
+            const phf_mg_level& Cl = mg->lev[l - 1];
+            const phf_mesh* mc = Cl.mesh;
+            d.nEc = mc->nE;
+            d.nc = Cl.nf;
+            d.elem_edges_c = mc->elem_edges;
+            d.red_row_c = mc->red_row;
+            d.red_edge_c = mc->red_edge;
+            d.edge_elems_c = mc->edge_elems;
+            d.led_c = mc->led;
+            d.ledTN_c = mc->ledTN;
+            d.P_col = L.P_col;
+            d.P_val = L.P_val;
+            d.rows9 = L.rows9;
+            d.sel_c = Cl.sel;
+            d.b[0] = blk;
+            blk += (int32_t)nblk(L.nf);
+            d.b[1] = blk;
+            blk += (int32_t)nblk(d.nEc);
+            d.b[2] = blk;
+            blk += (int32_t)nblk(d.nc);
+        }
+        mg->setup_table_blocks = blk;
+        blk = 0;
+        for (int l = 0; l < nlev; ++l) {
+            mg->h_setup[l].b[3] = blk;
+            blk += (int32_t)nblk(mg->lev[l].nf);
+        }
+        mg->setup_row_blocks = blk;
+        TRY(phf_dmalloc(ctx, &mg->d_setup, (size_t)nlev, "multigrid set-up table"));
+        PHF_HIP(ctx, hipMemcpyAsync(mg->d_setup, mg->h_setup, sizeof(phf_mg_setup_level) * nlev,
+                                    hipMemcpyHostToDevice, ctx->stream));
+        if (mg->setup_table_blocks > 0)
+            PHF_LAUNCH(ctx, "k_mg_setup_tables", k_mg_setup_tables, mg->setup_table_blocks, NT, 0,
+                       mg->d_setup, nlev);
         return PHF_OK;
     };
     int rc = body();
@@ -864,47 +958,25 @@ int phf_mg_numeric(phf_mg* mg, const phf_coeffs* co, double cK, double cM)
 {
     phf_ctx* ctx = mg->lev[0].mesh->ctx;
     const int top = mg->nlev - 1;
-    // triangle coefficients, finest to coarsest
+    // coarse levels, finest to coarsest: the triangle coefficient averaged
+    // over the four children and the element blocks of the re-discretised
+    // operator (no convection)
     const double* aT_prev = co->a_T;
     for (int l = top - 1; l >= 0; --l) {
         phf_mg_level& L = mg->lev[l];
-        if (aT_prev) {
-            PHF_LAUNCH(ctx, "k_mg_coef", k_mg_coef, nblk(L.mesh->nE), NT, 0, L.mesh->nE, aT_prev,
-                       L.aT);
-            aT_prev = L.aT;
-        }
-    }
-    // coarse levels: the re-discretised operator (no convection) straight
-    // into the cycle's scaled single-precision rows
-    for (int l = 0; l < top; ++l) {
-        phf_mg_level& L = mg->lev[l];
         const phf_mesh* ms = L.mesh;
         PHF_LAUNCH(ctx, "k_mg_cblocks", k_mg_cblocks, nblk(ms->nE), NT, 0, ms->nE, ms->exy,
-                   co->a_T ? L.aT : nullptr, co->A[0], co->A[1], co->A[2], co->A[3], cK, cM, L.B);
-        if (L.nf == 0) continue;
-        const bool c64 = l == 0 && mg->cinv;
-        PHF_LAUNCH(ctx, "k_mg_crows", k_mg_crows, nblk(L.nf), NT, 0, L.nf, ms->red_edge,
-                   ms->edge_elems, ms->led, ms->ledTN, ms->elem_edges, ms->red_row, L.B, L.col4,
-                   L.val4, L.diag32, L.dinv32, c64 ? mg->col64 : nullptr,
-                   c64 ? mg->val64 : nullptr);
+                   aT_prev, L.aT, co->A[0], co->A[1], co->A[2], co->A[3], cK, cM, L.B);
+        if (aT_prev) aT_prev = L.aT;
     }
-    // finest level: from the operator the caller built
-    {
-        phf_mg_level& L = mg->lev[top];
-        if (L.nf > 0)
-            PHF_LAUNCH(ctx, "k_mg_scale", k_mg_scale, grid_for(L.nf), NT, 0, L.nf, L.ns->ell_col,
-                       L.ns->ell_val, L.col4, L.val4, L.diag32, L.dinv32);
-    }
-    // sweep weights
+    // every level's scaled single-precision rows (coarse levels from their
+    // blocks, the finest from the operator the caller built) and, for the
+    // Chebyshev weights, their Gershgorin bounds
     const bool cheb = mg->smoother == PHF_MG_SMOOTH_CHEBYSHEV;
     PHF_LAUNCH(ctx, "k_mg_lmax_clear", k_mg_lmax_clear, 1, PHF_MG_MAX_LEVELS, 0, mg->nlev, mg->lmax);
-    if (cheb)
-        for (int l = 0; l <= top; ++l) {
-            phf_mg_level& L = mg->lev[l];
-            if (L.nf == 0) continue;
-            PHF_LAUNCH(ctx, "k_mg_gersh", k_mg_gersh, grid_for(L.nf), NT, 0, L.nf, L.val4,
-                       mg->lmax + l);
-        }
+    if (mg->setup_row_blocks > 0)
+        PHF_LAUNCH(ctx, "k_mg_setup_rows", k_mg_setup_rows, mg->setup_row_blocks, NT, 0,
+                   mg->d_setup, mg->nlev, cheb ? 1 : 0, mg->lmax);
     PHF_LAUNCH(ctx, "k_mg_weights", k_mg_weights, 1, PHF_MG_MAX_LEVELS, 0, mg->nlev, mg->nu,
                cheb ? 1 : 0, (float)mg->omega, (float)mg->range, mg->lmax, mg->wts);
     if (mg->cinv) {
