@@ -708,22 +708,24 @@ __global__ __launch_bounds__(NT) void k_mg_setup_rows(const phf_mg_setup_level* 
     __shared__ float sh[NT];
     const int l = find_level(lv, nlev, blockIdx.x, 3);
     const phf_mg_setup_level& L = lv[l];
-    const int32_t r = (blockIdx.x - L.b[3]) * NT + threadIdx.x;
-    if (L.B)
-        d_mg_crows(r, L.nf, L.red_edge, L.edge_elems, L.led, L.ledTN, L.elem_edges, L.red_row,
-                   L.B, L.col4, L.val4, L.diag, L.dinv, L.col64, L.val64);
-    else
-        d_mg_scale(r, L.nf, L.ell_col, L.ell_val, L.col4, L.val4, L.diag, L.dinv);
+    // a level has at most 1024 blocks (few atomics on its bound); each loops
+    const int32_t nb = (l + 1 < nlev ? lv[l + 1].b[3] : gridDim.x) - L.b[3];
+    float m = 0.0f;  // Gershgorin bound of D^-1 A over this block's rows
+    for (int32_t r = (blockIdx.x - L.b[3]) * NT + threadIdx.x; r < L.nf; r += nb * NT) {
+        if (L.B)
+            d_mg_crows(r, L.nf, L.red_edge, L.edge_elems, L.led, L.ledTN, L.elem_edges,
+                       L.red_row, L.B, L.col4, L.val4, L.diag, L.dinv, L.col64, L.val64);
+        else
+            d_mg_scale(r, L.nf, L.ell_col, L.ell_val, L.col4, L.val4, L.diag, L.dinv);
+        // 1 + sum_j |a_ij| / a_ii
+        float s = 1.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s += fabsf(L.val4[(int64_t)k * L.nf + r]);
+        m = fmaxf(m, s);
+    }
     if (!gersh) return;
-    // Gershgorin bound of D^-1 A: max over rows of 1 + sum_j |a_ij| / a_ii,
     // merged into lmax[l] as the bits of a non-negative float (which order
     // like unsigned integers)
-    float m = 0.0f;
-    if (r < L.nf) {
-        m = 1.0f;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) m += fabsf(L.val4[(int64_t)k * L.nf + r]);
-    }
     sh[threadIdx.x] = m;
     __syncthreads();
     for (int h = NT / 2; h > 0; h >>= 1) {
@@ -933,7 +935,7 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
         blk = 0;
         for (int l = 0; l < nlev; ++l) {
             mg->h_setup[l].b[3] = blk;
-            blk += (int32_t)nblk(mg->lev[l].nf);
+            blk += (int32_t)std::min<int64_t>(nblk(mg->lev[l].nf), 1024);
         }
         mg->setup_row_blocks = blk;
         TRY(phf_dmalloc(ctx, &mg->d_setup, (size_t)nlev, "multigrid set-up table"));
