@@ -362,9 +362,11 @@ __device__ inline void d_elem_codes(int32_t bid, int32_t nE, int4* __restrict__ 
         e.w = code;
         elem4[m] = e;
         ecode[m] = code;
-        exy[3 * (int64_t)m] = xy[e.x];
-        exy[3 * (int64_t)m + 1] = xy[e.y];
-        exy[3 * (int64_t)m + 2] = xy[e.z];
+        if (xy) {  // (a refined mesh has its element coordinates already)
+            exy[3 * (int64_t)m] = xy[e.x];
+            exy[3 * (int64_t)m + 1] = xy[e.y];
+            exy[3 * (int64_t)m + 2] = xy[e.z];
+        }
     }
     const int32_t tot = phf_block_sum_i32<256>(nneu, sh);
     if (threadIdx.x == 0) tiles[bid] = tot;
@@ -487,10 +489,15 @@ __device__ inline void d_refine_nodes(int32_t bid, int32_t nC, int32_t ne,
 
 // Children of element m: [M0 M1 M2] at m and [v_i, M_(i+2), M_(i+1)] at
 // nE + 3m + i, with M_i = nC + (edge opposite vertex i).
+// Also the children's element-major coordinates from the parent's: the
+// midpoint of the edge opposite v_i is 0.5 (P_(i+1) + P_(i+2)), the value the
+// refined node gets (the sum is the same in either order).
 __device__ inline void d_refine_elems(int32_t bid, int32_t nC, int32_t nE,
                                                       const int4* __restrict__ elem4,
                                                       const int32_t* __restrict__ elem_edges,
-                                                      int4* __restrict__ el_f)
+                                                      const double2* __restrict__ exy,
+                                                      int4* __restrict__ el_f,
+                                                      double2* __restrict__ exy_f)
 {
     const int32_t m = bid * 256 + threadIdx.x;
     if (m >= nE) return;
@@ -501,6 +508,19 @@ __device__ inline void d_refine_elems(int32_t bid, int32_t nC, int32_t nE,
     el_f[m] = make_int4(M[0], M[1], M[2], 0);
     for (int i = 0; i < 3; ++i)
         el_f[(int64_t)nE + 3 * (int64_t)m + i] = make_int4(v[i], M[(i + 2) % 3], M[(i + 1) % 3], 0);
+    double2 P[3], Q[3];
+    for (int i = 0; i < 3; ++i) P[i] = exy[3 * (int64_t)m + i];
+    for (int i = 0; i < 3; ++i) {
+        const double2 a = P[(i + 1) % 3], b = P[(i + 2) % 3];
+        Q[i] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y + b.y));
+    }
+    for (int i = 0; i < 3; ++i) exy_f[3 * (int64_t)m + i] = Q[i];
+    for (int i = 0; i < 3; ++i) {
+        const int64_t c = 3 * ((int64_t)nE + 3 * (int64_t)m + i);
+        exy_f[c] = P[i];
+        exy_f[c + 1] = Q[(i + 2) % 3];
+        exy_f[c + 2] = Q[(i + 1) % 3];
+    }
 }
 
 // Listed pair q of edge e: (a, M_e) at q and (M_e, b) at n + q.
@@ -713,7 +733,9 @@ struct refine_a_args {
     double2* xy_f;
     const int4* elem4_c;
     const int32_t* elem_edges_c;
+    const double2* exy_c;
     int4* elem4_f;
+    double2* exy_f;
     const int2 *dir_pairs_c, *neu_pairs_c;
     const int32_t *dir_edges_c, *neu_edges_c;
     int2 *dir_pairs_f, *neu_pairs_f;
@@ -725,7 +747,9 @@ __global__ __launch_bounds__(256) void k_refine_a(refine_a_args a)
 {
     const int32_t b = blockIdx.x;
     if (b < a.b1) d_refine_nodes(b, a.nC_c, a.ne_c, a.xy_c, a.edge_nodes_c, a.xy_f);
-    else if (b < a.b2) d_refine_elems(b - a.b1, a.nC_c, a.nE_c, a.elem4_c, a.elem_edges_c, a.elem4_f);
+    else if (b < a.b2)
+        d_refine_elems(b - a.b1, a.nC_c, a.nE_c, a.elem4_c, a.elem_edges_c, a.exy_c, a.elem4_f,
+                       a.exy_f);
     else if (b < a.b3) d_refine_pairs(b - a.b2, a.nC_c, a.nD_c, a.dir_pairs_c, a.dir_edges_c, a.dir_pairs_f);
     else if (b < a.b4) d_refine_pairs(b - a.b3, a.nC_c, a.nN_c, a.neu_pairs_c, a.neu_edges_c, a.neu_pairs_f);
     else d_rt_count(b - a.b4, a.ne_c, a.edge_elems_c, a.led_c, a.ledTN_c, a.elem_edges_c, a.ucount);
@@ -918,6 +942,7 @@ int refined_tables(phf_mesh* M, const phf_mesh* P, build_tmp* T, int32_t* ne_out
     const int32_t ne = 2 * ne_c + 3 * nE_c;
     TRY(phf_dmalloc(ctx, &M->xy, M->nC, "coordinates"));
     TRY(phf_dmalloc(ctx, &M->elem4, nE, "elements"));
+    TRY(phf_dmalloc(ctx, &M->exy, 3 * (size_t)nE, "element coordinates"));
     TRY(phf_dmalloc(ctx, &M->dir_pairs, nD, "Dirichlet pairs"));
     TRY(phf_dmalloc(ctx, &M->neu_pairs, nN, "Neumann pairs"));
     TRY(phf_dmalloc(ctx, &T->totals, 8, "totals"));
@@ -939,7 +964,9 @@ int refined_tables(phf_mesh* M, const phf_mesh* P, build_tmp* T, int32_t* ne_out
         a.xy_f = M->xy;
         a.elem4_c = P->elem4;
         a.elem_edges_c = P->elem_edges;
+        a.exy_c = P->exy;
         a.elem4_f = M->elem4;
+        a.exy_f = M->exy;
         a.dir_pairs_c = P->dir_pairs;
         a.neu_pairs_c = P->neu_pairs;
         a.dir_edges_c = P->dir_edges;
@@ -1088,7 +1115,7 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     TRY(phf_dmalloc(ctx, &T.tiles, (size_t)nt, "row tile counts"));
     TRY(phf_dmalloc(ctx, &T.tile_total, 1, "row totals"));
     TRY(phf_dmalloc(ctx, &T.etiles, (size_t)ntE, "element tile counts"));
-    TRY(phf_dmalloc(ctx, &M->exy, 3 * (size_t)nE, "element coordinates"));
+    if (!parent) TRY(phf_dmalloc(ctx, &M->exy, 3 * (size_t)nE, "element coordinates"));
     TRY(phf_dmalloc(ctx, &M->ecode, nE, "element codes"));
     {
         counts_args a{};
@@ -1102,7 +1129,7 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
         a.flags = ctx->d_flags;
         a.elem4 = M->elem4;
         a.elem_edges = M->elem_edges;
-        a.xy = M->xy;
+        a.xy = parent ? nullptr : M->xy;  // refined: built with the children
         a.exy = M->exy;
         a.ecode = M->ecode;
         a.etiles = T.etiles;
