@@ -34,9 +34,14 @@
 #define PHF_MG_MAX_LEVELS 20
 #define PHF_MG_DENSE_MAX 256
 // Levels with at most this many unknowns (below the finest) run their part of
-// the cycle in one single-workgroup launch.
+// the cycle in one single-workgroup launch, as long as their vectors fit in
+// that workgroup's local data share (PHF_MG_TAIL_LDS bytes; gfx950 gives one
+// workgroup up to 160 KiB).
 #ifndef PHF_MG_TAIL_MAX
-#define PHF_MG_TAIL_MAX 2048
+#define PHF_MG_TAIL_MAX 8192
+#endif
+#ifndef PHF_MG_TAIL_LDS
+#define PHF_MG_TAIL_LDS (160 * 1024)
 #endif
 // Sweeps per side at most; each level keeps PHF_MG_MAX_SWEEPS sweep weights
 // and, last, the weight of the plain sweeps of an iterative coarsest solve.
@@ -56,6 +61,9 @@ struct phf_mg_dev_level {
     const int32_t* ecode_c = nullptr;  // element codes of the next coarser mesh
     const int2* sel = nullptr;         // own gather map (from the finer level's sums)
     const float* w = nullptr;          // sweep weights (PHF_MG_WSTRIDE)
+    // offsets (in floats) of the level's vectors in the workgroup's local
+    // data share: the two iterates, D^-1 b, and the restriction sums
+    int32_t sx = 0, sy = 0, sb = 0, st = 0;
 };
 
 // One level's entry in the table that drives the set-up launches over all
@@ -121,6 +129,7 @@ struct phf_mg {
     double* val64 = nullptr;
     int32_t n0 = 0;
     int32_t tail_top = -1;   // levels 0..tail_top run in the single-workgroup kernel
+    int32_t tail_lds = 0;    // its local data share (bytes)
     phf_mg_dev_level h_lv[PHF_MG_MAX_LEVELS];
     phf_mg_dev_level* d_lv = nullptr;
     phf_mg_setup_level h_setup[PHF_MG_MAX_LEVELS];

@@ -172,8 +172,12 @@ __global__ __launch_bounds__(1024) void k_mg_gj(int32_t n, double* __restrict__ 
     for (int64_t q = tid; q < (int64_t)n * n; q += nth) A[q] = W[q];
 }
 
-__device__ inline float ell5(int32_t r, int32_t n, const int32_t* __restrict__ col,
-                             const float* __restrict__ val, const float* __restrict__ x)
+// The per-row helpers take their pointers as template parameters, so that a
+// caller can pass pointers typed as device memory or local data share and the
+// compiler emits the matching (not flat) loads and stores.
+template <typename PC, typename PV, typename PX>
+__device__ inline float ell5(int32_t r, int32_t n, PC __restrict__ col, PV __restrict__ val,
+                             PX __restrict__ x)
 {
     float s = 0.0f;
 #pragma unroll
@@ -188,9 +192,9 @@ __device__ inline float ell5(int32_t r, int32_t n, const int32_t* __restrict__ c
 // off-diagonal slots of D^-1 A (ELL-4, slot-major; unused slots hold column r
 // and value 0) and an implicit unit diagonal; right-hand sides are kept as
 // D^-1 b. sres is then the scaled residual D^-1 (b - A x) of row i.
-__device__ inline float sres(int32_t i, int32_t n, const int32_t* __restrict__ col,
-                             const float* __restrict__ val, const float* __restrict__ bh,
-                             const float* __restrict__ x)
+template <typename PC, typename PV, typename PB, typename PX>
+__device__ inline float sres(int32_t i, int32_t n, PC __restrict__ col, PV __restrict__ val,
+                             PB __restrict__ bh, PX __restrict__ x)
 {
     float s = 0.0f;
 #pragma unroll
@@ -212,10 +216,10 @@ __device__ inline void row_smooth(int32_t i, int32_t n, const int32_t* __restric
 }
 
 // Unscaled residual b - A x = D (D^-1 b - D^-1 A x).
-__device__ inline void row_resid(int32_t i, int32_t n, const int32_t* __restrict__ col,
-                                 const float* __restrict__ val, const float* __restrict__ diag,
-                                 const float* __restrict__ bh, const float* __restrict__ x,
-                                 float* __restrict__ r)
+template <typename PC, typename PV, typename PD, typename PB, typename PX, typename PR>
+__device__ inline void row_resid(int32_t i, int32_t n, PC __restrict__ col, PV __restrict__ val,
+                                 PD __restrict__ diag, PB __restrict__ bh, PX __restrict__ x,
+                                 PR __restrict__ r)
 {
     r[i] = diag[i] * sres(i, n, col, val, bh, x);
 }
@@ -226,16 +230,22 @@ __device__ inline void row_resid(int32_t i, int32_t n, const int32_t* __restrict
 // fine edge midpoint and s_e = 1/2 on halves of a coarse edge shared with a
 // second coarse triangle (the prolongation averages the two sides there), 1
 // otherwise. The barycentric coordinates of the fine midpoints do not depend
-// on the shape of p, so the weights are the constants below.
-__device__ inline void tri_restrict(int32_t p, int32_t nEc, const int32_t* __restrict__ rows9,
-                                    const int32_t* __restrict__ ecode_c,
-                                    const float* __restrict__ rf, float* __restrict__ t)
+// on the shape of p, so the weights are the constants below. rf must hold at
+// least one element (the gathers read a clamped index, so that all nine row
+// loads are issued before the first gather waits).
+template <typename PR9, typename PE, typename PF, typename PT>
+__device__ inline void tri_restrict(int32_t p, int32_t nEc, PR9 __restrict__ rows9,
+                                    PE __restrict__ ecode_c, PF __restrict__ rf,
+                                    PT __restrict__ t)
 {
+    int32_t row[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) row[k] = rows9[(int64_t)k * nEc + p];
     float v[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        const int32_t row = rows9[(int64_t)k * nEc + p];
-        v[k] = row >= 0 ? rf[row] : 0.0f;
+        const float g = rf[row[k] >= 0 ? row[k] : 0];
+        v[k] = row[k] >= 0 ? g : 0.0f;
     }
     const int32_t code = ecode_c[p];
     float s[3];
@@ -265,12 +275,22 @@ __device__ inline void tri_restrict(int32_t p, int32_t nEc, const int32_t* __res
 // Restriction, second half: coarse row c sums its edge's entries from T+ and
 // T- (in that order), keeps the scaled right-hand side D^-1 b and takes the
 // coarse level's first sweep from zero, x = omega D^-1 b.
-__device__ inline void row_collect(int32_t c, const int2* __restrict__ sel,
-                                   const float* __restrict__ t, const float* __restrict__ dinv,
-                                   float omega, float* __restrict__ bh, float* __restrict__ x)
+// Entry c of a gather map, given as int2 or (in device memory) as int32 pairs.
+__device__ inline int2 sel_at(const int2* __restrict__ sel, int32_t c) { return sel[c]; }
+template <typename PS>
+__device__ inline int2 sel_at(PS __restrict__ sel, int32_t c)
 {
-    const int2 q = sel[c];
-    const float b = q.y >= 0 ? t[q.x] + t[q.y] : t[q.x];
+    return make_int2(sel[2 * c], sel[2 * c + 1]);
+}
+
+template <typename PS, typename PT, typename PD, typename PB, typename PX>
+__device__ inline void row_collect(int32_t c, PS __restrict__ sel, PT __restrict__ t,
+                                   PD __restrict__ dinv, float omega, PB __restrict__ bh,
+                                   PX __restrict__ x)
+{
+    const int2 q = sel_at(sel, c);
+    const float tx = t[q.x], ty = t[q.y >= 0 ? q.y : q.x];
+    const float b = q.y >= 0 ? tx + ty : tx;
     const float h = b * dinv[c];
     bh[c] = h;
     x[c] = omega * h;
@@ -284,9 +304,9 @@ __device__ inline void row_prolong(int32_t i, int32_t n, const int32_t* __restri
 }
 
 // Coarsest level: x = A^-1 b with b = D (D^-1 b).
-__device__ inline void row_coarse(int32_t i, int32_t n, const double* __restrict__ Ainv,
-                                  const float* __restrict__ diag, const float* __restrict__ bh,
-                                  float* __restrict__ x)
+template <typename PA, typename PD, typename PB, typename PX>
+__device__ inline void row_coarse(int32_t i, int32_t n, PA __restrict__ Ainv, PD __restrict__ diag,
+                                  PB __restrict__ bh, PX __restrict__ x)
 {
     double s = 0.0;
     for (int32_t j = 0; j < n; ++j)
@@ -542,14 +562,58 @@ __global__ __launch_bounds__(NT) void k_mg_prolong(int32_t n, const int32_t* __r
 
 // The whole V-cycle on levels 0..top of the descriptor table in one
 // workgroup: every step is a loop over its rows followed by a workgroup
-// barrier (the barrier orders the global-memory writes of the step before
-// the reads of the next one within the workgroup). On entry the top level
-// holds D^-1 b and its first sweep from zero in y (level 0: in x), written by
-// the restriction from the level above; lower levels receive theirs the same
-// way inside the kernel. Every level then takes 2 nu - 1 more sweeps, an odd
-// number, so its result ends in x; the coarsest level solves directly into
-// x, or takes 40 further sweeps (an even number) from its first one in x.
+// barrier. The levels' vectors (two iterates, D^-1 b, the restriction sums)
+// live in the workgroup's local data share, so a step reads only its
+// operator rows and transfer tables from memory; the residual of a level
+// takes the iterate buffer that is free at that point. On entry the top
+// level's D^-1 b and first sweep from zero are in memory (L.b and L.y; level
+// 0: L.x), written by the restriction from the level above; lower levels
+// receive theirs the same way inside the kernel. Every level then takes
+// 2 nu - 1 more sweeps, an odd number; the coarsest level solves directly, or
+// takes 40 further sweeps (an even number) from its first one. The top
+// level's result is stored to L.x.
 constexpr int TAIL_NT = 1024;
+// The level descriptor as the single-workgroup kernel uses it: device-memory
+// pointers typed as such, so that their loads are global (not flat) loads,
+// whose counter is separate from the local data share's; a step can then
+// issue all its memory loads before it waits for any.
+template <typename T>
+using gmem_ptr = __attribute__((address_space(1))) T*;
+struct tail_lv {
+    int32_t n, nEc, sx, sy, sb, st;
+    gmem_ptr<const int32_t> col;
+    gmem_ptr<const float> val, diag, dinv;
+    gmem_ptr<float> x;
+    gmem_ptr<const float> y, b;
+    gmem_ptr<const int32_t> P_col;
+    gmem_ptr<const float> P_val;
+    gmem_ptr<const int32_t> rows9, ecode_c;
+    gmem_ptr<const int32_t> sel;  // int2 entries as int32 pairs
+    gmem_ptr<const float> w;
+};
+__device__ inline tail_lv tail_level(const phf_mg_dev_level* __restrict__ lv, int32_t l)
+{
+    const phf_mg_dev_level& L = lv[l];
+    return tail_lv{L.n,
+                   L.nEc,
+                   L.sx,
+                   L.sy,
+                   L.sb,
+                   L.st,
+                   (gmem_ptr<const int32_t>)L.col,
+                   (gmem_ptr<const float>)L.val,
+                   (gmem_ptr<const float>)L.diag,
+                   (gmem_ptr<const float>)L.dinv,
+                   (gmem_ptr<float>)L.x,
+                   (gmem_ptr<const float>)L.y,
+                   (gmem_ptr<const float>)L.b,
+                   (gmem_ptr<const int32_t>)L.P_col,
+                   (gmem_ptr<const float>)L.P_val,
+                   (gmem_ptr<const int32_t>)L.rows9,
+                   (gmem_ptr<const int32_t>)L.ecode_c,
+                   (gmem_ptr<const int32_t>)L.sel,
+                   (gmem_ptr<const float>)L.w};
+}
 // Rows 0..n-1 of one step of the single-workgroup cycle: row i gets
 // st(i, f(i)).
 template <typename F, typename S>
@@ -564,47 +628,72 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
                                                      int32_t dense, const int* iflags)
 {
     if (iflags && iflags[0]) return;
+    extern __shared__ float lds[];
     const int32_t tid = threadIdx.x;
+    {
+        const tail_lv T = tail_level(lv, top);
+        const gmem_ptr<const float> first = top == 0 ? T.x : T.y;
+        float* u0 = lds + (top == 0 ? T.sx : T.sy);
+        for (int32_t i = tid; i < T.n; i += TAIL_NT) {
+            lds[T.sb + i] = T.b[i];
+            u0[i] = first[i];
+        }
+        __syncthreads();
+    }
     // down: pre-smoothing, residual, restriction (with the coarse first sweep)
     for (int32_t l = top; l >= 1; --l) {
-        const phf_mg_dev_level L = lv[l];
-        const phf_mg_dev_level C = lv[l - 1];
-        float *u = L.y, *v = L.x;
+        const tail_lv L = tail_level(lv, l);
+        const tail_lv C = tail_level(lv, l - 1);
+        const float* bh = lds + L.sb;
+        float *u = lds + L.sy, *v = lds + L.sx;
         for (int32_t s = 1; s < nu; ++s) {
             const float omega = L.w[s];
             tail_rows(
-                L.n, tid, [&](int32_t i) { return u[i] + omega * sres(i, L.n, L.col, L.val, L.b, u); },
+                L.n, tid, [&](int32_t i) { return u[i] + omega * sres(i, L.n, L.col, L.val, bh, u); },
                 [&](int32_t i, float y) { v[i] = y; });
             __syncthreads();
             float* q = u;
             u = v;
             v = q;
         }
+        // residual into the free iterate buffer (unused until the way up)
+        float* r = v;
         tail_rows(
-            L.n, tid, [&](int32_t i) { return L.diag[i] * sres(i, L.n, L.col, L.val, L.b, u); },
-            [&](int32_t i, float y) { L.r[i] = y; });
+            L.n, tid, [&](int32_t i) { return L.diag[i] * sres(i, L.n, L.col, L.val, bh, u); },
+            [&](int32_t i, float y) { r[i] = y; });
         __syncthreads();
-        for (int32_t p = tid; p < L.nEc; p += TAIL_NT)
-            tri_restrict(p, L.nEc, L.rows9, L.ecode_c, L.r, L.t);
+        float* t = lds + L.st;
+        for (int32_t p = tid; p < L.nEc; p += TAIL_NT) {
+            if (L.n > 0) {
+                tri_restrict(p, L.nEc, L.rows9, L.ecode_c, r, t);
+            } else {  // no fine unknowns: the sums are zero
+                t[3 * p] = 0.0f;
+                t[3 * p + 1] = 0.0f;
+                t[3 * p + 2] = 0.0f;
+            }
+        }
         __syncthreads();
         const float wc = l - 1 == 0 ? C.w[PHF_MG_MAX_SWEEPS] : C.w[0];
-        float* xc = l - 1 == 0 ? C.x : C.y;
-        for (int32_t c = tid; c < C.n; c += TAIL_NT) row_collect(c, C.sel, L.t, C.dinv, wc, C.b, xc);
+        float* xc = lds + (l - 1 == 0 ? C.sx : C.sy);
+        for (int32_t c = tid; c < C.n; c += TAIL_NT)
+            row_collect(c, C.sel, t, C.dinv, wc, lds + C.sb, xc);
         __syncthreads();
     }
-    // coarsest level
+    // coarsest level: the solution ends in sx
     {
-        const phf_mg_dev_level L = lv[0];
+        const tail_lv L = tail_level(lv, 0);
+        float* x = lds + L.sx;
+        const float* bh = lds + L.sb;
         if (dense) {
-            for (int32_t i = tid; i < L.n; i += TAIL_NT) row_coarse(i, L.n, cinv, L.diag, L.b, L.x);
+            for (int32_t i = tid; i < L.n; i += TAIL_NT) row_coarse(i, L.n, (gmem_ptr<const double>)cinv, L.diag, bh, x);
             __syncthreads();
         } else {
-            float *u = L.x, *v = L.y;
+            float *u = x, *v = lds + L.sy;
             const float omega = L.w[PHF_MG_MAX_SWEEPS];
             for (int32_t s = 0; s < 40; ++s) {
                 tail_rows(
                     L.n, tid,
-                    [&](int32_t i) { return u[i] + omega * sres(i, L.n, L.col, L.val, L.b, u); },
+                    [&](int32_t i) { return u[i] + omega * sres(i, L.n, L.col, L.val, bh, u); },
                     [&](int32_t i, float y) { v[i] = y; });
                 __syncthreads();
                 float* q = u;
@@ -613,29 +702,37 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
             }
         }
     }
-    // up: prolongation, post-smoothing
+    // up: prolongation, post-smoothing; each level's result ends in sx
     for (int32_t l = 1; l <= top; ++l) {
-        const phf_mg_dev_level L = lv[l];
-        const phf_mg_dev_level C = lv[l - 1];
-        // the pre-smoothing ended nu - 1 swaps away from y
-        float* u = ((nu - 1) & 1) ? L.x : L.y;
-        float* v = u == L.x ? L.y : L.x;
+        const tail_lv L = tail_level(lv, l);
+        const tail_lv C = tail_level(lv, l - 1);
+        const float* bh = lds + L.sb;
+        // the pre-smoothing (from sy) ended nu - 1 swaps away
+        float* u = lds + (((nu - 1) & 1) ? L.sx : L.sy);
+        float* v = lds + (((nu - 1) & 1) ? L.sy : L.sx);
         if (C.n > 0) {  // (uniform branch) no coarse unknowns: no correction
+            const float* xc = lds + C.sx;
             tail_rows(
-                L.n, tid, [&](int32_t i) { return u[i] + ell5(i, L.n, L.P_col, L.P_val, C.x); },
+                L.n, tid, [&](int32_t i) { return u[i] + ell5(i, L.n, L.P_col, L.P_val, xc); },
                 [&](int32_t i, float y) { u[i] = y; });
             __syncthreads();
         }
         for (int32_t s = 0; s < nu; ++s) {
             const float omega = L.w[s];
             tail_rows(
-                L.n, tid, [&](int32_t i) { return u[i] + omega * sres(i, L.n, L.col, L.val, L.b, u); },
+                L.n, tid, [&](int32_t i) { return u[i] + omega * sres(i, L.n, L.col, L.val, bh, u); },
                 [&](int32_t i, float y) { v[i] = y; });
             __syncthreads();
             float* q = u;
             u = v;
             v = q;
         }
+        if (l == top)
+            for (int32_t i = tid; i < L.n; i += TAIL_NT) L.x[i] = u[i];
+    }
+    if (top == 0) {
+        const tail_lv T = tail_level(lv, 0);
+        for (int32_t i = tid; i < T.n; i += TAIL_NT) T.x[i] = lds[T.sx + i];
     }
 }
 
@@ -847,10 +944,26 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             TRY(phf_dmalloc(ctx, &mg->col64, 5 * (size_t)mg->n0, "coarse operator columns"));
             TRY(phf_dmalloc(ctx, &mg->val64, 5 * (size_t)mg->n0, "coarse operator values"));
         }
-        // the small levels below the finest: one workgroup runs their cycle
-        mg->tail_top = 0;
-        while (mg->tail_top + 1 < nlev - 1 && mg->lev[mg->tail_top + 1].nf <= PHF_MG_TAIL_MAX)
+        // the small levels below the finest: one workgroup runs their cycle,
+        // with their vectors in its local data share (two iterates and D^-1 b
+        // per row, three sums per triangle of the next coarser mesh)
+        auto tail_floats = [&](int l) {
+            return 3 * (int64_t)mg->lev[l].nf + (l > 0 ? 3 * (int64_t)mg->lev[l - 1].mesh->nE : 0);
+        };
+        // (a coarsest level too large for it runs with one launch per step)
+        mg->tail_top = -1;
+        int64_t lds_floats = 0;
+        while (mg->tail_top + 1 < nlev - 1 && mg->lev[mg->tail_top + 1].nf <= PHF_MG_TAIL_MAX &&
+               (lds_floats + tail_floats(mg->tail_top + 1)) * (int64_t)sizeof(float) <= PHF_MG_TAIL_LDS) {
             ++mg->tail_top;
+            lds_floats += tail_floats(mg->tail_top);
+        }
+        mg->tail_lds = (int32_t)(lds_floats * (int64_t)sizeof(float));
+        if (mg->tail_top >= 0)
+            PHF_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mg_tail),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             mg->tail_lds));
+        int32_t lds_off = 0;
         for (int l = 0; l <= mg->tail_top; ++l) {
             const phf_mg_level& L = mg->lev[l];
             phf_mg_dev_level& d = mg->h_lv[l];
@@ -864,6 +977,10 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             d.b = L.b;
             d.r = L.r;
             d.sel = L.sel;
+            d.sx = lds_off;
+            d.sy = lds_off + L.nf;
+            d.sb = lds_off + 2 * L.nf;
+            lds_off += 3 * L.nf;
             if (l > 0) {
                 d.nEc = mg->lev[l - 1].mesh->nE;
                 d.P_col = L.P_col;
@@ -871,14 +988,19 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
                 d.rows9 = L.rows9;
                 d.t = L.t;
                 d.ecode_c = mg->lev[l - 1].mesh->ecode;
+                d.st = lds_off;
+                lds_off += 3 * d.nEc;
             }
         }
         TRY(phf_dmalloc(ctx, &mg->lmax, (size_t)nlev, "multigrid spectral bounds"));
         TRY(phf_dmalloc(ctx, &mg->wts, (size_t)nlev * PHF_MG_WSTRIDE, "multigrid sweep weights"));
         for (int l = 0; l <= mg->tail_top; ++l) mg->h_lv[l].w = mg->wts + (size_t)l * PHF_MG_WSTRIDE;
-        TRY(phf_dmalloc(ctx, &mg->d_lv, (size_t)mg->tail_top + 1, "multigrid level table"));
-        PHF_HIP(ctx, hipMemcpyAsync(mg->d_lv, mg->h_lv, sizeof(phf_mg_dev_level) * (mg->tail_top + 1),
-                                    hipMemcpyHostToDevice, ctx->stream));
+        if (mg->tail_top >= 0) {
+            TRY(phf_dmalloc(ctx, &mg->d_lv, (size_t)mg->tail_top + 1, "multigrid level table"));
+            PHF_HIP(ctx, hipMemcpyAsync(mg->d_lv, mg->h_lv,
+                                        sizeof(phf_mg_dev_level) * (mg->tail_top + 1),
+                                        hipMemcpyHostToDevice, ctx->stream));
+        }
         // set-up table: per level the mesh tables, outputs and block ranges
         int32_t blk = 0;
         for (int l = 0; l < nlev; ++l) {
@@ -1012,7 +1134,9 @@ int smooth(phf_mg* mg, int l, int k, const int* iflags)
 }
 
 // Cycle on level l > tail_top. On entry L.b holds D^-1 b and L.x the first
-// sweep from zero, except on the finest level (r_top != null), where this
+// sweep from zero (a coarsest level outside the single-workgroup kernel then
+// takes 40 further plain sweeps, an even number, so its result is in L.x),
+// except on the finest level (r_top != null), where this
 // function starts from the double-precision residual r_top (unless
 // first_done) and the last sweep writes z (z64 or z32) and the partial sums
 // of r.z instead of x.
@@ -1023,12 +1147,16 @@ int vcycle(phf_mg* mg, int l, const double* r_top, bool first_done, double* z64,
     phf_ctx* ctx = L.mesh->ctx;
     if (l <= mg->tail_top) {
         // this level and all below in one workgroup; the result is in L.x
-        PHF_LAUNCH(ctx, "k_mg_tail", k_mg_tail, 1, TAIL_NT, 0, mg->d_lv, (int32_t)l, mg->nu,
-                   mg->cinv, mg->cinv ? 1 : 0, iflags);
+        PHF_LAUNCH(ctx, "k_mg_tail", k_mg_tail, 1, TAIL_NT, mg->tail_lds, mg->d_lv, (int32_t)l,
+                   mg->nu, mg->cinv, mg->cinv ? 1 : 0, iflags);
         return PHF_OK;
     }
     const int32_t n = L.nf;
     if (n == 0) return PHF_OK;
+    if (l == 0) {
+        for (int s = 0; s < 40; ++s) TRY(smooth(mg, 0, PHF_MG_MAX_SWEEPS, iflags));
+        return PHF_OK;
+    }
     const unsigned g = grid_for(n);
     const float* w = level_weights(mg, l);
     if (r_top && !first_done)
