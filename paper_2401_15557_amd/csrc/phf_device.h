@@ -199,3 +199,42 @@ __device__ inline int phf_reduced_entries(int32_t e, const int2* edge_elems, con
     }
     return n;
 }
+
+// Single-precision scaled copy of row r of a reduced operator given as five
+// (column, value) slots, unused ones holding column r and value 0: the
+// off-diagonal entries of D^-1 A in slot order (a free edge has at most four
+// neighbours; the remaining slots get column r and value 0), the diagonal
+// a_rr and its inverse (1 where a_rr <= 0, as for the double-precision
+// inverse diagonal), stored slot-major over n rows. Returns the row's
+// Gershgorin sum 1 + sum_j |a_ij| / a_ii in single precision.
+__device__ inline float phf_scale_row(int32_t r, int32_t n, const int32_t* c, const double* v,
+                                      int32_t* __restrict__ col4, float* __restrict__ val4,
+                                      float* __restrict__ diag, float* __restrict__ dinv)
+{
+    double d = 0.0;
+    int32_t c4[4] = {r, r, r, r};
+    double v4[4] = {0.0, 0.0, 0.0, 0.0};
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        if (c[k] == r) {
+            d += v[k];  // the diagonal (unused slots add zero)
+        } else if (cnt < 4) {
+            c4[cnt] = c[k];
+            v4[cnt] = v[k];
+            ++cnt;
+        }
+    }
+    const double di = d > 0.0 ? 1.0 / d : 1.0;
+    float s = 1.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float f = (float)(v4[k] * di);
+        col4[(int64_t)k * n + r] = c4[k];
+        val4[(int64_t)k * n + r] = f;
+        s += fabsf(f);
+    }
+    diag[r] = d > 0.0 ? (float)d : 1.0f;
+    dinv[r] = (float)di;
+    return s;
+}

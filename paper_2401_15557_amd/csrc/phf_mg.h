@@ -142,6 +142,19 @@ struct phf_mg {
     uint32_t* lmax = nullptr;  // per level: Gershgorin bound (float bits)
     float* wts = nullptr;      // per level: PHF_MG_WSTRIDE sweep weights
     float* z32 = nullptr;      // finest-level result for conjugate gradients
+    bool fine_rows_ready = false;  // the finest scaled rows came with the operator
+};
+
+// Finest-level outputs that the kernel building the double-precision rows of
+// the finest operator can fill at the same time: the scaled single-precision
+// rows, the diagonal and its inverse (phf_scale_row), and the level's
+// Gershgorin bound (float bits, merged with atomicMax; cleared beforehand).
+struct phf_mg_rows {
+    int32_t* col4;
+    float* val4;
+    float* diag;
+    float* dinv;
+    uint32_t* lmax;
 };
 
 // Finest-level buffers through which the outer iteration's update can take
@@ -171,5 +184,9 @@ int phf_mg_apply(phf_mg* mg, const double* r, double* z, double* part_rz, const 
 int phf_mg_apply32(phf_mg* mg, const double* r, bool first_done, double* part_rz,
                    const int* iflags);
 phf_mg_top phf_mg_top_view(phf_mg* mg);
+// Queues the clearing of the spectral bounds and hands out the finest-level
+// outputs for the operator kernel; the next phf_mg_numeric then takes the
+// finest rows as written and builds only the coarser levels.
+int phf_mg_fine_rows(phf_mg* mg, phf_mg_rows* out);
 // Number of hierarchy levels below and including `mesh`.
 int32_t phf_mg_levels(const phf_mesh* mesh);

@@ -375,10 +375,10 @@ __global__ __launch_bounds__(NT) void k_mg_cblocks(int32_t nE, const double2* __
 
 // Coarse-level rows of the reduced operator: the ELL-5 entries of row r
 // (columns sorted, values B[s0] + B[s1]) scaled straight into the cycle's
-// rows (off-diagonals of D^-1 A in ELL-4, the diagonal and its inverse, as
-// k_mg_scale computes them from the double-precision rows). With col64 and
-// val64 (the coarsest level) also the double-precision ELL-5 rows.
-__device__ inline void d_mg_crows(int32_t r, 
+// rows by phf_scale_row (off-diagonals of D^-1 A in ELL-4, the diagonal and
+// its inverse); returns the row's Gershgorin sum. With col64 and val64 (the
+// coarsest level) also the double-precision ELL-5 rows.
+__device__ inline float d_mg_crows(int32_t r, 
     int32_t nf, const int32_t* __restrict__ red_edge, const int2* __restrict__ edge_elems,
     const int8_t* __restrict__ led, const int8_t* __restrict__ ledTN,
     const int32_t* __restrict__ elem_edges, const int32_t* __restrict__ red_row,
@@ -386,74 +386,21 @@ __device__ inline void d_mg_crows(int32_t r,
     float* __restrict__ diag, float* __restrict__ dinv, int32_t* __restrict__ col64,
     double* __restrict__ val64)
 {
-    if (r >= nf) return;
+    if (r >= nf) return 0.0f;
     int32_t col[5], s0[5], s1[5];
     const int n = phf_reduced_entries(red_edge[r], edge_elems, led, ledTN, elem_edges, red_row,
                                       col, s0, s1);
     double v[5];
-    double d = 0.0;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         v[k] = k < n ? B[s0[k]] + (s1[k] >= 0 ? B[s1[k]] : 0.0) : 0.0;
-        if (k < n && col[k] == r) d = v[k];
+        if (k >= n) col[k] = r;
         if (col64) {
-            col64[(int64_t)k * nf + r] = k < n ? col[k] : r;
+            col64[(int64_t)k * nf + r] = col[k];
             val64[(int64_t)k * nf + r] = v[k];
         }
     }
-    const double di = d > 0.0 ? 1.0 / d : 1.0;
-    int q = 0;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        if (k >= n || col[k] == r || q >= 4) continue;
-        col4[(int64_t)q * nf + r] = col[k];
-        val4[(int64_t)q * nf + r] = (float)(v[k] * di);
-        ++q;
-    }
-    for (; q < 4; ++q) {
-        col4[(int64_t)q * nf + r] = r;
-        val4[(int64_t)q * nf + r] = 0.0f;
-    }
-    diag[r] = d > 0.0 ? (float)d : 1.0f;
-    dinv[r] = (float)di;
-}
-
-// Single-precision scaled copy of a level's operator: off-diagonal entries
-// of row r divided by its diagonal a_rr (1 where a_rr <= 0, as for the
-// double-precision inverse diagonal), the diagonal and its inverse.
-__device__ inline void d_mg_scale(int32_t r, int32_t n, const int32_t* __restrict__ col,
-                                  const double* __restrict__ val, int32_t* __restrict__ col4,
-                                  float* __restrict__ val4, float* __restrict__ diag,
-                                  float* __restrict__ dinv)
-{
-    if (r >= n) return;
-    {
-        double d = 0.0;
-        int32_t c4[4] = {r, r, r, r};
-        double v4[4] = {0.0, 0.0, 0.0, 0.0};
-        int cnt = 0;
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const int64_t slot = (int64_t)k * n + r;
-            const int32_t c = col[slot];
-            const double v = val[slot];
-            if (c == r) {
-                d += v;  // the diagonal (unused slots add zero)
-            } else if (cnt < 4) {  // a free edge has at most four neighbours
-                c4[cnt] = c;
-                v4[cnt] = v;
-                ++cnt;
-            }
-        }
-        const double di = d > 0.0 ? 1.0 / d : 1.0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            col4[(int64_t)k * n + r] = c4[k];
-            val4[(int64_t)k * n + r] = (float)(v4[k] * di);
-        }
-        diag[r] = d > 0.0 ? (float)d : 1.0f;
-        dinv[r] = (float)di;
-    }
+    return phf_scale_row(r, nf, col, v, col4, val4, diag, dinv);
 }
 
 // First sweep from x = 0 on the finest level: also rounds the right-hand side
@@ -805,19 +752,24 @@ __global__ __launch_bounds__(NT) void k_mg_setup_rows(const phf_mg_setup_level* 
     __shared__ float sh[NT];
     const int l = find_level(lv, nlev, blockIdx.x, 3);
     const phf_mg_setup_level& L = lv[l];
-    // a level has at most 1024 blocks (few atomics on its bound); each loops
+    // a level's blocks loop over its rows
     const int32_t nb = (l + 1 < nlev ? lv[l + 1].b[3] : gridDim.x) - L.b[3];
     float m = 0.0f;  // Gershgorin bound of D^-1 A over this block's rows
     for (int32_t r = (blockIdx.x - L.b[3]) * NT + threadIdx.x; r < L.nf; r += nb * NT) {
-        if (L.B)
-            d_mg_crows(r, L.nf, L.red_edge, L.edge_elems, L.led, L.ledTN, L.elem_edges,
-                       L.red_row, L.B, L.col4, L.val4, L.diag, L.dinv, L.col64, L.val64);
-        else
-            d_mg_scale(r, L.nf, L.ell_col, L.ell_val, L.col4, L.val4, L.diag, L.dinv);
-        // 1 + sum_j |a_ij| / a_ii
-        float s = 1.0f;
+        float s;  // 1 + sum_j |a_ij| / a_ii
+        if (L.B) {
+            s = d_mg_crows(r, L.nf, L.red_edge, L.edge_elems, L.led, L.ledTN, L.elem_edges,
+                           L.red_row, L.B, L.col4, L.val4, L.diag, L.dinv, L.col64, L.val64);
+        } else {  // the finest level, from the caller's double-precision rows
+            int32_t c[5];
+            double v[5];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) s += fabsf(L.val4[(int64_t)k * L.nf + r]);
+            for (int k = 0; k < 5; ++k) {
+                c[k] = L.ell_col[(int64_t)k * L.nf + r];
+                v[k] = L.ell_val[(int64_t)k * L.nf + r];
+            }
+            s = phf_scale_row(r, L.nf, c, v, L.col4, L.val4, L.diag, L.dinv);
+        }
         m = fmaxf(m, s);
     }
     if (!gersh) return;
@@ -829,7 +781,13 @@ __global__ __launch_bounds__(NT) void k_mg_setup_rows(const phf_mg_setup_level* 
         if (threadIdx.x < h) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + h]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax(lmax + l, __float_as_uint(sh[0]));
+    // (only where it raises the value already there: the bound only grows,
+    // so a stale read costs at most an unneeded atomic)
+    if (threadIdx.x == 0) {
+        const uint32_t bits = __float_as_uint(sh[0]);
+        if (bits > __hip_atomic_load(lmax + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(lmax + l, bits);
+    }
 }
 
 unsigned grid_for(int32_t n) { return (unsigned)std::min<int64_t>(std::max<int64_t>(nblk(n), 1), 1024); }
@@ -1057,7 +1015,7 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
         blk = 0;
         for (int l = 0; l < nlev; ++l) {
             mg->h_setup[l].b[3] = blk;
-            blk += (int32_t)std::min<int64_t>(nblk(mg->lev[l].nf), 1024);
+            blk += (int32_t)nblk(mg->lev[l].nf);
         }
         mg->setup_row_blocks = blk;
         TRY(phf_dmalloc(ctx, &mg->d_setup, (size_t)nlev, "multigrid set-up table"));
@@ -1096,11 +1054,17 @@ int phf_mg_numeric(phf_mg* mg, const phf_coeffs* co, double cK, double cM)
     // every level's scaled single-precision rows (coarse levels from their
     // blocks, the finest from the operator the caller built) and, for the
     // Chebyshev weights, their Gershgorin bounds
+    // (the finest level's come with the operator when phf_mg_fine_rows was
+    // used for it: its row blocks, the last ones, are then left out)
     const bool cheb = mg->smoother == PHF_MG_SMOOTH_CHEBYSHEV;
-    PHF_LAUNCH(ctx, "k_mg_lmax_clear", k_mg_lmax_clear, 1, PHF_MG_MAX_LEVELS, 0, mg->nlev, mg->lmax);
-    if (mg->setup_row_blocks > 0)
-        PHF_LAUNCH(ctx, "k_mg_setup_rows", k_mg_setup_rows, mg->setup_row_blocks, NT, 0,
-                   mg->d_setup, mg->nlev, cheb ? 1 : 0, mg->lmax);
+    const int32_t row_blocks = mg->fine_rows_ready ? mg->h_setup[top].b[3] : mg->setup_row_blocks;
+    if (!mg->fine_rows_ready)
+        PHF_LAUNCH(ctx, "k_mg_lmax_clear", k_mg_lmax_clear, 1, PHF_MG_MAX_LEVELS, 0, mg->nlev,
+                   mg->lmax);
+    mg->fine_rows_ready = false;
+    if (row_blocks > 0)
+        PHF_LAUNCH(ctx, "k_mg_setup_rows", k_mg_setup_rows, row_blocks, NT, 0, mg->d_setup,
+                   mg->nlev, cheb ? 1 : 0, mg->lmax);
     PHF_LAUNCH(ctx, "k_mg_weights", k_mg_weights, 1, PHF_MG_MAX_LEVELS, 0, mg->nlev, mg->nu,
                cheb ? 1 : 0, (float)mg->omega, (float)mg->range, mg->lmax, mg->wts);
     if (mg->cinv) {
@@ -1208,6 +1172,17 @@ int phf_mg_apply32(phf_mg* mg, const double* r, bool first_done, double* part_rz
     const int top = mg->nlev - 1;
     if (mg->lev[top].nf == 0) return PHF_OK;
     return vcycle(mg, top, r, first_done, nullptr, mg->z32, part_rz, iflags);
+}
+
+int phf_mg_fine_rows(phf_mg* mg, phf_mg_rows* out)
+{
+    phf_ctx* ctx = mg->lev[0].mesh->ctx;
+    const int top = mg->nlev - 1;
+    phf_mg_level& F = mg->lev[top];
+    PHF_LAUNCH(ctx, "k_mg_lmax_clear", k_mg_lmax_clear, 1, PHF_MG_MAX_LEVELS, 0, mg->nlev, mg->lmax);
+    *out = phf_mg_rows{F.col4, F.val4, F.diag32, F.dinv32, mg->lmax + top};
+    mg->fine_rows_ready = true;
+    return PHF_OK;
 }
 
 phf_mg_top phf_mg_top_view(phf_mg* mg)

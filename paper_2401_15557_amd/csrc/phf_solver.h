@@ -26,6 +26,7 @@ struct phf_ns {
     phf_mesh* mesh = nullptr;
     phf_mg* mg = nullptr;         // multilevel preconditioner (owned)
     bool mg_on = false;           // use it (else Jacobi)
+    bool fuse_fine_rows = false;  // the next operator build also writes mg's finest rows
     int32_t nE = 0, nf = 0, L = 0, nbv = 0;
     // symbolic (per mesh)
     int32_t* elem_red = nullptr;  // 3 nE: reduced row of local edge l (-1 Dirichlet)
@@ -88,6 +89,9 @@ struct phf_mg_params {
     int32_t sweeps = 0, smoother = 0;
     double omega = 0.0, range = 0.0;
 };
+// Checks the multigrid options and builds the hierarchy (first use) without
+// its numeric part; nothing for Jacobi.
+int phf_ns_prepare_precond(phf_ns* ns, int32_t precond, const phf_mg_params& mp);
 // Chooses Jacobi or the multilevel preconditioner (built on first use, its
 // coarse operators recomputed for A = cK K + cM M and coeffs' a_T).
 int phf_ns_set_precond(phf_ns* ns, int32_t precond, const phf_mg_params& mp,

@@ -81,7 +81,10 @@ __global__ __launch_bounds__(NT) void k_ns_blocks(int32_t nE, const double* __re
 // ELL-5 rows of the reduced operator straight from the edge tables and the
 // element blocks B (column major; unused slots point at the diagonal with
 // value 0): columns, values B[s0] + B[s1] of each entry's sources, and the
-// inverse diagonal (1 where it is not positive).
+// inverse diagonal (1 where it is not positive). With FINE also the
+// multigrid preconditioner's finest-level rows (phf_scale_row, from the same
+// values) and their Gershgorin bound.
+template <bool FINE>
 __global__ __launch_bounds__(NT) void k_ns_ellval(int32_t nf, const int32_t* __restrict__ red_edge,
                                                   const int2* __restrict__ edge_elems,
                                                   const int8_t* __restrict__ led,
@@ -91,28 +94,51 @@ __global__ __launch_bounds__(NT) void k_ns_ellval(int32_t nf, const int32_t* __r
                                                   const double* __restrict__ B,
                                                   int32_t* __restrict__ ell_col,
                                                   double* __restrict__ ell_val,
-                                                  double* __restrict__ dinv)
+                                                  double* __restrict__ dinv, phf_mg_rows fr)
 {
     const int32_t r = blockIdx.x * NT + threadIdx.x;
-    if (r >= nf) return;
-    int32_t col[5], s0[5], s1[5];
-    const int n = phf_reduced_entries(red_edge[r], edge_elems, led, ledTN, elem_edges, red_row,
-                                      col, s0, s1);
-    double d = 0.0;
+    float gs = 0.0f;  // Gershgorin sum of the row (FINE)
+    if (r < nf) {
+        int32_t col[5], s0[5], s1[5];
+        const int n = phf_reduced_entries(red_edge[r], edge_elems, led, ledTN, elem_edges,
+                                          red_row, col, s0, s1);
+        double v[5];
+        double d = 0.0;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const int64_t slot = (int64_t)k * nf + r;
-        if (k < n) {
-            const double v = B[s0[k]] + (s1[k] >= 0 ? B[s1[k]] : 0.0);
+        for (int k = 0; k < 5; ++k) {
+            const int64_t slot = (int64_t)k * nf + r;
+            if (k < n) {
+                v[k] = B[s0[k]] + (s1[k] >= 0 ? B[s1[k]] : 0.0);
+                if (col[k] == r) d = v[k];
+            } else {
+                col[k] = r;
+                v[k] = 0.0;
+            }
             ell_col[slot] = col[k];
-            ell_val[slot] = v;
-            if (col[k] == r) d = v;
-        } else {
-            ell_col[slot] = r;
-            ell_val[slot] = 0.0;
+            ell_val[slot] = v[k];
+        }
+        dinv[r] = d > 0.0 ? 1.0 / d : 1.0;
+        if (FINE) gs = phf_scale_row(r, nf, col, v, fr.col4, fr.val4, fr.diag, fr.dinv);
+    }
+    if (FINE) {
+        // block maximum; merged into the bound only where it raises the value
+        // already there (the bound only grows, so a stale read costs at most
+        // an unneeded atomic)
+        __shared__ float wm[NT / 64];
+        float m = gs;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float b = wm[0];
+#pragma unroll
+            for (int w = 1; w < NT / 64; ++w) b = fmaxf(b, wm[w]);
+            const uint32_t bits = __float_as_uint(b);
+            if (bits > __hip_atomic_load(fr.lmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                atomicMax(fr.lmax, bits);
         }
     }
-    dinv[r] = d > 0.0 ? 1.0 / d : 1.0;
 }
 
 __global__ __launch_bounds__(NT) void k_ns_rowh(int32_t L, const int32_t* __restrict__ C_rowptr,
@@ -748,10 +774,17 @@ int phf_ns_operator(phf_ns* ns, const double* K, const double* M, const double* 
     phf_ctx* ctx = mesh->ctx;
     PHF_LAUNCH(ctx, "k_ns_blocks", k_ns_blocks, nblk(ns->nE), NT, 0, ns->nE, K, M, D, cK, cM, cD,
                ns->Ablk, ns->B);
+    // with a multigrid preconditioner about to be set up for this operator,
+    // its finest-level rows are written in the same pass
+    const bool fine = ns->mg && ns->fuse_fine_rows && ns->nf > 0;
+    ns->fuse_fine_rows = false;
+    phf_mg_rows fr{};
+    if (fine) TRY(phf_mg_fine_rows(ns->mg, &fr));
+    else if (ns->mg) ns->mg->fine_rows_ready = false;
     if (ns->nf > 0)
-        PHF_LAUNCH(ctx, "k_ns_ellval", k_ns_ellval, nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge,
-                   mesh->edge_elems, mesh->led, mesh->ledTN, mesh->elem_edges, mesh->red_row,
-                   ns->B, ns->ell_col, ns->ell_val, ns->dinv);
+        PHF_LAUNCH(ctx, "k_ns_ellval", fine ? k_ns_ellval<true> : k_ns_ellval<false>, nblk(ns->nf),
+                   NT, 0, ns->nf, mesh->red_edge, mesh->edge_elems, mesh->led, mesh->ledTN,
+                   mesh->elem_edges, mesh->red_row, ns->B, ns->ell_col, ns->ell_val, ns->dinv, fr);
     if (ns->L > 0)
         PHF_LAUNCH(ctx, "k_ns_rowh", k_ns_rowh, nblk(ns->L), NT, 0, ns->L, mesh->C_rowptr, C,
                    ns->row_h);
@@ -961,10 +994,8 @@ int phf_ns_bicg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_e
     return PHF_OK;
 }
 
-int phf_ns_set_precond(phf_ns* ns, int32_t precond, const phf_mg_params& mp,
-                       const phf_coeffs* co, double cK, double cM)
+int phf_ns_prepare_precond(phf_ns* ns, int32_t precond, const phf_mg_params& mp)
 {
-    ns->mg_on = false;
     if (precond != PHF_PRECOND_MULTIGRID) return PHF_OK;
     phf_ctx* ctx = ns->mesh->ctx;
     if (mp.sweeps < 0 || mp.sweeps > PHF_MG_MAX_SWEEPS)
@@ -983,6 +1014,15 @@ int phf_ns_set_precond(phf_ns* ns, int32_t precond, const phf_mg_params& mp,
     ns->mg->nu = mp.sweeps > 0 ? mp.sweeps : jacobi ? 2 : 4;
     ns->mg->omega = mp.omega > 0 ? mp.omega : 0.8;
     ns->mg->range = mp.range > 0 ? mp.range : 10.0;
+    return PHF_OK;
+}
+
+int phf_ns_set_precond(phf_ns* ns, int32_t precond, const phf_mg_params& mp,
+                       const phf_coeffs* co, double cK, double cM)
+{
+    ns->mg_on = false;
+    if (precond != PHF_PRECOND_MULTIGRID) return PHF_OK;
+    TRY(phf_ns_prepare_precond(ns, precond, mp));
     TRY(phf_mg_numeric(ns->mg, co, cK, cM));
     ns->mg_on = true;
     return PHF_OK;
@@ -1035,13 +1075,17 @@ extern "C" int phf_solve(phf_mesh* mesh, const phf_coeffs* co, const phf_system*
         return phf_set_error(ctx, PHF_EINVAL, "phf_solve: unknown preconditioner %d", o.precond);
     phf_ns* ns = nullptr;
     TRY(phf_ns_get(mesh, &ns));
-    TRY(phf_ns_operator(ns, sys->K, sys->M, sys->C, 1.0, co->delta, conv_term ? sys->D : nullptr,
-                        1.0));
     phf_mg_params mp;
     mp.sweeps = o.mg_sweeps;
     mp.smoother = o.mg_smoother;
     mp.omega = o.mg_omega;
     mp.range = o.mg_range;
+    // the multigrid hierarchy exists before the operator, so that the
+    // operator kernel writes its finest rows too
+    TRY(phf_ns_prepare_precond(ns, o.precond, mp));
+    ns->fuse_fine_rows = o.precond == PHF_PRECOND_MULTIGRID;
+    TRY(phf_ns_operator(ns, sys->K, sys->M, sys->C, 1.0, co->delta, conv_term ? sys->D : nullptr,
+                        1.0));
     TRY(phf_ns_set_precond(ns, o.precond, mp, co, 1.0, co->delta));
     TRY(phf_ns_rhs(ns, sys->F, sys->bD));
     // both iterations start from w = 0 (the CG initialisation writes it)
