@@ -64,8 +64,8 @@ def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None, jacobi=Fa
     later ones get it from the CG update) 8 + 4 (dinv) + 4 + 4 = 20 B/row;
     last finest sweep, which also writes z (fp32 for CG) and reduces r.z,
     32 + 4 + 4 + 8 (r) + 4 (z) = 52 B/row; residual 32 + 4 (diag) + 4 + 4 +
-    4 (r) = 48 B/row; prolongation 40 (P) + 8 (x in and out) B/fine row +
-    4 B/coarse row; restriction from level l: per coarse triangle 36 B of fine
+    4 (r) = 48 B/row; prolongation 20 (five int32 columns) + 4 (five 4-bit
+    weight codes) + 8 (x in and out) = 32 B/fine row + 4 B/coarse row; restriction from level l: per coarse triangle 36 B of fine
     row ids, 4 B code word, 12 B of sums written, plus the fine residual once
     (4 B/fine row), then per coarse row 8 (positions) + 8 (two sums) + 4
     (dinv) in, 4 (D^-1 b) + 4 (first sweep) out = 28 B.
@@ -83,7 +83,7 @@ def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None, jacobi=Fa
             mg[f"k_mg_smooth_z.L{l}"] = 52 * n
         mg[f"k_mg_resid.L{l}"] = 48 * n
         if l > 0:
-            mg[f"k_mg_prolong.L{l}"] = 48 * n + 4 * level_nf[l - 1]
+            mg[f"k_mg_prolong.L{l}"] = 32 * n + 4 * level_nf[l - 1]
             if level_nE:
                 mg[f"k_mg_restrict.L{l}"] = 52 * level_nE[l - 1] + 4 * n
             mg[f"k_mg_collect.L{l}"] = 28 * level_nf[l - 1]

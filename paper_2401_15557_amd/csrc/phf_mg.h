@@ -55,7 +55,7 @@ struct phf_mg_dev_level {
     const float *val = nullptr, *diag = nullptr, *dinv = nullptr;
     float *x = nullptr, *y = nullptr, *b = nullptr, *r = nullptr;  // b holds D^-1 b
     const int32_t* P_col = nullptr;  // prolongation from the next coarser level
-    const float* P_val = nullptr;
+    const uint32_t* P_code = nullptr;
     const int32_t* rows9 = nullptr;  // restriction to the next coarser level
     float* t = nullptr;
     const int32_t* ecode_c = nullptr;  // element codes of the next coarser mesh
@@ -81,7 +81,7 @@ struct phf_mg_setup_level {
     const int2* edge_elems_c = nullptr;
     const int8_t *led_c = nullptr, *ledTN_c = nullptr;
     int32_t* P_col = nullptr;  // outputs of the tables
-    float* P_val = nullptr;
+    uint32_t* P_code = nullptr;
     int32_t* rows9 = nullptr;
     int2* sel_c = nullptr;
     const double* B = nullptr;  // operator: element blocks (coarse levels) or
@@ -107,9 +107,11 @@ struct phf_mg_level {
     float *val4 = nullptr, *diag32 = nullptr, *dinv32 = nullptr;
     // V-cycle vectors (single precision); b holds the scaled D^-1 b
     float *x = nullptr, *y = nullptr, *b = nullptr, *r = nullptr;
-    // prolongation from the next coarser level (ELL-5 over this level's rows)
+    // prolongation from the next coarser level: ELL-5 columns over this
+    // level's rows and per row the five weights, each a multiple of 1/4 in
+    // [-1, 1], as 4-bit codes c (weight (c - 4) / 4, slot k in bits 4k..4k+3)
     int32_t* P_col = nullptr;
-    float* P_val = nullptr;
+    uint32_t* P_code = nullptr;
     // restriction to the next coarser level: fine rows of the nine fine edges
     // in each coarse triangle (slot-major, 9 x nE_coarse), per-triangle sums
     // (3 x nE_coarse)

@@ -43,7 +43,7 @@ __device__ inline void d_mg_prolong_build(int32_t rf,
     int32_t nf_f, int32_t nEc, const int32_t* __restrict__ red_edge_f,
     const int2* __restrict__ edge_elems_f, const int8_t* __restrict__ led_f,
     const int8_t* __restrict__ ledTN_f, const int32_t* __restrict__ elem_edges_c,
-    const int32_t* __restrict__ red_row_c, int32_t* __restrict__ P_col, float* __restrict__ P_val)
+    const int32_t* __restrict__ red_row_c, int32_t* __restrict__ P_col, uint32_t* __restrict__ P_code)
 {
     if (rf >= nf_f) return;
     const int32_t e = red_edge_f[rf];
@@ -86,11 +86,20 @@ __device__ inline void d_mg_prolong_build(int32_t rf,
             val[q] += scale * w[k];
         }
     }
+    // every weight is a multiple of 1/4 in [-1, 1]: four bits per slot
+    uint32_t code = 0;
     for (int k = 0; k < 5; ++k) {
         const int64_t slot = (int64_t)k * nf_f + rf;
         P_col[slot] = k < n ? col[k] : 0;
-        P_val[slot] = k < n ? val[k] : 0.0f;
+        code |= (uint32_t)((int)((k < n ? val[k] : 0.0f) * 4.0f) + 4) << (4 * k);
     }
+    P_code[rf] = code;
+}
+
+// Weight of slot k of a prolongation row from its code (exact).
+__device__ inline float prolong_weight(uint32_t code, int k)
+{
+    return (float)((int)((code >> (4 * k)) & 15u) - 4) * 0.25f;
 }
 
 // Fine rows of the nine fine edges inside coarse triangle p (-1 where the
@@ -175,18 +184,6 @@ __global__ __launch_bounds__(1024) void k_mg_gj(int32_t n, double* __restrict__ 
 // The per-row helpers take their pointers as template parameters, so that a
 // caller can pass pointers typed as device memory or local data share and the
 // compiler emits the matching (not flat) loads and stores.
-template <typename PC, typename PV, typename PX>
-__device__ inline float ell5(int32_t r, int32_t n, PC __restrict__ col, PV __restrict__ val,
-                             PX __restrict__ x)
-{
-    float s = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const int64_t slot = (int64_t)k * n + r;
-        s = fmaf(val[slot], x[col[slot]], s);
-    }
-    return s;
-}
 
 // The cycle's operator rows are scaled by the inverse diagonal: four
 // off-diagonal slots of D^-1 A (ELL-4, slot-major; unused slots hold column r
@@ -296,11 +293,24 @@ __device__ inline void row_collect(int32_t c, PS __restrict__ sel, PT __restrict
     x[c] = omega * h;
 }
 
-__device__ inline void row_prolong(int32_t i, int32_t n, const int32_t* __restrict__ P_col,
-                                   const float* __restrict__ P_val, const float* __restrict__ xc,
-                                   float* __restrict__ x)
+// Prolongation of row r: sum over its five slots of weight times the coarse
+// value (unused slots: column 0, weight 0).
+template <typename PC, typename PW, typename PX>
+__device__ inline float prolong_sum(int32_t r, int32_t n, PC __restrict__ col, PW __restrict__ code,
+                                    PX __restrict__ xc)
 {
-    x[i] += ell5(i, n, P_col, P_val, xc);
+    const uint32_t c = code[r];
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) s = fmaf(prolong_weight(c, k), xc[col[(int64_t)k * n + r]], s);
+    return s;
+}
+
+__device__ inline void row_prolong(int32_t i, int32_t n, const int32_t* __restrict__ P_col,
+                                   const uint32_t* __restrict__ P_code,
+                                   const float* __restrict__ xc, float* __restrict__ x)
+{
+    x[i] += prolong_sum(i, n, P_col, P_code, xc);
 }
 
 // Coarsest level: x = A^-1 b with b = D (D^-1 b).
@@ -498,13 +508,13 @@ __global__ __launch_bounds__(NT) void k_mg_collect(int32_t nc, const int2* __res
 }
 
 __global__ __launch_bounds__(NT) void k_mg_prolong(int32_t n, const int32_t* __restrict__ P_col,
-                                                   const float* __restrict__ P_val,
+                                                   const uint32_t* __restrict__ P_code,
                                                    const float* __restrict__ xc,
                                                    float* __restrict__ x, const int* iflags)
 {
     if (iflags && iflags[0]) return;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
-        row_prolong(i, n, P_col, P_val, xc, x);
+        row_prolong(i, n, P_col, P_code, xc, x);
 }
 
 // The whole V-cycle on levels 0..top of the descriptor table in one
@@ -533,7 +543,7 @@ struct tail_lv {
     gmem_ptr<float> x;
     gmem_ptr<const float> y, b;
     gmem_ptr<const int32_t> P_col;
-    gmem_ptr<const float> P_val;
+    gmem_ptr<const uint32_t> P_code;
     gmem_ptr<const int32_t> rows9, ecode_c;
     gmem_ptr<const int32_t> sel;  // int2 entries as int32 pairs
     gmem_ptr<const float> w;
@@ -555,7 +565,7 @@ __device__ inline tail_lv tail_level(const phf_mg_dev_level* __restrict__ lv, in
                    (gmem_ptr<const float>)L.y,
                    (gmem_ptr<const float>)L.b,
                    (gmem_ptr<const int32_t>)L.P_col,
-                   (gmem_ptr<const float>)L.P_val,
+                   (gmem_ptr<const uint32_t>)L.P_code,
                    (gmem_ptr<const int32_t>)L.rows9,
                    (gmem_ptr<const int32_t>)L.ecode_c,
                    (gmem_ptr<const int32_t>)L.sel,
@@ -660,7 +670,7 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
         if (C.n > 0) {  // (uniform branch) no coarse unknowns: no correction
             const float* xc = lds + C.sx;
             tail_rows(
-                L.n, tid, [&](int32_t i) { return u[i] + ell5(i, L.n, L.P_col, L.P_val, xc); },
+                L.n, tid, [&](int32_t i) { return u[i] + prolong_sum(i, L.n, L.P_col, L.P_code, xc); },
                 [&](int32_t i, float y) { u[i] = y; });
             __syncthreads();
         }
@@ -736,7 +746,7 @@ __global__ __launch_bounds__(NT) void k_mg_setup_tables(const phf_mg_setup_level
     const int32_t t = threadIdx.x;
     if (b < L.b[1]) {
         d_mg_prolong_build((b - L.b[0]) * NT + t, L.nf, L.nEc, L.red_edge, L.edge_elems, L.led,
-                           L.ledTN, L.elem_edges_c, L.red_row_c, L.P_col, L.P_val);
+                           L.ledTN, L.elem_edges_c, L.red_row_c, L.P_col, L.P_code);
     } else if (b < L.b[2]) {
         d_mg_rows9((b - L.b[1]) * NT + t, L.nEc, L.elem_edges, L.red_row, L.rows9);
     } else {
@@ -829,8 +839,9 @@ void phf_mg_destroy(phf_mg* mg)
         phf_mg_level& L = mg->lev[l];
         phf_dfree(L.aT);
         phf_dfree(L.B);
-        float* f[] = {L.val4, L.diag32, L.dinv32, L.x, L.y, L.b, L.r, L.P_val, L.t};
+        float* f[] = {L.val4, L.diag32, L.dinv32, L.x, L.y, L.b, L.r, L.t};
         for (float* p : f) phf_dfree(p);
+        phf_dfree(L.P_code);
         phf_dfree(L.col4);
         phf_dfree(L.P_col);
         if (l == mg->nlev - 1) phf_dfree(mg->z32);
@@ -888,7 +899,7 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             // prolongation from level l-1
             phf_mg_level& Cl = mg->lev[l - 1];
             TRY(phf_dmalloc(ctx, &L.P_col, 5 * nf, "multigrid P columns"));
-            TRY(phf_dmalloc(ctx, &L.P_val, 5 * nf, "multigrid P values"));
+            TRY(phf_dmalloc(ctx, &L.P_code, (size_t)nf, "multigrid P weights"));
             // restriction tables
             const int32_t nEc = Cl.mesh->nE, nc = Cl.mesh->n_free;
             TRY(phf_dmalloc(ctx, &L.rows9, 9 * (size_t)nEc, "multigrid restriction rows"));
@@ -942,7 +953,7 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             if (l > 0) {
                 d.nEc = mg->lev[l - 1].mesh->nE;
                 d.P_col = L.P_col;
-                d.P_val = L.P_val;
+                d.P_code = L.P_code;
                 d.rows9 = L.rows9;
                 d.t = L.t;
                 d.ecode_c = mg->lev[l - 1].mesh->ecode;
@@ -1001,7 +1012,7 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             d.led_c = mc->led;
             d.ledTN_c = mc->ledTN;
             d.P_col = L.P_col;
-            d.P_val = L.P_val;
+            d.P_code = L.P_code;
             d.rows9 = L.rows9;
             d.sel_c = Cl.sel;
             d.b[0] = blk;
@@ -1142,7 +1153,7 @@ int vcycle(phf_mg* mg, int l, const double* r_top, bool first_done, double* z64,
         PHF_LAUNCH(ctx, mg_name(NM_COLLECT, l), k_mg_collect, grid_for(C.nf), NT, 0, C.nf, C.sel,
                    L.t, C.dinv32, level_weights(mg, l - 1), kc, C.b, xc, iflags);
         TRY(vcycle(mg, l - 1, nullptr, false, nullptr, nullptr, nullptr, iflags));
-        PHF_LAUNCH(ctx, mg_name(NM_PROLONG, l), k_mg_prolong, g, NT, 0, n, L.P_col, L.P_val, C.x,
+        PHF_LAUNCH(ctx, mg_name(NM_PROLONG, l), k_mg_prolong, g, NT, 0, n, L.P_col, L.P_code, C.x,
                    L.x, iflags);
     }
     const int last = r_top ? mg->nu - 1 : mg->nu;
