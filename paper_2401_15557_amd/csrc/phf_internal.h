@@ -154,6 +154,9 @@ struct phf_mesh {
     // reduced (edge-midpoint) operator: rows = non-Dirichlet edges
     int32_t* red_row = nullptr;    // n_edges: reduced index, -1 for Dirichlet
     int32_t* red_edge = nullptr;   // n_free: edge of reduced row
+    // per element, the rows of its local edges l (3 nE, element-major)
+    int32_t* elem_row = nullptr;   // multiplier row (-1 Neumann)
+    int32_t* elem_red = nullptr;   // reduced row (-1 Dirichlet)
     unsigned long long* d_nnzR = nullptr;  // entries of the reduced operator (device)
 };
 

@@ -382,8 +382,11 @@ __device__ inline void d_saddle_dof(int32_t bid, int32_t nE, const int32_t* __re
                                                     const int32_t* __restrict__ tiles,
                                                     const int32_t* __restrict__ elem_edges,
                                                     const int32_t* __restrict__ edge_row,
+                                                    const int32_t* __restrict__ red_row,
                                                     int32_t* __restrict__ S_rowptr,
-                                                    int32_t* __restrict__ S_col)
+                                                    int32_t* __restrict__ S_col,
+                                                    int32_t* __restrict__ elem_row,
+                                                    int32_t* __restrict__ elem_red)
 {
     __shared__ int32_t sh[256 / 64 + 1];
     __shared__ int32_t scol[256 * 15];
@@ -399,6 +402,16 @@ __device__ inline void d_saddle_dof(int32_t bid, int32_t nE, const int32_t* __re
     const int32_t base = 15 * m0 - 2 * tiles[bid];  // first entry of the block
     if (m < nE) {
         const int32_t N = 3 * nE;
+        // the rows of the three local edges, gathered once (also kept per
+        // element for the solver)
+        int32_t er[3];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const int32_t e = elem_edges[3 * (int64_t)m + l];
+            er[l] = edge_row[e];
+            elem_row[3 * (int64_t)m + l] = er[l];
+            elem_red[3 * (int64_t)m + l] = red_row[e];
+        }
         int32_t s = 15 * (int32_t)threadIdx.x - 2 * ex;  // offset in the block
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -413,8 +426,8 @@ __device__ inline void d_saddle_dof(int32_t bid, int32_t nE, const int32_t* __re
                 l2 = t;
             }
             int32_t k = s + 3;
-            if (PHF_CODE_TYPE(code, l1) != 2) scol[k++] = N + edge_row[elem_edges[3 * (int64_t)m + l1]];
-            if (PHF_CODE_TYPE(code, l2) != 2) scol[k++] = N + edge_row[elem_edges[3 * (int64_t)m + l2]];
+            if (PHF_CODE_TYPE(code, l1) != 2) scol[k++] = N + er[l1];
+            if (PHF_CODE_TYPE(code, l2) != 2) scol[k++] = N + er[l2];
             s = k;
         }
     }
@@ -712,6 +725,8 @@ static void mesh_free(phf_mesh* m)
     phf_dfree(m->S_col);
     phf_dfree(m->red_row);
     phf_dfree(m->red_edge);
+    phf_dfree(m->elem_row);
+    phf_dfree(m->elem_red);
     phf_dfree(m->d_nnzR);
 }
 
@@ -838,15 +853,17 @@ __global__ __launch_bounds__(256) void k_rows(rows_args a)
 // element mask and the reduced-operator size (a bounded range of blocks).
 struct tail_args {
     int32_t nE, L, ntE, b1, b2, nred;  // range ends: saddle rows, C tiles, Neumann mask; reduced-count blocks
-    const int32_t *ecode, *etiles, *elem_edges, *edge_row, *C_rowptr;
-    int32_t *S_rowptr, *S_col, *C_tile;
+    const int32_t *ecode, *etiles, *elem_edges, *edge_row, *red_row, *C_rowptr;
+    int32_t *S_rowptr, *S_col, *C_tile, *elem_row, *elem_red;
     uint64_t* neu_mask;
     unsigned long long* nnzR;
 };
 __global__ __launch_bounds__(256) void k_build_tail(tail_args a)
 {
     const int32_t b = blockIdx.x;
-    if (b < a.ntE) d_saddle_dof(b, a.nE, a.ecode, a.etiles, a.elem_edges, a.edge_row, a.S_rowptr, a.S_col);
+    if (b < a.ntE)
+        d_saddle_dof(b, a.nE, a.ecode, a.etiles, a.elem_edges, a.edge_row, a.red_row, a.S_rowptr,
+                     a.S_col, a.elem_row, a.elem_red);
     else if (b < a.b1) d_c_tiles(b - a.ntE, a.L, a.C_rowptr, a.C_tile);
     else if (b < a.b2) d_neu_mask(b - a.b1, a.nE, a.ecode, a.neu_mask);
     else d_reduced_count(b - a.b2, a.nred, a.nE, a.ecode, a.nnzR);
@@ -1202,6 +1219,8 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     TRY(phf_dmalloc(ctx, &M->C_tile, (size_t)(L + 255) / 256 + 1, "C tile bases"));
     TRY(phf_dmalloc(ctx, &M->neu_mask, ((size_t)nE + 63) / 64, "Neumann element mask"));
     TRY(phf_dmalloc(ctx, &M->d_nnzR, 1, "reduced count"));
+    TRY(phf_dmalloc(ctx, &M->elem_row, (size_t)N, "element multiplier rows"));
+    TRY(phf_dmalloc(ctx, &M->elem_red, (size_t)N, "element reduced rows"));
     PHF_HIP(ctx, hipMemsetAsync(M->d_nnzR, 0, sizeof(unsigned long long), ctx->stream));
     {
         tail_args a{};
@@ -1215,6 +1234,9 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
         a.etiles = T.etiles;
         a.elem_edges = M->elem_edges;
         a.edge_row = M->edge_row;
+        a.red_row = M->red_row;
+        a.elem_row = M->elem_row;
+        a.elem_red = M->elem_red;
         a.C_rowptr = M->C_rowptr;
         a.S_rowptr = M->S_rowptr;
         a.S_col = M->S_col;
@@ -1227,7 +1249,7 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     M->nnz_R = -1;
     // later work on the mesh runs in stream order behind these kernels
     if (!parent) PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    M->bytes = (int64_t)nC * 16 + (int64_t)nE * (16 + 48 + 4) + (int64_t)ne * (8 + 8 + 1 + 1 + 1 + 4 + 4) +
+    M->bytes = (int64_t)nC * 16 + (int64_t)nE * (16 + 48 + 4 + 24) + (int64_t)ne * (8 + 8 + 1 + 1 + 1 + 4 + 4) +
                (int64_t)nE * 12 + (int64_t)(nD + nN) * 4 + (int64_t)L * (4 + 8 + 4) +
                M->nnz_C * 4 + ((int64_t)N + L + 1) * 4 + M->nnz_S * 4 + (int64_t)nf * 8;
     return PHF_OK;

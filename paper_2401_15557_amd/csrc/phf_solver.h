@@ -28,9 +28,9 @@ struct phf_ns {
     bool mg_on = false;           // use it (else Jacobi)
     bool fuse_fine_rows = false;  // the next operator build also writes mg's finest rows
     int32_t nE = 0, nf = 0, L = 0, nbv = 0;
-    // symbolic (per mesh)
-    int32_t* elem_red = nullptr;  // 3 nE: reduced row of local edge l (-1 Dirichlet)
-    int32_t* elem_row = nullptr;  // 3 nE: multiplier row of local edge l (-1 Neumann)
+    // symbolic (per mesh; the element tables are the mesh's)
+    const int32_t* elem_red = nullptr;  // 3 nE: reduced row of local edge l (-1 Dirichlet)
+    const int32_t* elem_row = nullptr;  // 3 nE: multiplier row of local edge l (-1 Neumann)
     int32_t* ell_col = nullptr;   // 5 nf, column-major ELL of R
     double* row_h = nullptr;      // L: |E|/2 of each multiplier row
     // numeric
@@ -52,6 +52,7 @@ struct phf_ns {
     double *rh = nullptr, *s = nullptr, *sh = nullptr, *t = nullptr;
     double* scal = nullptr;       // device scalars
     int* iflags = nullptr;        // [0] done, [1] iterations
+    int* jflag = nullptr;         // raised: interior constraint rows with a right-hand side
     bool have_operator = false;
     int32_t next_it = 0;          // index of the next CG iteration issued
 };

@@ -20,19 +20,6 @@ __device__ inline void apply_P(const double w[3], double U[3])
     U[2] = s - 2.0 * w[2];
 }
 
-__global__ __launch_bounds__(NT) void k_ns_symbolic(int32_t nE, const int32_t* __restrict__ elem_edges,
-                                                    const int32_t* __restrict__ red_row,
-                                                    const int32_t* __restrict__ edge_row,
-                                                    int32_t* __restrict__ elem_red,
-                                                    int32_t* __restrict__ elem_row)
-{
-    int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (g >= 3 * (int64_t)nE) return;
-    int32_t e = elem_edges[g];
-    elem_red[g] = red_row[e];
-    elem_row[g] = edge_row[e];
-}
-
 // A_T = cK K_T + cD D_T + cM M_T (D nullable) and B_T = P^T A_T P; A_T need
 // not be symmetric. A tile of NT elements is staged in LDS so that the
 // 9-value element rows are read and written with coalesced accesses.
@@ -163,8 +150,23 @@ __device__ inline void tile_store(T* __restrict__ g, int64_t m0, int32_t nt, con
     for (int32_t q = threadIdx.x; q < W * nt; q += NT) g[W * m0 + q] = s[q];
 }
 
+// Raises *jflag when an interior (non-Dirichlet) multiplier row has a
+// non-zero constraint right-hand side, i.e. when k_ns_known has jumps to
+// gather; it never lowers it (k_ns_gather does, after use), so a flag left
+// raised only costs the gathers. One store per block at most.
+__global__ __launch_bounds__(NT) void k_ns_jumpflag(int32_t L, const int2* __restrict__ row_nodes,
+                                                    const double* __restrict__ rhs2,
+                                                    int* __restrict__ jflag)
+{
+    int any = 0;
+    for (int32_t r = blockIdx.x * NT + threadIdx.x; r < L; r += gridDim.x * NT)
+        any |= row_nodes[r].x >= 0 && rhs2[r] != 0.0;
+    if (__syncthreads_or(any) && threadIdx.x == 0) *jflag = 1;
+}
+
 // Known midpoint values (Dirichlet) and T+-side jumps (interior rows with a
-// non-zero right-hand side), and the element part of the reduced rhs,
+// non-zero right-hand side; gathered only when *jflag is raised), and the
+// element part of the reduced rhs,
 // c_T = P^T (rhs1_T - A_T P kv_T). Element records go through LDS.
 __global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int32_t* __restrict__ ecode,
                                                  const int32_t* __restrict__ elem_row,
@@ -172,9 +174,11 @@ __global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int32_t* __re
                                                  const double* __restrict__ rhs1,
                                                  const double* __restrict__ rhs2,
                                                  const double* __restrict__ Ablk,
+                                                 const int* __restrict__ jflag,
                                                  double* __restrict__ kv, double* __restrict__ cs)
 {
     __shared__ double sA[9 * NT], sR[3 * NT], sK[3 * NT], sC[3 * NT];
+    const bool jumps = *jflag != 0;
     __shared__ int32_t sRow[3 * NT];
     const int tid = threadIdx.x;
     const int64_t m0 = (int64_t)blockIdx.x * NT;
@@ -190,7 +194,7 @@ __global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int32_t* __re
         for (int l = 0; l < 3; ++l) {
             const int t = PHF_CODE_TYPE(code, l);
             double v = 0.0;
-            if (t == 1 || (t == 0 && PHF_CODE_TPLUS(code, l))) {
+            if (t == 1 || (jumps && t == 0 && PHF_CODE_TPLUS(code, l))) {
                 const int32_t r = sRow[3 * tid + l];
                 v = -rhs2[r] / (2.0 * row_h[r]);
             }
@@ -220,9 +224,10 @@ __global__ __launch_bounds__(NT) void k_ns_gather(int32_t nf, const int32_t* __r
                                                   const int8_t* __restrict__ led,
                                                   const int8_t* __restrict__ ledTN,
                                                   const double* __restrict__ cs,
-                                                  double* __restrict__ b)
+                                                  double* __restrict__ b, int* __restrict__ jflag)
 {
     int32_t r = blockIdx.x * NT + threadIdx.x;
+    if (r == 0) *jflag = 0;  // the jumps of this right-hand side are used
     if (r >= nf) return;
     int32_t e = red_edge[r];
     int2 tt = edge_elems[e];
@@ -706,12 +711,13 @@ void phf_ns_destroy(phf_ns* ns)
 {
     if (!ns) return;
     if (ns->mg) phf_mg_destroy(ns->mg);
-    phf_dfree(ns->elem_red); phf_dfree(ns->elem_row); phf_dfree(ns->ell_col);
+    phf_dfree(ns->ell_col);
     phf_dfree(ns->row_h); phf_dfree(ns->B); phf_dfree(ns->Ablk);
     phf_dfree(ns->ell_val); phf_dfree(ns->dinv); phf_dfree(ns->kv); phf_dfree(ns->cs);
     phf_dfree(ns->b); phf_dfree(ns->w); phf_dfree(ns->r); phf_dfree(ns->z);
     phf_dfree(ns->p); phf_dfree(ns->q); phf_dfree(ns->part); phf_dfree(ns->scal);
     phf_dfree(ns->iflags);
+    phf_dfree(ns->jflag);
     phf_dfree(ns->rh); phf_dfree(ns->s); phf_dfree(ns->sh); phf_dfree(ns->t);
     delete ns;
 }
@@ -726,14 +732,14 @@ int phf_ns_create(phf_mesh* mesh, phf_ns** out)
     ns->nf = mesh->n_free;
     ns->L = mesh->L;
     ns->nbv = (int32_t)std::min<int64_t>(std::max<int64_t>(nblk(ns->nf), 1), MAXB);
+    ns->elem_red = mesh->elem_red;
+    ns->elem_row = mesh->elem_row;
     const size_t e3 = 3 * (size_t)ns->nE, e9 = 9 * (size_t)ns->nE, nf = ns->nf;
     int rc = 0;
     rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_col, 5 * nf, "solver ELL columns");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->B, e9, "solver blocks");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_val, 5 * nf, "solver ELL values");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->dinv, nf, "solver diagonal");
-    rc = rc ? rc : phf_dmalloc(ctx, &ns->elem_red, e3, "solver element rows");
-    rc = rc ? rc : phf_dmalloc(ctx, &ns->elem_row, e3, "solver element rows");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->row_h, (size_t)ns->L, "solver row h");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->Ablk, e9, "solver blocks");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->kv, e3, "solver known values");
@@ -747,14 +753,14 @@ int phf_ns_create(phf_mesh* mesh, phf_ns** out)
     rc = rc ? rc : phf_dmalloc(ctx, &ns->part, P_NARR * MAXB, "solver partials");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->scal, NS_NSCAL, "solver scalars");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->iflags, 4, "solver flags");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->jflag, 1, "solver jump flag");
     if (rc) {
         phf_ns_destroy(ns);
         return rc;
     }
     auto launch = [&]() -> int {
-        PHF_LAUNCH(ctx, "k_ns_symbolic", k_ns_symbolic, nblk(3 * (int64_t)ns->nE), NT, 0, ns->nE,
-                   mesh->elem_edges, mesh->red_row, mesh->edge_row, ns->elem_red, ns->elem_row);
         PHF_HIP(ctx, hipMemsetAsync(ns->w, 0, sizeof(double) * std::max<size_t>(nf, 1), ctx->stream));
+        PHF_HIP(ctx, hipMemsetAsync(ns->jflag, 0, sizeof(int), ctx->stream));
         PHF_HIP(ctx, hipMemsetAsync(ns->iflags, 0, 4 * sizeof(int), ctx->stream));
         return PHF_OK;
     };
@@ -796,11 +802,15 @@ int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2)
 {
     phf_mesh* mesh = ns->mesh;
     phf_ctx* ctx = mesh->ctx;
+    if (ns->L > 0)
+        PHF_LAUNCH(ctx, "k_ns_jumpflag", k_ns_jumpflag,
+                   (unsigned)std::min<int64_t>(nblk(ns->L), 1024), NT, 0, ns->L, mesh->row_nodes,
+                   rhs2, ns->jflag);
     PHF_LAUNCH(ctx, "k_ns_known", k_ns_known, nblk(ns->nE), NT, 0, ns->nE, mesh->ecode,
-               ns->elem_row, ns->row_h, rhs1, rhs2, ns->Ablk, ns->kv, ns->cs);
+               ns->elem_row, ns->row_h, rhs1, rhs2, ns->Ablk, ns->jflag, ns->kv, ns->cs);
     if (ns->nf > 0)
         PHF_LAUNCH(ctx, "k_ns_gather", k_ns_gather, nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge,
-                   mesh->edge_elems, mesh->led, mesh->ledTN, ns->cs, ns->b);
+                   mesh->edge_elems, mesh->led, mesh->ledTN, ns->cs, ns->b, ns->jflag);
     return PHF_OK;
 }
 
