@@ -800,7 +800,20 @@ __global__ __launch_bounds__(NT) void k_mg_setup_rows(const phf_mg_setup_level* 
     }
 }
 
-unsigned grid_for(int32_t n) { return (unsigned)std::min<int64_t>(std::max<int64_t>(nblk(n), 1), 1024); }
+#ifndef PHF_MG_GRID_MAX
+#define PHF_MG_GRID_MAX (1 << 30)
+#endif
+// Grid of a per-step kernel over n rows (grid-stride beyond the cap), and of
+// the last finest sweep, whose per-block partial sums must match the outer
+// iteration's grid (at most PHF_PART_MAX blocks).
+unsigned grid_for(int32_t n)
+{
+    return (unsigned)std::min<int64_t>(std::max<int64_t>(nblk(n), 1), PHF_MG_GRID_MAX);
+}
+unsigned part_grid(int32_t n)
+{
+    return (unsigned)std::min<int64_t>(std::max<int64_t>(nblk(n), 1), PHF_PART_MAX);
+}
 
 // Trace names carry the level ("k_mg_smooth.L9"), counted from the coarsest
 // mesh, so per-launch byte counts can be attributed to a level.
@@ -1159,10 +1172,12 @@ int vcycle(phf_mg* mg, int l, const double* r_top, bool first_done, double* z64,
     const int last = r_top ? mg->nu - 1 : mg->nu;
     for (int s = 0; s < last; ++s) TRY(smooth(mg, l, s, iflags));
     if (r_top && z32)
-        PHF_LAUNCH(ctx, mg_name(NM_SMOOTHZ, l), k_mg_smooth_z<float>, g, NT, 0, n, L.col4, L.val4,
+        PHF_LAUNCH(ctx, mg_name(NM_SMOOTHZ, l), k_mg_smooth_z<float>, part_grid(n), NT, 0, n,
+                   L.col4, L.val4,
                    L.b, w, mg->nu - 1, L.x, r_top, z32, part_rz, iflags);
     else if (r_top)
-        PHF_LAUNCH(ctx, mg_name(NM_SMOOTHZ, l), k_mg_smooth_z<double>, g, NT, 0, n, L.col4,
+        PHF_LAUNCH(ctx, mg_name(NM_SMOOTHZ, l), k_mg_smooth_z<double>, part_grid(n), NT, 0, n,
+                   L.col4,
                    L.val4, L.b, w, mg->nu - 1, L.x, r_top, z64, part_rz, iflags);
     return PHF_OK;
 }

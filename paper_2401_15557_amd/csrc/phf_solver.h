@@ -22,6 +22,13 @@
 
 struct phf_mg;
 
+// Blocks of the solver's vector kernels at most, i.e. partial-sum slots per
+// reduced quantity (each block writes one and every block of the next kernel
+// reduces all of them in the same order).
+#ifndef PHF_PART_MAX
+#define PHF_PART_MAX 1024
+#endif
+
 struct phf_ns {
     phf_mesh* mesh = nullptr;
     phf_mg* mg = nullptr;         // multilevel preconditioner (owned)

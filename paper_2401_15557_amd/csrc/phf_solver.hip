@@ -7,7 +7,7 @@
 namespace {
 
 constexpr int NT = 256;
-constexpr int MAXB = 1024;  // max blocks of the vector kernels = partial-sum slots
+constexpr int MAXB = PHF_PART_MAX;  // max blocks of the vector kernels = partial-sum slots
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 
