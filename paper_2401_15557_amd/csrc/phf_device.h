@@ -238,3 +238,36 @@ __device__ inline float phf_scale_row(int32_t r, int32_t n, const int32_t* c, co
     dinv[r] = (float)di;
     return s;
 }
+
+// ---- XCD-aware row blocks ----------------------------------------------------
+// Workgroups are dealt to the eight XCDs of the device in turn, and each XCD
+// has its own L2. Row kernels whose rows gather neighbouring values of the
+// same vector therefore give the workgroups of one XCD one contiguous range
+// of row tiles, through which they stride together (so each XCD streams one
+// window of rows at a time): the lines that neighbouring rows share are then
+// fetched into one L2 only. With one block per tile this is a permutation of
+// the blocks.
+template <int NT, typename F>
+__device__ inline void phf_for_rows_xcd(int32_t n, F f)
+{
+    const int32_t nb = gridDim.x, b = blockIdx.x, x = b % 8, q = nb / 8, rem = nb % 8;
+    const int32_t nbx = q + (x < rem ? 1 : 0);             // blocks on this XCD
+    const int64_t first = (int64_t)x * q + min(x, rem);     // blocks on lower XCDs
+    const int64_t tiles = ((int64_t)n + NT - 1) / NT;
+    const int64_t t0 = tiles * first / nb, t1 = tiles * (first + nbx) / nb;
+    for (int64_t t = t0 + b / 8; t < t1; t += nbx) {
+        const int64_t i = t * NT + threadIdx.x;
+        if (i < n) f((int32_t)i);
+    }
+}
+// Calls f(i) for the rows of this workgroup: XCD ranges (XCD) or the plain
+// grid-stride order.
+template <bool XCD, int NT, typename F>
+__device__ inline void phf_for_rows(int32_t n, F f)
+{
+    if (XCD) {
+        phf_for_rows_xcd<NT>(n, f);
+    } else {
+        for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) f(i);
+    }
+}

@@ -413,6 +413,12 @@ __device__ inline float d_mg_crows(int32_t r,
     return phf_scale_row(r, nf, col, v, col4, val4, diag, dinv);
 }
 
+// Row order of the per-step kernels (phf_for_rows): XCD-contiguous chunks
+// where the rows gather from neighbouring rows of the same vector.
+constexpr bool XCD_SMOOTH = PHF_XCD_BITS & 1, XCD_RESID = PHF_XCD_BITS & 2,
+               XCD_PROLONG = PHF_XCD_BITS & 4, XCD_RESTRICT = PHF_XCD_BITS & 8,
+               XCD_COLLECT = PHF_XCD_BITS & 16, XCD_SMOOTHZ = PHF_XCD_BITS & 32;
+
 // First sweep from x = 0 on the finest level: also rounds the right-hand side
 // (the double-precision residual of the outer iteration) once, scaled.
 __global__ __launch_bounds__(NT) void k_mg_smooth0_top(int32_t n, const float* __restrict__ dinv,
@@ -423,11 +429,11 @@ __global__ __launch_bounds__(NT) void k_mg_smooth0_top(int32_t n, const float* _
 {
     if (iflags && iflags[0]) return;
     const float omega = w[0];
-    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+    phf_for_rows<XCD_SMOOTH, NT>(n, [&](int32_t i) {
         const float h = (float)b64[i] * dinv[i];
         bh[i] = h;
         x[i] = omega * h;
-    }
+    });
 }
 
 // FINEST only separates the finest level's launches under their own symbol
@@ -442,8 +448,7 @@ __global__ __launch_bounds__(NT) void k_mg_smooth(int32_t n, const int32_t* __re
 {
     if (iflags && iflags[0]) return;
     const float omega = w[k];
-    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
-        row_smooth(i, n, col, val, bh, omega, x, y);
+    phf_for_rows<XCD_SMOOTH, NT>(n, [&](int32_t i) { row_smooth(i, n, col, val, bh, omega, x, y); });
 }
 
 // Last sweep on the finest level, which also hands the cycle's result to the
@@ -463,11 +468,11 @@ __global__ __launch_bounds__(NT) void k_mg_smooth_z(int32_t n, const int32_t* __
     __shared__ double sh[NT / 64];
     const float omega = w[k];
     double s = 0.0;
-    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+    phf_for_rows<XCD_SMOOTHZ, NT>(n, [&](int32_t i) {
         const float zi = x[i] + omega * sres(i, n, col, val, bh, x);
         z[i] = (ZT)zi;
         s = fma(r[i], (double)zi, s);
-    }
+    });
     const double t = phf_block_sum_f64<NT>(s, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
@@ -480,8 +485,7 @@ __global__ __launch_bounds__(NT) void k_mg_resid(int32_t n, const int32_t* __res
                                                  float* __restrict__ r, const int* iflags)
 {
     if (iflags && iflags[0]) return;
-    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
-        row_resid(i, n, col, val, diag, bh, x, r);
+    phf_for_rows<XCD_RESID, NT>(n, [&](int32_t i) { row_resid(i, n, col, val, diag, bh, x, r); });
 }
 
 __global__ __launch_bounds__(NT) void k_mg_restrict(int32_t nEc, const int32_t* __restrict__ rows9,
@@ -490,8 +494,7 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(int32_t nEc, const int32_t* 
                                                     float* __restrict__ t, const int* iflags)
 {
     if (iflags && iflags[0]) return;
-    for (int32_t p = blockIdx.x * NT + threadIdx.x; p < nEc; p += gridDim.x * NT)
-        tri_restrict(p, nEc, rows9, ecode_c, rf, t);
+    phf_for_rows<XCD_RESTRICT, NT>(nEc, [&](int32_t p) { tri_restrict(p, nEc, rows9, ecode_c, rf, t); });
 }
 
 __global__ __launch_bounds__(NT) void k_mg_collect(int32_t nc, const int2* __restrict__ sel,
@@ -503,8 +506,7 @@ __global__ __launch_bounds__(NT) void k_mg_collect(int32_t nc, const int2* __res
 {
     if (iflags && iflags[0]) return;
     const float omega = w[k];
-    for (int32_t c = blockIdx.x * NT + threadIdx.x; c < nc; c += gridDim.x * NT)
-        row_collect(c, sel, t, dinv, omega, bh, x);
+    phf_for_rows<XCD_COLLECT, NT>(nc, [&](int32_t c) { row_collect(c, sel, t, dinv, omega, bh, x); });
 }
 
 __global__ __launch_bounds__(NT) void k_mg_prolong(int32_t n, const int32_t* __restrict__ P_col,
@@ -513,8 +515,7 @@ __global__ __launch_bounds__(NT) void k_mg_prolong(int32_t n, const int32_t* __r
                                                    float* __restrict__ x, const int* iflags)
 {
     if (iflags && iflags[0]) return;
-    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
-        row_prolong(i, n, P_col, P_code, xc, x);
+    phf_for_rows<XCD_PROLONG, NT>(n, [&](int32_t i) { row_prolong(i, n, P_col, P_code, xc, x); });
 }
 
 // The whole V-cycle on levels 0..top of the descriptor table in one

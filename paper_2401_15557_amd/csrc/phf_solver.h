@@ -25,6 +25,12 @@ struct phf_mg;
 // Blocks of the solver's vector kernels at most, i.e. partial-sum slots per
 // reduced quantity (each block writes one and every block of the next kernel
 // reduces all of them in the same order).
+// Row order of the row kernels (bit set: XCD-contiguous chunks): 1 sweeps,
+// 2 residual, 4 prolongation, 8 restriction, 16 gather, 32 last finest sweep,
+// 64 the conjugate-gradient direction.
+#ifndef PHF_XCD_BITS
+#define PHF_XCD_BITS 0x33
+#endif
 #ifndef PHF_PART_MAX
 #define PHF_PART_MAX 1024
 #endif

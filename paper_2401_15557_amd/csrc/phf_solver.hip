@@ -375,13 +375,13 @@ __global__ __launch_bounds__(NT) void k_cg_dir(int32_t nf, int32_t it, int32_t n
         if (blockIdx.x == 0 && threadIdx.x == 0) scal[NS_RR] = rr;
     }
     double s = 0.0;
-    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
+    phf_for_rows<(PHF_XCD_BITS & 64) != 0, NT>(nf, [&](int32_t i) {
         const double pi = fma(beta, p[i], (double)z[i]);
         const double qi = fma(beta, q[i], ell_row(i, nf, col, val, z));
         p[i] = pi;
         q[i] = qi;
         s = fma(pi, qi, s);
-    }
+    });
     const double t = phf_block_sum_f64<NT>(s, sh);
     if (threadIdx.x == 0) part[P_PQ * MAXB + blockIdx.x] = t;
 }
