@@ -181,6 +181,21 @@ __global__ __launch_bounds__(1024) void k_mg_gj(int32_t n, double* __restrict__ 
     for (int64_t q = tid; q < (int64_t)n * n; q += nth) A[q] = W[q];
 }
 
+// Tables and vectors that a per-step kernel reads once and nothing reads
+// again before they are rewritten (prolongation and restriction tables, the
+// outer iteration's residual) are loaded non-temporally with PHF_NT_MG, so
+// that they displace less of the operator rows and iterates that the next
+// sweep reads again.
+#ifndef PHF_NT_MG
+#define PHF_NT_MG 1
+#endif
+template <bool NTL, typename P, typename I>
+__device__ inline auto ldx(P p, I i) -> std::remove_cv_t<std::remove_reference_t<decltype(p[i])>>
+{
+    if constexpr (NTL) return __builtin_nontemporal_load(&p[i]);
+    else return p[i];
+}
+
 // The per-row helpers take their pointers as template parameters, so that a
 // caller can pass pointers typed as device memory or local data share and the
 // compiler emits the matching (not flat) loads and stores.
@@ -230,21 +245,21 @@ __device__ inline void row_resid(int32_t i, int32_t n, PC __restrict__ col, PV _
 // on the shape of p, so the weights are the constants below. rf must hold at
 // least one element (the gathers read a clamped index, so that all nine row
 // loads are issued before the first gather waits).
-template <typename PR9, typename PE, typename PF, typename PT>
+template <bool NTL = false, typename PR9, typename PE, typename PF, typename PT>
 __device__ inline void tri_restrict(int32_t p, int32_t nEc, PR9 __restrict__ rows9,
                                     PE __restrict__ ecode_c, PF __restrict__ rf,
                                     PT __restrict__ t)
 {
     int32_t row[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) row[k] = rows9[(int64_t)k * nEc + p];
+    for (int k = 0; k < 9; ++k) row[k] = ldx<NTL>(rows9, (int64_t)k * nEc + p);
     float v[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const float g = rf[row[k] >= 0 ? row[k] : 0];
         v[k] = row[k] >= 0 ? g : 0.0f;
     }
-    const int32_t code = ecode_c[p];
+    const int32_t code = ldx<NTL>(ecode_c, p);
     float s[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) s[e] = PHF_CODE_TYPE(code, e) == 0 ? 0.5f : 1.0f;
@@ -295,14 +310,15 @@ __device__ inline void row_collect(int32_t c, PS __restrict__ sel, PT __restrict
 
 // Prolongation of row r: sum over its five slots of weight times the coarse
 // value (unused slots: column 0, weight 0).
-template <typename PC, typename PW, typename PX>
+template <bool NTL = false, typename PC, typename PW, typename PX>
 __device__ inline float prolong_sum(int32_t r, int32_t n, PC __restrict__ col, PW __restrict__ code,
                                     PX __restrict__ xc)
 {
-    const uint32_t c = code[r];
+    const uint32_t c = ldx<NTL>(code, r);
     float s = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) s = fmaf(prolong_weight(c, k), xc[col[(int64_t)k * n + r]], s);
+    for (int k = 0; k < 5; ++k)
+        s = fmaf(prolong_weight(c, k), xc[ldx<NTL>(col, (int64_t)k * n + r)], s);
     return s;
 }
 
@@ -310,7 +326,7 @@ __device__ inline void row_prolong(int32_t i, int32_t n, const int32_t* __restri
                                    const uint32_t* __restrict__ P_code,
                                    const float* __restrict__ xc, float* __restrict__ x)
 {
-    x[i] += prolong_sum(i, n, P_col, P_code, xc);
+    x[i] += prolong_sum<PHF_NT_MG>(i, n, P_col, P_code, xc);
 }
 
 // Coarsest level: x = A^-1 b with b = D (D^-1 b).
@@ -430,7 +446,7 @@ __global__ __launch_bounds__(NT) void k_mg_smooth0_top(int32_t n, const float* _
     if (iflags && iflags[0]) return;
     const float omega = w[0];
     phf_for_rows<XCD_SMOOTH, NT>(n, [&](int32_t i) {
-        const float h = (float)b64[i] * dinv[i];
+        const float h = (float)ldx<PHF_NT_MG>(b64, i) * dinv[i];
         bh[i] = h;
         x[i] = omega * h;
     });
@@ -471,7 +487,7 @@ __global__ __launch_bounds__(NT) void k_mg_smooth_z(int32_t n, const int32_t* __
     phf_for_rows<XCD_SMOOTHZ, NT>(n, [&](int32_t i) {
         const float zi = x[i] + omega * sres(i, n, col, val, bh, x);
         z[i] = (ZT)zi;
-        s = fma(r[i], (double)zi, s);
+        s = fma(ldx<PHF_NT_MG>(r, i), (double)zi, s);
     });
     const double t = phf_block_sum_f64<NT>(s, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
@@ -494,7 +510,7 @@ __global__ __launch_bounds__(NT) void k_mg_restrict(int32_t nEc, const int32_t* 
                                                     float* __restrict__ t, const int* iflags)
 {
     if (iflags && iflags[0]) return;
-    phf_for_rows<XCD_RESTRICT, NT>(nEc, [&](int32_t p) { tri_restrict(p, nEc, rows9, ecode_c, rf, t); });
+    phf_for_rows<XCD_RESTRICT, NT>(nEc, [&](int32_t p) { tri_restrict<PHF_NT_MG>(p, nEc, rows9, ecode_c, rf, t); });
 }
 
 __global__ __launch_bounds__(NT) void k_mg_collect(int32_t nc, const int2* __restrict__ sel,

@@ -255,6 +255,31 @@ __global__ __launch_bounds__(NT) void k_ns_gather(int32_t nf, const int32_t* __r
 // a kernel argument, so an unrolled chain can be captured in a graph; once
 // done is set, the remaining kernels of the chain return immediately.
 
+#ifndef PHF_NT_CG
+#define PHF_NT_CG 1
+#endif
+// Streamed loads and stores of the conjugate-gradient vectors and operator,
+// marked non-temporal with PHF_NT_CG: the cycle's sweeps between them then
+// find more of their operator rows still in the caches.
+template <typename T>
+__device__ inline T ntl(const T* p)
+{
+#if PHF_NT_CG
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+template <typename T>
+__device__ inline void nts(T* p, T v)
+{
+#if PHF_NT_CG
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
 template <typename XT>
 __device__ inline double ell_row(int32_t r, int32_t nf, const int32_t* __restrict__ col,
                                  const double* __restrict__ val, const XT* __restrict__ x)
@@ -263,7 +288,7 @@ __device__ inline double ell_row(int32_t r, int32_t nf, const int32_t* __restric
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         int64_t slot = (int64_t)k * nf + r;
-        s = fma(val[slot], (double)x[col[slot]], s);
+        s = fma(ntl(val + slot), (double)x[ntl(col + slot)], s);
     }
     return s;
 }
@@ -376,10 +401,10 @@ __global__ __launch_bounds__(NT) void k_cg_dir(int32_t nf, int32_t it, int32_t n
     }
     double s = 0.0;
     phf_for_rows<(PHF_XCD_BITS & 64) != 0, NT>(nf, [&](int32_t i) {
-        const double pi = fma(beta, p[i], (double)z[i]);
-        const double qi = fma(beta, q[i], ell_row(i, nf, col, val, z));
-        p[i] = pi;
-        q[i] = qi;
+        const double pi = fma(beta, ntl(p + i), (double)z[i]);
+        const double qi = fma(beta, ntl(q + i), ell_row(i, nf, col, val, z));
+        nts(p + i, pi);
+        nts(q + i, qi);
         s = fma(pi, qi, s);
     });
     const double t = phf_block_sum_f64<NT>(s, sh);
@@ -441,11 +466,11 @@ __global__ __launch_bounds__(NT) void k_cg_upd_mg(int32_t nf, int32_t it, int32_
     const float w0 = wts[0];
     double s_rr = 0.0;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
-        w[i] = fma(alpha, p[i], w[i]);
-        const double ri = fma(-alpha, q[i], r[i]);
-        r[i] = ri;
+        nts(w + i, fma(alpha, ntl(p + i), ntl(w + i)));
+        const double ri = fma(-alpha, ntl(q + i), ntl(r + i));
+        nts(r + i, ri);
         s_rr = fma(ri, ri, s_rr);
-        const float h = (float)ri * dinv32[i];
+        const float h = (float)ri * ntl(dinv32 + i);
         bh[i] = h;
         x[i] = w0 * h;
     }
