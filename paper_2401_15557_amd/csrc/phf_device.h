@@ -200,13 +200,18 @@ __device__ inline int phf_reduced_entries(int32_t e, const int2* edge_elems, con
     return n;
 }
 
+// Four-lane vectors for 16-byte row loads and stores.
+typedef int32_t phf_i4 __attribute__((ext_vector_type(4)));
+typedef float phf_f4 __attribute__((ext_vector_type(4)));
+
 // Single-precision scaled copy of row r of a reduced operator given as five
 // (column, value) slots, unused ones holding column r and value 0: the
 // off-diagonal entries of D^-1 A in slot order (a free edge has at most four
 // neighbours; the remaining slots get column r and value 0), the diagonal
 // a_rr and its inverse (1 where a_rr <= 0, as for the double-precision
-// inverse diagonal), stored slot-major over n rows. Returns the row's
-// Gershgorin sum 1 + sum_j |a_ij| / a_ii in single precision.
+// inverse diagonal), stored row-major (the row's four columns at col4[4r..],
+// its four values at val4[4r..]; n is unused). Returns the row's Gershgorin
+// sum 1 + sum_j |a_ij| / a_ii in single precision.
 __device__ inline float phf_scale_row(int32_t r, int32_t n, const int32_t* c, const double* v,
                                       int32_t* __restrict__ col4, float* __restrict__ val4,
                                       float* __restrict__ diag, float* __restrict__ dinv)
@@ -226,14 +231,17 @@ __device__ inline float phf_scale_row(int32_t r, int32_t n, const int32_t* c, co
         }
     }
     const double di = d > 0.0 ? 1.0 / d : 1.0;
+    (void)n;
     float s = 1.0f;
+    phf_f4 f4;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const float f = (float)(v4[k] * di);
-        col4[(int64_t)k * n + r] = c4[k];
-        val4[(int64_t)k * n + r] = f;
+        f4[k] = f;
         s += fabsf(f);
     }
+    *(phf_i4*)(col4 + 4 * (int64_t)r) = phf_i4{c4[0], c4[1], c4[2], c4[3]};
+    *(phf_f4*)(val4 + 4 * (int64_t)r) = f4;
     diag[r] = d > 0.0 ? (float)d : 1.0f;
     dinv[r] = (float)di;
     return s;

@@ -199,21 +199,39 @@ __device__ inline auto ldx(P p, I i) -> std::remove_cv_t<std::remove_reference_t
 // The per-row helpers take their pointers as template parameters, so that a
 // caller can pass pointers typed as device memory or local data share and the
 // compiler emits the matching (not flat) loads and stores.
+template <typename T>
+using gmem_ptr = __attribute__((address_space(1))) T*;
+
+// Row r of a row-major ELL-4 array (four consecutive entries, 16-byte
+// aligned) in one 16-byte load.
+__device__ inline phf_i4 ld_row4(const int32_t* p, int32_t r) { return *(const phf_i4*)(p + 4 * (int64_t)r); }
+__device__ inline phf_f4 ld_row4(const float* p, int32_t r) { return *(const phf_f4*)(p + 4 * (int64_t)r); }
+__device__ inline phf_i4 ld_row4(gmem_ptr<const int32_t> p, int32_t r)
+{
+    return *(gmem_ptr<const phf_i4>)(p + 4 * (int64_t)r);
+}
+__device__ inline phf_f4 ld_row4(gmem_ptr<const float> p, int32_t r)
+{
+    return *(gmem_ptr<const phf_f4>)(p + 4 * (int64_t)r);
+}
 
 // The cycle's operator rows are scaled by the inverse diagonal: four
-// off-diagonal slots of D^-1 A (ELL-4, slot-major; unused slots hold column r
-// and value 0) and an implicit unit diagonal; right-hand sides are kept as
+// off-diagonal entries of D^-1 A (ELL-4, row-major: the row's four columns,
+// then in a second array its four values; unused entries hold column r and
+// value 0) and an implicit unit diagonal; right-hand sides are kept as
 // D^-1 b. sres is then the scaled residual D^-1 (b - A x) of row i.
 template <typename PC, typename PV, typename PB, typename PX>
 __device__ inline float sres(int32_t i, int32_t n, PC __restrict__ col, PV __restrict__ val,
                              PB __restrict__ bh, PX __restrict__ x)
 {
+    (void)n;
+    const phf_i4 c = ld_row4(col, i);
+    const phf_f4 v = ld_row4(val, i);
     float s = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int64_t slot = (int64_t)k * n + i;
-        s = fmaf(val[slot], x[col[slot]], s);
-    }
+    s = fmaf(v.x, x[c.x], s);
+    s = fmaf(v.y, x[c.y], s);
+    s = fmaf(v.z, x[c.z], s);
+    s = fmaf(v.w, x[c.w], s);
     return bh[i] - x[i] - s;
 }
 
@@ -551,8 +569,6 @@ constexpr int TAIL_NT = 1024;
 // pointers typed as such, so that their loads are global (not flat) loads,
 // whose counter is separate from the local data share's; a step can then
 // issue all its memory loads before it waits for any.
-template <typename T>
-using gmem_ptr = __attribute__((address_space(1))) T*;
 struct tail_lv {
     int32_t n, nEc, sx, sy, sb, st;
     gmem_ptr<const int32_t> col;
