@@ -324,7 +324,7 @@ def main():
         phfem.phf_synchronize(h)
         t2 = time.perf_counter()
         st = phfem.phf_solve(mh, co, sysd, t["U"], t["Lam"], rtol=a.rtol, max_iter=200000,
-                             check_every=32 if pc == phfem.PHF_PRECOND_JACOBI else 1,
+                             check_every=32 if pc == phfem.PHF_PRECOND_JACOBI else 0,
                              precond=pc)
         t3 = time.perf_counter()
         for c in reversed(chain):

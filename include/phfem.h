@@ -333,7 +333,10 @@ typedef struct {
     int32_t max_iter;    /* 0 = 20000                                      */
     double rtol;         /* relative residual of the reduced system; 0 = 1e-10 */
     int32_t check_every; /* host convergence test period (iterations); 0 = 8,
-                            or 1 with the multigrid preconditioner */
+                            or with the multigrid preconditioner: CG predicts
+                            from the residual decay so far how many to issue
+                            before the next test (about one at most past
+                            convergence), BiCGSTAB tests after each */
     int32_t saddle_residual; /* 1: compute the saddle residual into stats   */
     int32_t precond;     /* PHF_PRECOND_*                                  */
     int32_t mg_sweeps;   /* sweeps before and after the coarse correction,

@@ -740,8 +740,8 @@ void phf_ns_destroy(phf_ns* ns)
     phf_dfree(ns->row_h); phf_dfree(ns->B); phf_dfree(ns->Ablk);
     phf_dfree(ns->ell_val); phf_dfree(ns->dinv); phf_dfree(ns->kv); phf_dfree(ns->cs);
     phf_dfree(ns->b); phf_dfree(ns->w); phf_dfree(ns->r); phf_dfree(ns->z);
-    phf_dfree(ns->p); phf_dfree(ns->q); phf_dfree(ns->part); phf_dfree(ns->scal);
-    phf_dfree(ns->iflags);
+    phf_dfree(ns->p); phf_dfree(ns->q); phf_dfree(ns->part);
+    phf_dfree(ns->scal);  // (the flags share its allocation)
     phf_dfree(ns->jflag);
     phf_dfree(ns->rh); phf_dfree(ns->s); phf_dfree(ns->sh); phf_dfree(ns->t);
     delete ns;
@@ -776,8 +776,9 @@ int phf_ns_create(phf_mesh* mesh, phf_ns** out)
     rc = rc ? rc : phf_dmalloc(ctx, &ns->p, nf, "solver p");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->q, nf, "solver q");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->part, P_NARR * MAXB, "solver partials");
-    rc = rc ? rc : phf_dmalloc(ctx, &ns->scal, NS_NSCAL, "solver scalars");
-    rc = rc ? rc : phf_dmalloc(ctx, &ns->iflags, 4, "solver flags");
+    // the scalars and, behind them, the flags: one block, read back at once
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->scal, NS_NSCAL + 2, "solver scalars and flags");
+    if (!rc) ns->iflags = reinterpret_cast<int*>(ns->scal + NS_NSCAL);
     rc = rc ? rc : phf_dmalloc(ctx, &ns->jflag, 1, "solver jump flag");
     if (rc) {
         phf_ns_destroy(ns);
@@ -912,31 +913,51 @@ int phf_ns_recover(phf_ns* ns, const double* rhs1, double* U, double* mu, double
     return PHF_OK;
 }
 
-// Host-side convergence loop shared by phf_solve and Crank-Nicolson.
+// Iterations to issue before the next convergence test when the caller leaves
+// the period to the solver (multigrid): from the mean reduction of the
+// residual norm per iteration so far, the number m still needed to reach the
+// tolerance, less one, so that at most about one iteration runs past
+// convergence; 1 until there is a rate to go by. rr0, rr: squared residual
+// norms at the start and now; goal: the squared norm to reach.
+static int32_t predicted_block(int32_t done, double rr0, double rr, double goal)
+{
+    if (done <= 0 || !(rr0 > 0.0) || !(rr > 0.0) || !(rr < rr0) || !(goal > 0.0) || rr <= goal)
+        return 1;
+    const double q = std::pow(rr / rr0, 0.5 / done);  // per-iteration factor on the norm
+    if (!(q < 0.95)) return 1;
+    const double m = std::ceil(0.5 * std::log(goal / rr) / std::log(q));
+    return (int32_t)std::min(std::max(m - 1.0, 1.0), 16.0);
+}
+
+// Host-side convergence loop of phf_solve. check_every > 0: test after every
+// check_every iterations; 0: the predicted schedule above. Each test reads the
+// solver's scalars and flags back in one copy into pinned memory.
 int phf_ns_cg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_every,
                     int32_t* iters_out, double* relres_out, int* converged, bool zero_start)
 {
     phf_ctx* ctx = ns->mesh->ctx;
     TRY(phf_ns_cg_start(ns, rtol, zero_start));
+    double* h = reinterpret_cast<double*>(ctx->h_pinned);
+    const int* hf = reinterpret_cast<const int*>(h + NS_NSCAL);
+    auto read_back = [&]() -> int {
+        PHF_HIP(ctx, hipMemcpyAsync(h, ns->scal, (NS_NSCAL + 2) * sizeof(double),
+                                    hipMemcpyDeviceToHost, ctx->stream));
+        PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        return PHF_OK;
+    };
+    TRY(read_back());
+    const double rr0 = h[NS_RR];
     int32_t done_iters = 0;
-    int hf[2] = {0, 0};
-    PHF_HIP(ctx, hipMemcpyAsync(hf, ns->iflags, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
     while (!hf[0] && done_iters < max_iter) {
-        int32_t n = std::min(check_every, max_iter - done_iters);
+        int32_t n = check_every > 0 ? check_every
+                                    : predicted_block(done_iters, rr0, h[NS_RR], h[NS_TOL2] * h[NS_BB]);
+        n = std::min(n, max_iter - done_iters);
         TRY(phf_ns_cg_iterate(ns, n));
         done_iters += n;
-        PHF_HIP(ctx, hipMemcpyAsync(hf, ns->iflags, 2 * sizeof(int), hipMemcpyDeviceToHost,
-                                    ctx->stream));
-        PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    }
-    double sc[NS_NSCAL] = {0};
-    if (ns->nf > 0) {
-        PHF_HIP(ctx, hipMemcpyAsync(sc, ns->scal, sizeof(sc), hipMemcpyDeviceToHost, ctx->stream));
-        PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        TRY(read_back());
     }
     if (iters_out) *iters_out = hf[1];
-    if (relres_out) *relres_out = sc[NS_BB] > 0 ? std::sqrt(sc[NS_RR] / sc[NS_BB]) : 0.0;
+    if (relres_out) *relres_out = h[NS_BB] > 0 ? std::sqrt(h[NS_RR] / h[NS_BB]) : 0.0;
     if (converged) *converged = ns->nf == 0 ? 1 : hf[0];
     return PHF_OK;
 }
@@ -1095,9 +1116,12 @@ extern "C" int phf_solve(phf_mesh* mesh, const phf_coeffs* co, const phf_system*
     if (opts) o = *opts;
     if (o.max_iter <= 0) o.max_iter = 20000;
     if (o.rtol <= 0) o.rtol = 1e-10;
-    // a V-cycle iteration is long enough that testing after each one costs
-    // less than the launches it would otherwise queue past convergence
-    if (o.check_every <= 0) o.check_every = o.precond == PHF_PRECOND_MULTIGRID ? 1 : 8;
+    // with the multigrid preconditioner, conjugate gradients predict how many
+    // iterations to issue between tests (0); BiCGSTAB tests after each one
+    if (o.check_every <= 0)
+        o.check_every = o.precond == PHF_PRECOND_MULTIGRID && o.method == PHF_SOLVER_NULLSPACE_CG ? 0
+                        : o.precond == PHF_PRECOND_MULTIGRID                                      ? 1
+                                                                                                  : 8;
     if (o.method != PHF_SOLVER_NULLSPACE_CG && o.method != PHF_SOLVER_NULLSPACE_BICGSTAB)
         return phf_set_error(ctx, PHF_EINVAL, "phf_solve: unknown method %d", o.method);
     if (conv_term && o.method == PHF_SOLVER_NULLSPACE_CG)
