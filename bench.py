@@ -21,7 +21,11 @@ per second through that step (Melem/s). `--precond jacobi` solves with the
 Jacobi preconditioner instead.
 
 The JSON line also carries, measured in the same process:
-  rows      per-stage milliseconds of the step and solver iterations;
+  rows      host-observed milliseconds between the calls of the step (the
+            library's calls return before their GPU work ends, so the mesh
+            build and the assembly run on in the next rows; the last row,
+            the release, waits for the solve's final kernels) and solver
+            iterations;
   assembly  the numeric assembly alone (the paper's timed computation):
             Melem/s, algorithmic GB/s and fraction of the HBM peak;
   cn        Crank-Nicolson steps/s on the parabolic configuration (unit
@@ -304,8 +308,10 @@ def main():
             chain.append(phfem.phf_mesh_refine(chain[-1]))
         mh = chain[-1]
         t1 = time.perf_counter()
-        info = phfem.phf_mesh_get_info(mh)
         if "sys" not in out:
+            # sizes for the caller-owned outputs, allocated once (the mesh is
+            # the same every step)
+            info = phfem.phf_mesh_get_info(mh)
             sysd = phfem.phf_system()
             t = dict(K=torch.empty(info.nnz_K, dtype=torch.float64, device=dev),
                      M=torch.empty(info.nnz_K, dtype=torch.float64, device=dev),
@@ -321,7 +327,6 @@ def main():
             out["level_nE"] = [phfem.phf_mesh_get_info(c).nE for c in chain]
         sysd, t = out["sys"], out["t"]
         phfem.phf_assemble(mh, co, data, sysd)
-        phfem.phf_synchronize(h)
         t2 = time.perf_counter()
         st = phfem.phf_solve(mh, co, sysd, t["U"], t["Lam"], rtol=a.rtol, max_iter=200000,
                              check_every=32 if pc == phfem.PHF_PRECOND_JACOBI else 0,

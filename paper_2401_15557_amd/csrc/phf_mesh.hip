@@ -889,14 +889,21 @@ struct build_tmp {
     }
 };
 
-int read_flags(phf_ctx* ctx, int* code, int* where)
+// The validation flags and, in the same synchronisation, `bytes` (at most 64)
+// from device address d into h (through the context's pinned words).
+int read_flags(phf_ctx* ctx, int* code, int* where, const void* d = nullptr, void* h = nullptr,
+               size_t bytes = 0)
 {
-    int h[2];
-    PHF_HIP(ctx, hipMemcpyAsync(h, ctx->d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost,
+    int64_t* p = ctx->h_pinned;
+    PHF_HIP(ctx, hipMemcpyAsync(p, ctx->d_flags, 2 * sizeof(int), hipMemcpyDeviceToHost,
                                 ctx->stream));
+    if (bytes)
+        PHF_HIP(ctx, hipMemcpyAsync(p + 1, d, bytes, hipMemcpyDeviceToHost, ctx->stream));
     PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    *code = h[0];
-    *where = h[1];
+    const int* f = reinterpret_cast<const int*>(p);
+    *code = f[0];
+    *where = f[1];
+    if (bytes) memcpy(h, p + 1, bytes);
     return PHF_OK;
 }
 
@@ -931,13 +938,6 @@ __global__ void k_flags_reset(int* flags)
 int reset_flags(phf_ctx* ctx)
 {
     PHF_LAUNCH(ctx, "k_flags_reset", k_flags_reset, 1, 1, 0, ctx->d_flags);
-    return PHF_OK;
-}
-
-int read_i32(phf_ctx* ctx, const int32_t* d, int32_t* h)
-{
-    PHF_HIP(ctx, hipMemcpyAsync(h, d, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return PHF_OK;
 }
 
@@ -1087,11 +1087,13 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
         TRY(phf_dmalloc(ctx, &T.eoff, (size_t)nC + 1, "edge offsets"));
         PHF_LAUNCH(ctx, "k_bucket_sort", k_bucket_sort, nblk(nC), 256, 0, T.keys, T.boff, nC,
                    M->elem4, T.ucount, ctx->d_flags);
-        TRY(read_flags(ctx, &bits, &where));
-        TRY(flags_to_status(ctx, bits, where, "topology"));
+        // (the scan only reads the bucket counts, which stay in range even
+        // when the topology check fails; the edge count comes back with the
+        // flags)
         PHF_HIP(ctx, hipMemsetAsync(T.ucount + nC, 0, sizeof(int32_t), ctx->stream));
         TRY(phf_scan_i32(ctx, T.ucount, T.eoff, nC + 1, T.totals));
-        TRY(read_i32(ctx, T.totals, &ne));
+        TRY(read_flags(ctx, &bits, &where, T.totals, &ne, sizeof(int32_t)));
+        TRY(flags_to_status(ctx, bits, where, "topology"));
         M->n_edges = ne;
         TRY(phf_dmalloc(ctx, &M->edge_nodes, ne, "edge nodes"));
         TRY(phf_dmalloc(ctx, &M->edge_elems, ne, "edge elements"));
@@ -1152,21 +1154,17 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
         a.etiles = T.etiles;
         PHF_LAUNCH(ctx, "k_counts", k_counts, nt + ntE, 256, 0, a);
     }
-    if (!parent) {
-        TRY(read_flags(ctx, &bits, &where));
-        TRY(flags_to_status(ctx, bits, where, "boundary"));
-    }
     phf_dfree(T.eoff);
     phf_dfree(T.mark);
     PHF_LAUNCH(ctx, "k_tile_scans", k_tile_scans, 2, 1024, 0, nt, T.tiles, T.tile_total, ntE,
                T.etiles);
     phf_cnt2 cnt{nD, nN};
     if (!parent) {
-        // (every boundary edge of a refined mesh is listed exactly once: the
-        // parent was checked)
-        PHF_HIP(ctx, hipMemcpyAsync(&cnt, T.tile_total, sizeof(cnt), hipMemcpyDeviceToHost,
-                                    ctx->stream));
-        PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        // boundary check and the boundary edge counts in one read-back (the
+        // tile scans only read the counts); every boundary edge of a refined
+        // mesh is listed exactly once: the parent was checked
+        TRY(read_flags(ctx, &bits, &where, T.tile_total, &cnt, sizeof(cnt)));
+        TRY(flags_to_status(ctx, bits, where, "boundary"));
     }
     M->L = ne - cnt.n;                          // multiplier rows
     M->n_free = ne - cnt.d;                     // free edges
@@ -1247,8 +1245,8 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     }
     phf_dfree(T.etiles);
     M->nnz_R = -1;
-    // later work on the mesh runs in stream order behind these kernels
-    if (!parent) PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    // later work on the mesh runs in stream order behind these kernels (the
+    // caller's input arrays were consumed before the first read-back)
     M->bytes = (int64_t)nC * 16 + (int64_t)nE * (16 + 48 + 4 + 24) + (int64_t)ne * (8 + 8 + 1 + 1 + 1 + 4 + 4) +
                (int64_t)nE * 12 + (int64_t)(nD + nN) * 4 + (int64_t)L * (4 + 8 + 4) +
                M->nnz_C * 4 + ((int64_t)N + L + 1) * 4 + M->nnz_S * 4 + (int64_t)nf * 8;
