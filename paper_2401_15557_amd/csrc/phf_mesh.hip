@@ -330,10 +330,20 @@ __device__ inline void d_rows(int32_t bid,
 
 // Element code words, the element-major coordinate copy, and per tile (256
 // elements) the number of Neumann edge incidences.
+// Element codes. On a refined mesh (ecode_c: the parent's codes) the edge
+// types and T+ flags follow from the parent's code (numbering Section 2.3):
+// the centre child m < nE_c has three interior edges and is their T+ side; the
+// corner child nE_c + 3T + i has the interior edge shared with the centre
+// child as local edge 0 (its T- side) and, as local edges 1 and 2, the halves
+// of the parent's edges i+1 and i+2 at vertex i, with their parent's type and
+// on the T+ side exactly where T is. Otherwise they are gathered from the
+// edge tables.
 __device__ inline void d_elem_codes(int32_t bid, int32_t nE, int4* __restrict__ elem4,
                                                     const int32_t* __restrict__ elem_edges,
                                                     const int8_t* __restrict__ etype,
                                                     const int2* __restrict__ edge_elems,
+                                                    const int32_t* __restrict__ ecode_c,
+                                                    int32_t nE_c,
                                                     const double2* __restrict__ xy,
                                                     double2* __restrict__ exy,
                                                     int32_t* __restrict__ ecode,
@@ -346,12 +356,27 @@ __device__ inline void d_elem_codes(int32_t bid, int32_t nE, int4* __restrict__ 
         int32_t ed[3];
         int code = 0;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            ed[i] = elem_edges[3 * (int64_t)m + i];
-            const int tp = etype[ed[i]];
-            nneu += tp == 2;
-            code |= tp << (2 * i);
-            if (edge_elems[ed[i]].x == m) code |= 1 << (6 + i);
+        for (int i = 0; i < 3; ++i) ed[i] = elem_edges[3 * (int64_t)m + i];
+        if (ecode_c) {
+            if (m < nE_c) {
+                code = 7 << 6;
+            } else {
+                const int32_t q = m - nE_c, ci = q % 3;
+                const int pc = ecode_c[q / 3];
+                const int e1 = (ci + 1) % 3, e2 = (ci + 2) % 3;
+                const int t1 = PHF_CODE_TYPE(pc, e1), t2 = PHF_CODE_TYPE(pc, e2);
+                nneu = (t1 == 2) + (t2 == 2);
+                code = (t1 << 2) | (t2 << 4) | (PHF_CODE_TPLUS(pc, e1) << 7) |
+                       (PHF_CODE_TPLUS(pc, e2) << 8);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int tp = etype[ed[i]];
+                nneu += tp == 2;
+                code |= tp << (2 * i);
+                if (edge_elems[ed[i]].x == m) code |= 1 << (6 + i);
+            }
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -810,6 +835,8 @@ struct counts_args {
     int* flags;
     int4* elem4;
     const int32_t* elem_edges;
+    const int32_t* ecode_c;  // refined mesh: the parent's element codes
+    int32_t nE_c;
     const double2* xy;
     double2* exy;
     int32_t* ecode;
@@ -819,8 +846,8 @@ __global__ __launch_bounds__(256) void k_counts(counts_args a)
 {
     const int32_t b = blockIdx.x;
     if (b < a.nt) d_rows_count(b, a.ne, a.etype, a.edge_elems, a.mark, a.tiles, a.flags);
-    else d_elem_codes(b - a.nt, a.nE, a.elem4, a.elem_edges, a.etype, a.edge_elems, a.xy, a.exy,
-                      a.ecode, a.etiles);
+    else d_elem_codes(b - a.nt, a.nE, a.elem4, a.elem_edges, a.etype, a.edge_elems, a.ecode_c,
+                      a.nE_c, a.xy, a.exy, a.ecode, a.etiles);
 }
 
 // Both tile scans: block 0 the edge tiles, block 1 the element tiles.
@@ -1148,6 +1175,8 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
         a.flags = ctx->d_flags;
         a.elem4 = M->elem4;
         a.elem_edges = M->elem_edges;
+        a.ecode_c = parent ? parent->ecode : nullptr;
+        a.nE_c = parent ? parent->nE : 0;
         a.xy = parent ? nullptr : M->xy;  // refined: built with the children
         a.exy = M->exy;
         a.ecode = M->ecode;
