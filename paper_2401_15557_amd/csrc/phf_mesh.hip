@@ -589,24 +589,35 @@ __device__ inline void d_refine_pairs(int32_t bid, int32_t nC, int32_t n,
 // the parent's T+ for halves.
 
 // Fine edges of group e (2 halves + inner edges with e' < e).
+// Fine edges in the group of parent edge e, summed over each tile of 256
+// parent edges (tiles[bid]) and as the exclusive prefix inside the tile
+// (pre[e]); the group's offset is the tile base (one scan over the tiles)
+// plus pre[e].
 __device__ inline void d_rt_count(int32_t bid, int32_t ne_c, const int2* __restrict__ edge_elems_c,
                                                   const int8_t* __restrict__ led_c,
                                                   const int8_t* __restrict__ ledTN_c,
                                                   const int32_t* __restrict__ elem_edges_c,
-                                                  int32_t* __restrict__ cnt)
+                                                  int32_t* __restrict__ pre,
+                                                  int32_t* __restrict__ tiles)
 {
+    __shared__ int32_t sh[256 / 64 + 1];
     const int32_t e = bid * 256 + threadIdx.x;
-    if (e >= ne_c) return;
-    const int2 tt = edge_elems_c[e];
-    int32_t c = 2;
-    for (int side = 0; side < 2; ++side) {
-        const int32_t T = side ? tt.y : tt.x;
-        if (T < 0) continue;
-        const int le = side ? ledTN_c[e] : led_c[e];
-        for (int d = 1; d <= 2; ++d)
-            if (elem_edges_c[3 * (int64_t)T + (le + d) % 3] < e) ++c;
+    int32_t c = 0;
+    if (e < ne_c) {
+        const int2 tt = edge_elems_c[e];
+        c = 2;
+        for (int side = 0; side < 2; ++side) {
+            const int32_t T = side ? tt.y : tt.x;
+            if (T < 0) continue;
+            const int le = side ? ledTN_c[e] : led_c[e];
+            for (int d = 1; d <= 2; ++d)
+                if (elem_edges_c[3 * (int64_t)T + (le + d) % 3] < e) ++c;
+        }
     }
-    cnt[e] = c;
+    int32_t tot;
+    const int32_t ex = phf_block_exscan_i32<256>(c, sh, &tot);
+    if (e < ne_c) pre[e] = ex;
+    if (threadIdx.x == 0) tiles[bid] = tot;
 }
 
 __device__ inline void d_rt_emit(int32_t bid, 
@@ -614,13 +625,14 @@ __device__ inline void d_rt_emit(int32_t bid,
     const int2* __restrict__ edge_elems_c, const int8_t* __restrict__ led_c,
     const int8_t* __restrict__ ledTN_c, const int32_t* __restrict__ elem_edges_c,
     const int4* __restrict__ elem4_c, const int8_t* __restrict__ etype_c,
-    const int32_t* __restrict__ off, int2* __restrict__ edge_nodes, int2* __restrict__ edge_elems,
+    const int32_t* __restrict__ pre, const int32_t* __restrict__ tiles,
+    int2* __restrict__ edge_nodes, int2* __restrict__ edge_elems,
     int32_t* __restrict__ elem_edges, int8_t* __restrict__ led, int8_t* __restrict__ ledTN,
     int8_t* __restrict__ etype)
 {
     const int32_t e = bid * 256 + threadIdx.x;
     if (e >= ne_c) return;
-    const int32_t base = off[e], Me = nC_c + e;
+    const int32_t base = tiles[bid] + pre[e], Me = nC_c + e;
     const int2 tt = edge_elems_c[e];
     const int2 kl = edge_nodes_c[e];
     const int32_t lo = min(kl.x, kl.y);
@@ -708,7 +720,8 @@ __device__ inline void d_rt_emit(int32_t bid,
 __device__ inline void d_rt_bnd(int32_t bid, int32_t n, const int2* __restrict__ pairs_c,
                                                 const int32_t* __restrict__ edges_c,
                                                 const int2* __restrict__ edge_nodes_c,
-                                                const int32_t* __restrict__ off,
+                                                const int32_t* __restrict__ pre,
+                                                const int32_t* __restrict__ tiles,
                                                 int32_t* __restrict__ edges_f)
 {
     const int32_t q = bid * 256 + threadIdx.x;
@@ -716,8 +729,9 @@ __device__ inline void d_rt_bnd(int32_t bid, int32_t n, const int2* __restrict__
     const int32_t e = edges_c[q];
     const int2 ab = pairs_c[q], kl = edge_nodes_c[e];
     const int32_t lo = min(kl.x, kl.y);
-    edges_f[q] = off[e] + (ab.x == lo ? 0 : 1);
-    edges_f[n + q] = off[e] + (ab.y == lo ? 0 : 1);
+    const int32_t off = tiles[e >> 8] + pre[e];
+    edges_f[q] = off + (ab.x == lo ? 0 : 1);
+    edges_f[n + q] = off + (ab.y == lo ? 0 : 1);
 }
 }  // namespace
 
@@ -782,6 +796,7 @@ struct refine_a_args {
     const int2* edge_elems_c;
     const int8_t *led_c, *ledTN_c;
     int32_t* ucount;
+    int32_t* utiles;
 };
 __global__ __launch_bounds__(256) void k_refine_a(refine_a_args a)
 {
@@ -792,7 +807,8 @@ __global__ __launch_bounds__(256) void k_refine_a(refine_a_args a)
                        a.exy_f);
     else if (b < a.b3) d_refine_pairs(b - a.b2, a.nC_c, a.nD_c, a.dir_pairs_c, a.dir_edges_c, a.dir_pairs_f);
     else if (b < a.b4) d_refine_pairs(b - a.b3, a.nC_c, a.nN_c, a.neu_pairs_c, a.neu_edges_c, a.neu_pairs_f);
-    else d_rt_count(b - a.b4, a.ne_c, a.edge_elems_c, a.led_c, a.ledTN_c, a.elem_edges_c, a.ucount);
+    else d_rt_count(b - a.b4, a.ne_c, a.edge_elems_c, a.led_c, a.ledTN_c, a.elem_edges_c, a.ucount,
+                    a.utiles);
 }
 
 // Refinement, second launch: the fine topology and the boundary edge lists.
@@ -803,7 +819,7 @@ struct refine_b_args {
     const int8_t *led_c, *ledTN_c, *etype_c;
     const int32_t* elem_edges_c;
     const int4* elem4_c;
-    const int32_t* off;
+    const int32_t *pre, *tiles;  // in-tile prefixes of the group sizes, scanned tile sums
     int2 *edge_nodes, *edge_elems;
     int32_t* elem_edges;
     int8_t *led, *ledTN, *etype;
@@ -816,12 +832,14 @@ __global__ __launch_bounds__(256) void k_refine_b(refine_b_args a)
     const int32_t b = blockIdx.x;
     if (b < a.b1)
         d_rt_emit(b, a.ne_c, a.nC_c, a.nE_c, a.edge_nodes_c, a.edge_elems_c, a.led_c, a.ledTN_c,
-                  a.elem_edges_c, a.elem4_c, a.etype_c, a.off, a.edge_nodes, a.edge_elems,
+                  a.elem_edges_c, a.elem4_c, a.etype_c, a.pre, a.tiles, a.edge_nodes, a.edge_elems,
                   a.elem_edges, a.led, a.ledTN, a.etype);
     else if (b < a.b2)
-        d_rt_bnd(b - a.b1, a.nD_c, a.dir_pairs_c, a.dir_edges_c, a.edge_nodes_c, a.off, a.dir_edges);
+        d_rt_bnd(b - a.b1, a.nD_c, a.dir_pairs_c, a.dir_edges_c, a.edge_nodes_c, a.pre, a.tiles,
+                 a.dir_edges);
     else
-        d_rt_bnd(b - a.b2, a.nN_c, a.neu_pairs_c, a.neu_edges_c, a.edge_nodes_c, a.off, a.neu_edges);
+        d_rt_bnd(b - a.b2, a.nN_c, a.neu_pairs_c, a.neu_edges_c, a.edge_nodes_c, a.pre, a.tiles,
+                 a.neu_edges);
 }
 
 // Per-tile boundary counts of the edges (blocks [0, nt)) and the element codes
@@ -848,6 +866,12 @@ __global__ __launch_bounds__(256) void k_counts(counts_args a)
     if (b < a.nt) d_rows_count(b, a.ne, a.etype, a.edge_elems, a.mark, a.tiles, a.flags);
     else d_elem_codes(b - a.nt, a.nE, a.elem4, a.elem_edges, a.etype, a.edge_elems, a.ecode_c,
                       a.nE_c, a.xy, a.exy, a.ecode, a.etiles);
+}
+
+// Exclusive scan of n tile sums in place (one workgroup).
+__global__ __launch_bounds__(1024) void k_tile_scan1(int32_t n, int32_t* __restrict__ tiles)
+{
+    d_tile_exscan<int32_t>(n, tiles, nullptr);
 }
 
 // Both tile scans: block 0 the edge tiles, block 1 the element tiles.
@@ -989,9 +1013,8 @@ int refined_tables(phf_mesh* M, const phf_mesh* P, build_tmp* T, int32_t* ne_out
     TRY(phf_dmalloc(ctx, &M->exy, 3 * (size_t)nE, "element coordinates"));
     TRY(phf_dmalloc(ctx, &M->dir_pairs, nD, "Dirichlet pairs"));
     TRY(phf_dmalloc(ctx, &M->neu_pairs, nN, "Neumann pairs"));
-    TRY(phf_dmalloc(ctx, &T->totals, 8, "totals"));
-    TRY(phf_dmalloc(ctx, &T->ucount, (size_t)ne_c + 1, "group sizes"));
-    TRY(phf_dmalloc(ctx, &T->eoff, (size_t)ne_c + 1, "group offsets"));
+    TRY(phf_dmalloc(ctx, &T->ucount, (size_t)ne_c + 1, "group size prefixes"));
+    TRY(phf_dmalloc(ctx, &T->eoff, (size_t)nblk(ne_c) + 1, "group tile sums"));
     {
         refine_a_args a{};
         a.nC_c = nC_c;
@@ -1021,10 +1044,11 @@ int refined_tables(phf_mesh* M, const phf_mesh* P, build_tmp* T, int32_t* ne_out
         a.led_c = P->led;
         a.ledTN_c = P->ledTN;
         a.ucount = T->ucount;
+        a.utiles = T->eoff;
         PHF_LAUNCH(ctx, "k_refine_a", k_refine_a, a.b4 + (int32_t)nblk(ne_c), 256, 0, a);
     }
-    // edge groups per parent edge
-    TRY(phf_scan_i32(ctx, T->ucount, T->eoff, ne_c, T->totals));
+    // edge groups per parent edge: exclusive scan of the tile sums
+    PHF_LAUNCH(ctx, "k_tile_scan1", k_tile_scan1, 1, 1024, 0, (int32_t)nblk(ne_c), T->eoff);
     M->n_edges = ne;
     TRY(phf_dmalloc(ctx, &M->edge_nodes, ne, "edge nodes"));
     TRY(phf_dmalloc(ctx, &M->edge_elems, ne, "edge elements"));
@@ -1050,7 +1074,8 @@ int refined_tables(phf_mesh* M, const phf_mesh* P, build_tmp* T, int32_t* ne_out
         a.etype_c = P->edge_type;
         a.elem_edges_c = P->elem_edges;
         a.elem4_c = P->elem4;
-        a.off = T->eoff;
+        a.pre = T->ucount;
+        a.tiles = T->eoff;
         a.edge_nodes = M->edge_nodes;
         a.edge_elems = M->edge_elems;
         a.elem_edges = M->elem_edges;
