@@ -331,3 +331,64 @@ def test_cn_multigrid_parity(ctx, oracle, use_graph):
     assert _rel(Ug, Uo) < 1e-9
     assert _rel(Lg, Lo) < 1e-8
     phfem.phf_cn_destroy(cn)
+
+
+@pytest.mark.parametrize("precond", ["multigrid", "jacobi"])
+def test_solve_interior_constraint_rhs(ctx, oracle, precond):
+    """A constraint right-hand side that is non-zero on interior multiplier
+    rows (jumps across interior edges; the assembled b_D is zero there): the
+    solver must gather those jumps, and a following solve with the assembled
+    b_D must give the plain solution again. Both against the oracle's sparse
+    LU of the same saddle systems."""
+    import torch
+    from paper_2401_15557_amd import phfem
+    pc = dict(multigrid=phfem.PHF_PRECOND_MULTIGRID, jacobi=phfem.PHF_PRECOND_JACOBI)[precond]
+    dm, m = _refined_pair(ctx, oracle, G.lshape(0), 3)
+    od, gd = _both(oracle, phfem, "sincos")
+    co = phfem.make_coeffs()
+    s, t = phfem.alloc_system(dm)
+    phfem.phf_assemble(dm.handle, co, gd, s)
+    tables = oracle.mesh_tables(m)
+    asm = oracle.assemble(m, tables, **od)
+    bD0 = t["bD"].clone()
+    L = dm.info.L
+    extra = np.random.default_rng(11).uniform(-0.1, 0.1, L)
+    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    Lam = torch.empty(L, dtype=torch.float64, device=ctx.device)
+    for bump in (True, False, True):
+        t["bD"].copy_(bD0 + torch.tensor(extra if bump else 0.0 * extra, device=ctx.device))
+        a2 = dict(asm)
+        a2["bD"] = asm["bD"] + (extra if bump else 0.0)
+        st = phfem.phf_solve(dm.handle, co, s, U, Lam, rtol=1e-13, max_iter=50000, precond=pc)
+        assert st.converged
+        Uo, Lo = oracle.solve_saddle(a2)
+        print(f"{precond} bump={bump}: iterations {st.iterations}", flush=True)
+        assert _rel(U.cpu().numpy(), Uo) < 1e-9, _rel(U.cpu().numpy(), Uo)
+        assert _rel(Lam.cpu().numpy(), Lo) < 1e-8, _rel(Lam.cpu().numpy(), Lo)
+
+
+def test_predicted_check_schedule(ctx):
+    """The default multigrid schedule (check_every = 0: the host predicts how
+    many iterations to issue between convergence tests) gives bitwise the same
+    solution and iteration count as testing after every iteration: iterations
+    issued past convergence do nothing."""
+    import torch
+    from paper_2401_15557_amd import phfem
+    dm = phfem.Mesh(ctx, G.lshape(0))
+    for _ in range(4):
+        dm = dm.refine()
+    co = phfem.make_coeffs(a_T=torch.tensor(G.per_triangle_coefficient(dm.info.nE, 2),
+                                            device=ctx.device))
+    d = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * PI * PI, 0),
+                        phfem.make_fn(phfem.PHF_FN_CONST, 1), phfem.make_fn(phfem.PHF_FN_CONST, 1))
+    s, t = phfem.alloc_system(dm)
+    phfem.phf_assemble(dm.handle, co, d, s)
+    out = []
+    for ce in (1, 0, 3):
+        U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+        L = torch.empty(dm.info.L, dtype=torch.float64, device=ctx.device)
+        st = phfem.phf_solve(dm.handle, co, s, U, L, rtol=1e-12, check_every=ce,
+                             precond=phfem.PHF_PRECOND_MULTIGRID)
+        assert st.converged
+        out.append((st.iterations, U.cpu().numpy().tobytes(), L.cpu().numpy().tobytes()))
+    assert out[0] == out[1] == out[2]
