@@ -94,9 +94,10 @@ def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None, jacobi=Fa
     return {
         **mg,
         "k_assemble": asm,
-        # reduced operator values + columns (12 B/nnz), z in (fp64 with
-        # Jacobi, the cycle's fp32 result with multigrid); p, q in and out
-        "k_cg_dir": 12 * nnzR + (40 if jacobi else 36) * nf,
+        # reduced operator: column + value of each off-diagonal entry (12 B),
+        # the diagonal value (8 B/row); z in (fp64 with Jacobi, the cycle's
+        # fp32 result with multigrid); p, q in and out
+        "k_cg_dir": 12 * (nnzR - nf) + 8 * nf + (40 if jacobi else 36) * nf,
         # read p, q, w, r; write w, r; Jacobi: dinv in, z out (fp64);
         # multigrid: the first sweep, dinv (fp32) in, D^-1 r and x out (fp32)
         "k_cg_upd": (64 if jacobi else 60) * nf,

@@ -203,6 +203,7 @@ __device__ inline int phf_reduced_entries(int32_t e, const int2* edge_elems, con
 // Four-lane vectors for 16-byte row loads and stores.
 typedef int32_t phf_i4 __attribute__((ext_vector_type(4)));
 typedef float phf_f4 __attribute__((ext_vector_type(4)));
+typedef double phf_d2 __attribute__((ext_vector_type(2)));
 
 // Single-precision scaled copy of row r of a reduced operator given as five
 // (column, value) slots, unused ones holding column r and value 0: the
@@ -210,8 +211,9 @@ typedef float phf_f4 __attribute__((ext_vector_type(4)));
 // neighbours; the remaining slots get column r and value 0), the diagonal
 // a_rr and its inverse (1 where a_rr <= 0, as for the double-precision
 // inverse diagonal), stored row-major (the row's four columns at col4[4r..],
-// its four values at val4[4r..]; n is unused). Returns the row's Gershgorin
-// sum 1 + sum_j |a_ij| / a_ii in single precision.
+// its four values at val4[4r..]; n is unused; col4 null: the columns are
+// already there). Returns the row's Gershgorin sum 1 + sum_j |a_ij| / a_ii in
+// single precision.
 __device__ inline float phf_scale_row(int32_t r, int32_t n, const int32_t* c, const double* v,
                                       int32_t* __restrict__ col4, float* __restrict__ val4,
                                       float* __restrict__ diag, float* __restrict__ dinv)
@@ -240,7 +242,7 @@ __device__ inline float phf_scale_row(int32_t r, int32_t n, const int32_t* c, co
         f4[k] = f;
         s += fabsf(f);
     }
-    *(phf_i4*)(col4 + 4 * (int64_t)r) = phf_i4{c4[0], c4[1], c4[2], c4[3]};
+    if (col4) *(phf_i4*)(col4 + 4 * (int64_t)r) = phf_i4{c4[0], c4[1], c4[2], c4[3]};
     *(phf_f4*)(val4 + 4 * (int64_t)r) = f4;
     diag[r] = d > 0.0 ? (float)d : 1.0f;
     dinv[r] = (float)di;

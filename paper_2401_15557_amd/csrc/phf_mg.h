@@ -85,7 +85,9 @@ struct phf_mg_setup_level {
     int32_t* rows9 = nullptr;
     int2* sel_c = nullptr;
     const double* B = nullptr;  // operator: element blocks (coarse levels) or
-    const int32_t* ell_col = nullptr;  // the caller's double-precision rows (finest)
+    // the caller's double-precision rows (finest): off-diagonal columns and
+    // values as row-major ELL-4, then the nf diagonal values behind the values
+    const int32_t* ell_col = nullptr;
     const double* ell_val = nullptr;
     int32_t* col4 = nullptr;  // the cycle's scaled rows
     float *val4 = nullptr, *diag = nullptr, *dinv = nullptr;
@@ -101,8 +103,9 @@ struct phf_mg_level {
     // and element blocks B_T = P^T A_T P of the re-discretised operator
     double *aT = nullptr, *B = nullptr;
     // single-precision scaled operator: the off-diagonal entries of D^-1 A
-    // (ELL-4, slot-major; unused slots hold the row itself and 0), the
-    // diagonal D and its inverse
+    // (ELL-4, row-major; unused slots hold the row itself and 0), the
+    // diagonal D and its inverse. The finest level's columns are the caller's
+    // operator columns (not owned).
     int32_t* col4 = nullptr;
     float *val4 = nullptr, *diag32 = nullptr, *dinv32 = nullptr;
     // V-cycle vectors (single precision); b holds the scaled D^-1 b

@@ -804,14 +804,13 @@ __global__ __launch_bounds__(NT) void k_mg_setup_rows(const phf_mg_setup_level* 
             s = d_mg_crows(r, L.nf, L.red_edge, L.edge_elems, L.led, L.ledTN, L.elem_edges,
                            L.red_row, L.B, L.col4, L.val4, L.diag, L.dinv, L.col64, L.val64);
         } else {  // the finest level, from the caller's double-precision rows
-            int32_t c[5];
-            double v[5];
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                c[k] = L.ell_col[(int64_t)k * L.nf + r];
-                v[k] = L.ell_val[(int64_t)k * L.nf + r];
-            }
-            s = phf_scale_row(r, L.nf, c, v, L.col4, L.val4, L.diag, L.dinv);
+            // (diagonal, then the four off-diagonal entries; the columns are
+            // shared with the caller and already in place)
+            const phf_i4 c4 = *(const phf_i4*)(L.ell_col + 4 * (int64_t)r);
+            const double* v4 = L.ell_val + 4 * (int64_t)r;
+            const int32_t c[5] = {r, c4.x, c4.y, c4.z, c4.w};
+            const double v[5] = {L.ell_val[4 * (int64_t)L.nf + r], v4[0], v4[1], v4[2], v4[3]};
+            s = phf_scale_row(r, L.nf, c, v, nullptr, L.val4, L.diag, L.dinv);
         }
         m = fmaxf(m, s);
     }
@@ -888,7 +887,7 @@ void phf_mg_destroy(phf_mg* mg)
         float* f[] = {L.val4, L.diag32, L.dinv32, L.x, L.y, L.b, L.r, L.t};
         for (float* p : f) phf_dfree(p);
         phf_dfree(L.P_code);
-        phf_dfree(L.col4);
+        if (l < mg->nlev - 1) phf_dfree(L.col4);  // (the finest level's is the operator's)
         phf_dfree(L.P_col);
         if (l == mg->nlev - 1) phf_dfree(mg->z32);
         phf_dfree(L.rows9);
@@ -932,7 +931,9 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             }
             L.nf = ms->n_free;
             const size_t nf = std::max<int32_t>(L.nf, 1);
-            TRY(phf_dmalloc(ctx, &L.col4, 4 * nf, "multigrid operator columns"));
+            // (the finest level shares the operator's columns)
+            if (l == nlev - 1) L.col4 = fine->ell_col;
+            else TRY(phf_dmalloc(ctx, &L.col4, 4 * nf, "multigrid operator columns"));
             TRY(phf_dmalloc(ctx, &L.val4, 4 * nf, "multigrid operator (single)"));
             TRY(phf_dmalloc(ctx, &L.diag32, nf, "multigrid diagonal (single)"));
             TRY(phf_dmalloc(ctx, &L.dinv32, nf, "multigrid inverse diagonal (single)"));
@@ -1239,7 +1240,8 @@ int phf_mg_fine_rows(phf_mg* mg, phf_mg_rows* out)
     const int top = mg->nlev - 1;
     phf_mg_level& F = mg->lev[top];
     PHF_LAUNCH(ctx, "k_mg_lmax_clear", k_mg_lmax_clear, 1, PHF_MG_MAX_LEVELS, 0, mg->nlev, mg->lmax);
-    *out = phf_mg_rows{F.col4, F.val4, F.diag32, F.dinv32, mg->lmax + top};
+    // (no columns: the finest level shares the operator's)
+    *out = phf_mg_rows{nullptr, F.val4, F.diag32, F.dinv32, mg->lmax + top};
     mg->fine_rows_ready = true;
     return PHF_OK;
 }

@@ -44,12 +44,12 @@ struct phf_ns {
     // symbolic (per mesh; the element tables are the mesh's)
     const int32_t* elem_red = nullptr;  // 3 nE: reduced row of local edge l (-1 Dirichlet)
     const int32_t* elem_row = nullptr;  // 3 nE: multiplier row of local edge l (-1 Neumann)
-    int32_t* ell_col = nullptr;   // 5 nf, column-major ELL of R
+    int32_t* ell_col = nullptr;   // 4 nf: off-diagonal columns of R, row-major ELL-4
     double* row_h = nullptr;      // L: |E|/2 of each multiplier row
     // numeric
     double* B = nullptr;          // 9 nE: P^T A_T P
     double* Ablk = nullptr;       // 9 nE: A_T
-    double* ell_val = nullptr;    // 5 nf
+    double* ell_val = nullptr;    // 5 nf: the 4 nf off-diagonal values, then the diagonal
     double* dinv = nullptr;       // nf
     double* kv = nullptr;         // 3 nE known midpoint values / jumps
     double* cs = nullptr;         // 3 nE element right-hand side / residual

@@ -65,12 +65,14 @@ __global__ __launch_bounds__(NT) void k_ns_blocks(int32_t nE, const double* __re
     }
 }
 
-// ELL-5 rows of the reduced operator straight from the edge tables and the
-// element blocks B (column major; unused slots point at the diagonal with
-// value 0): columns, values B[s0] + B[s1] of each entry's sources, and the
+// Rows of the reduced operator straight from the edge tables and the element
+// blocks B (values B[s0] + B[s1] of each entry's sources): the diagonal, and
+// the off-diagonal entries in ascending column order as ELL-4, row-major
+// (ell_col[4r..4r+3] int32, ell_val[4r..4r+3] double; unused entries column
+// r, value 0), the diagonal values behind them at ell_val[4 nf + r], and the
 // inverse diagonal (1 where it is not positive). With FINE also the
 // multigrid preconditioner's finest-level rows (phf_scale_row, from the same
-// values) and their Gershgorin bound.
+// values; they share the columns) and their Gershgorin bound.
 template <bool FINE>
 __global__ __launch_bounds__(NT) void k_ns_ellval(int32_t nf, const int32_t* __restrict__ red_edge,
                                                   const int2* __restrict__ edge_elems,
@@ -93,7 +95,6 @@ __global__ __launch_bounds__(NT) void k_ns_ellval(int32_t nf, const int32_t* __r
         double d = 0.0;
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-            const int64_t slot = (int64_t)k * nf + r;
             if (k < n) {
                 v[k] = B[s0[k]] + (s1[k] >= 0 ? B[s1[k]] : 0.0);
                 if (col[k] == r) d = v[k];
@@ -101,9 +102,21 @@ __global__ __launch_bounds__(NT) void k_ns_ellval(int32_t nf, const int32_t* __r
                 col[k] = r;
                 v[k] = 0.0;
             }
-            ell_col[slot] = col[k];
-            ell_val[slot] = v[k];
         }
+        int32_t c4[4] = {r, r, r, r};
+        double v4[4] = {0.0, 0.0, 0.0, 0.0};
+        int q = 0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            if (col[k] != r && q < 4) {
+                c4[q] = col[k];
+                v4[q] = v[k];
+                ++q;
+            }
+        *(phf_i4*)(ell_col + 4 * (int64_t)r) = phf_i4{c4[0], c4[1], c4[2], c4[3]};
+        *(phf_d2*)(ell_val + 4 * (int64_t)r) = phf_d2{v4[0], v4[1]};
+        *(phf_d2*)(ell_val + 4 * (int64_t)r + 2) = phf_d2{v4[2], v4[3]};
+        ell_val[4 * (int64_t)nf + r] = d;
         dinv[r] = d > 0.0 ? 1.0 / d : 1.0;
         if (FINE) gs = phf_scale_row(r, nf, col, v, fr.col4, fr.val4, fr.diag, fr.dinv);
     }
@@ -280,16 +293,31 @@ __device__ inline void nts(T* p, T v)
 #endif
 }
 
+// Row r of the reduced operator times x (layout as k_ns_ellval writes it).
+// The terms are summed in ascending column order, the diagonal in its place
+// (unused entries add an exact zero), so that the rounding does not depend on
+// the storage layout.
 template <typename XT>
 __device__ inline double ell_row(int32_t r, int32_t nf, const int32_t* __restrict__ col,
                                  const double* __restrict__ val, const XT* __restrict__ x)
 {
+    const phf_i4 c = ntl(reinterpret_cast<const phf_i4*>(col + 4 * (int64_t)r));
+    const phf_d2 v01 = ntl(reinterpret_cast<const phf_d2*>(val + 4 * (int64_t)r));
+    const phf_d2 v23 = ntl(reinterpret_cast<const phf_d2*>(val + 4 * (int64_t)r + 2));
+    const double dv = ntl(val + 4 * (int64_t)nf + r);
+    const int32_t cc[4] = {c.x, c.y, c.z, c.w};
+    const double vv[4] = {v01.x, v01.y, v23.x, v23.y};
     double s = 0.0;
+    bool dd = false;  // diagonal term added
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        int64_t slot = (int64_t)k * nf + r;
-        s = fma(ntl(val + slot), (double)x[ntl(col + slot)], s);
+    for (int k = 0; k < 4; ++k) {
+        if (!dd && cc[k] > r) {
+            s = fma(dv, (double)x[r], s);
+            dd = true;
+        }
+        s = fma(vv[k], (double)x[cc[k]], s);
     }
+    if (!dd) s = fma(dv, (double)x[r], s);
     return s;
 }
 
@@ -761,7 +789,7 @@ int phf_ns_create(phf_mesh* mesh, phf_ns** out)
     ns->elem_row = mesh->elem_row;
     const size_t e3 = 3 * (size_t)ns->nE, e9 = 9 * (size_t)ns->nE, nf = ns->nf;
     int rc = 0;
-    rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_col, 5 * nf, "solver ELL columns");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_col, 4 * nf, "solver ELL columns");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->B, e9, "solver blocks");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_val, 5 * nf, "solver ELL values");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->dinv, nf, "solver diagonal");
