@@ -306,8 +306,9 @@ int phf_spmv(phf_ctx* ctx, int32_t nrows, const int32_t* rowptr, const int32_t* 
  * nonsymmetric and needs BiCGSTAB (right-preconditioned). U, Lambda: device,
  * N and L doubles; Lambda may be NULL. Synchronises the stream. Returns
  * PHF_ENOCONV if rtol is not reached in max_iter iterations or BiCGSTAB
- * breaks down (the iterate is still written), PHF_EINVAL for CG with p != 0
- * or p != 0 without D. */
+ * still breaks down after its restarts (a breakdown restarts it from the
+ * current iterate, at most 8 times; the iterate is still written),
+ * PHF_EINVAL for CG with p != 0 or p != 0 without D. */
 #define PHF_SOLVER_NULLSPACE_CG 0
 #define PHF_SOLVER_NULLSPACE_BICGSTAB 1
 /* Preconditioners of the reduced operator: Jacobi (any mesh), or a V-cycle

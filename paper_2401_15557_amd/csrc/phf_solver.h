@@ -91,7 +91,9 @@ int phf_ns_recover(phf_ns* ns, const double* rhs1, double* U, double* mu, double
 int phf_ns_zero_w(phf_ns* ns);
 // Right-preconditioned BiCGSTAB on the same reduced system (any A, also
 // nonsymmetric), with the same device-side scalars and convergence flag;
-// iflags[2] is set on a breakdown.
+// iflags[2] is set on a breakdown, after which the iteration restarts from
+// the current iterate (a bounded number of times; *breakdown reports the
+// last run's).
 int phf_ns_bicg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_every,
                       int32_t* iters_out, double* relres_out, int* converged, int* breakdown);
 // Host convergence loop: cg_start + batches of check_every iterations.

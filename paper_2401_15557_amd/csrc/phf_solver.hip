@@ -1049,29 +1049,39 @@ int bicg_iterate(phf_ns* ns, int32_t iters)
 }
 }  // namespace
 
+// Runs after a breakdown at most: each restarts the iteration from the
+// current iterate, with its residual (recomputed) as the new shadow residual.
+constexpr int BICG_RESTARTS = 8;
+
 int phf_ns_bicg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_every,
                       int32_t* iters_out, double* relres_out, int* converged, int* breakdown)
 {
     phf_ctx* ctx = ns->mesh->ctx;
-    TRY(bicg_start(ns, rtol));
-    int32_t done_iters = 0;
+    int32_t prior = 0;  // iterations of the runs that broke down
     int hf[3] = {0, 0, 0};
-    PHF_HIP(ctx, hipMemcpyAsync(hf, ns->iflags, 3 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    while (!hf[0] && done_iters < max_iter) {
-        int32_t n = std::min(check_every, max_iter - done_iters);
-        TRY(bicg_iterate(ns, n));
-        done_iters += n;
+    for (int run = 0;; ++run) {
+        TRY(bicg_start(ns, rtol));
         PHF_HIP(ctx, hipMemcpyAsync(hf, ns->iflags, 3 * sizeof(int), hipMemcpyDeviceToHost,
                                     ctx->stream));
         PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        int32_t done_iters = prior;
+        while (!hf[0] && done_iters < max_iter) {
+            int32_t n = std::min(check_every, max_iter - done_iters);
+            TRY(bicg_iterate(ns, n));
+            done_iters += n;
+            PHF_HIP(ctx, hipMemcpyAsync(hf, ns->iflags, 3 * sizeof(int), hipMemcpyDeviceToHost,
+                                        ctx->stream));
+            PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        }
+        if (!hf[2] || run == BICG_RESTARTS || prior + hf[1] >= max_iter) break;
+        prior += hf[1];
     }
     double sc[NS_NSCAL] = {0};
     if (ns->nf > 0) {
         PHF_HIP(ctx, hipMemcpyAsync(sc, ns->scal, sizeof(sc), hipMemcpyDeviceToHost, ctx->stream));
         PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
     }
-    if (iters_out) *iters_out = hf[1];
+    if (iters_out) *iters_out = prior + hf[1];
     if (relres_out) *relres_out = sc[NS_BB] > 0 ? std::sqrt(sc[NS_RR] / sc[NS_BB]) : 0.0;
     if (breakdown) *breakdown = ns->nf == 0 ? 0 : hf[2];
     if (converged) *converged = ns->nf == 0 ? 1 : (hf[0] && !hf[2]);
