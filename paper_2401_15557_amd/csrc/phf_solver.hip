@@ -338,6 +338,37 @@ __device__ inline double block_reduce_partials(const double* __restrict__ part, 
     return phf_block_sum_f64<NT>(s, sh);
 }
 
+// K partial-sum slots reduced together, behind one pair of barriers; each in
+// the same order as block_reduce_partials, so the results are identical. sh
+// holds K * NT / 64 doubles.
+template <int K>
+__device__ inline void block_reduce_slots(const double* __restrict__ part, const int (&slot)[K],
+                                          int32_t nb, double* sh, double (&out)[K])
+{
+    double s[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = 0.0;
+    for (int q = threadIdx.x; q < nb; q += NT) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) s[k] += part[slot[k] * MAXB + q];
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double x = phf_wave_sum(s[k]);
+        if (lane == 0) sh[k * (NT / 64) + wid] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) t += sh[k * (NT / 64) + w];
+        out[k] = t;
+    }
+    __syncthreads();
+}
+
 // ZERO: the iteration starts from w = 0, which the kernel writes; r = b
 // without a product.
 template <bool JAC, bool ZERO>
@@ -410,10 +441,14 @@ __global__ __launch_bounds__(NT) void k_cg_dir(int32_t nf, int32_t it, int32_t n
                                                int* iflags)
 {
     if (iflags[0]) return;
-    __shared__ double sh[NT / 64];
+    __shared__ double sh[3 * NT / 64];
     double beta = 0.0;
     if (it > 0) {
-        const double rr = block_reduce_partials(part + P_RR * MAXB, nb, sh);
+        // r.r (convergence test), r.z of this and of the previous iteration
+        double red[3];
+        block_reduce_slots<3>(part, {P_RR, (it & 1) ? P_RZ1 : P_RZ0, (it & 1) ? P_RZ0 : P_RZ1},
+                              nb, sh, red);
+        const double rr = red[0];
         const double bb = scal[NS_BB], tol2 = scal[NS_TOL2];
         if (rr <= tol2 * bb) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -422,9 +457,7 @@ __global__ __launch_bounds__(NT) void k_cg_dir(int32_t nf, int32_t it, int32_t n
             }
             return;
         }
-        const double rz_new = block_reduce_partials(part + ((it & 1) ? P_RZ1 : P_RZ0) * MAXB, nb, sh);
-        const double rz_old = block_reduce_partials(part + ((it & 1) ? P_RZ0 : P_RZ1) * MAXB, nb, sh);
-        beta = rz_new / rz_old;
+        beta = red[1] / red[2];
         if (blockIdx.x == 0 && threadIdx.x == 0) scal[NS_RR] = rr;
     }
     double s = 0.0;
@@ -449,10 +482,10 @@ __global__ __launch_bounds__(NT) void k_cg_upd(int32_t nf, int32_t it, int32_t n
                                                double* __restrict__ part, int* iflags)
 {
     if (iflags[0]) return;
-    __shared__ double sh[NT / 64];
-    const double rz = block_reduce_partials(part + ((it & 1) ? P_RZ1 : P_RZ0) * MAXB, nb, sh);
-    const double pq = block_reduce_partials(part + P_PQ * MAXB, nb, sh);
-    const double alpha = rz / pq;
+    __shared__ double sh[2 * NT / 64];
+    double red[2];  // r.z, p.q
+    block_reduce_slots<2>(part, {(it & 1) ? P_RZ1 : P_RZ0, P_PQ}, nb, sh, red);
+    const double alpha = red[0] / red[1];
     double s_rz = 0.0, s_rr = 0.0;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
         w[i] = fma(alpha, p[i], w[i]);
@@ -487,10 +520,10 @@ __global__ __launch_bounds__(NT) void k_cg_upd_mg(int32_t nf, int32_t it, int32_
                                                   float* __restrict__ bh, float* __restrict__ x)
 {
     if (iflags[0]) return;
-    __shared__ double sh[NT / 64];
-    const double rz = block_reduce_partials(part + ((it & 1) ? P_RZ1 : P_RZ0) * MAXB, nb, sh);
-    const double pq = block_reduce_partials(part + P_PQ * MAXB, nb, sh);
-    const double alpha = rz / pq;
+    __shared__ double sh[2 * NT / 64];
+    double red[2];  // r.z, p.q
+    block_reduce_slots<2>(part, {(it & 1) ? P_RZ1 : P_RZ0, P_PQ}, nb, sh, red);
+    const double alpha = red[0] / red[1];
     const float w0 = wts[0];
     double s_rr = 0.0;
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
