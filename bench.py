@@ -65,7 +65,8 @@ def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None, jacobi=Fa
     off-diagonal (int32 column, fp32 value) slots = 32 B/row: smoothing sweep
     32 + 4 (D^-1 b) + 4 (x) + 4 (y) = 44 B/row; first sweep from zero on the
     finest level (rounds the fp64 residual once; only for the first cycle,
-    later ones get it from the CG update) 8 + 4 (dinv) + 4 + 4 = 20 B/row;
+    later ones get it from the CG update) 8 + 4 (dinv) + 4 (D^-1 b) = 16
+    B/row, the second sweep forming the first from D^-1 b 32 + 4 + 4 = 40;
     last finest sweep, which also writes z (fp32 for CG) and reduces r.z,
     32 + 4 + 4 + 8 (r) + 4 (z) = 52 B/row; residual 32 + 4 (diag) + 4 + 4 +
     4 (r) = 48 B/row; prolongation 20 (five int32 columns) + 4 (five 4-bit
@@ -83,7 +84,9 @@ def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None, jacobi=Fa
     for l, n in enumerate(level_nf or []):
         mg[f"k_mg_smooth.L{l}"] = 44 * n
         if l == top:
-            mg[f"k_mg_smooth0.L{l}"] = 20 * n
+            mg[f"k_mg_smooth0.L{l}"] = 16 * n
+            # second sweep, the first formed from D^-1 b: 16 + 16 + 4 + 4
+            mg[f"k_mg_smooth1.L{l}"] = 40 * n
             mg[f"k_mg_smooth_z.L{l}"] = 52 * n
         mg[f"k_mg_resid.L{l}"] = 48 * n
         if l > 0:
@@ -99,8 +102,9 @@ def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None, jacobi=Fa
         # fp32 result with multigrid); p, q in and out
         "k_cg_dir": 12 * (nnzR - nf) + 8 * nf + (40 if jacobi else 36) * nf,
         # read p, q, w, r; write w, r; Jacobi: dinv in, z out (fp64);
-        # multigrid: the first sweep, dinv (fp32) in, D^-1 r and x out (fp32)
-        "k_cg_upd": (64 if jacobi else 60) * nf,
+        # multigrid: dinv (fp32) in, D^-1 r out (fp32; the first sweep is
+        # formed by the second)
+        "k_cg_upd": (64 if jacobi else 56) * nf,
     }
 
 

@@ -167,7 +167,7 @@ struct phf_mg_rows {
 // x = w[0] bh. Valid until the next cycle is queued.
 struct phf_mg_top {
     float* bh;
-    float* x;
+    float* x;  // null: the cycle's second sweep forms x from bh (not stored)
     const float* dinv;
     const float* w;
 };

@@ -466,7 +466,36 @@ __global__ __launch_bounds__(NT) void k_mg_smooth0_top(int32_t n, const float* _
     phf_for_rows<XCD_SMOOTH, NT>(n, [&](int32_t i) {
         const float h = (float)ldx<PHF_NT_MG>(b64, i) * dinv[i];
         bh[i] = h;
-        x[i] = omega * h;
+        if (x) x[i] = omega * h;
+    });
+}
+
+// Second sweep on the finest level. The first one, from zero, is
+// x = w[0] D^-1 b; it is formed here from D^-1 b where it is read (the same
+// rounded product), so the first sweep need not store it. Same arithmetic as
+// row_smooth.
+__global__ __launch_bounds__(NT) void k_mg_smooth1_top(int32_t n, const int32_t* __restrict__ col,
+                                                       const float* __restrict__ val,
+                                                       const float* __restrict__ bh,
+                                                       const float* __restrict__ w,
+                                                       float* __restrict__ y, const int* iflags)
+{
+    if (iflags && iflags[0]) return;
+    const float w0 = w[0], omega = w[1];
+    phf_for_rows<XCD_SMOOTH, NT>(n, [&](int32_t i) {
+        const phf_i4 c = ld_row4(col, i);
+        const phf_f4 v = ld_row4(val, i);
+        float s = 0.0f;
+        s = fmaf(v.x, __fmul_rn(w0, bh[c.x]), s);
+        s = fmaf(v.y, __fmul_rn(w0, bh[c.y]), s);
+        s = fmaf(v.z, __fmul_rn(w0, bh[c.z]), s);
+        s = fmaf(v.w, __fmul_rn(w0, bh[c.w]), s);
+        const float bi = bh[i];
+        float xi = __fmul_rn(w0, bi);
+        // (opaque to the compiler, so that bi - xi is not contracted with the
+        // product into one fused operation: the first sweep is a stored value)
+        __asm__ volatile("" : "+v"(xi));
+        y[i] = xi + omega * (bi - xi - s);
     });
 }
 
@@ -849,14 +878,17 @@ unsigned part_grid(int32_t n)
 
 // Trace names carry the level ("k_mg_smooth.L9"), counted from the coarsest
 // mesh, so per-launch byte counts can be attributed to a level.
-enum { NM_SMOOTH0, NM_SMOOTH, NM_SMOOTHZ, NM_RESID, NM_RESTRICT, NM_COLLECT, NM_PROLONG, NM_COUNT };
+enum {
+    NM_SMOOTH0, NM_SMOOTH, NM_SMOOTHZ, NM_RESID, NM_RESTRICT, NM_COLLECT, NM_PROLONG, NM_SMOOTH1,
+    NM_COUNT
+};
 struct mg_names {
     char s[NM_COUNT][PHF_MG_MAX_LEVELS][32];
     mg_names()
     {
         static const char* base[NM_COUNT] = {"k_mg_smooth0", "k_mg_smooth", "k_mg_smooth_z",
                                              "k_mg_resid", "k_mg_restrict", "k_mg_collect",
-                                             "k_mg_prolong"};
+                                             "k_mg_prolong", "k_mg_smooth1"};
         for (int k = 0; k < NM_COUNT; ++k)
             for (int l = 0; l < PHF_MG_MAX_LEVELS; ++l)
                 snprintf(s[k][l], sizeof(s[k][l]), "%s.L%d", base[k], l);
@@ -1181,10 +1213,21 @@ int vcycle(phf_mg* mg, int l, const double* r_top, bool first_done, double* z64,
     }
     const unsigned g = grid_for(n);
     const float* w = level_weights(mg, l);
+    // (on the finest level the second sweep forms the first from D^-1 b, which
+    // is then not stored, unless it is the only sweep)
+    const bool form1 = r_top && mg->nu >= 2;
     if (r_top && !first_done)
         PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0_top, g, NT, 0, n, L.dinv32, r_top, w,
-                   L.b, L.x, iflags);
-    for (int s = 1; s < mg->nu; ++s) TRY(smooth(mg, l, s, iflags));
+                   L.b, form1 ? nullptr : L.x, iflags);
+    for (int s = 1; s < mg->nu; ++s) {
+        if (s == 1 && form1) {
+            PHF_LAUNCH(ctx, mg_name(NM_SMOOTH1, l), k_mg_smooth1_top, g, NT, 0, n, L.col4, L.val4,
+                       L.b, w, L.y, iflags);
+            std::swap(L.x, L.y);
+        } else {
+            TRY(smooth(mg, l, s, iflags));
+        }
+    }
     phf_mg_level& C = mg->lev[l - 1];
     if (C.nf > 0) {
         PHF_LAUNCH(ctx, mg_name(NM_RESID, l), k_mg_resid, g, NT, 0, n, L.col4, L.val4, L.diag32,
@@ -1250,5 +1293,5 @@ phf_mg_top phf_mg_top_view(phf_mg* mg)
 {
     const int top = mg->nlev - 1;
     phf_mg_level& F = mg->lev[top];
-    return phf_mg_top{F.b, F.x, F.dinv32, level_weights(mg, top)};
+    return phf_mg_top{F.b, mg->nu >= 2 ? nullptr : F.x, F.dinv32, level_weights(mg, top)};
 }

@@ -509,7 +509,8 @@ __global__ __launch_bounds__(NT) void k_cg_upd(int32_t nf, int32_t it, int32_t n
 
 // The update with the multigrid preconditioner, which also takes the cycle's
 // first sweep from zero on the finest level: bh = D^-1 r rounded to single
-// precision, x = w[0] bh (the cycle then continues from its second sweep).
+// precision, x = w[0] bh (the cycle then continues from its second sweep; x
+// null: that sweep forms x from bh itself).
 __global__ __launch_bounds__(NT) void k_cg_upd_mg(int32_t nf, int32_t it, int32_t nb,
                                                   double* __restrict__ w, double* __restrict__ r,
                                                   const double* __restrict__ p,
@@ -533,7 +534,7 @@ __global__ __launch_bounds__(NT) void k_cg_upd_mg(int32_t nf, int32_t it, int32_
         s_rr = fma(ri, ri, s_rr);
         const float h = (float)ri * ntl(dinv32 + i);
         bh[i] = h;
-        x[i] = w0 * h;
+        if (x) x[i] = w0 * h;
     }
     const double t1 = phf_block_sum_f64<NT>(s_rr, sh);
     if (threadIdx.x == 0) {
