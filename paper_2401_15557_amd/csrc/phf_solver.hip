@@ -999,6 +999,14 @@ int phf_ns_cg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_eve
 {
     phf_ctx* ctx = ns->mesh->ctx;
     TRY(phf_ns_cg_start(ns, rtol, zero_start));
+    if (ns->nf == 0) {
+        // no free unknowns: the reduced system is empty and solved as it is
+        // (nothing was launched that writes the scalars read below)
+        if (iters_out) *iters_out = 0;
+        if (relres_out) *relres_out = 0.0;
+        if (converged) *converged = 1;
+        return PHF_OK;
+    }
     double* h = reinterpret_cast<double*>(ctx->h_pinned);
     const int* hf = reinterpret_cast<const int*>(h + NS_NSCAL);
     auto read_back = [&]() -> int {
@@ -1020,7 +1028,7 @@ int phf_ns_cg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_eve
     }
     if (iters_out) *iters_out = hf[1];
     if (relres_out) *relres_out = h[NS_BB] > 0 ? std::sqrt(h[NS_RR] / h[NS_BB]) : 0.0;
-    if (converged) *converged = ns->nf == 0 ? 1 : hf[0];
+    if (converged) *converged = hf[0];
     return PHF_OK;
 }
 

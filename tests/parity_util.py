@@ -12,6 +12,26 @@ term, sign or index is off by O(1) of the scale.
 import numpy as np
 
 RTOL = 1e-12
+# Every device output of a parity test starts as NaN: an entry the library
+# does not write stays NaN and fails the comparison (torch's caching
+# allocator would otherwise hand back the previous case's values).
+NAN = float("nan")
+
+
+def nan_vec(n, dev):
+    import torch
+    return torch.full((max(int(n), 1),), NAN, dtype=torch.float64, device=dev)
+
+
+def assert_written(t, info):
+    """Every entry of the outputs of one assembly (dict of NaN-filled device
+    tensors, as from alloc_system(fill=NAN)) was written: none is NaN."""
+    size = dict(K=info.nnz_K, M=info.nnz_K, D=info.nnz_K, C=info.nnz_C, F=info.N, bD=info.L,
+                S=info.nnz_saddle)
+    for k, v in t.items():
+        n = size.get(k, v.numel())
+        bad = int(v[:n].isnan().sum().item())
+        assert bad == 0, f"{k}: {bad} of {n} entries not written"
 
 
 def block_scale(v, width):

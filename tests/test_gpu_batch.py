@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2401_15557_amd import meshgen as G
-from parity_util import assert_close_scaled, block_scale, row_scale_fast
+from parity_util import NAN, assert_close_scaled, assert_written, block_scale, row_scale_fast
 
 pytestmark = pytest.mark.gpu
 PI = np.pi
@@ -42,10 +42,11 @@ def test_batch_bit_identical_all_shapes(ctx):
     print("sizes", [m.nE for m, _ in inst], flush=True)
     ref = []
     for dm, co, d in zip(meshes, coeffs, data):
-        s, t = phfem.alloc_system(dm)
+        s, t = phfem.alloc_system(dm, fill=NAN)
         phfem.phf_assemble(dm.handle, co, d, s)
+        assert_written(t, dm.info)
         ref.append(_host(t))
-    outs = [phfem.alloc_system(dm) for dm in meshes]
+    outs = [phfem.alloc_system(dm, fill=NAN) for dm in meshes]
     b = phfem.phf_batch_create(ctx.handle, [dm.handle for dm in meshes])
     try:
         for tile in (64, 128, 256):
@@ -81,14 +82,15 @@ def test_batch_with_D_and_aT_and_oracle(ctx, oracle):
     aTs = [G.per_triangle_coefficient(m.nE, 20 + i) for i, (m, _) in enumerate(inst)]
     aT_d = [torch.tensor(a, device=ctx.device) for a in aTs]
     coeffs = [phfem.make_coeffs(p=(0.5, -1.0), delta=1.0, a_T=a) for a in aT_d]
-    outs = [phfem.alloc_system(dm, with_D=True) for dm in meshes]
+    outs = [phfem.alloc_system(dm, with_D=True, fill=NAN) for dm in meshes]
     b = phfem.phf_batch_create(ctx.handle, [dm.handle for dm in meshes])
     try:
         phfem.phf_batch_set_config(b, 128, 2)
         phfem.phf_batch_assemble(b, coeffs, data, [s for s, _ in outs])
         for i, (dm, co, d) in enumerate(zip(meshes, coeffs, data)):
-            s, t = phfem.alloc_system(dm, with_D=True)
+            s, t = phfem.alloc_system(dm, with_D=True, fill=NAN)
             phfem.phf_assemble(dm.handle, co, d, s)
+            assert_written(t, dm.info)
             for k in KEYS + ("D",):
                 gb, gs = outs[i][1][k].cpu().numpy(), t[k].cpu().numpy()
                 nd = int((gb != gs).sum())

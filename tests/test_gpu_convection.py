@@ -6,6 +6,7 @@ import pytest
 
 from conftest import read_golden
 from paper_2401_15557_amd import meshgen as G
+from parity_util import NAN, nan_vec
 
 pytestmark = pytest.mark.gpu
 PI = np.pi
@@ -44,10 +45,10 @@ def _example1(phfem):
 
 def _solve(ctx, phfem, dm, co, d, precond, rtol=1e-13):
     import torch
-    s, t = phfem.alloc_system(dm, with_D=True, with_S=True)
+    s, t = phfem.alloc_system(dm, with_D=True, with_S=True, fill=NAN)
     phfem.phf_assemble(dm.handle, co, d, s)
-    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
-    Lam = torch.empty(max(dm.info.L, 1), dtype=torch.float64, device=ctx.device)
+    U = nan_vec(dm.info.N, ctx.device)
+    Lam = nan_vec(dm.info.L, ctx.device)
     st = phfem.phf_solve(dm.handle, co, s, U, Lam, rtol=rtol, saddle_residual=True,
                          method=phfem.PHF_SOLVER_NULLSPACE_BICGSTAB, precond=precond)
     return st, U, Lam
@@ -90,9 +91,9 @@ def test_convection_needs_bicgstab_and_D(ctx):
     from paper_2401_15557_amd import phfem
     dm = phfem.Mesh(ctx, G.paper_square(2))
     co, d = _example1(phfem)
-    s, t = phfem.alloc_system(dm, with_D=True)
+    s, t = phfem.alloc_system(dm, with_D=True, fill=NAN)
     phfem.phf_assemble(dm.handle, co, d, s)
-    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    U = nan_vec(dm.info.N, ctx.device)
     with pytest.raises(phfem.PhfError) as ei:
         phfem.phf_solve(dm.handle, co, s, U)  # conjugate gradients
     assert ei.value.code == phfem.PHF_EINVAL
@@ -111,11 +112,11 @@ def test_bicgstab_symmetric_matches_cg(ctx):
     co = phfem.make_coeffs(delta=0.5)
     d = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * PI * PI, 0),
                         phfem.make_fn(phfem.PHF_FN_CONST, 1), phfem.make_fn(phfem.PHF_FN_CONST, 1))
-    s, t = phfem.alloc_system(dm)
+    s, t = phfem.alloc_system(dm, fill=NAN)
     phfem.phf_assemble(dm.handle, co, d, s)
     out = []
     for meth in (phfem.PHF_SOLVER_NULLSPACE_CG, phfem.PHF_SOLVER_NULLSPACE_BICGSTAB):
-        U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+        U = nan_vec(dm.info.N, ctx.device)
         st = phfem.phf_solve(dm.handle, co, s, U, rtol=1e-13, method=meth)
         assert st.converged
         out.append(U.cpu().numpy())

@@ -9,7 +9,8 @@ import numpy as np
 import pytest
 
 from paper_2401_15557_amd import meshgen as G
-from parity_util import assert_close_scaled, block_scale, compare_topology, row_scale_fast
+from parity_util import (NAN, assert_close_scaled, block_scale, compare_topology, nan_vec,
+                         row_scale_fast)
 
 pytestmark = pytest.mark.gpu
 PI = np.pi
@@ -44,7 +45,7 @@ def test_lshape_level9_pipeline(oracle):
     data = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * PI * PI, 0),
                            phfem.make_fn(phfem.PHF_FN_CONST, 1.0),
                            phfem.make_fn(phfem.PHF_FN_CONST, 1.0))
-    s, t = phfem.alloc_system(dm)
+    s, t = phfem.alloc_system(dm, fill=NAN)
     phfem.phf_assemble(dm.handle, co, data, s)
     asm = oracle.assemble(m, tables, aT=aT, f=oracle.fn(oracle.FN_SIN_COS, 2 * PI * PI, 0),
                           g=oracle.fn(oracle.FN_CONST, 1.0), uD=oracle.fn(oracle.FN_CONST, 1.0))
@@ -59,8 +60,8 @@ def test_lshape_level9_pipeline(oracle):
         assert_close_scaled(t[key].cpu().numpy()[:len(o)], o, np.full(len(o), np.abs(o).max()), key)
     print("assembly within 1e-12 (scaled)", flush=True)
 
-    U = torch.empty(dm.info.N, dtype=torch.float64, device=dev)
-    Lam = torch.empty(dm.info.L, dtype=torch.float64, device=dev)
+    U = nan_vec(dm.info.N, dev)
+    Lam = nan_vec(dm.info.L, dev)
     rp, col, val = oracle.saddle(asm)
     Fv = np.concatenate([asm["F"], asm["bD"]])
 

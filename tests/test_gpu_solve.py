@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 from paper_2401_15557_amd import meshgen as G
+from parity_util import NAN, nan_vec
 
 pytestmark = pytest.mark.gpu
 PI = np.pi
@@ -61,10 +62,10 @@ def test_solve_parity(ctx, oracle, name):
     dm = phfem.Mesh(ctx, m)
     aT_d = torch.tensor(aT, device=ctx.device) if aT is not None else None
     co = phfem.make_coeffs(delta=delta, a_T=aT_d)
-    s, t = phfem.alloc_system(dm, with_S=True)
+    s, t = phfem.alloc_system(dm, with_S=True, fill=NAN)
     phfem.phf_assemble(dm.handle, co, gd, s)
-    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
-    Lam = torch.empty(max(dm.info.L, 1), dtype=torch.float64, device=ctx.device)
+    U = nan_vec(dm.info.N, ctx.device)
+    Lam = nan_vec(dm.info.L, ctx.device)
     st = phfem.phf_solve(dm.handle, co, s, U, Lam, rtol=1e-13, saddle_residual=True)
     assert st.converged
     Ug, Lg = U.cpu().numpy(), Lam.cpu().numpy()[:dm.info.L]
@@ -89,16 +90,17 @@ def test_solve_deterministic_and_noconv(ctx):
     co = phfem.make_coeffs()
     d = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * PI * PI, 0),
                         phfem.make_fn(phfem.PHF_FN_CONST, 1), phfem.make_fn(phfem.PHF_FN_CONST, 1))
-    s, t = phfem.alloc_system(dm)
+    s, t = phfem.alloc_system(dm, fill=NAN)
     phfem.phf_assemble(dm.handle, co, d, s)
     res = []
     for _ in range(2):
-        U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
-        L = torch.empty(dm.info.L, dtype=torch.float64, device=ctx.device)
+        U = nan_vec(dm.info.N, ctx.device)
+        L = nan_vec(dm.info.L, ctx.device)
         phfem.phf_solve(dm.handle, co, s, U, L, rtol=1e-12)
+        assert not U.isnan().any().item() and not L.isnan().any().item()
         res.append((U.cpu().numpy().tobytes(), L.cpu().numpy().tobytes()))
     assert res[0] == res[1]
-    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    U = nan_vec(dm.info.N, ctx.device)
     with pytest.raises(phfem.PhfError) as ei:
         phfem.phf_solve(dm.handle, co, s, U, None, rtol=1e-12, max_iter=2, check_every=1)
     assert ei.value.code == phfem.PHF_ENOCONV
@@ -128,8 +130,8 @@ def _cn_setup(ctx, oracle, phfem, m, k):
 def _get(ctx, cn, dm):
     import torch
     from paper_2401_15557_amd import phfem
-    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
-    L = torch.empty(dm.info.L, dtype=torch.float64, device=ctx.device)
+    U = nan_vec(dm.info.N, ctx.device)
+    L = nan_vec(dm.info.L, ctx.device)
     t = phfem.phf_cn_get_state(cn, U, L)
     torch.cuda.synchronize()
     return U.cpu().numpy(), L.cpu().numpy(), t
@@ -174,10 +176,10 @@ def test_cn_steady_state(ctx, oracle):
     co = phfem.make_coeffs(delta=0.5)
     gd = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 3.0, 0),
                          phfem.make_fn(phfem.PHF_FN_CONST, 0.5), phfem.make_fn(phfem.PHF_FN_CONST, 1))
-    s, t = phfem.alloc_system(dm)
+    s, t = phfem.alloc_system(dm, fill=NAN)
     phfem.phf_assemble(dm.handle, co, gd, s)
-    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
-    L = torch.empty(dm.info.L, dtype=torch.float64, device=ctx.device)
+    U = nan_vec(dm.info.N, ctx.device)
+    L = nan_vec(dm.info.L, ctx.device)
     phfem.phf_solve(dm.handle, co, s, U, L, rtol=1e-14, max_iter=50000)
     cn = phfem.phf_cn_create(dm.handle, co, 0.05, rtol=1e-14)
     phfem.phf_cn_set_state(cn, U, L, 0.0)
@@ -215,10 +217,10 @@ def test_multigrid_solve_parity(ctx, oracle, levels, smoother):
     aT = G.per_triangle_coefficient(m.nE, 5)
     od, gd = _both(oracle, phfem, "const")
     co = phfem.make_coeffs(a_T=torch.tensor(aT, device=ctx.device))
-    s, t = phfem.alloc_system(dm, with_S=True)
+    s, t = phfem.alloc_system(dm, with_S=True, fill=NAN)
     phfem.phf_assemble(dm.handle, co, gd, s)
-    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
-    Lam = torch.empty(dm.info.L, dtype=torch.float64, device=ctx.device)
+    U = nan_vec(dm.info.N, ctx.device)
+    Lam = nan_vec(dm.info.L, ctx.device)
     st = phfem.phf_solve(dm.handle, co, s, U, Lam, rtol=1e-13, saddle_residual=True,
                          precond=phfem.PHF_PRECOND_MULTIGRID, mg_smoother=sm)
     print(f"  iterations {st.iterations}", flush=True)
@@ -230,7 +232,7 @@ def test_multigrid_solve_parity(ctx, oracle, levels, smoother):
     assert _rel(Lam.cpu().numpy(), Lo) < 1e-8
     assert 0 <= st.saddle_rel_residual < 1e-11
     # Jacobi on the same system reaches the same solution
-    U2 = torch.empty_like(U)
+    U2 = nan_vec(len(U), U.device)
     st2 = phfem.phf_solve(dm.handle, co, s, U2, None, rtol=1e-13, max_iter=50000)
     assert _rel(U2.cpu().numpy(), Uo) < 1e-9
     print(f"  jacobi iterations {st2.iterations}", flush=True)
@@ -249,10 +251,10 @@ def test_multigrid_smoothers_jittered(ctx, oracle):
     aT = G.per_triangle_coefficient(m.nE, 9)
     od, gd = _both(oracle, phfem, "const")
     co = phfem.make_coeffs(a_T=torch.tensor(aT, device=ctx.device))
-    s, t = phfem.alloc_system(dm)
+    s, t = phfem.alloc_system(dm, fill=NAN)
     phfem.phf_assemble(dm.handle, co, gd, s)
     Uo, _ = oracle.solve_saddle(oracle.assemble(m, oracle.mesh_tables(m), aT=aT, **od))
-    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    U = nan_vec(dm.info.N, ctx.device)
     its = {}
     for sm, nu, rg in ((phfem.PHF_MG_SMOOTH_JACOBI, 2, 0.0), (phfem.PHF_MG_SMOOTH_JACOBI, 1, 0.0),
                        (phfem.PHF_MG_SMOOTH_CHEBYSHEV, 1, 0.0),
@@ -279,9 +281,9 @@ def test_multigrid_option_errors(ctx):
     from paper_2401_15557_amd import phfem
     dm = phfem.Mesh(ctx, G.lshape(0)).refine()
     co = phfem.make_coeffs()
-    s, t = phfem.alloc_system(dm)
+    s, t = phfem.alloc_system(dm, fill=NAN)
     phfem.phf_assemble(dm.handle, co, phfem.make_data(phfem.make_fn(phfem.PHF_FN_CONST, 1)), s)
-    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    U = nan_vec(dm.info.N, ctx.device)
     for kw in (dict(mg_sweeps=9), dict(mg_sweeps=-1), dict(mg_smoother=3),
                dict(mg_range=1.0), dict(mg_range=-2.0), dict(mg_omega=-0.5)):
         with pytest.raises(phfem.PhfError) as ei:
@@ -298,9 +300,9 @@ def test_multigrid_needs_hierarchy(ctx):
     from paper_2401_15557_amd import phfem
     dm = phfem.Mesh(ctx, G.lshape(2))
     co = phfem.make_coeffs()
-    s, t = phfem.alloc_system(dm)
+    s, t = phfem.alloc_system(dm, fill=NAN)
     phfem.phf_assemble(dm.handle, co, phfem.make_data(phfem.make_fn(phfem.PHF_FN_CONST, 1)), s)
-    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
+    U = nan_vec(dm.info.N, ctx.device)
     with pytest.raises(phfem.PhfError) as ei:
         phfem.phf_solve(dm.handle, co, s, U, precond=phfem.PHF_PRECOND_MULTIGRID)
     assert ei.value.code == phfem.PHF_EINVAL
@@ -346,15 +348,15 @@ def test_solve_interior_constraint_rhs(ctx, oracle, precond):
     dm, m = _refined_pair(ctx, oracle, G.lshape(0), 3)
     od, gd = _both(oracle, phfem, "sincos")
     co = phfem.make_coeffs()
-    s, t = phfem.alloc_system(dm)
+    s, t = phfem.alloc_system(dm, fill=NAN)
     phfem.phf_assemble(dm.handle, co, gd, s)
     tables = oracle.mesh_tables(m)
     asm = oracle.assemble(m, tables, **od)
     bD0 = t["bD"].clone()
     L = dm.info.L
     extra = np.random.default_rng(11).uniform(-0.1, 0.1, L)
-    U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
-    Lam = torch.empty(L, dtype=torch.float64, device=ctx.device)
+    U = nan_vec(dm.info.N, ctx.device)
+    Lam = nan_vec(L, ctx.device)
     for bump in (True, False, True):
         t["bD"].copy_(bD0 + torch.tensor(extra if bump else 0.0 * extra, device=ctx.device))
         a2 = dict(asm)
@@ -381,14 +383,39 @@ def test_predicted_check_schedule(ctx):
                                             device=ctx.device))
     d = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * PI * PI, 0),
                         phfem.make_fn(phfem.PHF_FN_CONST, 1), phfem.make_fn(phfem.PHF_FN_CONST, 1))
-    s, t = phfem.alloc_system(dm)
+    s, t = phfem.alloc_system(dm, fill=NAN)
     phfem.phf_assemble(dm.handle, co, d, s)
     out = []
     for ce in (1, 0, 3):
-        U = torch.empty(dm.info.N, dtype=torch.float64, device=ctx.device)
-        L = torch.empty(dm.info.L, dtype=torch.float64, device=ctx.device)
+        U = nan_vec(dm.info.N, ctx.device)
+        L = nan_vec(dm.info.L, ctx.device)
         st = phfem.phf_solve(dm.handle, co, s, U, L, rtol=1e-12, check_every=ce,
                              precond=phfem.PHF_PRECOND_MULTIGRID)
         assert st.converged
         out.append((st.iterations, U.cpu().numpy().tobytes(), L.cpu().numpy().tobytes()))
     assert out[0] == out[1] == out[2]
+
+
+def test_solve_no_free_unknowns(ctx, oracle):
+    """One triangle with all three edges Dirichlet: every edge is
+    constrained, the reduced system is empty, and the solve returns at once
+    with U fixed by the constraint alone (against the oracle's LU)."""
+    from paper_2401_15557_amd import phfem
+    m = G.Mesh(np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]]), np.array([[0, 1, 2]], np.int32),
+               np.array([[0, 1], [1, 2], [2, 0]], np.int32), np.zeros((0, 2), np.int32),
+               name="one_triangle_dirichlet")
+    od, gd = _both(oracle, phfem, "sincos")
+    dm = phfem.Mesh(ctx, m)
+    assert dm.info.n_free == 0
+    co = phfem.make_coeffs()
+    s, t = phfem.alloc_system(dm, fill=NAN)
+    phfem.phf_assemble(dm.handle, co, gd, s)
+    U = nan_vec(dm.info.N, ctx.device)
+    Lam = nan_vec(dm.info.L, ctx.device)
+    st = phfem.phf_solve(dm.handle, co, s, U, Lam, rtol=1e-13)
+    assert st.converged and st.iterations == 0 and st.rel_residual == 0.0
+    asm = oracle.assemble(m, oracle.mesh_tables(m), **od)
+    Uo, Lo = oracle.solve_saddle(asm)
+    assert _rel(U.cpu().numpy(), Uo) < 1e-12
+    assert _rel(Lam.cpu().numpy(), Lo) < 1e-11
+    dm.close()
