@@ -58,9 +58,30 @@ typedef enum { PHF_HOST = 0, PHF_DEVICE = 1 } phf_memspace;
 
 /* ---- context ----------------------------------------------------------- */
 
+/* Source of the library's device memory. alloc returns `bytes` of device
+ * memory on the context's device (NULL on failure; the library then frees
+ * its cached blocks through `free` and asks once more), usable in the order
+ * of the context's stream; free returns a block obtained from alloc, once
+ * no work issued on that stream before the call uses it any longer (the
+ * allocator may hand it out again for later work on the same stream).
+ * `user` is passed back unchanged. Both are called from the host thread
+ * that makes the library call (phf_destroy and phf_release_cache included).
+ * A caller that keeps a caching allocator of its own (torch's, from
+ * Python) passes it here, so that every device byte of the context comes
+ * from it. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* ptr, void* user);
+    void* user;
+} phf_allocator;
+
 /* Creates a context on HIP device `device` whose kernels run on `hip_stream`
- * (a hipStream_t; NULL = the null stream). *out receives the handle. */
-int phf_create(phf_ctx** out, int device, void* hip_stream);
+ * (a hipStream_t; NULL = the null stream). *out receives the handle.
+ * `alloc` (copied; may be NULL) supplies every device block the context
+ * holds: mesh tables, solver and time-stepper state, temporaries and the
+ * context's own flag words. NULL: hipMalloc / hipFree. Either way the
+ * context keeps released blocks in its cache (phf_release_cache). */
+int phf_create(phf_ctx** out, int device, void* hip_stream, const phf_allocator* alloc);
 /* Synchronises the stream and frees the context. Returns PHF_ESTATE (and
  * frees nothing) while meshes, Crank-Nicolson steppers or batches created on
  * it are alive: destroy those first. */
@@ -71,13 +92,16 @@ int phf_set_stream(phf_ctx* ctx, void* hip_stream);
 
 /* ---- device memory -------------------------------------------------------
  * All device memory the library owns (mesh tables, solver and time-stepper
- * state, temporaries) comes from a caching pool of the context: a released
- * block is kept and handed out again for a request of the same rounded size
- * (512 B granules up to 1 MiB, 2 MiB granules above), so rebuilding meshes of
- * the same sizes makes no hipMalloc/hipFree calls. The library runs all its
- * work in order on the context's stream, which makes reuse safe. Cached
- * blocks return to HIP on phf_release_cache, when an allocation fails (then
- * it is retried once), and in phf_destroy. Not thread-safe per context. */
+ * state, temporaries) comes from a caching pool of the context, which takes
+ * its blocks from the context's allocator (phf_create): a released block is
+ * kept and handed out again for a request of the same rounded size (512 B
+ * granules up to 1 MiB, 2 MiB granules above), so rebuilding meshes of the
+ * same sizes makes no allocator calls. The library runs all its work in order
+ * on the context's stream, which makes reuse safe. Cached blocks go back to
+ * the allocator on phf_release_cache, when an allocation fails (then it is
+ * retried once), and in phf_destroy; blocks of objects that outlive their
+ * context go back when those objects are destroyed. Not thread-safe per
+ * context. */
 /* Bytes held by live library objects / kept in the cache (either nullable). */
 int phf_mem_stats(phf_ctx* ctx, int64_t* live_bytes, int64_t* cached_bytes);
 /* Waits for the stream, then frees every cached block. */
@@ -158,6 +182,8 @@ typedef struct {
     int64_t device_bytes;      /* device memory held by the mesh             */
 } phf_mesh_info;
 
+/* Sizes of a mesh. (Named _get_info because C does not allow a function
+ * and the struct typedef above to share the name phf_mesh_info.) */
 int phf_mesh_get_info(const phf_mesh* mesh, phf_mesh_info* out);
 
 /* Copies topology tables into caller buffers in memory space `ms` (device

@@ -55,13 +55,21 @@ extern "C" const char* phf_version(void) { return "0.1.0"; }
 struct phf_pool {
     std::multimap<size_t, void*> free_blocks;  // rounded size -> block
     int64_t live_bytes = 0, cached_bytes = 0;
+    phf_allocator al{};                        // the context's allocator (alloc null: HIP)
 };
 
 namespace {
 std::mutex g_pool_mu;
-// every block handed out by any pool: owner (null once that context is
-// destroyed: the block then goes straight back to HIP) and rounded size
-std::unordered_map<void*, std::pair<phf_pool*, size_t>> g_blocks;
+
+// Where a block came from, so that it goes back there even after its
+// context is gone: the owning pool (null once that context is destroyed),
+// the rounded size and the allocator.
+struct block_rec {
+    phf_pool* pool;
+    size_t size;
+    phf_allocator al;
+};
+std::unordered_map<void*, block_rec> g_blocks;
 
 size_t round_block(size_t bytes)
 {
@@ -70,12 +78,32 @@ size_t round_block(size_t bytes)
                                       : (bytes + large - 1) / large * large;
 }
 
+void* raw_alloc(const phf_allocator& al, size_t bytes)
+{
+    if (al.alloc) return al.alloc(bytes, al.user);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void raw_free(const phf_allocator& al, void* p)
+{
+    if (al.alloc) {
+        if (al.free) al.free(p, al.user);
+        return;
+    }
+    (void)hipFree(p);
+}
+
 // Frees every cached block of the pool (caller holds the lock).
 void pool_trim(phf_pool* pl)
 {
     for (auto& kv : pl->free_blocks) {
         g_blocks.erase(kv.second);
-        (void)hipFree(kv.second);
+        raw_free(pl->al, kv.second);
     }
     pl->free_blocks.clear();
     pl->cached_bytes = 0;
@@ -97,19 +125,15 @@ int phf_dmalloc_bytes(phf_ctx* ctx, void** p, size_t bytes, const char* what)
         pl->free_blocks.erase(it);
         return PHF_OK;
     }
-    hipError_t e = hipMalloc(p, sz);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
+    *p = raw_alloc(pl->al, sz);
+    if (!*p) {
         pool_trim(pl);
-        e = hipMalloc(p, sz);
+        *p = raw_alloc(pl->al, sz);
     }
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        *p = nullptr;
+    if (!*p)
         return phf_set_error(ctx, PHF_ENOMEM, "device allocation of %s (%zu bytes) failed", what,
                              bytes);
-    }
-    g_blocks[*p] = {pl, sz};
+    g_blocks[*p] = block_rec{pl, sz, pl->al};
     pl->live_bytes += (int64_t)sz;
     return PHF_OK;
 }
@@ -122,11 +146,12 @@ void phf_dfree_ptr(void* p)
         (void)hipFree(p);
         return;
     }
-    phf_pool* pl = it->second.first;
-    const size_t sz = it->second.second;
+    phf_pool* pl = it->second.pool;
+    const size_t sz = it->second.size;
     if (!pl) {
+        const phf_allocator al = it->second.al;
         g_blocks.erase(it);
-        (void)hipFree(p);
+        raw_free(al, p);
         return;
     }
     pl->live_bytes -= (int64_t)sz;
@@ -156,10 +181,11 @@ extern "C" int phf_release_cache(phf_ctx* ctx)
 // context
 // ---------------------------------------------------------------------------
 
-extern "C" int phf_create(phf_ctx** out, int device, void* hip_stream)
+extern "C" int phf_create(phf_ctx** out, int device, void* hip_stream, const phf_allocator* alloc)
 {
     if (!out) return PHF_EINVAL;
     *out = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->free)) return PHF_EINVAL;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
         (void)hipGetLastError();
@@ -174,15 +200,21 @@ extern "C" int phf_create(phf_ctx** out, int device, void* hip_stream)
         delete ctx;
         return PHF_ENOMEM;
     }
+    if (alloc) ctx->pool->al = *alloc;
     if (hipSetDevice(device) != hipSuccess) {
+        delete ctx->pool;
         delete ctx;
         return PHF_EHIP;
     }
-    if (hipMalloc((void**)&ctx->d_flags, 64 * sizeof(int)) != hipSuccess ||
+    if (phf_dmalloc(ctx, &ctx->d_flags, 64, "context flags") != PHF_OK ||
         hipHostMalloc((void**)&ctx->h_pinned, 64 * sizeof(int64_t), hipHostMallocDefault) !=
             hipSuccess) {
         (void)hipGetLastError();
-        if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+        phf_dfree(ctx->d_flags);
+        {
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            pool_trim(ctx->pool);
+        }
         delete ctx->pool;
         delete ctx;
         return PHF_ENOMEM;
@@ -206,15 +238,15 @@ extern "C" int phf_destroy(phf_ctx* ctx)
         ctx->event_pool.push_back(r.stop);
     }
     for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
-    if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+    phf_dfree(ctx->d_flags);
     if (ctx->h_pinned) (void)hipHostFree(ctx->h_pinned);
     {
         std::lock_guard<std::mutex> lk(g_pool_mu);
         pool_trim(ctx->pool);
-        // blocks still held by objects of this context are released to HIP
-        // directly when those objects are destroyed
+        // blocks still held by objects of this context go back to the
+        // allocator directly when those objects are destroyed
         for (auto& kv : g_blocks)
-            if (kv.second.first == ctx->pool) kv.second.first = nullptr;
+            if (kv.second.pool == ctx->pool) kv.second.pool = nullptr;
         delete ctx->pool;
     }
     delete ctx;

@@ -267,7 +267,7 @@ extern "C" int phf_server_create(int device, const phf_server_opts* opts, phf_se
         hipStream_t st = nullptr;
         phf_ctx* c = nullptr;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
-            phf_create(&c, device, st) != PHF_OK) {
+            phf_create(&c, device, st, nullptr) != PHF_OK) {
             (void)hipGetLastError();
             if (st) (void)hipStreamDestroy(st);
             server_stop(s);

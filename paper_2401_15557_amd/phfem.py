@@ -108,6 +108,14 @@ class phf_cn_opts(ctypes.Structure):
                 ("mg_range", ctypes.c_double)]
 
 
+PHF_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+PHF_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class phf_allocator(ctypes.Structure):
+    _fields_ = [("alloc", PHF_ALLOC_FN), ("free", PHF_FREE_FN), ("user", ctypes.c_void_p)]
+
+
 class phf_batch_config(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("ms", ctypes.c_double)]
@@ -146,7 +154,7 @@ class phf_server_stats(ctypes.Structure):
 _lib = None
 _VP, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 _SIGS = {
-    "phf_create": [ctypes.POINTER(_VP), ctypes.c_int, _VP],
+    "phf_create": [ctypes.POINTER(_VP), ctypes.c_int, _VP, ctypes.POINTER(phf_allocator)],
     "phf_destroy": [_VP],
     "phf_set_stream": [_VP, _VP],
     "phf_synchronize": [_VP],
@@ -259,9 +267,41 @@ def phf_status_str(code):
     return load().phf_status_str(code).decode()
 
 
-def phf_create(device=0, stream=None):
+def make_allocator(alloc_fn, free_fn):
+    """A phf_allocator calling two Python functions: alloc_fn(nbytes) -> device
+    address (0 or an exception: failure) and free_fn(address). The returned
+    structure keeps the C callbacks alive; keep it as long as the context."""
+    def _alloc(nbytes, user):
+        try:
+            return int(alloc_fn(int(nbytes))) or None
+        except Exception:
+            return None
+
+    def _free(ptr, user):
+        try:
+            free_fn(int(ptr))
+        except Exception:
+            pass
+
+    a = phf_allocator(PHF_ALLOC_FN(_alloc), PHF_FREE_FN(_free), None)
+    a._keep = (_alloc, _free)
+    return a
+
+
+def torch_allocator(device, stream):
+    """phf_allocator backed by torch's caching allocator on ``stream``, so that
+    torch owns every device byte of the context."""
+    import torch
+    return make_allocator(lambda n: torch.cuda.caching_allocator_alloc(n, device, stream),
+                          torch.cuda.caching_allocator_delete)
+
+
+def phf_create(device=0, stream=None, allocator=None):
+    """allocator: a phf_allocator (make_allocator / torch_allocator) or None
+    (the library's hipMalloc)."""
     h = _VP()
-    _call("phf_create", None, ctypes.byref(h), int(device), _ptr(stream))
+    _call("phf_create", None, ctypes.byref(h), int(device), _ptr(stream),
+          ctypes.byref(allocator) if allocator is not None else None)
     return h.value
 
 
@@ -607,15 +647,20 @@ def phf_cn_destroy(cn):
 # ---- conveniences: tensor allocation around the calls above ----------------
 
 class Context:
-    """A phf context on ``device`` bound to torch's current stream."""
+    """A phf context on ``device`` bound to torch's current stream. Its device
+    memory comes from torch's caching allocator unless ``allocator`` is
+    given (a phf_allocator, or False for the library's own hipMalloc)."""
 
-    def __init__(self, device=0, stream=None):
+    def __init__(self, device=0, stream=None, allocator=None):
         import torch
         self.device = torch.device("cuda", device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
-        self.handle = phf_create(device, stream.cuda_stream)
+        if allocator is None:
+            allocator = torch_allocator(self.device, stream)
+        self.allocator = allocator or None
+        self.handle = phf_create(device, stream.cuda_stream, self.allocator)
         self._meshes = []  # weak references, in creation order
 
     def close(self):
@@ -705,23 +750,28 @@ class Mesh:
         return out
 
 
-def alloc_system(mesh: Mesh, with_D=False, with_S=False):
-    """Device output tensors sized from the mesh info, and the phf_system."""
-    return alloc_system_for(mesh.info, mesh.ctx.device, with_D, with_S)
+def alloc_system(mesh: Mesh, with_D=False, with_S=False, fill=None):
+    """Device output tensors sized from the mesh info, and the phf_system.
+    fill: a value written into every output first (tests pass NaN, so that
+    an entry the library does not write cannot pass a comparison)."""
+    return alloc_system_for(mesh.info, mesh.ctx.device, with_D, with_S, fill)
 
 
-def alloc_system_for(i, dev, with_D=False, with_S=False):
+def alloc_system_for(i, dev, with_D=False, with_S=False, fill=None):
     """As alloc_system, from a phf_mesh_info and a torch device."""
     import torch
-    t = dict(K=torch.empty(i.nnz_K, dtype=torch.float64, device=dev),
-             M=torch.empty(i.nnz_K, dtype=torch.float64, device=dev),
-             C=torch.empty(max(i.nnz_C, 1), dtype=torch.float64, device=dev),
-             F=torch.empty(i.N, dtype=torch.float64, device=dev),
-             bD=torch.empty(max(i.L, 1), dtype=torch.float64, device=dev))
+
+    def buf(n):
+        if fill is None:
+            return torch.empty(n, dtype=torch.float64, device=dev)
+        return torch.full((n,), float(fill), dtype=torch.float64, device=dev)
+
+    t = dict(K=buf(i.nnz_K), M=buf(i.nnz_K), C=buf(max(i.nnz_C, 1)), F=buf(i.N),
+             bD=buf(max(i.L, 1)))
     if with_D:
-        t["D"] = torch.empty(i.nnz_K, dtype=torch.float64, device=dev)
+        t["D"] = buf(i.nnz_K)
     if with_S:
-        t["S"] = torch.empty(i.nnz_saddle, dtype=torch.float64, device=dev)
+        t["S"] = buf(i.nnz_saddle)
     s = phf_system()
     for k, v in t.items():
         setattr(s, k, v.data_ptr())

@@ -50,6 +50,8 @@ int main(void){
    sizeof(phf_result), sizeof(phf_server_stats));
  printf("%zu %zu %zu %zu\n", offsetof(phf_data, g), offsetof(phf_data, t),
    offsetof(phf_solver_opts, rtol), offsetof(phf_mesh_info, nnz_K));
+ printf("%zu %zu %zu %zu\n", sizeof(phf_allocator), offsetof(phf_allocator, alloc),
+   offsetof(phf_allocator, free), offsetof(phf_allocator, user));
  return 0;}
 '''
     with tempfile.TemporaryDirectory() as d:
@@ -67,6 +69,9 @@ int main(void){
     assert sizes == [ctypes.sizeof(s) for s in mirror]
     assert offs == [phfem.phf_data.g.offset, phfem.phf_data.t.offset,
                     phfem.phf_solver_opts.rtol.offset, phfem.phf_mesh_info.nnz_K.offset]
+    al = [int(v) for v in out[2].split()]
+    A = phfem.phf_allocator
+    assert al == [ctypes.sizeof(A), A.alloc.offset, A.free.offset, A.user.offset]
 
 
 def test_status_strings(lib):
@@ -84,7 +89,7 @@ def test_null_arguments_rejected(lib):
     assert lib.phf_assemble(None, None, None, None) == -1
     assert lib.phf_solve(None, None, None, None, None, None, None) == -1
     assert lib.phf_cn_destroy(None) == -1
-    assert lib.phf_create(None, 0, None) == -1
+    assert lib.phf_create(None, 0, None, None) == -1
 
 
 def test_missing_library_fails_loudly(tmp_path):
