@@ -5,16 +5,18 @@
 // K, M, D is the identity map (element m owns values 9m..9m+8), and C rows
 // are written in place at their precomputed row pointers.
 //
-// Memory layout: element tiles read the element-major coordinate copy built
-// with the mesh (three double2 per triangle, streamed) and the element code
-// words, not the node array through vertex ids: with the paper's
-// red-refinement numbering consecutive triangles are far apart, and three
-// scattered 16-byte gathers per triangle cost more than streaming 48 bytes.
-// An element tile of 256 triangles computes its 9 K values per element into
-// LDS and the whole tile then streams out as one contiguous 18 KB block with
-// 16-byte stores; M is regenerated from the staged areas; F from a staged
-// 3-value record. Multiplier rows gather their two end nodes (rows are in
-// edge-id order, so the larger end node is monotone).
+// Memory layout: element tiles read element-major vertex coordinates
+// (three double2 per triangle, streamed), not the node array through vertex
+// ids: with the paper's red-refinement numbering consecutive triangles are
+// far apart, and three scattered 16-byte gathers per triangle cost more than
+// streaming 48 bytes. On a mesh refined by phf_mesh_refine the tiles form
+// each child's vertices from its parent's record (24 bytes per element
+// instead of 48); other meshes read their own. An element tile of 256
+// triangles computes its 9 K values per element into LDS and the whole tile
+// then streams out as one contiguous 18 KB block with 16-byte non-temporal
+// stores; M is regenerated from the staged areas; F from a staged 3-value
+// record. Multiplier rows gather their two end nodes (rows are in edge-id
+// order, so the larger end node is monotone).
 #include <algorithm>
 
 #include "phf_device.h"
@@ -26,7 +28,9 @@ constexpr int TILE = 256;
 
 struct AsmArgs {
     int32_t nE, L, nbE, nbR;
+    int32_t nEp, pad_;      // refined meshes: elements of the coarse mesh (nE = 4 nEp)
     const double2* exy;
+    const double2* pexy;    // coarse mesh's element-major coordinates, or null
     const int32_t* ecode;
     const double2* xy;
     const double* aT;
@@ -68,7 +72,174 @@ __device__ inline void fused_tile(int32_t b, int32_t nbE, int32_t nbR, bool* is_
     }
 }
 
-template <int TN, bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A>
+// Element m with vertices P0, P1, P2 (counter-clockwise): its K (9 values,
+// row-major), |T|/12 (M is regenerated from it), D and F = b + LN (3 values)
+// into LDS slot `slot`.
+template <bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A>
+__device__ inline void element_values(const AsmArgs& a, int32_t m, const double2 P0,
+                                      const double2 P1, const double2 P2, int slot, double* shK,
+                                      double* shD, double* shA, double* shF)
+{
+    // No contraction into fused multiply-adds here: element and parent tiles
+    // (different instantiations, scheduled differently) then round every
+    // value the same way and give bit-identical outputs.
+#pragma clang fp contract(off)
+    // g_i = 2|T| grad lambda_i (the edge opposite vertex i turned by 90 deg)
+    const double g0x = P1.y - P2.y, g0y = P2.x - P1.x;
+    const double g1x = P2.y - P0.y, g1y = P0.x - P2.x;
+    const double g2x = P0.y - P1.y, g2y = P1.x - P0.x;
+    const double det = (P1.x - P0.x) * (P2.y - P0.y) - (P2.x - P0.x) * (P1.y - P0.y);
+    const double area = 0.5 * det;
+    if (MATS) {
+        const double aT = HAS_AT ? a.aT[m] : 1.0;
+        const double s = aT / (2.0 * det);
+        double k00, k01, k02, k11, k12, k22, k10, k20, k21;
+        if (GEN_A) {
+            // K[j][i] = aT |T| (A grad lambda_j) . grad lambda_i
+            double a0x = a.A00 * g0x + a.A01 * g0y, a0y = a.A10 * g0x + a.A11 * g0y;
+            double a1x = a.A00 * g1x + a.A01 * g1y, a1y = a.A10 * g1x + a.A11 * g1y;
+            double a2x = a.A00 * g2x + a.A01 * g2y, a2y = a.A10 * g2x + a.A11 * g2y;
+            k00 = s * (a0x * g0x + a0y * g0y);
+            k01 = s * (a0x * g1x + a0y * g1y);
+            k02 = s * (a0x * g2x + a0y * g2y);
+            k10 = s * (a1x * g0x + a1y * g0y);
+            k11 = s * (a1x * g1x + a1y * g1y);
+            k12 = s * (a1x * g2x + a1y * g2y);
+            k20 = s * (a2x * g0x + a2y * g0y);
+            k21 = s * (a2x * g1x + a2y * g1y);
+            k22 = s * (a2x * g2x + a2y * g2y);
+        } else {
+            k00 = s * (g0x * g0x + g0y * g0y);
+            k11 = s * (g1x * g1x + g1y * g1y);
+            k22 = s * (g2x * g2x + g2y * g2y);
+            k01 = s * (g0x * g1x + g0y * g1y);
+            k02 = s * (g0x * g2x + g0y * g2y);
+            k12 = s * (g1x * g2x + g1y * g2y);
+            k10 = k01;
+            k20 = k02;
+            k21 = k12;
+        }
+        double* kk = shK + slot * 9;
+        kk[0] = k00; kk[1] = k01; kk[2] = k02;
+        kk[3] = k10; kk[4] = k11; kk[5] = k12;
+        kk[6] = k20; kk[7] = k21; kk[8] = k22;
+        shA[slot] = area / 12.0;
+        if (WITH_D) {
+            // D[j][i] = (|T|/3) p . grad lambda_i = p . g_i / 6
+            double h0 = (a.p0 * g0x + a.p1 * g0y) / 6.0;
+            double h1 = (a.p0 * g1x + a.p1 * g1y) / 6.0;
+            double h2 = (a.p0 * g2x + a.p1 * g2y) / 6.0;
+            double* dd = shD + slot * 9;
+            dd[0] = h0; dd[1] = h1; dd[2] = h2;
+            dd[3] = h0; dd[4] = h1; dd[5] = h2;
+            dd[6] = h0; dd[7] = h1; dd[8] = h2;
+        }
+    }
+    // source load: midpoint rule over the three edge midpoints; the
+    // midpoint of edge i (opposite vertex i) has lambda_j = 1/2, j != i
+    int32_t ed0 = -1, ed1 = -1, ed2 = -1;
+    const bool fe = a.f.kind == PHF_FN_EDGE_ARRAY;
+    if (fe) {
+        ed0 = a.elem_edges[3 * (int64_t)m];
+        ed1 = a.elem_edges[3 * (int64_t)m + 1];
+        ed2 = a.elem_edges[3 * (int64_t)m + 2];
+    }
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0;
+    if (a.f.kind != PHF_FN_ZERO) {
+        const double f0 = phf_fn_eval(a.f, 0.5 * (P1.x + P2.x), 0.5 * (P1.y + P2.y), a.t, 0, 0, ed0);
+        const double f1 = phf_fn_eval(a.f, 0.5 * (P2.x + P0.x), 0.5 * (P2.y + P0.y), a.t, 0, 0, ed1);
+        const double f2 = phf_fn_eval(a.f, 0.5 * (P0.x + P1.x), 0.5 * (P0.y + P1.y), a.t, 0, 0, ed2);
+        const double c = area / 6.0;
+        b0 = c * (f1 + f2);
+        b1 = c * (f0 + f2);
+        b2 = c * (f0 + f1);
+    }
+    // Neumann load: |E| g(m_E) / 2 on the two vertices of each Neumann
+    // edge, for the (boundary) elements flagged in the mask
+    if ((a.neu_mask[m >> 6] >> (m & 63)) & 1) {
+        const int code = a.ecode[m];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (PHF_CODE_TYPE(code, i) != 2) continue;
+            const double2 Pa = i == 0 ? P1 : (i == 1 ? P2 : P0);
+            const double2 Pb = i == 0 ? P2 : (i == 1 ? P0 : P1);
+            const double dx = Pb.x - Pa.x, dy = Pb.y - Pa.y;
+            const double len = sqrt(dx * dx + dy * dy);
+            const int32_t eid =
+                a.g.kind == PHF_FN_EDGE_ARRAY ? a.elem_edges[3 * (int64_t)m + i] : -1;
+            // outward normal of the counter-clockwise edge Pa -> Pb
+            const double gv = phf_fn_eval(a.g, 0.5 * (Pa.x + Pb.x), 0.5 * (Pa.y + Pb.y), a.t,
+                                          dy / len, -dx / len, eid);
+            const double w = len * gv * 0.5;
+            if (i == 0) { b1 += w; b2 += w; }
+            if (i == 1) { b2 += w; b0 += w; }
+            if (i == 2) { b0 += w; b1 += w; }
+        }
+    }
+    shF[3 * slot] = b0;
+    shF[3 * slot + 1] = b1;
+    shF[3 * slot + 2] = b2;
+}
+
+typedef double phf_v2d __attribute__((ext_vector_type(2)));
+
+// Output stores. NT: non-temporal (streamed to memory without displacing
+// cached lines): the outputs are written once and not read again by the
+// kernel, so that back-to-back assemblies of one mesh keep its inputs (the
+// coarse coordinates, a_T, row records, about 40 bytes per element) in the
+// last-level cache instead of the previous launch's outputs.
+template <bool NT>
+__device__ inline void put2(phf_v2d* p, double x, double y)
+{
+    phf_v2d w;
+    w.x = x;
+    w.y = y;
+    if (NT) __builtin_nontemporal_store(w, p);
+    else *p = w;
+}
+
+template <bool NT>
+__device__ inline void put1(double* p, double x)
+{
+    if (NT) __builtin_nontemporal_store(x, p);
+    else *p = x;
+}
+
+// Streams cnt values v(0..cnt-1) to dst with 16-byte stores where dst allows
+// (dst is 8-byte aligned; a leading odd word is stored alone).
+template <int TN, bool NT, typename F>
+__device__ inline void store_run(double* dst, int32_t cnt, F v)
+{
+    const int tid = threadIdx.x;
+    const int32_t head = (((uintptr_t)dst & 15) != 0 && cnt > 0) ? 1 : 0;
+    if (head && tid == 0) put1<NT>(dst, v(0));
+    const int32_t pairs = (cnt - head) >> 1;
+    phf_v2d* d2 = reinterpret_cast<phf_v2d*>(dst + head);
+    for (int32_t q = tid; q < pairs; q += TN) put2<NT>(d2 + q, v(head + 2 * q), v(head + 2 * q + 1));
+    if (((cnt - head) & 1) && tid == 0) put1<NT>(dst + cnt - 1, v(cnt - 1));
+}
+
+// Stores elements m0 .. m0+cnt-1 from LDS slots 0 .. cnt-1: K, M, (D) as 9
+// contiguous values per element, F as 3.
+template <int TN, bool NT, bool MATS, bool WITH_D>
+__device__ inline void store_elements(const AsmArgs& a, int32_t m0, int32_t cnt, const double* shK,
+                                      const double* shD, const double* shA, const double* shF)
+{
+    if (MATS) {
+        store_run<TN, NT>(a.K + 9 * (int64_t)m0, 9 * cnt, [&](int32_t v) { return shK[v]; });
+        store_run<TN, NT>(a.M + 9 * (int64_t)m0, 9 * cnt, [&](int32_t v) {
+            const int32_t el = v / 9, r = v - 9 * el;
+            return shA[el] * ((r & 3) == 0 ? 2.0 : 1.0);
+        });
+        if (WITH_D)
+            store_run<TN, NT>(a.D + 9 * (int64_t)m0, 9 * cnt, [&](int32_t v) { return shD[v]; });
+    }
+    store_run<TN, NT>(a.F + 3 * (int64_t)m0, 3 * cnt, [&](int32_t v) { return shF[v]; });
+}
+
+// An element tile: TN consecutive elements, vertices from the element-major
+// coordinate copy.
+template <int TN, bool NT, bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A>
 __device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK, double* shD,
                                     double* shA, double* shF)
 {
@@ -79,143 +250,57 @@ __device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK,
         const int32_t m = m0 + tid;
         const double2 P0 = a.exy[3 * (int64_t)m], P1 = a.exy[3 * (int64_t)m + 1];
         const double2 P2 = a.exy[3 * (int64_t)m + 2];
-        // g_i = 2|T| grad lambda_i (the edge opposite vertex i turned by 90 deg)
-        const double g0x = P1.y - P2.y, g0y = P2.x - P1.x;
-        const double g1x = P2.y - P0.y, g1y = P0.x - P2.x;
-        const double g2x = P0.y - P1.y, g2y = P1.x - P0.x;
-        const double det = (P1.x - P0.x) * (P2.y - P0.y) - (P2.x - P0.x) * (P1.y - P0.y);
-        const double area = 0.5 * det;
-        if (MATS) {
-            const double aT = HAS_AT ? a.aT[m] : 1.0;
-            const double s = aT / (2.0 * det);
-            double k00, k01, k02, k11, k12, k22, k10, k20, k21;
-            if (GEN_A) {
-                // K[j][i] = aT |T| (A grad lambda_j) . grad lambda_i
-                double a0x = a.A00 * g0x + a.A01 * g0y, a0y = a.A10 * g0x + a.A11 * g0y;
-                double a1x = a.A00 * g1x + a.A01 * g1y, a1y = a.A10 * g1x + a.A11 * g1y;
-                double a2x = a.A00 * g2x + a.A01 * g2y, a2y = a.A10 * g2x + a.A11 * g2y;
-                k00 = s * (a0x * g0x + a0y * g0y);
-                k01 = s * (a0x * g1x + a0y * g1y);
-                k02 = s * (a0x * g2x + a0y * g2y);
-                k10 = s * (a1x * g0x + a1y * g0y);
-                k11 = s * (a1x * g1x + a1y * g1y);
-                k12 = s * (a1x * g2x + a1y * g2y);
-                k20 = s * (a2x * g0x + a2y * g0y);
-                k21 = s * (a2x * g1x + a2y * g1y);
-                k22 = s * (a2x * g2x + a2y * g2y);
-            } else {
-                k00 = s * (g0x * g0x + g0y * g0y);
-                k11 = s * (g1x * g1x + g1y * g1y);
-                k22 = s * (g2x * g2x + g2y * g2y);
-                k01 = s * (g0x * g1x + g0y * g1y);
-                k02 = s * (g0x * g2x + g0y * g2y);
-                k12 = s * (g1x * g2x + g1y * g2y);
-                k10 = k01;
-                k20 = k02;
-                k21 = k12;
-            }
-            double* kk = shK + tid * 9;
-            kk[0] = k00; kk[1] = k01; kk[2] = k02;
-            kk[3] = k10; kk[4] = k11; kk[5] = k12;
-            kk[6] = k20; kk[7] = k21; kk[8] = k22;
-            shA[tid] = area / 12.0;
-            if (WITH_D) {
-                // D[j][i] = (|T|/3) p . grad lambda_i = p . g_i / 6
-                double h0 = (a.p0 * g0x + a.p1 * g0y) / 6.0;
-                double h1 = (a.p0 * g1x + a.p1 * g1y) / 6.0;
-                double h2 = (a.p0 * g2x + a.p1 * g2y) / 6.0;
-                double* dd = shD + tid * 9;
-                dd[0] = h0; dd[1] = h1; dd[2] = h2;
-                dd[3] = h0; dd[4] = h1; dd[5] = h2;
-                dd[6] = h0; dd[7] = h1; dd[8] = h2;
-            }
-        }
-        // source load: midpoint rule over the three edge midpoints; the
-        // midpoint of edge i (opposite vertex i) has lambda_j = 1/2, j != i
-        int32_t ed0 = -1, ed1 = -1, ed2 = -1;
-        const bool fe = a.f.kind == PHF_FN_EDGE_ARRAY;
-        if (fe) {
-            ed0 = a.elem_edges[3 * (int64_t)m];
-            ed1 = a.elem_edges[3 * (int64_t)m + 1];
-            ed2 = a.elem_edges[3 * (int64_t)m + 2];
-        }
-        double b0 = 0.0, b1 = 0.0, b2 = 0.0;
-        if (a.f.kind != PHF_FN_ZERO) {
-            const double f0 = phf_fn_eval(a.f, 0.5 * (P1.x + P2.x), 0.5 * (P1.y + P2.y), a.t, 0, 0, ed0);
-            const double f1 = phf_fn_eval(a.f, 0.5 * (P2.x + P0.x), 0.5 * (P2.y + P0.y), a.t, 0, 0, ed1);
-            const double f2 = phf_fn_eval(a.f, 0.5 * (P0.x + P1.x), 0.5 * (P0.y + P1.y), a.t, 0, 0, ed2);
-            const double c = area / 6.0;
-            b0 = c * (f1 + f2);
-            b1 = c * (f0 + f2);
-            b2 = c * (f0 + f1);
-        }
-        // Neumann load: |E| g(m_E) / 2 on the two vertices of each Neumann
-        // edge, for the (boundary) elements flagged in the mask
-        if ((a.neu_mask[m >> 6] >> (m & 63)) & 1) {
-            const int code = a.ecode[m];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                if (PHF_CODE_TYPE(code, i) != 2) continue;
-                const double2 Pa = i == 0 ? P1 : (i == 1 ? P2 : P0);
-                const double2 Pb = i == 0 ? P2 : (i == 1 ? P0 : P1);
-                const double dx = Pb.x - Pa.x, dy = Pb.y - Pa.y;
-                const double len = sqrt(dx * dx + dy * dy);
-                const int32_t eid =
-                    a.g.kind == PHF_FN_EDGE_ARRAY ? a.elem_edges[3 * (int64_t)m + i] : -1;
-                // outward normal of the counter-clockwise edge Pa -> Pb
-                const double gv = phf_fn_eval(a.g, 0.5 * (Pa.x + Pb.x), 0.5 * (Pa.y + Pb.y), a.t,
-                                              dy / len, -dx / len, eid);
-                const double w = len * gv * 0.5;
-                if (i == 0) { b1 += w; b2 += w; }
-                if (i == 1) { b2 += w; b0 += w; }
-                if (i == 2) { b0 += w; b1 += w; }
-            }
-        }
-        shF[3 * tid] = b0;
-        shF[3 * tid + 1] = b1;
-        shF[3 * tid + 2] = b2;
+        element_values<HAS_AT, MATS, WITH_D, GEN_A>(a, m, P0, P1, P2, tid, shK, shD, shA, shF);
     }
     __syncthreads();
-    // coalesced tile stores (16-byte chunks; the tile base is 16-byte aligned)
-    if (MATS) {
-        const int32_t cnt = 9 * nt;
-        double2* K2 = reinterpret_cast<double2*>(a.K + 9 * (int64_t)m0);
-        double2* M2 = reinterpret_cast<double2*>(a.M + 9 * (int64_t)m0);
-        const double2* sK2 = reinterpret_cast<const double2*>(shK);
-        for (int32_t q = tid; q < cnt / 2; q += TN) {
-            K2[q] = sK2[q];
-            const int32_t v0 = 2 * q, v1 = 2 * q + 1;
-            const int32_t el0 = v0 / 9, el1 = v1 / 9;
-            const int32_t r0 = v0 - 9 * el0, r1 = v1 - 9 * el1;
-            M2[q] = make_double2(shA[el0] * ((r0 & 3) == 0 ? 2.0 : 1.0),
-                                 shA[el1] * ((r1 & 3) == 0 ? 2.0 : 1.0));
-        }
-        if ((cnt & 1) && tid == 0) {
-            const int32_t v = cnt - 1, el = v / 9, rr = v - 9 * el;
-            a.K[9 * (int64_t)m0 + v] = shK[v];
-            a.M[9 * (int64_t)m0 + v] = shA[el] * ((rr & 3) == 0 ? 2.0 : 1.0);
-        }
-        if (WITH_D) {
-            double2* D2 = reinterpret_cast<double2*>(a.D + 9 * (int64_t)m0);
-            const double2* sD2 = reinterpret_cast<const double2*>(shD);
-            for (int32_t q = tid; q < cnt / 2; q += TN) D2[q] = sD2[q];
-            if ((cnt & 1) && tid == 0) a.D[9 * (int64_t)m0 + cnt - 1] = shD[cnt - 1];
-        }
+    store_elements<TN, NT, MATS, WITH_D>(a, m0, nt, shK, shD, shA, shF);
+}
+
+// An element tile of a red-refined mesh: TN consecutive elements whose
+// vertices follow from their parent's (the coarse mesh's element-major
+// coordinates) exactly as the refinement forms them: Q_i = 0.5 (P_{i+1} +
+// P_{i+2}); element p < nEp is the interior child [Q0 Q1 Q2] of parent p and
+// element nEp + 3p + i the corner child [P_i Q_{i+2} Q_{i+1}] of its vertex
+// i. An interior child reads its parent's 48 bytes, the three corner
+// children of a parent (neighbouring lanes) share one read: 24 bytes per
+// element on average instead of the 48 of the element's own record. Each
+// tile still writes one contiguous run of every output (a tile covering
+// interior and corner children of different parents would split its writes
+// between two distant runs, which measured slower).
+template <int TN, bool NT, bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A>
+__device__ inline void child_tile(const AsmArgs& a, int32_t tile, double* shK, double* shD,
+                                  double* shA, double* shF)
+{
+    const int tid = threadIdx.x;
+    const int32_t m0 = tile * TN;
+    const int32_t nt = min(TN, a.nE - m0);
+    if (tid < nt) {
+        const int32_t m = m0 + tid;
+        const bool interior = m < a.nEp;
+        const int32_t j = m - a.nEp;
+        const int32_t p = interior ? m : j / 3;
+        const int c = interior ? 3 : j - 3 * p;  // corner vertex, or 3 for the interior child
+        const double2 P0 = a.pexy[3 * (int64_t)p], P1 = a.pexy[3 * (int64_t)p + 1];
+        const double2 P2 = a.pexy[3 * (int64_t)p + 2];
+        const double2 Q0 = make_double2(0.5 * (P1.x + P2.x), 0.5 * (P1.y + P2.y));
+        const double2 Q1 = make_double2(0.5 * (P2.x + P0.x), 0.5 * (P2.y + P0.y));
+        const double2 Q2 = make_double2(0.5 * (P0.x + P1.x), 0.5 * (P0.y + P1.y));
+        double2 V0, V1, V2;
+        if (c == 3) { V0 = Q0; V1 = Q1; V2 = Q2; }
+        else if (c == 0) { V0 = P0; V1 = Q2; V2 = Q1; }
+        else if (c == 1) { V0 = P1; V1 = Q0; V2 = Q2; }
+        else { V0 = P2; V1 = Q1; V2 = Q0; }
+        element_values<HAS_AT, MATS, WITH_D, GEN_A>(a, m, V0, V1, V2, tid, shK, shD, shA, shF);
     }
-    {
-        const int32_t cnt = 3 * nt;
-        double2* F2 = reinterpret_cast<double2*>(a.F + 3 * (int64_t)m0);
-        const double2* sF2 = reinterpret_cast<const double2*>(shF);
-        for (int32_t q = tid; q < cnt / 2; q += TN) F2[q] = sF2[q];
-        if ((cnt & 1) && tid == 0) a.F[3 * (int64_t)m0 + cnt - 1] = shF[cnt - 1];
-    }
+    __syncthreads();
+    store_elements<TN, NT, MATS, WITH_D>(a, m0, nt, shK, shD, shA, shF);
 }
 
 // A row tile: TN consecutive multiplier rows. Their C values are one
 // contiguous run starting at the tile's base pointer; each row's offset in it
 // is an exclusive scan of the row lengths (4 interior, 2 Dirichlet), the
 // Dirichlet rows being flagged by a negative first end node.
-template <int TN, bool MATS>
+template <int TN, bool NT, bool MATS>
 __device__ inline void row_tile(const AsmArgs& a, int32_t tile, int32_t* shs)
 {
     const int32_t r = tile * TN + threadIdx.x;
@@ -235,19 +320,19 @@ __device__ inline void row_tile(const AsmArgs& a, int32_t tile, int32_t* shs)
     const double len_e = sqrt(dx * dx + dy * dy);
     const double h = 0.5 * len_e;
     if (MATS) {
-        double2* C2 = reinterpret_cast<double2*>(a.C + c0);
-        C2[0] = make_double2(h, h);
-        if (!dirichlet) C2[1] = make_double2(-h, -h);
+        phf_v2d* C2 = reinterpret_cast<phf_v2d*>(a.C + c0);
+        put2<NT>(C2, h, h);
+        if (!dirichlet) put2<NT>(C2 + 1, -h, -h);
     }
     double v = 0.0;
     if (dirichlet && a.uD.kind != PHF_FN_ZERO) {
         int32_t eid = a.uD.kind == PHF_FN_EDGE_ARRAY ? a.row_edge[r] : -1;
         v = -len_e * phf_fn_eval(a.uD, 0.5 * (Pk.x + Pl.x), 0.5 * (Pk.y + Pl.y), a.t, 0, 0, eid);
     }
-    a.bD[r] = v;
+    put1<NT>(a.bD + r, v);
 }
 
-template <bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A>
+template <bool PARENT, bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A>
 __global__ __launch_bounds__(TILE) void k_assemble(AsmArgs a)
 {
     if (a.t_step) a.t = a.t0 + (double)(*a.t_step) * a.dt;
@@ -259,8 +344,14 @@ __global__ __launch_bounds__(TILE) void k_assemble(AsmArgs a)
     bool is_elem;
     int32_t tile;
     fused_tile(blockIdx.x, a.nbE, a.nbR, &is_elem, &tile);
-    if (is_elem) element_tile<TILE, HAS_AT, MATS, WITH_D, GEN_A>(a, tile, shK, shD, shA, shF);
-    else row_tile<TILE, MATS>(a, tile, shs);
+    if (is_elem) {
+        if (PARENT)
+            child_tile<TILE, true, HAS_AT, MATS, WITH_D, GEN_A>(a, tile, shK, shD, shA, shF);
+        else
+            element_tile<TILE, true, HAS_AT, MATS, WITH_D, GEN_A>(a, tile, shK, shD, shA, shF);
+    } else {
+        row_tile<TILE, true, MATS>(a, tile, shs);
+    }
 }
 
 // ---- batched assembly -------------------------------------------------------
@@ -269,8 +360,10 @@ __global__ __launch_bounds__(TILE) void k_assemble(AsmArgs a)
 // ~item.y. PERSIST = false: one workgroup per item; PERSIST = true: each
 // workgroup takes items blockIdx.x, blockIdx.x + gridDim.x, ... (the loop
 // costs about 25 more VGPRs, one wave per SIMD of occupancy). The instance
-// record is staged in LDS. The tile code is the single-mesh kernel's, so the
-// outputs are bit-identical to it.
+// record is staged in LDS. The tile code is the single-mesh kernel's
+// (element tiles read each mesh's own element records; stores are ordinary
+// ones, the batch's inputs being far larger than the last-level cache), so
+// the outputs are bit-identical to it.
 template <int TN, bool PERSIST, bool HAS_AT, bool WITH_D, bool GEN_A>
 __global__ __launch_bounds__(TN) void k_assemble_batch(const AsmArgs* __restrict__ args,
                                                        const int2* __restrict__ work,
@@ -290,8 +383,10 @@ __global__ __launch_bounds__(TN) void k_assemble_batch(const AsmArgs* __restrict
                 reinterpret_cast<const uint64_t*>(args + item.x)[threadIdx.x];
         __syncthreads();
         const AsmArgs& a = sa;
-        if (item.y >= 0) element_tile<TN, HAS_AT, true, WITH_D, GEN_A>(a, item.y, shK, shD, shA, shF);
-        else row_tile<TN, true>(a, ~item.y, shs);
+        if (item.y >= 0)
+            element_tile<TN, false, HAS_AT, true, WITH_D, GEN_A>(a, item.y, shK, shD, shA, shF);
+        else
+            row_tile<TN, false, true>(a, ~item.y, shs);
         if (!PERSIST) break;
         __syncthreads();  // the next item reuses the shared arrays
     }
@@ -381,8 +476,12 @@ __global__ __launch_bounds__(TILE) void k_saddle_values(SaddleArgs a)
 template <bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A>
 int launch_assemble(phf_ctx* ctx, const AsmArgs& a)
 {
-    PHF_LAUNCH(ctx, "k_assemble", (k_assemble<HAS_AT, MATS, WITH_D, GEN_A>), a.nbE + a.nbR, TILE,
-               0, a);
+    if (a.pexy)
+        PHF_LAUNCH(ctx, "k_assemble", (k_assemble<true, HAS_AT, MATS, WITH_D, GEN_A>),
+                   a.nbE + a.nbR, TILE, 0, a);
+    else
+        PHF_LAUNCH(ctx, "k_assemble", (k_assemble<false, HAS_AT, MATS, WITH_D, GEN_A>),
+                   a.nbE + a.nbR, TILE, 0, a);
     return PHF_OK;
 }
 
@@ -420,7 +519,10 @@ int make_args(phf_mesh* mesh, const phf_coeffs* co, const phf_data* data, const 
     a.L = mesh->L;
     a.nbE = (mesh->nE + TILE - 1) / TILE;
     a.nbR = (mesh->L + TILE - 1) / TILE;
+    a.nEp = 0;
+    a.pad_ = 0;
     a.exy = mesh->exy;
+    a.pexy = nullptr;
     a.ecode = mesh->ecode;
     a.xy = mesh->xy;
     a.aT = co->a_T;
@@ -464,6 +566,11 @@ int phf_assemble_impl(phf_mesh* mesh, const phf_coeffs* co, const phf_data* data
     phf_ctx* ctx = mesh->ctx;
     AsmArgs a;
     TRY(make_args(mesh, co, data, out, "phf_assemble", &a));
+    if (mesh->parent && mesh->parent->exy && mesh->nE == 4 * mesh->parent->nE) {
+        // red-refined: element tiles read the coarse mesh's coordinates
+        a.pexy = mesh->parent->exy;
+        a.nEp = mesh->parent->nE;
+    }
     a.t_step = t_step;
     a.t0 = t0;
     a.dt = dt;

@@ -87,6 +87,9 @@ __device__ inline double phf_block_sum_f64(double v, double* sh)
 __device__ inline double phf_fn_eval(const phf_fn_dev& f, double x, double y, double t, double nx,
                                      double ny, int32_t edge)
 {
+    // evaluated without fused multiply-adds, so that every kernel that
+    // inlines it rounds the same way
+#pragma clang fp contract(off)
     switch (f.kind) {
     case PHF_FN_ZERO: return 0.0;
     case PHF_FN_CONST: return f.c0;

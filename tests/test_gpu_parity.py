@@ -6,8 +6,8 @@ import numpy as np
 import pytest
 
 from paper_2401_15557_amd import meshgen as G
-from parity_util import (RTOL, assert_close_scaled, block_scale, compare_topology, gpu_tables,
-                         row_scale_fast)
+from parity_util import (NAN, RTOL, assert_close_scaled, assert_written, block_scale,
+                         compare_topology, gpu_tables, row_scale_fast)
 
 pytestmark = pytest.mark.gpu
 PI = np.pi
@@ -136,10 +136,11 @@ def test_assembly_values(ctx, oracle, name):
     aT_d = torch.tensor(aT, device=ctx.device) if aT is not None else None
     od, gd, keep = _data(oracle, phfem, case, topo_o, ctx.device)
     with_D = p != (0.0, 0.0)
-    sysg, tg = phfem.alloc_system(dm, with_D=with_D, with_S=True)
+    sysg, tg = phfem.alloc_system(dm, with_D=with_D, with_S=True, fill=NAN)
     co = phfem.make_coeffs(A, p, delta, aT_d)
     phfem.phf_assemble(dm.handle, co, gd, sysg)
     torch.cuda.synchronize()
+    assert_written(tg, dm.info)
     asm = oracle.assemble(m, topo_o, A=A, p=p, aT=aT, **od)
     for key in ("K", "M") + (("D",) if with_D else ()):
         o = asm[key]
@@ -166,9 +167,10 @@ def test_assembly_deterministic(ctx):
                         phfem.make_fn(phfem.PHF_FN_CONST, 1), phfem.make_fn(phfem.PHF_FN_CONST, 1))
     outs = []
     for _ in range(3):
-        s, t = phfem.alloc_system(dm)
+        s, t = phfem.alloc_system(dm, fill=NAN)
         phfem.phf_assemble(dm.handle, co, d, s)
         torch.cuda.synchronize()
+        assert_written(t, dm.info)
         outs.append({k: v.cpu().numpy().tobytes() for k, v in t.items()})
     assert outs[0] == outs[1] == outs[2]
     # a second mesh build gives identical tables
@@ -260,3 +262,75 @@ def test_memory_pool_reuse(ctx):
         np.testing.assert_array_equal(tops[2][k], tops[0][k])
     phfem.phf_release_cache(h)
     assert phfem.phf_mem_stats(h) == (live0, 0)
+
+
+def _pentagon():
+    """Five triangles around the origin (an odd element count, so the corner
+    children of the first refinement start at an odd element: their output
+    runs begin off 16-byte alignment). Dirichlet on two sides, Neumann on
+    three."""
+    ang = 2 * np.pi * np.arange(5) / 5 + 0.3
+    xy = np.vstack([[0.0, 0.0], np.stack([np.cos(ang), np.sin(ang)], axis=1)])
+    el = np.array([[0, 1 + i, 1 + (i + 1) % 5] for i in range(5)], np.int32)
+    bnd = np.array([[1 + i, 1 + (i + 1) % 5] for i in range(5)], np.int32)
+    return G.Mesh(xy, el, bnd[:2], bnd[2:], name="pentagon")
+
+
+REFINED = {
+    "pentagon": dict(base=_pentagon, levels=3, data="sincos", aT=5),
+    "paper_xsides": dict(base=lambda: G.paper_square(0, bc="x_sides"), levels=4, data="sincos"),
+    "lshape_D_aniso": dict(base=lambda: G.lshape(0), levels=3, data="const", aT=2,
+                           A=(2.0, 0.7, 0.7, 1.3), p=(0.5, -1.0)),
+    "paper_arrays": dict(base=lambda: G.paper_square(0), levels=3, data="arrays"),
+}
+
+
+@pytest.mark.parametrize("name", list(REFINED))
+def test_refined_assembly(ctx, oracle, name):
+    """Meshes refined on the device assemble from their parent's coordinates
+    (four children per parent thread group): every level against the oracle
+    on the same refined mesh, and bit for bit against the same mesh uploaded
+    directly (assembled from its own element records)."""
+    import torch
+    from paper_2401_15557_amd import phfem
+    case = REFINED[name]
+    base = case["base"]()
+    A = case.get("A", (1.0, 0.0, 0.0, 1.0))
+    p = case.get("p", (0.0, 0.0))
+    with_D = p != (0.0, 0.0)
+    dm = phfem.Mesh(ctx, base)
+    chain = [dm]
+    for lev in range(1, case["levels"] + 1):
+        dm = dm.refine()
+        chain.append(dm)
+        xy, el, d, n = dm.geometry()
+        m = G.Mesh(xy, el, d, n, name=f"{name}_L{lev}")
+        print(f"case {name} level {lev}: nE={m.nE}", flush=True)
+        topo_o = oracle.mesh_tables(m)
+        aT = G.per_triangle_coefficient(m.nE, case["aT"] + lev) if "aT" in case else None
+        aT_d = torch.tensor(aT, device=ctx.device) if aT is not None else None
+        od, gd, keep = _data(oracle, phfem, case, topo_o, ctx.device)
+        co = phfem.make_coeffs(A, p, 0.0, aT_d)
+        s, t = phfem.alloc_system(dm, with_D=with_D, fill=NAN)
+        phfem.phf_assemble(dm.handle, co, gd, s)
+        flat = phfem.Mesh(ctx, m)
+        s2, t2 = phfem.alloc_system(flat, with_D=with_D, fill=NAN)
+        phfem.phf_assemble(flat.handle, co, gd, s2)
+        torch.cuda.synchronize()
+        assert_written(t, dm.info)
+        for k in t:
+            assert t[k].cpu().numpy().tobytes() == t2[k].cpu().numpy().tobytes(), (lev, k)
+        asm = oracle.assemble(m, topo_o, A=A, p=p, aT=aT, **od)
+        for key in ("K", "M") + (("D",) if with_D else ()):
+            o = asm[key]
+            assert_close_scaled(t[key].cpu().numpy(), o, block_scale(o, 9), key)
+        nc = len(asm["C"])
+        assert_close_scaled(t["C"].cpu().numpy()[:nc], asm["C"],
+                            row_scale_fast(asm["C"], asm["C_rowptr"]), "C")
+        for key in ("F", "bD"):
+            o = asm[key]
+            assert_close_scaled(t[key].cpu().numpy()[:len(o)], o,
+                                np.full(len(o), np.abs(o).max() if len(o) else 1.0), key)
+        flat.close()
+    for c in reversed(chain):
+        c.close()
