@@ -2,38 +2,47 @@
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Workload (the elliptic benchmark configuration): L-shaped domain
-[-1,1]^2 minus [0,1]x[-1,0], 12 triangles red-refined 9 times =
-3,145,728 triangles, fp64, per-triangle coefficient a_T ~ U[0.5, 2]
-(seed 0), Dirichlet u_D = 1 on the two re-entrant edges, Neumann g = 1 on
-the rest, f = 2 pi^2 sin(pi x) cos(pi y). Inputs are synthetic and resident
-in device memory before timing starts.
+Headline workload (the paper's largest run): the unit square with the
+paper's four-triangle criss-cross start mesh, red-refined 10 times on the
+device = 4,194,304 triangles, fp64, per-triangle coefficient a_T ~ U[0.5, 2]
+(seed 0), Dirichlet u_D = 1 on x = 0 and x = 1, Neumann g = 1 on y = 0 and
+y = 1, f = 2 pi^2 sin(pi x) cos(pi y). Inputs are synthetic and resident in
+device memory before timing starts; the mesh, its edge tables and CSR
+patterns are built once (the paper times topology and assembly separately).
 
-One step = one pass of the elliptic hot path: the 12-triangle L-shape
-(device-resident) is validated and given its edge tables (phf_mesh_create),
-red-refined 9 times on the device, each level getting its edge tables,
-boundary classification and CSR patterns (phf_mesh_refine); the numeric
-assembly of K, M, C, F, b_D runs on the finest mesh (phf_assemble), and the
-saddle-point system is solved to a relative residual of 1e-10 by
-conjugate gradients preconditioned with a V-cycle over the refinement levels
-(phf_solve); then the meshes are released. `value` is finest-mesh elements
-per second through that step (Melem/s). `--precond jacobi` solves with the
-Jacobi preconditioner instead.
+One timed step = one numeric assembly of that mesh (phf_assemble): K, M, C,
+F = b + LN and b_D written into their CSR value arrays. `value` is assembled
+elements per second (Melem/s); `roofline` is that kernel's algorithmic
+bytes (268 B per triangle) over its average launch time, from HIP events the
+library records on its own stream during the timed steps.
 
 The JSON line also carries, measured in the same process:
-  rows      host-observed milliseconds between the calls of the step (the
-            library's calls return before their GPU work ends, so the mesh
-            build and the assembly run on in the next rows; the last row,
-            the release, waits for the solve's final kernels) and solver
-            iterations;
-  assembly  the numeric assembly alone (the paper's timed computation):
-            Melem/s, algorithmic GB/s and fraction of the HBM peak;
-  cn        Crank-Nicolson steps/s on the parabolic configuration (unit
-            square, 1,048,576 triangles, k = 1e-3, 200 steps), replaying one
-            captured HIP graph per step, and eagerly;
-  roofline  the dominant kernel of the step, from HIP events on the
-            library's stream over the timed region;
-  cpu_baseline  the CPU oracle on a bounded sample, one core.
+  pipeline   the whole elliptic path on the same workload per step: the
+             4-triangle base mesh uploaded and validated with its edge
+             tables (phf_mesh_create), 10 device red refinements with edge
+             tables, boundary classification and patterns
+             (phf_mesh_refine), the assembly, and the saddle solve by
+             multigrid-preconditioned conjugate gradients to rtol 1e-10 (and
+             once to 1e-13); stage times from events on the library stream;
+  lshape     the L-shaped configuration (12 triangles refined 9 times,
+             3,145,728 triangles, Dirichlet u_D = 1 on the re-entrant edges,
+             Neumann g = 1 elsewhere): assembly alone and the whole path;
+  kernels_traced_step  every kernel of one fully traced pipeline step, and
+             the dominant one (the finest multigrid sweep, whose operator
+             largely stays in the 256 MB last-level cache: its fraction is
+             labelled cache-assisted);
+  copy_probe a plain 512 MiB device-to-device copy (read + write bytes / time)
+             next to the 8 TB/s peak;
+  scatter    segment-length histogram of the scatter (source terms summed
+             into each output entry);
+  cn         Crank-Nicolson steps/s (unit square, 1,048,576 triangles,
+             k = 1e-3, 200 steps), replaying captured HIP graphs and eagerly;
+  batch      256 uneven meshes in one launch vs one launch per mesh;
+  serve      mixed elliptic / Crank-Nicolson requests at Poisson rates,
+             one slot vs continuous batching, p50/p99 latency;
+  cpu_baseline  the CPU oracle, one core, assembly alone on a bounded sample
+             of the headline workload (median of 5), plus the whole path with
+             sparse LU on a smaller sample.
 """
 from __future__ import annotations
 
@@ -70,10 +79,11 @@ def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None, jacobi=Fa
     last finest sweep, which also writes z (fp32 for CG) and reduces r.z,
     32 + 4 + 4 + 8 (r) + 4 (z) = 52 B/row; residual 32 + 4 (diag) + 4 + 4 +
     4 (r) = 48 B/row; prolongation 20 (five int32 columns) + 4 (five 4-bit
-    weight codes) + 8 (x in and out) = 32 B/fine row + 4 B/coarse row; restriction from level l: per coarse triangle 36 B of fine
-    row ids, 4 B code word, 12 B of sums written, plus the fine residual once
-    (4 B/fine row), then per coarse row 8 (positions) + 8 (two sums) + 4
-    (dinv) in, 4 (D^-1 b) + 4 (first sweep) out = 28 B.
+    weight codes) + 8 (x in and out) = 32 B/fine row + 4 B/coarse row;
+    restriction from level l: per coarse triangle 36 B of fine row ids, 4 B
+    code word, 12 B of sums written, plus the fine residual once (4 B/fine
+    row), then per coarse row 8 (positions) + 8 (two sums) + 4 (dinv) in,
+    4 (D^-1 b) + 4 (first sweep) out = 28 B.
     """
     nE, nC, L = info.nE, info.nC, info.L
     nf, nnzR = info.n_free, info.nnz_reduced
@@ -116,15 +126,16 @@ def sources_hash(files):
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel):
+def traffic_for(kernel, workload_key=None):
     """HBM traffic per launch from the committed counter summary, if it was
-    taken on the current sources of that kernel; otherwise None."""
+    taken on the current sources of that kernel (and on this workload, when
+    a key is given); otherwise None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(p))
     except (OSError, ValueError):
         return None
-    k = rec.get("kernels", {}).get(kernel)
+    k = rec.get("kernels", {}).get(workload_key or kernel)
     if not k:
         return None
     try:
@@ -135,20 +146,74 @@ def traffic_for(kernel):
     return k.get("bytes_per_launch")
 
 
-def cpu_baseline(level=7, repeat=2):
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return None
+
+
+def cpu_baseline(level, repeat, pipeline_level):
+    """The oracle on the host, one thread: assembly alone on the paper mesh
+    at `level` (median of `repeat`), and the whole path with sparse LU on the
+    L-shape at `pipeline_level`."""
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    r = subprocess.run([sys.executable, "-m", "oracle.baseline", "--level", str(level),
-                        "--repeat", str(repeat), "--solve"], cwd=ROOT, env=env,
-                       capture_output=True, text=True, timeout=600)
-    if r.returncode != 0:
-        return {"error": r.stderr[-500:]}
-    o = json.loads(r.stdout.strip().splitlines()[-1])
-    return {"value": o["nE"] / o["total_s"] / 1e6, "unit": "Melem/s", "cores": 1,
-            "kind": "oracle",
-            "sample": (f"L-shape level {level} ({o['nE']} triangles), same data; topology + "
-                       f"assembly + saddle CSR + sparse LU solve, best of {repeat}; "
-                       f"stage s: topo {o['topology_s']:.3f} asm {o['assembly_s']:.3f} "
-                       f"saddle {o['saddle_s']:.3f} solve {o['solve_s']:.3f}")}
+
+    def run(args):
+        r = subprocess.run([sys.executable, "-m", "oracle.baseline", *args], cwd=ROOT, env=env,
+                           capture_output=True, text=True, timeout=900)
+        if r.returncode != 0:
+            return {"error": r.stderr[-500:]}
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    a = run(["--mesh", "paper", "--level", str(level), "--repeat", str(repeat),
+             "--assembly-only"])
+    p = run(["--mesh", "lshape", "--level", str(pipeline_level), "--repeat", "2", "--solve"])
+    if "error" in a:
+        return a
+    out = {"value": round(a["nE"] / a["assembly_median_s"] / 1e6, 4), "unit": "Melem/s",
+           "cores": 1, "kind": "oracle",
+           "sample": (f"assembly alone (K, M, C, F, b_D into CSR) on the headline workload's mesh "
+                      f"at level {level} ({a['nE']} triangles, same data), median of {repeat} "
+                      f"runs {[round(x, 3) for x in a['assembly_runs_s']]} s, one thread; "
+                      f"topology {a['topology_s']:.3f} s"),
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    if "error" not in p:
+        out["pipeline"] = {
+            "value": round(p["nE"] / p["total_s"] / 1e6, 4), "unit": "Melem/s",
+            "sample": (f"L-shape level {pipeline_level} ({p['nE']} triangles): topology + "
+                       f"assembly + saddle CSR + sparse LU solve, best of 2"),
+            "stage_s": {k: round(p[k], 4) for k in ("topology_s", "assembly_s", "saddle_s",
+                                                      "solve_s")}}
+    return out
+
+
+def scatter_histogram(topo, nE):
+    """Segment lengths of the scatter: how many source terms are summed into
+    each output entry. K, M (element blocks), C (one per edge side and
+    vertex) and b_D (one per Dirichlet row) have exactly one; F gets the
+    element's body load plus |E| g / 2 from each Neumann edge of that element
+    through the vertex (local edges other than the vertex's own)."""
+    import numpy as np
+    et = topo["edge_type"].astype(np.int64)
+    ee = topo["elem_edges"].reshape(nE, 3)
+    neu = et[ee] == 2                         # local edge i of element m is Neumann
+    cnt = np.ones((nE, 3), np.int64)
+    for j in range(3):
+        for i in range(3):
+            if i != j:
+                cnt[:, j] += neu[:, i]
+    hist = np.bincount(cnt.reshape(-1))
+    f = {str(k): int(v) for k, v in enumerate(hist) if v}
+    # b_D: one term on a Dirichlet row, none (an explicit zero) on an
+    # interior row
+    return {"K": {"1": 9 * nE}, "M": {"1": 9 * nE}, "F": f,
+            "C": {"1": int(4 * (et == 0).sum() + 2 * (et == 1).sum())},
+            "bD": {"0": int((et == 0).sum()), "1": int((et == 1).sum())}}
 
 
 def serve_requests(G, phfem, count, seed):
@@ -224,29 +289,155 @@ def serve_run(phfem, reqs, rate, slots, seed):
                 triangles_per_s=round(sum(r.nE for r in res) / (t1 - t0), 1))
 
 
+
+
+def build_chain(phfem, h, base, levels):
+    """Device mesh chain: the base mesh (device arrays) and `levels` red
+    refinements; returns the handles, coarsest first."""
+    chain = [phfem.phf_mesh_create(h, *base, phfem.PHF_DEVICE)]
+    for _ in range(levels):
+        chain.append(phfem.phf_mesh_refine(chain[-1]))
+    return chain
+
+
+def release(phfem, chain):
+    for c in reversed(chain):
+        phfem.phf_mesh_destroy(c)
+
+
+def time_assembly(phfem, torch, h, mh, co, data, sysd, reps, warmup):
+    """`reps` back-to-back assemblies after `warmup` untimed ones: wall time
+    per call (stream synchronised on both sides) and the kernel's per-launch
+    times from the library's HIP events on its stream."""
+    for _ in range(warmup):
+        phfem.phf_assemble(mh, co, data, sysd)
+    torch.cuda.synchronize()
+    phfem.phf_trace_enable(h, True)
+    phfem.phf_trace_filter(h, "k_assemble")
+    phfem.phf_trace_reset(h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        phfem.phf_assemble(mh, co, data, sysd)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    samples = phfem.phf_trace_samples(h, "k_assemble")
+    phfem.phf_trace_filter(h, None)
+    phfem.phf_trace_enable(h, False)
+    return 1e3 * (t1 - t0) / reps, samples
+
+
+def time_assembly_cold(phfem, torch, h, mh, co, data, sysd, reps, dev):
+    """Per-launch kernel times of assemblies that each follow a 1 GiB device
+    copy, which evicts the inputs from the last-level cache."""
+    fa = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    fb = torch.empty_like(fa)
+    phfem.phf_trace_enable(h, True)
+    phfem.phf_trace_filter(h, "k_assemble")
+    phfem.phf_trace_reset(h)
+    for _ in range(reps):
+        fb.copy_(fa)
+        phfem.phf_assemble(mh, co, data, sysd)
+    torch.cuda.synchronize()
+    samples = phfem.phf_trace_samples(h, "k_assemble")
+    phfem.phf_trace_filter(h, None)
+    phfem.phf_trace_enable(h, False)
+    del fa, fb
+    return samples
+
+
+def assembly_summary(info, ms_call, samples, traffic_key, cold=None, has_aT=True):
+    ab = algorithmic_bytes(info, has_aT=has_aT)["k_assemble"]
+    avg_us = 1e3 * sum(samples) / len(samples)
+    gbs = ab / (avg_us * 1e-6) / 1e9
+    cold_s = None
+    if cold:
+        cus = 1e3 * sum(cold) / len(cold)
+        cgbs = ab / (cus * 1e-6) / 1e9
+        cold_s = {"kernel_us": round(cus, 2), "GB_per_s": round(cgbs, 1),
+                  "frac_of_hbm_peak": round(cgbs / HBM_PEAK_GBS, 4), "launches": len(cold),
+                  "note": "each launch after a 1 GiB copy (inputs evicted from the cache)"}
+    return {"Melem_per_s": round(info.nE / (ms_call * 1e3), 1),
+            "kernel_us": round(avg_us, 2), "kernel_us_min": round(1e3 * min(samples), 2),
+            "kernel_us_max": round(1e3 * max(samples), 2), "call_us": round(ms_call * 1e3, 2),
+            "kernel_Melem_per_s": round(info.nE / avg_us, 1),
+            "algorithmic_bytes": ab, "bytes_per_elem": round(ab / info.nE, 1),
+            "GB_per_s": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for("k_assemble", traffic_key), "launches": len(samples),
+            "cold": cold_s}
+
+
+def pipeline_steps(phfem, torch, h, base, levels, co, data, sysd, U, Lam, rtol, steps, pc):
+    """Whole elliptic path per step, with events on the library's stream
+    between the stages (device times, idle gaps while the host waits on a
+    read-back included)."""
+    rows = []
+    for _ in range(steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        t0 = time.perf_counter()
+        ev[0].record()
+        chain = build_chain(phfem, h, base, levels)
+        ev[1].record()
+        phfem.phf_assemble(chain[-1], co, data, sysd)
+        ev[2].record()
+        st = phfem.phf_solve(chain[-1], co, sysd, U, Lam, rtol=rtol, max_iter=200000,
+                             check_every=32 if pc == phfem.PHF_PRECOND_JACOBI else 0,
+                             precond=pc)
+        ev[3].record()
+        release(phfem, chain)
+        ev[4].record()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rows.append(dict(step_ms=1e3 * (t1 - t0), mesh_ms=ev[0].elapsed_time(ev[1]),
+                         assembly_ms=ev[1].elapsed_time(ev[2]),
+                         solve_ms=ev[2].elapsed_time(ev[3]),
+                         release_ms=ev[3].elapsed_time(ev[4]),
+                         iterations=st.iterations, rel_residual=st.rel_residual,
+                         converged=bool(st.converged)))
+    return rows
+
+
+def summarise_pipeline(rows, nE):
+    import numpy as np
+    med = {k: float(np.median([r[k] for r in rows])) for k in rows[0] if k != "converged"}
+    return {"steps": len(rows), "ms_per_step": round(med["step_ms"], 3),
+            "Melem_per_s": round(nE / (med["step_ms"] * 1e3), 2),
+            "device_stage_ms": {k[:-3]: round(med[k], 3)
+                                for k in ("mesh_ms", "assembly_ms", "solve_ms", "release_ms")},
+            "iterations": int(med["iterations"]), "rel_residual": med["rel_residual"],
+            "all_converged": all(r["converged"] for r in rows)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--level", type=int, default=9, help="L-shape refinement level")
-    ap.add_argument("--asm-reps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=100, help="timed assemblies")
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--level", type=int, default=10, help="paper-mesh refinement level")
+    ap.add_argument("--pipeline-steps", type=int, default=3)
+    ap.add_argument("--lshape-level", type=int, default=9)
     ap.add_argument("--cn-level", type=int, default=9)
     ap.add_argument("--cn-steps", type=int, default=200)
     ap.add_argument("--cn-chunk", type=int, default=8,
                     help="expected CG iterations of the first time step")
+    ap.add_argument("--cpu-level", type=int, default=9,
+                    help="paper-mesh level of the CPU oracle's assembly sample")
+    ap.add_argument("--cpu-repeat", type=int, default=5)
+    ap.add_argument("--no-lshape", action="store_true")
+    ap.add_argument("--no-pipeline", action="store_true")
     ap.add_argument("--no-cn", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--rtol", type=float, default=1e-10)
-    ap.add_argument("--mode", choices=("full", "assembly"), default="full",
-                    help="assembly: only the numeric assembly on the benchmark mesh plus one "
-                         "plain device copy of --copy-mib MiB (for hardware-counter runs)")
-    ap.add_argument("--copy-mib", type=int, default=None,
-                    help="size of the plain device copy run for counter calibration "
-                         "(default 512 in assembly mode, none in full mode)")
-    ap.add_argument("--precond", choices=("multigrid", "jacobi"), default="multigrid")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--mode", choices=("full", "assembly"), default="full",
+                    help="assembly: only the numeric assembly (headline mesh, or the L-shape "
+                         "with --workload lshape) plus one plain device copy of --copy-mib MiB "
+                         "(for hardware-counter runs)")
+    ap.add_argument("--workload", choices=("paper", "lshape"), default="paper")
+    ap.add_argument("--asm-reps", type=int, default=2)
+    ap.add_argument("--copy-mib", type=int, default=512)
+    ap.add_argument("--precond", choices=("multigrid", "jacobi"), default="multigrid")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--serve-rates", type=str, default="20,40,80",
                     help="Poisson arrival rates (requests/s) to sweep")
@@ -267,162 +458,171 @@ def main():
 
     dev = torch.device("cuda", 0)
     pi = np.pi
-    print(f"[bench] building inputs (L-shape level {a.level})", file=sys.stderr, flush=True)
-    m = G.lshape(a.level)
-    base = G.lshape(0)
-    aT = G.per_triangle_coefficient(m.nE, 0)
-    xy_d = torch.tensor(m.coords, device=dev)
-    el_d = torch.tensor(m.elements, device=dev)
-    D_d = torch.tensor(m.dirichlet, device=dev)
-    N_d = torch.tensor(m.neumann, device=dev)
-    bxy_d = torch.tensor(base.coords, device=dev)
-    bel_d = torch.tensor(base.elements, device=dev)
-    bD_d = torch.tensor(base.dirichlet, device=dev)
-    bN_d = torch.tensor(base.neumann, device=dev)
-    aT_d = torch.tensor(aT, device=dev)
     pc = phfem.PHF_PRECOND_MULTIGRID if a.precond == "multigrid" else phfem.PHF_PRECOND_JACOBI
     ctx = phfem.Context(0)
-    co = phfem.make_coeffs(a_T=aT_d)
+    h = ctx.handle
+
+    def dev_mesh(m):
+        return tuple(torch.tensor(x, device=dev) for x in
+                     (m.coords, m.elements, m.dirichlet, m.neumann))
+
+    # data of the elliptic workloads: f = 2 pi^2 sin(pi x) cos(pi y), g = 1, u_D = 1
     data = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * pi * pi, 0),
                            phfem.make_fn(phfem.PHF_FN_CONST, 1.0),
                            phfem.make_fn(phfem.PHF_FN_CONST, 1.0))
-    h = ctx.handle
-    out = {}
+    paper_base = dev_mesh(G.paper_square(0, bc="x_sides"))
+    lshape_base = dev_mesh(G.lshape(0))
 
     if a.mode == "assembly":
-        mh = phfem.phf_mesh_create(h, xy_d, el_d, D_d, N_d, phfem.PHF_DEVICE)
-        info = phfem.phf_mesh_get_info(mh)
+        base, lev = ((paper_base, a.level) if a.workload == "paper"
+                     else (lshape_base, a.lshape_level))
+        chain = build_chain(phfem, h, base, lev)
+        info = phfem.phf_mesh_get_info(chain[-1])
+        aT_d = torch.tensor(G.per_triangle_coefficient(info.nE, 0), device=dev)
+        co = phfem.make_coeffs(a_T=aT_d)
         sysd, t = phfem.alloc_system_for(info, dev)
         for _ in range(a.asm_reps):
-            phfem.phf_assemble(mh, co, data, sysd)
-        src = torch.ones((a.copy_mib or 512) << 17, dtype=torch.float64, device=dev)
+            phfem.phf_assemble(chain[-1], co, data, sysd)
+        src = torch.ones(a.copy_mib << 17, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        phfem.phf_mesh_destroy(mh)
-        ab = algorithmic_bytes(info)
-        print(json.dumps({"mode": "assembly", "nE": info.nE, "launches": a.asm_reps,
-                          "algorithmic_bytes_per_launch": ab["k_assemble"],
+        release(phfem, chain)
+        print(json.dumps({"mode": "assembly", "workload": a.workload, "nE": info.nE,
+                          "launches": a.asm_reps,
+                          "algorithmic_bytes_per_launch": algorithmic_bytes(info)["k_assemble"],
                           "copy_bytes_each_way": src.numel() * 8}))
         return
 
-    def one_step(rows):
-        t0 = time.perf_counter()
-        chain = [phfem.phf_mesh_create(h, bxy_d, bel_d, bD_d, bN_d, phfem.PHF_DEVICE)]
-        for _ in range(a.level):
-            chain.append(phfem.phf_mesh_refine(chain[-1]))
-        mh = chain[-1]
-        t1 = time.perf_counter()
-        if "sys" not in out:
-            # sizes for the caller-owned outputs, allocated once (the mesh is
-            # the same every step)
-            info = phfem.phf_mesh_get_info(mh)
-            sysd = phfem.phf_system()
-            t = dict(K=torch.empty(info.nnz_K, dtype=torch.float64, device=dev),
-                     M=torch.empty(info.nnz_K, dtype=torch.float64, device=dev),
-                     C=torch.empty(info.nnz_C, dtype=torch.float64, device=dev),
-                     F=torch.empty(info.N, dtype=torch.float64, device=dev),
-                     bD=torch.empty(info.L, dtype=torch.float64, device=dev),
-                     U=torch.empty(info.N, dtype=torch.float64, device=dev),
-                     Lam=torch.empty(info.L, dtype=torch.float64, device=dev))
-            for k in ("K", "M", "C", "F", "bD"):
-                setattr(sysd, k, t[k].data_ptr())
-            out["sys"], out["t"], out["info"] = sysd, t, info
-            out["level_nf"] = [phfem.phf_mesh_get_info(c).n_free for c in chain]
-            out["level_nE"] = [phfem.phf_mesh_get_info(c).nE for c in chain]
-        sysd, t = out["sys"], out["t"]
-        phfem.phf_assemble(mh, co, data, sysd)
-        t2 = time.perf_counter()
-        st = phfem.phf_solve(mh, co, sysd, t["U"], t["Lam"], rtol=a.rtol, max_iter=200000,
-                             check_every=32 if pc == phfem.PHF_PRECOND_JACOBI else 0,
-                             precond=pc)
-        t3 = time.perf_counter()
-        for c in reversed(chain):
-            phfem.phf_mesh_destroy(c)
-        t4 = time.perf_counter()
-        rows.append(dict(mesh_ms=1e3 * (t1 - t0), assemble_ms=1e3 * (t2 - t1),
-                         solve_ms=1e3 * (t3 - t2), release_ms=1e3 * (t4 - t3),
-                         iterations=st.iterations, rel_residual=st.rel_residual))
-
-    print(f"[bench] warmup {a.warmup} step(s), nE={m.nE}", file=sys.stderr, flush=True)
-    warm = []
-    for _ in range(a.warmup):
-        one_step(warm)
-        print(f"[bench] warmup step {warm[-1]}", file=sys.stderr, flush=True)
-    # one untimed step with every launch traced: per-kernel breakdown and the
-    # dominant kernel
-    phfem.phf_trace_enable(h, True)
-    phfem.phf_trace_reset(h)
-    prof = []
-    one_step(prof)
-    kern = phfem.phf_trace_dump(h)
-    info = out["info"]
+    # ---- headline: numeric assembly of the 4,194,304-triangle mesh ----------
+    print(f"[bench] building the paper mesh, {a.level} device refinements", file=sys.stderr,
+          flush=True)
+    chain = build_chain(phfem, h, paper_base, a.level)
+    mh = chain[-1]
+    info = phfem.phf_mesh_get_info(mh)
     nE = info.nE
-    ab = algorithmic_bytes(info, level_nf=out["level_nf"], level_nE=out["level_nE"],
-                           jacobi=pc == phfem.PHF_PRECOND_JACOBI)
-    dname = max(kern.items(), key=lambda kv: kv[1][1])[0]
-    print(f"[bench] traced step {prof[-1]}; dominant kernel {dname}", file=sys.stderr, flush=True)
-    # timed steps; only the dominant kernel carries events
-    phfem.phf_trace_filter(h, dname)
-    phfem.phf_trace_reset(h)
-    rows = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(a.steps):
-        one_step(rows)
-        print(f"[bench] step {s}: {rows[-1]}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    samples = phfem.phf_trace_samples(h, dname)
-    phfem.phf_trace_filter(h, None)
-    phfem.phf_trace_enable(h, False)
-    ms_step = 1e3 * (t1 - t0) / a.steps
-    # The launches queued behind the iteration that converges return at once
-    # on the device (a few microseconds, no bytes moved): they are not part of
-    # the kernel's average.
-    med = sorted(samples)[len(samples) // 2] if samples else 0.0
-    work = [d for d in samples if d >= 0.25 * med]
+    aT_d = torch.tensor(G.per_triangle_coefficient(nE, 0), device=dev)
+    co = phfem.make_coeffs(a_T=aT_d)
+    sysd, sys_t = phfem.alloc_system_for(info, dev)
+    U = torch.empty(info.N, dtype=torch.float64, device=dev)
+    Lam = torch.empty(info.L, dtype=torch.float64, device=dev)
+    print(f"[bench] headline: {a.warmup} warm-up + {a.steps} timed assemblies, nE={nE}",
+          file=sys.stderr, flush=True)
+    ms_call, samples = time_assembly(phfem, torch, h, mh, co, data, sysd, a.steps, a.warmup)
+    cold = time_assembly_cold(phfem, torch, h, mh, co, data, sysd, 20, dev)
+    head = assembly_summary(info, ms_call, samples, f"k_assemble@paper_L{a.level}", cold)
+    print(f"[bench] assembly: {head}", file=sys.stderr, flush=True)
+    topo = {k: np.empty(n, dt) for k, n, dt in (("edge_type", info.n_edges, np.int8),
+                                                ("elem_edges", 3 * nE, np.int32))}
+    phfem.phf_mesh_topology(mh, elem_edges=topo["elem_edges"], edge_type=topo["edge_type"],
+                            memspace=phfem.PHF_HOST)
+    scatter = scatter_histogram(topo, nE)
+    del topo
+    roof = {"bound": "hbm", "kernel": "k_assemble", "achieved": head["GB_per_s"],
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": head["frac_of_hbm_peak"],
+            "traffic": head["traffic"], "avg_launch_us": head["kernel_us"],
+            "launches": head["launches"], "algorithmic_bytes_per_launch": head["algorithmic_bytes"],
+            "bytes_per_elem": head["bytes_per_elem"]}
+    release(phfem, chain)
 
-    roof = None
-    if dname in ab and work:
-        avg_s = sum(work) / len(work) / 1e3
-        ach = ab[dname] / avg_s / 1e9
-        tr = traffic_for(dname)
-        roof = {"bound": "hbm", "kernel": dname, "achieved": round(ach, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": tr, "avg_launch_us": round(avg_s * 1e6, 3), "launches": len(work),
-                "skipped_launches": len(samples) - len(work),
-                "algorithmic_bytes_per_launch": ab[dname]}
+    # ---- the whole elliptic path on the same workload ------------------------
+    out_pipe = None
+    kern = {}
+    if not a.no_pipeline:
+        print("[bench] pipeline: warm-up step", file=sys.stderr, flush=True)
+        pipeline_steps(phfem, torch, h, paper_base, a.level, co, data, sysd, U, Lam, a.rtol, 1,
+                       pc)
+        rows = pipeline_steps(phfem, torch, h, paper_base, a.level, co, data, sysd, U, Lam,
+                              a.rtol, a.pipeline_steps, pc)
+        print(f"[bench] pipeline rows {rows}", file=sys.stderr, flush=True)
+        tight = pipeline_steps(phfem, torch, h, paper_base, a.level, co, data, sysd, U, Lam,
+                               1e-13, 1, pc)
+        print(f"[bench] pipeline rtol 1e-13 {tight}", file=sys.stderr, flush=True)
+        # one fully traced step: every kernel, per-kernel breakdown
+        phfem.phf_trace_enable(h, True)
+        phfem.phf_trace_reset(h)
+        chain = build_chain(phfem, h, paper_base, a.level)
+        level_nf = [phfem.phf_mesh_get_info(c).n_free for c in chain]
+        level_nE = [phfem.phf_mesh_get_info(c).nE for c in chain]
+        phfem.phf_assemble(chain[-1], co, data, sysd)
+        phfem.phf_solve(chain[-1], co, sysd, U, Lam, rtol=a.rtol, precond=pc)
+        release(phfem, chain)
+        kern = phfem.phf_trace_dump(h)
+        phfem.phf_trace_enable(h, False)
+        ab = algorithmic_bytes(info, level_nf=level_nf, level_nE=level_nE,
+                               jacobi=pc == phfem.PHF_PRECOND_JACOBI)
+        dname = max(kern.items(), key=lambda kv: kv[1][1])[0]
+        dom = None
+        if dname in ab:
+            us = kern[dname][1] / kern[dname][0] * 1e3
+            gbs = ab[dname] / (us * 1e-6) / 1e9
+            dom = {"kernel": dname, "avg_launch_us": round(us, 3), "launches": kern[dname][0],
+                   "algorithmic_bytes_per_launch": ab[dname], "GB_per_s": round(gbs, 1),
+                   "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                   "cache_assisted": dname.startswith("k_mg_")}
+        out_pipe = {
+            "workload": (f"paper mesh refined {a.level} times on the device ({nE} triangles); "
+                         f"step = base upload + {a.level} refinements with topology and "
+                         f"patterns + assembly + saddle solve (CG + {a.precond}, rtol {a.rtol})"),
+            **summarise_pipeline(rows, nE),
+            "rtol_1e-13": summarise_pipeline(tight, nE),
+            "kernels_traced_step": {
+                "total_kernel_ms": round(sum(v[1] for v in kern.values()), 3),
+                "launches": int(sum(v[0] for v in kern.values())),
+                "dominant": dom,
+                "top": {k: {"ms": round(v[1], 3), "launches": v[0],
+                            "GB_per_s": (round(ab[k] / (v[1] / v[0] * 1e-3) / 1e9, 1)
+                                         if k in ab else None)}
+                        for k, v in sorted(kern.items(), key=lambda kv: -kv[1][1])[:14]}}}
+    del sysd, sys_t, U, Lam, aT_d
 
-    # numeric assembly alone (the computation the paper times)
-    print("[bench] assembly-only timing", file=sys.stderr, flush=True)
-    mh = phfem.phf_mesh_create(h, xy_d, el_d, D_d, N_d, phfem.PHF_DEVICE)
-    sysd = out["sys"]
-    for _ in range(3):
-        phfem.phf_assemble(mh, co, data, sysd)
-    phfem.phf_synchronize(h)
-    phfem.phf_trace_enable(h, True)
-    phfem.phf_trace_reset(h)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(a.asm_reps):
-        phfem.phf_assemble(mh, co, data, sysd)
-    ev1.record()
+    # ---- L-shaped configuration ----------------------------------------------
+    out_l = None
+    if not a.no_lshape:
+        print(f"[bench] L-shape level {a.lshape_level}", file=sys.stderr, flush=True)
+        chain = build_chain(phfem, h, lshape_base, a.lshape_level)
+        li = phfem.phf_mesh_get_info(chain[-1])
+        laT = torch.tensor(G.per_triangle_coefficient(li.nE, 0), device=dev)
+        lco = phfem.make_coeffs(a_T=laT)
+        lsys, lt = phfem.alloc_system_for(li, dev)
+        lU = torch.empty(li.N, dtype=torch.float64, device=dev)
+        lL = torch.empty(li.L, dtype=torch.float64, device=dev)
+        ms_l, samp_l = time_assembly(phfem, torch, h, chain[-1], lco, data, lsys, 30, 3)
+        cold_l = time_assembly_cold(phfem, torch, h, chain[-1], lco, data, lsys, 20, dev)
+        release(phfem, chain)
+        out_l = {"nE": li.nE,
+                 "assembly": assembly_summary(li, ms_l, samp_l,
+                                              f"k_assemble@lshape_L{a.lshape_level}", cold_l)}
+        if not a.no_pipeline:
+            pipeline_steps(phfem, torch, h, lshape_base, a.lshape_level, lco, data, lsys, lU, lL,
+                           a.rtol, 1, pc)
+            rows = pipeline_steps(phfem, torch, h, lshape_base, a.lshape_level, lco, data, lsys,
+                                  lU, lL, a.rtol, a.pipeline_steps, pc)
+            out_l["pipeline"] = summarise_pipeline(rows, li.nE)
+        print(f"[bench] L-shape {out_l}", file=sys.stderr, flush=True)
+        del lsys, lt, lU, lL, laT
+
+    # ---- plain copy probe -------------------------------------------------------
+    src = torch.ones(a.copy_mib << 17, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
     torch.cuda.synchronize()
-    cnt, tot = phfem.phf_trace_query(h, "k_assemble")
-    phfem.phf_trace_enable(h, False)
-    asm_us = tot / cnt * 1e3
-    wall_us = ev0.elapsed_time(ev1) / a.asm_reps * 1e3
-    asm_gbs = ab["k_assemble"] / (asm_us * 1e-6) / 1e9
-    out_asm = {"Melem_per_s": round(nE / asm_us, 1), "kernel_us": round(asm_us, 2),
-               "stream_us_per_call": round(wall_us, 2),
-               "algorithmic_bytes": ab["k_assemble"],
-               "bytes_per_elem": round(ab["k_assemble"] / nE, 1),
-               "GB_per_s": round(asm_gbs, 1), "frac_of_hbm_peak": round(asm_gbs / HBM_PEAK_GBS, 4),
-               "traffic": traffic_for("k_assemble"), "launches": cnt}
-    phfem.phf_mesh_destroy(mh)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    cms = e0.elapsed_time(e1) / 10
+    nbytes = 2 * src.numel() * 8
+    copy_probe = {"MiB_each_way": a.copy_mib, "ms": round(cms, 4),
+                  "GB_per_s": round(nbytes / (cms * 1e-3) / 1e9, 1),
+                  "frac_of_hbm_peak": round(nbytes / (cms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "kernel_vs_copy": round(head["GB_per_s"] / (nbytes / (cms * 1e-3) / 1e9), 4)}
+    del src, dst
+    print(f"[bench] copy probe {copy_probe}", file=sys.stderr, flush=True)
 
-    # Crank-Nicolson on the parabolic configuration
+    # ---- Crank-Nicolson on the parabolic configuration ------------------------
     out_cn = None
     if not a.no_cn:
         print(f"[bench] Crank-Nicolson (paper mesh level {a.cn_level})", file=sys.stderr,
@@ -477,16 +677,16 @@ def main():
         torch.cuda.synchronize()
         ue = np.exp(-tf) * np.sin(pi * P[..., 0]) * np.sin(pi * P[..., 1])
         err = float(np.abs(Ud.cpu().numpy().reshape(-1, 3) - ue).max())
+        h1, l2 = phfem.phf_error_norms(dmc, Ud, phfem.make_fn(phfem.PHF_FN_SIN_SIN, 1, -1), tf)
         phfem.phf_cn_destroy(cn)
         for c in reversed(cchain):
             phfem.phf_mesh_destroy(c)
         out_cn = dict(workload=f"unit square, paper mesh level {a.cn_level} ({ic.nE} triangles, "
                                f"device-refined), u = exp(-t) sin(pi x) sin(pi y), k = {k}, "
                                f"CG + {a.precond}",
-                      t_final=tf, max_nodal_error=err, **res)
+                      t_final=tf, max_nodal_error=err, h1_error=h1, l2_error=l2, **res)
 
-    # batched assembly (many uneven meshes in one launch) against one
-    # phf_assemble launch per mesh
+    # ---- batched assembly (many uneven meshes in one launch) -----------------
     out_batch = None
     if not a.no_batch:
         print(f"[bench] batched assembly ({a.batch_count} instances)", file=sys.stderr,
@@ -546,13 +746,12 @@ def main():
         print(f"[bench] batch: {out_batch['batched']} vs per mesh {out_batch['one_launch_per_mesh']}",
               file=sys.stderr, flush=True)
 
-    # serving: continuous batching against one request at a time
+    # ---- serving: continuous batching against one request at a time ----------
     out_serve = None
     if not a.no_serve:
         print(f"[bench] serving ({a.serve_requests} requests)", file=sys.stderr, flush=True)
         reqs = serve_requests(G, phfem, a.serve_requests, 2)
-        # warm-up (code objects, pools)
-        w = phfem.phf_server_create(0, slots=2)
+        w = phfem.phf_server_create(0, slots=2)  # warm-up (code objects, pools)
         for r in reqs[:4]:
             phfem.phf_server_wait(w, phfem.phf_server_submit(w, r))
         phfem.phf_server_destroy(w)
@@ -570,58 +769,39 @@ def main():
                       f"batching"),
             runs=runs)
 
-    if a.copy_mib:
-        # a plain copy of known size: the reference for hardware byte counters
-        src = torch.ones(a.copy_mib << 17, dtype=torch.float64, device=dev)
-        torch.empty_like(src).copy_(src)
-        torch.cuda.synchronize()
-        del src
-
     cpu = None
     if not a.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline()
+        cpu = cpu_baseline(a.cpu_level, a.cpu_repeat, 7)
 
-    mean = {k: float(np.mean([r[k] for r in rows])) for k in rows[0]}
     line = {
         "metric": METRIC,
-        "value": round(nE / (ms_step * 1e-3) / 1e6, 3),
+        "value": head["Melem_per_s"],
         "unit": "Melem/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(ms_step, 3),
+        "ms_per_step": round(ms_call, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": (f"elliptic L-shape, {nE} triangles (12 x 4^{a.level}), fp64, "
-                                f"a_T~U[0.5,2] seed 0, mixed BCs; step = base mesh upload + "
-                                f"{a.level} device red refinements with topology and patterns + "
-                                f"assembly + saddle solve (CG + {a.precond}, rtol {a.rtol})"),
-                   "nE": nE, "n_edges": info.n_edges, "L": info.L, "N": info.N},
-        "rows": {"refine_topology_patterns_ms": round(mean["mesh_ms"], 3),
-                 "assembly_ms": round(mean["assemble_ms"], 3),
-                 "solve_ms": round(mean["solve_ms"], 3),
-                 "release_ms": round(mean["release_ms"], 3),
-                 "solve_iterations": int(mean["iterations"]),
-                 "solve_rel_residual": mean["rel_residual"]},
-        "assembly": out_asm,
+        "config": {"workload": (f"numeric assembly (K, M, C, F, b_D into CSR) of the paper's "
+                                f"unit-square mesh red-refined {a.level} times on the device, "
+                                f"{nE} triangles, fp64, a_T~U[0.5,2] seed 0, Dirichlet x=0,1, "
+                                f"Neumann y=0,1; mesh tables built before timing"),
+                   "nE": nE, "n_edges": info.n_edges, "L": info.L, "N": info.N,
+                   "nnz_C": info.nnz_C},
+        "assembly": {**head, "HBM_GB_per_s": head["GB_per_s"]},
+        "roofline": roof,
+        "copy_probe": copy_probe,
+        "scatter": scatter,
+        "pipeline": out_pipe,
+        "lshape": out_l,
         "cn": out_cn,
         "batch": out_batch,
         "serve": out_serve,
-        "roofline": roof,
-        # from the one fully traced (untimed) step
-        "kernels_traced_step": {
-            "total_kernel_ms": round(sum(v[1] for v in kern.values()), 3),
-            "launches": int(sum(v[0] for v in kern.values())),
-            "top": {k: {"ms": round(v[1], 3), "launches": v[0],
-                        "GB_per_s": (round(ab[k] / (v[1] / v[0] * 1e-3) / 1e9, 1)
-                                     if k in ab else None)}
-                    for k, v in sorted(kern.items(), key=lambda kv: -kv[1][1])[:14]},
-            "all": {k: [v[0], round(v[1], 4)]
-                    for k, v in sorted(kern.items(), key=lambda kv: -kv[1][1])}},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
