@@ -396,6 +396,20 @@ int phf_solve(phf_mesh* mesh, const phf_coeffs* coeffs, const phf_system* sys,
  * order (deterministic). h1, l2: host outputs. Synchronises the stream. */
 int phf_error_norms(phf_mesh* mesh, const double* U, const phf_fn* u, double t, double* h1,
                     double* l2);
+/* The same norms for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and reduction order as phf_error_norms, with its block
+ * partial sums in a 16 KiB device array of the library (one per device,
+ * shared by every call on that device and kept until the process ends)
+ * instead of a pool block. Writes norms[0] = H^1 seminorm, norms[1] = L^2
+ * norm into `norms` (device, 2 doubles) on the context's stream and returns
+ * without waiting: no allocation, no host copy, no memset, no event. The
+ * partial sums of any mesh fit (at most 1024 blocks stride over the
+ * elements); a larger count would give PHF_EINVAL. Calls that overlap on one
+ * device (other streams or host threads) race on the shared array: order
+ * them. The first call on a device resolves the array's address there. */
+int phf_error_norms_noalloc(phf_mesh* mesh, const double* U, const phf_fn* u, double t,
+                            double* norms);
 
 /* ---- Crank-Nicolson (Section 4) -----------------------------------------
  * M+ W^n = M- W^{n-1} + [k F^{n-1/2}; b_D^{n-1/2}] with

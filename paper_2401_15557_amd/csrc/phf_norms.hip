@@ -1,6 +1,7 @@
 // Broken H^1 seminorm and L^2 norm of u - U_h on the device (the error
 // columns of Section 3.7's tables), for a discontinuous piecewise-linear U_h.
 #include <cmath>
+#include <mutex>
 
 #include "phf_device.h"
 
@@ -95,6 +96,9 @@ __global__ __launch_bounds__(NT) void k_err(int32_t nE, const double2* __restric
     }
 }
 
+// Sums the block partials in a fixed order; ROOT: writes the square roots
+// (the norms) instead of the squared norms.
+template <bool ROOT>
 __global__ __launch_bounds__(NT) void k_err_final(const double* __restrict__ part, int32_t nb,
                                                   double* __restrict__ out)
 {
@@ -107,9 +111,20 @@ __global__ __launch_bounds__(NT) void k_err_final(const double* __restrict__ par
     a = phf_block_sum_f64<NT>(a, sh);
     b = phf_block_sum_f64<NT>(b, sh);
     if (threadIdx.x == 0) {
-        out[0] = a;
-        out[1] = b;
+        out[0] = ROOT ? sqrt(a) : a;
+        out[1] = ROOT ? sqrt(b) : b;
     }
+}
+
+bool norm_kind_ok(int k)
+{
+    return k == PHF_FN_ZERO || k == PHF_FN_CONST || k == PHF_FN_SIN_COS || k == PHF_FN_SIN_SIN ||
+           k == PHF_FN_PAPER_U;
+}
+
+int32_t norm_blocks(int32_t nE)
+{
+    return (int32_t)std::min<int64_t>(std::max<int64_t>((nE + NT - 1) / NT, 1), MAXB);
 }
 
 #define TRY(x)               \
@@ -125,21 +140,18 @@ extern "C" int phf_error_norms(phf_mesh* mesh, const double* U, const phf_fn* u,
 {
     if (!mesh || !U || !u || !h1 || !l2) return PHF_EINVAL;
     phf_ctx* ctx = mesh->ctx;
-    const int k = u->kind;
-    if (k != PHF_FN_ZERO && k != PHF_FN_CONST && k != PHF_FN_SIN_COS && k != PHF_FN_SIN_SIN &&
-        k != PHF_FN_PAPER_U)
+    if (!norm_kind_ok(u->kind))
         return phf_set_error(ctx, PHF_EINVAL,
-                             "phf_error_norms: kind %d has no device gradient", k);
+                             "phf_error_norms: kind %d has no device gradient", u->kind);
     static const quad_rule rule = make_rule();
-    const int32_t nb = (int32_t)std::min<int64_t>(std::max<int64_t>((mesh->nE + NT - 1) / NT, 1),
-                                                  MAXB);
+    const int32_t nb = norm_blocks(mesh->nE);
     double* part = nullptr;
     TRY(phf_dmalloc(ctx, &part, 2 * MAXB + 2, "norm partials"));
     int rc = PHF_OK;
     auto body = [&]() -> int {
         PHF_LAUNCH(ctx, "k_err", k_err, nb, NT, 0, mesh->nE, mesh->exy, U, phf_fn_to_dev(*u), t,
                    rule, part);
-        PHF_LAUNCH(ctx, "k_err_final", k_err_final, 1, NT, 0, part, nb, part + 2 * MAXB);
+        PHF_LAUNCH(ctx, "k_err_final", k_err_final<false>, 1, NT, 0, part, nb, part + 2 * MAXB);
         double h[2];
         PHF_HIP(ctx, hipMemcpyAsync(h, part + 2 * MAXB, sizeof(h), hipMemcpyDeviceToHost,
                                     ctx->stream));
@@ -151,4 +163,69 @@ extern "C" int phf_error_norms(phf_mesh* mesh, const double* U, const phf_fn* u,
     rc = body();
     phf_dfree(part);
     return rc;
+}
+
+// ---- the variant that allocates nothing ----------------------------------
+// The block partials of k_err (MAXB for each norm) live in this file-scope
+// device array instead of a pool block: 16 KiB, one copy per device, held
+// until the process ends. Every call on a device writes all the partials it
+// reads, so nothing needs clearing; calls that overlap on one device (two
+// streams, or two host threads) race on it.
+static __device__ __align__(256) double scratch[2 * MAXB];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[MAX_DEVICES];  // device address of `scratch`, per device, once resolved
+
+// Address of the scratch array on `device` (current), resolved on the first
+// call for that device. In host code the array's name is only a stand-in
+// for its symbol; kernels are given this address.
+int scratch_address(phf_ctx* ctx, double** out)
+{
+    const int dev = ctx->device;
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return phf_set_error(ctx, PHF_EINVAL, "phf_error_norms_noalloc: device %d >= %d", dev,
+                             MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return phf_set_error(ctx, PHF_EHIP,
+                                 "phf_error_norms_noalloc: hipGetSymbolAddress failed: %s",
+                                 hipGetErrorString(e));
+        g_scratch[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch[dev];
+    return PHF_OK;
+}
+}  // namespace
+
+extern "C" int phf_error_norms_noalloc(phf_mesh* mesh, const double* U, const phf_fn* u, double t,
+                                       double* norms)
+{
+    if (!mesh || !U || !u || !norms) return PHF_EINVAL;
+    phf_ctx* ctx = mesh->ctx;
+    if (!norm_kind_ok(u->kind))
+        return phf_set_error(ctx, PHF_EINVAL,
+                             "phf_error_norms_noalloc: kind %d has no device gradient", u->kind);
+    static const quad_rule rule = make_rule();
+    const int32_t nb = norm_blocks(mesh->nE);
+    if (2 * (int64_t)nb > (int64_t)(sizeof(scratch) / sizeof(double)))
+        return phf_set_error(ctx, PHF_EINVAL,
+                             "phf_error_norms_noalloc: %d partial pairs exceed the %d the scratch "
+                             "array holds", nb, MAXB);
+    PHF_HIP(ctx, hipSetDevice(ctx->device));
+    double* part = nullptr;
+    TRY(scratch_address(ctx, &part));
+    // plain launches: no trace events, nothing allocated, nothing waited for
+    hipLaunchKernelGGL(k_err, dim3(nb), dim3(NT), 0, ctx->stream, mesh->nE, mesh->exy, U,
+                       phf_fn_to_dev(*u), t, rule, part);
+    hipLaunchKernelGGL(k_err_final<true>, dim3(1), dim3(NT), 0, ctx->stream, part, nb, norms);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return phf_set_error(ctx, PHF_EHIP, "phf_error_norms_noalloc: launch failed: %s",
+                             hipGetErrorString(e));
+    return PHF_OK;
 }

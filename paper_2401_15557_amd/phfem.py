@@ -34,14 +34,16 @@ PHF_MG_SMOOTH_DEFAULT, PHF_MG_SMOOTH_JACOBI, PHF_MG_SMOOTH_CHEBYSHEV = 0, 1, 2
 
 EXPORTED = (
     "phf_create", "phf_destroy", "phf_set_stream", "phf_synchronize", "phf_mem_stats",
-    "phf_release_cache", "phf_status_str",
-    "phf_last_error", "phf_version", "phf_trace_enable", "phf_trace_filter", "phf_trace_reset", "phf_trace_query",
-    "phf_trace_dump", "phf_trace_samples", "phf_mesh_create", "phf_mesh_destroy", "phf_mesh_refine", "phf_mesh_geometry",
-    "phf_mesh_get_info",
-    "phf_mesh_topology", "phf_mesh_pattern", "phf_assemble", "phf_spmv", "phf_solve",
+    "phf_release_cache", "phf_status_str", "phf_last_error", "phf_version",
+    "phf_trace_enable", "phf_trace_filter", "phf_trace_reset", "phf_trace_query",
+    "phf_trace_dump", "phf_trace_samples",
+    "phf_mesh_create", "phf_mesh_destroy", "phf_mesh_refine", "phf_mesh_geometry",
+    "phf_mesh_get_info", "phf_mesh_topology", "phf_mesh_pattern",
+    "phf_assemble", "phf_spmv", "phf_solve",
     "phf_cn_create", "phf_cn_set_state", "phf_cn_run", "phf_cn_get_state", "phf_cn_destroy",
-    "phf_error_norms", "phf_batch_create", "phf_batch_destroy", "phf_batch_assemble",
-    "phf_batch_tune", "phf_batch_get_config", "phf_batch_set_config",
+    "phf_error_norms", "phf_error_norms_noalloc",
+    "phf_batch_create", "phf_batch_destroy", "phf_batch_assemble", "phf_batch_tune",
+    "phf_batch_get_config", "phf_batch_set_config",
     "phf_server_create", "phf_server_destroy", "phf_server_submit", "phf_server_wait",
     "phf_server_query",
 )
@@ -191,6 +193,7 @@ _SIGS = {
     "phf_cn_destroy": [_VP],
     "phf_error_norms": [_VP, _VP, ctypes.POINTER(phf_fn), _D, ctypes.POINTER(_D),
                         ctypes.POINTER(_D)],
+    "phf_error_norms_noalloc": [_VP, _VP, ctypes.POINTER(phf_fn), _D, _VP],
     "phf_batch_create": [_VP, ctypes.POINTER(_VP), _I32, ctypes.POINTER(_VP)],
     "phf_batch_destroy": [_VP],
     "phf_batch_assemble": [_VP, ctypes.POINTER(phf_coeffs), ctypes.POINTER(phf_data),
@@ -483,6 +486,14 @@ def phf_error_norms(mesh, U, u, t=0.0):
     if rc < 0:
         raise PhfError(rc, "phf_error_norms", "")
     return h1.value, l2.value
+
+
+def phf_error_norms_noalloc(mesh, U, u, t, norms):
+    """(H1, L2) of u - U_h into the device array norms (2 doubles), without
+    allocating or waiting."""
+    rc = load().phf_error_norms_noalloc(mesh, _ptr(U), ctypes.byref(u), float(t), _ptr(norms))
+    if rc < 0:
+        raise PhfError(rc, "phf_error_norms_noalloc", "")
 
 
 def _struct_array(typ, items):
