@@ -373,6 +373,19 @@ typedef struct {
     int32_t reserved_;   /* 0                                               */
     double mg_range;     /* Chebyshev: lmax / lower end of the range (> 1);
                             0 = 10                                          */
+    double saddle_rtol;  /* > 0: also require ||F_vec - M_vec W|| / ||F_vec||
+                            <= saddle_rtol for the saddle system itself
+                            (Section 3.5; needs sys->S and Lambda, CG only):
+                            after rtol is met, conjugate gradients continue
+                            from the iterate with the reduced tolerance
+                            tightened by the observed ratio of the two
+                            residuals (at most 6 passes, stopping early when
+                            a pass does not halve the saddle residual; not
+                            met: the result is written and PHF_ENOCONV
+                            returned). Targets below the rounding of the
+                            residual itself, about eps || |M_vec| |W| || /
+                            ||F_vec|| (growing like 1/h), cannot be met.
+                            0: off                                          */
 } phf_solver_opts;
 
 typedef struct {

@@ -35,6 +35,7 @@ struct AsmArgs {
     const double2* xy;
     const double* aT;
     const int32_t* elem_edges;
+    const double* row_hs;
     const int2* row_nodes;
     const int32_t* row_edge;
     const int32_t* C_tile;   // row pointer of every 256th row
@@ -298,36 +299,37 @@ __device__ inline void child_tile(const AsmArgs& a, int32_t tile, double* shK, d
 
 // A row tile: TN consecutive multiplier rows. Their C values are one
 // contiguous run starting at the tile's base pointer; each row's offset in it
-// is an exclusive scan of the row lengths (4 interior, 2 Dirichlet), the
-// Dirichlet rows being flagged by a negative first end node.
+// is an exclusive scan of the row lengths (4 interior, 2 Dirichlet). A row
+// reads its edge's half-length |E|/2 from the mesh's row records (negated on
+// Dirichlet rows); only a Dirichlet row with data reads its end nodes, for
+// the midpoint of u_D.
 template <int TN, bool NT, bool MATS>
 __device__ inline void row_tile(const AsmArgs& a, int32_t tile, int32_t* shs)
 {
     const int32_t r = tile * TN + threadIdx.x;
-    int2 kl = make_int2(0, 0);
+    double hs = 0.0;
     int32_t len = 0;
     if (r < a.L) {
-        kl = a.row_nodes[r];
-        len = kl.x < 0 ? 2 : 4;
+        hs = a.row_hs[r];
+        len = hs < 0.0 ? 2 : 4;
     }
     int32_t tot;
     const int32_t off = phf_block_exscan_i32<TN>(len, shs, &tot);
     if (r >= a.L) return;
-    const bool dirichlet = kl.x < 0;
-    const int32_t c0 = (TN == 256 ? a.C_tile[tile] : a.C_rowptr[tile * TN]) + off;
-    const double2 Pk = a.xy[dirichlet ? ~kl.x : kl.x], Pl = a.xy[kl.y];
-    const double dx = Pl.x - Pk.x, dy = Pl.y - Pk.y;
-    const double len_e = sqrt(dx * dx + dy * dy);
-    const double h = 0.5 * len_e;
+    const bool dirichlet = hs < 0.0;
+    const double h = fabs(hs);
     if (MATS) {
+        const int32_t c0 = (TN == 256 ? a.C_tile[tile] : a.C_rowptr[tile * TN]) + off;
         phf_v2d* C2 = reinterpret_cast<phf_v2d*>(a.C + c0);
         put2<NT>(C2, h, h);
         if (!dirichlet) put2<NT>(C2 + 1, -h, -h);
     }
     double v = 0.0;
     if (dirichlet && a.uD.kind != PHF_FN_ZERO) {
-        int32_t eid = a.uD.kind == PHF_FN_EDGE_ARRAY ? a.row_edge[r] : -1;
-        v = -len_e * phf_fn_eval(a.uD, 0.5 * (Pk.x + Pl.x), 0.5 * (Pk.y + Pl.y), a.t, 0, 0, eid);
+        const int2 kl = a.row_nodes[r];
+        const double2 Pk = a.xy[~kl.x], Pl = a.xy[kl.y];
+        const int32_t eid = a.uD.kind == PHF_FN_EDGE_ARRAY ? a.row_edge[r] : -1;
+        v = -(2.0 * h) * phf_fn_eval(a.uD, 0.5 * (Pk.x + Pl.x), 0.5 * (Pk.y + Pl.y), a.t, 0, 0, eid);
     }
     put1<NT>(a.bD + r, v);
 }
@@ -400,8 +402,7 @@ struct SaddleArgs {
     const double2* xy;
     const double* aT;
     const int32_t* S_rowptr;
-    const int32_t* C_rowptr;
-    const int2* row_nodes;
+    const double* row_hs;
     double A00, A01, A10, A11, p0, p1, delta;
     double* S;
 };
@@ -428,11 +429,8 @@ __global__ __launch_bounds__(TILE) void k_saddle_values(SaddleArgs a)
         const double aT = a.aT ? a.aT[m] : 1.0;
         const double s = aT / (2.0 * det);
         double len[3];
-        for (int i = 0; i < 3; ++i) {
-            const double2 Pa = P[(i + 1) % 3], Pb = P[(i + 2) % 3];
-            const double dx = Pb.x - Pa.x, dy = Pb.y - Pa.y;
-            len[i] = sqrt(dx * dx + dy * dy);
-        }
+        for (int i = 0; i < 3; ++i)  // as the row records round them: S = -C exactly
+            len[i] = 2.0 * phf_half_length(P[(i + 1) % 3], P[(i + 2) % 3]);
         const int code = a.ecode[m];
         for (int j = 0; j < 3; ++j) {
             int32_t q = a.S_rowptr[3 * (int64_t)m + j];
@@ -458,15 +456,12 @@ __global__ __launch_bounds__(TILE) void k_saddle_values(SaddleArgs a)
     } else {
         const int32_t r = tile * TILE + threadIdx.x;
         if (r >= a.L) return;
-        const int2 kl = a.row_nodes[r];
-        const int32_t c0 = a.C_rowptr[r], c1 = a.C_rowptr[r + 1];
-        const double2 Pk = a.xy[kl.x < 0 ? ~kl.x : kl.x], Pl = a.xy[kl.y];
-        const double dx = Pl.x - Pk.x, dy = Pl.y - Pk.y;
-        const double h = 0.5 * sqrt(dx * dx + dy * dy);
+        const double hs = a.row_hs[r];
+        const double h = fabs(hs);
         const int32_t q = a.S_rowptr[N + r];
         a.S[q] = -h;
         a.S[q + 1] = -h;
-        if (c1 - c0 == 4) {
+        if (hs > 0.0) {  // interior row: the T- half too
             a.S[q + 2] = h;
             a.S[q + 3] = h;
         }
@@ -527,6 +522,7 @@ int make_args(phf_mesh* mesh, const phf_coeffs* co, const phf_data* data, const 
     a.xy = mesh->xy;
     a.aT = co->a_T;
     a.elem_edges = mesh->elem_edges;
+    a.row_hs = mesh->row_hs;
     a.row_nodes = mesh->row_nodes;
     a.row_edge = mesh->row_edge;
     a.C_tile = mesh->C_tile;
@@ -601,8 +597,7 @@ int phf_assemble_impl(phf_mesh* mesh, const phf_coeffs* co, const phf_data* data
         s.xy = mesh->xy;
         s.aT = co->a_T;
         s.S_rowptr = mesh->S_rowptr;
-        s.C_rowptr = mesh->C_rowptr;
-        s.row_nodes = mesh->row_nodes;
+        s.row_hs = mesh->row_hs;
         s.A00 = co->A[0];
         s.A01 = co->A[1];
         s.A10 = co->A[2];

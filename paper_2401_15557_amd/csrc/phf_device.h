@@ -84,6 +84,15 @@ __device__ inline double phf_block_sum_f64(double v, double* sh)
 
 // Problem data (phfem.h PHF_FN_*): value at (x, y, t); flux kinds return the
 // flux vector dotted with (nx, ny); PHF_FN_EDGE_ARRAY reads ev[edge].
+// |E| / 2 of the edge a -> b, rounded the same way in every kernel (the mesh
+// build's row records and the assembly's element-side edge lengths).
+__device__ inline double phf_half_length(const double2 a, const double2 b)
+{
+#pragma clang fp contract(off)
+    const double dx = b.x - a.x, dy = b.y - a.y;
+    return 0.5 * sqrt(dx * dx + dy * dy);
+}
+
 __device__ inline double phf_fn_eval(const phf_fn_dev& f, double x, double y, double t, double nx,
                                      double ny, int32_t edge)
 {

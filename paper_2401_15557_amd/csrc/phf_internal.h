@@ -142,6 +142,7 @@ struct phf_mesh {
     int2* neu_pairs = nullptr;     // nN
     // multiplier rows
     int32_t* row_edge = nullptr;   // L
+    double* row_hs = nullptr;      // L: |E|/2 of the row's edge, negated on Dirichlet rows
     int2* row_nodes = nullptr;     // L: (k, l) of the row's edge; k stored as ~k
                                    // (negative) on Dirichlet rows
     int32_t* C_tile = nullptr;     // L/256 + 1: C row pointer of every 256th row

@@ -268,7 +268,8 @@ __device__ inline void d_rows(int32_t bid,
     const int8_t* __restrict__ led, const int8_t* __restrict__ ledTN,
     int32_t* __restrict__ edge_row, int32_t* __restrict__ red_row,
     int32_t* __restrict__ red_edge, int32_t* __restrict__ row_edge,
-    int2* __restrict__ row_nodes, int32_t* __restrict__ C_rowptr, int32_t* __restrict__ C_col,
+    int2* __restrict__ row_nodes, const double2* __restrict__ xy, double* __restrict__ row_hs,
+    int32_t* __restrict__ C_rowptr, int32_t* __restrict__ C_col,
     int32_t L, int32_t nnzC, int32_t nnz_dof, int32_t* __restrict__ S_rowptr_m,
     int32_t* __restrict__ S_col_m)
 {
@@ -305,6 +306,8 @@ __device__ inline void d_rows(int32_t bid,
     row_edge[r] = e;
     const int2 kl = edge_nodes[e];
     row_nodes[r] = make_int2(t == 1 ? ~kl.x : kl.x, kl.y);
+    const double h = phf_half_length(xy[kl.x], xy[kl.y]);
+    row_hs[r] = t == 1 ? -h : h;
     const int32_t c = 4 * (e - nd - nn) + 2 * nd;
     C_rowptr[r] = c;
     // saddle multiplier row r = C's row r, after the DOF rows' entries
@@ -756,6 +759,7 @@ static void mesh_free(phf_mesh* m)
     phf_dfree(m->neu_pairs);
     phf_dfree(m->row_edge);
     phf_dfree(m->row_nodes);
+    phf_dfree(m->row_hs);
     phf_dfree(m->C_tile);
     phf_dfree(m->neu_mask);
     phf_dfree(m->C_rowptr);
@@ -891,13 +895,15 @@ struct rows_args {
     const int8_t *led, *ledTN;
     int32_t *edge_row, *red_row, *red_edge, *row_edge;
     int2* row_nodes;
+    const double2* xy;
+    double* row_hs;
     int32_t *C_rowptr, *C_col, *S_rowptr_m, *S_col_m;
 };
 __global__ __launch_bounds__(256) void k_rows(rows_args a)
 {
     d_rows(blockIdx.x, a.ne, a.etype, a.tiles, a.edge_nodes, a.edge_elems, a.led, a.ledTN,
-           a.edge_row, a.red_row, a.red_edge, a.row_edge, a.row_nodes, a.C_rowptr, a.C_col, a.L,
-           a.nnzC, a.nnz_dof, a.S_rowptr_m, a.S_col_m);
+           a.edge_row, a.red_row, a.red_edge, a.row_edge, a.row_nodes, a.xy, a.row_hs,
+           a.C_rowptr, a.C_col, a.L, a.nnzC, a.nnz_dof, a.S_rowptr_m, a.S_col_m);
 }
 
 // The saddle DOF rows (blocks [0, ntE)), the C tile bases, the Neumann
@@ -1235,6 +1241,7 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
     TRY(phf_dmalloc(ctx, &M->red_edge, M->n_free, "reduced edges"));
     TRY(phf_dmalloc(ctx, &M->row_edge, L, "row edges"));
     TRY(phf_dmalloc(ctx, &M->row_nodes, L, "row nodes"));
+    TRY(phf_dmalloc(ctx, &M->row_hs, L, "row half-lengths"));
     TRY(phf_dmalloc(ctx, &M->C_rowptr, (size_t)L + 1, "C rowptr"));
     TRY(phf_dmalloc(ctx, &M->C_col, M->nnz_C, "C columns"));
     TRY(phf_dmalloc(ctx, &M->S_rowptr, (size_t)N + L + 1, "saddle rowptr"));
@@ -1256,6 +1263,8 @@ int mesh_build(phf_mesh* M, const double* xy, const int32_t* elem, const int32_t
         a.red_edge = M->red_edge;
         a.row_edge = M->row_edge;
         a.row_nodes = M->row_nodes;
+        a.xy = M->xy;
+        a.row_hs = M->row_hs;
         a.C_rowptr = M->C_rowptr;
         a.C_col = M->C_col;
         a.S_rowptr_m = M->S_rowptr + N;

@@ -94,7 +94,7 @@ class phf_solver_opts(ctypes.Structure):
                 ("saddle_residual", ctypes.c_int32), ("precond", ctypes.c_int32),
                 ("mg_sweeps", ctypes.c_int32), ("mg_omega", ctypes.c_double),
                 ("mg_smoother", ctypes.c_int32), ("reserved_", ctypes.c_int32),
-                ("mg_range", ctypes.c_double)]
+                ("mg_range", ctypes.c_double), ("saddle_rtol", ctypes.c_double)]
 
 
 class phf_solve_stats(ctypes.Structure):
@@ -466,10 +466,11 @@ def phf_spmv(ctx, nrows, rowptr, col, val, alpha, x, beta, y):
 def phf_solve(mesh, coeffs, system, U, Lam=None, rtol=1e-10, max_iter=20000, check_every=0,
               saddle_residual=False, raise_on_noconv=True, precond=PHF_PRECOND_JACOBI,
               mg_sweeps=0, mg_omega=0.0, method=PHF_SOLVER_NULLSPACE_CG,
-              mg_smoother=PHF_MG_SMOOTH_DEFAULT, mg_range=0.0):
+              mg_smoother=PHF_MG_SMOOTH_DEFAULT, mg_range=0.0, saddle_rtol=0.0):
     o = phf_solver_opts(int(method), int(max_iter), float(rtol), int(check_every),
                         1 if saddle_residual else 0, int(precond), int(mg_sweeps),
-                        float(mg_omega), int(mg_smoother), 0, float(mg_range))
+                        float(mg_omega), int(mg_smoother), 0, float(mg_range),
+                        float(saddle_rtol))
     st = phf_solve_stats()
     rc = load().phf_solve(mesh, ctypes.byref(coeffs), ctypes.byref(system), ctypes.byref(o),
                           _ptr(U), _ptr(Lam), ctypes.byref(st))

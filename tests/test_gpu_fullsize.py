@@ -1,36 +1,34 @@
-"""Parity at the benchmark's full size and in its launch configuration: the
-12-triangle L-shape refined 9 times on the device (3,145,728 triangles), the
-per-triangle coefficient and data of the benchmark, assembly, and the
-multigrid-preconditioned solve to rtol 1e-10. The oracle computes the same
-refined mesh's tables and the whole assembled system on the host (about 25 s
-of CPU); integers must match bit for bit, values within the scaled 1e-12
-tolerance, and the solution must satisfy the oracle's own saddle system."""
+"""Parity at the benchmark's full sizes and in its launch configuration.
+
+* The paper's largest run: its unit-square start mesh refined 10 times on the
+  device (4,194,304 triangles), per-triangle coefficient a_T (seed 0), the
+  headline data, assembly.
+* The L-shaped configuration: 12 triangles refined 9 times (3,145,728
+  triangles), assembly, and the multigrid-preconditioned solve.
+
+The oracle computes the same refined mesh's tables and the whole assembled
+system on the host (about 20-30 s of CPU each); integers must match bit for
+bit, values within the scaled 1e-12 tolerance, and the solution must satisfy
+the oracle's own saddle system."""
 import numpy as np
 import pytest
 
 from paper_2401_15557_amd import meshgen as G
-from parity_util import (NAN, assert_close_scaled, block_scale, compare_topology, nan_vec,
-                         row_scale_fast)
+from parity_util import (NAN, assert_close_scaled, assert_written, block_scale, compare_topology,
+                         nan_vec, row_scale_fast)
 
 pytestmark = pytest.mark.gpu
 PI = np.pi
 
 
-def test_lshape_level9_pipeline(oracle):
-    import torch
-    from paper_2401_15557_amd import phfem
-    assert torch.cuda.is_available()
-    dev = torch.device("cuda", 0)
-    ctx = phfem.Context(0)
-    base = G.lshape(0)
+def _chain(phfem, ctx, base, levels):
     chain = [phfem.Mesh(ctx, base)]
-    for _ in range(9):
+    for _ in range(levels):
         chain.append(chain[-1].refine())
-    dm = chain[-1]
-    m = G.lshape(9)
-    print(f"device mesh nE={dm.info.nE}", flush=True)
-    assert dm.info.nE == m.nE == 3145728
-    # the refined mesh itself (coordinates, elements, boundary lists)
+    return chain
+
+
+def _check_mesh(dm, m, oracle):
     xy, el, d, n = dm.geometry()
     np.testing.assert_array_equal(xy, m.coords)
     np.testing.assert_array_equal(el, m.elements)
@@ -38,17 +36,11 @@ def test_lshape_level9_pipeline(oracle):
     np.testing.assert_array_equal(n, m.neumann)
     tables = oracle.mesh_tables(m)
     compare_topology(dm.topology(), tables)
-    print("topology bit-exact", flush=True)
+    print("refined mesh and topology bit-exact", flush=True)
+    return tables
 
-    aT = G.per_triangle_coefficient(m.nE, 0)
-    co = phfem.make_coeffs(a_T=torch.tensor(aT, device=dev))
-    data = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * PI * PI, 0),
-                           phfem.make_fn(phfem.PHF_FN_CONST, 1.0),
-                           phfem.make_fn(phfem.PHF_FN_CONST, 1.0))
-    s, t = phfem.alloc_system(dm, fill=NAN)
-    phfem.phf_assemble(dm.handle, co, data, s)
-    asm = oracle.assemble(m, tables, aT=aT, f=oracle.fn(oracle.FN_SIN_COS, 2 * PI * PI, 0),
-                          g=oracle.fn(oracle.FN_CONST, 1.0), uD=oracle.fn(oracle.FN_CONST, 1.0))
+
+def _check_assembly(t, asm):
     for key in ("K", "M"):
         o = asm[key]
         assert_close_scaled(t[key].cpu().numpy(), o, block_scale(o, 9), key)
@@ -60,31 +52,105 @@ def test_lshape_level9_pipeline(oracle):
         assert_close_scaled(t[key].cpu().numpy()[:len(o)], o, np.full(len(o), np.abs(o).max()), key)
     print("assembly within 1e-12 (scaled)", flush=True)
 
+
+def _data(phfem, oracle):
+    return (phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * PI * PI, 0),
+                            phfem.make_fn(phfem.PHF_FN_CONST, 1.0),
+                            phfem.make_fn(phfem.PHF_FN_CONST, 1.0)),
+            dict(f=oracle.fn(oracle.FN_SIN_COS, 2 * PI * PI, 0), g=oracle.fn(oracle.FN_CONST, 1.0),
+                 uD=oracle.fn(oracle.FN_CONST, 1.0)))
+
+
+def test_paper_level10_assembly(oracle):
+    import torch
+    from paper_2401_15557_amd import phfem
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda", 0)
+    ctx = phfem.Context(0)
+    chain = _chain(phfem, ctx, G.paper_square(0, bc="x_sides"), 10)
+    dm = chain[-1]
+    m = G.paper_square(10, bc="x_sides")
+    print(f"device mesh nE={dm.info.nE}", flush=True)
+    assert dm.info.nE == m.nE == 4194304
+    tables = _check_mesh(dm, m, oracle)
+    aT = G.per_triangle_coefficient(m.nE, 0)
+    co = phfem.make_coeffs(a_T=torch.tensor(aT, device=dev))
+    data, odata = _data(phfem, oracle)
+    s, t = phfem.alloc_system(dm, fill=NAN)
+    phfem.phf_assemble(dm.handle, co, data, s)
+    torch.cuda.synchronize()
+    assert_written(t, dm.info)
+    _check_assembly(t, oracle.assemble(m, tables, aT=aT, **odata))
+    for c in reversed(chain):
+        c.close()
+    ctx.close()
+
+
+def test_lshape_level9_pipeline(oracle):
+    import torch
+    from paper_2401_15557_amd import phfem
+    assert torch.cuda.is_available()
+    dev = torch.device("cuda", 0)
+    ctx = phfem.Context(0)
+    chain = _chain(phfem, ctx, G.lshape(0), 9)
+    dm = chain[-1]
+    m = G.lshape(9)
+    print(f"device mesh nE={dm.info.nE}", flush=True)
+    assert dm.info.nE == m.nE == 3145728
+    tables = _check_mesh(dm, m, oracle)
+    aT = G.per_triangle_coefficient(m.nE, 0)
+    co = phfem.make_coeffs(a_T=torch.tensor(aT, device=dev))
+    data, odata = _data(phfem, oracle)
+    s, t = phfem.alloc_system(dm, with_S=True, fill=NAN)
+    phfem.phf_assemble(dm.handle, co, data, s)
+    torch.cuda.synchronize()
+    assert_written(t, dm.info)
+    asm = oracle.assemble(m, tables, aT=aT, **odata)
+    _check_assembly(t, asm)
+    rp, col, val = oracle.saddle(asm)
+    assert_close_scaled(t["S"].cpu().numpy(), val, row_scale_fast(val, rp), "S")
+    Fv = np.concatenate([asm["F"], asm["bD"]])
+
     U = nan_vec(dm.info.N, dev)
     Lam = nan_vec(dm.info.L, dev)
-    rp, col, val = oracle.saddle(asm)
-    Fv = np.concatenate([asm["F"], asm["bD"]])
 
     def saddle_residual():
         W = np.concatenate([U.cpu().numpy(), Lam.cpu().numpy()])
         r = oracle.csr_matvec(rp, col, val, W) - Fv
         return np.linalg.norm(r) / np.linalg.norm(Fv)
 
-    # The conjugate-gradient test is on the reduced residual; in the saddle
-    # system it appears on the T- side of the first block row, measured
-    # against ||F_vec||. Here ||F_vec|| is small (loads scale with |T|, b_D
-    # with |E|) while the reduced right-hand side carries a_T u_D on the rows
-    # next to the Dirichlet boundary, about 300 times larger: a reduced rtol
-    # gives a saddle residual of a few hundred rtol.
-    for rtol, bound in ((1e-10, 1e-7), (1e-13, 1e-10)):
-        st = phfem.phf_solve(dm.handle, co, s, U, Lam, rtol=rtol,
-                             precond=phfem.PHF_PRECOND_MULTIGRID)
-        rel = saddle_residual()
-        print(f"rtol {rtol:.0e}: {st.iterations} iterations, reduced residual "
-              f"{st.rel_residual:.2e}, saddle residual in the oracle's system {rel:.2e}",
-              flush=True)
-        assert st.converged and st.iterations <= 40
-        assert rel < bound
+    # The benchmark's configuration: conjugate gradients to a reduced
+    # relative residual of 1e-10. The reduced residual appears in the first
+    # block row of the saddle system scaled by ||b_red|| / ||F_vec||, which is
+    # about 300 here (loads scale with |T|, while the reduced right-hand side
+    # carries a_T u_D on the rows next to the Dirichlet edges): the saddle
+    # residual is a few hundred times rtol.
+    st = phfem.phf_solve(dm.handle, co, s, U, Lam, rtol=1e-10, saddle_residual=True,
+                         precond=phfem.PHF_PRECOND_MULTIGRID)
+    rel = saddle_residual()
+    print(f"rtol 1e-10: {st.iterations} iterations, reduced residual {st.rel_residual:.2e}, "
+          f"saddle residual {st.saddle_rel_residual:.2e} (device), {rel:.2e} (oracle)", flush=True)
+    assert st.converged and st.iterations <= 40 and rel < 1e-7
+    assert abs(rel - st.saddle_rel_residual) <= 1e-3 * rel
+    # With a saddle-residual target the solve continues until the saddle
+    # system itself (Section 3.5) meets it. The target must lie above the
+    # rounding of the residual's own evaluation, eps || |M_vec| |W| || /
+    # ||F_vec||, computed here by the oracle. It grows about threefold per
+    # level; on the levels a sparse LU reaches, the LU solution's own saddle
+    # residual is 0.4 of it (levels 4-6 of this mesh: 4.5e-14, 1.3e-13,
+    # 4.0e-13 against 1.2e-13, 3.7e-13, 1.1e-12), and solves iterated far
+    # past convergence level off near it (about 2e-11 at this size).
+    st = phfem.phf_solve(dm.handle, co, s, U, Lam, rtol=1e-10, saddle_rtol=1e-10,
+                         precond=phfem.PHF_PRECOND_MULTIGRID)
+    rel = saddle_residual()
+    W = np.abs(np.concatenate([U.cpu().numpy(), Lam.cpu().numpy()]))
+    floor = np.finfo(float).eps * np.linalg.norm(
+        oracle.csr_matvec(rp, col, np.abs(val), W)) / np.linalg.norm(Fv)
+    print(f"saddle target 1e-10: {st.iterations} iterations, reduced residual "
+          f"{st.rel_residual:.2e}, saddle residual {st.saddle_rel_residual:.2e} (device), "
+          f"{rel:.2e} (oracle); rounding floor {floor:.2e}", flush=True)
+    assert st.converged and st.saddle_rel_residual <= 1e-10 and rel <= 1e-10
+    assert floor < 1e-10
     for c in reversed(chain):
         c.close()
     ctx.close()
