@@ -462,6 +462,29 @@ int phf_cn_run(phf_cn* cn, const phf_data* data, int32_t nsteps, int32_t use_gra
 int phf_cn_get_state(phf_cn* cn, double* U, double* Lambda, double* t);
 int phf_cn_destroy(phf_cn* cn);
 
+/* ---- batched Crank-Nicolson (Section 4.1, many problems at once) ---------
+ * A batch of n steppers of one context (distinct; meshes of any sizes)
+ * advanced together: each step of all of them is two HIP graph launches.
+ * The first graph holds every stepper's head (loads, right-hand side, CG
+ * start, first iteration) and CG iterations up to its budget (the smallest
+ * odd count >= its last step's count), one independent branch per stepper,
+ * and gathers the convergence flags; after one read-back, a stepper that has
+ * not converged gets further pairs of iterations (tested after each), and
+ * the second graph runs every stepper's tail. A stepper whose step needed
+ * more than its budget gets a larger one from the next step on (the graphs
+ * are rebuilt). Iterations past convergence return at once on the device,
+ * so each stepper's state after phf_cn_batch_run equals, bit for bit, the
+ * state phf_cn_run would give it. Each stepper must have a state
+ * (phf_cn_set_state); data: n entries (as for phf_cn_run, per stepper);
+ * stats: n entries or NULL. A stepper in a batch cannot be destroyed
+ * (PHF_ESTATE) until the batch is. PHF_ENOCONV if a stepper had a step that
+ * did not reach rtol within its max_iter. */
+typedef struct phf_cn_batch phf_cn_batch;
+int phf_cn_batch_create(phf_cn* const* steppers, int32_t n, phf_cn_batch** out);
+int phf_cn_batch_run(phf_cn_batch* batch, const phf_data* data, int32_t nsteps,
+                     phf_solve_stats* stats);
+int phf_cn_batch_destroy(phf_cn_batch* batch);
+
 /* ---- serving ---------------------------------------------------------------
  * A request server on one device: continuous batching of elliptic solves
  * (Section 3) and Crank-Nicolson runs (Section 4) from independent callers.

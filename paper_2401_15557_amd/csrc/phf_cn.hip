@@ -40,6 +40,7 @@ struct phf_cn {
     hipGraph_t g[NG] = {};
     phf_data gdata{};           // data the graphs were captured with
     bool counted = false;       // registered with the mesh and context
+    int32_t n_batches = 0;      // batches (phf_cn_batch) this stepper is part of
 };
 
 namespace {
@@ -274,6 +275,9 @@ int cn_capture(phf_cn* cn, const phf_data* data)
 extern "C" int phf_cn_destroy(phf_cn* cn)
 {
     if (!cn) return PHF_EINVAL;
+    if (cn->n_batches > 0)
+        return phf_set_error(cn->mesh->ctx, PHF_ESTATE,
+                             "phf_cn_destroy: the stepper is part of %d batches", cn->n_batches);
     (void)hipStreamSynchronize(cn->mesh->ctx->stream);
     if (cn->counted) {
         cn->mesh->n_users--;
@@ -476,5 +480,255 @@ extern "C" int phf_cn_run(phf_cn* cn, const phf_data* data, int32_t nsteps, int3
     if (st[2] != 0.0)
         return phf_set_error(ctx, PHF_ENOCONV, "phf_cn_run: %d of %d steps did not reach rtol (worst %.3e)",
                              (int)st[2], nsteps, st[1]);
+    return PHF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched Crank-Nicolson: the steps of many independent steppers of one
+// context as two HIP graphs per step. The main graph holds, for every
+// stepper, its captured head (loads, right-hand side, CG start, first
+// iteration) followed by its iteration chunks up to its iteration budget, as
+// one branch per stepper with no edges between branches, and ends with one
+// kernel that gathers every stepper's convergence flag; the tail graph holds
+// every stepper's tail (recovery, state update). Per step the host launches
+// the main graph, reads the gathered flags once, gives the few steppers that
+// have not converged further pairs of iterations (their own 2-iteration
+// graph, tested after each), and launches the tail graph. Iterations after a
+// stepper's convergence return at once on the device, so every stepper does
+// exactly the work of phf_cn_run and its state is bit-identical to it.
+// ---------------------------------------------------------------------------
+
+struct phf_cn_batch {
+    phf_ctx* ctx = nullptr;
+    std::vector<phf_cn*> cns;
+    std::vector<int32_t> budget;     // iterations per step inside the main graph
+    hipGraph_t gmain = nullptr, gtail = nullptr;
+    hipGraphExec_t xmain = nullptr, xtail = nullptr;
+    const int** d_flagp = nullptr;   // each stepper's convergence flag word
+    int* d_conv = nullptr;           // gathered flags
+    int* h_conv = nullptr;           // pinned copy
+    bool counted = false;
+};
+
+namespace {
+__global__ void k_cnb_gather(int32_t n, const int* const* __restrict__ flagp,
+                             int* __restrict__ conv)
+{
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) conv[i] = *flagp[i];
+}
+
+void cnb_drop(phf_cn_batch* b)
+{
+    if (b->xmain) (void)hipGraphExecDestroy(b->xmain);
+    if (b->xtail) (void)hipGraphExecDestroy(b->xtail);
+    if (b->gmain) (void)hipGraphDestroy(b->gmain);
+    if (b->gtail) (void)hipGraphDestroy(b->gtail);
+    b->xmain = b->xtail = nullptr;
+    b->gmain = b->gtail = nullptr;
+}
+
+// Builds the main and tail graphs from the steppers' captured parts.
+int cnb_build(phf_cn_batch* b)
+{
+    phf_ctx* ctx = b->ctx;
+    cnb_drop(b);
+    const int32_t n = (int32_t)b->cns.size();
+    PHF_HIP(ctx, hipGraphCreate(&b->gmain, 0));
+    PHF_HIP(ctx, hipGraphCreate(&b->gtail, 0));
+    std::vector<hipGraphNode_t> last(n);
+    for (int32_t i = 0; i < n; ++i) {
+        phf_cn* cn = b->cns[i];
+        hipGraphNode_t prev = nullptr;
+        PHF_HIP(ctx, hipGraphAddChildGraphNode(&prev, b->gmain, nullptr, 0, cn->g[0]));
+        int32_t left = b->budget[i] - 1;  // the head runs the first iteration
+        for (int q = phf_cn::NG - 2; q >= 1; --q)
+            while (left >= (1 << q)) {
+                hipGraphNode_t node = nullptr;
+                PHF_HIP(ctx, hipGraphAddChildGraphNode(&node, b->gmain, &prev, 1, cn->g[q]));
+                prev = node;
+                left -= 1 << q;
+            }
+        last[i] = prev;
+        hipGraphNode_t tnode = nullptr;
+        PHF_HIP(ctx, hipGraphAddChildGraphNode(&tnode, b->gtail, nullptr, 0, cn->g[phf_cn::NG - 1]));
+    }
+    hipKernelNodeParams kp{};
+    void* args[] = {(void*)&n, (void*)&b->d_flagp, (void*)&b->d_conv};
+    kp.func = (void*)k_cnb_gather;
+    kp.gridDim = dim3(1);
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t gnode = nullptr;
+    PHF_HIP(ctx, hipGraphAddKernelNode(&gnode, b->gmain, last.data(), (size_t)n, &kp));
+    PHF_HIP(ctx, hipGraphInstantiate(&b->xmain, b->gmain, nullptr, nullptr, 0));
+    PHF_HIP(ctx, hipGraphInstantiate(&b->xtail, b->gtail, nullptr, nullptr, 0));
+    return PHF_OK;
+}
+
+// Iteration budget inside the main graph: the head's one plus an even number,
+// at least the stepper's last step count.
+int32_t cnb_budget(int32_t predicted) { return 1 + ((std::max(predicted, 2) - 1 + 1) & ~1); }
+}  // namespace
+
+extern "C" int phf_cn_batch_destroy(phf_cn_batch* b)
+{
+    if (!b) return PHF_EINVAL;
+    (void)hipStreamSynchronize(b->ctx->stream);
+    cnb_drop(b);
+    if (b->counted) {
+        for (phf_cn* cn : b->cns) cn->n_batches--;
+        b->ctx->n_objects--;
+    }
+    phf_dfree(b->d_flagp);
+    phf_dfree(b->d_conv);
+    if (b->h_conv) (void)hipHostFree(b->h_conv);
+    delete b;
+    return PHF_OK;
+}
+
+extern "C" int phf_cn_batch_create(phf_cn* const* steppers, int32_t n, phf_cn_batch** out)
+{
+    if (!steppers || n < 1 || !out || !steppers[0]) return PHF_EINVAL;
+    *out = nullptr;
+    phf_ctx* ctx = steppers[0]->mesh->ctx;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!steppers[i] || steppers[i]->mesh->ctx != ctx)
+            return phf_set_error(ctx, PHF_EINVAL,
+                                 "phf_cn_batch_create: stepper %d is null or of another context", i);
+        for (int32_t j = 0; j < i; ++j)
+            if (steppers[j] == steppers[i])
+                return phf_set_error(ctx, PHF_EINVAL, "phf_cn_batch_create: stepper %d repeated", i);
+    }
+    phf_cn_batch* b = new (std::nothrow) phf_cn_batch;
+    if (!b) return phf_set_error(ctx, PHF_ENOMEM, "host allocation failed");
+    b->ctx = ctx;
+    b->cns.assign(steppers, steppers + n);
+    b->budget.assign(n, 0);
+    auto body = [&]() -> int {
+        TRY(phf_dmalloc(ctx, &b->d_flagp, (size_t)n, "batch flag pointers"));
+        TRY(phf_dmalloc(ctx, &b->d_conv, (size_t)n, "batch flags"));
+        PHF_HIP(ctx, hipHostMalloc((void**)&b->h_conv, sizeof(int) * n, hipHostMallocDefault));
+        std::vector<const int*> fp(n);
+        for (int32_t i = 0; i < n; ++i) fp[i] = b->cns[i]->ns->iflags;
+        PHF_HIP(ctx, hipMemcpyAsync(b->d_flagp, fp.data(), sizeof(int*) * n,
+                                    hipMemcpyHostToDevice, ctx->stream));
+        PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        return PHF_OK;
+    };
+    int rc = body();
+    if (rc) {
+        phf_cn_batch_destroy(b);
+        return rc;
+    }
+    b->counted = true;
+    for (phf_cn* cn : b->cns) cn->n_batches++;
+    ctx->n_objects++;
+    *out = b;
+    return PHF_OK;
+}
+
+extern "C" int phf_cn_batch_run(phf_cn_batch* b, const phf_data* data, int32_t nsteps,
+                                phf_solve_stats* stats)
+{
+    if (!b || !data || nsteps < 0) return PHF_EINVAL;
+    phf_ctx* ctx = b->ctx;
+    const int32_t n = (int32_t)b->cns.size();
+    bool rebuild = !b->xmain;
+    for (int32_t i = 0; i < n; ++i) {
+        phf_cn* cn = b->cns[i];
+        const phf_data& d = data[i];
+        if (!cn->have_state)
+            return phf_set_error(ctx, PHF_ESTATE, "phf_cn_batch_run: stepper %d has no state", i);
+        if (!phf_fn_valid(d.f) || !phf_fn_valid(d.g) || !phf_fn_valid(d.uD))
+            return phf_set_error(ctx, PHF_EINVAL,
+                                 "phf_cn_batch_run: stepper %d: unknown function kind", i);
+        if (cn->gx[0] && !(same_fn(cn->gdata.f, d.f) && same_fn(cn->gdata.g, d.g) &&
+                           same_fn(cn->gdata.uD, d.uD))) {
+            cn_drop_graph(cn);
+            rebuild = true;
+        }
+        if (!cn->gx[0]) {
+            TRY(cn_capture(cn, &d));
+            rebuild = true;
+        }
+        const int32_t want = cnb_budget(cn->predict);
+        if (want > b->budget[i]) {
+            b->budget[i] = want;
+            rebuild = true;
+        }
+        // loads at the current time, the device step counter, the statistics
+        TRY(cn_loads(cn, &d, cn->F0, cn->bD0, false));
+        int64_t n_host = cn->n;
+        PHF_HIP(ctx, hipMemcpyAsync(cn->d_step, &n_host, sizeof(int64_t), hipMemcpyHostToDevice,
+                                    ctx->stream));
+        PHF_HIP(ctx, hipMemsetAsync(cn->d_stats, 0, 4 * sizeof(double), ctx->stream));
+    }
+    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (rebuild) TRY(cnb_build(b));
+    std::vector<int32_t> need(n, 0);
+    for (int32_t s = 0; s < nsteps; ++s) {
+        phf_trace_rec rec;
+        phf_trace_begin(ctx, "cn_batch_step", &rec);
+        PHF_HIP(ctx, hipGraphLaunch(b->xmain, ctx->stream));
+        PHF_HIP(ctx, hipMemcpyAsync(b->h_conv, b->d_conv, sizeof(int) * n, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        for (int32_t i = 0; i < n; ++i) {
+            if (b->h_conv[i]) continue;
+            // beyond the budget: pairs of iterations until this stepper converges
+            phf_cn* cn = b->cns[i];
+            int32_t it = b->budget[i];
+            int hf[2] = {0, 0};
+            while (it < cn->opts.max_iter) {
+                PHF_HIP(ctx, hipGraphLaunch(cn->gx[1], ctx->stream));
+                it += 2;
+                PHF_HIP(ctx, hipMemcpyAsync(hf, cn->ns->iflags, 2 * sizeof(int),
+                                            hipMemcpyDeviceToHost, ctx->stream));
+                PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+                if (hf[0]) break;
+            }
+            need[i] = std::max(need[i], it);
+        }
+        PHF_HIP(ctx, hipGraphLaunch(b->xtail, ctx->stream));
+        phf_trace_end(ctx, &rec);
+        // a stepper that needed more than its budget gets a larger one from
+        // the next step on
+        bool grow = false;
+        for (int32_t i = 0; i < n; ++i)
+            if (need[i] > b->budget[i]) {
+                b->budget[i] = cnb_budget(need[i]);
+                grow = true;
+            }
+        if (grow && s + 1 < nsteps) {
+            PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            TRY(cnb_build(b));
+        }
+    }
+    // statistics and host step counts
+    int bad = 0;
+    std::vector<double> st(4 * (size_t)n, 0.0);
+    for (int32_t i = 0; i < n; ++i)
+        PHF_HIP(ctx, hipMemcpyAsync(&st[4 * (size_t)i], b->cns[i]->d_stats, 4 * sizeof(double),
+                                    hipMemcpyDeviceToHost, ctx->stream));
+    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int32_t i = 0; i < n; ++i) {
+        phf_cn* cn = b->cns[i];
+        const double* q = &st[4 * (size_t)i];
+        cn->n += nsteps;
+        if (nsteps > 0) cn->predict = std::max<int32_t>((int32_t)(q[0] / nsteps + 0.5), 1);
+        if (stats) {
+            stats[i].iterations = (int32_t)q[0];
+            stats[i].converged = q[2] == 0.0;
+            stats[i].rel_residual = q[1];
+            stats[i].saddle_rel_residual = -1.0;
+        }
+        bad += q[2] != 0.0;
+    }
+    if (bad)
+        return phf_set_error(ctx, PHF_ENOCONV,
+                             "phf_cn_batch_run: %d of %d steppers had steps that did not reach "
+                             "rtol", bad, n);
     return PHF_OK;
 }

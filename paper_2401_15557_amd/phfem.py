@@ -41,6 +41,7 @@ EXPORTED = (
     "phf_mesh_get_info", "phf_mesh_topology", "phf_mesh_pattern",
     "phf_assemble", "phf_spmv", "phf_solve",
     "phf_cn_create", "phf_cn_set_state", "phf_cn_run", "phf_cn_get_state", "phf_cn_destroy",
+    "phf_cn_batch_create", "phf_cn_batch_run", "phf_cn_batch_destroy",
     "phf_error_norms", "phf_error_norms_noalloc",
     "phf_batch_create", "phf_batch_destroy", "phf_batch_assemble", "phf_batch_tune",
     "phf_batch_get_config", "phf_batch_set_config",
@@ -191,6 +192,9 @@ _SIGS = {
     "phf_cn_run": [_VP, ctypes.POINTER(phf_data), _I32, _I32, ctypes.POINTER(phf_solve_stats)],
     "phf_cn_get_state": [_VP, _VP, _VP, ctypes.POINTER(_D)],
     "phf_cn_destroy": [_VP],
+    "phf_cn_batch_create": [ctypes.POINTER(_VP), _I32, ctypes.POINTER(_VP)],
+    "phf_cn_batch_run": [_VP, ctypes.POINTER(phf_data), _I32, ctypes.POINTER(phf_solve_stats)],
+    "phf_cn_batch_destroy": [_VP],
     "phf_error_norms": [_VP, _VP, ctypes.POINTER(phf_fn), _D, ctypes.POINTER(_D),
                         ctypes.POINTER(_D)],
     "phf_error_norms_noalloc": [_VP, _VP, ctypes.POINTER(phf_fn), _D, _VP],
@@ -654,6 +658,29 @@ def phf_cn_get_state(cn, U=None, Lam=None):
 
 def phf_cn_destroy(cn):
     _call("phf_cn_destroy", None, cn)
+
+
+def phf_cn_batch_create(steppers):
+    """A batch of Crank-Nicolson steppers (handles) of one context."""
+    arr = (_VP * len(steppers))(*steppers)
+    out = _VP()
+    _check(load().phf_cn_batch_create(arr, len(steppers), ctypes.byref(out)),
+           "phf_cn_batch_create")
+    return out.value
+
+
+def phf_cn_batch_run(batch, data, nsteps, raise_on_noconv=True):
+    """Advances every stepper of the batch nsteps steps; data: one phf_data
+    per stepper. Returns the per-stepper phf_solve_stats."""
+    st = (phf_solve_stats * len(data))()
+    rc = load().phf_cn_batch_run(batch, _struct_array(phf_data, data), int(nsteps), st)
+    if rc < 0 and (rc != PHF_ENOCONV or raise_on_noconv):
+        raise PhfError(rc, "phf_cn_batch_run", "")
+    return [st[i] for i in range(len(data))]
+
+
+def phf_cn_batch_destroy(batch):
+    _check(load().phf_cn_batch_destroy(batch), "phf_cn_batch_destroy")
 
 
 # ---- conveniences: tensor allocation around the calls above ----------------
