@@ -38,6 +38,8 @@ The JSON line also carries, measured in the same process:
   cn         Crank-Nicolson steps/s (unit square, 1,048,576 triangles,
              k = 1e-3, 200 steps), replaying captured HIP graphs and eagerly;
   batch      256 uneven meshes in one launch vs one launch per mesh;
+  cn_batch   16 uneven Crank-Nicolson problems advanced together (two graph
+             launches per step) vs one stepper at a time;
   serve      mixed elliptic / Crank-Nicolson requests at Poisson rates,
              one slot vs continuous batching, p50/p99 latency;
   cpu_baseline  the CPU oracle, one core, assembly alone on a bounded sample
@@ -444,6 +446,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-reps", type=int, default=20)
+    ap.add_argument("--cn-batch-count", type=int, default=16)
+    ap.add_argument("--cn-batch-steps", type=int, default=50)
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -746,6 +750,78 @@ def main():
         print(f"[bench] batch: {out_batch['batched']} vs per mesh {out_batch['one_launch_per_mesh']}",
               file=sys.stderr, flush=True)
 
+    # ---- batched Crank-Nicolson (many uneven problems per graph launch) ------
+    out_cnb = None
+    if not a.no_batch:
+        print(f"[bench] batched Crank-Nicolson ({a.cn_batch_count} steppers)", file=sys.stderr,
+              flush=True)
+        rng = np.random.default_rng(4)
+        levels = rng.integers(3, 8, size=a.cn_batch_count)
+        chains, steppers, states = [], [], []
+        cdata = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_SIN, 2 * pi * pi - 1, -1),
+                                phfem.make_fn(phfem.PHF_FN_GRAD_SIN_SIN, 1, -1),
+                                phfem.make_fn(phfem.PHF_FN_SIN_SIN, 1, -1))
+        for lev in levels:
+            ch = build_chain(phfem, h, paper_base, int(lev))
+            chains.append(ch)
+            ii = phfem.phf_mesh_get_info(ch[-1])
+            xy = np.empty((ii.nC, 2)); el = np.empty((ii.nE, 3), np.int32)
+            phfem.phf_mesh_geometry(ch[-1], xy, el, None, None, phfem.PHF_HOST)
+            P = xy[el]
+            um = np.sin(pi * (P[:, [1, 2, 0], 0] + P[:, [2, 0, 1], 0]) / 2) * \
+                np.sin(pi * (P[:, [1, 2, 0], 1] + P[:, [2, 0, 1], 1]) / 2)
+            U0 = (um[:, [1, 2, 0]] + um[:, [2, 0, 1]] - um).reshape(-1)
+            states.append((torch.tensor(U0, device=dev),
+                           torch.zeros(ii.L, dtype=torch.float64, device=dev)))
+            steppers.append(phfem.phf_cn_create(ch[-1], phfem.make_coeffs(), 1e-3, rtol=1e-10,
+                                                iters_per_step=8, precond=pc))
+        sizes = [phfem.phf_mesh_get_info(ch[-1]).nE for ch in chains]
+
+        def reset():
+            for cn, (u0, l0) in zip(steppers, states):
+                phfem.phf_cn_set_state(cn, u0, l0, 0.0)
+
+        nst = a.cn_batch_steps
+        # one launch per stepper and step (captured graphs), steppers in turn
+        reset()
+        for cn in steppers:
+            phfem.phf_cn_run(cn, cdata, 2, use_graph=True)
+        reset()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for cn in steppers:
+            phfem.phf_cn_run(cn, cdata, nst, use_graph=True)
+        torch.cuda.synchronize()
+        w1 = time.perf_counter()
+        cb = phfem.phf_cn_batch_create(steppers)
+        reset()
+        phfem.phf_cn_batch_run(cb, [cdata] * len(steppers), 2)
+        reset()
+        torch.cuda.synchronize()
+        w2 = time.perf_counter()
+        bst = phfem.phf_cn_batch_run(cb, [cdata] * len(steppers), nst)
+        torch.cuda.synchronize()
+        w3 = time.perf_counter()
+        phfem.phf_cn_batch_destroy(cb)
+        for cn in steppers:
+            phfem.phf_cn_destroy(cn)
+        for ch in chains:
+            release(phfem, ch)
+        tot = len(steppers) * nst
+        out_cnb = dict(
+            workload=(f"{len(steppers)} Crank-Nicolson problems on the paper mesh refined 3-7 "
+                      f"times (seed 4; {min(sizes)}-{max(sizes)} triangles, {sum(sizes)} in "
+                      f"total), k = 1e-3, {nst} steps each, CG + {a.precond}"),
+            sizes=sizes,
+            batched=dict(s=round(w3 - w2, 4), stepper_steps_per_s=round(tot / (w3 - w2), 1),
+                         steps_per_s=round(nst / (w3 - w2), 1),
+                         cg_iters_per_step=round(sum(x.iterations for x in bst) / tot, 2),
+                         all_converged=all(bool(x.converged) for x in bst)),
+            one_stepper_at_a_time=dict(s=round(w1 - w0, 4),
+                                       stepper_steps_per_s=round(tot / (w1 - w0), 1)),
+            speedup=round((w1 - w0) / (w3 - w2), 2))
+        print(f"[bench] cn batch {out_cnb}", file=sys.stderr, flush=True)
+
     # ---- serving: continuous batching against one request at a time ----------
     out_serve = None
     if not a.no_serve:
@@ -801,6 +877,7 @@ def main():
         "lshape": out_l,
         "cn": out_cn,
         "batch": out_batch,
+        "cn_batch": out_cnb,
         "serve": out_serve,
         "cpu_baseline": cpu,
     }

@@ -464,21 +464,23 @@ int phf_cn_destroy(phf_cn* cn);
 
 /* ---- batched Crank-Nicolson (Section 4.1, many problems at once) ---------
  * A batch of n steppers of one context (distinct; meshes of any sizes)
- * advanced together: each step of all of them is two HIP graph launches.
- * The first graph holds every stepper's head (loads, right-hand side, CG
- * start, first iteration) and CG iterations up to its budget (the smallest
- * odd count >= its last step's count), one independent branch per stepper,
- * and gathers the convergence flags; after one read-back, a stepper that has
- * not converged gets further pairs of iterations (tested after each), and
- * the second graph runs every stepper's tail. A stepper whose step needed
- * more than its budget gets a larger one from the next step on (the graphs
- * are rebuilt). Iterations past convergence return at once on the device,
- * so each stepper's state after phf_cn_batch_run equals, bit for bit, the
- * state phf_cn_run would give it. Each stepper must have a state
- * (phf_cn_set_state); data: n entries (as for phf_cn_run, per stepper);
- * stats: n entries or NULL. A stepper in a batch cannot be destroyed
- * (PHF_ESTATE) until the batch is. PHF_ENOCONV if a stepper had a step that
- * did not reach rtol within its max_iter. */
+ * advanced together. Each step of each stepper is replayed from its captured
+ * HIP graphs (as phf_cn_run with use_graph = 1); the steppers are spread over
+ * min(n, 4) streams the batch creates (default priority), so that the small
+ * launches of different problems overlap. Per step every stepper runs its
+ * head (loads, right-hand side, CG start, first iteration) and CG iterations
+ * up to its budget (the smallest odd count >= its last steps' mean count);
+ * the context's stream joins them and the convergence flags come back in one
+ * read; a stepper that has not converged gets further pairs of iterations
+ * (tested after each, and a larger budget from then on); then every
+ * stepper's tail (recovery, state update) runs, joined again. Iterations
+ * past convergence return at once on the device, so each stepper's state
+ * after phf_cn_batch_run equals, bit for bit, the state phf_cn_run would
+ * give it. Each stepper must have a state (phf_cn_set_state); data: n
+ * entries (as for phf_cn_run, per stepper); stats: n entries or NULL. A
+ * stepper in a batch cannot be destroyed (PHF_ESTATE) until the batch is.
+ * PHF_ENOCONV if a stepper had a step that did not reach rtol within its
+ * max_iter. Returns after the last step has finished. */
 typedef struct phf_cn_batch phf_cn_batch;
 int phf_cn_batch_create(phf_cn* const* steppers, int32_t n, phf_cn_batch** out);
 int phf_cn_batch_run(phf_cn_batch* batch, const phf_data* data, int32_t nsteps,

@@ -485,25 +485,28 @@ extern "C" int phf_cn_run(phf_cn* cn, const phf_data* data, int32_t nsteps, int3
 
 // ---------------------------------------------------------------------------
 // Batched Crank-Nicolson: the steps of many independent steppers of one
-// context as two HIP graphs per step. The main graph holds, for every
-// stepper, its captured head (loads, right-hand side, CG start, first
-// iteration) followed by its iteration chunks up to its iteration budget, as
-// one branch per stepper with no edges between branches, and ends with one
-// kernel that gathers every stepper's convergence flag; the tail graph holds
-// every stepper's tail (recovery, state update). Per step the host launches
-// the main graph, reads the gathered flags once, gives the few steppers that
-// have not converged further pairs of iterations (their own 2-iteration
-// graph, tested after each), and launches the tail graph. Iterations after a
-// stepper's convergence return at once on the device, so every stepper does
-// exactly the work of phf_cn_run and its state is bit-identical to it.
+// context, each step of each stepper replayed from its captured HIP graphs
+// (head with the first CG iteration, iteration chunks, tail), the steppers
+// spread over a few streams of their own so that the small launches of
+// different problems overlap on the device. Per step: every stepper's head
+// and its CG iterations up to its budget go to its stream; the context's
+// stream joins them and one kernel gathers every convergence flag for a
+// single read-back; a stepper that has not converged gets further pairs of
+// iterations (tested after each); then every stepper's tail, joined again.
+// Iterations after a stepper's convergence return at once on the device, so
+// every stepper does exactly the work of phf_cn_run and its state is
+// bit-identical to it. (One graph holding every stepper as a branch was
+// measured too: its nodes ran one after another, no faster than stepping
+// the problems in turn.)
 // ---------------------------------------------------------------------------
 
 struct phf_cn_batch {
     phf_ctx* ctx = nullptr;
     std::vector<phf_cn*> cns;
-    std::vector<int32_t> budget;     // iterations per step inside the main graph
-    hipGraph_t gmain = nullptr, gtail = nullptr;
-    hipGraphExec_t xmain = nullptr, xtail = nullptr;
+    std::vector<int32_t> budget;     // CG iterations per step before the flag read-back
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> done;    // one per stream
+    hipEvent_t fork = nullptr;
     const int** d_flagp = nullptr;   // each stepper's convergence flag word
     int* d_conv = nullptr;           // gathered flags
     int* h_conv = nullptr;           // pinned copy
@@ -511,72 +514,49 @@ struct phf_cn_batch {
 };
 
 namespace {
+constexpr int CNB_STREAMS = 4;
+
 __global__ void k_cnb_gather(int32_t n, const int* const* __restrict__ flagp,
                              int* __restrict__ conv)
 {
     for (int32_t i = threadIdx.x; i < n; i += blockDim.x) conv[i] = *flagp[i];
 }
 
-void cnb_drop(phf_cn_batch* b)
-{
-    if (b->xmain) (void)hipGraphExecDestroy(b->xmain);
-    if (b->xtail) (void)hipGraphExecDestroy(b->xtail);
-    if (b->gmain) (void)hipGraphDestroy(b->gmain);
-    if (b->gtail) (void)hipGraphDestroy(b->gtail);
-    b->xmain = b->xtail = nullptr;
-    b->gmain = b->gtail = nullptr;
-}
+// Iteration budget: the head's one plus an even number of chunk iterations,
+// at least the stepper's last step count.
+int32_t cnb_budget(int32_t predicted) { return 1 + (std::max(predicted, 2) & ~1); }
 
-// Builds the main and tail graphs from the steppers' captured parts.
-int cnb_build(phf_cn_batch* b)
+// Forks the batch streams off the context's stream.
+int cnb_fork(phf_cn_batch* b)
 {
     phf_ctx* ctx = b->ctx;
-    cnb_drop(b);
-    const int32_t n = (int32_t)b->cns.size();
-    PHF_HIP(ctx, hipGraphCreate(&b->gmain, 0));
-    PHF_HIP(ctx, hipGraphCreate(&b->gtail, 0));
-    std::vector<hipGraphNode_t> last(n);
-    for (int32_t i = 0; i < n; ++i) {
-        phf_cn* cn = b->cns[i];
-        hipGraphNode_t prev = nullptr;
-        PHF_HIP(ctx, hipGraphAddChildGraphNode(&prev, b->gmain, nullptr, 0, cn->g[0]));
-        int32_t left = b->budget[i] - 1;  // the head runs the first iteration
-        for (int q = phf_cn::NG - 2; q >= 1; --q)
-            while (left >= (1 << q)) {
-                hipGraphNode_t node = nullptr;
-                PHF_HIP(ctx, hipGraphAddChildGraphNode(&node, b->gmain, &prev, 1, cn->g[q]));
-                prev = node;
-                left -= 1 << q;
-            }
-        last[i] = prev;
-        hipGraphNode_t tnode = nullptr;
-        PHF_HIP(ctx, hipGraphAddChildGraphNode(&tnode, b->gtail, nullptr, 0, cn->g[phf_cn::NG - 1]));
-    }
-    hipKernelNodeParams kp{};
-    void* args[] = {(void*)&n, (void*)&b->d_flagp, (void*)&b->d_conv};
-    kp.func = (void*)k_cnb_gather;
-    kp.gridDim = dim3(1);
-    kp.blockDim = dim3(256);
-    kp.sharedMemBytes = 0;
-    kp.kernelParams = args;
-    kp.extra = nullptr;
-    hipGraphNode_t gnode = nullptr;
-    PHF_HIP(ctx, hipGraphAddKernelNode(&gnode, b->gmain, last.data(), (size_t)n, &kp));
-    PHF_HIP(ctx, hipGraphInstantiate(&b->xmain, b->gmain, nullptr, nullptr, 0));
-    PHF_HIP(ctx, hipGraphInstantiate(&b->xtail, b->gtail, nullptr, nullptr, 0));
+    PHF_HIP(ctx, hipEventRecord(b->fork, ctx->stream));
+    for (hipStream_t st : b->streams) PHF_HIP(ctx, hipStreamWaitEvent(st, b->fork, 0));
     return PHF_OK;
 }
 
-// Iteration budget inside the main graph: the head's one plus an even number,
-// at least the stepper's last step count.
-int32_t cnb_budget(int32_t predicted) { return 1 + ((std::max(predicted, 2) - 1 + 1) & ~1); }
+// Joins the batch streams back into the context's stream.
+int cnb_join(phf_cn_batch* b)
+{
+    phf_ctx* ctx = b->ctx;
+    for (size_t p = 0; p < b->streams.size(); ++p) {
+        PHF_HIP(ctx, hipEventRecord(b->done[p], b->streams[p]));
+        PHF_HIP(ctx, hipStreamWaitEvent(ctx->stream, b->done[p], 0));
+    }
+    return PHF_OK;
+}
 }  // namespace
 
 extern "C" int phf_cn_batch_destroy(phf_cn_batch* b)
 {
     if (!b) return PHF_EINVAL;
     (void)hipStreamSynchronize(b->ctx->stream);
-    cnb_drop(b);
+    for (hipStream_t st : b->streams) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    for (hipEvent_t e : b->done) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->counted) {
         for (phf_cn* cn : b->cns) cn->n_batches--;
         b->ctx->n_objects--;
@@ -607,6 +587,17 @@ extern "C" int phf_cn_batch_create(phf_cn* const* steppers, int32_t n, phf_cn_ba
     b->cns.assign(steppers, steppers + n);
     b->budget.assign(n, 0);
     auto body = [&]() -> int {
+        PHF_HIP(ctx, hipSetDevice(ctx->device));
+        const int ns = std::min(n, CNB_STREAMS);
+        for (int p = 0; p < ns; ++p) {
+            hipStream_t st = nullptr;
+            PHF_HIP(ctx, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            b->streams.push_back(st);
+            hipEvent_t e = nullptr;
+            PHF_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            b->done.push_back(e);
+        }
+        PHF_HIP(ctx, hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
         TRY(phf_dmalloc(ctx, &b->d_flagp, (size_t)n, "batch flag pointers"));
         TRY(phf_dmalloc(ctx, &b->d_conv, (size_t)n, "batch flags"));
         PHF_HIP(ctx, hipHostMalloc((void**)&b->h_conv, sizeof(int) * n, hipHostMallocDefault));
@@ -635,7 +626,7 @@ extern "C" int phf_cn_batch_run(phf_cn_batch* b, const phf_data* data, int32_t n
     if (!b || !data || nsteps < 0) return PHF_EINVAL;
     phf_ctx* ctx = b->ctx;
     const int32_t n = (int32_t)b->cns.size();
-    bool rebuild = !b->xmain;
+    const int32_t P = (int32_t)b->streams.size();
     for (int32_t i = 0; i < n; ++i) {
         phf_cn* cn = b->cns[i];
         const phf_data& d = data[i];
@@ -645,19 +636,10 @@ extern "C" int phf_cn_batch_run(phf_cn_batch* b, const phf_data* data, int32_t n
             return phf_set_error(ctx, PHF_EINVAL,
                                  "phf_cn_batch_run: stepper %d: unknown function kind", i);
         if (cn->gx[0] && !(same_fn(cn->gdata.f, d.f) && same_fn(cn->gdata.g, d.g) &&
-                           same_fn(cn->gdata.uD, d.uD))) {
+                           same_fn(cn->gdata.uD, d.uD)))
             cn_drop_graph(cn);
-            rebuild = true;
-        }
-        if (!cn->gx[0]) {
-            TRY(cn_capture(cn, &d));
-            rebuild = true;
-        }
-        const int32_t want = cnb_budget(cn->predict);
-        if (want > b->budget[i]) {
-            b->budget[i] = want;
-            rebuild = true;
-        }
+        if (!cn->gx[0]) TRY(cn_capture(cn, &d));
+        b->budget[i] = std::max(b->budget[i], cnb_budget(cn->predict));
         // loads at the current time, the device step counter, the statistics
         TRY(cn_loads(cn, &d, cn->F0, cn->bD0, false));
         int64_t n_host = cn->n;
@@ -666,18 +648,32 @@ extern "C" int phf_cn_batch_run(phf_cn_batch* b, const phf_data* data, int32_t n
         PHF_HIP(ctx, hipMemsetAsync(cn->d_stats, 0, 4 * sizeof(double), ctx->stream));
     }
     PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    if (rebuild) TRY(cnb_build(b));
-    std::vector<int32_t> need(n, 0);
     for (int32_t s = 0; s < nsteps; ++s) {
         phf_trace_rec rec;
         phf_trace_begin(ctx, "cn_batch_step", &rec);
-        PHF_HIP(ctx, hipGraphLaunch(b->xmain, ctx->stream));
+        TRY(cnb_fork(b));
+        for (int32_t i = 0; i < n; ++i) {
+            phf_cn* cn = b->cns[i];
+            hipStream_t st = b->streams[i % P];
+            PHF_HIP(ctx, hipGraphLaunch(cn->gx[0], st));
+            int32_t left = b->budget[i] - 1;  // the head runs the first iteration
+            for (int q = phf_cn::NG - 2; q >= 1; --q)
+                while (left >= (1 << q)) {
+                    PHF_HIP(ctx, hipGraphLaunch(cn->gx[q], st));
+                    left -= 1 << q;
+                }
+        }
+        TRY(cnb_join(b));
+        hipLaunchKernelGGL(k_cnb_gather, dim3(1), dim3(256), 0, ctx->stream, n,
+                           (const int* const*)b->d_flagp, b->d_conv);
+        PHF_HIP(ctx, hipGetLastError());
         PHF_HIP(ctx, hipMemcpyAsync(b->h_conv, b->d_conv, sizeof(int) * n, hipMemcpyDeviceToHost,
                                     ctx->stream));
         PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
         for (int32_t i = 0; i < n; ++i) {
             if (b->h_conv[i]) continue;
-            // beyond the budget: pairs of iterations until this stepper converges
+            // beyond the budget: pairs of iterations until this stepper
+            // converges; it gets a larger budget from the next step on
             phf_cn* cn = b->cns[i];
             int32_t it = b->budget[i];
             int hf[2] = {0, 0};
@@ -689,22 +685,13 @@ extern "C" int phf_cn_batch_run(phf_cn_batch* b, const phf_data* data, int32_t n
                 PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
                 if (hf[0]) break;
             }
-            need[i] = std::max(need[i], it);
+            b->budget[i] = std::max(b->budget[i], cnb_budget(it));
         }
-        PHF_HIP(ctx, hipGraphLaunch(b->xtail, ctx->stream));
-        phf_trace_end(ctx, &rec);
-        // a stepper that needed more than its budget gets a larger one from
-        // the next step on
-        bool grow = false;
+        TRY(cnb_fork(b));
         for (int32_t i = 0; i < n; ++i)
-            if (need[i] > b->budget[i]) {
-                b->budget[i] = cnb_budget(need[i]);
-                grow = true;
-            }
-        if (grow && s + 1 < nsteps) {
-            PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            TRY(cnb_build(b));
-        }
+            PHF_HIP(ctx, hipGraphLaunch(b->cns[i]->gx[phf_cn::NG - 1], b->streams[i % P]));
+        TRY(cnb_join(b));
+        phf_trace_end(ctx, &rec);
     }
     // statistics and host step counts
     int bad = 0;
