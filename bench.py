@@ -737,7 +737,8 @@ def main():
             workload=(f"{a.batch_count} jittered unit squares, triangles log-uniform in "
                       f"[2e3, 2e5] (seed 1), {nE_tot} triangles in total, per-instance "
                       f"coefficient a ~ U[0.5, 2], fp64"),
-            nE_total=nE_tot, config={"tile": cfg[0], "blocks_per_cu": cfg[1]},
+            nE_total=nE_tot, config={"tile": cfg[0], "blocks_per_cu": cfg[1], "lanes": cfg[2],
+                                     "direct": cfg[3]},
             batched=dict(ms=round(ms_b, 4), Melem_per_s=round(nE_tot / ms_b / 1e3, 1),
                          GB_per_s=round(bytes_tot / ms_b / 1e6, 1),
                          frac_of_hbm_peak=round(bytes_tot / ms_b / 1e6 / HBM_PEAK_GBS, 4),
@@ -746,7 +747,8 @@ def main():
                                      host_wall_ms=round(wall_p, 4)),
             speedup=round(ms_p / ms_b, 2),
             algorithmic_bytes=bytes_tot,
-            tuning=[{"tile": t_, "blocks_per_cu": b_, "ms": round(m_, 4)} for t_, b_, m_ in tuning])
+            tuning=[{"tile": t_, "blocks_per_cu": b_, "lanes": l_, "direct": d_, "ms": round(m_, 4)}
+                    for t_, b_, l_, d_, m_ in tuning])
         print(f"[bench] batch: {out_batch['batched']} vs per mesh {out_batch['one_launch_per_mesh']}",
               file=sys.stderr, flush=True)
 

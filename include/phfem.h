@@ -286,22 +286,35 @@ int phf_assemble(phf_mesh* mesh, const phf_coeffs* coeffs, const phf_data* data,
  * across meshes). The launch walks a work list of (mesh, tile) items, element
  * tiles then multiplier-row tiles of each mesh; its shape is the batch's
  * configuration: the tile size (64, 128 or 256 triangles or rows per
- * workgroup) and the grid (blocks_per_cu = 0: one workgroup per item; k > 0:
- * a persistent grid of k workgroups per compute unit striding over the list).
+ * workgroup), the grid (blocks_per_cu = 0: one workgroup per item; k > 0:
+ * a persistent grid of k workgroups per compute unit striding over the list),
+ * the lanes per triangle and whether element tiles are staged in LDS.
  * phf_batch_assemble: coeffs[i], data[i], out[i] as for phf_assemble of
  * meshes[i] (K, M, C, F, bD required; D and a_T given for all instances or
  * none; S is not written). The outputs are bit-identical to phf_assemble of
  * each mesh. phf_batch_tune times every candidate shape on the given
  * arguments (a warm-up and `reps` launches each, HIP events on the context's
  * stream), keeps the fastest as the batch's configuration and returns the
- * candidates' average milliseconds in results (up to max_results; 12
- * candidates); it writes the outputs as phf_batch_assemble does. The meshes
+ * candidates' average milliseconds in results (up to max_results; 18
+ * candidates: tile x {one workgroup per item, 2, 4, 8 per CU} staged, tile x
+ * per-thread stores, tile x four lanes per triangle); it writes the outputs
+ * as phf_batch_assemble does. Every shape gives bit-identical outputs. The meshes
  * must outlive the batch; the caller keeps ownership. */
 typedef struct phf_batch phf_batch;
 typedef struct {
-    int32_t tile;          /* 64, 128 or 256                                 */
-    int32_t blocks_per_cu; /* 0 = one workgroup per work item; else 1..64     */
+    int32_t tile;          /* 64, 128 or 256 threads per workgroup; element
+                              tiles of that many triangles (a quarter with
+                              lanes = 4), row tiles of that many rows        */
+    int32_t blocks_per_cu; /* 0 = one workgroup per work item; else 1..64
+                              (lanes = 1 and direct = 0 only)                */
     double ms;             /* tuning: average milliseconds per launch        */
+    int32_t lanes;         /* threads per triangle: 1 (0 reads as 1), or 4
+                              (three compute one row of the element block
+                              each, exchanging f and Neumann terms across
+                              lanes, and store it directly; no LDS)          */
+    int32_t direct;        /* lanes = 1: 0 = element tile staged in LDS and
+                              streamed out with 16-byte stores, 1 = each
+                              thread stores its own triangle's values        */
 } phf_batch_config;
 int phf_batch_create(phf_ctx* ctx, phf_mesh* const* meshes, int32_t n, phf_batch** out);
 /* (the meshes cannot be destroyed while the batch is alive: PHF_ESTATE) */

@@ -18,6 +18,7 @@
 // record. Multiplier rows gather their two end nodes (rows are in edge-id
 // order, so the larger end node is monotone).
 #include <algorithm>
+#include <cstring>
 
 #include "phf_device.h"
 #include "phf_internal.h"
@@ -356,25 +357,143 @@ __global__ __launch_bounds__(TILE) void k_assemble(AsmArgs a)
     }
 }
 
+// An element tile without the cooperative store: each thread computes its
+// triangle (into its own LDS slot) and stores its own 9 + 9 (+ 9) + 3 values
+// with 8-byte stores (no barrier; a launch-shape variant of the tuner).
+template <int TN, bool NT, bool HAS_AT, bool WITH_D, bool GEN_A>
+__device__ inline void element_direct(const AsmArgs& a, int32_t tile, double* shK, double* shD,
+                                      double* shA, double* shF)
+{
+    const int tid = threadIdx.x;
+    const int32_t m = tile * TN + tid;
+    if (m >= a.nE) return;
+    const double2 P0 = a.exy[3 * (int64_t)m], P1 = a.exy[3 * (int64_t)m + 1];
+    const double2 P2 = a.exy[3 * (int64_t)m + 2];
+    element_values<HAS_AT, true, WITH_D, GEN_A>(a, m, P0, P1, P2, tid, shK, shD, shA, shF);
+    const double* k = shK + 9 * tid;
+    for (int q = 0; q < 9; ++q) {
+        put1<NT>(a.K + 9 * (int64_t)m + q, k[q]);
+        put1<NT>(a.M + 9 * (int64_t)m + q, shA[tid] * ((q & 3) == 0 ? 2.0 : 1.0));
+        if (WITH_D) put1<NT>(a.D + 9 * (int64_t)m + q, shD[9 * tid + q]);
+    }
+    for (int q = 0; q < 3; ++q) put1<NT>(a.F + 3 * (int64_t)m + q, shF[3 * tid + q]);
+}
+
+// An element tile with four lanes per triangle: lane i < 3 computes row i of
+// K, M (and D) and F_i, lane 3 idles, and the lanes of a triangle exchange
+// their midpoint values of f and Neumann terms through cross-lane moves; the
+// rows go out with 8-byte stores, consecutive lanes writing consecutive 24
+// bytes (no LDS, no barrier). The arithmetic and its order are those of
+// element_values, so the outputs are bit-identical to the other tiles.
+template <int TN, bool NT, bool HAS_AT, bool WITH_D, bool GEN_A>
+__device__ inline void element_quad(const AsmArgs& a, int32_t tile)
+{
+#pragma clang fp contract(off)
+    const int tid = threadIdx.x;
+    const int i = tid & 3;
+    const int base = (tid & 63) & ~3;  // the triangle's first lane in the wavefront
+    const int32_t m = tile * (TN / 4) + (tid >> 2);
+    const bool act = m < a.nE;
+    double2 P0 = make_double2(0.0, 0.0), P1 = make_double2(1.0, 0.0), P2 = make_double2(0.0, 1.0);
+    if (act) {
+        P0 = a.exy[3 * (int64_t)m];
+        P1 = a.exy[3 * (int64_t)m + 1];
+        P2 = a.exy[3 * (int64_t)m + 2];
+    }
+    const double g0x = P1.y - P2.y, g0y = P2.x - P1.x;
+    const double g1x = P2.y - P0.y, g1y = P0.x - P2.x;
+    const double g2x = P0.y - P1.y, g2y = P1.x - P0.x;
+    const double det = (P1.x - P0.x) * (P2.y - P0.y) - (P2.x - P0.x) * (P1.y - P0.y);
+    const double area = 0.5 * det;
+    const bool row = act && i < 3;
+    // this lane's edge (opposite vertex i): midpoint value of f, Neumann term
+    const double2 Pa = i == 0 ? P1 : (i == 1 ? P2 : P0);
+    const double2 Pb = i == 0 ? P2 : (i == 1 ? P0 : P1);
+    double fv = 0.0, wv = 0.0;
+    int nv = 0;
+    if (row && a.f.kind != PHF_FN_ZERO) {
+        const int32_t ed = a.f.kind == PHF_FN_EDGE_ARRAY ? a.elem_edges[3 * (int64_t)m + i] : -1;
+        fv = phf_fn_eval(a.f, 0.5 * (Pa.x + Pb.x), 0.5 * (Pa.y + Pb.y), a.t, 0, 0, ed);
+    }
+    if (row && ((a.neu_mask[m >> 6] >> (m & 63)) & 1)) {
+        const int code = a.ecode[m];
+        if (PHF_CODE_TYPE(code, i) == 2) {
+            const double dx = Pb.x - Pa.x, dy = Pb.y - Pa.y;
+            const double len = sqrt(dx * dx + dy * dy);
+            const int32_t eid =
+                a.g.kind == PHF_FN_EDGE_ARRAY ? a.elem_edges[3 * (int64_t)m + i] : -1;
+            const double gv = phf_fn_eval(a.g, 0.5 * (Pa.x + Pb.x), 0.5 * (Pa.y + Pb.y), a.t,
+                                          dy / len, -dx / len, eid);
+            wv = len * gv * 0.5;
+            nv = 1;
+        }
+    }
+    const double f0 = __shfl(fv, base), f1 = __shfl(fv, base + 1), f2 = __shfl(fv, base + 2);
+    const double w0 = __shfl(wv, base), w1 = __shfl(wv, base + 1), w2 = __shfl(wv, base + 2);
+    const int n0 = __shfl(nv, base), n1 = __shfl(nv, base + 1), n2 = __shfl(nv, base + 2);
+    if (!row) return;
+    double b = 0.0;
+    if (a.f.kind != PHF_FN_ZERO) {
+        const double c = area / 6.0;
+        b = i == 0 ? c * (f1 + f2) : (i == 1 ? c * (f0 + f2) : c * (f0 + f1));
+    }
+    // the Neumann terms in the order of element_values' edge loop
+    if (i == 0) { if (n1) b += w1; if (n2) b += w2; }
+    if (i == 1) { if (n0) b += w0; if (n2) b += w2; }
+    if (i == 2) { if (n0) b += w0; if (n1) b += w1; }
+    put1<NT>(a.F + 3 * (int64_t)m + i, b);
+    const double gix = i == 0 ? g0x : (i == 1 ? g1x : g2x);
+    const double giy = i == 0 ? g0y : (i == 1 ? g1y : g2y);
+    const double aT = HAS_AT ? a.aT[m] : 1.0;
+    const double s = aT / (2.0 * det);
+    double k0, k1, k2;
+    if (GEN_A) {
+        const double aix = a.A00 * gix + a.A01 * giy, aiy = a.A10 * gix + a.A11 * giy;
+        k0 = s * (aix * g0x + aiy * g0y);
+        k1 = s * (aix * g1x + aiy * g1y);
+        k2 = s * (aix * g2x + aiy * g2y);
+    } else {
+        // the symmetric entries as element_values forms them (lower index first)
+        k0 = s * (g0x * gix + g0y * giy);
+        k1 = i == 0 ? s * (g0x * g1x + g0y * g1y) : s * (g1x * gix + g1y * giy);
+        k2 = i == 2 ? s * (g2x * g2x + g2y * g2y) : s * (gix * g2x + giy * g2y);
+    }
+    const int64_t o = 9 * (int64_t)m + 3 * i;
+    put1<NT>(a.K + o, k0);
+    put1<NT>(a.K + o + 1, k1);
+    put1<NT>(a.K + o + 2, k2);
+    const double a12 = area / 12.0;
+    put1<NT>(a.M + o, a12 * (i == 0 ? 2.0 : 1.0));
+    put1<NT>(a.M + o + 1, a12 * (i == 1 ? 2.0 : 1.0));
+    put1<NT>(a.M + o + 2, a12 * (i == 2 ? 2.0 : 1.0));
+    if (WITH_D) {
+        put1<NT>(a.D + o, (a.p0 * g0x + a.p1 * g0y) / 6.0);
+        put1<NT>(a.D + o + 1, (a.p0 * g1x + a.p1 * g1y) / 6.0);
+        put1<NT>(a.D + o + 2, (a.p0 * g2x + a.p1 * g2y) / 6.0);
+    }
+}
+
 // ---- batched assembly -------------------------------------------------------
 // One launch over a work list of (instance, tile) items of many meshes:
 // item.y >= 0 is element tile item.y of instance item.x, item.y < 0 row tile
 // ~item.y. PERSIST = false: one workgroup per item; PERSIST = true: each
 // workgroup takes items blockIdx.x, blockIdx.x + gridDim.x, ... (the loop
-// costs about 25 more VGPRs, one wave per SIMD of occupancy). The instance
-// record is staged in LDS. The tile code is the single-mesh kernel's
-// (element tiles read each mesh's own element records; stores are ordinary
-// ones, the batch's inputs being far larger than the last-level cache), so
-// the outputs are bit-identical to it.
-template <int TN, bool PERSIST, bool HAS_AT, bool WITH_D, bool GEN_A>
+// costs about 25 more VGPRs, one wave per SIMD of occupancy). MODE: the
+// element tile's form, 0 staged through LDS (TN triangles), 1 per-thread
+// stores (TN triangles), 2 four lanes per triangle (TN / 4 triangles). The
+// instance record is staged in LDS. The tile code is the single-mesh
+// kernel's (element tiles read each mesh's own element records), so the
+// outputs are bit-identical to it.
+template <int TN, int MODE, bool PERSIST, bool HAS_AT, bool WITH_D, bool GEN_A>
 __global__ __launch_bounds__(TN) void k_assemble_batch(const AsmArgs* __restrict__ args,
                                                        const int2* __restrict__ work,
                                                        int32_t nwork)
 {
-    __shared__ __align__(16) double shK[TN * 9];
-    __shared__ __align__(16) double shD[WITH_D ? TN * 9 : 2];
-    __shared__ double shA[TN];
-    __shared__ __align__(16) double shF[TN * 3];
+    constexpr bool LDS = MODE != 2;
+    __shared__ __align__(16) double shK[LDS ? TN * 9 : 2];
+    __shared__ __align__(16) double shD[LDS && WITH_D ? TN * 9 : 2];
+    __shared__ double shA[LDS ? TN : 1];
+    __shared__ __align__(16) double shF[LDS ? TN * 3 : 2];
     __shared__ int32_t shs[TN / 64 + 1];
     __shared__ AsmArgs sa;
     static_assert(sizeof(AsmArgs) % 8 == 0 && sizeof(AsmArgs) / 8 <= TN, "record copy");
@@ -385,10 +504,14 @@ __global__ __launch_bounds__(TN) void k_assemble_batch(const AsmArgs* __restrict
                 reinterpret_cast<const uint64_t*>(args + item.x)[threadIdx.x];
         __syncthreads();
         const AsmArgs& a = sa;
-        if (item.y >= 0)
-            element_tile<TN, false, HAS_AT, true, WITH_D, GEN_A>(a, item.y, shK, shD, shA, shF);
+        if (item.y < 0)
+            row_tile<TN, true, true>(a, ~item.y, shs);
+        else if (MODE == 0)
+            element_tile<TN, true, HAS_AT, true, WITH_D, GEN_A>(a, item.y, shK, shD, shA, shF);
+        else if (MODE == 1)
+            element_direct<TN, true, HAS_AT, WITH_D, GEN_A>(a, item.y, shK, shD, shA, shF);
         else
-            row_tile<TN, false, true>(a, ~item.y, shs);
+            element_quad<TN, true, HAS_AT, WITH_D, GEN_A>(a, item.y);
         if (!PERSIST) break;
         __syncthreads();  // the next item reuses the shared arrays
     }
@@ -629,9 +752,12 @@ struct phf_batch {
     AsmArgs* d_args = nullptr;
     hipEvent_t args_ev = nullptr;  // the last upload of h_args
     bool args_pending = false;
-    int2* d_work[3] = {nullptr, nullptr, nullptr};  // work lists for tiles 64, 128, 256
-    int32_t nwork[3] = {0, 0, 0};
-    int32_t tile = 256, blocks_per_cu = 0, ncu = 256;
+    std::vector<AsmArgs> last;     // records of the last upload (skipped when unchanged)
+    // work lists for tiles of 64, 128, 256 threads with as many triangles
+    // ([0..2]) or a quarter as many ([3..5], four lanes per triangle)
+    int2* d_work[6] = {};
+    int32_t nwork[6] = {};
+    int32_t tile = 256, blocks_per_cu = 0, ncu = 256, lanes = 1, direct = 0;
     bool counted = false;  // registered with the meshes and context
 };
 
@@ -639,59 +765,70 @@ namespace {
 int tile_index(int32_t tile) { return tile == 64 ? 0 : (tile == 128 ? 1 : (tile == 256 ? 2 : -1)); }
 
 // Work list for one tile size: per instance its element and row tiles,
-// interleaved in proportion as in the single-mesh launch.
-int batch_work(phf_batch* b, int ti)
+// interleaved in proportion as in the single-mesh launch. wi = ti: element
+// tiles of 64 << ti triangles; wi = 3 + ti: a quarter of that.
+int batch_work(phf_batch* b, int wi)
 {
-    if (b->d_work[ti]) return PHF_OK;
-    const int32_t tn = 64 << ti;
+    if (b->d_work[wi]) return PHF_OK;
+    const int32_t tn = 64 << (wi % 3), te = wi >= 3 ? tn / 4 : tn;
     std::vector<int2> w;
     for (size_t i = 0; i < b->meshes.size(); ++i) {
         const phf_mesh* m = b->meshes[i];
-        const int64_t ne = (m->nE + tn - 1) / tn, nr = (m->L + tn - 1) / tn, T = ne + nr;
+        const int64_t ne = (m->nE + te - 1) / te, nr = (m->L + tn - 1) / tn, T = ne + nr;
         for (int64_t q = 0; q < T; ++q) {
             const int64_t e0 = q * ne / T, e1 = (q + 1) * ne / T;
             w.push_back(make_int2((int32_t)i, e1 > e0 ? (int32_t)e0 : ~(int32_t)(q - e0)));
         }
     }
     phf_ctx* ctx = b->ctx;
-    TRY(phf_dmalloc(ctx, &b->d_work[ti], std::max<size_t>(w.size(), 1), "batch work list"));
-    PHF_HIP(ctx, hipMemcpyAsync(b->d_work[ti], w.data(), sizeof(int2) * w.size(),
+    TRY(phf_dmalloc(ctx, &b->d_work[wi], std::max<size_t>(w.size(), 1), "batch work list"));
+    PHF_HIP(ctx, hipMemcpyAsync(b->d_work[wi], w.data(), sizeof(int2) * w.size(),
                                 hipMemcpyHostToDevice, ctx->stream));
     PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));  // w is released on return
-    b->nwork[ti] = (int32_t)w.size();
+    b->nwork[wi] = (int32_t)w.size();
     return PHF_OK;
 }
 
-template <int TN, bool HAS_AT, bool WITH_D, bool GEN_A>
-int launch_batch_t(phf_batch* b, int ti)
+template <int TN, int MODE, bool HAS_AT, bool WITH_D, bool GEN_A>
+int launch_batch_t(phf_batch* b, int wi)
 {
     phf_ctx* ctx = b->ctx;
-    const int32_t nw = b->nwork[ti];
+    const int32_t nw = b->nwork[wi];
     if (nw == 0) return PHF_OK;
-    if (b->blocks_per_cu > 0) {
+    if (MODE == 0 && b->blocks_per_cu > 0) {
         const int64_t grid = std::min<int64_t>(nw, (int64_t)b->blocks_per_cu * b->ncu);
-        PHF_LAUNCH(ctx, "k_assemble_batch", (k_assemble_batch<TN, true, HAS_AT, WITH_D, GEN_A>),
-                   (unsigned)grid, TN, 0, b->d_args, b->d_work[ti], nw);
+        PHF_LAUNCH(ctx, "k_assemble_batch",
+                   (k_assemble_batch<TN, MODE, true, HAS_AT, WITH_D, GEN_A>), (unsigned)grid, TN,
+                   0, b->d_args, b->d_work[wi], nw);
     } else {
-        PHF_LAUNCH(ctx, "k_assemble_batch", (k_assemble_batch<TN, false, HAS_AT, WITH_D, GEN_A>),
-                   (unsigned)nw, TN, 0, b->d_args, b->d_work[ti], nw);
+        PHF_LAUNCH(ctx, "k_assemble_batch",
+                   (k_assemble_batch<TN, MODE, false, HAS_AT, WITH_D, GEN_A>), (unsigned)nw, TN,
+                   0, b->d_args, b->d_work[wi], nw);
     }
     return PHF_OK;
+}
+
+template <int TN, int MODE>
+int launch_batch_mode(phf_batch* b, int wi, bool hasAT, bool withD, bool genA)
+{
+    if (hasAT) {
+        if (withD) return genA ? launch_batch_t<TN, MODE, true, true, true>(b, wi)
+                               : launch_batch_t<TN, MODE, true, true, false>(b, wi);
+        return genA ? launch_batch_t<TN, MODE, true, false, true>(b, wi)
+                    : launch_batch_t<TN, MODE, true, false, false>(b, wi);
+    }
+    if (withD) return genA ? launch_batch_t<TN, MODE, false, true, true>(b, wi)
+                           : launch_batch_t<TN, MODE, false, true, false>(b, wi);
+    return genA ? launch_batch_t<TN, MODE, false, false, true>(b, wi)
+                : launch_batch_t<TN, MODE, false, false, false>(b, wi);
 }
 
 template <int TN>
-int launch_batch_tn(phf_batch* b, int ti, bool hasAT, bool withD, bool genA)
+int launch_batch_tn(phf_batch* b, int wi, int mode, bool hasAT, bool withD, bool genA)
 {
-    if (hasAT) {
-        if (withD) return genA ? launch_batch_t<TN, true, true, true>(b, ti)
-                               : launch_batch_t<TN, true, true, false>(b, ti);
-        return genA ? launch_batch_t<TN, true, false, true>(b, ti)
-                    : launch_batch_t<TN, true, false, false>(b, ti);
-    }
-    if (withD) return genA ? launch_batch_t<TN, false, true, true>(b, ti)
-                           : launch_batch_t<TN, false, true, false>(b, ti);
-    return genA ? launch_batch_t<TN, false, false, true>(b, ti)
-                : launch_batch_t<TN, false, false, false>(b, ti);
+    if (mode == 2) return launch_batch_mode<TN, 2>(b, wi, hasAT, withD, genA);
+    if (mode == 1) return launch_batch_mode<TN, 1>(b, wi, hasAT, withD, genA);
+    return launch_batch_mode<TN, 0>(b, wi, hasAT, withD, genA);
 }
 
 // Validates and uploads the per-instance records; returns the variant flags.
@@ -701,15 +838,12 @@ int batch_prepare(phf_batch* b, const phf_coeffs* co, const phf_data* data, cons
     phf_ctx* ctx = b->ctx;
     if (!co || !data || !out) return phf_set_error(ctx, PHF_EINVAL, "phf_batch_assemble: null argument");
     const size_t n = b->meshes.size();
-    if (b->args_pending) {
-        PHF_HIP(ctx, hipEventSynchronize(b->args_ev));  // h_args is free again
-        b->args_pending = false;
-    }
     *hasAT = n > 0 && co[0].a_T != nullptr;
     *withD = n > 0 && out[0].D != nullptr;
     *genA = false;
+    std::vector<AsmArgs> rec(n);
     for (size_t i = 0; i < n; ++i) {
-        TRY(make_args(b->meshes[i], &co[i], &data[i], &out[i], "phf_batch_assemble", &b->h_args[i]));
+        TRY(make_args(b->meshes[i], &co[i], &data[i], &out[i], "phf_batch_assemble", &rec[i]));
         if (!out[i].K)
             return phf_set_error(ctx, PHF_EINVAL, "phf_batch_assemble: instance %zu: K, M, C required", i);
         if ((co[i].a_T != nullptr) != *hasAT || (out[i].D != nullptr) != *withD)
@@ -720,21 +854,33 @@ int batch_prepare(phf_batch* b, const phf_coeffs* co, const phf_data* data, cons
     // the variant choice of phf_assemble (D implies the general-A form), so
     // that the outputs are bit-identical to it
     *genA = *genA || *withD;
+    // the records go up only when they differ from the last upload (repeated
+    // assemblies of one batch with the same buffers and data reuse them)
+    if (b->last.size() == n && std::memcmp(b->last.data(), rec.data(), sizeof(AsmArgs) * n) == 0)
+        return PHF_OK;
+    if (b->args_pending) {
+        PHF_HIP(ctx, hipEventSynchronize(b->args_ev));  // h_args is free again
+        b->args_pending = false;
+    }
+    std::memcpy(b->h_args, rec.data(), sizeof(AsmArgs) * n);
     PHF_HIP(ctx, hipMemcpyAsync(b->d_args, b->h_args, sizeof(AsmArgs) * n, hipMemcpyHostToDevice,
                                 ctx->stream));
     PHF_HIP(ctx, hipEventRecord(b->args_ev, ctx->stream));
     b->args_pending = true;
+    b->last = rec;
     return PHF_OK;
 }
 
 int batch_launch(phf_batch* b, bool hasAT, bool withD, bool genA)
 {
     const int ti = tile_index(b->tile);
-    TRY(batch_work(b, ti));
+    const int mode = b->lanes == 4 ? 2 : (b->direct ? 1 : 0);
+    const int wi = mode == 2 ? 3 + ti : ti;
+    TRY(batch_work(b, wi));
     switch (b->tile) {
-    case 64: return launch_batch_tn<64>(b, ti, hasAT, withD, genA);
-    case 128: return launch_batch_tn<128>(b, ti, hasAT, withD, genA);
-    default: return launch_batch_tn<256>(b, ti, hasAT, withD, genA);
+    case 64: return launch_batch_tn<64>(b, wi, mode, hasAT, withD, genA);
+    case 128: return launch_batch_tn<128>(b, wi, mode, hasAT, withD, genA);
+    default: return launch_batch_tn<256>(b, wi, mode, hasAT, withD, genA);
     }
 }
 }  // namespace
@@ -804,18 +950,26 @@ extern "C" int phf_batch_get_config(const phf_batch* b, phf_batch_config* cfg)
     cfg->tile = b->tile;
     cfg->blocks_per_cu = b->blocks_per_cu;
     cfg->ms = -1.0;
+    cfg->lanes = b->lanes;
+    cfg->direct = b->direct;
     return PHF_OK;
 }
 
 extern "C" int phf_batch_set_config(phf_batch* b, const phf_batch_config* cfg)
 {
     if (!b || !cfg) return PHF_EINVAL;
-    if (tile_index(cfg->tile) < 0 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64)
+    const int32_t lanes = cfg->lanes == 0 ? 1 : cfg->lanes;
+    if (tile_index(cfg->tile) < 0 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64 ||
+        (lanes != 1 && lanes != 4) || (cfg->direct != 0 && cfg->direct != 1) ||
+        ((lanes == 4 || cfg->direct) && cfg->blocks_per_cu != 0))
         return phf_set_error(b->ctx, PHF_EINVAL,
-                             "phf_batch_set_config: tile must be 64, 128 or 256 and "
-                             "blocks_per_cu 0..64");
+                             "phf_batch_set_config: tile must be 64, 128 or 256, blocks_per_cu "
+                             "0..64 (0 unless lanes = 1 and direct = 0), lanes 1 or 4, direct 0 "
+                             "or 1");
     b->tile = cfg->tile;
     b->blocks_per_cu = cfg->blocks_per_cu;
+    b->lanes = lanes;
+    b->direct = lanes == 4 ? 0 : cfg->direct;
     return PHF_OK;
 }
 
@@ -828,57 +982,67 @@ extern "C" int phf_batch_tune(phf_batch* b, const phf_coeffs* co, const phf_data
     if (reps < 1) reps = 5;
     bool hasAT, withD, genA;
     TRY(batch_prepare(b, co, data, out, &hasAT, &withD, &genA));
-    static const int32_t tiles[] = {64, 128, 256};
-    static const int32_t bpcs[] = {0, 2, 4, 8};
+    // candidate shapes: staged element tiles with one workgroup per item or a
+    // persistent grid; per-thread stores; four lanes per triangle
+    struct shape {
+        int32_t tile, bpc, lanes, direct;
+    };
+    std::vector<shape> shapes;
+    for (int32_t tile : {64, 128, 256})
+        for (int32_t bpc : {0, 2, 4, 8}) shapes.push_back({tile, bpc, 1, 0});
+    for (int32_t tile : {64, 128, 256}) shapes.push_back({tile, 0, 1, 1});
+    for (int32_t tile : {64, 128, 256}) shapes.push_back({tile, 0, 4, 0});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     PHF_HIP(ctx, hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
         (void)hipEventDestroy(e0);
         return phf_set_error(ctx, PHF_EHIP, "phf_batch_tune: event creation failed");
     }
-    const int32_t keep_tile = b->tile, keep_bpc = b->blocks_per_cu;
-    int32_t best_tile = keep_tile, best_bpc = keep_bpc, cnt = 0;
+    const shape keep{b->tile, b->blocks_per_cu, b->lanes, b->direct};
+    shape bestc = keep;
+    int32_t cnt = 0;
     double best = 1e300;
     int rc = PHF_OK;
-    for (int32_t tile : tiles) {
-        for (int32_t bpc : bpcs) {
-            b->tile = tile;
-            b->blocks_per_cu = bpc;
-            rc = batch_launch(b, hasAT, withD, genA);  // warm-up (and work list)
-            if (rc) break;
-            if (hipEventRecord(e0, ctx->stream) != hipSuccess) {
-                rc = phf_set_error(ctx, PHF_EHIP, "phf_batch_tune: event record failed");
-                break;
-            }
-            for (int32_t r = 0; r < reps && !rc; ++r) rc = batch_launch(b, hasAT, withD, genA);
-            if (rc) break;
-            float ms = 0.f;
-            if (hipEventRecord(e1, ctx->stream) != hipSuccess ||
-                hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                rc = phf_set_error(ctx, PHF_EHIP, "phf_batch_tune: timing failed");
-                break;
-            }
-            const double avg = (double)ms / reps;
-            if (results && cnt < max_results) results[cnt] = {tile, bpc, avg};
-            ++cnt;
-            if (avg < best) {
-                best = avg;
-                best_tile = tile;
-                best_bpc = bpc;
-            }
-        }
+    for (const shape& sh : shapes) {
+        b->tile = sh.tile;
+        b->blocks_per_cu = sh.bpc;
+        b->lanes = sh.lanes;
+        b->direct = sh.direct;
+        rc = batch_launch(b, hasAT, withD, genA);  // warm-up (and work list)
         if (rc) break;
+        if (hipEventRecord(e0, ctx->stream) != hipSuccess) {
+            rc = phf_set_error(ctx, PHF_EHIP, "phf_batch_tune: event record failed");
+            break;
+        }
+        for (int32_t r = 0; r < reps && !rc; ++r) rc = batch_launch(b, hasAT, withD, genA);
+        if (rc) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = phf_set_error(ctx, PHF_EHIP, "phf_batch_tune: timing failed");
+            break;
+        }
+        const double avg = (double)ms / reps;
+        if (results && cnt < max_results) results[cnt] = {sh.tile, sh.bpc, avg, sh.lanes, sh.direct};
+        ++cnt;
+        if (avg < best) {
+            best = avg;
+            bestc = sh;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) {
-        b->tile = keep_tile;
-        b->blocks_per_cu = keep_bpc;
+        b->tile = keep.tile;
+        b->blocks_per_cu = keep.bpc;
+        b->lanes = keep.lanes;
+        b->direct = keep.direct;
         return rc;
     }
-    b->tile = best_tile;
-    b->blocks_per_cu = best_bpc;
+    b->tile = bestc.tile;
+    b->blocks_per_cu = bestc.bpc;
+    b->lanes = bestc.lanes;
+    b->direct = bestc.direct;
     if (n_results) *n_results = std::min(cnt, max_results);
     return PHF_OK;
 }

@@ -48,23 +48,28 @@ def test_batch_bit_identical_all_shapes(ctx):
         ref.append(_host(t))
     outs = [phfem.alloc_system(dm, fill=NAN) for dm in meshes]
     b = phfem.phf_batch_create(ctx.handle, [dm.handle for dm in meshes])
+    shapes = [(tile, bpc, 1, 0) for tile in (64, 128, 256) for bpc in (0, 1, 4)]
+    shapes += [(tile, 0, 1, 1) for tile in (64, 128, 256)]  # per-thread stores
+    shapes += [(tile, 0, 4, 0) for tile in (64, 128, 256)]  # four lanes per triangle
     try:
-        for tile in (64, 128, 256):
-            for bpc in (0, 1, 4):
-                for s, t in outs:  # poison the outputs
-                    for k in KEYS:
-                        t[k].fill_(np.nan)
-                phfem.phf_batch_set_config(b, tile, bpc)
-                phfem.phf_batch_assemble(b, coeffs, data, [s for s, _ in outs])
-                for i, (s, t) in enumerate(outs):
-                    got = _host(t)
-                    for k in KEYS:
-                        assert got[k].tobytes() == ref[i][k].tobytes(), (tile, bpc, i, k)
+        for shape in shapes:
+            for s, t in outs:  # poison the outputs
+                for k in KEYS:
+                    t[k].fill_(np.nan)
+            phfem.phf_batch_set_config(b, *shape)
+            assert phfem.phf_batch_get_config(b) == shape
+            phfem.phf_batch_assemble(b, coeffs, data, [s for s, _ in outs])
+            for i, (s, t) in enumerate(outs):
+                got = _host(t)
+                for k in KEYS:
+                    assert got[k].tobytes() == ref[i][k].tobytes(), (shape, i, k)
+        with pytest.raises(phfem.PhfError):
+            phfem.phf_batch_set_config(b, 128, 2, 4, 0)  # persistent grids stage in LDS
         res = phfem.phf_batch_tune(b, coeffs, data, [s for s, _ in outs], reps=2)
         print("tuning", res, "->", phfem.phf_batch_get_config(b), flush=True)
-        assert len(res) == 12 and all(ms > 0 for _, _, ms in res)
-        best = min(res, key=lambda r: r[2])
-        assert phfem.phf_batch_get_config(b) == best[:2]
+        assert len(res) == 18 and all(r[4] > 0 for r in res)
+        best = min(res, key=lambda r: r[4])
+        assert phfem.phf_batch_get_config(b) == best[:4]
         for i, (s, t) in enumerate(outs):
             got = _host(t)
             for k in KEYS:
@@ -85,17 +90,25 @@ def test_batch_with_D_and_aT_and_oracle(ctx, oracle):
     outs = [phfem.alloc_system(dm, with_D=True, fill=NAN) for dm in meshes]
     b = phfem.phf_batch_create(ctx.handle, [dm.handle for dm in meshes])
     try:
-        phfem.phf_batch_set_config(b, 128, 2)
-        phfem.phf_batch_assemble(b, coeffs, data, [s for s, _ in outs])
-        for i, (dm, co, d) in enumerate(zip(meshes, coeffs, data)):
+        single = []
+        for dm, co, d in zip(meshes, coeffs, data):
             s, t = phfem.alloc_system(dm, with_D=True, fill=NAN)
             phfem.phf_assemble(dm.handle, co, d, s)
             assert_written(t, dm.info)
-            for k in KEYS + ("D",):
-                gb, gs = outs[i][1][k].cpu().numpy(), t[k].cpu().numpy()
-                nd = int((gb != gs).sum())
-                assert nd == 0, (i, k, nd, gb.size, float(np.abs(gb - gs).max()),
-                                 float(np.abs(gs).max()))
+            single.append({k: t[k].cpu().numpy() for k in KEYS + ("D",)})
+        # staged persistent grid, four lanes per triangle, per-thread stores
+        for shape in ((128, 2, 1, 0), (64, 0, 4, 0), (256, 0, 1, 1)):
+            for _, t in outs:
+                for k in KEYS + ("D",):
+                    t[k].fill_(np.nan)
+            phfem.phf_batch_set_config(b, *shape)
+            phfem.phf_batch_assemble(b, coeffs, data, [s for s, _ in outs])
+            for i in range(len(meshes)):
+                for k in KEYS + ("D",):
+                    gb, gs = outs[i][1][k].cpu().numpy(), single[i][k]
+                    nd = int((gb != gs).sum())
+                    assert nd == 0, (shape, i, k, nd, gb.size, float(np.nanmax(np.abs(gb - gs))),
+                                     float(np.abs(gs).max()))
         # one instance against the oracle (values per scaled tolerance)
         m, a = inst[0]
         asm = oracle.assemble(m, oracle.mesh_tables(m), p=(0.5, -1.0), aT=aTs[0],
