@@ -432,10 +432,11 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--rtol", type=float, default=1e-10)
-    ap.add_argument("--mode", choices=("full", "assembly"), default="full",
-                    help="assembly: only the numeric assembly (headline mesh, or the L-shape "
-                         "with --workload lshape) plus one plain device copy of --copy-mib MiB "
-                         "(for hardware-counter runs)")
+    ap.add_argument("--mode", choices=("full", "assembly", "batch", "pipeline"), default="full",
+                    help="counter runs: assembly = the numeric assembly alone (headline mesh, or "
+                         "the L-shape with --workload lshape); batch = the batched assembly at "
+                         "tile 128; pipeline = one whole elliptic step on the headline mesh; "
+                         "each followed by one plain device copy of --copy-mib MiB")
     ap.add_argument("--workload", choices=("paper", "lshape"), default="paper")
     ap.add_argument("--asm-reps", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=512)
@@ -495,6 +496,51 @@ def main():
         print(json.dumps({"mode": "assembly", "workload": a.workload, "nE": info.nE,
                           "launches": a.asm_reps,
                           "algorithmic_bytes_per_launch": algorithmic_bytes(info)["k_assemble"],
+                          "copy_bytes_each_way": src.numel() * 8}))
+        return
+
+    if a.mode == "batch":
+        inst = G.batch_instances(a.batch_count, 1)
+        bm = [phfem.phf_mesh_create(h, mm.coords, mm.elements, mm.dirichlet, mm.neumann)
+              for mm, _ in inst]
+        binfo = [phfem.phf_mesh_get_info(x) for x in bm]
+        bco = [phfem.make_coeffs(A=(av, 0.0, 0.0, av)) for _, av in inst]
+        bdat = [phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_COS, 2 * pi * pi * av, 0),
+                                phfem.make_fn(phfem.PHF_FN_GRAD_SIN_COS, av, 0),
+                                phfem.make_fn(phfem.PHF_FN_SIN_COS, 1, 0)) for _, av in inst]
+        bsys = [phfem.alloc_system_for(bi, dev)[0] for bi in binfo]
+        batch = phfem.phf_batch_create(h, bm)
+        phfem.phf_batch_set_config(batch, 128, 0, 1, 0)
+        for _ in range(a.asm_reps):
+            phfem.phf_batch_assemble(batch, bco, bdat, bsys)
+        src = torch.ones(a.copy_mib << 17, dtype=torch.float64, device=dev)
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        phfem.phf_batch_destroy(batch)
+        for x in bm:
+            phfem.phf_mesh_destroy(x)
+        print(json.dumps({"mode": "batch", "nE_total": sum(bi.nE for bi in binfo),
+                          "launches": a.asm_reps,
+                          "algorithmic_bytes_per_launch": sum(
+                              algorithmic_bytes(bi, has_aT=False)["k_assemble"] for bi in binfo),
+                          "copy_bytes_each_way": src.numel() * 8}))
+        return
+
+    if a.mode == "pipeline":
+        chain = build_chain(phfem, h, paper_base, a.level)
+        info = phfem.phf_mesh_get_info(chain[-1])
+        aT_d = torch.tensor(G.per_triangle_coefficient(info.nE, 0), device=dev)
+        co = phfem.make_coeffs(a_T=aT_d)
+        sysd, t = phfem.alloc_system_for(info, dev)
+        U = torch.empty(info.N, dtype=torch.float64, device=dev)
+        Lam = torch.empty(info.L, dtype=torch.float64, device=dev)
+        release(phfem, chain)
+        rows = pipeline_steps(phfem, torch, h, paper_base, a.level, co, data, sysd, U, Lam, a.rtol,
+                              1, pc)
+        src = torch.ones(a.copy_mib << 17, dtype=torch.float64, device=dev)
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "pipeline", "nE": info.nE, "step": rows[0],
                           "copy_bytes_each_way": src.numel() * 8}))
         return
 
@@ -747,6 +793,9 @@ def main():
                                      host_wall_ms=round(wall_p, 4)),
             speedup=round(ms_p / ms_b, 2),
             algorithmic_bytes=bytes_tot,
+            # counters were taken with the staged tile of 128
+            traffic=(traffic_for("k_assemble_batch", "k_assemble_batch@256_meshes")
+                     if tuple(cfg) == (128, 0, 1, 0) and a.batch_count == 256 else None),
             tuning=[{"tile": t_, "blocks_per_cu": b_, "lanes": l_, "direct": d_, "ms": round(m_, 4)}
                     for t_, b_, l_, d_, m_ in tuning])
         print(f"[bench] batch: {out_batch['batched']} vs per mesh {out_batch['one_launch_per_mesh']}",
