@@ -300,31 +300,39 @@ __device__ inline void child_tile(const AsmArgs& a, int32_t tile, double* shK, d
 
 // A row tile: TN consecutive multiplier rows. Their C values are one
 // contiguous run starting at the tile's base pointer; each row's offset in it
-// is an exclusive scan of the row lengths (4 interior, 2 Dirichlet). A row
-// reads its edge's half-length |E|/2 from the mesh's row records (negated on
-// Dirichlet rows); only a Dirichlet row with data reads its end nodes, for
-// the midpoint of u_D.
+// is an exclusive scan of the row lengths (4 interior, 2 Dirichlet). The rows
+// put their values into LDS at those offsets and the tile streams the run out
+// with 16-byte stores, so that every store instruction covers whole lines
+// (rows writing their own 16 or 32 bytes leave lines split between two
+// instructions, which non-temporal stores send to memory as two partial
+// writes). A row reads its edge's half-length |E|/2 from the mesh's row
+// records (negated on Dirichlet rows); only a Dirichlet row with data reads
+// its end nodes, for the midpoint of u_D. shC: 4 TN doubles.
 template <int TN, bool NT, bool MATS>
-__device__ inline void row_tile(const AsmArgs& a, int32_t tile, int32_t* shs)
+__device__ inline void row_tile(const AsmArgs& a, int32_t tile, int32_t* shs, double* shC)
 {
     const int32_t r = tile * TN + threadIdx.x;
-    double hs = 0.0;
-    int32_t len = 0;
-    if (r < a.L) {
-        hs = a.row_hs[r];
-        len = hs < 0.0 ? 2 : 4;
-    }
+    const bool live = r < a.L;
+    const double hs = live ? a.row_hs[r] : 0.0;
+    const int32_t len = live ? (hs < 0.0 ? 2 : 4) : 0;
     int32_t tot;
     const int32_t off = phf_block_exscan_i32<TN>(len, shs, &tot);
-    if (r >= a.L) return;
     const bool dirichlet = hs < 0.0;
     const double h = fabs(hs);
     if (MATS) {
-        const int32_t c0 = (TN == 256 ? a.C_tile[tile] : a.C_rowptr[tile * TN]) + off;
-        phf_v2d* C2 = reinterpret_cast<phf_v2d*>(a.C + c0);
-        put2<NT>(C2, h, h);
-        if (!dirichlet) put2<NT>(C2 + 1, -h, -h);
+        if (live) {
+            shC[off] = h;
+            shC[off + 1] = h;
+            if (!dirichlet) {
+                shC[off + 2] = -h;
+                shC[off + 3] = -h;
+            }
+        }
+        __syncthreads();
+        const int32_t c0 = TN == 256 ? a.C_tile[tile] : a.C_rowptr[tile * TN];
+        store_run<TN, NT>(a.C + c0, tot, [&](int32_t v) { return shC[v]; });
     }
+    if (!live) return;
     double v = 0.0;
     if (dirichlet && a.uD.kind != PHF_FN_ZERO) {
         const int2 kl = a.row_nodes[r];
@@ -353,7 +361,7 @@ __global__ __launch_bounds__(TILE) void k_assemble(AsmArgs a)
         else
             element_tile<TILE, true, HAS_AT, MATS, WITH_D, GEN_A>(a, tile, shK, shD, shA, shF);
     } else {
-        row_tile<TILE, true, MATS>(a, tile, shs);
+        row_tile<TILE, true, MATS>(a, tile, shs, shK);
     }
 }
 
@@ -490,7 +498,7 @@ __global__ __launch_bounds__(TN) void k_assemble_batch(const AsmArgs* __restrict
                                                        int32_t nwork)
 {
     constexpr bool LDS = MODE != 2;
-    __shared__ __align__(16) double shK[LDS ? TN * 9 : 2];
+    __shared__ __align__(16) double shK[LDS ? TN * 9 : TN * 4];  // row tiles stage C here
     __shared__ __align__(16) double shD[LDS && WITH_D ? TN * 9 : 2];
     __shared__ double shA[LDS ? TN : 1];
     __shared__ __align__(16) double shF[LDS ? TN * 3 : 2];
@@ -505,7 +513,7 @@ __global__ __launch_bounds__(TN) void k_assemble_batch(const AsmArgs* __restrict
         __syncthreads();
         const AsmArgs& a = sa;
         if (item.y < 0)
-            row_tile<TN, true, true>(a, ~item.y, shs);
+            row_tile<TN, true, true>(a, ~item.y, shs, shK);
         else if (MODE == 0)
             element_tile<TN, true, HAS_AT, true, WITH_D, GEN_A>(a, item.y, shK, shD, shA, shF);
         else if (MODE == 1)
