@@ -450,6 +450,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-reps", type=int, default=20)
     ap.add_argument("--cn-batch-count", type=int, default=16)
+    ap.add_argument("--batch-tile", type=int, default=128, help="--mode batch: tile")
+    ap.add_argument("--batch-gather", type=int, default=0, help="--mode batch: gathered coordinates")
     ap.add_argument("--cn-batch-steps", type=int, default=50)
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -512,7 +514,7 @@ def main():
                                 phfem.make_fn(phfem.PHF_FN_SIN_COS, 1, 0)) for _, av in inst]
         bsys = [phfem.alloc_system_for(bi, dev)[0] for bi in binfo]
         batch = phfem.phf_batch_create(h, bm)
-        phfem.phf_batch_set_config(batch, 128, 0, 1, 0)
+        phfem.phf_batch_set_config(batch, a.batch_tile, 0, 1, 0, a.batch_gather)
         for _ in range(a.asm_reps):
             phfem.phf_batch_assemble(batch, bco, bdat, bsys)
         src = torch.ones(a.copy_mib << 17, dtype=torch.float64, device=dev)
@@ -786,7 +788,7 @@ def main():
                       f"[2e3, 2e5] (seed 1), {nE_tot} triangles in total, per-instance "
                       f"coefficient a ~ U[0.5, 2], fp64"),
             nE_total=nE_tot, config={"tile": cfg[0], "blocks_per_cu": cfg[1], "lanes": cfg[2],
-                                     "direct": cfg[3]},
+                                     "direct": cfg[3], "gather": cfg[4]},
             batched=dict(ms=round(ms_b, 4), Melem_per_s=round(nE_tot / ms_b / 1e3, 1),
                          GB_per_s=round(bytes_tot / ms_b / 1e6, 1),
                          frac_of_hbm_peak=round(bytes_tot / ms_b / 1e6 / HBM_PEAK_GBS, 4),
@@ -797,9 +799,9 @@ def main():
             algorithmic_bytes=bytes_tot,
             # counters were taken with the staged tile of 128
             traffic=(traffic_for("k_assemble_batch", "k_assemble_batch@256_meshes")
-                     if tuple(cfg) == (128, 0, 1, 0) and a.batch_count == 256 else None),
-            tuning=[{"tile": t_, "blocks_per_cu": b_, "lanes": l_, "direct": d_, "ms": round(m_, 4)}
-                    for t_, b_, l_, d_, m_ in tuning])
+                     if tuple(cfg) == (128, 0, 1, 0, 0) and a.batch_count == 256 else None),
+            tuning=[{"tile": t_, "blocks_per_cu": b_, "lanes": l_, "direct": d_, "gather": g_,
+                     "ms": round(m_, 4)} for t_, b_, l_, d_, g_, m_ in tuning])
         print(f"[bench] batch: {out_batch['batched']} vs per mesh {out_batch['one_launch_per_mesh']}",
               file=sys.stderr, flush=True)
 

@@ -288,17 +288,19 @@ int phf_assemble(phf_mesh* mesh, const phf_coeffs* coeffs, const phf_data* data,
  * configuration: the tile size (64, 128 or 256 triangles or rows per
  * workgroup), the grid (blocks_per_cu = 0: one workgroup per item; k > 0:
  * a persistent grid of k workgroups per compute unit striding over the list),
- * the lanes per triangle and whether element tiles are staged in LDS.
+ * the lanes per triangle, whether element tiles are staged in LDS, and where
+ * their vertex coordinates come from.
  * phf_batch_assemble: coeffs[i], data[i], out[i] as for phf_assemble of
  * meshes[i] (K, M, C, F, bD required; D and a_T given for all instances or
  * none; S is not written). The outputs are bit-identical to phf_assemble of
  * each mesh. phf_batch_tune times every candidate shape on the given
  * arguments (a warm-up and `reps` launches each, HIP events on the context's
  * stream), keeps the fastest as the batch's configuration and returns the
- * candidates' average milliseconds in results (up to max_results; 18
+ * candidates' average milliseconds in results (up to max_results; 21
  * candidates: tile x {one workgroup per item, 2, 4, 8 per CU} staged, tile x
- * per-thread stores, tile x four lanes per triangle); it writes the outputs
- * as phf_batch_assemble does. Every shape gives bit-identical outputs. The meshes
+ * per-thread stores, tile x four lanes per triangle, tile x staged with
+ * gathered coordinates); it writes the outputs as phf_batch_assemble does.
+ * Every shape gives bit-identical outputs. The meshes
  * must outlive the batch; the caller keeps ownership. */
 typedef struct phf_batch phf_batch;
 typedef struct {
@@ -315,6 +317,11 @@ typedef struct {
     int32_t direct;        /* lanes = 1: 0 = element tile staged in LDS and
                               streamed out with 16-byte stores, 1 = each
                               thread stores its own triangle's values        */
+    int32_t gather;        /* staged tiles: 1 = vertex coordinates gathered
+                              from the node array through the vertex ids
+                              (16 bytes per triangle plus cached gathers)
+                              instead of the element-major copy (48 bytes)   */
+    int32_t reserved_;     /* 0                                              */
 } phf_batch_config;
 int phf_batch_create(phf_ctx* ctx, phf_mesh* const* meshes, int32_t n, phf_batch** out);
 /* (the meshes cannot be destroyed while the batch is alive: PHF_ESTATE) */

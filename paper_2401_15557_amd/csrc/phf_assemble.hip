@@ -32,6 +32,7 @@ struct AsmArgs {
     int32_t nEp, pad_;      // refined meshes: elements of the coarse mesh (nE = 4 nEp)
     const double2* exy;
     const double2* pexy;    // coarse mesh's element-major coordinates, or null
+    const int4* elem4;      // vertex ids (and code) of each element
     const int32_t* ecode;
     const double2* xy;
     const double* aT;
@@ -240,8 +241,11 @@ __device__ inline void store_elements(const AsmArgs& a, int32_t m0, int32_t cnt,
 }
 
 // An element tile: TN consecutive elements, vertices from the element-major
-// coordinate copy.
-template <int TN, bool NT, bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A>
+// coordinate copy (GATHER: through the vertex ids from the node array, 16
+// bytes per element plus cached gathers, which pays on meshes numbered so
+// that neighbouring elements share nodes, e.g. structured ones; the values
+// are the same).
+template <int TN, bool NT, bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A, bool GATHER = false>
 __device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK, double* shD,
                                     double* shA, double* shF)
 {
@@ -250,8 +254,17 @@ __device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK,
     const int32_t nt = min(TN, a.nE - m0);
     if (tid < nt) {
         const int32_t m = m0 + tid;
-        const double2 P0 = a.exy[3 * (int64_t)m], P1 = a.exy[3 * (int64_t)m + 1];
-        const double2 P2 = a.exy[3 * (int64_t)m + 2];
+        double2 P0, P1, P2;
+        if (GATHER) {
+            const int4 v = a.elem4[m];
+            P0 = a.xy[v.x];
+            P1 = a.xy[v.y];
+            P2 = a.xy[v.z];
+        } else {
+            P0 = a.exy[3 * (int64_t)m];
+            P1 = a.exy[3 * (int64_t)m + 1];
+            P2 = a.exy[3 * (int64_t)m + 2];
+        }
         element_values<HAS_AT, MATS, WITH_D, GEN_A>(a, m, P0, P1, P2, tid, shK, shD, shA, shF);
     }
     __syncthreads();
@@ -488,7 +501,8 @@ __device__ inline void element_quad(const AsmArgs& a, int32_t tile)
 // workgroup takes items blockIdx.x, blockIdx.x + gridDim.x, ... (the loop
 // costs about 25 more VGPRs, one wave per SIMD of occupancy). MODE: the
 // element tile's form, 0 staged through LDS (TN triangles), 1 per-thread
-// stores (TN triangles), 2 four lanes per triangle (TN / 4 triangles). The
+// stores (TN triangles), 2 four lanes per triangle (TN / 4 triangles), 3
+// staged with coordinates gathered through the vertex ids. The
 // instance record is staged in LDS. The tile code is the single-mesh
 // kernel's (element tiles read each mesh's own element records), so the
 // outputs are bit-identical to it.
@@ -516,6 +530,9 @@ __global__ __launch_bounds__(TN) void k_assemble_batch(const AsmArgs* __restrict
             row_tile<TN, true, true>(a, ~item.y, shs, shK);
         else if (MODE == 0)
             element_tile<TN, true, HAS_AT, true, WITH_D, GEN_A>(a, item.y, shK, shD, shA, shF);
+        else if (MODE == 3)
+            element_tile<TN, true, HAS_AT, true, WITH_D, GEN_A, true>(a, item.y, shK, shD, shA,
+                                                                     shF);
         else if (MODE == 1)
             element_direct<TN, true, HAS_AT, WITH_D, GEN_A>(a, item.y, shK, shD, shA, shF);
         else
@@ -649,6 +666,7 @@ int make_args(phf_mesh* mesh, const phf_coeffs* co, const phf_data* data, const 
     a.pad_ = 0;
     a.exy = mesh->exy;
     a.pexy = nullptr;
+    a.elem4 = mesh->elem4;
     a.ecode = mesh->ecode;
     a.xy = mesh->xy;
     a.aT = co->a_T;
@@ -765,7 +783,7 @@ struct phf_batch {
     // ([0..2]) or a quarter as many ([3..5], four lanes per triangle)
     int2* d_work[6] = {};
     int32_t nwork[6] = {};
-    int32_t tile = 256, blocks_per_cu = 0, ncu = 256, lanes = 1, direct = 0;
+    int32_t tile = 256, blocks_per_cu = 0, ncu = 256, lanes = 1, direct = 0, gather = 0;
     bool counted = false;  // registered with the meshes and context
 };
 
@@ -834,6 +852,7 @@ int launch_batch_mode(phf_batch* b, int wi, bool hasAT, bool withD, bool genA)
 template <int TN>
 int launch_batch_tn(phf_batch* b, int wi, int mode, bool hasAT, bool withD, bool genA)
 {
+    if (mode == 3) return launch_batch_mode<TN, 3>(b, wi, hasAT, withD, genA);
     if (mode == 2) return launch_batch_mode<TN, 2>(b, wi, hasAT, withD, genA);
     if (mode == 1) return launch_batch_mode<TN, 1>(b, wi, hasAT, withD, genA);
     return launch_batch_mode<TN, 0>(b, wi, hasAT, withD, genA);
@@ -882,7 +901,7 @@ int batch_prepare(phf_batch* b, const phf_coeffs* co, const phf_data* data, cons
 int batch_launch(phf_batch* b, bool hasAT, bool withD, bool genA)
 {
     const int ti = tile_index(b->tile);
-    const int mode = b->lanes == 4 ? 2 : (b->direct ? 1 : 0);
+    const int mode = b->lanes == 4 ? 2 : (b->direct ? 1 : (b->gather ? 3 : 0));
     const int wi = mode == 2 ? 3 + ti : ti;
     TRY(batch_work(b, wi));
     switch (b->tile) {
@@ -960,6 +979,8 @@ extern "C" int phf_batch_get_config(const phf_batch* b, phf_batch_config* cfg)
     cfg->ms = -1.0;
     cfg->lanes = b->lanes;
     cfg->direct = b->direct;
+    cfg->gather = b->gather;
+    cfg->reserved_ = 0;
     return PHF_OK;
 }
 
@@ -969,15 +990,19 @@ extern "C" int phf_batch_set_config(phf_batch* b, const phf_batch_config* cfg)
     const int32_t lanes = cfg->lanes == 0 ? 1 : cfg->lanes;
     if (tile_index(cfg->tile) < 0 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64 ||
         (lanes != 1 && lanes != 4) || (cfg->direct != 0 && cfg->direct != 1) ||
-        ((lanes == 4 || cfg->direct) && cfg->blocks_per_cu != 0))
+        (cfg->gather != 0 && cfg->gather != 1) ||
+        ((lanes == 4 || cfg->direct || cfg->gather) && cfg->blocks_per_cu != 0) ||
+        (lanes == 4 && (cfg->direct || cfg->gather)) || (cfg->direct && cfg->gather))
         return phf_set_error(b->ctx, PHF_EINVAL,
                              "phf_batch_set_config: tile must be 64, 128 or 256, blocks_per_cu "
-                             "0..64 (0 unless lanes = 1 and direct = 0), lanes 1 or 4, direct 0 "
-                             "or 1");
+                             "0..64 (0 unless the tile is staged from element records), lanes 1 "
+                             "or 4, direct and gather 0 or 1, at most one of lanes = 4, direct, "
+                             "gather");
     b->tile = cfg->tile;
     b->blocks_per_cu = cfg->blocks_per_cu;
     b->lanes = lanes;
-    b->direct = lanes == 4 ? 0 : cfg->direct;
+    b->direct = cfg->direct;
+    b->gather = cfg->gather;
     return PHF_OK;
 }
 
@@ -993,20 +1018,21 @@ extern "C" int phf_batch_tune(phf_batch* b, const phf_coeffs* co, const phf_data
     // candidate shapes: staged element tiles with one workgroup per item or a
     // persistent grid; per-thread stores; four lanes per triangle
     struct shape {
-        int32_t tile, bpc, lanes, direct;
+        int32_t tile, bpc, lanes, direct, gather;
     };
     std::vector<shape> shapes;
     for (int32_t tile : {64, 128, 256})
-        for (int32_t bpc : {0, 2, 4, 8}) shapes.push_back({tile, bpc, 1, 0});
-    for (int32_t tile : {64, 128, 256}) shapes.push_back({tile, 0, 1, 1});
-    for (int32_t tile : {64, 128, 256}) shapes.push_back({tile, 0, 4, 0});
+        for (int32_t bpc : {0, 2, 4, 8}) shapes.push_back({tile, bpc, 1, 0, 0});
+    for (int32_t tile : {64, 128, 256}) shapes.push_back({tile, 0, 1, 1, 0});
+    for (int32_t tile : {64, 128, 256}) shapes.push_back({tile, 0, 4, 0, 0});
+    for (int32_t tile : {64, 128, 256}) shapes.push_back({tile, 0, 1, 0, 1});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     PHF_HIP(ctx, hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
         (void)hipEventDestroy(e0);
         return phf_set_error(ctx, PHF_EHIP, "phf_batch_tune: event creation failed");
     }
-    const shape keep{b->tile, b->blocks_per_cu, b->lanes, b->direct};
+    const shape keep{b->tile, b->blocks_per_cu, b->lanes, b->direct, b->gather};
     shape bestc = keep;
     int32_t cnt = 0;
     double best = 1e300;
@@ -1016,6 +1042,7 @@ extern "C" int phf_batch_tune(phf_batch* b, const phf_coeffs* co, const phf_data
         b->blocks_per_cu = sh.bpc;
         b->lanes = sh.lanes;
         b->direct = sh.direct;
+        b->gather = sh.gather;
         rc = batch_launch(b, hasAT, withD, genA);  // warm-up (and work list)
         if (rc) break;
         if (hipEventRecord(e0, ctx->stream) != hipSuccess) {
@@ -1031,7 +1058,8 @@ extern "C" int phf_batch_tune(phf_batch* b, const phf_coeffs* co, const phf_data
             break;
         }
         const double avg = (double)ms / reps;
-        if (results && cnt < max_results) results[cnt] = {sh.tile, sh.bpc, avg, sh.lanes, sh.direct};
+        if (results && cnt < max_results)
+            results[cnt] = {sh.tile, sh.bpc, avg, sh.lanes, sh.direct, sh.gather, 0};
         ++cnt;
         if (avg < best) {
             best = avg;
@@ -1045,12 +1073,14 @@ extern "C" int phf_batch_tune(phf_batch* b, const phf_coeffs* co, const phf_data
         b->blocks_per_cu = keep.bpc;
         b->lanes = keep.lanes;
         b->direct = keep.direct;
+        b->gather = keep.gather;
         return rc;
     }
     b->tile = bestc.tile;
     b->blocks_per_cu = bestc.bpc;
     b->lanes = bestc.lanes;
     b->direct = bestc.direct;
+    b->gather = bestc.gather;
     if (n_results) *n_results = std::min(cnt, max_results);
     return PHF_OK;
 }

@@ -121,7 +121,8 @@ class phf_allocator(ctypes.Structure):
 
 class phf_batch_config(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("ms", ctypes.c_double), ("lanes", ctypes.c_int32), ("direct", ctypes.c_int32)]
+                ("ms", ctypes.c_double), ("lanes", ctypes.c_int32), ("direct", ctypes.c_int32),
+                ("gather", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class phf_server_opts(ctypes.Structure):
@@ -533,8 +534,8 @@ def phf_batch_assemble(batch, coeffs, data, systems):
 
 
 def phf_batch_tune(batch, coeffs, data, systems, reps=5):
-    """Times every launch shape; returns [(tile, blocks_per_cu, lanes, direct, ms)]
-    and keeps the fastest as the batch's configuration."""
+    """Times every launch shape; returns [(tile, blocks_per_cu, lanes, direct,
+    gather, ms)] and keeps the fastest as the batch's configuration."""
     res = (phf_batch_config * 32)()
     n = _I32()
     rc = load().phf_batch_tune(batch, _struct_array(phf_coeffs, coeffs),
@@ -542,21 +543,22 @@ def phf_batch_tune(batch, coeffs, data, systems, reps=5):
                                int(reps), res, 32, ctypes.byref(n))
     if rc < 0:
         raise PhfError(rc, "phf_batch_tune", "")
-    return [(res[i].tile, res[i].blocks_per_cu, res[i].lanes, res[i].direct, res[i].ms)
-            for i in range(n.value)]
+    return [(res[i].tile, res[i].blocks_per_cu, res[i].lanes, res[i].direct, res[i].gather,
+             res[i].ms) for i in range(n.value)]
 
 
 def phf_batch_get_config(batch):
-    """(tile, blocks_per_cu, lanes, direct) of the batch's launch shape."""
+    """(tile, blocks_per_cu, lanes, direct, gather) of the batch's launch shape."""
     c = phf_batch_config()
     rc = load().phf_batch_get_config(batch, ctypes.byref(c))
     if rc < 0:
         raise PhfError(rc, "phf_batch_get_config", "")
-    return c.tile, c.blocks_per_cu, c.lanes, c.direct
+    return c.tile, c.blocks_per_cu, c.lanes, c.direct, c.gather
 
 
-def phf_batch_set_config(batch, tile, blocks_per_cu=0, lanes=1, direct=0):
-    c = phf_batch_config(int(tile), int(blocks_per_cu), 0.0, int(lanes), int(direct))
+def phf_batch_set_config(batch, tile, blocks_per_cu=0, lanes=1, direct=0, gather=0):
+    c = phf_batch_config(int(tile), int(blocks_per_cu), 0.0, int(lanes), int(direct),
+                         int(gather), 0)
     rc = load().phf_batch_set_config(batch, ctypes.byref(c))
     if rc < 0:
         raise PhfError(rc, "phf_batch_set_config", "")

@@ -48,9 +48,10 @@ def test_batch_bit_identical_all_shapes(ctx):
         ref.append(_host(t))
     outs = [phfem.alloc_system(dm, fill=NAN) for dm in meshes]
     b = phfem.phf_batch_create(ctx.handle, [dm.handle for dm in meshes])
-    shapes = [(tile, bpc, 1, 0) for tile in (64, 128, 256) for bpc in (0, 1, 4)]
-    shapes += [(tile, 0, 1, 1) for tile in (64, 128, 256)]  # per-thread stores
-    shapes += [(tile, 0, 4, 0) for tile in (64, 128, 256)]  # four lanes per triangle
+    shapes = [(tile, bpc, 1, 0, 0) for tile in (64, 128, 256) for bpc in (0, 1, 4)]
+    shapes += [(tile, 0, 1, 1, 0) for tile in (64, 128, 256)]  # per-thread stores
+    shapes += [(tile, 0, 4, 0, 0) for tile in (64, 128, 256)]  # four lanes per triangle
+    shapes += [(tile, 0, 1, 0, 1) for tile in (64, 128, 256)]  # gathered coordinates
     try:
         for shape in shapes:
             for s, t in outs:  # poison the outputs
@@ -65,11 +66,13 @@ def test_batch_bit_identical_all_shapes(ctx):
                     assert got[k].tobytes() == ref[i][k].tobytes(), (shape, i, k)
         with pytest.raises(phfem.PhfError):
             phfem.phf_batch_set_config(b, 128, 2, 4, 0)  # persistent grids stage in LDS
+        with pytest.raises(phfem.PhfError):
+            phfem.phf_batch_set_config(b, 128, 0, 1, 1, 1)  # one form at a time
         res = phfem.phf_batch_tune(b, coeffs, data, [s for s, _ in outs], reps=2)
         print("tuning", res, "->", phfem.phf_batch_get_config(b), flush=True)
-        assert len(res) == 18 and all(r[4] > 0 for r in res)
-        best = min(res, key=lambda r: r[4])
-        assert phfem.phf_batch_get_config(b) == best[:4]
+        assert len(res) == 21 and all(r[5] > 0 for r in res)
+        best = min(res, key=lambda r: r[5])
+        assert phfem.phf_batch_get_config(b) == best[:5]
         for i, (s, t) in enumerate(outs):
             got = _host(t)
             for k in KEYS:
@@ -97,7 +100,7 @@ def test_batch_with_D_and_aT_and_oracle(ctx, oracle):
             assert_written(t, dm.info)
             single.append({k: t[k].cpu().numpy() for k in KEYS + ("D",)})
         # staged persistent grid, four lanes per triangle, per-thread stores
-        for shape in ((128, 2, 1, 0), (64, 0, 4, 0), (256, 0, 1, 1)):
+        for shape in ((128, 2, 1, 0, 0), (64, 0, 4, 0, 0), (256, 0, 1, 1, 0), (128, 0, 1, 0, 1)):
             for _, t in outs:
                 for k in KEYS + ("D",):
                     t[k].fill_(np.nan)
