@@ -82,7 +82,7 @@ __global__ __launch_bounds__(NT) void k_cn_keep(int32_t nf, int32_t* __restrict_
 __global__ __launch_bounds__(NT) void k_cn_rhs_elem(
     int32_t nE, const int32_t* __restrict__ ecode, const double* __restrict__ K,
     const double* __restrict__ M, const double* __restrict__ U, const double* __restrict__ Lam,
-    const int32_t* __restrict__ elem_row, const double* __restrict__ row_h,
+    const int32_t* __restrict__ elem_row, const double* __restrict__ row_hs,
     const double* __restrict__ F0, const double* __restrict__ F1, double cM, double cK,
     double hk, double* __restrict__ r1)
 {
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(NT) void k_cn_rhs_elem(
         double v = 0.0;
         if (PHF_CODE_TYPE(code, l) != 2) {
             int32_t r = elem_row[3 * (int64_t)m + l];
-            v = (PHF_CODE_TPLUS(code, l) ? 1.0 : -1.0) * row_h[r] * Lam[r];
+            v = (PHF_CODE_TPLUS(code, l) ? 1.0 : -1.0) * fabs(row_hs[r]) * Lam[r];
         }
         lt[l] = v;
     }
@@ -173,7 +173,7 @@ int cn_step_head(phf_cn* cn, const phf_data* data)
     TRY(cn_loads(cn, data, cn->F1, cn->bD1, true));
     const double cM = 1.0 - 0.5 * cn->k * cn->delta, cK = 0.5 * cn->k, hk = 0.5 * cn->k;
     PHF_LAUNCH(ctx, "k_cn_rhs_elem", k_cn_rhs_elem, nblk(nE), NT, 0, nE, mesh->ecode, cn->K, cn->M,
-               cn->U, cn->Lam, cn->ns->elem_row, cn->ns->row_h, cn->F0, cn->F1, cM, cK, hk, cn->r1);
+               cn->U, cn->Lam, cn->ns->elem_row, cn->mesh->row_hs, cn->F0, cn->F1, cM, cK, hk, cn->r1);
     if (L > 0)
         PHF_LAUNCH(ctx, "k_cn_rhs_row", k_cn_rhs_row, nblk(L), NT, 0, L, mesh->C_rowptr,
                    mesh->C_col, cn->C, cn->U, cn->bD0, cn->bD1, cn->r2);
@@ -353,7 +353,7 @@ extern "C" int phf_cn_create(phf_mesh* mesh, const phf_coeffs* co, double k,
         phf_data d{};
         TRY(phf_assemble_impl(mesh, co, &d, &s));
         TRY(phf_ns_create(mesh, &cn->ns));
-        TRY(phf_ns_operator(cn->ns, cn->K, cn->M, cn->C, 0.5 * k, 1.0 + 0.5 * k * co->delta));
+        TRY(phf_ns_operator(cn->ns, cn->K, cn->M, 0.5 * k, 1.0 + 0.5 * k * co->delta));
         phf_mg_params mp;
         mp.sweeps = cn->opts.mg_sweeps;
         mp.smoother = cn->opts.mg_smoother;

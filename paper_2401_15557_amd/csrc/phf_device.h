@@ -163,59 +163,95 @@ __device__ inline void phf_fn_grad(const phf_fn_dev& f, double x, double y, doub
     }
 }
 
-// Row of free edge e of the reduced (edge-midpoint) operator: e couples with
-// the other free edges of T+ and T-. Writes the columns (ascending) and, per
-// entry, up to two sources in the element blocks B (9T + 3 a + b, -1 none);
-// returns the number of entries (at most 5).
-__device__ inline int phf_reduced_entries(int32_t e, const int2* edge_elems, const int8_t* led,
-                                      const int8_t* ledTN, const int32_t* elem_edges,
-                                      const int32_t* red_row, int32_t* col, int32_t* s0,
-                                      int32_t* s1)
-{
-    int n = 0;
-    int2 tt = edge_elems[e];
-    int lp = led[e];
-    // diagonal: block (lp, lp) of T+ plus (ln, ln) of T-
-    col[n] = red_row[e];
-    s0[n] = 9 * tt.x + 4 * lp;
-    s1[n] = tt.y >= 0 ? 9 * tt.y + 4 * ledTN[e] : -1;
-    ++n;
-    for (int side = 0; side < 2; ++side) {
-        int32_t T = side == 0 ? tt.x : tt.y;
-        if (T < 0) continue;
-        int le = side == 0 ? lp : ledTN[e];
-        for (int o = 0; o < 3; ++o) {
-            if (o == le) continue;
-            int32_t e2 = elem_edges[3 * (int64_t)T + o];
-            int32_t r2 = red_row[e2];
-            if (r2 < 0) continue;
-            col[n] = r2;
-            s0[n] = 9 * T + 3 * le + o;
-            s1[n] = -1;
-            ++n;
-        }
-    }
-    // sort by column (at most 5 entries)
-    for (int a = 1; a < n; ++a) {
-        int32_t c = col[a], x0 = s0[a], x1 = s1[a];
-        int b = a - 1;
-        while (b >= 0 && col[b] > c) {
-            col[b + 1] = col[b];
-            s0[b + 1] = s0[b];
-            s1[b + 1] = s1[b];
-            --b;
-        }
-        col[b + 1] = c;
-        s0[b + 1] = x0;
-        s1[b + 1] = x1;
-    }
-    return n;
-}
-
 // Four-lane vectors for 16-byte row loads and stores.
 typedef int32_t phf_i4 __attribute__((ext_vector_type(4)));
 typedef float phf_f4 __attribute__((ext_vector_type(4)));
 typedef double phf_d2 __attribute__((ext_vector_type(2)));
+
+// Half-row records of the reduced (edge-midpoint) operator. Row r (a free
+// edge) couples with the other free edges of its two triangles; each
+// triangle T contributes one record to it, stored in element order at
+// 3 T + l (l the row edge's local index in T): the reduced columns of T's
+// two other local edges o1 < o2 (-1 where Dirichlet), the entries
+// B_T[l][o1], B_T[l][o2] of T's block B_T = P^T A_T P, and B_T[l][l], its
+// part of the diagonal. Layout, 32 bytes: two int32 columns and the first
+// value as one 16-byte unit, the second value and the diagonal part as the
+// next.
+__device__ inline void phf_hrec_store(phf_i4* __restrict__ rec, int64_t slot, int32_t c1,
+                                      int32_t c2, double v1, double v2, double d)
+{
+    const long long b = __double_as_longlong(v1);
+    rec[2 * slot] = phf_i4{c1, c2, (int32_t)(b & 0xffffffffLL), (int32_t)(b >> 32)};
+    *reinterpret_cast<phf_d2*>(rec + 2 * slot + 1) = phf_d2{v2, d};
+}
+
+// The records of element m (its block Bm, row-major, and the reduced rows
+// red[] of its local edges; none for a Dirichlet local edge).
+__device__ inline void phf_hrec_element(phf_i4* __restrict__ rec, int64_t m, const int32_t red[3],
+                                        const double Bm[9])
+{
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if (red[l] < 0) continue;
+        const int o1 = l == 0 ? 1 : 0, o2 = l == 2 ? 1 : 2;
+        phf_hrec_store(rec, 3 * m + l, red[o1], red[o2], Bm[3 * l + o1], Bm[3 * l + o2],
+                       Bm[4 * l]);
+    }
+}
+
+// Row r (free edge e) from the records of its T+ and T- (tt, with the edge's
+// local indices lp, ln; no T-: a boundary edge) as five (column, value)
+// slots: the diagonal (the two parts summed) and the off-diagonal entries,
+// sorted by column, then the unused slots (column r, value 0); returns the
+// number of entries. An off-diagonal value is its one source plus zero, and
+// a boundary row's diagonal its T+ part plus zero, as when each entry sums
+// its sources over both sides with zero for an absent one. The columns are
+// distinct, so a fixed five-input sorting network gives the unique order.
+__device__ inline int phf_hrec_row(int32_t r, int2 tt, int lp, int ln,
+                                   const phf_i4* __restrict__ rec, int32_t col[5], double v[5])
+{
+    const int64_t pa = 2 * (3 * (int64_t)tt.x + lp);
+    const phf_i4 a0 = rec[pa];
+    const phf_d2 a1 = *reinterpret_cast<const phf_d2*>(rec + pa + 1);
+    phf_i4 b0 = phf_i4{-1, -1, 0, 0};
+    phf_d2 b1 = phf_d2{0.0, 0.0};
+    if (tt.y >= 0) {
+        const int64_t pb = 2 * (3 * (int64_t)tt.y + ln);
+        b0 = rec[pb];
+        b1 = *reinterpret_cast<const phf_d2*>(rec + pb + 1);
+    }
+    auto first = [](const phf_i4 u) {
+        return __longlong_as_double(((long long)u.w << 32) | (long long)(uint32_t)u.z);
+    };
+    constexpr int32_t NONE = 0x7fffffff;  // sorts after every column
+    const int32_t cc[4] = {a0.x, a0.y, b0.x, b0.y};
+    const double vv[4] = {first(a0), a1.x, first(b0), b1.x};
+    col[0] = r;
+    v[0] = a1.y + b1.y;
+    int n = 1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool used = cc[k] >= 0;
+        col[k + 1] = used ? cc[k] : NONE;
+        v[k + 1] = used ? vv[k] + 0.0 : 0.0;
+        n += used ? 1 : 0;
+    }
+    auto cx = [&](int i, int j) {
+        if (col[i] > col[j]) {
+            const int32_t c = col[i];
+            col[i] = col[j];
+            col[j] = c;
+            const double x = v[i];
+            v[i] = v[j];
+            v[j] = x;
+        }
+    };
+    cx(0, 1); cx(3, 4); cx(2, 4); cx(2, 3); cx(1, 4); cx(0, 3); cx(0, 2); cx(1, 3); cx(1, 2);
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+        if (col[k] == NONE) col[k] = r;
+    return n;
+}
 
 // Single-precision scaled copy of row r of a reduced operator given as five
 // (column, value) slots, unused ones holding column r and value 0: the

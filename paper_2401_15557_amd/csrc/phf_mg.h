@@ -76,15 +76,15 @@ struct phf_mg_setup_level {
     const int32_t* red_edge = nullptr;  // this level's mesh tables
     const int2* edge_elems = nullptr;
     const int8_t *led = nullptr, *ledTN = nullptr;
-    const int32_t *elem_edges = nullptr, *red_row = nullptr;
-    const int32_t *elem_edges_c = nullptr, *red_row_c = nullptr, *red_edge_c = nullptr;  // coarser
+    const int32_t* elem_red = nullptr;  // reduced rows of the elements' local edges
+    const int32_t *elem_red_c = nullptr, *red_edge_c = nullptr;  // coarser
     const int2* edge_elems_c = nullptr;
     const int8_t *led_c = nullptr, *ledTN_c = nullptr;
     int32_t* P_col = nullptr;  // outputs of the tables
     uint32_t* P_code = nullptr;
     int32_t* rows9 = nullptr;
     int2* sel_c = nullptr;
-    const double* B = nullptr;  // operator: element blocks (coarse levels) or
+    const int32_t* rec = nullptr;  // operator: half-row records (coarse levels) or
     // the caller's double-precision rows (finest): off-diagonal columns and
     // values as row-major ELL-4, then the nf diagonal values behind the values
     const int32_t* ell_col = nullptr;
@@ -100,8 +100,9 @@ struct phf_mg_level {
     phf_ns* ns = nullptr;       // the caller's operator (finest level only)
     int32_t nf = 0;
     // coarse levels: triangle coefficient (averaged from the finer level)
-    // and element blocks B_T = P^T A_T P of the re-discretised operator
-    double *aT = nullptr, *B = nullptr;
+    // and the half-row records of the re-discretised operator (24 nE)
+    double* aT = nullptr;
+    int32_t* rec = nullptr;
     // single-precision scaled operator: the off-diagonal entries of D^-1 A
     // (ELL-4, row-major; unused slots hold the row itself and 0), the
     // diagonal D and its inverse. The finest level's columns are the caller's

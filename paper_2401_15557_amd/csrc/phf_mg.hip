@@ -42,8 +42,8 @@ __device__ inline int32_t parent_of(int32_t m, int32_t nEc)
 __device__ inline void d_mg_prolong_build(int32_t rf, 
     int32_t nf_f, int32_t nEc, const int32_t* __restrict__ red_edge_f,
     const int2* __restrict__ edge_elems_f, const int8_t* __restrict__ led_f,
-    const int8_t* __restrict__ ledTN_f, const int32_t* __restrict__ elem_edges_c,
-    const int32_t* __restrict__ red_row_c, int32_t* __restrict__ P_col, uint32_t* __restrict__ P_code)
+    const int8_t* __restrict__ ledTN_f, const int32_t* __restrict__ elem_red_c,
+    int32_t* __restrict__ P_col, uint32_t* __restrict__ P_code)
 {
     if (rf >= nf_f) return;
     const int32_t e = red_edge_f[rf];
@@ -74,7 +74,7 @@ __device__ inline void d_mg_prolong_build(int32_t rf,
         }
         for (int k = 0; k < 3; ++k) {
             if (w[k] == 0.0f) continue;
-            const int32_t rc = red_row_c[elem_edges_c[3 * (int64_t)p + k]];
+            const int32_t rc = elem_red_c[3 * (int64_t)p + k];
             if (rc < 0) continue;
             int q = 0;
             while (q < n && col[q] != rc) ++q;
@@ -109,17 +109,15 @@ __device__ inline float prolong_weight(uint32_t code, int k)
 //   slot 4 + 2i         half of coarse edge i+2 at vertex v_i.
 // The centre child of p is element p = [M0 M1 M2], corner child i is
 // nEc + 3p + i = [v_i M_(i+2) M_(i+1)] (M_j the midpoint of coarse edge j).
-__device__ inline void d_mg_rows9(int32_t p, int32_t nEc, const int32_t* __restrict__ elem_edges_f,
-                                                 const int32_t* __restrict__ red_row_f,
-                                                 int32_t* __restrict__ rows9)
+__device__ inline void d_mg_rows9(int32_t p, int32_t nEc, const int32_t* __restrict__ elem_red_f,
+                                  int32_t* __restrict__ rows9)
 {
     if (p >= nEc) return;
-    for (int j = 0; j < 3; ++j)
-        rows9[(int64_t)j * nEc + p] = red_row_f[elem_edges_f[3 * (int64_t)p + j]];
+    for (int j = 0; j < 3; ++j) rows9[(int64_t)j * nEc + p] = elem_red_f[3 * (int64_t)p + j];
     for (int i = 0; i < 3; ++i) {
         const int64_t ch = (int64_t)nEc + 3 * (int64_t)p + i;
-        rows9[(int64_t)(3 + 2 * i) * nEc + p] = red_row_f[elem_edges_f[3 * ch + 1]];
-        rows9[(int64_t)(4 + 2 * i) * nEc + p] = red_row_f[elem_edges_f[3 * ch + 2]];
+        rows9[(int64_t)(3 + 2 * i) * nEc + p] = elem_red_f[3 * ch + 1];
+        rows9[(int64_t)(4 + 2 * i) * nEc + p] = elem_red_f[3 * ch + 2];
     }
 }
 
@@ -361,17 +359,18 @@ __device__ inline void row_coarse(int32_t i, int32_t n, PA __restrict__ Ainv, PD
 // Element blocks of a coarse level's re-discretised operator,
 // B_T = P^T (cK K_T + cM M_T) P with K_T = a_T |T| (A grad lambda_j) . grad
 // lambda_i and the unit mass M_T = |T|/12 (1 + delta_ij) (Definition 3.1),
-// straight from the element coordinates. The tile's blocks are staged in LDS
-// and stored coalesced.
+// straight from the element coordinates, written as the level's half-row
+// records (phf_hrec_element; staged in LDS, stored as one run per tile).
 // aT_f: the next finer level's triangle coefficient (null: 1); the level's
 // own, the average over the four children, is written to aT.
 __global__ __launch_bounds__(NT) void k_mg_cblocks(int32_t nE, const double2* __restrict__ exy,
+                                                   const int32_t* __restrict__ elem_red,
                                                    const double* __restrict__ aT_f,
                                                    double* __restrict__ aT, double A00,
                                                    double A01, double A10, double A11, double cK,
-                                                   double cM, double* __restrict__ B)
+                                                   double cM, phf_i4* __restrict__ rec)
 {
-    __shared__ double sB[9 * NT];
+    __shared__ __align__(16) phf_i4 srec[6 * NT];
     const int tid = threadIdx.x;
     const int64_t m0 = (int64_t)blockIdx.x * NT;
     const int32_t nt = (int32_t)min((int64_t)NT, (int64_t)nE - m0);
@@ -406,40 +405,41 @@ __global__ __launch_bounds__(NT) void k_mg_cblocks(int32_t nE, const double2* __
 #pragma unroll
             for (int l = 0; l < 3; ++l) AP[3 * i + l] = rs - 2.0 * A[3 * i + l];
         }
+        double Bm[9];
 #pragma unroll
         for (int lp = 0; lp < 3; ++lp) {
             const double cs = AP[lp] + AP[3 + lp] + AP[6 + lp];
 #pragma unroll
-            for (int l = 0; l < 3; ++l) sB[9 * tid + 3 * l + lp] = cs - 2.0 * AP[3 * l + lp];
+            for (int l = 0; l < 3; ++l) Bm[3 * l + lp] = cs - 2.0 * AP[3 * l + lp];
         }
+        const int32_t red[3] = {elem_red[3 * m], elem_red[3 * m + 1], elem_red[3 * m + 2]};
+        phf_hrec_element(srec, tid, red, Bm);
     }
     __syncthreads();
-    for (int32_t q = tid; q < 9 * nt; q += NT) B[9 * m0 + q] = sB[q];
+    for (int32_t q = tid; q < 6 * nt; q += NT) rec[6 * m0 + q] = srec[q];
 }
 
-// Coarse-level rows of the reduced operator: the ELL-5 entries of row r
-// (columns sorted, values B[s0] + B[s1]) scaled straight into the cycle's
-// rows by phf_scale_row (off-diagonals of D^-1 A in ELL-4, the diagonal and
-// its inverse); returns the row's Gershgorin sum. With col64 and val64 (the
+// Coarse-level rows of the reduced operator: the five (column, value) slots
+// of row r from its half-row records, scaled straight into the cycle's rows
+// by phf_scale_row (off-diagonals of D^-1 A in ELL-4, the diagonal and its
+// inverse); returns the row's Gershgorin sum. With col64 and val64 (the
 // coarsest level) also the double-precision ELL-5 rows.
-__device__ inline float d_mg_crows(int32_t r, 
-    int32_t nf, const int32_t* __restrict__ red_edge, const int2* __restrict__ edge_elems,
-    const int8_t* __restrict__ led, const int8_t* __restrict__ ledTN,
-    const int32_t* __restrict__ elem_edges, const int32_t* __restrict__ red_row,
-    const double* __restrict__ B, int32_t* __restrict__ col4, float* __restrict__ val4,
-    float* __restrict__ diag, float* __restrict__ dinv, int32_t* __restrict__ col64,
-    double* __restrict__ val64)
+__device__ inline float d_mg_crows(int32_t r, int32_t nf, const int32_t* __restrict__ red_edge,
+                                   const int2* __restrict__ edge_elems,
+                                   const int8_t* __restrict__ led, const int8_t* __restrict__ ledTN,
+                                   const phf_i4* __restrict__ rec,
+                                   int32_t* __restrict__ col4, float* __restrict__ val4,
+                                   float* __restrict__ diag, float* __restrict__ dinv,
+                                   int32_t* __restrict__ col64, double* __restrict__ val64)
 {
     if (r >= nf) return 0.0f;
-    int32_t col[5], s0[5], s1[5];
-    const int n = phf_reduced_entries(red_edge[r], edge_elems, led, ledTN, elem_edges, red_row,
-                                      col, s0, s1);
+    int32_t col[5];
     double v[5];
+    const int32_t e = red_edge[r];
+    phf_hrec_row(r, edge_elems[e], led[e], ledTN[e], rec, col, v);
+    if (col64) {
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        v[k] = k < n ? B[s0[k]] + (s1[k] >= 0 ? B[s1[k]] : 0.0) : 0.0;
-        if (k >= n) col[k] = r;
-        if (col64) {
+        for (int k = 0; k < 5; ++k) {
             col64[(int64_t)k * nf + r] = col[k];
             val64[(int64_t)k * nf + r] = v[k];
         }
@@ -808,9 +808,9 @@ __global__ __launch_bounds__(NT) void k_mg_setup_tables(const phf_mg_setup_level
     const int32_t t = threadIdx.x;
     if (b < L.b[1]) {
         d_mg_prolong_build((b - L.b[0]) * NT + t, L.nf, L.nEc, L.red_edge, L.edge_elems, L.led,
-                           L.ledTN, L.elem_edges_c, L.red_row_c, L.P_col, L.P_code);
+                           L.ledTN, L.elem_red_c, L.P_col, L.P_code);
     } else if (b < L.b[2]) {
-        d_mg_rows9((b - L.b[1]) * NT + t, L.nEc, L.elem_edges, L.red_row, L.rows9);
+        d_mg_rows9((b - L.b[1]) * NT + t, L.nEc, L.elem_red, L.rows9);
     } else {
         d_mg_sel((b - L.b[2]) * NT + t, L.nc, L.red_edge_c, L.edge_elems_c, L.led_c, L.ledTN_c,
                  L.sel_c);
@@ -829,9 +829,10 @@ __global__ __launch_bounds__(NT) void k_mg_setup_rows(const phf_mg_setup_level* 
     float m = 0.0f;  // Gershgorin bound of D^-1 A over this block's rows
     for (int32_t r = (blockIdx.x - L.b[3]) * NT + threadIdx.x; r < L.nf; r += nb * NT) {
         float s;  // 1 + sum_j |a_ij| / a_ii
-        if (L.B) {
-            s = d_mg_crows(r, L.nf, L.red_edge, L.edge_elems, L.led, L.ledTN, L.elem_edges,
-                           L.red_row, L.B, L.col4, L.val4, L.diag, L.dinv, L.col64, L.val64);
+        if (L.rec) {
+            s = d_mg_crows(r, L.nf, L.red_edge, L.edge_elems, L.led, L.ledTN,
+                           reinterpret_cast<const phf_i4*>(L.rec), L.col4, L.val4, L.diag,
+                           L.dinv, L.col64, L.val64);
         } else {  // the finest level, from the caller's double-precision rows
             // (diagonal, then the four off-diagonal entries; the columns are
             // shared with the caller and already in place)
@@ -915,7 +916,7 @@ void phf_mg_destroy(phf_mg* mg)
     for (int l = 0; l < mg->nlev; ++l) {
         phf_mg_level& L = mg->lev[l];
         phf_dfree(L.aT);
-        phf_dfree(L.B);
+        phf_dfree(L.rec);
         float* f[] = {L.val4, L.diag32, L.dinv32, L.x, L.y, L.b, L.r, L.t};
         for (float* p : f) phf_dfree(p);
         phf_dfree(L.P_code);
@@ -958,7 +959,8 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             if (l == nlev - 1) {
                 L.ns = fine;
             } else {
-                TRY(phf_dmalloc(ctx, &L.B, 9 * (size_t)ms->nE, "multigrid element blocks"));
+                TRY(phf_dmalloc(ctx, &L.rec, 24 * (size_t)std::max<int32_t>(ms->nE, 1),
+                                "multigrid half-row records"));
                 TRY(phf_dmalloc(ctx, &L.aT, (size_t)ms->nE, "multigrid coefficient"));
             }
             L.nf = ms->n_free;
@@ -1060,8 +1062,7 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             d.edge_elems = ms->edge_elems;
             d.led = ms->led;
             d.ledTN = ms->ledTN;
-            d.elem_edges = ms->elem_edges;
-            d.red_row = ms->red_row;
+            d.elem_red = ms->elem_red;
             d.col4 = L.col4;
             d.val4 = L.val4;
             d.diag = L.diag32;
@@ -1070,7 +1071,7 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
                 d.ell_col = fine->ell_col;
                 d.ell_val = fine->ell_val;
             } else {
-                d.B = L.B;
+                d.rec = L.rec;
             }
             if (l == 0 && mg->cinv) {
                 d.col64 = mg->col64;
@@ -1084,8 +1085,7 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             const phf_mesh* mc = Cl.mesh;
             d.nEc = mc->nE;
             d.nc = Cl.nf;
-            d.elem_edges_c = mc->elem_edges;
-            d.red_row_c = mc->red_row;
+            d.elem_red_c = mc->elem_red;
             d.red_edge_c = mc->red_edge;
             d.edge_elems_c = mc->edge_elems;
             d.led_c = mc->led;
@@ -1138,7 +1138,8 @@ int phf_mg_numeric(phf_mg* mg, const phf_coeffs* co, double cK, double cM)
         phf_mg_level& L = mg->lev[l];
         const phf_mesh* ms = L.mesh;
         PHF_LAUNCH(ctx, "k_mg_cblocks", k_mg_cblocks, nblk(ms->nE), NT, 0, ms->nE, ms->exy,
-                   aT_prev, L.aT, co->A[0], co->A[1], co->A[2], co->A[3], cK, cM, L.B);
+                   ms->elem_red, aT_prev, L.aT, co->A[0], co->A[1], co->A[2], co->A[3], cK, cM,
+                   reinterpret_cast<phf_i4*>(L.rec));
         if (aT_prev) aT_prev = L.aT;
     }
     // every level's scaled single-precision rows (coarse levels from their

@@ -45,10 +45,11 @@ struct phf_ns {
     const int32_t* elem_red = nullptr;  // 3 nE: reduced row of local edge l (-1 Dirichlet)
     const int32_t* elem_row = nullptr;  // 3 nE: multiplier row of local edge l (-1 Neumann)
     int32_t* ell_col = nullptr;   // 4 nf: off-diagonal columns of R, row-major ELL-4
-    double* row_h = nullptr;      // L: |E|/2 of each multiplier row
     // numeric
-    double* B = nullptr;          // 9 nE: P^T A_T P
-    double* Ablk = nullptr;       // 9 nE: A_T
+    int32_t* rec = nullptr;       // 24 nE: half-row records of the reduced operator
+                                  // (32 bytes per element and local edge, phf_hrec_row)
+    double* Ablk = nullptr;       // 9 nE: A_T (allocated when A is not K itself)
+    const double* A = nullptr;    // the element blocks A_T of the current operator
     double* ell_val = nullptr;    // 5 nf: the 4 nf off-diagonal values, then the diagonal
     double* dinv = nullptr;       // nf
     double* kv = nullptr;         // 3 nE known midpoint values / jumps
@@ -75,10 +76,14 @@ enum { NS_RR = 0, NS_BB, NS_TOL2, NS_NSCAL = 8 };
 
 int phf_ns_create(phf_mesh* mesh, phf_ns** out);
 void phf_ns_destroy(phf_ns* ns);
-// Builds A_T, B, the ELL values, the Jacobi diagonal for A = cK K + cD D + cM M,
-// and |E|/2 per multiplier row from the assembled C.
-int phf_ns_operator(phf_ns* ns, const double* K, const double* M, const double* C, double cK,
-                    double cM, const double* D = nullptr, double cD = 0.0);
+// Builds A_T, the half-row records, the ELL values and the Jacobi diagonal
+// for A = cK K + cD D + cM M. borrow_K: with A = K (cK = 1, no M or D term)
+// the solver reads the element blocks from K itself, which the caller keeps
+// unchanged until the last phf_ns_rhs / phf_ns_recover of this operator.
+// The multiplier scaling |E|/2 is the mesh's (the value phf_assemble writes
+// into C).
+int phf_ns_operator(phf_ns* ns, const double* K, const double* M, double cK, double cM,
+                    const double* D = nullptr, double cD = 0.0, bool borrow_K = false);
 // Right-hand side reduction (rhs2 is the right-hand side of -C U = rhs2).
 int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2);
 // Starts CG from the current w, or with zero_start from w = 0 (written by

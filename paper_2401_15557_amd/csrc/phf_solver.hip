@@ -20,27 +20,40 @@ __device__ inline void apply_P(const double w[3], double U[3])
     U[2] = s - 2.0 * w[2];
 }
 
-// A_T = cK K_T + cD D_T + cM M_T (D nullable) and B_T = P^T A_T P; A_T need
-// not be symmetric. A tile of NT elements is staged in LDS so that the
-// 9-value element rows are read and written with coalesced accesses.
-__global__ __launch_bounds__(NT) void k_ns_blocks(int32_t nE, const double* __restrict__ K,
-                                                  const double* __restrict__ M,
-                                                  const double* __restrict__ D, double cK,
-                                                  double cM, double cD, double* __restrict__ Ablk,
-                                                  double* __restrict__ B)
+// A_T = cK K_T + cM M_T + cD D_T (M, D nullable) for a tile of NT elements,
+// staged in LDS so that the 9-value element blocks are read (and, with Ablk,
+// stored) with coalesced accesses; then each element's B_T = P^T A_T P
+// (A_T need not be symmetric) and its half-row records of the reduced
+// operator (phf_hrec_element), staged in LDS as well and stored as one
+// contiguous run per tile. (A Dirichlet local edge's record is not formed;
+// its slot is stored unset and never read.)
+__global__ __launch_bounds__(NT) void k_ns_elem(int32_t nE, const double* __restrict__ K,
+                                                const double* __restrict__ M,
+                                                const double* __restrict__ D, double cK,
+                                                double cM, double cD,
+                                                const int32_t* __restrict__ elem_red,
+                                                double* __restrict__ Ablk,
+                                                phf_i4* __restrict__ rec)
 {
-    __shared__ double sA[NT * 9], sB[NT * 9];
+    // the tile's blocks A_T, then (same space) its records, 6 units each
+    __shared__ __align__(16) phf_i4 smem[6 * NT];
+    double* sA = reinterpret_cast<double*>(smem);
     const int tid = threadIdx.x;
     const int64_t m0 = (int64_t)blockIdx.x * NT;
     const int32_t nt = (int32_t)min((int64_t)NT, (int64_t)nE - m0);
-    const int32_t cnt = 9 * nt;
-    for (int32_t q = tid; q < cnt; q += NT) {
-        double a = cK * K[9 * m0 + q] + cM * M[9 * m0 + q];
-        if (D) a += cD * D[9 * m0 + q];
+    for (int32_t q = tid; q < 9 * nt; q += NT) {
+        const int64_t g = 9 * m0 + q;
+        double a = M ? cK * K[g] + cM * M[g] : cK * K[g];
+        if (D) a += cD * D[g];
         sA[q] = a;
     }
     __syncthreads();
+    if (Ablk)
+        for (int32_t q = tid; q < 9 * nt; q += NT) Ablk[9 * m0 + q] = sA[q];
+    double Bm[9];
+    int32_t red[3] = {-1, -1, -1};
     if (tid < nt) {
+        const int64_t m = m0 + tid;
         const double* A = sA + 9 * tid;
         // AP[i][l] = rowsum_i(A) - 2 A[i][l]
         double AP[9];
@@ -55,54 +68,45 @@ __global__ __launch_bounds__(NT) void k_ns_blocks(int32_t nE, const double* __re
         for (int lp = 0; lp < 3; ++lp) {
             const double cs = AP[lp] + AP[3 + lp] + AP[6 + lp];
 #pragma unroll
-            for (int l = 0; l < 3; ++l) sB[9 * tid + 3 * l + lp] = cs - 2.0 * AP[3 * l + lp];
+            for (int l = 0; l < 3; ++l) Bm[3 * l + lp] = cs - 2.0 * AP[3 * l + lp];
         }
+#pragma unroll
+        for (int l = 0; l < 3; ++l) red[l] = elem_red[3 * m + l];
     }
+    __syncthreads();  // (the records overwrite the blocks)
+    if (tid < nt) phf_hrec_element(smem, tid, red, Bm);
     __syncthreads();
-    for (int32_t q = tid; q < cnt; q += NT) {
-        Ablk[9 * m0 + q] = sA[q];
-        B[9 * m0 + q] = sB[q];
-    }
+    for (int32_t q = tid; q < 6 * nt; q += NT) rec[6 * m0 + q] = smem[q];
 }
 
-// Rows of the reduced operator straight from the edge tables and the element
-// blocks B (values B[s0] + B[s1] of each entry's sources): the diagonal, and
+// Rows of the reduced operator from the half-row records: the diagonal, and
 // the off-diagonal entries in ascending column order as ELL-4, row-major
 // (ell_col[4r..4r+3] int32, ell_val[4r..4r+3] double; unused entries column
-// r, value 0), the diagonal values behind them at ell_val[4 nf + r], and the
-// inverse diagonal (1 where it is not positive). With FINE also the
-// multigrid preconditioner's finest-level rows (phf_scale_row, from the same
-// values; they share the columns) and their Gershgorin bound.
+// r, value 0), the diagonal values behind them at ell_val[4 nf + r], and
+// either the inverse diagonal (1 where it is not positive) or, with FINE,
+// the multigrid preconditioner's finest-level rows (phf_scale_row, from the
+// same values; they share the columns) and their Gershgorin bound.
 template <bool FINE>
-__global__ __launch_bounds__(NT) void k_ns_ellval(int32_t nf, const int32_t* __restrict__ red_edge,
-                                                  const int2* __restrict__ edge_elems,
-                                                  const int8_t* __restrict__ led,
-                                                  const int8_t* __restrict__ ledTN,
-                                                  const int32_t* __restrict__ elem_edges,
-                                                  const int32_t* __restrict__ red_row,
-                                                  const double* __restrict__ B,
-                                                  int32_t* __restrict__ ell_col,
-                                                  double* __restrict__ ell_val,
-                                                  double* __restrict__ dinv, phf_mg_rows fr)
+__global__ __launch_bounds__(NT) void k_ns_ellrows(int32_t nf, const int32_t* __restrict__ red_edge,
+                                                   const int2* __restrict__ edge_elems,
+                                                   const int8_t* __restrict__ led,
+                                                   const int8_t* __restrict__ ledTN,
+                                                   const phf_i4* __restrict__ rec,
+                                                   int32_t* __restrict__ ell_col,
+                                                   double* __restrict__ ell_val,
+                                                   double* __restrict__ dinv, phf_mg_rows fr)
 {
     const int32_t r = blockIdx.x * NT + threadIdx.x;
     float gs = 0.0f;  // Gershgorin sum of the row (FINE)
     if (r < nf) {
-        int32_t col[5], s0[5], s1[5];
-        const int n = phf_reduced_entries(red_edge[r], edge_elems, led, ledTN, elem_edges,
-                                          red_row, col, s0, s1);
+        int32_t col[5];
         double v[5];
+        const int32_t e = red_edge[r];
+        const int n = phf_hrec_row(r, edge_elems[e], led[e], ledTN[e], rec, col, v);
         double d = 0.0;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            if (k < n) {
-                v[k] = B[s0[k]] + (s1[k] >= 0 ? B[s1[k]] : 0.0);
-                if (col[k] == r) d = v[k];
-            } else {
-                col[k] = r;
-                v[k] = 0.0;
-            }
-        }
+        for (int k = 0; k < 5; ++k)
+            if (k < n && col[k] == r) d = v[k];
         int32_t c4[4] = {r, r, r, r};
         double v4[4] = {0.0, 0.0, 0.0, 0.0};
         int q = 0;
@@ -117,7 +121,8 @@ __global__ __launch_bounds__(NT) void k_ns_ellval(int32_t nf, const int32_t* __r
         *(phf_d2*)(ell_val + 4 * (int64_t)r) = phf_d2{v4[0], v4[1]};
         *(phf_d2*)(ell_val + 4 * (int64_t)r + 2) = phf_d2{v4[2], v4[3]};
         ell_val[4 * (int64_t)nf + r] = d;
-        dinv[r] = d > 0.0 ? 1.0 / d : 1.0;
+        // (the Jacobi preconditioner's; the multigrid one scales its own rows)
+        if (!FINE) dinv[r] = d > 0.0 ? 1.0 / d : 1.0;
         if (FINE) gs = phf_scale_row(r, nf, col, v, fr.col4, fr.val4, fr.diag, fr.dinv);
     }
     if (FINE) {
@@ -139,15 +144,6 @@ __global__ __launch_bounds__(NT) void k_ns_ellval(int32_t nf, const int32_t* __r
                 atomicMax(fr.lmax, bits);
         }
     }
-}
-
-__global__ __launch_bounds__(NT) void k_ns_rowh(int32_t L, const int32_t* __restrict__ C_rowptr,
-                                                const double* __restrict__ C,
-                                                double* __restrict__ row_h)
-{
-    int32_t r = blockIdx.x * NT + threadIdx.x;
-    if (r >= L) return;
-    row_h[r] = C[C_rowptr[r]];
 }
 
 // Element records of a tile of NT elements (W values each, element-major)
@@ -173,54 +169,58 @@ __global__ __launch_bounds__(NT) void k_ns_jumpflag(int32_t L, const int2* __res
 {
     int any = 0;
     for (int32_t r = blockIdx.x * NT + threadIdx.x; r < L; r += gridDim.x * NT)
-        any |= row_nodes[r].x >= 0 && rhs2[r] != 0.0;
+        if (rhs2[r] != 0.0) any |= row_nodes[r].x >= 0;
     if (__syncthreads_or(any) && threadIdx.x == 0) *jflag = 1;
 }
 
 // Known midpoint values (Dirichlet) and T+-side jumps (interior rows with a
 // non-zero right-hand side; gathered only when *jflag is raised), and the
 // element part of the reduced rhs,
-// c_T = P^T (rhs1_T - A_T P kv_T). Element records go through LDS.
+// c_T = P^T (rhs1_T - A_T P kv_T). Where kv_T = 0 (most elements: no known
+// value on their edges) the product is zero and A_T is not read. The
+// element rows of rhs1, kv and c go through LDS.
 __global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int32_t* __restrict__ ecode,
                                                  const int32_t* __restrict__ elem_row,
-                                                 const double* __restrict__ row_h,
+                                                 const double* __restrict__ row_hs,
                                                  const double* __restrict__ rhs1,
                                                  const double* __restrict__ rhs2,
-                                                 const double* __restrict__ Ablk,
+                                                 const double* __restrict__ A,
                                                  const int* __restrict__ jflag,
                                                  double* __restrict__ kv, double* __restrict__ cs)
 {
-    __shared__ double sA[9 * NT], sR[3 * NT], sK[3 * NT], sC[3 * NT];
+    __shared__ double sR[3 * NT], sK[3 * NT], sC[3 * NT];
     const bool jumps = *jflag != 0;
-    __shared__ int32_t sRow[3 * NT];
     const int tid = threadIdx.x;
     const int64_t m0 = (int64_t)blockIdx.x * NT;
     const int32_t nt = (int32_t)min((int64_t)NT, (int64_t)nE - m0);
-    tile_load<9>(Ablk, m0, nt, sA);
     tile_load<3>(rhs1, m0, nt, sR);
-    tile_load<3>(elem_row, m0, nt, sRow);
     __syncthreads();
     if (tid < nt) {
-        const int code = ecode[m0 + tid];
+        const int64_t m = m0 + tid;
+        const int code = ecode[m];
         double k3[3];
+        bool known = false;
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             const int t = PHF_CODE_TYPE(code, l);
             double v = 0.0;
             if (t == 1 || (jumps && t == 0 && PHF_CODE_TPLUS(code, l))) {
-                const int32_t r = sRow[3 * tid + l];
-                v = -rhs2[r] / (2.0 * row_h[r]);
+                const int32_t r = elem_row[3 * m + l];
+                v = -rhs2[r] / (2.0 * fabs(row_hs[r]));
+                known |= v != 0.0;
             }
             k3[l] = v;
             sK[3 * tid + l] = v;
         }
-        double Ub[3];
-        apply_P(k3, Ub);
-        double res[3];
+        double res[3] = {sR[3 * tid], sR[3 * tid + 1], sR[3 * tid + 2]};
+        if (known) {
+            double Ub[3];
+            apply_P(k3, Ub);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const double* a = sA + 9 * tid + 3 * i;
-            res[i] = sR[3 * tid + i] - (a[0] * Ub[0] + a[1] * Ub[1] + a[2] * Ub[2]);
+            for (int i = 0; i < 3; ++i) {
+                const double* a = A + 9 * m + 3 * i;
+                res[i] -= a[0] * Ub[0] + a[1] * Ub[1] + a[2] * Ub[2];
+            }
         }
         double c[3];
         apply_P(res, c);  // P is symmetric, so P^T v = P v
@@ -558,12 +558,13 @@ __global__ __launch_bounds__(NT) void k_cg_check(int32_t nb, const double* __res
 
 // ---- recovery -------------------------------------------------------------
 
-// U_T = P (w_T + kv_T) and the element residual P^T (A_T U_T - rhs1_T) from
-// which the multipliers follow.
+// U_T = P (w_T + kv_T) and (MU) the element residual P^T (A_T U_T - rhs1_T)
+// from which the multipliers follow.
+template <bool MU>
 __global__ __launch_bounds__(NT) void k_ns_recover_u(int32_t nE, const int32_t* __restrict__ elem_red,
                                                      const double* __restrict__ w,
                                                      const double* __restrict__ kv,
-                                                     const double* __restrict__ Ablk,
+                                                     const double* __restrict__ A,
                                                      const double* __restrict__ rhs1,
                                                      double* __restrict__ U,
                                                      double* __restrict__ cs)
@@ -578,11 +579,13 @@ __global__ __launch_bounds__(NT) void k_ns_recover_u(int32_t nE, const int32_t* 
     }
     double u[3];
     apply_P(wt, u);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) U[3 * (int64_t)m + i] = u[i];
+    if (!MU) return;
     double res[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        U[3 * (int64_t)m + i] = u[i];
-        const double* a = Ablk + 9 * (int64_t)m + 3 * i;
+        const double* a = A + 9 * (int64_t)m + 3 * i;
         res[i] = (a[0] * u[0] + a[1] * u[1] + a[2] * u[2]) - rhs1[3 * (int64_t)m + i];
     }
     double s[3];
@@ -594,7 +597,7 @@ __global__ __launch_bounds__(NT) void k_ns_recover_u(int32_t nE, const int32_t* 
 __global__ __launch_bounds__(NT) void k_ns_recover_mu(int32_t L, const int32_t* __restrict__ row_edge,
                                                       const int2* __restrict__ edge_elems,
                                                       const int8_t* __restrict__ led,
-                                                      const double* __restrict__ row_h,
+                                                      const double* __restrict__ row_hs,
                                                       const double* __restrict__ cs, double scale,
                                                       double* __restrict__ mu)
 {
@@ -602,7 +605,7 @@ __global__ __launch_bounds__(NT) void k_ns_recover_mu(int32_t L, const int32_t* 
     if (r >= L) return;
     int32_t e = row_edge[r];
     int32_t T = edge_elems[e].x;
-    mu[r] = scale * cs[3 * (int64_t)T + led[e]] / (2.0 * row_h[r]);
+    mu[r] = scale * cs[3 * (int64_t)T + led[e]] / (2.0 * fabs(row_hs[r]));
 }
 
 #define TRY(x)               \
@@ -799,7 +802,7 @@ void phf_ns_destroy(phf_ns* ns)
     if (!ns) return;
     if (ns->mg) phf_mg_destroy(ns->mg);
     phf_dfree(ns->ell_col);
-    phf_dfree(ns->row_h); phf_dfree(ns->B); phf_dfree(ns->Ablk);
+    phf_dfree(ns->rec); phf_dfree(ns->Ablk);
     phf_dfree(ns->ell_val); phf_dfree(ns->dinv); phf_dfree(ns->kv); phf_dfree(ns->cs);
     phf_dfree(ns->b); phf_dfree(ns->w); phf_dfree(ns->r); phf_dfree(ns->z);
     phf_dfree(ns->p); phf_dfree(ns->q); phf_dfree(ns->part);
@@ -821,14 +824,13 @@ int phf_ns_create(phf_mesh* mesh, phf_ns** out)
     ns->nbv = (int32_t)std::min<int64_t>(std::max<int64_t>(nblk(ns->nf), 1), MAXB);
     ns->elem_red = mesh->elem_red;
     ns->elem_row = mesh->elem_row;
-    const size_t e3 = 3 * (size_t)ns->nE, e9 = 9 * (size_t)ns->nE, nf = ns->nf;
+    const size_t e3 = 3 * (size_t)ns->nE, nf = ns->nf;
     int rc = 0;
     rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_col, 4 * nf, "solver ELL columns");
-    rc = rc ? rc : phf_dmalloc(ctx, &ns->B, e9, "solver blocks");
+    rc = rc ? rc : phf_dmalloc(ctx, &ns->rec, 24 * std::max<size_t>(ns->nE, 1),
+                               "solver half-row records");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->ell_val, 5 * nf, "solver ELL values");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->dinv, nf, "solver diagonal");
-    rc = rc ? rc : phf_dmalloc(ctx, &ns->row_h, (size_t)ns->L, "solver row h");
-    rc = rc ? rc : phf_dmalloc(ctx, &ns->Ablk, e9, "solver blocks");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->kv, e3, "solver known values");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->cs, e3, "solver element rhs");
     rc = rc ? rc : phf_dmalloc(ctx, &ns->b, nf, "solver rhs");
@@ -861,13 +863,18 @@ int phf_ns_create(phf_mesh* mesh, phf_ns** out)
     return PHF_OK;
 }
 
-int phf_ns_operator(phf_ns* ns, const double* K, const double* M, const double* C, double cK,
-                    double cM, const double* D, double cD)
+int phf_ns_operator(phf_ns* ns, const double* K, const double* M, double cK, double cM,
+                    const double* D, double cD, bool borrow_K)
 {
     phf_mesh* mesh = ns->mesh;
     phf_ctx* ctx = mesh->ctx;
-    PHF_LAUNCH(ctx, "k_ns_blocks", k_ns_blocks, nblk(ns->nE), NT, 0, ns->nE, K, M, D, cK, cM, cD,
-               ns->Ablk, ns->B);
+    // A = K: the element blocks are K's own (no copy)
+    const bool alias = borrow_K && cK == 1.0 && cM == 0.0 && !D;
+    if (!alias && !ns->Ablk) TRY(phf_dmalloc(ctx, &ns->Ablk, 9 * (size_t)ns->nE, "solver blocks"));
+    ns->A = alias ? K : ns->Ablk;
+    auto* rec = reinterpret_cast<phf_i4*>(ns->rec);
+    PHF_LAUNCH(ctx, "k_ns_elem", k_ns_elem, nblk(ns->nE), NT, 0, ns->nE, K, alias ? nullptr : M, D,
+               cK, cM, cD, mesh->elem_red, alias ? nullptr : ns->Ablk, rec);
     // with a multigrid preconditioner about to be set up for this operator,
     // its finest-level rows are written in the same pass
     const bool fine = ns->mg && ns->fuse_fine_rows && ns->nf > 0;
@@ -876,12 +883,9 @@ int phf_ns_operator(phf_ns* ns, const double* K, const double* M, const double* 
     if (fine) TRY(phf_mg_fine_rows(ns->mg, &fr));
     else if (ns->mg) ns->mg->fine_rows_ready = false;
     if (ns->nf > 0)
-        PHF_LAUNCH(ctx, "k_ns_ellval", fine ? k_ns_ellval<true> : k_ns_ellval<false>, nblk(ns->nf),
-                   NT, 0, ns->nf, mesh->red_edge, mesh->edge_elems, mesh->led, mesh->ledTN,
-                   mesh->elem_edges, mesh->red_row, ns->B, ns->ell_col, ns->ell_val, ns->dinv, fr);
-    if (ns->L > 0)
-        PHF_LAUNCH(ctx, "k_ns_rowh", k_ns_rowh, nblk(ns->L), NT, 0, ns->L, mesh->C_rowptr, C,
-                   ns->row_h);
+        PHF_LAUNCH(ctx, "k_ns_ellrows", fine ? k_ns_ellrows<true> : k_ns_ellrows<false>,
+                   nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge, mesh->edge_elems, mesh->led,
+                   mesh->ledTN, rec, ns->ell_col, ns->ell_val, ns->dinv, fr);
     ns->have_operator = true;
     return PHF_OK;
 }
@@ -895,7 +899,7 @@ int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2)
                    (unsigned)std::min<int64_t>(nblk(ns->L), 1024), NT, 0, ns->L, mesh->row_nodes,
                    rhs2, ns->jflag);
     PHF_LAUNCH(ctx, "k_ns_known", k_ns_known, nblk(ns->nE), NT, 0, ns->nE, mesh->ecode,
-               ns->elem_row, ns->row_h, rhs1, rhs2, ns->Ablk, ns->jflag, ns->kv, ns->cs);
+               ns->elem_row, mesh->row_hs, rhs1, rhs2, ns->A, ns->jflag, ns->kv, ns->cs);
     if (ns->nf > 0)
         PHF_LAUNCH(ctx, "k_ns_gather", k_ns_gather, nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge,
                    mesh->edge_elems, mesh->led, mesh->ledTN, ns->cs, ns->b, ns->jflag);
@@ -967,11 +971,13 @@ int phf_ns_recover(phf_ns* ns, const double* rhs1, double* U, double* mu, double
 {
     phf_mesh* mesh = ns->mesh;
     phf_ctx* ctx = mesh->ctx;
-    PHF_LAUNCH(ctx, "k_ns_recover_u", k_ns_recover_u, nblk(ns->nE), NT, 0, ns->nE, ns->elem_red,
-               ns->w, ns->kv, ns->Ablk, rhs1, U, ns->cs);
+    const bool with_mu = mu && ns->L > 0;
+    PHF_LAUNCH(ctx, "k_ns_recover_u", with_mu ? k_ns_recover_u<true> : k_ns_recover_u<false>,
+               nblk(ns->nE), NT, 0, ns->nE, ns->elem_red, ns->w, ns->kv, ns->A, rhs1, U, ns->cs);
     if (mu && ns->L > 0)
         PHF_LAUNCH(ctx, "k_ns_recover_mu", k_ns_recover_mu, nblk(ns->L), NT, 0, ns->L,
-                   mesh->row_edge, mesh->edge_elems, mesh->led, ns->row_h, ns->cs, mu_scale, mu);
+                   mesh->row_edge, mesh->edge_elems, mesh->led, mesh->row_hs, ns->cs, mu_scale,
+                   mu);
     return PHF_OK;
 }
 
@@ -1228,8 +1234,9 @@ extern "C" int phf_solve(phf_mesh* mesh, const phf_coeffs* co, const phf_system*
     // operator kernel writes its finest rows too
     TRY(phf_ns_prepare_precond(ns, o.precond, mp));
     ns->fuse_fine_rows = o.precond == PHF_PRECOND_MULTIGRID;
-    TRY(phf_ns_operator(ns, sys->K, sys->M, sys->C, 1.0, co->delta, conv_term ? sys->D : nullptr,
-                        1.0));
+    // (K stays the caller's until the recovery below, so A = K is not copied)
+    TRY(phf_ns_operator(ns, sys->K, sys->M, 1.0, co->delta, conv_term ? sys->D : nullptr, 1.0,
+                        true));
     TRY(phf_ns_set_precond(ns, o.precond, mp, co, 1.0, co->delta));
     TRY(phf_ns_rhs(ns, sys->F, sys->bD));
     // both iterations start from w = 0 (the CG initialisation writes it)
