@@ -19,7 +19,9 @@ struct phf_cn {
     double k = 0, delta = 0;
     phf_coeffs co{};
     phf_cn_opts opts{};
-    double *K = nullptr, *M = nullptr, *C = nullptr, *Fs = nullptr, *bs = nullptr;
+    // K and M are assembled once; after the operator A+ is built only
+    // A- = (1 - k delta/2) M - (k/2) K is kept (9 values per element)
+    double *K = nullptr, *M = nullptr, *Am = nullptr, *C = nullptr, *Fs = nullptr, *bs = nullptr;
     double *U = nullptr, *Lam = nullptr;
     double *F0 = nullptr, *F1 = nullptr, *bD0 = nullptr, *bD1 = nullptr;
     double *r1 = nullptr, *r2 = nullptr;
@@ -78,42 +80,57 @@ __global__ __launch_bounds__(NT) void k_cn_keep(int32_t nf, int32_t* __restrict_
     if (blockIdx.x == 0 && threadIdx.x == 0) *nsol = min(*nsol + 1, 2);
 }
 
-// r1 per element (see file comment).
-__global__ __launch_bounds__(NT) void k_cn_rhs_elem(
-    int32_t nE, const int32_t* __restrict__ ecode, const double* __restrict__ K,
-    const double* __restrict__ M, const double* __restrict__ U, const double* __restrict__ Lam,
-    const int32_t* __restrict__ elem_row, const double* __restrict__ row_hs,
-    const double* __restrict__ F0, const double* __restrict__ F1, double cM, double cK,
-    double hk, double* __restrict__ r1)
+// A- = cM M - cK K per element block, once per stepper.
+// (Am may be K itself: each element is read before it is written.)
+__global__ __launch_bounds__(NT) void k_cn_aminus(int64_t n, const double* K,
+                                                  const double* __restrict__ M, double cM,
+                                                  double cK, double* Am)
 {
-    int32_t m = blockIdx.x * NT + threadIdx.x;
-    if (m >= nE) return;
+    const int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (q < n) Am[q] = cM * M[q] - cK * K[q];
+}
+
+// r1 per element (see file comment); the tile's A- blocks go through LDS so
+// that they are read with coalesced accesses.
+__global__ __launch_bounds__(NT) void k_cn_rhs_elem(
+    int32_t nE, const int32_t* __restrict__ ecode, const double* __restrict__ Am,
+    const double* __restrict__ U, const double* __restrict__ Lam,
+    const int32_t* __restrict__ elem_row, const double* __restrict__ row_hs,
+    const double* __restrict__ F0, const double* __restrict__ F1, double hk,
+    double* __restrict__ r1)
+{
+    __shared__ double sA[9 * NT];
+    const int tid = threadIdx.x;
+    const int64_t m0 = (int64_t)blockIdx.x * NT;
+    const int32_t nt = (int32_t)min((int64_t)NT, (int64_t)nE - m0);
+    for (int32_t q = tid; q < 9 * nt; q += NT) sA[q] = Am[9 * m0 + q];
+    __syncthreads();
+    if (tid >= nt) return;
+    const int64_t m = m0 + tid;
     const int code = ecode[m];
     double u[3], lt[3];
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-        u[l] = U[3 * (int64_t)m + l];
+        u[l] = U[3 * m + l];
         // sigma_l h_l Lambda_row(l) for non-Neumann local edges
         double v = 0.0;
         if (PHF_CODE_TYPE(code, l) != 2) {
-            int32_t r = elem_row[3 * (int64_t)m + l];
+            int32_t r = elem_row[3 * m + l];
             v = (PHF_CODE_TPLUS(code, l) ? 1.0 : -1.0) * fabs(row_hs[r]) * Lam[r];
         }
         lt[l] = v;
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        const double* k = K + 9 * (int64_t)m + 3 * i;
-        const double* mm = M + 9 * (int64_t)m + 3 * i;
+        const double* a = sA + 9 * tid + 3 * i;
         double au = 0.0;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) au += (cM * mm[j] - cK * k[j]) * u[j];
+        for (int j = 0; j < 3; ++j) au += a[j] * u[j];
         // (C^T Lambda)_i = sum over the two edges through vertex i
         double ctl = 0.0;
 #pragma unroll
         for (int l = 0; l < 3; ++l) ctl += (l == i) ? 0.0 : lt[l];
-        r1[3 * (int64_t)m + i] =
-            au + hk * ctl + hk * (F0[3 * (int64_t)m + i] + F1[3 * (int64_t)m + i]);
+        r1[3 * m + i] = au + hk * ctl + hk * (F0[3 * m + i] + F1[3 * m + i]);
     }
 }
 
@@ -171,13 +188,13 @@ int cn_step_head(phf_cn* cn, const phf_data* data)
     const int32_t nE = mesh->nE, L = mesh->L;
     PHF_LAUNCH(ctx, "k_cn_inc", k_cn_inc, 1, 1, 0, cn->d_step);
     TRY(cn_loads(cn, data, cn->F1, cn->bD1, true));
-    const double cM = 1.0 - 0.5 * cn->k * cn->delta, cK = 0.5 * cn->k, hk = 0.5 * cn->k;
-    PHF_LAUNCH(ctx, "k_cn_rhs_elem", k_cn_rhs_elem, nblk(nE), NT, 0, nE, mesh->ecode, cn->K, cn->M,
-               cn->U, cn->Lam, cn->ns->elem_row, cn->mesh->row_hs, cn->F0, cn->F1, cM, cK, hk, cn->r1);
+    const double hk = 0.5 * cn->k;
+    PHF_LAUNCH(ctx, "k_cn_rhs_elem", k_cn_rhs_elem, nblk(nE), NT, 0, nE, mesh->ecode, cn->Am,
+               cn->U, cn->Lam, cn->ns->elem_row, cn->mesh->row_hs, cn->F0, cn->F1, hk, cn->r1);
     if (L > 0)
         PHF_LAUNCH(ctx, "k_cn_rhs_row", k_cn_rhs_row, nblk(L), NT, 0, L, mesh->C_rowptr,
                    mesh->C_col, cn->C, cn->U, cn->bD0, cn->bD1, cn->r2);
-    TRY(phf_ns_rhs(cn->ns, cn->r1, cn->r2));
+    TRY(phf_ns_rhs(cn->ns, cn->r1, cn->r2, true));
     if (cn->ns->nf > 0)
         PHF_LAUNCH(ctx, "k_cn_guess", k_cn_guess, cn->ns->nbv, NT, 0, cn->ns->nf, cn->d_nsol,
                    cn->w1, cn->w2, cn->ns->w);
@@ -285,7 +302,7 @@ extern "C" int phf_cn_destroy(phf_cn* cn)
     }
     cn_drop_graph(cn);
     if (cn->ns) phf_ns_destroy(cn->ns);
-    double* bufs[] = {cn->K, cn->M, cn->C, cn->Fs, cn->bs, cn->U, cn->Lam, cn->F0,
+    double* bufs[] = {cn->K, cn->M, cn->Am, cn->C, cn->Fs, cn->bs, cn->U, cn->Lam, cn->F0,
                       cn->F1, cn->bD0, cn->bD1, cn->r1, cn->r2, cn->d_stats};
     for (double* b : bufs) phf_dfree(b);
     phf_dfree(cn->d_step);
@@ -361,7 +378,13 @@ extern "C" int phf_cn_create(phf_mesh* mesh, const phf_coeffs* co, double k,
         mp.range = cn->opts.mg_range;
         TRY(phf_ns_set_precond(cn->ns, cn->opts.precond, mp, co, 0.5 * k,
                                1.0 + 0.5 * k * co->delta));
+        // A- in K's place; M is no longer needed
+        PHF_LAUNCH(ctx, "k_cn_aminus", k_cn_aminus, nblk((int64_t)nnzK), NT, 0, (int64_t)nnzK,
+                   cn->K, cn->M, 1.0 - 0.5 * k * co->delta, 0.5 * k, cn->K);
         PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        cn->Am = cn->K;
+        cn->K = nullptr;
+        phf_dfree(cn->M);
         return PHF_OK;
     };
     int rc = body();
