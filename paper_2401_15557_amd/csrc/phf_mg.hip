@@ -397,21 +397,8 @@ __global__ __launch_bounds__(NT) void k_mg_cblocks(int32_t nE, const double2* __
             for (int i = 0; i < 3; ++i)
                 A[3 * j + i] = cK * s * (ax * gx[i] + ay * gy[i]) + cM * mass * (i == j ? 2.0 : 1.0);
         }
-        // AP[i][l] = rowsum_i(A) - 2 A[i][l]; B[l][l'] = colsum_{l'}(AP) - 2 AP[l][l']
-        double AP[9];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const double rs = A[3 * i] + A[3 * i + 1] + A[3 * i + 2];
-#pragma unroll
-            for (int l = 0; l < 3; ++l) AP[3 * i + l] = rs - 2.0 * A[3 * i + l];
-        }
         double Bm[9];
-#pragma unroll
-        for (int lp = 0; lp < 3; ++lp) {
-            const double cs = AP[lp] + AP[3 + lp] + AP[6 + lp];
-#pragma unroll
-            for (int l = 0; l < 3; ++l) Bm[3 * l + lp] = cs - 2.0 * AP[3 * l + lp];
-        }
+        phf_reduce_block(A, Bm);
         const int32_t red[3] = {elem_red[3 * m], elem_red[3 * m + 1], elem_red[3 * m + 2]};
         phf_hrec_element(srec, tid, red, Bm);
     }

@@ -22,6 +22,26 @@
 
 struct phf_mg;
 
+// B = P^T A P for one element (3 x 3, row-major; A need not be symmetric),
+// with P[i][l] = -1 if l == i else 1: AP[i][l] = rowsum_i(A) - 2 A[i][l],
+// then B[l][l'] = colsum_l'(AP) - 2 AP[l][l'].
+__device__ inline void phf_reduce_block(const double* A, double B[9])
+{
+    double AP[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double rs = A[3 * i] + A[3 * i + 1] + A[3 * i + 2];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) AP[3 * i + l] = rs - 2.0 * A[3 * i + l];
+    }
+#pragma unroll
+    for (int lp = 0; lp < 3; ++lp) {
+        const double cs = AP[lp] + AP[3 + lp] + AP[6 + lp];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) B[3 * l + lp] = cs - 2.0 * AP[3 * l + lp];
+    }
+}
+
 // Blocks of the solver's vector kernels at most, i.e. partial-sum slots per
 // reduced quantity (each block writes one and every block of the next kernel
 // reduces all of them in the same order).
@@ -67,7 +87,6 @@ struct phf_ns {
     double* scal = nullptr;       // device scalars
     int* iflags = nullptr;        // [0] done, [1] iterations
     int* jflag = nullptr;         // raised: interior constraint rows with a right-hand side
-    bool have_operator = false;
     int32_t next_it = 0;          // index of the next CG iteration issued
 };
 

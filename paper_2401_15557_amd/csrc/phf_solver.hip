@@ -54,22 +54,7 @@ __global__ __launch_bounds__(NT) void k_ns_elem(int32_t nE, const double* __rest
     int32_t red[3] = {-1, -1, -1};
     if (tid < nt) {
         const int64_t m = m0 + tid;
-        const double* A = sA + 9 * tid;
-        // AP[i][l] = rowsum_i(A) - 2 A[i][l]
-        double AP[9];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const double rs = A[3 * i] + A[3 * i + 1] + A[3 * i + 2];
-#pragma unroll
-            for (int l = 0; l < 3; ++l) AP[3 * i + l] = rs - 2.0 * A[3 * i + l];
-        }
-        // B[l][l'] = colsum_{l'}(AP) - 2 AP[l][l']
-#pragma unroll
-        for (int lp = 0; lp < 3; ++lp) {
-            const double cs = AP[lp] + AP[3 + lp] + AP[6 + lp];
-#pragma unroll
-            for (int l = 0; l < 3; ++l) Bm[3 * l + lp] = cs - 2.0 * AP[3 * l + lp];
-        }
+        phf_reduce_block(sA + 9 * tid, Bm);
 #pragma unroll
         for (int l = 0; l < 3; ++l) red[l] = elem_red[3 * m + l];
     }
@@ -891,7 +876,6 @@ int phf_ns_operator(phf_ns* ns, const double* K, const double* M, double cK, dou
         PHF_LAUNCH(ctx, "k_ns_ellrows", fine ? k_ns_ellrows<true> : k_ns_ellrows<false>,
                    nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge, mesh->edge_elems, mesh->led,
                    mesh->ledTN, rec, ns->ell_col, ns->ell_val, ns->dinv, fr);
-    ns->have_operator = true;
     return PHF_OK;
 }
 
@@ -1231,6 +1215,12 @@ extern "C" int phf_solve(phf_mesh* mesh, const phf_coeffs* co, const phf_system*
         return phf_set_error(ctx, PHF_EINVAL, "phf_solve: saddle_rtol needs conjugate gradients");
     phf_ns* ns = nullptr;
     TRY(phf_ns_get(mesh, &ns));
+    // the operator below may read the element blocks from the caller's K;
+    // the cached workspace does not keep that pointer past this call
+    struct forget_A {
+        phf_ns* ns;
+        ~forget_A() { ns->A = nullptr; }
+    } forget{ns};
     phf_mg_params mp;
     mp.sweeps = o.mg_sweeps;
     mp.smoother = o.mg_smoother;
