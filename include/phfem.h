@@ -349,8 +349,11 @@ int phf_spmv(phf_ctx* ctx, int32_t nrows, const int32_t* rowptr, const int32_t* 
  * a sparse matrix with five entries per row, and Lambda is recovered element
  * by element. With p = 0 the projected operator is symmetric positive
  * definite and conjugate gradients apply; p != 0 (convection) makes it
- * nonsymmetric and needs BiCGSTAB (right-preconditioned). U, Lambda: device,
- * N and L doubles; Lambda may be NULL. Synchronises the stream. Returns
+ * nonsymmetric and needs BiCGSTAB (right-preconditioned). The element
+ * blocks are read from K (and M, D) during the call; the multipliers'
+ * scaling |E|/2 is the mesh's, the value phf_assemble writes into C.
+ * U, Lambda: device, N and L doubles; Lambda may be NULL. Synchronises the
+ * stream. Returns
  * PHF_ENOCONV if rtol is not reached in max_iter iterations or BiCGSTAB
  * still breaks down after its restarts (a breakdown restarts it from the
  * current iterate, at most 8 times; the iterate is still written),
