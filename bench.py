@@ -68,9 +68,9 @@ def algorithmic_bytes(info, has_aT=True, level_nf=None, level_nE=None, jacobi=Fa
     """Bytes a kernel must move at least, per launch, by kernel name.
 
     k_assemble: read coordinates once (16 B/node), element vertices
-    (12 B/elem), a_T (8 B/elem), the two end nodes of each multiplier row
-    (8 B/row); write K and M (72 B/elem each), F (24 B/elem), C (8 B/nnz)
-    and b_D (8 B/row).
+    (12 B/elem), a_T (8 B/elem), 8 B per multiplier row (the row's edge:
+    |E|/2, or its two end nodes); write K and M (72 B/elem each), F
+    (24 B/elem), C (8 B/nnz) and b_D (8 B/row).
     V-cycle kernels (single precision) on level l with n unknowns
     (level_nf[l]), operator rows scaled by the inverse diagonal with four
     off-diagonal (int32 column, fp32 value) slots = 32 B/row: smoothing sweep
