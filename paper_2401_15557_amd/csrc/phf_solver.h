@@ -104,10 +104,7 @@ void phf_ns_destroy(phf_ns* ns);
 int phf_ns_operator(phf_ns* ns, const double* K, const double* M, double cK, double cM,
                     const double* D = nullptr, double cD = 0.0, bool borrow_K = false);
 // Right-hand side reduction (rhs2 is the right-hand side of -C U = rhs2).
-// jumps_expected: rhs2 is generally non-zero on interior rows (Crank-Nicolson),
-// which selects the element pass that stages A_T (either pass is correct for
-// any rhs2).
-int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2, bool jumps_expected = false);
+int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2);
 // Starts CG from the current w, or with zero_start from w = 0 (written by
 // the start itself).
 int phf_ns_cg_start(phf_ns* ns, double rtol, bool zero_start = false);

@@ -163,10 +163,7 @@ __global__ __launch_bounds__(NT) void k_ns_jumpflag(int32_t L, const int2* __res
 // element part of the reduced rhs,
 // c_T = P^T (rhs1_T - A_T P kv_T). Where kv_T = 0 (in an elliptic solve most
 // elements: no known value on their edges) the product is zero and A_T is
-// not read. The element rows of rhs1, kv and c go through LDS, and with
-// STAGE_A the blocks A_T too (for right-hand sides with interior jumps,
-// where nearly every element has a known value).
-template <bool STAGE_A>
+// not read. The element rows of rhs1, kv and c go through LDS.
 __global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int32_t* __restrict__ ecode,
                                                  const int32_t* __restrict__ elem_row,
                                                  const double* __restrict__ row_hs,
@@ -177,13 +174,11 @@ __global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int32_t* __re
                                                  double* __restrict__ kv, double* __restrict__ cs)
 {
     __shared__ double sR[3 * NT], sK[3 * NT], sC[3 * NT];
-    __shared__ double sA[STAGE_A ? 9 * NT : 1];
     const bool jumps = *jflag != 0;
     const int tid = threadIdx.x;
     const int64_t m0 = (int64_t)blockIdx.x * NT;
     const int32_t nt = (int32_t)min((int64_t)NT, (int64_t)nE - m0);
     tile_load<3>(rhs1, m0, nt, sR);
-    if (STAGE_A) tile_load<9>(A, m0, nt, sA);
     __syncthreads();
     if (tid < nt) {
         const int64_t m = m0 + tid;
@@ -208,7 +203,7 @@ __global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int32_t* __re
             apply_P(k3, Ub);
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const double* a = STAGE_A ? sA + 9 * tid + 3 * i : A + 9 * m + 3 * i;
+                const double* a = A + 9 * m + 3 * i;
                 res[i] -= a[0] * Ub[0] + a[1] * Ub[1] + a[2] * Ub[2];
             }
         }
@@ -879,7 +874,7 @@ int phf_ns_operator(phf_ns* ns, const double* K, const double* M, double cK, dou
     return PHF_OK;
 }
 
-int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2, bool jumps_expected)
+int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2)
 {
     phf_mesh* mesh = ns->mesh;
     phf_ctx* ctx = mesh->ctx;
@@ -887,9 +882,8 @@ int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2, bool jumps_ex
         PHF_LAUNCH(ctx, "k_ns_jumpflag", k_ns_jumpflag,
                    (unsigned)std::min<int64_t>(nblk(ns->L), 1024), NT, 0, ns->L, mesh->row_nodes,
                    rhs2, ns->jflag);
-    PHF_LAUNCH(ctx, "k_ns_known", jumps_expected ? k_ns_known<true> : k_ns_known<false>,
-               nblk(ns->nE), NT, 0, ns->nE, mesh->ecode, ns->elem_row, mesh->row_hs, rhs1, rhs2,
-               ns->A, ns->jflag, ns->kv, ns->cs);
+    PHF_LAUNCH(ctx, "k_ns_known", k_ns_known, nblk(ns->nE), NT, 0, ns->nE, mesh->ecode,
+               ns->elem_row, mesh->row_hs, rhs1, rhs2, ns->A, ns->jflag, ns->kv, ns->cs);
     if (ns->nf > 0)
         PHF_LAUNCH(ctx, "k_ns_gather", k_ns_gather, nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge,
                    mesh->edge_elems, mesh->led, mesh->ledTN, ns->cs, ns->b, ns->jflag);
