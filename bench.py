@@ -456,8 +456,8 @@ def main():
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(how the path would shard is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path; "
+              "every figure is one GPU's.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
