@@ -75,10 +75,38 @@ __device__ inline void fused_tile(int32_t b, int32_t nbE, int32_t nbR, bool* is_
     }
 }
 
+// f, g or u_D at one point. OOL = false inlines the evaluation (the
+// single-mesh kernel); OOL = true calls one out-of-line copy: the batched
+// kernel has 120 instantiations, and inlining the fp64 sine, cosine and
+// exponential at its seven call sites grows the library from 2 to 15 MB for
+// about 1% of its time. The evaluation contracts no multiply-adds, so both
+// forms round alike.
+__device__ __noinline__ double fn_eval_call(int32_t kind, double c0, double c1, double c2,
+                                           double c3, const double* ev, double x, double y,
+                                           double t, double nx, double ny, int32_t edge)
+{
+    phf_fn_dev f;
+    f.kind = kind;
+    f.c0 = c0;
+    f.c1 = c1;
+    f.c2 = c2;
+    f.c3 = c3;
+    f.ev = ev;
+    return phf_fn_eval(f, x, y, t, nx, ny, edge);
+}
+
+template <bool OOL>
+__device__ inline double fn_at(const phf_fn_dev& f, double x, double y, double t, double nx,
+                               double ny, int32_t edge)
+{
+    if (OOL) return fn_eval_call(f.kind, f.c0, f.c1, f.c2, f.c3, f.ev, x, y, t, nx, ny, edge);
+    return phf_fn_eval(f, x, y, t, nx, ny, edge);
+}
+
 // Element m with vertices P0, P1, P2 (counter-clockwise): its K (9 values,
 // row-major), |T|/12 (M is regenerated from it), D and F = b + LN (3 values)
 // into LDS slot `slot`.
-template <bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A>
+template <bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A, bool OOL = false>
 __device__ inline void element_values(const AsmArgs& a, int32_t m, const double2 P0,
                                       const double2 P1, const double2 P2, int slot, double* shK,
                                       double* shD, double* shA, double* shF)
@@ -149,9 +177,9 @@ __device__ inline void element_values(const AsmArgs& a, int32_t m, const double2
     }
     double b0 = 0.0, b1 = 0.0, b2 = 0.0;
     if (a.f.kind != PHF_FN_ZERO) {
-        const double f0 = phf_fn_eval(a.f, 0.5 * (P1.x + P2.x), 0.5 * (P1.y + P2.y), a.t, 0, 0, ed0);
-        const double f1 = phf_fn_eval(a.f, 0.5 * (P2.x + P0.x), 0.5 * (P2.y + P0.y), a.t, 0, 0, ed1);
-        const double f2 = phf_fn_eval(a.f, 0.5 * (P0.x + P1.x), 0.5 * (P0.y + P1.y), a.t, 0, 0, ed2);
+        const double f0 = fn_at<OOL>(a.f, 0.5 * (P1.x + P2.x), 0.5 * (P1.y + P2.y), a.t, 0, 0, ed0);
+        const double f1 = fn_at<OOL>(a.f, 0.5 * (P2.x + P0.x), 0.5 * (P2.y + P0.y), a.t, 0, 0, ed1);
+        const double f2 = fn_at<OOL>(a.f, 0.5 * (P0.x + P1.x), 0.5 * (P0.y + P1.y), a.t, 0, 0, ed2);
         const double c = area / 6.0;
         b0 = c * (f1 + f2);
         b1 = c * (f0 + f2);
@@ -171,8 +199,8 @@ __device__ inline void element_values(const AsmArgs& a, int32_t m, const double2
             const int32_t eid =
                 a.g.kind == PHF_FN_EDGE_ARRAY ? a.elem_edges[3 * (int64_t)m + i] : -1;
             // outward normal of the counter-clockwise edge Pa -> Pb
-            const double gv = phf_fn_eval(a.g, 0.5 * (Pa.x + Pb.x), 0.5 * (Pa.y + Pb.y), a.t,
-                                          dy / len, -dx / len, eid);
+            const double gv = fn_at<OOL>(a.g, 0.5 * (Pa.x + Pb.x), 0.5 * (Pa.y + Pb.y), a.t,
+                                         dy / len, -dx / len, eid);
             const double w = len * gv * 0.5;
             if (i == 0) { b1 += w; b2 += w; }
             if (i == 1) { b2 += w; b0 += w; }
@@ -245,7 +273,8 @@ __device__ inline void store_elements(const AsmArgs& a, int32_t m0, int32_t cnt,
 // bytes per element plus cached gathers, which pays on meshes numbered so
 // that neighbouring elements share nodes, e.g. structured ones; the values
 // are the same).
-template <int TN, bool NT, bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A, bool GATHER = false>
+template <int TN, bool NT, bool HAS_AT, bool MATS, bool WITH_D, bool GEN_A, bool GATHER = false,
+          bool OOL = false>
 __device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK, double* shD,
                                     double* shA, double* shF)
 {
@@ -265,7 +294,8 @@ __device__ inline void element_tile(const AsmArgs& a, int32_t tile, double* shK,
             P1 = a.exy[3 * (int64_t)m + 1];
             P2 = a.exy[3 * (int64_t)m + 2];
         }
-        element_values<HAS_AT, MATS, WITH_D, GEN_A>(a, m, P0, P1, P2, tid, shK, shD, shA, shF);
+        element_values<HAS_AT, MATS, WITH_D, GEN_A, OOL>(a, m, P0, P1, P2, tid, shK, shD, shA,
+                                                         shF);
     }
     __syncthreads();
     store_elements<TN, NT, MATS, WITH_D>(a, m0, nt, shK, shD, shA, shF);
@@ -321,7 +351,7 @@ __device__ inline void child_tile(const AsmArgs& a, int32_t tile, double* shK, d
 // writes). A row reads its edge's half-length |E|/2 from the mesh's row
 // records (negated on Dirichlet rows); only a Dirichlet row with data reads
 // its end nodes, for the midpoint of u_D. shC: 4 TN doubles.
-template <int TN, bool NT, bool MATS>
+template <int TN, bool NT, bool MATS, bool OOL = false>
 __device__ inline void row_tile(const AsmArgs& a, int32_t tile, int32_t* shs, double* shC)
 {
     const int32_t r = tile * TN + threadIdx.x;
@@ -351,7 +381,7 @@ __device__ inline void row_tile(const AsmArgs& a, int32_t tile, int32_t* shs, do
         const int2 kl = a.row_nodes[r];
         const double2 Pk = a.xy[~kl.x], Pl = a.xy[kl.y];
         const int32_t eid = a.uD.kind == PHF_FN_EDGE_ARRAY ? a.row_edge[r] : -1;
-        v = -(2.0 * h) * phf_fn_eval(a.uD, 0.5 * (Pk.x + Pl.x), 0.5 * (Pk.y + Pl.y), a.t, 0, 0, eid);
+        v = -(2.0 * h) * fn_at<OOL>(a.uD, 0.5 * (Pk.x + Pl.x), 0.5 * (Pk.y + Pl.y), a.t, 0, 0, eid);
     }
     put1<NT>(a.bD + r, v);
 }
@@ -390,7 +420,7 @@ __device__ inline void element_direct(const AsmArgs& a, int32_t tile, double* sh
     if (m >= a.nE) return;
     const double2 P0 = a.exy[3 * (int64_t)m], P1 = a.exy[3 * (int64_t)m + 1];
     const double2 P2 = a.exy[3 * (int64_t)m + 2];
-    element_values<HAS_AT, true, WITH_D, GEN_A>(a, m, P0, P1, P2, tid, shK, shD, shA, shF);
+    element_values<HAS_AT, true, WITH_D, GEN_A, true>(a, m, P0, P1, P2, tid, shK, shD, shA, shF);
     const double* k = shK + 9 * tid;
     for (int q = 0; q < 9; ++q) {
         put1<NT>(a.K + 9 * (int64_t)m + q, k[q]);
@@ -434,7 +464,7 @@ __device__ inline void element_quad(const AsmArgs& a, int32_t tile)
     int nv = 0;
     if (row && a.f.kind != PHF_FN_ZERO) {
         const int32_t ed = a.f.kind == PHF_FN_EDGE_ARRAY ? a.elem_edges[3 * (int64_t)m + i] : -1;
-        fv = phf_fn_eval(a.f, 0.5 * (Pa.x + Pb.x), 0.5 * (Pa.y + Pb.y), a.t, 0, 0, ed);
+        fv = fn_at<true>(a.f, 0.5 * (Pa.x + Pb.x), 0.5 * (Pa.y + Pb.y), a.t, 0, 0, ed);
     }
     if (row && ((a.neu_mask[m >> 6] >> (m & 63)) & 1)) {
         const int code = a.ecode[m];
@@ -443,7 +473,7 @@ __device__ inline void element_quad(const AsmArgs& a, int32_t tile)
             const double len = sqrt(dx * dx + dy * dy);
             const int32_t eid =
                 a.g.kind == PHF_FN_EDGE_ARRAY ? a.elem_edges[3 * (int64_t)m + i] : -1;
-            const double gv = phf_fn_eval(a.g, 0.5 * (Pa.x + Pb.x), 0.5 * (Pa.y + Pb.y), a.t,
+            const double gv = fn_at<true>(a.g, 0.5 * (Pa.x + Pb.x), 0.5 * (Pa.y + Pb.y), a.t,
                                           dy / len, -dx / len, eid);
             wv = len * gv * 0.5;
             nv = 1;
@@ -495,6 +525,48 @@ __device__ inline void element_quad(const AsmArgs& a, int32_t tile)
 }
 
 // ---- batched assembly -------------------------------------------------------
+// A pointer field of a record in device memory, read as a global-memory
+// pointer. The compiler cannot tell where a pointer loaded from memory
+// points and would address through it with flat instructions (which also
+// count against the LDS wait counter); read this way the tile code keeps
+// global loads and stores, as with the single-mesh kernel's by-value
+// argument (measured: 6-8% of the batched launch).
+template <class T>
+__device__ inline T* as_global(T* const& field)
+{
+    typedef __attribute__((address_space(1))) T* GT;
+    return (T*)*static_cast<const GT*>(static_cast<const void*>(&field));
+}
+
+__device__ inline AsmArgs global_record(const AsmArgs& g)
+{
+    AsmArgs a = g;
+    a.exy = as_global(g.exy);
+    a.pexy = as_global(g.pexy);
+    a.elem4 = as_global(g.elem4);
+    a.ecode = as_global(g.ecode);
+    a.xy = as_global(g.xy);
+    a.aT = as_global(g.aT);
+    a.elem_edges = as_global(g.elem_edges);
+    a.row_hs = as_global(g.row_hs);
+    a.row_nodes = as_global(g.row_nodes);
+    a.row_edge = as_global(g.row_edge);
+    a.C_tile = as_global(g.C_tile);
+    a.C_rowptr = as_global(g.C_rowptr);
+    a.neu_mask = as_global(g.neu_mask);
+    a.t_step = as_global(g.t_step);
+    a.K = as_global(g.K);
+    a.M = as_global(g.M);
+    a.D = as_global(g.D);
+    a.C = as_global(g.C);
+    a.F = as_global(g.F);
+    a.bD = as_global(g.bD);
+    a.f.ev = as_global(g.f.ev);
+    a.g.ev = as_global(g.g.ev);
+    a.uD.ev = as_global(g.uD.ev);
+    return a;
+}
+
 // One launch over a work list of (instance, tile) items of many meshes:
 // item.y >= 0 is element tile item.y of instance item.x, item.y < 0 row tile
 // ~item.y. PERSIST = false: one workgroup per item; PERSIST = true: each
@@ -503,9 +575,10 @@ __device__ inline void element_quad(const AsmArgs& a, int32_t tile)
 // element tile's form, 0 staged through LDS (TN triangles), 1 per-thread
 // stores (TN triangles), 2 four lanes per triangle (TN / 4 triangles), 3
 // staged with coordinates gathered through the vertex ids. The
-// instance record is staged in LDS. The tile code is the single-mesh
-// kernel's (element tiles read each mesh's own element records), so the
-// outputs are bit-identical to it.
+// instance record is read with scalar loads (the work item and the record
+// are uniform over the workgroup). The tile code is the single-mesh kernel's
+// (element tiles read each mesh's own element records; f, g and u_D are
+// evaluated out of line), so the outputs are bit-identical to it.
 template <int TN, int MODE, bool PERSIST, bool HAS_AT, bool WITH_D, bool GEN_A>
 __global__ __launch_bounds__(TN) void k_assemble_batch(const AsmArgs* __restrict__ args,
                                                        const int2* __restrict__ work,
@@ -517,22 +590,17 @@ __global__ __launch_bounds__(TN) void k_assemble_batch(const AsmArgs* __restrict
     __shared__ double shA[LDS ? TN : 1];
     __shared__ __align__(16) double shF[LDS ? TN * 3 : 2];
     __shared__ int32_t shs[TN / 64 + 1];
-    __shared__ AsmArgs sa;
-    static_assert(sizeof(AsmArgs) % 8 == 0 && sizeof(AsmArgs) / 8 <= TN, "record copy");
     for (int32_t w = blockIdx.x; w < nwork; w += gridDim.x) {
         const int2 item = work[w];
-        if (threadIdx.x < sizeof(AsmArgs) / 8)
-            reinterpret_cast<uint64_t*>(&sa)[threadIdx.x] =
-                reinterpret_cast<const uint64_t*>(args + item.x)[threadIdx.x];
-        __syncthreads();
-        const AsmArgs& a = sa;
+        const AsmArgs a = global_record(args[item.x]);
         if (item.y < 0)
-            row_tile<TN, true, true>(a, ~item.y, shs, shK);
+            row_tile<TN, true, true, true>(a, ~item.y, shs, shK);
         else if (MODE == 0)
-            element_tile<TN, true, HAS_AT, true, WITH_D, GEN_A>(a, item.y, shK, shD, shA, shF);
+            element_tile<TN, true, HAS_AT, true, WITH_D, GEN_A, false, true>(a, item.y, shK, shD,
+                                                                            shA, shF);
         else if (MODE == 3)
-            element_tile<TN, true, HAS_AT, true, WITH_D, GEN_A, true>(a, item.y, shK, shD, shA,
-                                                                     shF);
+            element_tile<TN, true, HAS_AT, true, WITH_D, GEN_A, true, true>(a, item.y, shK, shD,
+                                                                           shA, shF);
         else if (MODE == 1)
             element_direct<TN, true, HAS_AT, WITH_D, GEN_A>(a, item.y, shK, shD, shA, shF);
         else
@@ -821,16 +889,18 @@ int launch_batch_t(phf_batch* b, int wi)
     phf_ctx* ctx = b->ctx;
     const int32_t nw = b->nwork[wi];
     if (nw == 0) return PHF_OK;
-    if (MODE == 0 && b->blocks_per_cu > 0) {
-        const int64_t grid = std::min<int64_t>(nw, (int64_t)b->blocks_per_cu * b->ncu);
-        PHF_LAUNCH(ctx, "k_assemble_batch",
-                   (k_assemble_batch<TN, MODE, true, HAS_AT, WITH_D, GEN_A>), (unsigned)grid, TN,
-                   0, b->d_args, b->d_work[wi], nw);
-    } else {
-        PHF_LAUNCH(ctx, "k_assemble_batch",
-                   (k_assemble_batch<TN, MODE, false, HAS_AT, WITH_D, GEN_A>), (unsigned)nw, TN,
-                   0, b->d_args, b->d_work[wi], nw);
+    if constexpr (MODE == 0) {  // persistent grids only for the staged tile
+        if (b->blocks_per_cu > 0) {
+            const int64_t grid = std::min<int64_t>(nw, (int64_t)b->blocks_per_cu * b->ncu);
+            PHF_LAUNCH(ctx, "k_assemble_batch",
+                       (k_assemble_batch<TN, MODE, true, HAS_AT, WITH_D, GEN_A>), (unsigned)grid,
+                       TN, 0, b->d_args, b->d_work[wi], nw);
+            return PHF_OK;
+        }
     }
+    PHF_LAUNCH(ctx, "k_assemble_batch",
+               (k_assemble_batch<TN, MODE, false, HAS_AT, WITH_D, GEN_A>), (unsigned)nw, TN, 0,
+               b->d_args, b->d_work[wi], nw);
     return PHF_OK;
 }
 
