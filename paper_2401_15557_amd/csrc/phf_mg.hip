@@ -261,21 +261,9 @@ __device__ inline void row_resid(int32_t i, int32_t n, PC __restrict__ col, PV _
 // on the shape of p, so the weights are the constants below. rf must hold at
 // least one element (the gathers read a clamped index, so that all nine row
 // loads are issued before the first gather waits).
-template <bool NTL = false, typename PR9, typename PE, typename PF, typename PT>
-__device__ inline void tri_restrict(int32_t p, int32_t nEc, PR9 __restrict__ rows9,
-                                    PE __restrict__ ecode_c, PF __restrict__ rf,
-                                    PT __restrict__ t)
+template <typename PT>
+__device__ inline void tri_combine(int32_t p, int32_t code, const float (&v)[9], PT __restrict__ t)
 {
-    int32_t row[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) row[k] = ldx<NTL>(rows9, (int64_t)k * nEc + p);
-    float v[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const float g = rf[row[k] >= 0 ? row[k] : 0];
-        v[k] = row[k] >= 0 ? g : 0.0f;
-    }
-    const int32_t code = ldx<NTL>(ecode_c, p);
     float s[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) s[e] = PHF_CODE_TYPE(code, e) == 0 ? 0.5f : 1.0f;
@@ -298,6 +286,23 @@ __device__ inline void tri_restrict(int32_t p, int32_t nEc, PR9 __restrict__ row
     t[3 * (int64_t)p] = acc[0];
     t[3 * (int64_t)p + 1] = acc[1];
     t[3 * (int64_t)p + 2] = acc[2];
+}
+
+template <bool NTL = false, typename PR9, typename PE, typename PF, typename PT>
+__device__ inline void tri_restrict(int32_t p, int32_t nEc, PR9 __restrict__ rows9,
+                                    PE __restrict__ ecode_c, PF __restrict__ rf,
+                                    PT __restrict__ t)
+{
+    int32_t row[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) row[k] = ldx<NTL>(rows9, (int64_t)k * nEc + p);
+    float v[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const float g = rf[row[k] >= 0 ? row[k] : 0];
+        v[k] = row[k] >= 0 ? g : 0.0f;
+    }
+    tri_combine(p, ldx<NTL>(ecode_c, p), v, t);
 }
 
 // Restriction, second half: coarse row c sums its edge's entries from T+ and
@@ -566,6 +571,78 @@ __global__ __launch_bounds__(NT) void k_mg_prolong(int32_t n, const int32_t* __r
 {
     if (iflags && iflags[0]) return;
     phf_for_rows<XCD_PROLONG, NT>(n, [&](int32_t i) { row_prolong(i, n, P_col, P_code, xc, x); });
+}
+
+// On the levels whose launches are bound by latency rather than bytes, two
+// pairs of steps run as one launch each; every value is the one the separate
+// launches compute (the same expressions on the same operands), so the cycle
+// is bit-identical either way.
+// Residual and the restriction's first half: a lane per fine row of each
+// coarse triangle (nine lanes per triangle, RR_TRI triangles per workgroup)
+// forms the row's residual; the triangle's first lane combines the nine
+// values from LDS. Rows on an edge shared by two coarse triangles are formed
+// twice; the residual vector is neither written nor read back. Workgroups
+// are dealt to the XCDs in contiguous ranges of triangles, as the row
+// kernels are.
+constexpr int RR_TRI = NT / 9;
+__global__ __launch_bounds__(NT) void k_mg_resid_restrict(
+    int32_t nEc, const int32_t* __restrict__ rows9, const int32_t* __restrict__ ecode_c, int32_t n,
+    const int32_t* __restrict__ col, const float* __restrict__ val, const float* __restrict__ diag,
+    const float* __restrict__ bh, const float* __restrict__ x, float* __restrict__ t,
+    const int* iflags)
+{
+    if (iflags && iflags[0]) return;
+    __shared__ float sv[RR_TRI * 9];
+    // block b takes tile (the XCD permutation of the blocks, one tile each)
+    const int32_t nb = gridDim.x, b = blockIdx.x, xcd = b % 8, q = nb / 8, rem = nb % 8;
+    const int32_t tile = xcd * q + min(xcd, rem) + b / 8;
+    const int32_t lane = threadIdx.x, tl = lane / 9, k = lane - 9 * tl;
+    const int32_t p0 = tile * RR_TRI;
+    if (tl < RR_TRI && p0 + tl < nEc) {
+        const int32_t row = ldx<PHF_NT_MG>(rows9, (int64_t)k * nEc + p0 + tl);
+        float v = 0.0f;
+        if (row >= 0)  // the product rounded on its own, as row_resid stores it
+            v = __fmul_rn(diag[row], sres(row, n, col, val, bh, x));
+        sv[lane] = v;
+    }
+    __syncthreads();
+    const int32_t p = p0 + lane;
+    if (lane < RR_TRI && p < nEc) {
+        float v[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) v[j] = sv[9 * lane + j];
+        tri_combine(p, ldx<PHF_NT_MG>(ecode_c, p), v, t);
+    }
+}
+
+// Prolongation and the first sweep after it: row i forms the corrected
+// iterate x + P x_c at itself and at its four neighbours (each as row_prolong
+// would store it) and takes the sweep from those values into y; the
+// corrected iterate itself is not stored (the next sweep reads only y).
+__global__ __launch_bounds__(NT) void k_mg_prolong_smooth(
+    int32_t n, const int32_t* __restrict__ P_col, const uint32_t* __restrict__ P_code,
+    const float* __restrict__ xc, const int32_t* __restrict__ col, const float* __restrict__ val,
+    const float* __restrict__ bh, const float* __restrict__ w, int32_t k,
+    const float* __restrict__ x, float* __restrict__ y, const int* iflags)
+{
+    if (iflags && iflags[0]) return;
+    const float omega = w[k];
+    phf_for_rows<XCD_SMOOTH, NT>(n, [&](int32_t i) {
+        const auto xp = [&](int32_t j) {
+            float u = x[j];
+            u += prolong_sum<PHF_NT_MG>(j, n, P_col, P_code, xc);
+            return u;
+        };
+        const phf_i4 c = ld_row4(col, i);
+        const phf_f4 v = ld_row4(val, i);
+        const float xi = xp(i);
+        float s = 0.0f;
+        s = fmaf(v.x, xp(c.x), s);
+        s = fmaf(v.y, xp(c.y), s);
+        s = fmaf(v.z, xp(c.z), s);
+        s = fmaf(v.w, xp(c.w), s);
+        y[i] = xi + omega * (bh[i] - xi - s);
+    });
 }
 
 // The whole V-cycle on levels 0..top of the descriptor table in one
@@ -849,6 +926,22 @@ __global__ __launch_bounds__(NT) void k_mg_setup_rows(const phf_mg_setup_level* 
     }
 }
 
+// Levels of at most this many rows take the fused launches (residual with
+// restriction, prolongation with the first sweep after it). There the
+// launches are bound by latency and the fused forms' extra work costs less
+// than the launch they save (measured, µs per cycle on the levels of 24,576
+// and 98,304 rows: 4.5 / 5.7 fused against 8.9 / 8.1 for residual and
+// restriction, 5.3 / 9.2 against 8.4 / 9.4 for prolongation and sweep). On
+// larger levels the fused residual's scattered row loads (nine rows of a
+// coarse triangle per group of lanes) and the five prolongations per row cost
+// more: 15.5 against 10 µs at 393,216 rows.
+#ifndef PHF_MG_FUSE_RR_MAX
+#define PHF_MG_FUSE_RR_MAX 120000
+#endif
+#ifndef PHF_MG_FUSE_PS_MAX
+#define PHF_MG_FUSE_PS_MAX 50000
+#endif
+
 #ifndef PHF_MG_GRID_MAX
 #define PHF_MG_GRID_MAX (1 << 30)
 #endif
@@ -868,7 +961,7 @@ unsigned part_grid(int32_t n)
 // mesh, so per-launch byte counts can be attributed to a level.
 enum {
     NM_SMOOTH0, NM_SMOOTH, NM_SMOOTHZ, NM_RESID, NM_RESTRICT, NM_COLLECT, NM_PROLONG, NM_SMOOTH1,
-    NM_COUNT
+    NM_RESID_RESTRICT, NM_PROLONG_SMOOTH, NM_COUNT
 };
 struct mg_names {
     char s[NM_COUNT][PHF_MG_MAX_LEVELS][32];
@@ -876,7 +969,8 @@ struct mg_names {
     {
         static const char* base[NM_COUNT] = {"k_mg_smooth0", "k_mg_smooth", "k_mg_smooth_z",
                                              "k_mg_resid", "k_mg_restrict", "k_mg_collect",
-                                             "k_mg_prolong", "k_mg_smooth1"};
+                                             "k_mg_prolong", "k_mg_smooth1",
+                                             "k_mg_resid_restrict", "k_mg_prolong_smooth"};
         for (int k = 0; k < NM_COUNT; ++k)
             for (int l = 0; l < PHF_MG_MAX_LEVELS; ++l)
                 snprintf(s[k][l], sizeof(s[k][l]), "%s.L%d", base[k], l);
@@ -1217,11 +1311,20 @@ int vcycle(phf_mg* mg, int l, const double* r_top, bool first_done, double* z64,
         }
     }
     phf_mg_level& C = mg->lev[l - 1];
+    const int last = r_top ? mg->nu - 1 : mg->nu;
+    bool swept = false;  // the first sweep after the correction is taken
     if (C.nf > 0) {
-        PHF_LAUNCH(ctx, mg_name(NM_RESID, l), k_mg_resid, g, NT, 0, n, L.col4, L.val4, L.diag32,
-                   L.b, L.x, L.r, iflags);
-        PHF_LAUNCH(ctx, mg_name(NM_RESTRICT, l), k_mg_restrict, grid_for(C.mesh->nE), NT, 0,
-                   C.mesh->nE, L.rows9, C.mesh->ecode, L.r, L.t, iflags);
+        if (n <= PHF_MG_FUSE_RR_MAX) {
+            const int32_t nEc = C.mesh->nE;
+            PHF_LAUNCH(ctx, mg_name(NM_RESID_RESTRICT, l), k_mg_resid_restrict,
+                       (unsigned)((nEc + RR_TRI - 1) / RR_TRI), NT, 0, nEc, L.rows9,
+                       C.mesh->ecode, n, L.col4, L.val4, L.diag32, L.b, L.x, L.t, iflags);
+        } else {
+            PHF_LAUNCH(ctx, mg_name(NM_RESID, l), k_mg_resid, g, NT, 0, n, L.col4, L.val4,
+                       L.diag32, L.b, L.x, L.r, iflags);
+            PHF_LAUNCH(ctx, mg_name(NM_RESTRICT, l), k_mg_restrict, grid_for(C.mesh->nE), NT, 0,
+                       C.mesh->nE, L.rows9, C.mesh->ecode, L.r, L.t, iflags);
+        }
         // the coarse level's first sweep lands where its cycle expects it:
         // the single-workgroup kernel in y (the coarsest level in x), the
         // per-step launches in the current x
@@ -1231,11 +1334,17 @@ int vcycle(phf_mg* mg, int l, const double* r_top, bool first_done, double* z64,
         PHF_LAUNCH(ctx, mg_name(NM_COLLECT, l), k_mg_collect, grid_for(C.nf), NT, 0, C.nf, C.sel,
                    L.t, C.dinv32, level_weights(mg, l - 1), kc, C.b, xc, iflags);
         TRY(vcycle(mg, l - 1, nullptr, false, nullptr, nullptr, nullptr, iflags));
-        PHF_LAUNCH(ctx, mg_name(NM_PROLONG, l), k_mg_prolong, g, NT, 0, n, L.P_col, L.P_code, C.x,
-                   L.x, iflags);
+        if (n <= PHF_MG_FUSE_PS_MAX && last > 0) {
+            PHF_LAUNCH(ctx, mg_name(NM_PROLONG_SMOOTH, l), k_mg_prolong_smooth, g, NT, 0, n,
+                       L.P_col, L.P_code, C.x, L.col4, L.val4, L.b, w, 0, L.x, L.y, iflags);
+            std::swap(L.x, L.y);
+            swept = true;
+        } else {
+            PHF_LAUNCH(ctx, mg_name(NM_PROLONG, l), k_mg_prolong, g, NT, 0, n, L.P_col, L.P_code,
+                       C.x, L.x, iflags);
+        }
     }
-    const int last = r_top ? mg->nu - 1 : mg->nu;
-    for (int s = 0; s < last; ++s) TRY(smooth(mg, l, s, iflags));
+    for (int s = swept ? 1 : 0; s < last; ++s) TRY(smooth(mg, l, s, iflags));
     if (r_top && z32)
         PHF_LAUNCH(ctx, mg_name(NM_SMOOTHZ, l), k_mg_smooth_z<float>, part_grid(n), NT, 0, n,
                    L.col4, L.val4,
