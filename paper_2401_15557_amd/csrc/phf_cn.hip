@@ -26,8 +26,11 @@ struct phf_cn {
     double *F0 = nullptr, *F1 = nullptr, *bD0 = nullptr, *bD1 = nullptr;
     double *r1 = nullptr, *r2 = nullptr;
     int64_t* d_step = nullptr;  // index n of the step being computed
-    double *w1 = nullptr, *w2 = nullptr;  // reduced solutions of the last two steps
-    int32_t* d_nsol = nullptr;            // solves since set_state (0, 1, 2+)
+    // reduced solutions of the last four steps (a ring of four vectors of
+    // n_free values) and, on the device, {solves since set_state capped at 4,
+    // ring slot of the latest}
+    double* wr = nullptr;
+    int32_t* d_nsol = nullptr;
     double* d_stats = nullptr;  // [0] CG iterations, [1] worst relres, [2] unconverged steps
     double t0 = 0;
     int64_t n = 0;              // completed steps since set_state
@@ -57,27 +60,48 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 
 __global__ void k_cn_inc(int64_t* step) { *step += 1; }
 
-// Initial CG guess from the last two reduced solutions: 0, w1, or the linear
-// extrapolation 2 w1 - w2 (second order in k for a smooth trajectory).
+// Initial CG guess from the reduced solutions of the last time levels, w1
+// (latest) to w4. Crank-Nicolson leaves the stiff error modes undamped (their
+// amplification factor tends to -1), so beside its smooth part the sequence
+// of solutions alternates in sign from step to step; a smooth extrapolation
+// (2 w1 - w2) errs by four times that component and needs as many
+// iterations as starting from w1. With four levels the guess is exact for a
+// quadratic trend plus a constant alternation, 2 (w1 - w3) + w4; with three,
+// for a linear trend plus the alternation, w2 + (w1 - w3); with one or two,
+// w1; with none, 0.
+constexpr int CN_RING = 4;
 __global__ __launch_bounds__(NT) void k_cn_guess(int32_t nf, const int32_t* __restrict__ nsol,
-                                                 const double* __restrict__ w1,
-                                                 const double* __restrict__ w2,
+                                                 const double* __restrict__ wr,
                                                  double* __restrict__ w)
 {
-    const int32_t c = *nsol;
-    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT)
-        w[i] = c == 0 ? 0.0 : (c == 1 ? w1[i] : 2.0 * w1[i] - w2[i]);
+    const int32_t c = nsol[0], h = nsol[1];
+    const double* w1 = wr + (int64_t)h * nf;
+    const double* w2 = wr + (int64_t)((h + 3) % CN_RING) * nf;
+    const double* w3 = wr + (int64_t)((h + 2) % CN_RING) * nf;
+    const double* w4 = wr + (int64_t)((h + 1) % CN_RING) * nf;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
+        double g = 0.0;
+        if (c >= 4) g = 2.0 * (w1[i] - w3[i]) + w4[i];
+        else if (c == 3) g = w2[i] + (w1[i] - w3[i]);
+        else if (c >= 1) g = w1[i];
+        w[i] = g;
+    }
 }
 
-__global__ __launch_bounds__(NT) void k_cn_keep(int32_t nf, int32_t* __restrict__ nsol,
+// The step's solution into the next ring slot (one vector written, none
+// moved); a one-thread kernel then advances the counters.
+__global__ __launch_bounds__(NT) void k_cn_keep(int32_t nf, const int32_t* __restrict__ nsol,
                                                 const double* __restrict__ w,
-                                                double* __restrict__ w1, double* __restrict__ w2)
+                                                double* __restrict__ wr)
 {
-    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) {
-        w2[i] = w1[i];
-        w1[i] = w[i];
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *nsol = min(*nsol + 1, 2);
+    double* dst = wr + (int64_t)((nsol[1] + 1) % CN_RING) * nf;
+    for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) dst[i] = w[i];
+}
+
+__global__ void k_cn_keep_count(int32_t* __restrict__ nsol)
+{
+    nsol[0] = min(nsol[0] + 1, CN_RING);
+    nsol[1] = (nsol[1] + 1) % CN_RING;
 }
 
 // A- = cM M - cK K per element block, once per stepper.
@@ -197,7 +221,7 @@ int cn_step_head(phf_cn* cn, const phf_data* data)
     TRY(phf_ns_rhs(cn->ns, cn->r1, cn->r2));
     if (cn->ns->nf > 0)
         PHF_LAUNCH(ctx, "k_cn_guess", k_cn_guess, cn->ns->nbv, NT, 0, cn->ns->nf, cn->d_nsol,
-                   cn->w1, cn->w2, cn->ns->w);
+                   cn->wr, cn->ns->w);
     TRY(phf_ns_cg_start(cn->ns, cn->opts.rtol));
     return PHF_OK;
 }
@@ -208,9 +232,11 @@ int cn_step_tail(phf_cn* cn)
     phf_ctx* ctx = mesh->ctx;
     const int32_t N = 3 * mesh->nE, L = mesh->L;
     TRY(phf_ns_recover(cn->ns, cn->r1, cn->U, cn->Lam, 2.0 / cn->k));
-    if (cn->ns->nf > 0)
+    if (cn->ns->nf > 0) {
         PHF_LAUNCH(ctx, "k_cn_keep", k_cn_keep, cn->ns->nbv, NT, 0, cn->ns->nf, cn->d_nsol,
-                   cn->ns->w, cn->w1, cn->w2);
+                   cn->ns->w, cn->wr);
+        PHF_LAUNCH(ctx, "k_cn_keep_count", k_cn_keep_count, 1, 1, 0, cn->d_nsol);
+    }
     PHF_LAUNCH(ctx, "k_cn_shift", k_cn_shift, nblk((int64_t)N + L), NT, 0, N, L, cn->F0, cn->F1,
                cn->bD0, cn->bD1);
     PHF_LAUNCH(ctx, "k_cn_stats", k_cn_stats, 1, 1, 0, cn->ns->iflags, cn->ns->scal, cn->d_stats);
@@ -306,8 +332,7 @@ extern "C" int phf_cn_destroy(phf_cn* cn)
                       cn->F1, cn->bD0, cn->bD1, cn->r1, cn->r2, cn->d_stats};
     for (double* b : bufs) phf_dfree(b);
     phf_dfree(cn->d_step);
-    phf_dfree(cn->w1);
-    phf_dfree(cn->w2);
+    phf_dfree(cn->wr);
     phf_dfree(cn->d_nsol);
     delete cn;
     return PHF_OK;
@@ -357,9 +382,9 @@ extern "C" int phf_cn_create(phf_mesh* mesh, const phf_coeffs* co, double k,
         TRY(phf_dmalloc(ctx, &cn->r2, L, "CN r2"));
         TRY(phf_dmalloc(ctx, &cn->d_stats, 4, "CN stats"));
         TRY(phf_dmalloc(ctx, &cn->d_step, 1, "CN step"));
-        TRY(phf_dmalloc(ctx, &cn->w1, std::max<int32_t>(mesh->n_free, 1), "CN w1"));
-        TRY(phf_dmalloc(ctx, &cn->w2, std::max<int32_t>(mesh->n_free, 1), "CN w2"));
-        TRY(phf_dmalloc(ctx, &cn->d_nsol, 1, "CN solves"));
+        TRY(phf_dmalloc(ctx, &cn->wr, CN_RING * (size_t)std::max<int32_t>(mesh->n_free, 1),
+                        "CN solution ring"));
+        TRY(phf_dmalloc(ctx, &cn->d_nsol, 2, "CN solves"));
         // K, M, C once (the coefficient is time independent)
         phf_system s{};
         s.K = cn->K;
@@ -412,7 +437,7 @@ extern "C" int phf_cn_set_state(phf_cn* cn, const double* U, const double* Lambd
     cn->n = 0;
     cn->have_state = true;
     TRY(phf_ns_zero_w(cn->ns));
-    PHF_HIP(ctx, hipMemsetAsync(cn->d_nsol, 0, sizeof(int32_t), ctx->stream));
+    PHF_HIP(ctx, hipMemsetAsync(cn->d_nsol, 0, 2 * sizeof(int32_t), ctx->stream));
     return PHF_OK;
 }
 

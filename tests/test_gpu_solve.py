@@ -335,6 +335,41 @@ def test_cn_multigrid_parity(ctx, oracle, use_graph):
     phfem.phf_cn_destroy(cn)
 
 
+def test_cn_start_guess_iterations(ctx, oracle):
+    """The start of each step's CG solve extrapolates the last four reduced
+    solutions exactly for a quadratic trend plus the sign-alternating part
+    of the undamped stiff modes; on the paper mesh refined 6 times with
+    k = 1e-3 that takes the multigrid CG from 5 (linear extrapolation) to 4
+    iterations per step, and the state still matches the oracle's
+    Crank-Nicolson after 40 steps."""
+    import torch
+    from paper_2401_15557_amd import phfem
+    dm, m = _refined_pair(ctx, oracle, G.paper_square(0, bc="x_sides"), 6)
+    k = 1e-3
+    tables = oracle.mesh_tables(m)
+    U0 = oracle.cr_interpolant(m, lambda x, y, t: np.sin(PI * x) * np.sin(PI * y))
+    L0 = np.zeros(tables["L"])
+    od = dict(f=oracle.fn(oracle.FN_SIN_SIN, 2 * PI * PI - 1, -1),
+              g=oracle.fn(oracle.FN_GRAD_SIN_SIN, 1, -1), uD=oracle.fn(oracle.FN_SIN_SIN, 1, -1))
+    gd = phfem.make_data(phfem.make_fn(phfem.PHF_FN_SIN_SIN, 2 * PI * PI - 1, -1),
+                         phfem.make_fn(phfem.PHF_FN_GRAD_SIN_SIN, 1, -1),
+                         phfem.make_fn(phfem.PHF_FN_SIN_SIN, 1, -1))
+    cn = phfem.phf_cn_create(dm.handle, phfem.make_coeffs(), k, rtol=1e-10, iters_per_step=8,
+                             precond=phfem.PHF_PRECOND_MULTIGRID)
+    phfem.phf_cn_set_state(cn, torch.tensor(U0, device=ctx.device),
+                           torch.tensor(L0, device=ctx.device), 0.0)
+    st1 = phfem.phf_cn_run(cn, gd, 10, use_graph=True)
+    st2 = phfem.phf_cn_run(cn, gd, 30, use_graph=True)
+    print(f"iterations: first 10 steps {st1.iterations}, next 30 {st2.iterations}", flush=True)
+    assert st1.converged and st2.converged
+    assert st2.iterations <= 4 * 30
+    Ug, Lg, t = _get(ctx, cn, dm)
+    assert t == pytest.approx(40 * k)
+    Uo, Lo, _ = oracle.cn_run(m, tables, k, 40, U0, L0, **od)
+    assert _rel(Ug, Uo) < 1e-8, _rel(Ug, Uo)
+    phfem.phf_cn_destroy(cn)
+
+
 @pytest.mark.parametrize("precond", ["multigrid", "jacobi"])
 def test_solve_interior_constraint_rhs(ctx, oracle, precond):
     """A constraint right-hand side that is non-zero on interior multiplier
