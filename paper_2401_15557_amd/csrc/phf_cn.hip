@@ -476,10 +476,13 @@ extern "C" int phf_cn_run(phf_cn* cn, const phf_data* data, int32_t nsteps, int3
     for (int32_t s = 0; s < nsteps; ++s) {
         phf_trace_rec rec;
         phf_trace_begin(ctx, use_graph ? "cn_graph_step" : "cn_step", &rec);
-        // head and first iteration, then (predicted - 2) rounded down to
-        // pairs without reading the flag, then pairs until converged
+        // head and first iteration, then the rest of the predicted count
+        // (the last step's) rounded down to pairs without reading the flag,
+        // then pairs until converged: a step that needs as many iterations as
+        // the last one reads the flag once (measured: 640 -> 648 steps/s
+        // against holding back one more iteration)
         int32_t it = 1;
-        const int32_t blind = std::max<int32_t>(cn->predict - 2, 0) & ~1;
+        const int32_t blind = std::max<int32_t>(cn->predict - 1, 0) & ~1;
         if (use_graph) {
             PHF_HIP(ctx, hipGraphLaunch(cn->gx[0], ctx->stream));
             for (int q = phf_cn::NG - 2; q >= 1; --q)
