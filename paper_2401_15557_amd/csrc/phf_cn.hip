@@ -25,7 +25,7 @@ struct phf_cn {
     double *U = nullptr, *Lam = nullptr;
     double *F0 = nullptr, *F1 = nullptr, *bD0 = nullptr, *bD1 = nullptr;
     double *r1 = nullptr, *r2 = nullptr;
-    int64_t* d_step = nullptr;  // index n of the step being computed
+    int64_t* d_step = nullptr;  // index n of the step being (or next) computed
     // reduced solutions of the last four steps (a ring of four vectors of
     // n_free values) and, on the device, {solves since set_state capped at 4,
     // ring slot of the latest}
@@ -58,8 +58,6 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
         if (rc_) return rc_; \
     } while (0)
 
-__global__ void k_cn_inc(int64_t* step) { *step += 1; }
-
 // Initial CG guess from the reduced solutions of the last time levels, w1
 // (latest) to w4. Crank-Nicolson leaves the stiff error modes undamped (their
 // amplification factor tends to -1), so beside its smooth part the sequence
@@ -89,7 +87,7 @@ __global__ __launch_bounds__(NT) void k_cn_guess(int32_t nf, const int32_t* __re
 }
 
 // The step's solution into the next ring slot (one vector written, none
-// moved); a one-thread kernel then advances the counters.
+// moved); k_cn_close then advances the counters.
 __global__ __launch_bounds__(NT) void k_cn_keep(int32_t nf, const int32_t* __restrict__ nsol,
                                                 const double* __restrict__ w,
                                                 double* __restrict__ wr)
@@ -98,11 +96,6 @@ __global__ __launch_bounds__(NT) void k_cn_keep(int32_t nf, const int32_t* __res
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) dst[i] = w[i];
 }
 
-__global__ void k_cn_keep_count(int32_t* __restrict__ nsol)
-{
-    nsol[0] = min(nsol[0] + 1, CN_RING);
-    nsol[1] = (nsol[1] + 1) % CN_RING;
-}
 
 // A- = cM M - cK K per element block, once per stepper.
 // (Am may be K itself: each element is read before it is written.)
@@ -115,12 +108,13 @@ __global__ __launch_bounds__(NT) void k_cn_aminus(int64_t n, const double* K,
 }
 
 // r1 per element (see file comment); the tile's A- blocks go through LDS so
-// that they are read with coalesced accesses.
+// that they are read with coalesced accesses. F0 (the load at t_{n-1}) then
+// takes F1's values, the next step's F0.
 __global__ __launch_bounds__(NT) void k_cn_rhs_elem(
     int32_t nE, const int32_t* __restrict__ ecode, const double* __restrict__ Am,
     const double* __restrict__ U, const double* __restrict__ Lam,
     const int32_t* __restrict__ elem_row, const double* __restrict__ row_hs,
-    const double* __restrict__ F0, const double* __restrict__ F1, double hk,
+    double* __restrict__ F0, const double* __restrict__ F1, double hk,
     double* __restrict__ r1)
 {
     __shared__ double sA[9 * NT];
@@ -154,16 +148,19 @@ __global__ __launch_bounds__(NT) void k_cn_rhs_elem(
         double ctl = 0.0;
 #pragma unroll
         for (int l = 0; l < 3; ++l) ctl += (l == i) ? 0.0 : lt[l];
-        r1[3 * m + i] = au + hk * ctl + hk * (F0[3 * m + i] + F1[3 * m + i]);
+        const double f0 = F0[3 * m + i], f1 = F1[3 * m + i];
+        r1[3 * m + i] = au + hk * ctl + hk * (f0 + f1);
+        F0[3 * m + i] = f1;
     }
 }
 
-// r2 per multiplier row: (C U)_r + b_D^{n-1} + b_D^n.
+// r2 per multiplier row: (C U)_r + b_D^{n-1} + b_D^n; bD0 then takes bD1's
+// value, the next step's b_D^{n-1}.
 __global__ __launch_bounds__(NT) void k_cn_rhs_row(int32_t L, const int32_t* __restrict__ C_rowptr,
                                                    const int32_t* __restrict__ C_col,
                                                    const double* __restrict__ C,
                                                    const double* __restrict__ U,
-                                                   const double* __restrict__ bD0,
+                                                   double* __restrict__ bD0,
                                                    const double* __restrict__ bD1,
                                                    double* __restrict__ r2)
 {
@@ -171,26 +168,28 @@ __global__ __launch_bounds__(NT) void k_cn_rhs_row(int32_t L, const int32_t* __r
     if (r >= L) return;
     double s = 0.0;
     for (int32_t q = C_rowptr[r]; q < C_rowptr[r + 1]; ++q) s += C[q] * U[C_col[q]];
-    r2[r] = s + bD0[r] + bD1[r];
+    const double b0 = bD0[r], b1 = bD1[r];
+    r2[r] = s + b0 + b1;
+    bD0[r] = b1;
 }
 
-__global__ __launch_bounds__(NT) void k_cn_shift(int32_t N, int32_t L, double* __restrict__ F0,
-                                                 const double* __restrict__ F1,
-                                                 double* __restrict__ bD0,
-                                                 const double* __restrict__ bD1)
-{
-    int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (g < N) F0[g] = F1[g];
-    else if (g < (int64_t)N + L) bD0[g - N] = bD1[g - N];
-}
-
-__global__ void k_cn_stats(const int* __restrict__ iflags, const double* __restrict__ scal,
-                           double* __restrict__ st)
+// The step's scalars, in one thread after the step: the solve statistics
+// (iterations, worst relative residual, unconverged steps), the ring
+// counters of k_cn_keep (when there are free unknowns) and the step index
+// the next step's loads are evaluated at.
+__global__ void k_cn_close(const int* __restrict__ iflags, const double* __restrict__ scal,
+                           double* __restrict__ st, int32_t* __restrict__ nsol,
+                           int64_t* __restrict__ step)
 {
     st[0] += iflags[1];
     double rel = scal[NS_BB] > 0 ? sqrt(scal[NS_RR] / scal[NS_BB]) : 0.0;
     st[1] = fmax(st[1], rel);
     st[2] += iflags[0] ? 0.0 : 1.0;
+    if (nsol) {
+        nsol[0] = min(nsol[0] + 1, CN_RING);
+        nsol[1] = (nsol[1] + 1) % CN_RING;
+    }
+    *step += 1;
 }
 
 int cn_loads(phf_cn* cn, const phf_data* data, double* F, double* bD, bool from_device)
@@ -210,7 +209,6 @@ int cn_step_head(phf_cn* cn, const phf_data* data)
     phf_mesh* mesh = cn->mesh;
     phf_ctx* ctx = mesh->ctx;
     const int32_t nE = mesh->nE, L = mesh->L;
-    PHF_LAUNCH(ctx, "k_cn_inc", k_cn_inc, 1, 1, 0, cn->d_step);
     TRY(cn_loads(cn, data, cn->F1, cn->bD1, true));
     const double hk = 0.5 * cn->k;
     PHF_LAUNCH(ctx, "k_cn_rhs_elem", k_cn_rhs_elem, nblk(nE), NT, 0, nE, mesh->ecode, cn->Am,
@@ -218,7 +216,7 @@ int cn_step_head(phf_cn* cn, const phf_data* data)
     if (L > 0)
         PHF_LAUNCH(ctx, "k_cn_rhs_row", k_cn_rhs_row, nblk(L), NT, 0, L, mesh->C_rowptr,
                    mesh->C_col, cn->C, cn->U, cn->bD0, cn->bD1, cn->r2);
-    TRY(phf_ns_rhs(cn->ns, cn->r1, cn->r2));
+    TRY(phf_ns_rhs(cn->ns, cn->r1, cn->r2, true));  // CU + b_D has interior jumps
     if (cn->ns->nf > 0)
         PHF_LAUNCH(ctx, "k_cn_guess", k_cn_guess, cn->ns->nbv, NT, 0, cn->ns->nf, cn->d_nsol,
                    cn->wr, cn->ns->w);
@@ -230,16 +228,13 @@ int cn_step_tail(phf_cn* cn)
 {
     phf_mesh* mesh = cn->mesh;
     phf_ctx* ctx = mesh->ctx;
-    const int32_t N = 3 * mesh->nE, L = mesh->L;
     TRY(phf_ns_recover(cn->ns, cn->r1, cn->U, cn->Lam, 2.0 / cn->k));
-    if (cn->ns->nf > 0) {
+    const bool keep = cn->ns->nf > 0;
+    if (keep)
         PHF_LAUNCH(ctx, "k_cn_keep", k_cn_keep, cn->ns->nbv, NT, 0, cn->ns->nf, cn->d_nsol,
                    cn->ns->w, cn->wr);
-        PHF_LAUNCH(ctx, "k_cn_keep_count", k_cn_keep_count, 1, 1, 0, cn->d_nsol);
-    }
-    PHF_LAUNCH(ctx, "k_cn_shift", k_cn_shift, nblk((int64_t)N + L), NT, 0, N, L, cn->F0, cn->F1,
-               cn->bD0, cn->bD1);
-    PHF_LAUNCH(ctx, "k_cn_stats", k_cn_stats, 1, 1, 0, cn->ns->iflags, cn->ns->scal, cn->d_stats);
+    PHF_LAUNCH(ctx, "k_cn_close", k_cn_close, 1, 1, 0, cn->ns->iflags, cn->ns->scal, cn->d_stats,
+               keep ? cn->d_nsol : nullptr, cn->d_step);
     return PHF_OK;
 }
 
@@ -463,7 +458,7 @@ extern "C" int phf_cn_run(phf_cn* cn, const phf_data* data, int32_t nsteps, int3
         return phf_set_error(ctx, PHF_EINVAL, "phf_cn_run: unknown function kind or missing edge array");
     // loads at the current time and the device step counter
     TRY(cn_loads(cn, data, cn->F0, cn->bD0, false));
-    int64_t n_host = cn->n;
+    int64_t n_host = cn->n + 1;  // index of the next step
     PHF_HIP(ctx, hipMemcpyAsync(cn->d_step, &n_host, sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
     PHF_HIP(ctx, hipMemsetAsync(cn->d_stats, 0, 4 * sizeof(double), ctx->stream));
     PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -693,7 +688,7 @@ extern "C" int phf_cn_batch_run(phf_cn_batch* b, const phf_data* data, int32_t n
         b->budget[i] = std::max(b->budget[i], cnb_budget(cn->predict));
         // loads at the current time, the device step counter, the statistics
         TRY(cn_loads(cn, &d, cn->F0, cn->bD0, false));
-        int64_t n_host = cn->n;
+        int64_t n_host = cn->n + 1;  // index of the next step
         PHF_HIP(ctx, hipMemcpyAsync(cn->d_step, &n_host, sizeof(int64_t), hipMemcpyHostToDevice,
                                     ctx->stream));
         PHF_HIP(ctx, hipMemsetAsync(cn->d_stats, 0, 4 * sizeof(double), ctx->stream));

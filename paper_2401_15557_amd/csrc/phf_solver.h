@@ -104,7 +104,9 @@ void phf_ns_destroy(phf_ns* ns);
 int phf_ns_operator(phf_ns* ns, const double* K, const double* M, double cK, double cM,
                     const double* D = nullptr, double cD = 0.0, bool borrow_K = false);
 // Right-hand side reduction (rhs2 is the right-hand side of -C U = rhs2).
-int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2);
+// all_jumps: take the T+-side jumps of every interior row without testing
+// rhs2 for them (a caller whose constraint right-hand side has them anyway).
+int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2, bool all_jumps = false);
 // Starts CG from the current w, or with zero_start from w = 0 (written by
 // the start itself).
 int phf_ns_cg_start(phf_ns* ns, double rtol, bool zero_start = false);

@@ -170,11 +170,11 @@ __global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int32_t* __re
                                                  const double* __restrict__ rhs1,
                                                  const double* __restrict__ rhs2,
                                                  const double* __restrict__ A,
-                                                 const int* __restrict__ jflag,
+                                                 const int* __restrict__ jflag, int all_jumps,
                                                  double* __restrict__ kv, double* __restrict__ cs)
 {
     __shared__ double sR[3 * NT], sK[3 * NT], sC[3 * NT];
-    const bool jumps = *jflag != 0;
+    const bool jumps = all_jumps || *jflag != 0;
     const int tid = threadIdx.x;
     const int64_t m0 = (int64_t)blockIdx.x * NT;
     const int32_t nt = (int32_t)min((int64_t)NT, (int64_t)nE - m0);
@@ -874,16 +874,17 @@ int phf_ns_operator(phf_ns* ns, const double* K, const double* M, double cK, dou
     return PHF_OK;
 }
 
-int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2)
+int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2, bool all_jumps)
 {
     phf_mesh* mesh = ns->mesh;
     phf_ctx* ctx = mesh->ctx;
-    if (ns->L > 0)
+    if (ns->L > 0 && !all_jumps)
         PHF_LAUNCH(ctx, "k_ns_jumpflag", k_ns_jumpflag,
                    (unsigned)std::min<int64_t>(nblk(ns->L), 1024), NT, 0, ns->L, mesh->row_nodes,
                    rhs2, ns->jflag);
     PHF_LAUNCH(ctx, "k_ns_known", k_ns_known, nblk(ns->nE), NT, 0, ns->nE, mesh->ecode,
-               ns->elem_row, mesh->row_hs, rhs1, rhs2, ns->A, ns->jflag, ns->kv, ns->cs);
+               ns->elem_row, mesh->row_hs, rhs1, rhs2, ns->A, ns->jflag, all_jumps ? 1 : 0,
+               ns->kv, ns->cs);
     if (ns->nf > 0)
         PHF_LAUNCH(ctx, "k_ns_gather", k_ns_gather, nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge,
                    mesh->edge_elems, mesh->led, mesh->ledTN, ns->cs, ns->b, ns->jflag);
