@@ -830,11 +830,21 @@ __global__ void k_mg_lmax_clear(int32_t nlev, uint32_t* __restrict__ lmax)
 // of the degree-nu Chebyshev polynomial mapped to [lo, hi] = [lmax / range,
 // lmax] (c, h its centre and half-width), and 1 / c (the best single weight
 // for that interval) for the plain sweeps of an iterative coarsest solve.
-__global__ void k_mg_weights(int32_t nlev, int32_t nu, int32_t cheb, float omega, float range,
-                             const uint32_t* __restrict__ lmax, float* __restrict__ wts)
+// Sweeps per side on the levels between the finest and the single-workgroup
+// tail: one fewer than on those two. Measured with nu = 4 on the paper mesh
+// (levels of 24,576-1,572,864 rows between them): 3 sweeps there kept the
+// iterations (elliptic solve at 4,194,304 triangles 7, Crank-Nicolson 3.04 ->
+// 3.06 per step) and took the solve from 7.49 to 7.10 ms and the stepper
+// from 657 to 689 steps/s; 2 sweeps raised the iterations to 10 and 4.07.
+__host__ __device__ constexpr int32_t mid_sweeps(int32_t nu) { return nu > 1 ? nu - 1 : 1; }
+
+__global__ void k_mg_weights(int32_t nlev, int32_t tail_top, int32_t nu0, int32_t cheb,
+                             float omega, float range, const uint32_t* __restrict__ lmax,
+                             float* __restrict__ wts)
 {
     const int32_t l = threadIdx.x;
     if (l >= nlev) return;
+    const int32_t nu = l > tail_top && l < nlev - 1 ? mid_sweeps(nu0) : nu0;
     float* w = wts + (int64_t)l * PHF_MG_WSTRIDE;
     if (!cheb) {
         for (int k = 0; k < PHF_MG_WSTRIDE; ++k) w[k] = omega;
@@ -1237,7 +1247,8 @@ int phf_mg_numeric(phf_mg* mg, const phf_coeffs* co, double cK, double cM)
     if (row_blocks > 0)
         PHF_LAUNCH(ctx, "k_mg_setup_rows", k_mg_setup_rows, row_blocks, NT, 0, mg->d_setup,
                    mg->nlev, cheb ? 1 : 0, mg->lmax);
-    PHF_LAUNCH(ctx, "k_mg_weights", k_mg_weights, 1, PHF_MG_MAX_LEVELS, 0, mg->nlev, mg->nu,
+    PHF_LAUNCH(ctx, "k_mg_weights", k_mg_weights, 1, PHF_MG_MAX_LEVELS, 0, mg->nlev,
+               mg->tail_top, mg->nu,
                cheb ? 1 : 0, (float)mg->omega, (float)mg->range, mg->lmax, mg->wts);
     if (mg->cinv) {
         const int32_t n0 = mg->n0;
@@ -1295,13 +1306,14 @@ int vcycle(phf_mg* mg, int l, const double* r_top, bool first_done, double* z64,
     }
     const unsigned g = grid_for(n);
     const float* w = level_weights(mg, l);
+    const int nu = r_top ? mg->nu : mid_sweeps(mg->nu);  // sweeps per side on this level
     // (on the finest level the second sweep forms the first from D^-1 b, which
     // is then not stored, unless it is the only sweep)
     const bool form1 = r_top && mg->nu >= 2;
     if (r_top && !first_done)
         PHF_LAUNCH(ctx, mg_name(NM_SMOOTH0, l), k_mg_smooth0_top, g, NT, 0, n, L.dinv32, r_top, w,
                    L.b, form1 ? nullptr : L.x, iflags);
-    for (int s = 1; s < mg->nu; ++s) {
+    for (int s = 1; s < nu; ++s) {
         if (s == 1 && form1) {
             PHF_LAUNCH(ctx, mg_name(NM_SMOOTH1, l), k_mg_smooth1_top, g, NT, 0, n, L.col4, L.val4,
                        L.b, w, L.y, iflags);
@@ -1311,7 +1323,7 @@ int vcycle(phf_mg* mg, int l, const double* r_top, bool first_done, double* z64,
         }
     }
     phf_mg_level& C = mg->lev[l - 1];
-    const int last = r_top ? mg->nu - 1 : mg->nu;
+    const int last = r_top ? nu - 1 : nu;
     bool swept = false;  // the first sweep after the correction is taken
     if (C.nf > 0) {
         if (n <= PHF_MG_FUSE_RR_MAX) {
