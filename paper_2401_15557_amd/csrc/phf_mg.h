@@ -142,6 +142,10 @@ struct phf_mg {
     phf_mg_setup_level* d_setup = nullptr;
     int32_t setup_table_blocks = 0, setup_row_blocks = 0;
     int32_t nu = 2;          // sweeps before and after the coarse correction
+    // plain sweeps of the coarsest level when it has no dense inverse (even,
+    // so that the result ends where the first sweep started): 40, or 8 when
+    // the coarsest levels were left out for a mass-dominated operator
+    int32_t coarse_sweeps = 40;
     int32_t smoother = 0;    // PHF_MG_SMOOTH_JACOBI or PHF_MG_SMOOTH_CHEBYSHEV
     double omega = 0.8;      // Jacobi damping
     double range = 4.0;      // Chebyshev: smoothing range [lmax / range, lmax]
@@ -175,7 +179,7 @@ struct phf_mg_top {
 
 // Builds the hierarchy below the finest operator `fine` (whose mesh must come
 // from phf_mesh_refine). Symbolic part only; call phf_mg_numeric next.
-int phf_mg_create(phf_ns* fine, phf_mg** out);
+int phf_mg_create(phf_ns* fine, phf_mg** out, int32_t drop_coarse = 0);
 void phf_mg_destroy(phf_mg* mg);
 // Coarse operators for A = cK K + cM M with the finest-level triangle
 // coefficient aT (nullable, constant A from coeffs), prolongations, coarse

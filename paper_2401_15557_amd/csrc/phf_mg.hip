@@ -655,7 +655,7 @@ __global__ __launch_bounds__(NT) void k_mg_prolong_smooth(
 // 0: L.x), written by the restriction from the level above; lower levels
 // receive theirs the same way inside the kernel. Every level then takes
 // 2 nu - 1 more sweeps, an odd number; the coarsest level solves directly, or
-// takes 40 further sweeps (an even number) from its first one. The top
+// takes an even number of further sweeps (csweeps) from its first one. The top
 // level's result is stored to L.x.
 constexpr int TAIL_NT = 1024;
 // The level descriptor as the single-workgroup kernel uses it: device-memory
@@ -708,7 +708,8 @@ __device__ inline void tail_rows(int32_t n, int32_t tid, F f, S st)
 __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __restrict__ lv,
                                                      int32_t top, int32_t nu,
                                                      const double* __restrict__ cinv,
-                                                     int32_t dense, const int* iflags)
+                                                     int32_t dense, int32_t csweeps,
+                                                     const int* iflags)
 {
     if (iflags && iflags[0]) return;
     extern __shared__ float lds[];
@@ -773,7 +774,7 @@ __global__ __launch_bounds__(TAIL_NT) void k_mg_tail(const phf_mg_dev_level* __r
         } else {
             float *u = x, *v = lds + L.sy;
             const float omega = L.w[PHF_MG_MAX_SWEEPS];
-            for (int32_t s = 0; s < 40; ++s) {
+            for (int32_t s = 0; s < csweeps; ++s) {
                 tail_rows(
                     L.n, tid,
                     [&](int32_t i) { return u[i] + omega * sres(i, L.n, L.col, L.val, bh, u); },
@@ -1028,19 +1029,23 @@ void phf_mg_destroy(phf_mg* mg)
     delete mg;
 }
 
-int phf_mg_create(phf_ns* fine, phf_mg** out)
+int phf_mg_create(phf_ns* fine, phf_mg** out, int32_t drop_coarse)
 {
     phf_mesh* fm = fine->mesh;
     phf_ctx* ctx = fm->ctx;
     *out = nullptr;
-    const int32_t nlev = phf_mg_levels(fm);
-    if (nlev < 2 || nlev > PHF_MG_MAX_LEVELS)
+    const int32_t chain = phf_mg_levels(fm);
+    if (chain < 2 || chain > PHF_MG_MAX_LEVELS)
         return phf_set_error(ctx, PHF_EINVAL,
                              "multigrid needs a mesh made by phf_mesh_refine (1..%d refinements)",
                              PHF_MG_MAX_LEVELS - 1);
+    // at least two levels stay
+    const int32_t drop = std::max<int32_t>(0, std::min<int32_t>(drop_coarse, chain - 2));
+    const int32_t nlev = chain - drop;
     phf_mg* mg = new (std::nothrow) phf_mg;
     if (!mg) return phf_set_error(ctx, PHF_ENOMEM, "host allocation failed");
     mg->nlev = nlev;
+    if (drop > 0) mg->coarse_sweeps = 8;
     auto body = [&]() -> int {
         phf_mesh* m = fm;
         for (int l = nlev - 1; l >= 0; --l, m = m->parent) mg->lev[l].mesh = m;
@@ -1079,7 +1084,7 @@ int phf_mg_create(phf_ns* fine, phf_mg** out)
             TRY(phf_dmalloc(ctx, &Cl.sel, (size_t)std::max(nc, 1), "multigrid restriction map"));
         }
         mg->n0 = mg->lev[0].nf;
-        if (mg->n0 > 0 && mg->n0 <= PHF_MG_DENSE_MAX) {
+        if (mg->n0 > 0 && mg->n0 <= PHF_MG_DENSE_MAX && drop == 0) {  // (else: sweeps)
             TRY(phf_dmalloc(ctx, &mg->cinv, (size_t)mg->n0 * mg->n0, "coarse inverse"));
             TRY(phf_dmalloc(ctx, &mg->cwork, (size_t)mg->n0 * mg->n0, "coarse work"));
             TRY(phf_dmalloc(ctx, &mg->col64, 5 * (size_t)mg->n0, "coarse operator columns"));
@@ -1282,7 +1287,7 @@ int smooth(phf_mg* mg, int l, int k, const int* iflags)
 
 // Cycle on level l > tail_top. On entry L.b holds D^-1 b and L.x the first
 // sweep from zero (a coarsest level outside the single-workgroup kernel then
-// takes 40 further plain sweeps, an even number, so its result is in L.x),
+// takes coarse_sweeps further plain sweeps, an even number, so its result is in L.x),
 // except on the finest level (r_top != null), where this
 // function starts from the double-precision residual r_top (unless
 // first_done) and the last sweep writes z (z64 or z32) and the partial sums
@@ -1295,13 +1300,14 @@ int vcycle(phf_mg* mg, int l, const double* r_top, bool first_done, double* z64,
     if (l <= mg->tail_top) {
         // this level and all below in one workgroup; the result is in L.x
         PHF_LAUNCH(ctx, "k_mg_tail", k_mg_tail, 1, TAIL_NT, mg->tail_lds, mg->d_lv, (int32_t)l,
-                   mg->nu, mg->cinv, mg->cinv ? 1 : 0, iflags);
+                   mg->nu, mg->cinv, mg->cinv ? 1 : 0, mg->coarse_sweeps, iflags);
         return PHF_OK;
     }
     const int32_t n = L.nf;
     if (n == 0) return PHF_OK;
     if (l == 0) {
-        for (int s = 0; s < 40; ++s) TRY(smooth(mg, 0, PHF_MG_MAX_SWEEPS, iflags));
+        for (int s = 0; s < mg->coarse_sweeps; ++s)
+            TRY(smooth(mg, 0, PHF_MG_MAX_SWEEPS, iflags));
         return PHF_OK;
     }
     const unsigned g = grid_for(n);

@@ -130,6 +130,10 @@ int phf_ns_cg_solve(phf_ns* ns, double rtol, int32_t max_iter, int32_t check_eve
 struct phf_mg_params {
     int32_t sweeps = 0, smoother = 0;
     double omega = 0.0, range = 0.0;
+    // coarsest levels of the refinement chain left out of the hierarchy when
+    // it is built (first use); the new coarsest level is then smoothed
+    // instead of solved
+    int32_t drop_coarse = 0;
 };
 // Checks the multigrid options and builds the hierarchy (first use) without
 // its numeric part; nothing for Jacobi.

@@ -1135,7 +1135,7 @@ int phf_ns_prepare_precond(phf_ns* ns, int32_t precond, const phf_mg_params& mp)
         return phf_set_error(ctx, PHF_EINVAL, "Chebyshev range must exceed 1 (got %g)", mp.range);
     if (!(mp.omega >= 0.0))
         return phf_set_error(ctx, PHF_EINVAL, "negative Jacobi damping %g", mp.omega);
-    if (!ns->mg) TRY(phf_mg_create(ns, &ns->mg));
+    if (!ns->mg) TRY(phf_mg_create(ns, &ns->mg, mp.drop_coarse));
     const bool jacobi = mp.smoother == PHF_MG_SMOOTH_JACOBI;
     ns->mg->smoother = jacobi ? PHF_MG_SMOOTH_JACOBI : PHF_MG_SMOOTH_CHEBYSHEV;
     ns->mg->nu = mp.sweeps > 0 ? mp.sweeps : jacobi ? 2 : 4;
