@@ -837,6 +837,9 @@ __global__ void k_mg_lmax_clear(int32_t nlev, uint32_t* __restrict__ lmax)
 // iterations (elliptic solve at 4,194,304 triangles 7, Crank-Nicolson 3.04 ->
 // 3.06 per step) and took the solve from 7.49 to 7.10 ms and the stepper
 // from 657 to 689 steps/s; 2 sweeps raised the iterations to 10 and 4.07.
+// With a per-triangle coefficient the level-10 solve went 9.40 -> 8.93 ms (9
+// iterations) and the 3,145,728-triangle L-shape 7.34 -> 7.58 ms (9 -> 10
+// iterations); keeping 4 on the level below the finest helped neither.
 __host__ __device__ constexpr int32_t mid_sweeps(int32_t nu) { return nu > 1 ? nu - 1 : 1; }
 
 __global__ void k_mg_weights(int32_t nlev, int32_t tail_top, int32_t nu0, int32_t cheb,
