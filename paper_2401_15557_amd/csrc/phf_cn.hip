@@ -226,6 +226,15 @@ __global__ void k_cn_close(const int* __restrict__ iflags, const double* __restr
 // (cM |Omega|) = 0.5 on the level of 1,024 triangles, 2.0 on the next):
 // levels 0-3 left out, 689 -> 712 steps/s at 3.06 CG iterations per step;
 // leaving out the next level as well raised them to 4.2.
+int domain_area(const phf_mesh* m, double* d_area, double* area)
+{
+    phf_ctx* ctx = m->ctx;
+    PHF_LAUNCH(ctx, "k_cn_area", k_cn_area, 1, 1024, 0, m->nE, (const double2*)m->exy, d_area);
+    PHF_HIP(ctx, hipMemcpyAsync(area, d_area, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    PHF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return PHF_OK;
+}
+
 int mass_levels(phf_mesh* mesh, const phf_coeffs* co, double cK, double cM, int32_t* out)
 {
     *out = 0;
@@ -234,18 +243,10 @@ int mass_levels(phf_mesh* mesh, const phf_coeffs* co, double cK, double cM, int3
     for (phf_mesh* m = mesh; m; m = m->parent) chain.push_back(m);
     if (chain.size() < 3) return PHF_OK;
     phf_ctx* ctx = mesh->ctx;
-    phf_mesh* root = chain.back();
     double* d_area = nullptr;
     TRY(phf_dmalloc(ctx, &d_area, 1, "domain area"));
     double area = 0.0;
-    int rc = PHF_OK;
-    hipLaunchKernelGGL(k_cn_area, dim3(1), dim3(1024), 0, ctx->stream, root->nE,
-                       (const double2*)root->exy, d_area);
-    if (hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(&area, d_area, sizeof(double), hipMemcpyDeviceToHost, ctx->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess)
-        rc = phf_set_error(ctx, PHF_EHIP, "domain area: HIP call failed");
+    const int rc = domain_area(chain.back(), d_area, &area);  // the coarsest mesh: fewest elements
     phf_dfree(d_area);
     TRY(rc);
     const double a = std::max(std::fabs(co->A[0]), std::fabs(co->A[3]));
