@@ -97,7 +97,6 @@ __global__ __launch_bounds__(NT) void k_cn_keep(int32_t nf, const int32_t* __res
     for (int32_t i = blockIdx.x * NT + threadIdx.x; i < nf; i += gridDim.x * NT) dst[i] = w[i];
 }
 
-
 // Area of the domain of a mesh: the sum of its element areas in one
 // workgroup, in a fixed order.
 __global__ __launch_bounds__(1024) void k_cn_area(int32_t nE, const double2* __restrict__ exy,

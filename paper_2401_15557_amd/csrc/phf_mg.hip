@@ -579,8 +579,8 @@ __global__ __launch_bounds__(NT) void k_mg_prolong(int32_t n, const int32_t* __r
 // is bit-identical either way.
 // Residual and the restriction's first half: a lane per fine row of each
 // coarse triangle (nine lanes per triangle, RR_TRI triangles per workgroup)
-// forms the row's residual; the triangle's first lane combines the nine
-// values from LDS. Rows on an edge shared by two coarse triangles are formed
+// forms the row's residual into LDS; lanes 0..RR_TRI-1 then combine one
+// triangle's nine values each. Rows on an edge shared by two coarse triangles are formed
 // twice; the residual vector is neither written nor read back. Workgroups
 // are dealt to the XCDs in contiguous ranges of triangles, as the row
 // kernels are.
