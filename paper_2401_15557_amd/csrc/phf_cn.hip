@@ -26,6 +26,9 @@ struct phf_cn {
     double *U = nullptr, *Lam = nullptr;
     double *F0 = nullptr, *F1 = nullptr, *bD0 = nullptr, *bD1 = nullptr;
     double *r1 = nullptr, *r2 = nullptr;
+    // per element and local edge: sigma_l |E_l| / 2 (+ on T+, - on T-), 0 on
+    // Neumann edges; the weights of the multipliers in C^T Lambda
+    double* sgh = nullptr;
     int64_t* d_step = nullptr;  // index n of the step being (or next) computed
     // reduced solutions of the last four steps (a ring of four vectors of
     // n_free values) and, on the device, {solves since set_state capped at 4,
@@ -128,15 +131,33 @@ __global__ __launch_bounds__(NT) void k_cn_aminus(int64_t n, const double* K,
     if (q < n) Am[q] = cM * M[q] - cK * K[q];
 }
 
+// sigma_l |E_l| / 2 per element and local edge, once per stepper (the
+// factor k_cn_rhs_elem applies to each multiplier, as a stream instead of a
+// gather of the row's half-length).
+__global__ __launch_bounds__(NT) void k_cn_sgh(int32_t nE, const int32_t* __restrict__ ecode,
+                                               const int32_t* __restrict__ elem_row,
+                                               const double* __restrict__ row_hs,
+                                               double* __restrict__ sgh)
+{
+    const int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (q >= 3 * (int64_t)nE) return;
+    const int64_t m = q / 3;
+    const int l = (int)(q - 3 * m);
+    const int code = ecode[m];
+    double v = 0.0;
+    if (PHF_CODE_TYPE(code, l) != 2)
+        v = (PHF_CODE_TPLUS(code, l) ? 1.0 : -1.0) * fabs(row_hs[elem_row[q]]);
+    sgh[q] = v;
+}
+
 // r1 per element (see file comment); the tile's A- blocks go through LDS so
 // that they are read with coalesced accesses. F0 (the load at t_{n-1}) then
 // takes F1's values, the next step's F0.
 __global__ __launch_bounds__(NT) void k_cn_rhs_elem(
-    int32_t nE, const int32_t* __restrict__ ecode, const double* __restrict__ Am,
-    const double* __restrict__ U, const double* __restrict__ Lam,
-    const int32_t* __restrict__ elem_row, const double* __restrict__ row_hs,
-    double* __restrict__ F0, const double* __restrict__ F1, double hk,
-    double* __restrict__ r1)
+    int32_t nE, const double* __restrict__ Am, const double* __restrict__ U,
+    const double* __restrict__ Lam, const int32_t* __restrict__ elem_row,
+    const double* __restrict__ sgh, double* __restrict__ F0, const double* __restrict__ F1,
+    double hk, double* __restrict__ r1)
 {
     __shared__ double sA[9 * NT];
     const int tid = threadIdx.x;
@@ -146,18 +167,13 @@ __global__ __launch_bounds__(NT) void k_cn_rhs_elem(
     __syncthreads();
     if (tid >= nt) return;
     const int64_t m = m0 + tid;
-    const int code = ecode[m];
     double u[3], lt[3];
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         u[l] = U[3 * m + l];
-        // sigma_l h_l Lambda_row(l) for non-Neumann local edges
-        double v = 0.0;
-        if (PHF_CODE_TYPE(code, l) != 2) {
-            int32_t r = elem_row[3 * m + l];
-            v = (PHF_CODE_TPLUS(code, l) ? 1.0 : -1.0) * fabs(row_hs[r]) * Lam[r];
-        }
-        lt[l] = v;
+        // sigma_l h_l Lambda_row(l) for non-Neumann local edges (row -1)
+        const int32_t r = elem_row[3 * m + l];
+        lt[l] = r >= 0 ? sgh[3 * m + l] * Lam[r] : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -278,8 +294,8 @@ int cn_step_head(phf_cn* cn, const phf_data* data)
     const int32_t nE = mesh->nE, L = mesh->L;
     TRY(cn_loads(cn, data, cn->F1, cn->bD1, true));
     const double hk = 0.5 * cn->k;
-    PHF_LAUNCH(ctx, "k_cn_rhs_elem", k_cn_rhs_elem, nblk(nE), NT, 0, nE, mesh->ecode, cn->Am,
-               cn->U, cn->Lam, cn->ns->elem_row, cn->mesh->row_hs, cn->F0, cn->F1, hk, cn->r1);
+    PHF_LAUNCH(ctx, "k_cn_rhs_elem", k_cn_rhs_elem, nblk(nE), NT, 0, nE, cn->Am, cn->U,
+               cn->Lam, cn->ns->elem_row, cn->sgh, cn->F0, cn->F1, hk, cn->r1);
     if (L > 0)
         PHF_LAUNCH(ctx, "k_cn_rhs_row", k_cn_rhs_row, nblk(L), NT, 0, L, mesh->C_rowptr,
                    mesh->C_col, cn->C, cn->U, cn->bD0, cn->bD1, cn->r2);
@@ -391,7 +407,7 @@ extern "C" int phf_cn_destroy(phf_cn* cn)
     cn_drop_graph(cn);
     if (cn->ns) phf_ns_destroy(cn->ns);
     double* bufs[] = {cn->K, cn->M, cn->Am, cn->C, cn->Fs, cn->bs, cn->U, cn->Lam, cn->F0,
-                      cn->F1, cn->bD0, cn->bD1, cn->r1, cn->r2, cn->d_stats};
+                      cn->F1, cn->bD0, cn->bD1, cn->r1, cn->r2, cn->sgh, cn->d_stats};
     for (double* b : bufs) phf_dfree(b);
     phf_dfree(cn->d_step);
     phf_dfree(cn->wr);
@@ -441,6 +457,7 @@ extern "C" int phf_cn_create(phf_mesh* mesh, const phf_coeffs* co, double k,
         TRY(phf_dmalloc(ctx, &cn->bD0, L, "CN bD0"));
         TRY(phf_dmalloc(ctx, &cn->bD1, L, "CN bD1"));
         TRY(phf_dmalloc(ctx, &cn->r1, N, "CN r1"));
+        TRY(phf_dmalloc(ctx, &cn->sgh, N, "CN edge weights"));
         TRY(phf_dmalloc(ctx, &cn->r2, L, "CN r2"));
         TRY(phf_dmalloc(ctx, &cn->d_stats, 4, "CN stats"));
         TRY(phf_dmalloc(ctx, &cn->d_step, 1, "CN step"));
@@ -457,6 +474,9 @@ extern "C" int phf_cn_create(phf_mesh* mesh, const phf_coeffs* co, double k,
         phf_data d{};
         TRY(phf_assemble_impl(mesh, co, &d, &s));
         TRY(phf_ns_create(mesh, &cn->ns));
+        if (N > 0)
+            PHF_LAUNCH(ctx, "k_cn_sgh", k_cn_sgh, nblk((int64_t)N), NT, 0, mesh->nE, mesh->ecode,
+                       cn->ns->elem_row, mesh->row_hs, cn->sgh);
         TRY(phf_ns_operator(cn->ns, cn->K, cn->M, 0.5 * k, 1.0 + 0.5 * k * co->delta));
         phf_mg_params mp;
         mp.sweeps = cn->opts.mg_sweeps;
