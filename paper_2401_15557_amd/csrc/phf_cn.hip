@@ -299,7 +299,8 @@ int cn_step_head(phf_cn* cn, const phf_data* data)
     if (L > 0)
         PHF_LAUNCH(ctx, "k_cn_rhs_row", k_cn_rhs_row, nblk(L), NT, 0, L, mesh->C_rowptr,
                    mesh->C_col, cn->C, cn->U, cn->bD0, cn->bD1, cn->r2);
-    TRY(phf_ns_rhs(cn->ns, cn->r1, cn->r2, true));  // CU + b_D has interior jumps
+    // (C U + b_D has interior jumps; the edge weights give |E|/2 per element edge)
+    TRY(phf_ns_rhs(cn->ns, cn->r1, cn->r2, true, cn->sgh));
     if (cn->ns->nf > 0)
         PHF_LAUNCH(ctx, "k_cn_guess", k_cn_guess, cn->ns->nbv, NT, 0, cn->ns->nf, cn->d_nsol,
                    cn->wr, cn->ns->w);

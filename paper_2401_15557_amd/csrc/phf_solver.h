@@ -106,7 +106,10 @@ int phf_ns_operator(phf_ns* ns, const double* K, const double* M, double cK, dou
 // Right-hand side reduction (rhs2 is the right-hand side of -C U = rhs2).
 // all_jumps: take the T+-side jumps of every interior row without testing
 // rhs2 for them (a caller whose constraint right-hand side has them anyway).
-int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2, bool all_jumps = false);
+// hs_elem: optional 3 nE values whose magnitude is |E|/2 of each element's
+// local edge (read as a stream instead of the row's half-length by row).
+int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2, bool all_jumps = false,
+               const double* hs_elem = nullptr);
 // Starts CG from the current w, or with zero_start from w = 0 (written by
 // the start itself).
 int phf_ns_cg_start(phf_ns* ns, double rtol, bool zero_start = false);

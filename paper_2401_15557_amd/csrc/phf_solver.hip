@@ -171,6 +171,7 @@ __global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int32_t* __re
                                                  const double* __restrict__ rhs2,
                                                  const double* __restrict__ A,
                                                  const int* __restrict__ jflag, int all_jumps,
+                                                 const double* __restrict__ hs_elem,
                                                  double* __restrict__ kv, double* __restrict__ cs)
 {
     __shared__ double sR[3 * NT], sK[3 * NT], sC[3 * NT];
@@ -191,7 +192,9 @@ __global__ __launch_bounds__(NT) void k_ns_known(int32_t nE, const int32_t* __re
             double v = 0.0;
             if (t == 1 || (jumps && t == 0 && PHF_CODE_TPLUS(code, l))) {
                 const int32_t r = elem_row[3 * m + l];
-                v = -rhs2[r] / (2.0 * fabs(row_hs[r]));
+                // |E|/2 per element edge when given (a stream), else by row
+                const double h = hs_elem ? hs_elem[3 * m + l] : row_hs[r];
+                v = -rhs2[r] / (2.0 * fabs(h));
                 known |= v != 0.0;
             }
             k3[l] = v;
@@ -874,7 +877,8 @@ int phf_ns_operator(phf_ns* ns, const double* K, const double* M, double cK, dou
     return PHF_OK;
 }
 
-int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2, bool all_jumps)
+int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2, bool all_jumps,
+               const double* hs_elem)
 {
     phf_mesh* mesh = ns->mesh;
     phf_ctx* ctx = mesh->ctx;
@@ -884,7 +888,7 @@ int phf_ns_rhs(phf_ns* ns, const double* rhs1, const double* rhs2, bool all_jump
                    rhs2, ns->jflag);
     PHF_LAUNCH(ctx, "k_ns_known", k_ns_known, nblk(ns->nE), NT, 0, ns->nE, mesh->ecode,
                ns->elem_row, mesh->row_hs, rhs1, rhs2, ns->A, ns->jflag, all_jumps ? 1 : 0,
-               ns->kv, ns->cs);
+               hs_elem, ns->kv, ns->cs);
     if (ns->nf > 0)
         PHF_LAUNCH(ctx, "k_ns_gather", k_ns_gather, nblk(ns->nf), NT, 0, ns->nf, mesh->red_edge,
                    mesh->edge_elems, mesh->led, mesh->ledTN, ns->cs, ns->b, ns->jflag);
