@@ -516,8 +516,8 @@ int phf_cn_batch_destroy(phf_cn_batch* batch);
  * The server has `slots` workers, each with its own context (HIP stream and
  * device memory pool) and host thread. A submitted request is copied (the
  * caller may free its arrays on return) and waits until a slot is free and
- * its estimated device footprint (about 1.2 KB per triangle of the refined
- * mesh for an elliptic solve, 1.6 KB for Crank-Nicolson) fits the memory
+ * its estimated device footprint (about 1.4 KB per triangle of the refined
+ * mesh for an elliptic solve, 1.8 KB for Crank-Nicolson) fits the memory
  * budget beside the running requests; the first waiting request in arrival
  * order that fits is admitted (a request larger than the budget runs alone).
  * Admitted requests run concurrently on their slots' streams. A request:

@@ -30,11 +30,12 @@ double ms_between(clk::time_point a, clk::time_point b)
 
 // Device bytes per triangle of the finest mesh, including the coarser
 // refinement levels, the system, the solver and the multigrid hierarchy
-// (measured peaks of the library's pool are below these; a Crank-Nicolson
-// stepper on the paper mesh, mesh chain included: 1,735 B per triangle at
-// 16,384 triangles, where the pool's size rounding weighs more, 1,556 at
-// 262,144).
-constexpr double BYTES_PER_ELEM_ELLIPTIC = 1200.0;
+// (measured peaks of the library's pool are below these; on the paper mesh,
+// mesh chain included, through the context's allocator: an elliptic request
+// (system, multigrid solve) 1,288 / 1,281 / 992 B per triangle at 16,384 /
+// 262,144 / 1,048,576 triangles, a Crank-Nicolson stepper 1,735 / 1,556 at
+// the first two; the pool's size rounding weighs more on small meshes).
+constexpr double BYTES_PER_ELEM_ELLIPTIC = 1400.0;
 constexpr double BYTES_PER_ELEM_CN = 1800.0;
 
 // Crank-Nicolson initial state: per element, the P1 values whose edge
